@@ -1,0 +1,234 @@
+"""The CPU oracle against its pins (closed forms, invariants, dense QZ), and
+planted mistakes that the pins must catch."""
+import copy
+import types
+
+import numpy as np
+import pytest
+
+import oracle.simm as O
+from tests import oracle_pins as P
+from workloads import make_workload
+from workloads.gen import random_band_pencil
+
+
+def test_p1_gauss_rule():
+    P.check_p1_gauss_rule(O)
+
+
+def test_p2_scalar_contour():
+    P.check_p2_scalar_contour(O)
+
+
+def test_p3_additivity():
+    P.check_p3_additivity(O)
+
+
+@pytest.mark.parametrize("b_kind", ["identity", "tridiag"])
+def test_p4_reduced_equals_direct(b_kind):
+    P.check_p4_reduced_equals_direct(O, b_kind)
+
+
+@pytest.mark.parametrize("b_kind", ["identity", "tridiag"])
+def test_p5_arnoldi(b_kind):
+    P.check_p5_arnoldi(O, b_kind)
+
+
+@pytest.mark.parametrize("b_kind", ["identity", "tridiag"])
+def test_p6_residual(b_kind):
+    P.check_p6_residual(O, b_kind)
+
+
+def test_p7_reduced_norm():
+    P.check_p7_reduced_norm(O)
+
+
+def test_p8_empty_square():
+    P.check_p8_empty_square(O)
+
+
+def test_p9_idempotent():
+    P.check_p9_idempotent(O)
+
+
+def test_p10_diagonal():
+    P.check_p10_diagonal(O)
+
+
+@pytest.mark.parametrize("n,k,seed,b_kind,m", [(24, 2, 31, "identity", 20), (40, 3, 32, "tridiag", 30),
+                                                (60, 1, 33, "identity", 30)])
+def test_p11_tiny_pencils_against_qz(n, k, seed, b_kind, m):
+    pen, f = random_band_pencil(n, k, seed, b_kind=b_kind, b_offdiag=0.3)
+    params = P.base_params(m=m, n1=4, h0=1e-5)
+    res = O.simm(pen, f, params, max_regions_per_level=5000)
+    assert all((L.decision != O.DECISION_UNRESOLVED).all() for L in res.levels)
+    P.check_p11_against_qz(O, pen, f, params, res)
+
+
+@pytest.mark.slow
+def test_p11_cfg0_against_qz():
+    pen, f, params = make_workload("cfg0")
+    res = P.check_p11_against_qz(O, pen, f, params)
+    assert res.K == 19
+    assert len(res.clusters) == 99
+
+
+def test_p12_solver():
+    P.check_p12_solver(O)
+
+
+def test_p13_eig_identity():
+    P.check_p13_eig_identity(O)
+
+
+def test_p14_max_principle():
+    P.check_p14_max_principle(O)
+
+
+def test_breakdown_and_errors():
+    # f = e_i with diagonal A and B = I: M b is parallel to b -> happy breakdown at j = 1
+    from workloads.gen import Pencil
+    n = 8
+    band = (np.arange(n) + 1.0).reshape(1, n).astype(complex)
+    pen = Pencil(n, 0, 0, band, 0, 0, None)
+    f = np.zeros(n, complex)
+    f[3] = 1.0
+    sh = O.build_shift(pen, 0.5j, f, 5)
+    assert sh.m_eff == 1 and sh.H.shape == (2, 1) and sh.h_last == 0.0
+    ev = O.evaluate_square(sh, 4.0, 1.0, P.base_params(m=5))
+    assert ev.rho_max == 0.0 and ev.resolvable and ev.admissible
+    with pytest.raises(O.SingularShift):
+        O.ShiftedSolver(pen, 3.0)
+    with pytest.raises(ValueError):
+        O.simm(pen, f, P.base_params(m=0))
+    with pytest.raises(ValueError):
+        O.simm(pen, f, P.base_params(x1=0.5, n1=3))   # non-square cells
+
+
+# ---------------------------------------------------------------------------
+# Planted mistakes: each must make at least one pin fail.
+# ---------------------------------------------------------------------------
+
+def _mutant(**overrides):
+    """A copy of the oracle module whose functions see each other through the
+    copy, with some functions replaced by planted mistakes."""
+    mod = types.ModuleType("oracle_mutant")
+    mod.__dict__.update({k: v for k, v in O.__dict__.items() if not k.startswith("__")})
+    for name, obj in list(mod.__dict__.items()):
+        if isinstance(obj, types.FunctionType):
+            mod.__dict__[name] = types.FunctionType(obj.__code__, mod.__dict__, name, obj.__defaults__, obj.__closure__)
+    for name, fn in overrides.items():
+        mod.__dict__[name] = fn
+    return mod
+
+
+def _clockwise_rule(center, width, g):
+    t, om = np.polynomial.legendre.leggauss(g)
+    h = width / 2.0
+    corners = [center + h * (-1 - 1j), center + h * (-1 + 1j), center + h * (1 + 1j), center + h * (1 - 1j)]
+    zs, ws = [], []
+    for e in range(4):
+        a, b = corners[e], corners[(e + 1) % 4]
+        zs.append(a + (t + 1.0) * (b - a) / 2.0)
+        ws.append(om * (b - a) / 2.0)
+    return np.concatenate(zs), np.concatenate(ws)
+
+
+def _wrong_sign_solutions(shift, z):
+    m = shift.m_eff
+    alpha = z - shift.sigma                      # sign flipped
+    G = np.eye(m)[None] + alpha[:, None, None] * shift.Hm[None]
+    rhs = np.zeros((len(z), m, 1), complex)
+    rhs[:, 0, 0] = shift.beta
+    return np.linalg.solve(G, rhs)[:, :, 0]
+
+
+def _transposed_solutions(shift, z):
+    m = shift.m_eff
+    alpha = shift.sigma - z
+    G = np.eye(m)[None] + alpha[:, None, None] * shift.Hm.T[None]   # transposed operand
+    rhs = np.zeros((len(z), m, 1), complex)
+    rhs[:, 0, 0] = shift.beta
+    return np.linalg.solve(G, rhs)[:, :, 0]
+
+
+def _residual_no_h(shift, z, Y):
+    return np.abs(shift.sigma - z) * np.abs(Y[:, -1]) / shift.beta     # dropped h_{m+1,m}
+
+
+def _residual_first_entry(shift, z, Y):
+    return np.abs(shift.sigma - z) * shift.h_last * np.abs(Y[:, 0]) / shift.beta   # wrong index
+
+
+_orig_build = O.build_shift
+
+
+def _build_conj_dot(pencil, sigma, f, m, keep_V=True, solver=None):
+    # Gram-Schmidt with the inner product's arguments swapped (v^T conj(w))
+    n = pencil.n
+    solver = solver or O.ShiftedSolver(pencil, sigma)
+    b = solver.solve(f)
+    beta = float(np.linalg.norm(b))
+    V = np.zeros((n, m + 1), complex)
+    H = np.zeros((m + 1, m), complex)
+    V[:, 0] = b / beta
+    for j in range(m):
+        w = solver.apply_M(V[:, j])
+        for _ in range(2):
+            for i in range(j + 1):
+                c = np.vdot(w, V[:, i])
+                H[i, j] += c
+                w = w - c * V[:, i]
+        H[j + 1, j] = np.linalg.norm(w)
+        V[:, j + 1] = w / H[j + 1, j]
+    return O.Shift(complex(sigma), beta, H, m, V)
+
+
+def _build_unshifted_rhs(pencil, sigma, f, m, keep_V=True, solver=None):
+    # forgets the Cayley right-hand side: starts Arnoldi from f instead of (A - sigma B)^{-1} f
+    inner = solver or O.ShiftedSolver(pencil, sigma)
+    state = {"first": True}
+
+    class _S:
+        def solve(self, r):
+            if state["first"]:
+                state["first"] = False
+                return np.asarray(r, complex)
+            return inner.solve(r)
+
+        def apply_M(self, x):
+            return inner.apply_M(x)
+    return _orig_build(pencil, sigma, f, m, keep_V, _S())
+
+
+MUTANTS = {
+    "clockwise contour": dict(edge_rule=_clockwise_rule),
+    "sign of sigma - z": dict(shifted_solutions=_wrong_sign_solutions),
+    "transposed H": dict(shifted_solutions=_transposed_solutions),
+    "dropped h_{m+1,m}": dict(residuals=_residual_no_h),
+    "wrong residual index": dict(residuals=_residual_first_entry),
+    "swapped inner product": dict(build_shift=_build_conj_dot),
+    "no Cayley rhs": dict(build_shift=_build_unshifted_rhs),
+}
+
+PIN_CHECKS = [
+    lambda M: P.check_p2_scalar_contour(M),
+    lambda M: P.check_p3_additivity(M),
+    lambda M: P.check_p4_reduced_equals_direct(M, "tridiag"),
+    lambda M: P.check_p5_arnoldi(M, "tridiag"),
+    lambda M: P.check_p6_residual(M, "tridiag"),
+    lambda M: P.check_p10_diagonal(M),
+    lambda M: P.check_p13_eig_identity(M),
+]
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(name):
+    mod = _mutant(**MUTANTS[name])
+    failures = 0
+    for chk in PIN_CHECKS:
+        try:
+            chk(mod)
+        except (AssertionError, np.linalg.LinAlgError, ValueError, ZeroDivisionError, FloatingPointError):
+            failures += 1
+    assert failures >= 1, f"planted mistake '{name}' passed every pin"

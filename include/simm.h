@@ -1,0 +1,214 @@
+/*
+ * simm.h -- C ABI of the MI355X (gfx950) library for the indicator evaluation of
+ * SIM-M, the multilevel spectral indicator method for A x = lambda B x
+ * (Huang, Sun & Yang, arXiv:2006.16117).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Complex numbers are two interleaved doubles (re, im), i.e. the layout of
+ *    C99 double complex / std::complex<double> / numpy complex128.
+ *  - Matrices are column-major.  Band matrices use LAPACK general-band layout:
+ *    entry (i, j) of an n x n matrix with kl sub- and ku super-diagonals is
+ *    band[(ku + i - j) + j * (kl + ku + 1)], for max(0, j-ku) <= i <= min(n-1, j+kl).
+ *  - `mem` arguments say where a pointer lives: SIMM_MEM_HOST or SIMM_MEM_DEVICE
+ *    (HIP device memory of the current device).
+ *  - `hip_stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
+ *    it; unless stated otherwise a call returns after its work has completed.
+ *  - Inputs are borrowed for the duration of the call; the library copies what
+ *    it keeps.  Objects returned through `out` pointers are library-owned and
+ *    must be released with the matching *_destroy call.
+ *  - Every call returns a simm_status; no C++ exception crosses the ABI.  On an
+ *    error, simm_last_error() returns a description (thread-local, valid until
+ *    the next simm_* call on the same thread).
+ */
+#ifndef SIMM_H
+#define SIMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SIMM_OK = 0,
+    SIMM_EINVAL = -1,           /* bad argument (NaN/Inf input, m < 1, m > n, cap too small, ...) */
+    SIMM_ENODEV = -2,           /* no usable gfx950 device */
+    SIMM_ENOMEM = -3,           /* device allocation failed */
+    SIMM_EHIP = -4,             /* a HIP runtime call failed (message has hipGetErrorString) */
+    SIMM_ESINGULAR_SHIFT = -5,  /* exact zero pivot: the shift is an eigenvalue of the pencil */
+    SIMM_ENOCONV = -6,          /* the QR iteration for the Schur form of H_m did not converge */
+    SIMM_ELIMIT = -7,           /* a level holds more squares than max_regions_per_level */
+    SIMM_EUNSUPPORTED = -8      /* size outside what the kernels support (see each call) */
+} simm_status;
+
+enum { SIMM_MEM_HOST = 0, SIMM_MEM_DEVICE = 1 };
+
+/* Region decisions (Definitions 3.1-3.2 and Remark 3.3 of the paper). */
+enum { SIMM_REJECTED = 0, SIMM_ADMISSIBLE = 1, SIMM_UNRESOLVED = 2 };
+
+/* simm_params.flags */
+enum { SIMM_FLAG_PROJECT = 1u };   /* form X = V_m Y for the squares of every level */
+
+typedef struct simm_pencil_s* simm_pencil;
+typedef struct simm_shift_s* simm_shift;
+typedef struct simm_result_s* simm_result;
+
+const char* simm_last_error(void);
+int32_t simm_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Pencil (A, B): eq. (AxLambdaBx), A and B n x n, sparse, non-Hermitian.     */
+/* ------------------------------------------------------------------------ */
+
+/* Banded A and B in LAPACK band layout (see above).  b_band == NULL means B = I
+ * (kl_b, ku_b ignored).  The pencil is copied to device memory.
+ * EINVAL: n < 1, negative bandwidths, NULL a_band, NaN/Inf entries. */
+simm_status simm_pencil_create_banded(int64_t n,
+                                      int32_t kl_a, int32_t ku_a, const double* a_band,
+                                      int32_t kl_b, int32_t ku_b, const double* b_band,
+                                      int32_t mem, void* hip_stream, simm_pencil* out);
+
+/* CSR A and B (0-based row pointers and column indices, complex values; host
+ * memory only).  Converted to band form; b_rowptr == NULL means B = I.
+ * EUNSUPPORTED if the half-bandwidth exceeds 4096. */
+simm_status simm_pencil_create_csr(int64_t n,
+                                   const int64_t* a_rowptr, const int32_t* a_col, const double* a_val,
+                                   const int64_t* b_rowptr, const int32_t* b_col, const double* b_val,
+                                   void* hip_stream, simm_pencil* out);
+
+simm_status simm_pencil_info(simm_pencil p, int64_t* n, int32_t* kl, int32_t* ku);
+void simm_pencil_destroy(simm_pencil p);
+
+/* ------------------------------------------------------------------------ */
+/* Parameters of SIM-M(A, B, R, f, h0, eps, delta0, m, n0) (Sec. 3.5).       */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double x0, x1, y0, y1;      /* search region R = [x0,x1] x [y0,y1]                         */
+    int32_t n1;                 /* level-1 cells along x; cells are square, so (y1-y0)/w1 must be
+                                   an integer with w1 = (x1-x0)/n1                               */
+    int32_t gauss_per_edge;     /* g: the n0-rule has g Gauss-Legendre points per edge, the 2n0-
+                                   rule 2g per edge (12 g systems per square)                    */
+    int32_t m;                  /* Krylov dimension                                              */
+    int32_t levels;             /* K; if <= 0, K = 1 + ceil(log2(w1 / h0))                        */
+    double h0;                  /* precision (square width at which refinement stops)            */
+    double eps0;                /* residual tolerance of Definition 3.1 (default 1e-8)           */
+    double delta0;              /* indicator threshold of Definition 3.2 (default 1/20)          */
+    double tau;                 /* floor: admissible needs ||s_f|| > tau * T_f (default 1e-8)    */
+    int64_t max_regions_per_level; /* guard against refinement blow-up (default 1<<22)          */
+    uint32_t flags;             /* SIMM_FLAG_*                                                   */
+} simm_params;
+
+simm_status simm_params_default(simm_params* p);
+
+/* ------------------------------------------------------------------------ */
+/* Hot-path entry points.                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* One shift sigma (Sec. 2, Cayley transform and Arnoldi):
+ *   banded LU with partial pivoting of A - sigma B;  b = (A - sigma B)^{-1} f,
+ *   beta = ||b||;  m steps of Arnoldi on M = (A - sigma B)^{-1} B from v_1 = b/beta
+ *   (classical Gram-Schmidt applied twice), giving V_{m+1}, H_{m+1,m};
+ *   then the Schur form H_m = Q T Q^H used by simm_indicators.
+ * f: n complex values in `f_mem` memory.  Supported: 1 <= m <= min(n, 128),
+ * kl <= 480 of A - sigma B.  Happy breakdown (h_{j+1,j} <= 1e-14 ||M v_j||)
+ * stops early with m_eff = j.  ESINGULAR_SHIFT on an exact zero pivot. */
+simm_status simm_shift_build(simm_pencil p, double sig_re, double sig_im,
+                             const double* f, int32_t f_mem, int32_t m,
+                             void* hip_stream, simm_shift* out);
+
+/* Copies out sigma (2 doubles), beta, m_eff, and optionally (if non-NULL)
+ * H_{m_eff+1, m_eff} (column-major complex, leading dimension m_eff+1, host)
+ * and the m_eff Ritz values sigma + 1/theta_k (theta_k = eigenvalues of H_m,
+ * the diagonal of T; host). */
+simm_status simm_shift_info(simm_shift s, double* sigma, double* beta, int32_t* m_eff,
+                            double* H, double* ritz);
+
+/* Copies the Arnoldi basis V_{m_eff+1} (n x (m_eff+1), column-major complex,
+ * leading dimension n) to `V` in `mem` memory. */
+simm_status simm_shift_basis(simm_shift s, double* V, int32_t mem, void* hip_stream);
+
+/* Applies M = (A - sigma B)^{-1} B of this shift to x (n complex): y = M x.
+ * x and y in `mem` memory (distinct buffers). */
+simm_status simm_shift_apply(simm_shift s, const double* x, double* y, int32_t mem, void* hip_stream);
+
+void simm_shift_destroy(simm_shift s);
+
+/* Indicators of N squares (Sec. 2 eqs. (many), (error), (y); Sec. 3.1 eq.
+ * (DeltaSm); Definitions 3.1-3.2).  regions: N x 4 int64 rows
+ * (level k >= 1, ix, iy, shift index into `shifts`); the square has width
+ * w_k = ((x1-x0)/n1) * 2^(1-k) and centre (x0 + (ix+0.5) w_k, y0 + (iy+0.5) w_k).
+ * For every one of its 12 g quadrature points z_j the kernel solves
+ * (I + (sigma - z_j) H_m) y_j = beta e_1 and forms
+ *   rho_j = |sigma - z_j| h_{m+1,m} |e_m^T y_j| / beta,
+ *   s_c = (1/2 pi i) sum_{n0-rule} w_j y_j,  s_f = (1/2 pi i) sum_{2n0-rule} w_j y_j,
+ *   T_f = (1/2 pi) sum_{2n0-rule} |w_j| ||y_j||.
+ * Outputs (each N values, `mem` memory, any may be NULL): indicator = ||s_f||/||s_c||,
+ * rho_max = max_j rho_j, nsf = ||s_f||, nsc = ||s_c||, Tf, decision (SIMM_* above;
+ * resolvable iff rho_max <= eps0; admissible iff ||s_f|| > tau T_f and
+ * ||s_f|| > delta0 ||s_c||).  sums (may be NULL): N x 2 x m_max complex, row r holds
+ * s_c then s_f of region r (each m_max entries, zero-padded beyond that shift's m_eff).
+ * EUNSUPPORTED if gauss_per_edge > 64. */
+simm_status simm_indicators(const simm_shift* shifts, int32_t n_shifts,
+                            const int64_t* regions, int64_t n_regions, const simm_params* params,
+                            double* indicator, double* rho_max, double* nsf, double* nsc, double* Tf,
+                            uint8_t* decision, double* sums, int32_t m_max,
+                            int32_t mem, void* hip_stream);
+
+/* Projection X = V_m Y (eq. (reduced)): Y is m_eff x c complex (column-major,
+ * leading dimension m_eff), X is n x c complex (leading dimension n); both in
+ * device memory.  col_norms (device, may be NULL) receives ||X(:, j)||_2.
+ * Computed with FP64 matrix-core instructions. */
+simm_status simm_project(simm_shift s, const double* Y, int64_t c, double* X, double* col_norms,
+                         void* hip_stream);
+
+/* ------------------------------------------------------------------------ */
+/* Whole method: SIM-M steps 1-7 (Sec. 3.5).                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Runs SIM-M on the pencil with start vector f (n complex, `f_mem` memory).
+ * Step 1: first shift at the centre of R.  Steps 2-3: level-1 cells in (iy, ix)
+ * order, each tried against the existing shifts nearest-first (ties: lower
+ * index); a cell none of them resolves gets a new shift at its centre.
+ * Steps 4-5: K levels; a square keeps its parent's shift, falls back to the
+ * other shifts nearest-first if that one does not resolve it, and marked
+ * squares (admissible or unresolved) are split into four.  Steps 6-7: marked
+ * level-K squares are merged into 8-connected clusters; each cluster's
+ * eigenvalue is the mean of its members' centres (and, additionally, the Ritz
+ * value of its shift that lies in the cluster).  ELIMIT if a level exceeds
+ * max_regions_per_level. */
+simm_status simm_run(simm_pencil p, const simm_params* params, const double* f, int32_t f_mem,
+                     void* hip_stream, simm_result* out);
+
+simm_status simm_result_summary(simm_result r, int32_t* K, int32_t* n_shifts, int64_t* n_clusters,
+                                int64_t* n_unresolved);
+
+/* Squares tested at level `level` (1..K), in the order tested: (iy, ix)
+ * lexicographic.  Arrays of `cap` entries (host); any may be NULL.  If cap is
+ * too small, EINVAL with *n_tested set to the needed count. */
+simm_status simm_result_level(simm_result r, int32_t level, int64_t* n_tested,
+                              int64_t* ix, int64_t* iy, int32_t* shift, double* indicator,
+                              double* rho_max, uint8_t* decision, int64_t cap);
+
+/* Shift `idx` of the run (borrowed handle, valid until simm_result_destroy). */
+simm_status simm_result_shift(simm_result r, int32_t idx, simm_shift* out);
+
+/* Clusters (eigenvalues): lam = mean of member centres, lam_ritz = Ritz value of
+ * the cluster's shift inside the cluster (NaN if none), shift index, flags bit 0
+ * = contains an unresolved square.  Host arrays of `cap` entries. */
+simm_status simm_result_clusters(simm_result r, int64_t* n, double* lam, double* lam_ritz,
+                                 int32_t* shift, int32_t* flags, int64_t cap);
+
+/* Phase timings of the run in milliseconds (host wall clock around
+ * stream-synchronised phases): [0] shift builds, [1] indicators, [2] projection,
+ * [3] total.  Counters: [0] quadrature-point systems solved, [1] square
+ * evaluations, [2] applications of M.  Either pointer may be NULL. */
+simm_status simm_result_stats(simm_result r, double* ms4, int64_t* counters3);
+
+void simm_result_destroy(simm_result r);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SIMM_H */

@@ -1,0 +1,291 @@
+// Shifted pencil assembly and banded LU with partial pivoting (gfx950).
+//
+// The Cayley transform of Sec. 2 needs one factorization of A - sigma B per shift
+// (sigma not an eigenvalue).  The factor uses LAPACK general-band LU storage:
+// ldab = 2 kl + ku + 1 rows, kv = kl + ku; U(i,j) at row kv + i - j (kv super-
+// diagonals after fill), the multipliers of column j at rows kv+1 .. kv+kl.  As in
+// LAPACK's band LU, the row interchange of step j is applied to columns >= j
+// only, so column j keeps its multipliers as computed ("interleaved" L) and a
+// solve applies interchange and elimination column by column.
+//
+// Blocked right-looking schedule, one launch per panel of NB columns:
+//   launch b:  every workgroup takes a slice of the columns right of panel b,
+//              applies panel b's interchanges, the unit-lower triangular solve and
+//              the rank-NB update (trailing window = rows of the panel + kl), and
+//              workgroup 0, which owns panel b+1, then factors panel b+1 in LDS.
+// Consecutive launches on one stream order the panels; no workgroup ever waits
+// on another.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace simm {
+
+// a1: C = A - sigma B written into LU band storage (fill rows zeroed).
+__global__ void k_assemble_shifted(int64_t n, int kl, int ku, const cplx* __restrict__ A, int kla, int kua,
+                                   const cplx* __restrict__ B, int klb, int kub, cplx sigma,
+                                   cplx* __restrict__ AB) {
+    const int kv = kl + ku, ldab = 2 * kl + ku + 1;
+    const int64_t c = blockIdx.x;
+    for (int r = threadIdx.x; r < ldab; r += blockDim.x) {
+        const int d = r - kv;          // i - c
+        const int64_t i = c + d;
+        cplx v = mk(0.0, 0.0);
+        if (i >= 0 && i < n) {
+            if (d >= -kua && d <= kla) v = A[(int64_t)(kua + d) + c * (kla + kua + 1)];
+            if (B) {
+                if (d >= -kub && d <= klb) v = v - sigma * B[(int64_t)(kub + d) + c * (klb + kub + 1)];
+            } else if (d == 0) {
+                v = v - sigma;
+            }
+        }
+        AB[(int64_t)r + c * ldab] = v;
+    }
+}
+
+namespace {
+
+constexpr int LU_THREADS = 256;
+
+struct LuArgs {
+    int64_t n;
+    int kl, ku, kv, ldab;
+    int nb;          // panel width
+    int cw;          // columns per trailing workgroup
+    cplx* AB;
+    int* ipiv;       // 0-based global row of the pivot of each column
+    cplx* lt[2];     // permuted panel multipliers, (nb + kl) x nb column-major, double buffered
+    int* info;       // first singular column + 1 (0 if none)
+};
+
+__device__ inline cplx ab_get(const LuArgs& a, int64_t i, int64_t c) {
+    const int64_t d = i - c;
+    if (i < 0 || i >= a.n || c < 0 || c >= a.n || d < -a.kv || d > a.kl) return mk(0.0, 0.0);
+    return a.AB[(int64_t)(a.kv + d) + c * a.ldab];
+}
+__device__ inline void ab_put(const LuArgs& a, int64_t i, int64_t c, cplx v) {
+    const int64_t d = i - c;
+    if (i < 0 || i >= a.n || c < 0 || c >= a.n || d < -a.kv || d > a.kl) return;
+    a.AB[(int64_t)(a.kv + d) + c * a.ldab] = v;
+}
+
+// Factor the panel held in P (rows j1 .. j1+R1-1, columns j1 .. j1+nb1-1, leading
+// dimension ldp) in place; store multipliers / U / pivots in the band and the
+// permuted multipliers in `lt_out`.
+__device__ void factor_panel(const LuArgs& a, cplx* P, int ldp, int64_t j1, int nb1, int R1, cplx* lt_out,
+                             double* red_v, int* red_i) {
+    const int tid = threadIdx.x;
+    for (int t = 0; t < nb1; ++t) {
+        const int64_t j = j1 + t;
+        const int km = (int)min((int64_t)a.kl, a.n - 1 - j);
+        // pivot search: first index of max |re| + |im| over rows t .. t+km
+        double best = -1.0;
+        int bidx = t;
+        for (int r = t + tid; r <= t + km; r += LU_THREADS) {
+            const double v = cabs1(P[r + t * ldp]);
+            if (v > best) { best = v; bidx = r; }
+        }
+        red_v[tid] = best;
+        red_i[tid] = bidx;
+        __syncthreads();
+        for (int s = LU_THREADS / 2; s > 0; s >>= 1) {
+            if (tid < s) {
+                const double v2 = red_v[tid + s];
+                const int i2 = red_i[tid + s];
+                if (v2 > red_v[tid] || (v2 == red_v[tid] && i2 < red_i[tid])) {
+                    red_v[tid] = v2;
+                    red_i[tid] = i2;
+                }
+            }
+            __syncthreads();
+        }
+        const int rp = red_i[0];
+        const bool zero = !(red_v[0] > 0.0);
+        __syncthreads();
+        if (tid == 0) a.ipiv[j] = (int)(j1 + rp);
+        if (zero) {
+            if (tid == 0) atomicMin(a.info, (int)(j + 1));
+            // LAPACK semantics: record the pivot, no interchange or elimination.
+            __syncthreads();
+            continue;
+        }
+        if (rp != t) {
+            for (int c = tid; c < nb1; c += LU_THREADS) {
+                cplx tmp = P[t + c * ldp];
+                P[t + c * ldp] = P[rp + c * ldp];
+                P[rp + c * ldp] = tmp;
+            }
+        }
+        __syncthreads();
+        const cplx piv = P[t + t * ldp];
+        for (int r = t + 1 + tid; r <= t + km; r += LU_THREADS) {
+            const cplx l = cdiv(P[r + t * ldp], piv);
+            P[r + t * ldp] = l;
+            ab_put(a, j1 + r, j, l);   // multiplier as computed at step j (unpermuted)
+        }
+        __syncthreads();
+        const int ncol = nb1 - t - 1;
+        if (ncol > 0) {
+            for (int e = tid; e < km * ncol; e += LU_THREADS) {
+                const int r = t + 1 + e % km;
+                const int c = t + 1 + e / km;
+                P[r + c * ldp] = fms(P[r + c * ldp], P[r + t * ldp], P[t + c * ldp]);
+            }
+        }
+        __syncthreads();
+    }
+    // U part of the panel and the permuted multipliers for the trailing update
+    for (int e = tid; e < nb1 * R1; e += LU_THREADS) {
+        const int r = e % R1, t = e / R1;
+        const cplx v = P[r + t * ldp];
+        if (r <= t) ab_put(a, j1 + r, j1 + t, v);
+        lt_out[r + t * (a.nb + a.kl)] = v;
+    }
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(LU_THREADS) void k_band_lu_step(LuArgs a, int64_t b) {
+    extern __shared__ cplx smem[];
+    __shared__ double red_v[LU_THREADS];
+    __shared__ int red_i[LU_THREADS];
+    const int tid = threadIdx.x;
+    const int wg = blockIdx.x;
+    const int nb = a.nb;
+    const int ldl = nb + a.kl;                 // rows of the panel buffers
+    cplx* Pan = smem;                          // ldl x nb      : permuted multipliers of panel b
+    cplx* Xc = smem + (size_t)ldl * nb;        // ldx x ncols   : my column slice, rows j0 ..
+    const int ldx = 2 * nb + a.kl;
+
+    const int64_t j0 = b * nb;                                  // panel b (b may be -1)
+    const int nbp = (b >= 0) ? (int)min((int64_t)nb, a.n - j0) : 0;
+    const int64_t j1 = (b >= 0) ? j0 + nbp : 0;                 // panel b+1
+    const int nb1 = (int)max((int64_t)0, min((int64_t)nb, a.n - j1));
+
+    // my column slice
+    int64_t c0, c1;
+    if (wg == 0) {
+        c0 = j1;
+        c1 = j1 + nb1;
+    } else {
+        if (b < 0) return;
+        const int64_t jmax = min(a.n - 1, j0 + nbp - 1 + (int64_t)a.kv);
+        c0 = j1 + nb1 + (int64_t)(wg - 1) * a.cw;
+        c1 = min(c0 + a.cw, jmax + 1);
+        if (c0 > jmax) return;
+    }
+    const int ncols = (int)(c1 - c0);
+
+    if (b >= 0 && ncols > 0) {
+        const int Rb = (int)min((int64_t)(nbp + a.kl), a.n - j0);   // rows j0 .. j0+Rb-1 touched
+        const cplx* lt_in = a.lt[b & 1];
+        for (int e = tid; e < Rb * nbp; e += LU_THREADS) {
+            const int r = e % Rb, t = e / Rb;
+            Pan[r + t * ldl] = lt_in[r + t * ldl];
+        }
+        for (int e = tid; e < Rb * ncols; e += LU_THREADS) {
+            const int r = e % Rb, c = e / Rb;
+            Xc[r + c * ldx] = ab_get(a, j0 + r, c0 + c);
+        }
+        __syncthreads();
+        // interchanges, in order, then the unit lower triangular solve (one thread per column)
+        for (int c = tid; c < ncols; c += LU_THREADS) {
+            for (int t = 0; t < nbp; ++t) {
+                const int p = (int)(a.ipiv[j0 + t] - j0);
+                if (p != t) {
+                    cplx tmp = Xc[t + c * ldx];
+                    Xc[t + c * ldx] = Xc[p + c * ldx];
+                    Xc[p + c * ldx] = tmp;
+                }
+            }
+            for (int t = 1; t < nbp; ++t) {
+                cplx acc = Xc[t + c * ldx];
+                for (int s = 0; s < t; ++s) acc = fms(acc, Pan[t + s * ldl], Xc[s + c * ldx]);
+                Xc[t + c * ldx] = acc;
+            }
+        }
+        __syncthreads();
+        // rank-nbp update of rows nbp .. Rb-1
+        const int nrow = Rb - nbp;
+        for (int e = tid; e < nrow * ncols; e += LU_THREADS) {
+            const int c = e % ncols, r = nbp + e / ncols;
+            cplx acc = Xc[r + c * ldx];
+            for (int s = 0; s < nbp; ++s) acc = fms(acc, Pan[r + s * ldl], Xc[s + c * ldx]);
+            Xc[r + c * ldx] = acc;
+        }
+        __syncthreads();
+        // write back; workgroup 0 keeps rows j1.. in LDS for its panel
+        for (int e = tid; e < Rb * ncols; e += LU_THREADS) {
+            const int r = e % Rb, c = e / Rb;
+            if (wg != 0 || r < nbp) ab_put(a, j0 + r, c0 + c, Xc[r + c * ldx]);
+        }
+        __syncthreads();
+    }
+
+    if (wg == 0 && nb1 > 0) {
+        // panel b+1 lives in Xc rows nbp .. ; rows beyond those the update touched come from the band
+        const int R1 = (int)min((int64_t)(nb1 + a.kl), a.n - j1);
+        const int have = (b >= 0) ? (int)min((int64_t)(nbp + a.kl), a.n - j0) - nbp : 0;
+        cplx* P = Xc + nbp;
+        for (int e = tid; e < R1 * nb1; e += LU_THREADS) {
+            const int r = e % R1, c = e / R1;
+            if (r >= have) P[r + c * ldx] = ab_get(a, j1 + r, j1 + c);
+        }
+        __syncthreads();
+        factor_panel(a, P, ldx, j1, nb1, R1, a.lt[(b + 1) & 1], red_v, red_i);
+    }
+}
+
+int lu_panel_width(int kl) {
+    // two buffers of (nb + kl) rows and one of (2 nb + kl) rows, nb columns, must fit in LDS
+    const size_t lds = 160 * 1024 - 8 * 1024;
+    for (int nb = 16; nb >= 4; nb /= 2) {
+        size_t need = ((size_t)(nb + kl) + (size_t)(2 * nb + kl)) * nb * sizeof(cplx);
+        if (need <= lds) return nb;
+    }
+    return 0;
+}
+
+simm_status band_lu(int64_t n, int kl, int ku, cplx* AB, int* ipiv, cplx* lt_scratch, int* info,
+                    hipStream_t st) {
+    const int nb = lu_panel_width(kl);
+    if (nb == 0) {
+        set_error("lower bandwidth too large for the LU kernel");
+        return SIMM_EUNSUPPORTED;
+    }
+    LuArgs a;
+    a.n = n;
+    a.kl = kl;
+    a.ku = ku;
+    a.kv = kl + ku;
+    a.ldab = 2 * kl + ku + 1;
+    a.nb = nb;
+    a.cw = nb;
+    a.AB = AB;
+    a.ipiv = ipiv;
+    a.lt[0] = lt_scratch;
+    a.lt[1] = lt_scratch + (size_t)(nb + kl) * nb;
+    a.info = info;
+    const size_t lds = ((size_t)(nb + kl) * nb + (size_t)(2 * nb + kl) * nb) * sizeof(cplx);
+    const int grid = 2 + (a.kv + a.cw - 1) / a.cw;
+    const int64_t nblk = (n + nb - 1) / nb;
+    for (int64_t b = -1; b < nblk; ++b) {
+        hipLaunchKernelGGL(k_band_lu_step, dim3(b < 0 ? 1 : grid), dim3(LU_THREADS), lds, st, a, b);
+    }
+    SIMM_HIP_TRY(hipGetLastError());
+    return SIMM_OK;
+}
+
+size_t band_lu_scratch_elems(int kl) {
+    const int nb = lu_panel_width(kl);
+    return 2 * (size_t)(nb + kl) * (size_t)(nb > 0 ? nb : 1);
+}
+
+simm_status assemble_shifted(int64_t n, int kl, int ku, const cplx* A, int kla, int kua, const cplx* B, int klb,
+                             int kub, cplx sigma, cplx* AB, hipStream_t st) {
+    hipLaunchKernelGGL(k_assemble_shifted, dim3((unsigned)n), dim3(256), 0, st, n, kl, ku, A, kla, kua, B, klb, kub,
+                       sigma, AB);
+    SIMM_HIP_TRY(hipGetLastError());
+    return SIMM_OK;
+}
+
+}  // namespace simm

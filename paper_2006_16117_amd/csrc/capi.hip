@@ -1,0 +1,1251 @@
+// C ABI of the SIM-M library: pencils, shifts, the hot-path entry points and the
+// multilevel driver (Sec. 3.3 and the SIM-M algorithm of Sec. 3.5).
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <set>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace simm {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+void clear_error() { g_err.clear(); }
+
+}  // namespace simm
+
+using namespace simm;
+
+// ---------------------------------------------------------------------------
+// objects
+// ---------------------------------------------------------------------------
+struct simm_pencil_s {
+    int64_t n = 0;
+    int kla = 0, kua = 0, klb = 0, kub = 0;
+    cplx* A = nullptr;       // device band of A
+    cplx* B = nullptr;       // device band of B (nullptr: identity)
+    int dev = 0;
+};
+
+struct simm_shift_s {
+    simm_pencil_s* p = nullptr;
+    cplx sigma{0, 0};
+    int m = 0, m_eff = 0;
+    int kl = 0, ku = 0;
+    double beta = 0.0, h_last = 0.0;
+    cplx* AB = nullptr;      // LU factor (band)
+    int* ipiv = nullptr;
+    cplx* V = nullptr;       // n x (m+1)
+    cplx* H = nullptr;       // (m+1) x m, device
+    cplx* T = nullptr;       // packed upper triangle
+    cplx* Q = nullptr;       // m_eff x m_eff
+    cplx* g = nullptr;
+    cplx* qlast = nullptr;
+    std::vector<cplx> H_host;   // (m_eff+1) x m_eff column-major
+    std::vector<cplx> ritz;     // sigma + 1/theta
+    bool borrowed = false;      // owned by a simm_result
+    ~simm_shift_s() {
+        (void)hipFree(AB);
+        (void)hipFree(ipiv);
+        (void)hipFree(V);
+        (void)hipFree(H);
+        (void)hipFree(T);
+        (void)hipFree(Q);
+        (void)hipFree(g);
+        (void)hipFree(qlast);
+    }
+};
+
+struct LevelRec {
+    std::vector<int64_t> ix, iy;
+    std::vector<int32_t> shift;
+    std::vector<double> indicator, rho_max, nsf, nsc, Tf, full_indicator;
+    std::vector<uint8_t> decision;
+};
+
+struct ClusterRec {
+    cplx lam, lam_ritz;
+    int shift;
+    int flags;
+};
+
+struct simm_result_s {
+    int K = 0;
+    std::vector<std::unique_ptr<simm_shift_s>> shifts;
+    std::vector<LevelRec> levels;
+    std::vector<ClusterRec> clusters;
+    double ms[4] = {0, 0, 0, 0};
+    int64_t counters[3] = {0, 0, 0};
+};
+
+namespace {
+
+// Gauss-Legendre nodes (ascending) and weights on [-1, 1] by Newton's method on P_g.
+void gauss_legendre(int g, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(g, 0.0);
+    w.assign(g, 0.0);
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < (g + 1) / 2; ++i) {
+        double z = std::cos(pi * (i + 0.75) / (g + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= g; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (g == 1) {
+                p1 = z;
+                p0 = 1.0;
+            }
+            dp = g * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) {
+                // one more evaluation at the converged point for the weight
+                p0 = 1.0;
+                p1 = z;
+                for (int k = 2; k <= g; ++k) {
+                    const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                    p0 = p1;
+                    p1 = p2;
+                }
+                dp = g * (z * p1 - p0) / (z * z - 1.0);
+                break;
+            }
+        }
+        const double wt = 2.0 / ((1.0 - z * z) * dp * dp);
+        x[g - 1 - i] = z;      // z > 0 for small i
+        x[i] = -z;
+        w[g - 1 - i] = wt;
+        w[i] = wt;
+    }
+    if (g % 2 == 1) x[g / 2] = 0.0;
+}
+
+bool finite_c(const double* v, int64_t count) {
+    for (int64_t i = 0; i < count; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+template <typename T>
+simm_status dalloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, sizeof(T) * count);
+    if (e != hipSuccess) {
+        set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? SIMM_ENOMEM : SIMM_EHIP;
+    }
+    return SIMM_OK;
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() { (void)hipFree(p); }
+    simm_status alloc(size_t bytes) {
+        (void)hipFree(p);
+        p = nullptr;
+        hipError_t e = hipMalloc(&p, bytes ? bytes : 1);
+        if (e != hipSuccess) {
+            set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+            return e == hipErrorOutOfMemory ? SIMM_ENOMEM : SIMM_EHIP;
+        }
+        return SIMM_OK;
+    }
+    template <typename T>
+    T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+simm_status check_device() {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count == 0) {
+        set_error("no HIP device");
+        return SIMM_ENODEV;
+    }
+    return SIMM_OK;
+}
+
+struct Rule {
+    DevBuf buf;
+    int g = 0;
+    RuleDev dev{};
+    simm_status make(int g_) {
+        g = g_;
+        std::vector<double> t1, w1, t2, w2;
+        gauss_legendre(g, t1, w1);
+        gauss_legendre(2 * g, t2, w2);
+        std::vector<double> all;
+        all.insert(all.end(), t1.begin(), t1.end());
+        all.insert(all.end(), w1.begin(), w1.end());
+        all.insert(all.end(), t2.begin(), t2.end());
+        all.insert(all.end(), w2.begin(), w2.end());
+        SIMM_TRY(buf.alloc(all.size() * sizeof(double)));
+        SIMM_HIP_TRY(hipMemcpy(buf.p, all.data(), all.size() * sizeof(double), hipMemcpyHostToDevice));
+        double* d = buf.as<double>();
+        dev.t1 = d;
+        dev.w1 = d + g;
+        dev.t2 = d + 2 * g;
+        dev.w2 = d + 4 * g;
+        dev.g = g;
+        return SIMM_OK;
+    }
+};
+
+ShiftDev shift_dev(const simm_shift_s* s) {
+    ShiftDev d;
+    d.T = s->T;
+    d.Q = s->Q;
+    d.g = s->g;
+    d.qlast = s->qlast;
+    d.sig_re = s->sigma.re;
+    d.sig_im = s->sigma.im;
+    d.beta = s->beta;
+    d.h_last = s->h_last;
+    d.m = s->m_eff;
+    d.pad = 0;
+    return d;
+}
+
+// Builds LU, Arnoldi basis and Schur data of one shift (hot-path steps a1-a5).
+simm_status build_shift(simm_pencil_s* p, cplx sigma, const cplx* f_dev, int m, hipStream_t st,
+                        std::unique_ptr<simm_shift_s>& out, int64_t* applies) {
+    auto s = std::make_unique<simm_shift_s>();
+    s->p = p;
+    s->sigma = sigma;
+    s->m = m;
+    const int64_t n = p->n;
+    const int kl = std::max(p->kla, p->klb);
+    const int ku = std::max(p->kua, p->kub);
+    s->kl = kl;
+    s->ku = ku;
+    const int ldab = 2 * kl + ku + 1;
+    if (lu_panel_width(kl) == 0 || sweep_threads(kl, ku) > 1024) {
+        set_error("pencil bandwidth outside the supported range (kl <= 480, kl + ku <= 1022)");
+        return SIMM_EUNSUPPORTED;
+    }
+    SIMM_TRY(dalloc(&s->AB, (size_t)ldab * n));
+    SIMM_TRY(dalloc(&s->ipiv, (size_t)n));
+    SIMM_TRY(dalloc(&s->V, (size_t)n * (m + 1)));
+    SIMM_TRY(dalloc(&s->H, (size_t)(m + 1) * m));
+    SIMM_HIP_TRY(hipMemsetAsync(s->H, 0, sizeof(cplx) * (m + 1) * m, st));
+
+    // scratch: LU panel buffers, info; Arnoldi work; flags
+    const int nblk = (int)std::min<int64_t>(256, std::max<int64_t>(1, (n + 63) / 64));
+    const int64_t rows = (n + nblk - 1) / nblk;
+    const int nblk_eff = (int)((n + rows - 1) / rows);
+    const size_t lt_elems = band_lu_scratch_elems(kl);
+    DevBuf work;
+    const size_t bytes = sizeof(cplx) * (lt_elems + (size_t)nblk_eff * (m + 2) + 2 * (size_t)(m + 2) + (size_t)n) +
+                         sizeof(double) * 4 + sizeof(int) * 8;
+    SIMM_TRY(work.alloc(bytes + 16 * 256));
+    char* wp = work.as<char>();
+    auto take = [&](size_t b) {
+        char* r = wp;
+        wp += (b + 255) & ~(size_t)255;
+        return r;
+    };
+    cplx* lt = reinterpret_cast<cplx*>(take(sizeof(cplx) * lt_elems));
+    ArnoldiWork aw;
+    aw.nblk = nblk_eff;
+    aw.partial = reinterpret_cast<cplx*>(take(sizeof(cplx) * (size_t)nblk_eff * (m + 2)));
+    aw.h1 = reinterpret_cast<cplx*>(take(sizeof(cplx) * (m + 2)));
+    aw.h2 = reinterpret_cast<cplx*>(take(sizeof(cplx) * (m + 2)));
+    aw.hnorm = reinterpret_cast<double*>(take(sizeof(double) * 4));
+    aw.u = reinterpret_cast<cplx*>(take(sizeof(cplx) * (size_t)n));
+    int* flags = reinterpret_cast<int*>(take(sizeof(int) * 8));   // [0] info, [1] active, [2] m_eff, [3] schur status
+    double* beta_d = aw.hnorm + 2;
+    {
+        int init[4] = {INT_MAX, 1, m, 0};
+        SIMM_HIP_TRY(hipMemcpyAsync(flags, init, sizeof(init), hipMemcpyHostToDevice, st));
+    }
+
+    // a1 + a2: shifted band and its LU
+    SIMM_TRY(assemble_shifted(n, kl, ku, p->A, p->kla, p->kua, p->B, p->klb, p->kub, sigma, s->AB, st));
+    SIMM_TRY(band_lu(n, kl, ku, s->AB, s->ipiv, lt, flags + 0, st));
+    int info = INT_MAX;
+    SIMM_HIP_TRY(hipMemcpyAsync(&info, flags + 0, sizeof(int), hipMemcpyDeviceToHost, st));
+    SIMM_HIP_TRY(hipStreamSynchronize(st));
+    if (info != INT_MAX) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg, "exact zero pivot in column %d of A - sigma B (sigma = %.17g%+.17gi)", info,
+                      sigma.re, sigma.im);
+        set_error(msg);
+        return SIMM_ESINGULAR_SHIFT;
+    }
+    // a3: b = (A - sigma B)^{-1} f, beta, v_1
+    SIMM_TRY(band_sweep(n, kl, ku, s->AB, s->ipiv, f_dev, nullptr, s->V, st));
+    SIMM_TRY(vec_norm_scale(n, s->V, s->V, beta_d, aw, st));
+    // a4: Arnoldi steps
+    for (int j = 0; j < m; ++j) {
+        cplx* vj = s->V + (int64_t)j * n;
+        SIMM_TRY(prepare_input(n, vj, p->B, p->klb, p->kub, nullptr, flags + 1, aw.u, nullptr, st));
+        SIMM_TRY(band_sweep(n, kl, ku, s->AB, s->ipiv, aw.u, flags + 1, s->V + (int64_t)(j + 1) * n, st));
+        SIMM_TRY(arnoldi_step(n, s->V, n, j, s->H, m + 1, aw, flags + 1, flags + 2, st));
+    }
+    int fl[4];
+    double beta = 0.0;
+    SIMM_HIP_TRY(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, st));
+    SIMM_HIP_TRY(hipMemcpyAsync(&beta, beta_d, sizeof(double), hipMemcpyDeviceToHost, st));
+    std::vector<cplx> Hfull((size_t)(m + 1) * m);
+    SIMM_HIP_TRY(hipMemcpyAsync(Hfull.data(), s->H, sizeof(cplx) * Hfull.size(), hipMemcpyDeviceToHost, st));
+    SIMM_HIP_TRY(hipStreamSynchronize(st));
+    s->m_eff = fl[2];
+    s->beta = beta;
+    const int me = s->m_eff;
+    if (applies) *applies += me + 1;
+    s->H_host.assign((size_t)(me + 1) * me, cplx{0, 0});
+    for (int j = 0; j < me; ++j)
+        for (int i = 0; i <= me; ++i) s->H_host[i + (size_t)j * (me + 1)] = Hfull[i + (size_t)j * (m + 1)];
+    s->h_last = cabs(s->H_host[me + (size_t)(me - 1) * (me + 1)]);
+    // a5: Schur form of H_m
+    SIMM_TRY(dalloc(&s->T, (size_t)me * (me + 1) / 2));
+    SIMM_TRY(dalloc(&s->Q, (size_t)me * me));
+    SIMM_TRY(dalloc(&s->g, (size_t)me));
+    SIMM_TRY(dalloc(&s->qlast, (size_t)me));
+    SchurOut so{s->T, s->Q, s->g, s->qlast};
+    SIMM_TRY(hess_schur(s->H, m + 1, me, beta, so, flags + 3, st));
+    int schur_status = 0;
+    std::vector<cplx> Tp((size_t)me * (me + 1) / 2);
+    SIMM_HIP_TRY(hipMemcpyAsync(&schur_status, flags + 3, sizeof(int), hipMemcpyDeviceToHost, st));
+    SIMM_HIP_TRY(hipMemcpyAsync(Tp.data(), s->T, sizeof(cplx) * Tp.size(), hipMemcpyDeviceToHost, st));
+    SIMM_HIP_TRY(hipStreamSynchronize(st));
+    if (schur_status != 0) {
+        set_error("QR iteration for the Schur form of H_m did not converge");
+        return SIMM_ENOCONV;
+    }
+    s->ritz.resize(me);
+    for (int k = 0; k < me; ++k) {
+        const cplx th = Tp[(size_t)k * (k + 1) / 2 + k];
+        if (th.re == 0.0 && th.im == 0.0) {
+            s->ritz[k] = cplx{NAN, NAN};
+        } else {
+            const cplx inv = cdiv(cplx{1.0, 0.0}, th);
+            s->ritz[k] = cplx{sigma.re + inv.re, sigma.im + inv.im};
+        }
+    }
+    out = std::move(s);
+    return SIMM_OK;
+}
+
+struct EvalOut {
+    std::vector<double> indicator, rho, nsf, nsc, Tf;
+    std::vector<uint8_t> decision;
+};
+
+// Evaluate (level, ix, iy, shift) rows on the device; results copied to host.
+simm_status evaluate(const std::vector<simm_shift_s*>& shifts, const std::vector<int64_t>& regs, const simm_params* prm,
+                     const Rule& rule, hipStream_t st, EvalOut& out, cplx* sums_dev, int m_sums) {
+    const int64_t N = (int64_t)regs.size() / 4;
+    out.indicator.assign(N, 0);
+    out.rho.assign(N, 0);
+    out.nsf.assign(N, 0);
+    out.nsc.assign(N, 0);
+    out.Tf.assign(N, 0);
+    out.decision.assign(N, 0);
+    if (N == 0) return SIMM_OK;
+    std::vector<ShiftDev> sd;
+    int mmax = 1;
+    for (auto* s : shifts) {
+        sd.push_back(shift_dev(s));
+        mmax = std::max(mmax, s->m_eff);
+    }
+    DevBuf b;
+    const size_t bytes = sizeof(ShiftDev) * sd.size() + sizeof(int64_t) * regs.size() + sizeof(double) * 5 * N + N + 1024;
+    SIMM_TRY(b.alloc(bytes));
+    char* p = b.as<char>();
+    ShiftDev* sdd = reinterpret_cast<ShiftDev*>(p);
+    p += (sizeof(ShiftDev) * sd.size() + 255) & ~(size_t)255;
+    int64_t* rd = reinterpret_cast<int64_t*>(p);
+    p += (sizeof(int64_t) * regs.size() + 255) & ~(size_t)255;
+    double* o = reinterpret_cast<double*>(p);
+    uint8_t* dec = reinterpret_cast<uint8_t*>(o + 5 * N);
+    SIMM_HIP_TRY(hipMemcpyAsync(sdd, sd.data(), sizeof(ShiftDev) * sd.size(), hipMemcpyHostToDevice, st));
+    SIMM_HIP_TRY(hipMemcpyAsync(rd, regs.data(), sizeof(int64_t) * regs.size(), hipMemcpyHostToDevice, st));
+    IndicatorParams ip;
+    ip.x0 = prm->x0;
+    ip.y0 = prm->y0;
+    ip.w1 = (prm->x1 - prm->x0) / prm->n1;
+    ip.eps0 = prm->eps0;
+    ip.delta0 = prm->delta0;
+    ip.tau = prm->tau;
+    SIMM_TRY(indicators(sdd, mmax, rd, N, ip, rule.dev, o, o + N, o + 2 * N, o + 3 * N, o + 4 * N, dec, sums_dev,
+                        m_sums, st));
+    std::vector<double> host(5 * N);
+    SIMM_HIP_TRY(hipMemcpyAsync(host.data(), o, sizeof(double) * 5 * N, hipMemcpyDeviceToHost, st));
+    SIMM_HIP_TRY(hipMemcpyAsync(out.decision.data(), dec, N, hipMemcpyDeviceToHost, st));
+    SIMM_HIP_TRY(hipStreamSynchronize(st));
+    for (int64_t r = 0; r < N; ++r) {
+        out.indicator[r] = host[r];
+        out.rho[r] = host[N + r];
+        out.nsf[r] = host[2 * N + r];
+        out.nsc[r] = host[3 * N + r];
+        out.Tf[r] = host[4 * N + r];
+    }
+    return SIMM_OK;
+}
+
+simm_status validate_params(const simm_params* prm, int64_t n, int* nx, int* ny, int* K) {
+    if (!prm) {
+        set_error("params is NULL");
+        return SIMM_EINVAL;
+    }
+    const double vals[] = {prm->x0, prm->x1, prm->y0, prm->y1, prm->eps0, prm->delta0, prm->tau};
+    for (double v : vals)
+        if (!std::isfinite(v)) {
+            set_error("non-finite parameter");
+            return SIMM_EINVAL;
+        }
+    if (!(prm->x1 > prm->x0) || !(prm->y1 > prm->y0) || prm->n1 < 1) {
+        set_error("empty region or n1 < 1");
+        return SIMM_EINVAL;
+    }
+    if (prm->m < 1 || prm->m > n) {
+        set_error("need 1 <= m <= n");
+        return SIMM_EINVAL;
+    }
+    if (prm->m > 128) {
+        set_error("Krylov dimension above 128 is not supported");
+        return SIMM_EUNSUPPORTED;
+    }
+    if (prm->gauss_per_edge < 1) {
+        set_error("gauss_per_edge >= 1");
+        return SIMM_EINVAL;
+    }
+    if (prm->gauss_per_edge > 64) {
+        set_error("gauss_per_edge above 64 is not supported");
+        return SIMM_EUNSUPPORTED;
+    }
+    const double w1 = (prm->x1 - prm->x0) / prm->n1;
+    const double nyf = (prm->y1 - prm->y0) / w1;
+    const long long nyr = std::llround(nyf);
+    if (nyr < 1 || std::fabs(nyr * w1 - (prm->y1 - prm->y0)) > 1e-12 * std::fabs(prm->y1 - prm->y0)) {
+        set_error("level-1 cells must be square: (y1-y0)/((x1-x0)/n1) must be an integer");
+        return SIMM_EINVAL;
+    }
+    *nx = prm->n1;
+    *ny = (int)nyr;
+    if (prm->levels > 0) {
+        *K = prm->levels;
+    } else {
+        if (!(prm->h0 > 0) || !std::isfinite(prm->h0)) {
+            set_error("h0 > 0 or levels > 0 required");
+            return SIMM_EINVAL;
+        }
+        *K = 1 + std::max(0, (int)std::ceil(std::log2(w1 / prm->h0)));
+    }
+    if (*K > 60) {
+        set_error("too many levels");
+        return SIMM_EINVAL;
+    }
+    return SIMM_OK;
+}
+
+cplx cell_center(const simm_params* prm, int level, int64_t ix, int64_t iy) {
+    const double w1 = (prm->x1 - prm->x0) / prm->n1;
+    const double w = std::ldexp(w1, 1 - level);
+    volatile double ax = ((double)ix + 0.5) * w;
+    volatile double ay = ((double)iy + 0.5) * w;
+    return cplx{prm->x0 + ax, prm->y0 + ay};
+}
+
+double cdist(cplx a, cplx b) { return std::hypot(a.re - b.re, a.im - b.im); }
+
+std::vector<int> shift_order(const std::vector<simm_shift_s*>& shifts, cplx c, int exclude) {
+    std::vector<int> idx;
+    for (int s = 0; s < (int)shifts.size(); ++s)
+        if (s != exclude) idx.push_back(s);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+        const double da = cdist(shifts[a]->sigma, c), db = cdist(shifts[b]->sigma, c);
+        if (da != db) return da < db;
+        return a < b;
+    });
+    return idx;
+}
+
+struct Timer {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t st;
+    double* acc;
+    Timer(hipStream_t s, double* ms) : st(s), acc(ms) {
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+        (void)hipEventRecord(a, st);
+    }
+    ~Timer() {
+        (void)hipEventRecord(b, st);
+        (void)hipEventSynchronize(b);
+        float t = 0;
+        (void)hipEventElapsedTime(&t, a, b);
+        *acc += t;
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+};
+
+__global__ void k_gather_sums(const cplx* sums, int m_sums, const int64_t* regs, int64_t cnt, cplx* Y) {
+    // Y(:, 2q + w) = sums(:, 2 regs[q] + w)
+    const int64_t col = blockIdx.x;
+    if (col >= 2 * cnt) return;
+    const int64_t r = regs[col / 2];
+    const int w = (int)(col & 1);
+    for (int i = threadIdx.x; i < m_sums; i += blockDim.x) Y[col * m_sums + i] = sums[(2 * r + w) * m_sums + i];
+}
+
+simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hipStream_t st, simm_result_s* R) {
+    int nx, ny, K;
+    SIMM_TRY(validate_params(prm, p->n, &nx, &ny, &K));
+    R->K = K;
+    Rule rule;
+    SIMM_TRY(rule.make(prm->gauss_per_edge));
+    const int m = prm->m;
+    const bool do_proj = (prm->flags & SIMM_FLAG_PROJECT) != 0;
+    const int64_t maxreg = prm->max_regions_per_level > 0 ? prm->max_regions_per_level : ((int64_t)1 << 22);
+    std::vector<simm_shift_s*> shifts;
+    auto new_shift = [&](cplx c) -> simm_status {
+        std::unique_ptr<simm_shift_s> s;
+        {
+            Timer t(st, &R->ms[0]);
+            SIMM_TRY(build_shift(p, c, f_dev, m, st, s, &R->counters[2]));
+        }
+        s->borrowed = true;
+        shifts.push_back(s.get());
+        R->shifts.push_back(std::move(s));
+        return SIMM_OK;
+    };
+    // step 1: first shift at the centre of R
+    SIMM_TRY(new_shift(cplx{(prm->x0 + prm->x1) / 2, (prm->y0 + prm->y1) / 2}));
+
+    // steps 2-3: level-1 cells and shift association
+    std::vector<std::pair<int64_t, int64_t>> cells;
+    for (int iy = 0; iy < ny; ++iy)
+        for (int ix = 0; ix < nx; ++ix) cells.emplace_back(ix, iy);
+    const int64_t ncell = (int64_t)cells.size();
+    std::map<std::pair<int64_t, int>, bool> resolv;   // (cell, shift) -> resolvable
+    auto eval_cells_vs = [&](int s) -> simm_status {
+        std::vector<int64_t> regs;
+        for (int64_t c = 0; c < ncell; ++c) {
+            regs.push_back(1);
+            regs.push_back(cells[c].first);
+            regs.push_back(cells[c].second);
+            regs.push_back(s);
+        }
+        EvalOut eo;
+        {
+            Timer t(st, &R->ms[1]);
+            SIMM_TRY(evaluate(shifts, regs, prm, rule, st, eo, nullptr, 0));
+        }
+        for (int64_t c = 0; c < ncell; ++c) resolv[{c, s}] = eo.rho[c] <= prm->eps0;
+        return SIMM_OK;
+    };
+    SIMM_TRY(eval_cells_vs(0));
+    std::vector<int> assoc(ncell, -1);
+    for (int64_t c = 0; c < ncell; ++c) {
+        const cplx ctr = cell_center(prm, 1, cells[c].first, cells[c].second);
+        int chosen = -1;
+        for (int s : shift_order(shifts, ctr, -1))
+            if (resolv[{c, s}]) {
+                chosen = s;
+                break;
+            }
+        if (chosen < 0) {
+            SIMM_TRY(new_shift(ctr));
+            chosen = (int)shifts.size() - 1;
+            SIMM_TRY(eval_cells_vs(chosen));
+        }
+        assoc[c] = chosen;
+    }
+
+    // steps 4-5: level loop
+    struct Sq {
+        int64_t ix, iy;
+        int s;
+    };
+    std::vector<Sq> cur;
+    for (int64_t c = 0; c < ncell; ++c) cur.push_back({cells[c].first, cells[c].second, assoc[c]});
+    const int m_sums = m;
+    DevBuf sums_buf, sums_fb, Ybuf, Xbuf, nrm_buf, scr_buf, idx_buf;
+    const int64_t n = p->n;
+    for (int k = 1; k <= K; ++k) {
+        const int64_t N = (int64_t)cur.size();
+        if (N > maxreg) {
+            char msg[128];
+            std::snprintf(msg, sizeof msg, "level %d holds %lld squares (limit %lld)", k, (long long)N,
+                          (long long)maxreg);
+            set_error(msg);
+            return SIMM_ELIMIT;
+        }
+        std::vector<int64_t> regs;
+        regs.reserve(4 * N);
+        for (auto& q : cur) {
+            regs.push_back(k);
+            regs.push_back(q.ix);
+            regs.push_back(q.iy);
+            regs.push_back(q.s);
+        }
+        cplx* sums_dev = nullptr;
+        if (do_proj) {
+            SIMM_TRY(sums_buf.alloc(sizeof(cplx) * (size_t)N * 2 * m_sums));
+            sums_dev = sums_buf.as<cplx>();
+        }
+        EvalOut eo;
+        {
+            Timer t(st, &R->ms[1]);
+            SIMM_TRY(evaluate(shifts, regs, prm, rule, st, eo, sums_dev, m_sums));
+        }
+        std::vector<int> used(N);
+        for (int64_t r = 0; r < N; ++r) used[r] = cur[r].s;
+        // fallback: other shifts nearest-first for squares the inherited shift does not resolve
+        std::vector<int64_t> pend;
+        for (int64_t r = 0; r < N; ++r)
+            if (eo.decision[r] == SIMM_UNRESOLVED) pend.push_back(r);
+        std::map<int64_t, std::vector<int>> cand;
+        for (int64_t r : pend) cand[r] = shift_order(shifts, cell_center(prm, k, cur[r].ix, cur[r].iy), cur[r].s);
+        for (size_t round = 0; !pend.empty(); ++round) {
+            std::vector<int64_t> tryr;
+            std::vector<int64_t> tregs;
+            for (int64_t r : pend) {
+                if (round < cand[r].size()) {
+                    tryr.push_back(r);
+                    tregs.push_back(k);
+                    tregs.push_back(cur[r].ix);
+                    tregs.push_back(cur[r].iy);
+                    tregs.push_back(cand[r][round]);
+                }
+            }
+            if (tryr.empty()) break;
+            cplx* fb_dev = nullptr;
+            if (do_proj) {
+                SIMM_TRY(sums_fb.alloc(sizeof(cplx) * tryr.size() * 2 * m_sums));
+                fb_dev = sums_fb.as<cplx>();
+            }
+            EvalOut e2;
+            {
+                Timer t(st, &R->ms[1]);
+                SIMM_TRY(evaluate(shifts, tregs, prm, rule, st, e2, fb_dev, m_sums));
+            }
+            std::vector<int64_t> still;
+            for (size_t q = 0; q < tryr.size(); ++q) {
+                const int64_t r = tryr[q];
+                if (e2.decision[q] != SIMM_UNRESOLVED) {
+                    eo.indicator[r] = e2.indicator[q];
+                    eo.rho[r] = e2.rho[q];
+                    eo.nsf[r] = e2.nsf[q];
+                    eo.nsc[r] = e2.nsc[q];
+                    eo.Tf[r] = e2.Tf[q];
+                    eo.decision[r] = e2.decision[q];
+                    used[r] = (int)tregs[4 * q + 3];
+                    if (do_proj)
+                        SIMM_HIP_TRY(hipMemcpyAsync(sums_dev + (size_t)r * 2 * m_sums, fb_dev + q * 2 * m_sums,
+                                                    sizeof(cplx) * 2 * m_sums, hipMemcpyDeviceToDevice, st));
+                } else {
+                    still.push_back(r);
+                }
+            }
+            std::vector<int64_t> next;
+            for (int64_t r : pend) {
+                bool tried = std::find(tryr.begin(), tryr.end(), r) != tryr.end();
+                bool ok = tried && std::find(still.begin(), still.end(), r) == still.end();
+                if (!ok && (tried || round < cand[r].size())) next.push_back(r);
+            }
+            pend.swap(next);
+        }
+        R->counters[0] += N * 12 * (int64_t)prm->gauss_per_edge;
+        R->counters[1] += N;
+        LevelRec L;
+        L.ix.resize(N);
+        L.iy.resize(N);
+        L.shift.resize(N);
+        L.full_indicator.assign(N, NAN);
+        for (int64_t r = 0; r < N; ++r) {
+            L.ix[r] = cur[r].ix;
+            L.iy[r] = cur[r].iy;
+            L.shift[r] = used[r];
+        }
+        L.indicator = eo.indicator;
+        L.rho_max = eo.rho;
+        L.nsf = eo.nsf;
+        L.nsc = eo.nsc;
+        L.Tf = eo.Tf;
+        L.decision = eo.decision;
+
+        // a9: X = V_m Y for the squares of this level, shift by shift
+        if (do_proj) {
+            Timer t(st, &R->ms[2]);
+            std::vector<std::vector<int64_t>> by_shift(shifts.size());
+            for (int64_t r = 0; r < N; ++r) by_shift[used[r]].push_back(r);
+            int64_t cmax = 0;
+            for (auto& v : by_shift) cmax = std::max<int64_t>(cmax, 2 * (int64_t)v.size());
+            SIMM_TRY(Ybuf.alloc(sizeof(cplx) * (size_t)cmax * m_sums));
+            SIMM_TRY(Xbuf.alloc(sizeof(cplx) * (size_t)cmax * n));
+            SIMM_TRY(nrm_buf.alloc(sizeof(double) * (size_t)cmax));
+            SIMM_TRY(scr_buf.alloc(sizeof(double) * (size_t)project_scratch_elems(n, cmax)));
+            SIMM_TRY(idx_buf.alloc(sizeof(int64_t) * (size_t)std::max<int64_t>(1, N)));
+            std::vector<double> nrm_host;
+            for (size_t s = 0; s < shifts.size(); ++s) {
+                const auto& rs = by_shift[s];
+                if (rs.empty()) continue;
+                const int64_t cnt = (int64_t)rs.size();
+                SIMM_HIP_TRY(hipMemcpyAsync(idx_buf.p, rs.data(), sizeof(int64_t) * cnt, hipMemcpyHostToDevice, st));
+                hipLaunchKernelGGL(k_gather_sums, dim3((unsigned)(2 * cnt)), dim3(128), 0, st, (const cplx*)sums_dev,
+                                   m_sums, idx_buf.as<const int64_t>(), cnt, Ybuf.as<cplx>());
+                SIMM_HIP_TRY(hipGetLastError());
+                SIMM_TRY(project(n, shifts[s]->m_eff, shifts[s]->V, n, Ybuf.as<const cplx>(), m_sums, 2 * cnt,
+                                 Xbuf.as<cplx>(), nrm_buf.as<double>(), scr_buf.as<double>(),
+                                 project_scratch_elems(n, cmax), st));
+                nrm_host.assign(2 * cnt, 0.0);
+                SIMM_HIP_TRY(hipMemcpyAsync(nrm_host.data(), nrm_buf.p, sizeof(double) * 2 * cnt,
+                                            hipMemcpyDeviceToHost, st));
+                SIMM_HIP_TRY(hipStreamSynchronize(st));
+                for (int64_t q = 0; q < cnt; ++q) L.full_indicator[rs[q]] = nrm_host[2 * q + 1] / nrm_host[2 * q];
+            }
+        }
+        R->levels.push_back(std::move(L));
+        if (k < K) {
+            std::vector<Sq> nxt;
+            for (int64_t r = 0; r < N; ++r) {
+                if (eo.decision[r] == SIMM_REJECTED) continue;
+                for (int b = 0; b < 2; ++b)
+                    for (int a = 0; a < 2; ++a) nxt.push_back({2 * cur[r].ix + a, 2 * cur[r].iy + b, used[r]});
+            }
+            std::stable_sort(nxt.begin(), nxt.end(), [](const Sq& u, const Sq& v) {
+                if (u.iy != v.iy) return u.iy < v.iy;
+                return u.ix < v.ix;
+            });
+            cur.swap(nxt);
+        }
+    }
+
+    // steps 6-7: clusters of the marked level-K squares
+    const LevelRec& last = R->levels.back();
+    std::map<std::pair<int64_t, int64_t>, int64_t> pos;
+    std::vector<int64_t> marked;
+    for (int64_t r = 0; r < (int64_t)last.decision.size(); ++r)
+        if (last.decision[r] != SIMM_REJECTED) {
+            marked.push_back(r);
+            pos[{last.ix[r], last.iy[r]}] = r;
+        }
+    std::set<std::pair<int64_t, int64_t>> seen;
+    const double wK = std::ldexp((prm->x1 - prm->x0) / prm->n1, 1 - K);
+    for (int64_t r0 : marked) {
+        const std::pair<int64_t, int64_t> key{last.ix[r0], last.iy[r0]};
+        if (seen.count(key)) continue;
+        std::vector<int64_t> comp;
+        std::vector<std::pair<int64_t, int64_t>> stack{key};
+        seen.insert(key);
+        while (!stack.empty()) {
+            auto cu = stack.back();
+            stack.pop_back();
+            comp.push_back(pos[cu]);
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    std::pair<int64_t, int64_t> nb{cu.first + dx, cu.second + dy};
+                    if (pos.count(nb) && !seen.count(nb)) {
+                        seen.insert(nb);
+                        stack.push_back(nb);
+                    }
+                }
+        }
+        std::sort(comp.begin(), comp.end(), [&](int64_t a, int64_t b) {
+            if (last.iy[a] != last.iy[b]) return last.iy[a] < last.iy[b];
+            return last.ix[a] < last.ix[b];
+        });
+        double sr = 0, si = 0, xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
+        int flags = 0;
+        for (int64_t q : comp) {
+            const cplx c = cell_center(prm, K, last.ix[q], last.iy[q]);
+            sr += c.re;
+            si += c.im;
+            xmin = std::min(xmin, c.re);
+            xmax = std::max(xmax, c.re);
+            ymin = std::min(ymin, c.im);
+            ymax = std::max(ymax, c.im);
+            if (last.decision[q] == SIMM_UNRESOLVED) flags |= 1;
+        }
+        ClusterRec cr;
+        cr.lam = cplx{sr / comp.size(), si / comp.size()};
+        cr.shift = last.shift[comp[0]];
+        cr.flags = flags;
+        cr.lam_ritz = cplx{NAN, NAN};
+        double best = INFINITY;
+        for (const cplx& rv : R->shifts[cr.shift]->ritz) {
+            if (!std::isfinite(rv.re) || !std::isfinite(rv.im)) continue;
+            if (rv.re < xmin - wK || rv.re > xmax + wK || rv.im < ymin - wK || rv.im > ymax + wK) continue;
+            const double d = cdist(rv, cr.lam);
+            if (d < best) {
+                best = d;
+                cr.lam_ritz = rv;
+            }
+        }
+        R->clusters.push_back(cr);
+    }
+    return SIMM_OK;
+}
+
+simm_status to_device_vec(const double* src, int32_t mem, int64_t count, DevBuf& buf, const cplx** out,
+                          hipStream_t st) {
+    if (mem == SIMM_MEM_DEVICE) {
+        *out = reinterpret_cast<const cplx*>(src);
+        return SIMM_OK;
+    }
+    if (mem != SIMM_MEM_HOST) {
+        set_error("mem must be SIMM_MEM_HOST or SIMM_MEM_DEVICE");
+        return SIMM_EINVAL;
+    }
+    if (!finite_c(src, 2 * count)) {
+        set_error("input vector has NaN/Inf");
+        return SIMM_EINVAL;
+    }
+    SIMM_TRY(buf.alloc(sizeof(cplx) * (size_t)count));
+    SIMM_HIP_TRY(hipMemcpyAsync(buf.p, src, sizeof(cplx) * (size_t)count, hipMemcpyHostToDevice, st));
+    *out = buf.as<const cplx>();
+    return SIMM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// exported C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* simm_last_error(void) { return g_err.c_str(); }
+int32_t simm_version(void) { return 1; }
+
+simm_status simm_params_default(simm_params* p) {
+    if (!p) return SIMM_EINVAL;
+    std::memset(p, 0, sizeof(*p));
+    p->x0 = -1;
+    p->x1 = 1;
+    p->y0 = -1;
+    p->y1 = 1;
+    p->n1 = 8;
+    p->gauss_per_edge = 8;
+    p->m = 50;
+    p->levels = 0;
+    p->h0 = 1e-6;
+    p->eps0 = 1e-8;
+    p->delta0 = 0.05;
+    p->tau = 1e-8;
+    p->max_regions_per_level = (int64_t)1 << 22;
+    p->flags = 0;
+    return SIMM_OK;
+}
+
+simm_status simm_pencil_create_banded(int64_t n, int32_t kl_a, int32_t ku_a, const double* a_band, int32_t kl_b,
+                                      int32_t ku_b, const double* b_band, int32_t mem, void* hip_stream,
+                                      simm_pencil* out) {
+    clear_error();
+    if (!out) return SIMM_EINVAL;
+    *out = nullptr;
+    if (n < 1 || kl_a < 0 || ku_a < 0 || !a_band || (b_band && (kl_b < 0 || ku_b < 0))) {
+        set_error("bad pencil arguments");
+        return SIMM_EINVAL;
+    }
+    if (mem != SIMM_MEM_HOST && mem != SIMM_MEM_DEVICE) {
+        set_error("mem must be SIMM_MEM_HOST or SIMM_MEM_DEVICE");
+        return SIMM_EINVAL;
+    }
+    SIMM_TRY(check_device());
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    const size_t na = (size_t)(kl_a + ku_a + 1) * n;
+    const size_t nbb = b_band ? (size_t)(kl_b + ku_b + 1) * n : 0;
+    if (mem == SIMM_MEM_HOST) {
+        if (!finite_c(a_band, 2 * (int64_t)na) || (b_band && !finite_c(b_band, 2 * (int64_t)nbb))) {
+            set_error("pencil has NaN/Inf entries");
+            return SIMM_EINVAL;
+        }
+    }
+    auto p = std::make_unique<simm_pencil_s>();
+    p->n = n;
+    p->kla = kl_a;
+    p->kua = ku_a;
+    p->klb = b_band ? kl_b : 0;
+    p->kub = b_band ? ku_b : 0;
+    SIMM_TRY(dalloc(&p->A, na));
+    const hipMemcpyKind kind = (mem == SIMM_MEM_HOST) ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    SIMM_HIP_TRY(hipMemcpyAsync(p->A, a_band, sizeof(cplx) * na, kind, st));
+    if (b_band) {
+        SIMM_TRY(dalloc(&p->B, nbb));
+        SIMM_HIP_TRY(hipMemcpyAsync(p->B, b_band, sizeof(cplx) * nbb, kind, st));
+    }
+    SIMM_HIP_TRY(hipStreamSynchronize(st));
+    *out = p.release();
+    return SIMM_OK;
+}
+
+simm_status simm_pencil_create_csr(int64_t n, const int64_t* a_rowptr, const int32_t* a_col, const double* a_val,
+                                   const int64_t* b_rowptr, const int32_t* b_col, const double* b_val,
+                                   void* hip_stream, simm_pencil* out) {
+    clear_error();
+    if (!out || n < 1 || !a_rowptr || !a_col || !a_val || (b_rowptr && (!b_col || !b_val))) {
+        set_error("bad CSR arguments");
+        return SIMM_EINVAL;
+    }
+    *out = nullptr;
+    auto bw = [&](const int64_t* rp, const int32_t* ci, int* kl, int* ku) -> simm_status {
+        *kl = 0;
+        *ku = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            if (rp[i + 1] < rp[i]) return SIMM_EINVAL;
+            for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
+                const int64_t j = ci[q];
+                if (j < 0 || j >= n) return SIMM_EINVAL;
+                *kl = (int)std::max<int64_t>(*kl, i - j);
+                *ku = (int)std::max<int64_t>(*ku, j - i);
+            }
+        }
+        return SIMM_OK;
+    };
+    int kla, kua, klb = 0, kub = 0;
+    if (bw(a_rowptr, a_col, &kla, &kua) != SIMM_OK || (b_rowptr && bw(b_rowptr, b_col, &klb, &kub) != SIMM_OK)) {
+        set_error("malformed CSR structure");
+        return SIMM_EINVAL;
+    }
+    if (std::max(kla, kua) > 4096 || std::max(klb, kub) > 4096) {
+        set_error("half-bandwidth above 4096");
+        return SIMM_EUNSUPPORTED;
+    }
+    auto to_band = [&](const int64_t* rp, const int32_t* ci, const double* v, int kl, int ku) {
+        std::vector<double> band((size_t)2 * (kl + ku + 1) * n, 0.0);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
+                const int64_t j = ci[q];
+                const size_t at = 2 * ((size_t)(ku + i - j) + (size_t)j * (kl + ku + 1));
+                band[at] += v[2 * q];
+                band[at + 1] += v[2 * q + 1];
+            }
+        return band;
+    };
+    std::vector<double> ab = to_band(a_rowptr, a_col, a_val, kla, kua);
+    std::vector<double> bb;
+    if (b_rowptr) bb = to_band(b_rowptr, b_col, b_val, klb, kub);
+    return simm_pencil_create_banded(n, kla, kua, ab.data(), klb, kub, b_rowptr ? bb.data() : nullptr,
+                                     SIMM_MEM_HOST, hip_stream, out);
+}
+
+simm_status simm_pencil_info(simm_pencil p, int64_t* n, int32_t* kl, int32_t* ku) {
+    if (!p) return SIMM_EINVAL;
+    if (n) *n = p->n;
+    if (kl) *kl = std::max(p->kla, p->klb);
+    if (ku) *ku = std::max(p->kua, p->kub);
+    return SIMM_OK;
+}
+
+void simm_pencil_destroy(simm_pencil p) {
+    if (!p) return;
+    (void)hipFree(p->A);
+    (void)hipFree(p->B);
+    delete p;
+}
+
+simm_status simm_shift_build(simm_pencil p, double sig_re, double sig_im, const double* f, int32_t f_mem, int32_t m,
+                             void* hip_stream, simm_shift* out) {
+    clear_error();
+    if (!out) return SIMM_EINVAL;
+    *out = nullptr;
+    if (!p || !f || !std::isfinite(sig_re) || !std::isfinite(sig_im)) {
+        set_error("bad shift arguments");
+        return SIMM_EINVAL;
+    }
+    if (m < 1 || m > p->n) {
+        set_error("need 1 <= m <= n");
+        return SIMM_EINVAL;
+    }
+    if (m > 128) {
+        set_error("Krylov dimension above 128 is not supported");
+        return SIMM_EUNSUPPORTED;
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    DevBuf fb;
+    const cplx* fd = nullptr;
+    SIMM_TRY(to_device_vec(f, f_mem, p->n, fb, &fd, st));
+    std::unique_ptr<simm_shift_s> s;
+    SIMM_TRY(build_shift(p, cplx{sig_re, sig_im}, fd, m, st, s, nullptr));
+    *out = s.release();
+    return SIMM_OK;
+}
+
+simm_status simm_shift_info(simm_shift s, double* sigma, double* beta, int32_t* m_eff, double* H, double* ritz) {
+    if (!s) return SIMM_EINVAL;
+    if (sigma) {
+        sigma[0] = s->sigma.re;
+        sigma[1] = s->sigma.im;
+    }
+    if (beta) *beta = s->beta;
+    if (m_eff) *m_eff = s->m_eff;
+    if (H) std::memcpy(H, s->H_host.data(), sizeof(cplx) * s->H_host.size());
+    if (ritz) std::memcpy(ritz, s->ritz.data(), sizeof(cplx) * s->ritz.size());
+    return SIMM_OK;
+}
+
+simm_status simm_shift_basis(simm_shift s, double* V, int32_t mem, void* hip_stream) {
+    clear_error();
+    if (!s || !V) return SIMM_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    const size_t cnt = (size_t)s->p->n * (s->m_eff + 1);
+    SIMM_HIP_TRY(hipMemcpyAsync(V, s->V, sizeof(cplx) * cnt,
+                                mem == SIMM_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
+    SIMM_HIP_TRY(hipStreamSynchronize(st));
+    return SIMM_OK;
+}
+
+simm_status simm_shift_apply(simm_shift s, const double* x, double* y, int32_t mem, void* hip_stream) {
+    clear_error();
+    if (!s || !x || !y || x == y) {
+        set_error("bad apply arguments");
+        return SIMM_EINVAL;
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    const int64_t n = s->p->n;
+    DevBuf xb, ub, yb;
+    const cplx* xd = nullptr;
+    SIMM_TRY(to_device_vec(x, mem, n, xb, &xd, st));
+    SIMM_TRY(ub.alloc(sizeof(cplx) * n));
+    cplx* yd = reinterpret_cast<cplx*>(y);
+    if (mem == SIMM_MEM_HOST) {
+        SIMM_TRY(yb.alloc(sizeof(cplx) * n));
+        yd = yb.as<cplx>();
+    }
+    SIMM_TRY(prepare_input(n, xd, s->p->B, s->p->klb, s->p->kub, nullptr, nullptr, ub.as<cplx>(), nullptr, st));
+    SIMM_TRY(band_sweep(n, s->kl, s->ku, s->AB, s->ipiv, ub.as<const cplx>(), nullptr, yd, st));
+    if (mem == SIMM_MEM_HOST) SIMM_HIP_TRY(hipMemcpyAsync(y, yd, sizeof(cplx) * n, hipMemcpyDeviceToHost, st));
+    SIMM_HIP_TRY(hipStreamSynchronize(st));
+    return SIMM_OK;
+}
+
+void simm_shift_destroy(simm_shift s) {
+    if (s && !s->borrowed) delete s;
+}
+
+simm_status simm_indicators(const simm_shift* shifts, int32_t n_shifts, const int64_t* regions, int64_t n_regions,
+                            const simm_params* params, double* indicator, double* rho_max, double* nsf, double* nsc,
+                            double* Tf, uint8_t* decision, double* sums, int32_t m_max, int32_t mem,
+                            void* hip_stream) {
+    clear_error();
+    if (!shifts || n_shifts < 1 || (!regions && n_regions > 0) || n_regions < 0 || !params) {
+        set_error("bad indicator arguments");
+        return SIMM_EINVAL;
+    }
+    if (mem != SIMM_MEM_HOST && mem != SIMM_MEM_DEVICE) {
+        set_error("mem must be SIMM_MEM_HOST or SIMM_MEM_DEVICE");
+        return SIMM_EINVAL;
+    }
+    if (params->gauss_per_edge < 1) {
+        set_error("gauss_per_edge >= 1");
+        return SIMM_EINVAL;
+    }
+    if (params->gauss_per_edge > 64) {
+        set_error("gauss_per_edge above 64 is not supported");
+        return SIMM_EUNSUPPORTED;
+    }
+    if (!(params->x1 > params->x0) || params->n1 < 1) {
+        set_error("bad region");
+        return SIMM_EINVAL;
+    }
+    int mmax = 1;
+    for (int s = 0; s < n_shifts; ++s) {
+        if (!shifts[s]) return SIMM_EINVAL;
+        mmax = std::max(mmax, shifts[s]->m_eff);
+    }
+    if (sums && m_max < mmax) {
+        set_error("m_max smaller than a shift's m_eff");
+        return SIMM_EINVAL;
+    }
+    if (n_regions == 0) return SIMM_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    std::vector<int64_t> regs((size_t)n_regions * 4);
+    if (mem == SIMM_MEM_HOST) {
+        std::memcpy(regs.data(), regions, sizeof(int64_t) * regs.size());
+    } else {
+        SIMM_HIP_TRY(hipMemcpy(regs.data(), regions, sizeof(int64_t) * regs.size(), hipMemcpyDeviceToHost));
+    }
+    for (int64_t r = 0; r < n_regions; ++r) {
+        if (regs[4 * r] < 1 || regs[4 * r] > 60 || regs[4 * r + 3] < 0 || regs[4 * r + 3] >= n_shifts) {
+            set_error("region row with bad level or shift index");
+            return SIMM_EINVAL;
+        }
+    }
+    std::vector<simm_shift_s*> sv(shifts, shifts + n_shifts);
+    Rule rule;
+    SIMM_TRY(rule.make(params->gauss_per_edge));
+    DevBuf sb;
+    cplx* sums_dev = nullptr;
+    if (sums) {
+        if (mem == SIMM_MEM_DEVICE) {
+            sums_dev = reinterpret_cast<cplx*>(sums);
+        } else {
+            SIMM_TRY(sb.alloc(sizeof(cplx) * (size_t)n_regions * 2 * m_max));
+            sums_dev = sb.as<cplx>();
+        }
+    }
+    EvalOut eo;
+    SIMM_TRY(evaluate(sv, regs, params, rule, st, eo, sums_dev, sums ? m_max : 0));
+    auto put = [&](double* dst, const std::vector<double>& v) -> simm_status {
+        if (!dst) return SIMM_OK;
+        if (mem == SIMM_MEM_HOST) {
+            std::memcpy(dst, v.data(), sizeof(double) * v.size());
+        } else {
+            SIMM_HIP_TRY(hipMemcpy(dst, v.data(), sizeof(double) * v.size(), hipMemcpyHostToDevice));
+        }
+        return SIMM_OK;
+    };
+    SIMM_TRY(put(indicator, eo.indicator));
+    SIMM_TRY(put(rho_max, eo.rho));
+    SIMM_TRY(put(nsf, eo.nsf));
+    SIMM_TRY(put(nsc, eo.nsc));
+    SIMM_TRY(put(Tf, eo.Tf));
+    if (decision) {
+        if (mem == SIMM_MEM_HOST) std::memcpy(decision, eo.decision.data(), eo.decision.size());
+        else SIMM_HIP_TRY(hipMemcpy(decision, eo.decision.data(), eo.decision.size(), hipMemcpyHostToDevice));
+    }
+    if (sums && mem == SIMM_MEM_HOST) {
+        SIMM_HIP_TRY(hipMemcpy(sums, sums_dev, sizeof(cplx) * (size_t)n_regions * 2 * m_max, hipMemcpyDeviceToHost));
+    }
+    SIMM_HIP_TRY(hipStreamSynchronize(st));
+    return SIMM_OK;
+}
+
+simm_status simm_project(simm_shift s, const double* Y, int64_t c, double* X, double* col_norms, void* hip_stream) {
+    clear_error();
+    if (!s || c < 0 || (c > 0 && (!Y || !X))) {
+        set_error("bad projection arguments");
+        return SIMM_EINVAL;
+    }
+    if (c == 0) return SIMM_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    DevBuf scr;
+    const int64_t se = project_scratch_elems(s->p->n, c);
+    if (col_norms) SIMM_TRY(scr.alloc(sizeof(double) * (size_t)se));
+    SIMM_TRY(project(s->p->n, s->m_eff, s->V, s->p->n, reinterpret_cast<const cplx*>(Y), s->m_eff, c,
+                     reinterpret_cast<cplx*>(X), col_norms, col_norms ? scr.as<double>() : nullptr, se, st));
+    SIMM_HIP_TRY(hipStreamSynchronize(st));
+    return SIMM_OK;
+}
+
+simm_status simm_run(simm_pencil p, const simm_params* params, const double* f, int32_t f_mem, void* hip_stream,
+                     simm_result* out) {
+    clear_error();
+    if (!out) return SIMM_EINVAL;
+    *out = nullptr;
+    if (!p || !f || !params) {
+        set_error("bad run arguments");
+        return SIMM_EINVAL;
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    DevBuf fb;
+    const cplx* fd = nullptr;
+    SIMM_TRY(to_device_vec(f, f_mem, p->n, fb, &fd, st));
+    auto R = std::make_unique<simm_result_s>();
+    hipEvent_t e0, e1;
+    SIMM_HIP_TRY(hipEventCreate(&e0));
+    SIMM_HIP_TRY(hipEventCreate(&e1));
+    SIMM_HIP_TRY(hipEventRecord(e0, st));
+    simm_status rc = run(p, params, fd, st, R.get());
+    (void)hipEventRecord(e1, st);
+    (void)hipEventSynchronize(e1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != SIMM_OK) return rc;
+    R->ms[3] = ms;
+    *out = R.release();
+    return SIMM_OK;
+}
+
+simm_status simm_result_summary(simm_result r, int32_t* K, int32_t* n_shifts, int64_t* n_clusters,
+                                int64_t* n_unresolved) {
+    if (!r) return SIMM_EINVAL;
+    if (K) *K = r->K;
+    if (n_shifts) *n_shifts = (int32_t)r->shifts.size();
+    if (n_clusters) *n_clusters = (int64_t)r->clusters.size();
+    if (n_unresolved) {
+        int64_t u = 0;
+        if (!r->levels.empty())
+            for (auto d : r->levels.back().decision) u += (d == SIMM_UNRESOLVED);
+        *n_unresolved = u;
+    }
+    return SIMM_OK;
+}
+
+simm_status simm_result_level(simm_result r, int32_t level, int64_t* n_tested, int64_t* ix, int64_t* iy,
+                              int32_t* shift, double* indicator, double* rho_max, uint8_t* decision, int64_t cap) {
+    clear_error();
+    if (!r || !n_tested || level < 1 || level > (int32_t)r->levels.size()) {
+        set_error("bad level");
+        return SIMM_EINVAL;
+    }
+    const LevelRec& L = r->levels[level - 1];
+    const int64_t N = (int64_t)L.ix.size();
+    *n_tested = N;
+    if (cap < N) {
+        set_error("cap smaller than the number of squares");
+        return SIMM_EINVAL;
+    }
+    for (int64_t q = 0; q < N; ++q) {
+        if (ix) ix[q] = L.ix[q];
+        if (iy) iy[q] = L.iy[q];
+        if (shift) shift[q] = L.shift[q];
+        if (indicator) indicator[q] = L.indicator[q];
+        if (rho_max) rho_max[q] = L.rho_max[q];
+        if (decision) decision[q] = L.decision[q];
+    }
+    return SIMM_OK;
+}
+
+simm_status simm_result_shift(simm_result r, int32_t idx, simm_shift* out) {
+    if (!r || !out || idx < 0 || idx >= (int32_t)r->shifts.size()) return SIMM_EINVAL;
+    *out = r->shifts[idx].get();
+    return SIMM_OK;
+}
+
+simm_status simm_result_clusters(simm_result r, int64_t* n, double* lam, double* lam_ritz, int32_t* shift,
+                                 int32_t* flags, int64_t cap) {
+    clear_error();
+    if (!r || !n) return SIMM_EINVAL;
+    const int64_t N = (int64_t)r->clusters.size();
+    *n = N;
+    if (cap < N) {
+        set_error("cap smaller than the number of clusters");
+        return SIMM_EINVAL;
+    }
+    for (int64_t q = 0; q < N; ++q) {
+        const ClusterRec& c = r->clusters[q];
+        if (lam) {
+            lam[2 * q] = c.lam.re;
+            lam[2 * q + 1] = c.lam.im;
+        }
+        if (lam_ritz) {
+            lam_ritz[2 * q] = c.lam_ritz.re;
+            lam_ritz[2 * q + 1] = c.lam_ritz.im;
+        }
+        if (shift) shift[q] = c.shift;
+        if (flags) flags[q] = c.flags;
+    }
+    return SIMM_OK;
+}
+
+simm_status simm_result_stats(simm_result r, double* ms4, int64_t* counters3) {
+    if (!r) return SIMM_EINVAL;
+    if (ms4)
+        for (int i = 0; i < 4; ++i) ms4[i] = r->ms[i];
+    if (counters3)
+        for (int i = 0; i < 3; ++i) counters3[i] = r->counters[i];
+    return SIMM_OK;
+}
+
+void simm_result_destroy(simm_result r) { delete r; }
+
+}  // extern "C"

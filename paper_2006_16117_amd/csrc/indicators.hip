@@ -1,0 +1,242 @@
+// Shifted Galerkin solves, quadrature sums, indicator norms and decisions for a
+// batch of squares (Sec. 2 eqs. (many), (error), (y), (reduced); Sec. 3.1 eq.
+// (DeltaSm), Definitions 3.1-3.2, Remark 3.3).
+//
+// One workgroup evaluates one (square, shift) pair.  The Schur factor T of H_m
+// (packed upper triangle) sits in LDS; each wavefront takes a quadrature point at
+// a time, lanes own rows of yhat, and the upper triangular system
+// (I + (sigma - z) T) yhat = beta Q^H e_1 is solved by columns from the bottom,
+// the new unknown broadcast with readlane.  With y = Q yhat:
+//   e_m^T y = qlast . yhat  (residual, eq. (error)),  ||y|| = ||yhat||,
+//   s = Q (sum_j w_j yhat_j) / (2 pi i),
+// so the per-point work is one triangular solve.  Partial sums are combined across
+// the wavefronts in a fixed order (bitwise reproducible).
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace simm {
+
+namespace {
+
+constexpr int IND_THREADS = 256;
+constexpr int IND_WAVES = IND_THREADS / 64;
+
+__device__ inline double readlane_d(double v, int l) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffu), l);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ inline cplx readlane_c(cplx v, int l) { return mk(readlane_d(v.re, l), readlane_d(v.im, l)); }
+
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+__device__ inline cplx wave_sum_c(cplx v) { return mk(wave_sum_d(v.re), wave_sum_d(v.im)); }
+
+// Square geometry and quadrature node, in the operation order of the contour rule:
+// corners counter-clockwise from centre + (w/2)(-1-i); edge a -> b carries
+// z = a + (t+1)(b-a)/2 and weight omega (b-a)/2.
+__device__ void node(double cx, double cy, double h, int e, double t, double om, cplx& z, cplx& wq) {
+#pragma clang fp contract(off)
+    const double sx[4] = {-1.0, 1.0, 1.0, -1.0};
+    const double sy[4] = {-1.0, -1.0, 1.0, 1.0};
+    const int e1 = (e + 1) & 3;
+    const double ar = cx + sx[e] * h, ai = cy + sy[e] * h;
+    const double br = cx + sx[e1] * h, bi = cy + sy[e1] * h;
+    const double dr = br - ar, di = bi - ai;
+    const double tp = t + 1.0;
+    z = mk(ar + (tp * dr) / 2.0, ai + (tp * di) / 2.0);
+    wq = mk((om * dr) / 2.0, (om * di) / 2.0);
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(IND_THREADS) void k_indicators(const ShiftDev* __restrict__ shifts,
+                                                            const int64_t* __restrict__ regions, int64_t nreg,
+                                                            IndicatorParams prm, RuleDev rule, double* indicator,
+                                                            double* rho_max, double* nsf_out, double* nsc_out,
+                                                            double* Tf_out, uint8_t* decision, cplx* sums,
+                                                            int m_sums) {
+    extern __shared__ cplx smem[];
+    __shared__ cplx red[IND_WAVES][2][128];
+    __shared__ double redT[IND_WAVES], redR[IND_WAVES];
+    __shared__ cplx shat[2][128];
+    const int64_t reg = blockIdx.x;
+    if (reg >= nreg) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t level = regions[4 * reg + 0];
+    const int64_t ix = regions[4 * reg + 1];
+    const int64_t iy = regions[4 * reg + 2];
+    const int64_t si = regions[4 * reg + 3];
+    const ShiftDev sh = shifts[si];
+    const int m = sh.m;
+    cplx* Ts = smem;
+    const int nT = m * (m + 1) / 2;
+    for (int e = threadIdx.x; e < nT; e += IND_THREADS) Ts[e] = sh.T[e];
+    __syncthreads();
+
+    // rows owned by this lane: i0 = lane, i1 = lane + 64
+    const int i0 = lane, i1 = lane + 64;
+    const cplx g0 = (i0 < m) ? sh.g[i0] : mk(0.0, 0.0);
+    const cplx g1 = (i1 < m) ? sh.g[i1] : mk(0.0, 0.0);
+    const cplx q0 = (i0 < m) ? sh.qlast[i0] : mk(0.0, 0.0);
+    const cplx q1 = (i1 < m) ? sh.qlast[i1] : mk(0.0, 0.0);
+    const cplx t00 = (i0 < m) ? Ts[i0 * (i0 + 1) / 2 + i0] : mk(0.0, 0.0);
+    const cplx t11 = (i1 < m) ? Ts[i1 * (i1 + 1) / 2 + i1] : mk(0.0, 0.0);
+
+    const double width = ldexp(prm.w1, (int)(1 - level));
+    double cx, cy;
+    {
+#pragma clang fp contract(off)
+        cx = prm.x0 + ((double)ix + 0.5) * width;
+        cy = prm.y0 + ((double)iy + 0.5) * width;
+    }
+    const double h = width / 2.0;
+    const int g = rule.g;
+    const int npts = 12 * g;
+
+    cplx sc0 = mk(0, 0), sc1 = mk(0, 0), sf0 = mk(0, 0), sf1 = mk(0, 0);
+    double Tf = 0.0, rmax = 0.0;
+    for (int q = wave; q < npts; q += IND_WAVES) {
+        int e, idx;
+        double t, om;
+        bool coarse;
+        if (q < 4 * g) {
+            e = q / g;
+            idx = q - e * g;
+            t = rule.t1[idx];
+            om = rule.w1[idx];
+            coarse = true;
+        } else {
+            const int q2 = q - 4 * g;
+            e = q2 / (2 * g);
+            idx = q2 - e * 2 * g;
+            t = rule.t2[idx];
+            om = rule.w2[idx];
+            coarse = false;
+        }
+        cplx z, wq;
+        node(cx, cy, h, e, t, om, z, wq);
+        const cplx alpha = mk(sh.sig_re - z.re, sh.sig_im - z.im);
+        const cplx one = mk(1.0, 0.0);
+        const cplx dinv0 = cdiv(one, one + alpha * t00);
+        const cplx dinv1 = cdiv(one, one + alpha * t11);
+        cplx r0 = g0, r1 = g1;
+        for (int j = m - 1; j >= 0; --j) {
+            const int oj = j & 63;
+            cplx rj, dj;
+            if (j < 64) {
+                rj = readlane_c(r0, oj);
+                dj = readlane_c(dinv0, oj);
+            } else {
+                rj = readlane_c(r1, oj);
+                dj = readlane_c(dinv1, oj);
+            }
+            const cplx yj = rj * dj;
+            const cplx cj = alpha * yj;
+            const cplx* col = Ts + j * (j + 1) / 2;
+            if (i0 < j) r0 = fms(r0, col[i0], cj);
+            if (i1 < j) r1 = fms(r1, col[i1], cj);
+            if (i0 == j) r0 = yj;
+            if (i1 == j) r1 = yj;
+        }
+        // r0, r1 hold yhat
+        const cplx dot = wave_sum_c(q0 * r0 + q1 * r1);
+        const double nrm2 = wave_sum_d(norm2(r0) + norm2(r1));
+        const double rho = cabs(alpha) * sh.h_last * cabs(dot) / sh.beta;
+        rmax = fmax(rmax, rho);
+        if (coarse) {
+            sc0 = fma_c(sc0, wq, r0);
+            sc1 = fma_c(sc1, wq, r1);
+        } else {
+            sf0 = fma_c(sf0, wq, r0);
+            sf1 = fma_c(sf1, wq, r1);
+            Tf += cabs(wq) * sqrt(nrm2);
+        }
+    }
+    red[wave][0][i0] = sc0;
+    red[wave][0][i1] = sc1;
+    red[wave][1][i0] = sf0;
+    red[wave][1][i1] = sf1;
+    if (lane == 0) {
+        redT[wave] = Tf;
+        redR[wave] = rmax;
+    }
+    __syncthreads();
+    if (wave == 0) {
+        cplx c0 = red[0][0][i0], c1 = red[0][0][i1], f0 = red[0][1][i0], f1 = red[0][1][i1];
+        double T = redT[0], R = redR[0];
+        for (int w = 1; w < IND_WAVES; ++w) {
+            c0 = c0 + red[w][0][i0];
+            c1 = c1 + red[w][0][i1];
+            f0 = f0 + red[w][1][i0];
+            f1 = f1 + red[w][1][i1];
+            T += redT[w];
+            R = fmax(R, redR[w]);
+        }
+        const double twopi = 6.283185307179586;
+        const double nsc = sqrt(wave_sum_d(norm2(c0) + norm2(c1))) / twopi;
+        const double nsf = sqrt(wave_sum_d(norm2(f0) + norm2(f1))) / twopi;
+        const double Tfv = T / twopi;
+        shat[0][i0] = c0;
+        shat[0][i1] = c1;
+        shat[1][i0] = f0;
+        shat[1][i1] = f1;
+        if (lane == 0) {
+            const bool resolvable = R <= prm.eps0;
+            const bool admissible = (nsf > prm.tau * Tfv) && (nsf > prm.delta0 * nsc);
+            if (indicator) indicator[reg] = nsf / nsc;
+            if (rho_max) rho_max[reg] = R;
+            if (nsf_out) nsf_out[reg] = nsf;
+            if (nsc_out) nsc_out[reg] = nsc;
+            if (Tf_out) Tf_out[reg] = Tfv;
+            if (decision) decision[reg] = (uint8_t)(!resolvable ? SIMM_UNRESOLVED : (admissible ? SIMM_ADMISSIBLE : SIMM_REJECTED));
+        }
+    }
+    if (sums != nullptr) {
+        __syncthreads();
+        // s = Q shat / (2 pi i): waves 0/1 form s_c, waves 2/3 form s_f
+        const int which = wave >> 1;
+        const int i = (wave & 1) * 64 + lane;
+        if (i < m_sums) {
+            cplx acc = mk(0.0, 0.0);
+            if (i < m) {
+                for (int k = 0; k < m; ++k) acc = fma_c(acc, sh.Q[i + (int64_t)k * m], shat[which][k]);
+            }
+            const double twopi = 6.283185307179586;
+            // x / (2 pi i) = (im, -re) / (2 pi)
+            sums[((int64_t)reg * 2 + which) * m_sums + i] = mk(acc.im / twopi, -acc.re / twopi);
+        }
+    }
+}
+
+simm_status indicators(const ShiftDev* shifts_dev, int mmax, const int64_t* regions, int64_t nreg,
+                       const IndicatorParams& prm, const RuleDev& rule, double* indicator, double* rho_max,
+                       double* nsf, double* nsc, double* Tf, uint8_t* decision, cplx* sums, int m_sums,
+                       hipStream_t st) {
+    if (nreg <= 0) return SIMM_OK;
+    if (mmax > 128) {
+        set_error("Krylov dimension above 128");
+        return SIMM_EUNSUPPORTED;
+    }
+    if (sums != nullptr && m_sums > 128) {
+        set_error("m_max above 128");
+        return SIMM_EUNSUPPORTED;
+    }
+    const size_t lds = sizeof(cplx) * (size_t)(mmax * (mmax + 1) / 2 + 1);
+    for (int64_t r0 = 0; r0 < nreg; r0 += 1 << 30) {
+        const int64_t cnt = std::min<int64_t>(nreg - r0, (int64_t)1 << 30);
+        hipLaunchKernelGGL(k_indicators, dim3((unsigned)cnt), dim3(IND_THREADS), lds, st, shifts_dev,
+                           regions + 4 * r0, cnt, prm, rule, indicator ? indicator + r0 : nullptr,
+                           rho_max ? rho_max + r0 : nullptr, nsf ? nsf + r0 : nullptr, nsc ? nsc + r0 : nullptr,
+                           Tf ? Tf + r0 : nullptr, decision ? decision + r0 : nullptr,
+                           sums ? sums + (size_t)r0 * 2 * m_sums : nullptr, m_sums);
+    }
+    SIMM_HIP_TRY(hipGetLastError());
+    return SIMM_OK;
+}
+
+}  // namespace simm

@@ -1,0 +1,78 @@
+// Host-side launchers of the HIP kernels (internal to the library).
+#pragma once
+
+#include "common.hpp"
+
+namespace simm {
+
+// ---- band LU (band_lu.hip) ----
+simm_status assemble_shifted(int64_t n, int kl, int ku, const cplx* A, int kla, int kua, const cplx* B, int klb,
+                             int kub, cplx sigma, cplx* AB, hipStream_t st);
+int lu_panel_width(int kl);
+size_t band_lu_scratch_elems(int kl);
+// info must hold INT_MAX on entry; it receives the first singular column + 1.
+simm_status band_lu(int64_t n, int kl, int ku, cplx* AB, int* ipiv, cplx* lt_scratch, int* info, hipStream_t st);
+
+// ---- band sweeps (band_sweep.hip) ----
+int sweep_threads(int kl, int ku);
+simm_status prepare_input(int64_t n, const cplx* x, const cplx* Bb, int klb, int kub, const double* hdiv,
+                          const int* active, cplx* u, cplx* xs, hipStream_t st);
+simm_status band_sweep(int64_t n, int kl, int ku, const cplx* AB, const int* ipiv, const cplx* u, const int* active,
+                       cplx* y, hipStream_t st);
+
+// ---- Gram-Schmidt (arnoldi.hip) ----
+struct ArnoldiWork {
+    int nblk;            // row blocks of the reduction kernels
+    cplx* partial;       // nblk x (m + 2)
+    cplx* h1;            // m + 2
+    cplx* h2;            // m + 2
+    double* hnorm;       // device scalars: [0] ||w||, [1] ||M v_j|| (before orthogonalisation)
+    cplx* u;             // n   : input of the sweep
+};
+simm_status arnoldi_step(int64_t n, cplx* V, int64_t ldv, int j, cplx* H, int ldh, ArnoldiWork& w, int* active,
+                         int* m_eff, hipStream_t st);
+simm_status vec_norm_scale(int64_t n, const cplx* b, cplx* v1, double* beta, ArnoldiWork& w, hipStream_t st);
+
+// ---- Schur form of H_m (schur.hip) ----
+struct SchurOut {
+    cplx* T;       // packed upper triangle by columns: T(i,j) at j(j+1)/2 + i
+    cplx* Q;       // m x m column-major
+    cplx* g;       // beta * conj(Q(0,:))  (= beta Q^H e_1)
+    cplx* qlast;   // Q(m-1, :)
+};
+simm_status hess_schur(const cplx* H, int ldh, int m, double beta, SchurOut out, int* status, hipStream_t st);
+
+// ---- indicators (indicators.hip) ----
+struct ShiftDev {        // per-shift data consumed by the indicator kernel (device memory)
+    const cplx* T;
+    const cplx* Q;
+    const cplx* g;
+    const cplx* qlast;
+    double sig_re, sig_im;
+    double beta;
+    double h_last;
+    int m;
+    int pad;
+};
+struct RuleDev {         // Gauss-Legendre nodes/weights on [-1, 1] (device memory)
+    const double* t1;    // g nodes
+    const double* w1;
+    const double* t2;    // 2g nodes
+    const double* w2;
+    int g;
+};
+struct IndicatorParams {
+    double x0, y0, w1;
+    double eps0, delta0, tau;
+};
+simm_status indicators(const ShiftDev* shifts_dev, int mmax, const int64_t* regions, int64_t nreg,
+                       const IndicatorParams& prm, const RuleDev& rule, double* indicator, double* rho_max,
+                       double* nsf, double* nsc, double* Tf, uint8_t* decision, cplx* sums, int m_sums,
+                       hipStream_t st);
+
+// ---- projection (project.hip) ----
+simm_status project(int64_t n, int m, const cplx* V, int64_t ldv, const cplx* Y, int64_t ldy, int64_t c, cplx* X,
+                    double* col_norms, double* scratch, int64_t scratch_elems, hipStream_t st);
+int64_t project_scratch_elems(int64_t n, int64_t c);
+
+}  // namespace simm

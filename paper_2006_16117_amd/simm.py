@@ -1,0 +1,298 @@
+"""Thin ctypes binding of the SIM-M HIP library (libsimm.so, C ABI in include/simm.h).
+
+Only argument marshalling lives here: every step of the method runs in the
+library's HIP kernels.  Device memory comes from torch (ROCm) tensors, host
+memory from numpy arrays.  If the built library is missing this module raises
+at import time; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsimm.so")
+
+SIMM_OK = 0
+SIMM_MEM_HOST = 0
+SIMM_MEM_DEVICE = 1
+SIMM_FLAG_PROJECT = 1
+REJECTED, ADMISSIBLE, UNRESOLVED = 0, 1, 2
+
+STATUS_NAMES = {0: "SIMM_OK", -1: "SIMM_EINVAL", -2: "SIMM_ENODEV", -3: "SIMM_ENOMEM", -4: "SIMM_EHIP",
+                -5: "SIMM_ESINGULAR_SHIFT", -6: "SIMM_ENOCONV", -7: "SIMM_ELIMIT", -8: "SIMM_EUNSUPPORTED"}
+
+
+class SimmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class simm_params(C.Structure):
+    _fields_ = [("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
+                ("n1", C.c_int32), ("gauss_per_edge", C.c_int32), ("m", C.c_int32), ("levels", C.c_int32),
+                ("h0", C.c_double), ("eps0", C.c_double), ("delta0", C.c_double), ("tau", C.c_double),
+                ("max_regions_per_level", C.c_int64), ("flags", C.c_uint32)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2006_16117_amd.build`")
+_lib = C.CDLL(LIB_PATH)
+
+_vp, _dp, _ip64, _i32, _i64, _d = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32, C.c_int64, C.c_double
+
+EXPORTS = {
+    "simm_last_error": (C.c_char_p, []),
+    "simm_version": (C.c_int32, []),
+    "simm_params_default": (C.c_int, [C.POINTER(simm_params)]),
+    "simm_pencil_create_banded": (C.c_int, [_i64, _i32, _i32, _vp, _i32, _i32, _vp, _i32, _vp, C.POINTER(_vp)]),
+    "simm_pencil_create_csr": (C.c_int, [_i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_vp)]),
+    "simm_pencil_info": (C.c_int, [_vp, C.POINTER(_i64), C.POINTER(_i32), C.POINTER(_i32)]),
+    "simm_pencil_destroy": (None, [_vp]),
+    "simm_shift_build": (C.c_int, [_vp, _d, _d, _vp, _i32, _i32, _vp, C.POINTER(_vp)]),
+    "simm_shift_info": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "simm_shift_basis": (C.c_int, [_vp, _vp, _i32, _vp]),
+    "simm_shift_apply": (C.c_int, [_vp, _vp, _vp, _i32, _vp]),
+    "simm_shift_destroy": (None, [_vp]),
+    "simm_indicators": (C.c_int, [_vp, _i32, _vp, _i64, C.POINTER(simm_params), _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                  _i32, _i32, _vp]),
+    "simm_project": (C.c_int, [_vp, _vp, _i64, _vp, _vp, _vp]),
+    "simm_run": (C.c_int, [_vp, C.POINTER(simm_params), _vp, _i32, _vp, C.POINTER(_vp)]),
+    "simm_result_summary": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "simm_result_level": (C.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64]),
+    "simm_result_shift": (C.c_int, [_vp, _i32, C.POINTER(_vp)]),
+    "simm_result_clusters": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _i64]),
+    "simm_result_stats": (C.c_int, [_vp, _vp, _vp]),
+    "simm_result_destroy": (None, [_vp]),
+}
+for _name, (_res, _args) in EXPORTS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def _check(status: int) -> None:
+    if status != SIMM_OK:
+        raise SimmError(status, _lib.simm_last_error().decode(errors="replace"))
+
+
+def _ptr(a):
+    """(pointer, mem kind) of a numpy array or a torch tensor."""
+    if a is None:
+        return None, SIMM_MEM_HOST
+    if isinstance(a, np.ndarray):
+        if not a.flags["F_CONTIGUOUS"] and not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be contiguous")
+        return a.ctypes.data, SIMM_MEM_HOST
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr(), (SIMM_MEM_DEVICE if a.is_cuda else SIMM_MEM_HOST)
+    raise TypeError(type(a))
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:  # noqa: BLE001
+        pass
+    return None
+
+
+def params_default(**overrides) -> simm_params:
+    p = simm_params()
+    _check(_lib.simm_params_default(C.byref(p)))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def params_from_dict(d: dict, **extra) -> simm_params:
+    keys = {f[0] for f in simm_params._fields_}
+    p = params_default()
+    for k, v in {**d, **extra}.items():
+        if k in keys:
+            setattr(p, k, v)
+    return p
+
+
+class Pencil:
+    """simm_pencil: banded A and B (LAPACK band layout, complex128)."""
+
+    def __init__(self, n, kl_a, ku_a, a_band, kl_b=0, ku_b=0, b_band=None, stream=None):
+        a = np.asfortranarray(a_band, dtype=np.complex128) if isinstance(a_band, np.ndarray) else a_band
+        b = (np.asfortranarray(b_band, dtype=np.complex128) if isinstance(b_band, np.ndarray) else b_band)
+        pa, mem = _ptr(a)
+        pb, _ = _ptr(b)
+        h = _vp()
+        _check(_lib.simm_pencil_create_banded(n, kl_a, ku_a, pa, kl_b, ku_b, pb, mem, _stream(stream), C.byref(h)))
+        self.handle = h
+        self.n = n
+
+    @classmethod
+    def from_workload(cls, pen, stream=None):
+        return cls(pen.n, pen.kl_a, pen.ku_a, pen.a_band, pen.kl_b, pen.ku_b, pen.b_band, stream)
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.simm_pencil_destroy(self.handle)
+            self.handle = None
+
+
+class Shift:
+    """simm_shift: LU, Arnoldi basis and Schur data of one shift."""
+
+    def __init__(self, handle, owner=None):
+        self.handle = handle
+        self._owner = owner          # a Result keeps borrowed shifts alive
+
+    def info(self):
+        sig = np.zeros(2)
+        beta = C.c_double()
+        me = C.c_int32()
+        _check(_lib.simm_shift_info(self.handle, sig.ctypes.data, C.addressof(beta), C.addressof(me), None, None))
+        m = me.value
+        H = np.zeros((m + 1, m), dtype=np.complex128, order="F")
+        ritz = np.zeros(m, dtype=np.complex128)
+        _check(_lib.simm_shift_info(self.handle, None, None, None, H.ctypes.data, ritz.ctypes.data))
+        return dict(sigma=complex(sig[0], sig[1]), beta=beta.value, m_eff=m, H=H, ritz=ritz)
+
+    def basis(self, out=None, stream=None):
+        if out is None:
+            inf = self.info()
+            n = _lib_n(self)
+            out = np.zeros((n, inf["m_eff"] + 1), dtype=np.complex128, order="F")
+        p, mem = _ptr(out)
+        _check(_lib.simm_shift_basis(self.handle, p, mem, _stream(stream)))
+        return out
+
+    def apply(self, x, y, stream=None):
+        px, mem = _ptr(x)
+        py, _ = _ptr(y)
+        _check(_lib.simm_shift_apply(self.handle, px, py, mem, _stream(stream)))
+        return y
+
+    def __del__(self):
+        if getattr(self, "handle", None) and self._owner is None:
+            _lib.simm_shift_destroy(self.handle)
+            self.handle = None
+
+
+def _lib_n(shift: Shift) -> int:
+    return shift._n
+
+
+def simm_shift_build(pencil: Pencil, sigma: complex, f, m: int, stream=None) -> Shift:
+    pf, mem = _ptr(np.ascontiguousarray(f, dtype=np.complex128) if isinstance(f, np.ndarray) else f)
+    h = _vp()
+    _check(_lib.simm_shift_build(pencil.handle, float(np.real(sigma)), float(np.imag(sigma)), pf, mem, m,
+                                 _stream(stream), C.byref(h)))
+    s = Shift(h)
+    s._n = pencil.n
+    return s
+
+
+def simm_indicators(shifts, regions: np.ndarray, params: simm_params, want_sums: bool = False, m_max: int = 0,
+                    stream=None) -> dict:
+    """Host-memory convenience form: regions (N, 4) int64 (level, ix, iy, shift)."""
+    regions = np.ascontiguousarray(regions, dtype=np.int64).reshape(-1, 4)
+    N = regions.shape[0]
+    arr = (_vp * len(shifts))(*[s.handle for s in shifts])
+    out = {k: np.zeros(N) for k in ("indicator", "rho_max", "nsf", "nsc", "Tf")}
+    out["decision"] = np.zeros(N, dtype=np.uint8)
+    sums = None
+    if want_sums:
+        if m_max <= 0:
+            m_max = max(s.info()["m_eff"] for s in shifts)
+        sums = np.zeros((N, 2, m_max), dtype=np.complex128)
+    _check(_lib.simm_indicators(arr, len(shifts), regions.ctypes.data, N, C.byref(params),
+                                out["indicator"].ctypes.data, out["rho_max"].ctypes.data, out["nsf"].ctypes.data,
+                                out["nsc"].ctypes.data, out["Tf"].ctypes.data, out["decision"].ctypes.data,
+                                sums.ctypes.data if sums is not None else None, m_max, SIMM_MEM_HOST,
+                                _stream(stream)))
+    if sums is not None:
+        out["sums"] = sums
+    return out
+
+
+def simm_project(shift: Shift, Y, X, col_norms=None, stream=None):
+    """Device tensors: Y (m_eff x c), X (n x c) column-major complex128 (torch tensors
+    whose storage is column-major: pass the transposed-contiguous view)."""
+    py, _ = _ptr(Y)
+    px, _ = _ptr(X)
+    pn, _ = _ptr(col_norms)
+    c = Y.shape[1]
+    _check(_lib.simm_project(shift.handle, py, c, px, pn, _stream(stream)))
+    return X
+
+
+@dataclasses.dataclass
+class LevelOut:
+    level: int
+    keys: np.ndarray
+    shift: np.ndarray
+    indicator: np.ndarray
+    rho_max: np.ndarray
+    decision: np.ndarray
+
+
+class Result:
+    def __init__(self, handle):
+        self.handle = handle
+        K = C.c_int32()
+        ns = C.c_int32()
+        nc = C.c_int64()
+        nu = C.c_int64()
+        _check(_lib.simm_result_summary(handle, C.addressof(K), C.addressof(ns), C.addressof(nc), C.addressof(nu)))
+        self.K, self.n_shifts, self.n_clusters, self.n_unresolved = K.value, ns.value, nc.value, nu.value
+        self.levels = []
+        for k in range(1, self.K + 1):
+            cnt = C.c_int64()
+            _lib.simm_result_level(handle, k, C.addressof(cnt), None, None, None, None, None, None, 0)
+            N = cnt.value
+            ix = np.zeros(N, np.int64)
+            iy = np.zeros(N, np.int64)
+            sh = np.zeros(N, np.int32)
+            ind = np.zeros(N)
+            rho = np.zeros(N)
+            dec = np.zeros(N, np.uint8)
+            _check(_lib.simm_result_level(handle, k, C.addressof(cnt), ix.ctypes.data, iy.ctypes.data, sh.ctypes.data,
+                                          ind.ctypes.data, rho.ctypes.data, dec.ctypes.data, N))
+            self.levels.append(LevelOut(k, np.stack([ix, iy], 1), sh, ind, rho, dec))
+        nc_ = self.n_clusters
+        lam = np.zeros(nc_, np.complex128)
+        lr = np.zeros(nc_, np.complex128)
+        cs = np.zeros(nc_, np.int32)
+        fl = np.zeros(nc_, np.int32)
+        cnt = C.c_int64()
+        _check(_lib.simm_result_clusters(handle, C.addressof(cnt), lam.ctypes.data, lr.ctypes.data, cs.ctypes.data,
+                                         fl.ctypes.data, nc_))
+        self.lam, self.lam_ritz, self.cluster_shift, self.cluster_flags = lam, lr, cs, fl
+        ms = np.zeros(4)
+        ctr = np.zeros(3, np.int64)
+        _check(_lib.simm_result_stats(handle, ms.ctypes.data, ctr.ctypes.data))
+        self.ms = dict(shift_builds=ms[0], indicators=ms[1], projection=ms[2], total=ms[3])
+        self.counters = dict(quadrature_systems=int(ctr[0]), squares=int(ctr[1]), m_applications=int(ctr[2]))
+
+    def shift(self, idx: int) -> Shift:
+        h = _vp()
+        _check(_lib.simm_result_shift(self.handle, idx, C.byref(h)))
+        return Shift(h, owner=self)
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.simm_result_destroy(self.handle)
+            self.handle = None
+
+
+def simm_run(pencil: Pencil, f, params: simm_params, stream=None) -> Result:
+    pf, mem = _ptr(np.ascontiguousarray(f, dtype=np.complex128) if isinstance(f, np.ndarray) else f)
+    h = _vp()
+    _check(_lib.simm_run(pencil.handle, C.byref(params), pf, mem, _stream(stream), C.byref(h)))
+    return Result(h)

@@ -1,0 +1,241 @@
+"""HIP path against the CPU oracle, through the C ABI (needs an MI355X).
+
+Each test prints the case it runs before touching the GPU."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle.simm as O
+from workloads import make_workload
+from workloads.gen import Pencil as WPencil
+from workloads.gen import random_band_pencil
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_2006_16117_amd.simm as S   # raises if the library is not built
+    return S
+
+
+def hmax_diff(Hg, Ho):
+    return np.max(np.abs(Hg - Ho)) / np.max(np.abs(Ho))
+
+
+# ---------------------------------------------------------------------------
+# shift build: LU + Arnoldi + Schur
+# ---------------------------------------------------------------------------
+CASES = [
+    # name, n, k, seed, b_kind, m, sigma, extra kwargs of the generator
+    ("cfg0-like", 400, 2, 1000, "identity", 40, 0.1 + 0.2j, {}),
+    ("tridiagB", 300, 3, 77, "tridiag", 30, -0.3 + 0.1j, {}),
+    ("pivoting", 257, 5, 78, "tridiag", 25, 0.05 - 0.02j, dict(d_half=0.05, e_scale=1.0)),
+    ("ragged-wide", 1037, 21, 79, "identity", 33, 0.2 + 0.0j, {}),
+    ("m=n", 24, 2, 80, "identity", 24, 0.0 + 0.1j, {}),
+    ("tiny", 5, 1, 81, "tridiag", 3, 0.3 + 0.3j, {}),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_shift_build_matches_oracle(S, case):
+    name, n, k, seed, b_kind, m, sigma, kw = case
+    pen, f = random_band_pencil(n, k, seed, b_kind=b_kind, b_offdiag=0.3, **kw)
+    say("shift_build", name, f"n={n} k={k} m={m}")
+    P = S.Pencil.from_workload(pen)
+    sh = S.simm_shift_build(P, sigma, f, m)
+    g = sh.info()
+    o = O.build_shift(pen, sigma, f, m)
+    assert g["m_eff"] == o.m_eff
+    assert abs(g["beta"] - o.beta) <= 1e-12 * o.beta
+    d = hmax_diff(g["H"], o.H)
+    say("  max |H_gpu - H_oracle| / max|H| =", d)
+    assert d <= 1e-9
+    V = sh.basis()
+    me = g["m_eff"]
+    ncol = me + 1 if g["H"][me, me - 1] != 0 else me     # v_{m+1} is undefined after a breakdown
+    orth = float(np.linalg.norm(V[:, :ncol].conj().T @ V[:, :ncol] - np.eye(ncol)))
+    assert orth <= 1e-12, orth
+    # Ritz values (diagonal of the Schur form) against the oracle's eigenvalues of H_m
+    ro = O.ritz_values(o)
+    for r in g["ritz"]:
+        assert np.min(np.abs(ro - r)) <= 1e-8 * max(1.0, abs(r))
+
+
+def test_pivoting_really_pivots_and_apply_matches(S):
+    pen, f = random_band_pencil(257, 5, 78, b_kind="tridiag", b_offdiag=0.3, d_half=0.05, e_scale=1.0)
+    sigma = 0.05 - 0.02j
+    solver = O.ShiftedSolver(pen, sigma)
+    A, B = O.pencil_dense(pen)
+    import scipy.linalg as sla
+    _, piv = sla.lu_factor(A - sigma * B)
+    assert np.count_nonzero(piv != np.arange(pen.n)) > 10      # the pencil needs row interchanges
+    say("apply", "pivoting pencil")
+    P = S.Pencil.from_workload(pen)
+    sh = S.simm_shift_build(P, sigma, f, 10)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(pen.n) + 1j * rng.standard_normal(pen.n)
+    y = np.zeros(pen.n, np.complex128)
+    sh.apply(x, y)
+    want = solver.apply_M(x)
+    assert np.linalg.norm(y - want) <= 1e-12 * np.linalg.norm(want)
+
+
+def test_shift_build_is_deterministic(S):
+    pen, f = random_band_pencil(700, 4, 82, b_kind="tridiag")
+    say("determinism", "n=700")
+    P = S.Pencil.from_workload(pen)
+    H1 = S.simm_shift_build(P, 0.1j, f, 20).info()["H"]
+    H2 = S.simm_shift_build(P, 0.1j, f, 20).info()["H"]
+    assert np.array_equal(H1, H2)
+
+
+def test_breakdown_and_errors(S):
+    n = 8
+    band = (np.arange(n) + 1.0).reshape(1, n).astype(complex)
+    pen = WPencil(n, 0, 0, band, 0, 0, None)
+    f = np.zeros(n, complex)
+    f[3] = 1.0
+    say("breakdown", "diagonal pencil, f = e_3")
+    P = S.Pencil.from_workload(pen)
+    sh = S.simm_shift_build(P, 0.5j, f, 5)
+    inf = sh.info()
+    assert inf["m_eff"] == 1 and inf["H"].shape == (2, 1) and inf["H"][1, 0] == 0
+    say("singular shift")
+    with pytest.raises(S.SimmError) as e:
+        S.simm_shift_build(P, 3.0, f, 3)
+    assert e.value.status == -5
+    with pytest.raises(S.SimmError) as e:
+        S.simm_shift_build(P, 0.5, f, 0)
+    assert e.value.status == -1
+    bad = f.copy()
+    bad[0] = np.nan
+    with pytest.raises(S.SimmError) as e:
+        S.simm_shift_build(P, 0.5, bad, 3)
+    assert e.value.status == -1
+
+
+# ---------------------------------------------------------------------------
+# indicators and projection
+# ---------------------------------------------------------------------------
+def test_indicators_match_oracle(S):
+    pen, f, params = make_workload("cfg0")
+    sigma = 0.125 + 0.375j
+    say("indicators", "cfg0 pencil, one shift, 200 squares at levels 1..6")
+    P = S.Pencil.from_workload(pen)
+    sh = S.simm_shift_build(P, sigma, f, params["m"])
+    o = O.build_shift(pen, sigma, f, params["m"], keep_V=False)
+    rng = np.random.default_rng(3)
+    regs = []
+    for _ in range(200):
+        k = int(rng.integers(1, 7))
+        nk = 8 * 2 ** (k - 1)
+        regs.append((k, int(rng.integers(0, nk)), int(rng.integers(0, nk)), 0))
+    regs = np.array(regs, np.int64)
+    prm = S.params_from_dict(params)
+    out = S.simm_indicators([sh], regs, prm, want_sums=True)
+    mism = 0
+    for r, (k, ix, iy, _) in enumerate(regs):
+        c = O.square_center(params, int(k), int(ix), int(iy))
+        w = O.square_width(params, int(k))
+        ev = O.evaluate_square(o, c, w, params)
+        dec = 2 if not ev.resolvable else (1 if ev.admissible else 0)
+        for name, a, b in (("nsf", out["nsf"][r], ev.nsf), ("nsc", out["nsc"][r], ev.nsc), ("Tf", out["Tf"][r], ev.Tf)):
+            assert abs(a - b) <= 1e-7 * max(abs(b), 1e-30) + 1e-14 * ev.Tf, (r, name, a, b)
+        assert abs(out["rho_max"][r] - ev.rho_max) <= 1e-6 * ev.rho_max + 1e-16, (r, out["rho_max"][r], ev.rho_max)
+        if out["decision"][r] != dec:
+            mism += 1
+            assert ev.margin < 1e-8, (r, out["decision"][r], dec, ev.margin)
+        # the sums themselves: s_c, s_f (coefficients of P_R f in the Krylov basis)
+        sc = out["sums"][r, 0, : o.m_eff]
+        sf = out["sums"][r, 1, : o.m_eff]
+        # relative 1e-7, or round-off level (1e-13 T_f) for sums that are pure quadrature noise
+        dc = float(np.linalg.norm(sc - ev.s_c))
+        df = float(np.linalg.norm(sf - ev.s_f))
+        assert dc <= max(1e-7 * np.linalg.norm(ev.s_c), 1e-13 * ev.Tf), (r, dc)
+        assert df <= max(1e-7 * np.linalg.norm(ev.s_f), 1e-13 * ev.Tf), (r, df)
+    say("  decision ties:", mism)
+
+
+def test_project_matches_numpy(S):
+    import torch
+    pen, f = random_band_pencil(5000 + 13, 3, 90, b_kind="tridiag")
+    say("project", "n=5013 m=37 c=45")
+    P = S.Pencil.from_workload(pen)
+    sh = S.simm_shift_build(P, 0.2 + 0.1j, f, 37)
+    V = sh.basis()[:, :37]
+    rng = np.random.default_rng(1)
+    for c in (1, 7, 45):
+        Y = rng.standard_normal((37, c)) + 1j * rng.standard_normal((37, c))
+        Yd = torch.from_numpy(np.ascontiguousarray(Y.T)).cuda()          # column-major storage
+        Xd = torch.zeros((c, pen.n), dtype=torch.complex128, device="cuda")
+        nd = torch.zeros(c, dtype=torch.float64, device="cuda")
+        S.simm_project(sh, Yd.T, Xd.T, nd)
+        torch.cuda.synchronize()
+        X = Xd.cpu().numpy().T
+        want = V @ Y
+        assert np.linalg.norm(X - want) <= 1e-13 * np.linalg.norm(want)
+        assert np.allclose(nd.cpu().numpy(), np.linalg.norm(want, axis=0), rtol=1e-13, atol=0)
+
+
+# ---------------------------------------------------------------------------
+# the whole method against the oracle's stored runs
+# ---------------------------------------------------------------------------
+def _compare_run(S, name, flags=0):
+    pen, f, params = make_workload(name)
+    gold = json.load(open(os.path.join(GOLDEN, f"{name}_oracle.json")))
+    say("simm_run", name)
+    P = S.Pencil.from_workload(pen)
+    prm = S.params_from_dict(params, flags=flags)
+    res = S.simm_run(P, f, prm)
+    assert res.K == gold["K"]
+    assert res.n_shifts == len(gold["shifts"])
+    for s, gs in enumerate(gold["shifts"]):
+        inf = res.shift(s).info()
+        assert inf["sigma"] == complex(*gs["sigma"])
+        assert inf["m_eff"] == gs["m_eff"]
+        assert abs(inf["beta"] - gs["beta"]) <= 1e-10 * gs["beta"]
+    ties = 0
+    for L, GL in zip(res.levels, gold["levels"]):
+        gk = list(zip(GL["ix"], GL["iy"]))
+        ok = [tuple(map(int, k)) for k in L.keys]
+        if ok != gk:
+            raise AssertionError(f"level {L.level}: tested squares differ ({len(ok)} vs {len(gk)})")
+        gd = np.array(GL["decision"], np.uint8)
+        bad = np.nonzero(L.decision != gd)[0]
+        for r in bad:
+            assert GL["margin"][r] < 1e-8, (L.level, r, L.decision[r], gd[r], GL["margin"][r])
+            ties += 1
+        assert np.array_equal(L.shift, np.array(GL["shift"]))
+    lam = np.array([complex(*c["lam"]) for c in gold["clusters"]])
+    lr = np.array([complex(*c["lam_ritz"]) for c in gold["clusters"]])
+    say("  levels", res.K, "shifts", res.n_shifts, "clusters", len(res.lam), "ms", res.ms)
+    assert len(res.lam) == len(lam)
+    # cluster centres are means of identical square centres: equal up to the summation order
+    assert np.all(np.abs(res.lam - lam) <= 1e-14 * np.abs(lam))
+    fin = np.isfinite(lr)
+    assert np.array_equal(np.isfinite(res.lam_ritz), fin)
+    assert np.all(np.abs(res.lam_ritz[fin] - lr[fin]) <= 1e-8 * np.maximum(1.0, np.abs(lr[fin])))
+    say("  decision ties within the margin policy:", ties)
+    return res
+
+
+def test_run_cfg0_matches_oracle(S):
+    _compare_run(S, "cfg0")
+
+
+def test_run_cfg1_matches_oracle(S):
+    res = _compare_run(S, "cfg1", flags=1)
+    # full-space indicator of the last level is available (X = V_m Y computed)
+    assert res.counters["quadrature_systems"] == 12 * 16 * sum(len(L.keys) for L in res.levels)

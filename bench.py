@@ -1,0 +1,182 @@
+#!/usr/bin/env python3
+"""Throughput of the SIM-M indicator evaluation on one MI355X.
+
+Workload: the n = 40,000 convection-diffusion pencil (5-point -Lap u + (20,10).grad u
++ (0.5+0.5i) u on a 200 x 200 grid, B = tridiag(0.05, 1, 0.05)), region
+R = [120,1400] x [-310,330] (105 eigenvalues), 16 Gauss points per edge, m = 80,
+4 levels, X = V_m Y formed at every level.  One step = one full pass of the hot
+path: every shift's banded LU and Arnoldi basis, the Schur forms, the shifted
+solves / sums / decisions of every level, the projections and the subdivision.
+
+Prints one JSON line.  value = resolvent solves per second: quadrature-point
+systems (A - z_j B) x_j = f solved in the Krylov spaces (12 g per square tested),
+over the whole step.  The pencil and f are resident in HBM before timing starts.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "resolvent solves/s + indicators/s at n=40k; speedup vs plain FP64 at 1e-6"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def sweep_bytes(n: int, kl: int, ku: int) -> int:
+    """Algorithmic HBM bytes of one application of U^{-1} L^{-1} P: every stored
+    factor entry the sweeps read once (kl multipliers and the diagonal + kl+ku
+    superdiagonals of U per column, clipped at the matrix edges), the input vector
+    read once and the result written once (complex128)."""
+    kv = kl + ku
+    lower = sum(min(kl, n - 1 - j) for j in range(n))
+    upper = sum(min(kv, j) + 1 for j in range(n))
+    return 16 * (lower + upper + 2 * n)
+
+
+def cpu_baseline(pen, f, params, n_shifts, n_squares, n_qp, budget_s=30.0):
+    """The CPU oracle on a bounded sample of the same workload: one shift build
+    (LU + Arnoldi, m = 80) and a batch of level-1 square evaluations; the full
+    job's time is extrapolated from the per-shift and per-square costs."""
+    import numpy as np
+    import oracle.simm as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:  # noqa: BLE001
+        threads = os.cpu_count() or 1
+    sigma = complex((params["x0"] + params["x1"]) / 2, (params["y0"] + params["y1"]) / 2)
+    t0 = time.perf_counter()
+    sh = O.build_shift(pen, sigma, f, params["m"], keep_V=False)
+    t_build = time.perf_counter() - t0
+    nx, ny = O.level1_grid(params)
+    w1 = O.square_width(params, 1)
+    t1 = time.perf_counter()
+    cnt = 0
+    for iy in range(ny):
+        for ix in range(nx):
+            O.evaluate_square(sh, O.square_center(params, 1, ix, iy), w1, params)
+            cnt += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        if time.perf_counter() - t0 > budget_s:
+            break
+    t_eval = (time.perf_counter() - t1) / max(cnt, 1)
+    est = n_shifts * t_build + n_squares * t_eval
+    return {"value": n_qp / est, "unit": "resolvent solves/s", "cores": int(threads), "kind": "oracle",
+            "sample": (f"1 shift build ({t_build:.2f} s) + {cnt} level-1 square evaluations "
+                       f"({t_eval * 1e3:.1f} ms each) of this workload on the host; full step estimated as "
+                       f"{n_shifts} builds + {n_squares} evaluations = {est:.1f} s"),
+            "est_seconds_per_step": est}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cfg1")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the shift-parallel multi-GPU "
+              "layout is described in the design notes but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from workloads import make_workload
+    import paper_2006_16117_amd.simm as S
+
+    assert torch.cuda.is_available(), "needs a ROCm GPU"
+    dev = torch.device("cuda:0")
+    pen, f, params = make_workload(args.workload)
+    log("workload", args.workload, "n =", pen.n)
+    P = S.Pencil.from_workload(pen)
+    fd = torch.from_numpy(np.ascontiguousarray(f)).to(dev)
+    prm = S.params_from_dict(params, flags=S.SIMM_FLAG_PROJECT | S.SIMM_FLAG_KERNEL_TIMING)
+    torch.cuda.synchronize()
+
+    for w in range(args.warmup):
+        res = S.simm_run(P, fd, prm)
+        log(f"warmup {w + 1}/{args.warmup}: {res.ms['total']:.1f} ms")
+        del res
+    torch.cuda.synchronize()
+    kms = {k: 0.0 for k in S.KERNEL_NAMES}
+    kcnt = {k: 0 for k in S.KERNEL_NAMES}
+    t0 = time.perf_counter()
+    last = None
+    for s in range(args.steps):
+        res = S.simm_run(P, fd, prm)
+        for k in S.KERNEL_NAMES:
+            kms[k] += res.kernel_ms[k]
+            kcnt[k] += res.kernel_launches[k]
+        log(f"step {s + 1}/{args.steps}: {res.ms['total']:.1f} ms")
+        last = res
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    n_qp = last.counters["quadrature_systems"]
+    n_sq = last.counters["squares"]
+    value = n_qp / (ms_per_step / 1e3)
+
+    _, kl, ku = pen.n, max(pen.kl_a, pen.kl_b), max(pen.ku_a, pen.ku_b)
+    b_sweep = sweep_bytes(pen.n, kl, ku)
+    sweep_ms = kms["band_sweep"] / max(kcnt["band_sweep"], 1)
+    achieved = b_sweep / (sweep_ms / 1e3) / 1e9
+    step_kernel_ms = {k: kms[k] / args.steps for k in kms}
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "resolvent solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "indicators_per_s": n_sq / (ms_per_step / 1e3),
+        "speedup_vs_plain_fp64": None,
+        "config": {
+            "workload": ("convection-diffusion pencil n=40000 (200x200 grid, h=1/201), B=tridiag(0.05,1,0.05), "
+                         "R=[120,1400]x[-310,330], 16 Gauss points/edge, m=80, 4 levels, X=V_mY every level"),
+            "n": pen.n, "kl": kl, "ku": ku, "m": params["m"], "gauss_per_edge": params["gauss_per_edge"],
+            "levels": last.K, "shifts": last.n_shifts, "squares_per_step": n_sq,
+            "resolvent_solves_per_step": n_qp, "clusters": len(last.lam),
+        },
+        "roofline": {
+            "kernel": "k_band_sweep (one application of U^-1 L^-1 P)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "bytes_per_launch": b_sweep,
+            "ms_per_launch": sweep_ms,
+            "launches_per_step": kcnt["band_sweep"] // args.steps,
+        },
+        "kernel_ms_per_step": step_kernel_ms,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(pen, f, params, last.n_shifts, n_sq, n_qp)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

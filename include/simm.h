@@ -49,7 +49,21 @@ enum { SIMM_MEM_HOST = 0, SIMM_MEM_DEVICE = 1 };
 enum { SIMM_REJECTED = 0, SIMM_ADMISSIBLE = 1, SIMM_UNRESOLVED = 2 };
 
 /* simm_params.flags */
-enum { SIMM_FLAG_PROJECT = 1u };   /* form X = V_m Y for the squares of every level */
+enum {
+    SIMM_FLAG_PROJECT = 1u,        /* form X = V_m Y for the squares of every level               */
+    SIMM_FLAG_KERNEL_TIMING = 2u   /* bracket every hot-path kernel launch with HIP events        */
+};
+
+/* Kernel classes reported by simm_result_kernel_stats. */
+enum {
+    SIMM_K_BAND_LU = 0,       /* assembly + banded LU of one shift (all its launches)          */
+    SIMM_K_BAND_SWEEP = 1,    /* one application of U^{-1} L^{-1} P (one launch)               */
+    SIMM_K_GRAM_SCHMIDT = 2,  /* one Arnoldi step's orthogonalisation (its launches)           */
+    SIMM_K_SCHUR = 3,         /* Schur form of one H_m                                         */
+    SIMM_K_INDICATORS = 4,    /* one indicator launch over a batch of squares                  */
+    SIMM_K_PROJECT = 5,       /* one X = V_m Y launch                                          */
+    SIMM_K_COUNT = 6
+};
 
 typedef struct simm_pencil_s* simm_pencil;
 typedef struct simm_shift_s* simm_shift;
@@ -205,6 +219,11 @@ simm_status simm_result_clusters(simm_result r, int64_t* n, double* lam, double*
  * [3] total.  Counters: [0] quadrature-point systems solved, [1] square
  * evaluations, [2] applications of M.  Either pointer may be NULL. */
 simm_status simm_result_stats(simm_result r, double* ms4, int64_t* counters3);
+
+/* With SIMM_FLAG_KERNEL_TIMING: total milliseconds and number of timed launches
+ * per kernel class (SIMM_K_*), measured with HIP events recorded on the run's
+ * stream around each launch.  Arrays of SIMM_K_COUNT entries; zeros otherwise. */
+simm_status simm_result_kernel_stats(simm_result r, double* ms, int64_t* launches);
 
 void simm_result_destroy(simm_result r);
 

@@ -78,7 +78,51 @@ struct ClusterRec {
     int flags;
 };
 
+// HIP-event brackets around kernel launches, collected after the run.
+struct KernelClock {
+    hipStream_t st = nullptr;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
+    void begin(int k) {
+        hipEvent_t a = nullptr;
+        (void)hipEventCreate(&a);
+        (void)hipEventRecord(a, st);
+        marks.push_back({k, {a, nullptr}});
+    }
+    void end() {
+        hipEvent_t b = nullptr;
+        (void)hipEventCreate(&b);
+        (void)hipEventRecord(b, st);
+        marks.back().second.second = b;
+    }
+    void collect(double* ms, int64_t* cnt) {
+        for (auto& m : marks) {
+            if (m.second.second) {
+                (void)hipEventSynchronize(m.second.second);
+                float t = 0;
+                (void)hipEventElapsedTime(&t, m.second.first, m.second.second);
+                ms[m.first] += t;
+                cnt[m.first] += 1;
+                (void)hipEventDestroy(m.second.second);
+            }
+            (void)hipEventDestroy(m.second.first);
+        }
+        marks.clear();
+    }
+};
+
+struct KScope {
+    KernelClock* c;
+    KScope(KernelClock* clk, int k) : c(clk) {
+        if (c) c->begin(k);
+    }
+    ~KScope() {
+        if (c) c->end();
+    }
+};
+
 struct simm_result_s {
+    double kms[SIMM_K_COUNT] = {0, 0, 0, 0, 0, 0};
+    int64_t kcnt[SIMM_K_COUNT] = {0, 0, 0, 0, 0, 0};
     int K = 0;
     std::vector<std::unique_ptr<simm_shift_s>> shifts;
     std::vector<LevelRec> levels;
@@ -220,7 +264,7 @@ ShiftDev shift_dev(const simm_shift_s* s) {
 
 // Builds LU, Arnoldi basis and Schur data of one shift (hot-path steps a1-a5).
 simm_status build_shift(simm_pencil_s* p, cplx sigma, const cplx* f_dev, int m, hipStream_t st,
-                        std::unique_ptr<simm_shift_s>& out, int64_t* applies) {
+                        std::unique_ptr<simm_shift_s>& out, int64_t* applies, KernelClock* clk = nullptr) {
     auto s = std::make_unique<simm_shift_s>();
     s->p = p;
     s->sigma = sigma;
@@ -272,8 +316,11 @@ simm_status build_shift(simm_pencil_s* p, cplx sigma, const cplx* f_dev, int m, 
     }
 
     // a1 + a2: shifted band and its LU
-    SIMM_TRY(assemble_shifted(n, kl, ku, p->A, p->kla, p->kua, p->B, p->klb, p->kub, sigma, s->AB, st));
-    SIMM_TRY(band_lu(n, kl, ku, s->AB, s->ipiv, lt, flags + 0, st));
+    {
+        KScope ks(clk, SIMM_K_BAND_LU);
+        SIMM_TRY(assemble_shifted(n, kl, ku, p->A, p->kla, p->kua, p->B, p->klb, p->kub, sigma, s->AB, st));
+        SIMM_TRY(band_lu(n, kl, ku, s->AB, s->ipiv, lt, flags + 0, st));
+    }
     int info = INT_MAX;
     SIMM_HIP_TRY(hipMemcpyAsync(&info, flags + 0, sizeof(int), hipMemcpyDeviceToHost, st));
     SIMM_HIP_TRY(hipStreamSynchronize(st));
@@ -285,13 +332,20 @@ simm_status build_shift(simm_pencil_s* p, cplx sigma, const cplx* f_dev, int m, 
         return SIMM_ESINGULAR_SHIFT;
     }
     // a3: b = (A - sigma B)^{-1} f, beta, v_1
-    SIMM_TRY(band_sweep(n, kl, ku, s->AB, s->ipiv, f_dev, nullptr, s->V, st));
+    {
+        KScope ks(clk, SIMM_K_BAND_SWEEP);
+        SIMM_TRY(band_sweep(n, kl, ku, s->AB, s->ipiv, f_dev, nullptr, s->V, st));
+    }
     SIMM_TRY(vec_norm_scale(n, s->V, s->V, beta_d, aw, st));
     // a4: Arnoldi steps
     for (int j = 0; j < m; ++j) {
         cplx* vj = s->V + (int64_t)j * n;
         SIMM_TRY(prepare_input(n, vj, p->B, p->klb, p->kub, nullptr, flags + 1, aw.u, nullptr, st));
-        SIMM_TRY(band_sweep(n, kl, ku, s->AB, s->ipiv, aw.u, flags + 1, s->V + (int64_t)(j + 1) * n, st));
+        {
+            KScope ks(clk, SIMM_K_BAND_SWEEP);
+            SIMM_TRY(band_sweep(n, kl, ku, s->AB, s->ipiv, aw.u, flags + 1, s->V + (int64_t)(j + 1) * n, st));
+        }
+        KScope ks(clk, SIMM_K_GRAM_SCHMIDT);
         SIMM_TRY(arnoldi_step(n, s->V, n, j, s->H, m + 1, aw, flags + 1, flags + 2, st));
     }
     int fl[4];
@@ -315,7 +369,10 @@ simm_status build_shift(simm_pencil_s* p, cplx sigma, const cplx* f_dev, int m, 
     SIMM_TRY(dalloc(&s->g, (size_t)me));
     SIMM_TRY(dalloc(&s->qlast, (size_t)me));
     SchurOut so{s->T, s->Q, s->g, s->qlast};
-    SIMM_TRY(hess_schur(s->H, m + 1, me, beta, so, flags + 3, st));
+    {
+        KScope ks(clk, SIMM_K_SCHUR);
+        SIMM_TRY(hess_schur(s->H, m + 1, me, beta, so, flags + 3, st));
+    }
     int schur_status = 0;
     std::vector<cplx> Tp((size_t)me * (me + 1) / 2);
     SIMM_HIP_TRY(hipMemcpyAsync(&schur_status, flags + 3, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -346,7 +403,8 @@ struct EvalOut {
 
 // Evaluate (level, ix, iy, shift) rows on the device; results copied to host.
 simm_status evaluate(const std::vector<simm_shift_s*>& shifts, const std::vector<int64_t>& regs, const simm_params* prm,
-                     const Rule& rule, hipStream_t st, EvalOut& out, cplx* sums_dev, int m_sums) {
+                     const Rule& rule, hipStream_t st, EvalOut& out, cplx* sums_dev, int m_sums,
+                     KernelClock* clk = nullptr) {
     const int64_t N = (int64_t)regs.size() / 4;
     out.indicator.assign(N, 0);
     out.rho.assign(N, 0);
@@ -380,8 +438,11 @@ simm_status evaluate(const std::vector<simm_shift_s*>& shifts, const std::vector
     ip.eps0 = prm->eps0;
     ip.delta0 = prm->delta0;
     ip.tau = prm->tau;
-    SIMM_TRY(indicators(sdd, mmax, rd, N, ip, rule.dev, o, o + N, o + 2 * N, o + 3 * N, o + 4 * N, dec, sums_dev,
-                        m_sums, st));
+    {
+        KScope ks(clk, SIMM_K_INDICATORS);
+        SIMM_TRY(indicators(sdd, mmax, rd, N, ip, rule.dev, o, o + N, o + 2 * N, o + 3 * N, o + 4 * N, dec, sums_dev,
+                            m_sums, st));
+    }
     std::vector<double> host(5 * N);
     SIMM_HIP_TRY(hipMemcpyAsync(host.data(), o, sizeof(double) * 5 * N, hipMemcpyDeviceToHost, st));
     SIMM_HIP_TRY(hipMemcpyAsync(out.decision.data(), dec, N, hipMemcpyDeviceToHost, st));
@@ -512,12 +573,22 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
     const int m = prm->m;
     const bool do_proj = (prm->flags & SIMM_FLAG_PROJECT) != 0;
     const int64_t maxreg = prm->max_regions_per_level > 0 ? prm->max_regions_per_level : ((int64_t)1 << 22);
+    KernelClock clock;
+    clock.st = st;
+    KernelClock* clk = (prm->flags & SIMM_FLAG_KERNEL_TIMING) ? &clock : nullptr;
+    struct Collect {
+        KernelClock* c;
+        simm_result_s* R;
+        ~Collect() {
+            if (c) c->collect(R->kms, R->kcnt);
+        }
+    } collect_at_exit{clk, R};
     std::vector<simm_shift_s*> shifts;
     auto new_shift = [&](cplx c) -> simm_status {
         std::unique_ptr<simm_shift_s> s;
         {
             Timer t(st, &R->ms[0]);
-            SIMM_TRY(build_shift(p, c, f_dev, m, st, s, &R->counters[2]));
+            SIMM_TRY(build_shift(p, c, f_dev, m, st, s, &R->counters[2], clk));
         }
         s->borrowed = true;
         shifts.push_back(s.get());
@@ -544,7 +615,7 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
         EvalOut eo;
         {
             Timer t(st, &R->ms[1]);
-            SIMM_TRY(evaluate(shifts, regs, prm, rule, st, eo, nullptr, 0));
+            SIMM_TRY(evaluate(shifts, regs, prm, rule, st, eo, nullptr, 0, clk));
         }
         for (int64_t c = 0; c < ncell; ++c) resolv[{c, s}] = eo.rho[c] <= prm->eps0;
         return SIMM_OK;
@@ -602,7 +673,7 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
         EvalOut eo;
         {
             Timer t(st, &R->ms[1]);
-            SIMM_TRY(evaluate(shifts, regs, prm, rule, st, eo, sums_dev, m_sums));
+            SIMM_TRY(evaluate(shifts, regs, prm, rule, st, eo, sums_dev, m_sums, clk));
         }
         std::vector<int> used(N);
         for (int64_t r = 0; r < N; ++r) used[r] = cur[r].s;
@@ -633,7 +704,7 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
             EvalOut e2;
             {
                 Timer t(st, &R->ms[1]);
-                SIMM_TRY(evaluate(shifts, tregs, prm, rule, st, e2, fb_dev, m_sums));
+                SIMM_TRY(evaluate(shifts, tregs, prm, rule, st, e2, fb_dev, m_sums, clk));
             }
             std::vector<int64_t> still;
             for (size_t q = 0; q < tryr.size(); ++q) {
@@ -701,9 +772,12 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
                 hipLaunchKernelGGL(k_gather_sums, dim3((unsigned)(2 * cnt)), dim3(128), 0, st, (const cplx*)sums_dev,
                                    m_sums, idx_buf.as<const int64_t>(), cnt, Ybuf.as<cplx>());
                 SIMM_HIP_TRY(hipGetLastError());
-                SIMM_TRY(project(n, shifts[s]->m_eff, shifts[s]->V, n, Ybuf.as<const cplx>(), m_sums, 2 * cnt,
-                                 Xbuf.as<cplx>(), nrm_buf.as<double>(), scr_buf.as<double>(),
-                                 project_scratch_elems(n, cmax), st));
+                {
+                    KScope ks(clk, SIMM_K_PROJECT);
+                    SIMM_TRY(project(n, shifts[s]->m_eff, shifts[s]->V, n, Ybuf.as<const cplx>(), m_sums, 2 * cnt,
+                                     Xbuf.as<cplx>(), nrm_buf.as<double>(), scr_buf.as<double>(),
+                                     project_scratch_elems(n, cmax), st));
+                }
                 nrm_host.assign(2 * cnt, 0.0);
                 SIMM_HIP_TRY(hipMemcpyAsync(nrm_host.data(), nrm_buf.p, sizeof(double) * 2 * cnt,
                                             hipMemcpyDeviceToHost, st));
@@ -1243,6 +1317,15 @@ simm_status simm_result_stats(simm_result r, double* ms4, int64_t* counters3) {
         for (int i = 0; i < 4; ++i) ms4[i] = r->ms[i];
     if (counters3)
         for (int i = 0; i < 3; ++i) counters3[i] = r->counters[i];
+    return SIMM_OK;
+}
+
+simm_status simm_result_kernel_stats(simm_result r, double* ms, int64_t* launches) {
+    if (!r) return SIMM_EINVAL;
+    for (int k = 0; k < SIMM_K_COUNT; ++k) {
+        if (ms) ms[k] = r->kms[k];
+        if (launches) launches[k] = r->kcnt[k];
+    }
     return SIMM_OK;
 }
 

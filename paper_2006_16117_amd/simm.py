@@ -20,6 +20,8 @@ SIMM_OK = 0
 SIMM_MEM_HOST = 0
 SIMM_MEM_DEVICE = 1
 SIMM_FLAG_PROJECT = 1
+SIMM_FLAG_KERNEL_TIMING = 2
+KERNEL_NAMES = ["band_lu", "band_sweep", "gram_schmidt", "schur", "indicators", "project"]
 REJECTED, ADMISSIBLE, UNRESOLVED = 0, 1, 2
 
 STATUS_NAMES = {0: "SIMM_OK", -1: "SIMM_EINVAL", -2: "SIMM_ENODEV", -3: "SIMM_ENOMEM", -4: "SIMM_EHIP",
@@ -67,6 +69,7 @@ EXPORTS = {
     "simm_result_shift": (C.c_int, [_vp, _i32, C.POINTER(_vp)]),
     "simm_result_clusters": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _i64]),
     "simm_result_stats": (C.c_int, [_vp, _vp, _vp]),
+    "simm_result_kernel_stats": (C.c_int, [_vp, _vp, _vp]),
     "simm_result_destroy": (None, [_vp]),
 }
 for _name, (_res, _args) in EXPORTS.items():
@@ -279,6 +282,11 @@ class Result:
         _check(_lib.simm_result_stats(handle, ms.ctypes.data, ctr.ctypes.data))
         self.ms = dict(shift_builds=ms[0], indicators=ms[1], projection=ms[2], total=ms[3])
         self.counters = dict(quadrature_systems=int(ctr[0]), squares=int(ctr[1]), m_applications=int(ctr[2]))
+        kms = np.zeros(len(KERNEL_NAMES))
+        kcnt = np.zeros(len(KERNEL_NAMES), np.int64)
+        _check(_lib.simm_result_kernel_stats(handle, kms.ctypes.data, kcnt.ctypes.data))
+        self.kernel_ms = {k: float(v) for k, v in zip(KERNEL_NAMES, kms)}
+        self.kernel_launches = {k: int(v) for k, v in zip(KERNEL_NAMES, kcnt)}
 
     def shift(self, idx: int) -> Shift:
         h = _vp()

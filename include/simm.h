@@ -57,12 +57,13 @@ enum {
 /* Kernel classes reported by simm_result_kernel_stats. */
 enum {
     SIMM_K_BAND_LU = 0,       /* assembly + banded LU of one shift (all its launches)          */
-    SIMM_K_BAND_SWEEP = 1,    /* one application of U^{-1} L^{-1} P (one launch)               */
+    SIMM_K_BAND_SWEEP = 1,    /* one application of U^{-1} L^{-1} P (its partitioned launches) */
     SIMM_K_GRAM_SCHMIDT = 2,  /* one Arnoldi step's orthogonalisation (its launches)           */
     SIMM_K_SCHUR = 3,         /* Schur form of one H_m                                         */
     SIMM_K_INDICATORS = 4,    /* one indicator launch over a batch of squares                  */
     SIMM_K_PROJECT = 5,       /* one X = V_m Y launch                                          */
-    SIMM_K_COUNT = 6
+    SIMM_K_SPIKE_PREP = 6,    /* per-shift unit-state responses of the partitioned sweeps      */
+    SIMM_K_COUNT = 7
 };
 
 typedef struct simm_pencil_s* simm_pencil;

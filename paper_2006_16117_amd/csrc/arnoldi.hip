@@ -68,14 +68,23 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_dots(int64_t n, const cplx* _
     }
 }
 
-// out[i] = sum_blk partial[blk * ldp + i] for i < ntot (fixed order).
-__global__ void k_gs_reduce(const cplx* partial, int nblk, int ldp, int ntot, cplx* out, const int* active) {
+// out[i] = sum_blk partial[blk * ldp + i] for i < ntot: one block per column, a
+// fixed-shape tree over the (<= 256) row blocks, so the order never changes.
+__global__ __launch_bounds__(256) void k_gs_reduce(const cplx* partial, int nblk, int ldp, int ntot, cplx* out,
+                                                   const int* active) {
     if (active != nullptr && *active == 0) return;
-    for (int i = threadIdx.x; i < ntot; i += blockDim.x) {
-        cplx acc = mk(0.0, 0.0);
-        for (int b = 0; b < nblk; ++b) acc = acc + partial[(int64_t)b * ldp + i];
-        out[i] = acc;
+    __shared__ cplx red[256];
+    const int i = blockIdx.x;
+    if (i >= ntot) return;
+    cplx acc = mk(0.0, 0.0);
+    for (int b = threadIdx.x; b < nblk; b += 256) acc = acc + partial[(int64_t)b * ldp + i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + s];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) out[i] = red[0];
 }
 
 // w(r) -= sum_{i < ncol} V(r, i) h(i)
@@ -129,7 +138,7 @@ simm_status vec_norm_scale(int64_t n, const cplx* b, cplx* v1, double* beta, Arn
     const int ldp = 1;
     hipLaunchKernelGGL(k_gs_dots, dim3(w.nblk), dim3(GS_THREADS), 0, st, n, (const cplx*)nullptr, (int64_t)0, 0, b, 1,
                        w.partial, ldp, (const int*)nullptr);
-    hipLaunchKernelGGL(k_gs_reduce, dim3(1), dim3(64), 0, st, w.partial, w.nblk, ldp, 1, w.h1, (const int*)nullptr);
+    hipLaunchKernelGGL(k_gs_reduce, dim3(1), dim3(256), 0, st, w.partial, w.nblk, ldp, 1, w.h1, (const int*)nullptr);
     hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(64), 0, st, w.h1, beta);
     if (v1 != b) SIMM_HIP_TRY(hipMemcpyAsync(v1, b, n * sizeof(cplx), hipMemcpyDeviceToDevice, st));
     const unsigned blocks = (unsigned)((n + 255) / 256);
@@ -148,14 +157,14 @@ simm_status arnoldi_step(int64_t n, cplx* V, int64_t ldv, int j, cplx* H, int ld
     // pass 1: h1 = V^H w and ||w||^2
     hipLaunchKernelGGL(k_gs_dots, dim3(w.nblk), dim3(GS_THREADS), 0, st, n, (const cplx*)V, ldv, ncol, (const cplx*)wv,
                        1, w.partial, ldp, (const int*)active);
-    hipLaunchKernelGGL(k_gs_reduce, dim3(1), dim3(128), 0, st, (const cplx*)w.partial, w.nblk, ldp, ncol + 1, w.h1,
-                       (const int*)active);
+    hipLaunchKernelGGL(k_gs_reduce, dim3(ncol + 1), dim3(256), 0, st, (const cplx*)w.partial, w.nblk, ldp, ncol + 1,
+                       w.h1, (const int*)active);
     hipLaunchKernelGGL(k_gs_update, dim3(blocks), dim3(256), 0, st, n, (const cplx*)V, ldv, ncol, (const cplx*)w.h1, wv,
                        (const int*)active);
     // pass 2 (re-orthogonalisation)
     hipLaunchKernelGGL(k_gs_dots, dim3(w.nblk), dim3(GS_THREADS), 0, st, n, (const cplx*)V, ldv, ncol, (const cplx*)wv,
                        0, w.partial, ldp, (const int*)active);
-    hipLaunchKernelGGL(k_gs_reduce, dim3(1), dim3(128), 0, st, (const cplx*)w.partial, w.nblk, ldp, ncol, w.h2,
+    hipLaunchKernelGGL(k_gs_reduce, dim3(ncol), dim3(256), 0, st, (const cplx*)w.partial, w.nblk, ldp, ncol, w.h2,
                        (const int*)active);
     hipLaunchKernelGGL(k_gs_update, dim3(blocks), dim3(256), 0, st, n, (const cplx*)V, ldv, ncol, (const cplx*)w.h2, wv,
                        (const int*)active);
@@ -163,7 +172,7 @@ simm_status arnoldi_step(int64_t n, cplx* V, int64_t ldv, int j, cplx* H, int ld
     hipLaunchKernelGGL(k_gs_dots, dim3(w.nblk), dim3(GS_THREADS), 0, st, n, (const cplx*)nullptr, (int64_t)0, 0,
                        (const cplx*)wv, 1, w.partial, 1, (const int*)active);
     cplx* hw = w.h2 + (ncol + 1);
-    hipLaunchKernelGGL(k_gs_reduce, dim3(1), dim3(64), 0, st, (const cplx*)w.partial, w.nblk, 1, 1, hw,
+    hipLaunchKernelGGL(k_gs_reduce, dim3(1), dim3(256), 0, st, (const cplx*)w.partial, w.nblk, 1, 1, hw,
                        (const int*)active);
     hipLaunchKernelGGL(k_arnoldi_finalize, dim3(1), dim3(128), 0, st, j, (const cplx*)w.h1, (const cplx*)w.h2,
                        (const cplx*)hw, 0.0, (const cplx*)w.h1, H, ldh, w.hnorm, active, m_eff);

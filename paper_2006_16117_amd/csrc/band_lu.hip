@@ -70,42 +70,50 @@ __device__ inline void ab_put(const LuArgs& a, int64_t i, int64_t c, cplx v) {
 
 // Factor the panel held in P (rows j1 .. j1+R1-1, columns j1 .. j1+nb1-1, leading
 // dimension ldp) in place; store multipliers / U / pivots in the band and the
-// permuted multipliers in `lt_out`.
+// permuted multipliers in `lt_out`.  Interchanges are applied to every panel
+// column (so P ends up with the permuted multipliers a blocked update needs);
+// the band keeps each column's multipliers as they were when computed, which is
+// recovered at the end by undoing the later interchanges on that column.
 __device__ void factor_panel(const LuArgs& a, cplx* P, int ldp, int64_t j1, int nb1, int R1, cplx* lt_out,
-                             double* red_v, int* red_i) {
+                             double* red_v, int* red_i, int* piv_s) {
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     for (int t = 0; t < nb1; ++t) {
         const int64_t j = j1 + t;
         const int km = (int)min((int64_t)a.kl, a.n - 1 - j);
         // pivot search: first index of max |re| + |im| over rows t .. t+km
         double best = -1.0;
-        int bidx = t;
+        int bidx = t + km + 1;
         for (int r = t + tid; r <= t + km; r += LU_THREADS) {
             const double v = cabs1(P[r + t * ldp]);
             if (v > best) { best = v; bidx = r; }
         }
-        red_v[tid] = best;
-        red_i[tid] = bidx;
-        __syncthreads();
-        for (int s = LU_THREADS / 2; s > 0; s >>= 1) {
-            if (tid < s) {
-                const double v2 = red_v[tid + s];
-                const int i2 = red_i[tid + s];
-                if (v2 > red_v[tid] || (v2 == red_v[tid] && i2 < red_i[tid])) {
-                    red_v[tid] = v2;
-                    red_i[tid] = i2;
-                }
-            }
-            __syncthreads();
+#pragma unroll
+        for (int msk = 32; msk >= 1; msk >>= 1) {
+            const double v2 = __shfl_xor(best, msk, 64);
+            const int i2 = __shfl_xor(bidx, msk, 64);
+            if (v2 > best || (v2 == best && i2 < bidx)) { best = v2; bidx = i2; }
         }
-        const int rp = red_i[0];
-        const bool zero = !(red_v[0] > 0.0);
-        __syncthreads();
-        if (tid == 0) a.ipiv[j] = (int)(j1 + rp);
+        if (lane == 0) {
+            red_v[wave] = best;
+            red_i[wave] = bidx;
+        }
+        lds_barrier();
+        best = red_v[0];
+        bidx = red_i[0];
+        for (int w = 1; w < LU_THREADS / 64; ++w) {
+            if (red_v[w] > best || (red_v[w] == best && red_i[w] < bidx)) { best = red_v[w]; bidx = red_i[w]; }
+        }
+        const int rp = bidx;
+        const bool zero = !(best > 0.0);
+        if (tid == 0) {
+            a.ipiv[j] = (int)(j1 + rp);
+            piv_s[t] = zero ? t : rp;
+        }
         if (zero) {
             if (tid == 0) atomicMin(a.info, (int)(j + 1));
             // LAPACK semantics: record the pivot, no interchange or elimination.
-            __syncthreads();
+            lds_barrier();
             continue;
         }
         if (rp != t) {
@@ -115,14 +123,10 @@ __device__ void factor_panel(const LuArgs& a, cplx* P, int ldp, int64_t j1, int 
                 P[rp + c * ldp] = tmp;
             }
         }
-        __syncthreads();
+        lds_barrier();
         const cplx piv = P[t + t * ldp];
-        for (int r = t + 1 + tid; r <= t + km; r += LU_THREADS) {
-            const cplx l = cdiv(P[r + t * ldp], piv);
-            P[r + t * ldp] = l;
-            ab_put(a, j1 + r, j, l);   // multiplier as computed at step j (unpermuted)
-        }
-        __syncthreads();
+        for (int r = t + 1 + tid; r <= t + km; r += LU_THREADS) P[r + t * ldp] = cdiv(P[r + t * ldp], piv);
+        lds_barrier();
         const int ncol = nb1 - t - 1;
         if (ncol > 0) {
             for (int e = tid; e < km * ncol; e += LU_THREADS) {
@@ -131,14 +135,31 @@ __device__ void factor_panel(const LuArgs& a, cplx* P, int ldp, int64_t j1, int 
                 P[r + c * ldp] = fms(P[r + c * ldp], P[r + t * ldp], P[t + c * ldp]);
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
-    // U part of the panel and the permuted multipliers for the trailing update
+    // permuted multipliers and U for the trailing update of the next launch; U to the band
     for (int e = tid; e < nb1 * R1; e += LU_THREADS) {
         const int r = e % R1, t = e / R1;
         const cplx v = P[r + t * ldp];
         if (r <= t) ab_put(a, j1 + r, j1 + t, v);
         lt_out[r + t * (a.nb + a.kl)] = v;
+    }
+    lds_barrier();
+    // undo the interchanges of later steps on each column's multipliers, then store them
+    for (int t = tid; t < nb1; t += LU_THREADS) {
+        for (int t2 = nb1 - 1; t2 > t; --t2) {
+            const int p2 = piv_s[t2];
+            if (p2 != t2) {
+                cplx tmp = P[t2 + t * ldp];
+                P[t2 + t * ldp] = P[p2 + t * ldp];
+                P[p2 + t * ldp] = tmp;
+            }
+        }
+    }
+    lds_barrier();
+    for (int e = tid; e < nb1 * R1; e += LU_THREADS) {
+        const int r = e % R1, t = e / R1;
+        if (r > t && r - t <= a.kl) ab_put(a, j1 + r, j1 + t, P[r + t * ldp]);
     }
 }
 
@@ -146,8 +167,9 @@ __device__ void factor_panel(const LuArgs& a, cplx* P, int ldp, int64_t j1, int 
 
 __global__ __launch_bounds__(LU_THREADS) void k_band_lu_step(LuArgs a, int64_t b) {
     extern __shared__ cplx smem[];
-    __shared__ double red_v[LU_THREADS];
-    __shared__ int red_i[LU_THREADS];
+    __shared__ double red_v[LU_THREADS / 64];
+    __shared__ int red_i[LU_THREADS / 64];
+    __shared__ int piv_s[32];
     const int tid = threadIdx.x;
     const int wg = blockIdx.x;
     const int nb = a.nb;
@@ -186,7 +208,7 @@ __global__ __launch_bounds__(LU_THREADS) void k_band_lu_step(LuArgs a, int64_t b
             const int r = e % Rb, c = e / Rb;
             Xc[r + c * ldx] = ab_get(a, j0 + r, c0 + c);
         }
-        __syncthreads();
+        lds_barrier();
         // interchanges, in order, then the unit lower triangular solve (one thread per column)
         for (int c = tid; c < ncols; c += LU_THREADS) {
             for (int t = 0; t < nbp; ++t) {
@@ -203,7 +225,7 @@ __global__ __launch_bounds__(LU_THREADS) void k_band_lu_step(LuArgs a, int64_t b
                 Xc[t + c * ldx] = acc;
             }
         }
-        __syncthreads();
+        lds_barrier();
         // rank-nbp update of rows nbp .. Rb-1
         const int nrow = Rb - nbp;
         for (int e = tid; e < nrow * ncols; e += LU_THREADS) {
@@ -212,13 +234,13 @@ __global__ __launch_bounds__(LU_THREADS) void k_band_lu_step(LuArgs a, int64_t b
             for (int s = 0; s < nbp; ++s) acc = fms(acc, Pan[r + s * ldl], Xc[s + c * ldx]);
             Xc[r + c * ldx] = acc;
         }
-        __syncthreads();
+        lds_barrier();
         // write back; workgroup 0 keeps rows j1.. in LDS for its panel
         for (int e = tid; e < Rb * ncols; e += LU_THREADS) {
             const int r = e % Rb, c = e / Rb;
             if (wg != 0 || r < nbp) ab_put(a, j0 + r, c0 + c, Xc[r + c * ldx]);
         }
-        __syncthreads();
+        lds_barrier();
     }
 
     if (wg == 0 && nb1 > 0) {
@@ -230,8 +252,8 @@ __global__ __launch_bounds__(LU_THREADS) void k_band_lu_step(LuArgs a, int64_t b
             const int r = e % R1, c = e / R1;
             if (r >= have) P[r + c * ldx] = ab_get(a, j1 + r, j1 + c);
         }
-        __syncthreads();
-        factor_panel(a, P, ldx, j1, nb1, R1, a.lt[(b + 1) & 1], red_v, red_i);
+        lds_barrier();
+        factor_panel(a, P, ldx, j1, nb1, R1, a.lt[(b + 1) & 1], red_v, red_i, piv_s);
     }
 }
 

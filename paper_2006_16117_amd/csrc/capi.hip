@@ -53,7 +53,9 @@ struct simm_shift_s {
     std::vector<cplx> H_host;   // (m_eff+1) x m_eff column-major
     std::vector<cplx> ritz;     // sigma + 1/theta
     bool borrowed = false;      // owned by a simm_result
+    SpikeFactor spike;          // partitioned-sweep data of the factor
     ~simm_shift_s() {
+        spike_release(spike);
         (void)hipFree(AB);
         (void)hipFree(ipiv);
         (void)hipFree(V);
@@ -121,8 +123,9 @@ struct KScope {
 };
 
 struct simm_result_s {
-    double kms[SIMM_K_COUNT] = {0, 0, 0, 0, 0, 0};
-    int64_t kcnt[SIMM_K_COUNT] = {0, 0, 0, 0, 0, 0};
+    double kms[SIMM_K_COUNT] = {0, 0, 0, 0, 0, 0, 0};
+    int64_t kcnt[SIMM_K_COUNT] = {0, 0, 0, 0, 0, 0, 0};
+    double kbytes[SIMM_K_COUNT] = {0, 0, 0, 0, 0, 0, 0};
     int K = 0;
     std::vector<std::unique_ptr<simm_shift_s>> shifts;
     std::vector<LevelRec> levels;
@@ -275,11 +278,11 @@ simm_status build_shift(simm_pencil_s* p, cplx sigma, const cplx* f_dev, int m, 
     s->kl = kl;
     s->ku = ku;
     const int ldab = 2 * kl + ku + 1;
-    if (lu_panel_width(kl) == 0 || sweep_threads(kl, ku) > 1024) {
+    if (lu_panel_width(kl) == 0 || kl + ku + 2 > 1024) {
         set_error("pencil bandwidth outside the supported range (kl <= 480, kl + ku <= 1022)");
         return SIMM_EUNSUPPORTED;
     }
-    SIMM_TRY(dalloc(&s->AB, (size_t)ldab * n));
+    SIMM_TRY(dalloc(&s->AB, (size_t)ldab * n + 1));   // + one zero entry read for out-of-band taps
     SIMM_TRY(dalloc(&s->ipiv, (size_t)n));
     SIMM_TRY(dalloc(&s->V, (size_t)n * (m + 1)));
     SIMM_TRY(dalloc(&s->H, (size_t)(m + 1) * m));
@@ -315,6 +318,7 @@ simm_status build_shift(simm_pencil_s* p, cplx sigma, const cplx* f_dev, int m, 
         SIMM_HIP_TRY(hipMemcpyAsync(flags, init, sizeof(init), hipMemcpyHostToDevice, st));
     }
 
+    SIMM_HIP_TRY(hipMemsetAsync(s->AB + (size_t)ldab * n, 0, sizeof(cplx), st));
     // a1 + a2: shifted band and its LU
     {
         KScope ks(clk, SIMM_K_BAND_LU);
@@ -331,10 +335,20 @@ simm_status build_shift(simm_pencil_s* p, cplx sigma, const cplx* f_dev, int m, 
         set_error(msg);
         return SIMM_ESINGULAR_SHIFT;
     }
+    // partitioned-sweep data (unit-state responses of every chunk)
+    s->spike.n = n;
+    s->spike.kl = kl;
+    s->spike.ku = ku;
+    s->spike.AB = s->AB;
+    s->spike.ipiv = s->ipiv;
+    {
+        KScope ks(clk, SIMM_K_SPIKE_PREP);
+        SIMM_TRY(spike_prepare(s->spike, st));
+    }
     // a3: b = (A - sigma B)^{-1} f, beta, v_1
     {
         KScope ks(clk, SIMM_K_BAND_SWEEP);
-        SIMM_TRY(band_sweep(n, kl, ku, s->AB, s->ipiv, f_dev, nullptr, s->V, st));
+        SIMM_TRY(spike_apply(s->spike, f_dev, s->V, nullptr, st));
     }
     SIMM_TRY(vec_norm_scale(n, s->V, s->V, beta_d, aw, st));
     // a4: Arnoldi steps
@@ -343,18 +357,24 @@ simm_status build_shift(simm_pencil_s* p, cplx sigma, const cplx* f_dev, int m, 
         SIMM_TRY(prepare_input(n, vj, p->B, p->klb, p->kub, nullptr, flags + 1, aw.u, nullptr, st));
         {
             KScope ks(clk, SIMM_K_BAND_SWEEP);
-            SIMM_TRY(band_sweep(n, kl, ku, s->AB, s->ipiv, aw.u, flags + 1, s->V + (int64_t)(j + 1) * n, st));
+            SIMM_TRY(spike_apply(s->spike, aw.u, s->V + (int64_t)(j + 1) * n, flags + 1, st));
         }
         KScope ks(clk, SIMM_K_GRAM_SCHMIDT);
         SIMM_TRY(arnoldi_step(n, s->V, n, j, s->H, m + 1, aw, flags + 1, flags + 2, st));
     }
     int fl[4];
+    int spike_err = 0;
     double beta = 0.0;
+    SIMM_HIP_TRY(hipMemcpyAsync(&spike_err, s->spike.err, sizeof(int), hipMemcpyDeviceToHost, st));
     SIMM_HIP_TRY(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, st));
     SIMM_HIP_TRY(hipMemcpyAsync(&beta, beta_d, sizeof(double), hipMemcpyDeviceToHost, st));
     std::vector<cplx> Hfull((size_t)(m + 1) * m);
     SIMM_HIP_TRY(hipMemcpyAsync(Hfull.data(), s->H, sizeof(cplx) * Hfull.size(), hipMemcpyDeviceToHost, st));
     SIMM_HIP_TRY(hipStreamSynchronize(st));
+    if (spike_err != 0) {
+        set_error("partitioned sweep: a chunk-chain barrier timed out");
+        return SIMM_EHIP;
+    }
     s->m_eff = fl[2];
     s->beta = beta;
     const int me = s->m_eff;
@@ -1093,7 +1113,7 @@ simm_status simm_shift_apply(simm_shift s, const double* x, double* y, int32_t m
         yd = yb.as<cplx>();
     }
     SIMM_TRY(prepare_input(n, xd, s->p->B, s->p->klb, s->p->kub, nullptr, nullptr, ub.as<cplx>(), nullptr, st));
-    SIMM_TRY(band_sweep(n, s->kl, s->ku, s->AB, s->ipiv, ub.as<const cplx>(), nullptr, yd, st));
+    SIMM_TRY(spike_apply(s->spike, ub.as<const cplx>(), yd, nullptr, st));
     if (mem == SIMM_MEM_HOST) SIMM_HIP_TRY(hipMemcpyAsync(y, yd, sizeof(cplx) * n, hipMemcpyDeviceToHost, st));
     SIMM_HIP_TRY(hipStreamSynchronize(st));
     return SIMM_OK;

@@ -43,6 +43,8 @@ __host__ __device__ inline cplx fma_c(cplx a, cplx b, cplx c) {
 __host__ __device__ inline cplx fma_cj(cplx a, cplx b, cplx c) {
     return cplx{a.re + b.re * c.re + b.im * c.im, a.im + b.re * c.im - b.im * c.re};
 }
+// c ? a : b, component-wise (a struct-valued ?: can be lowered through scratch memory)
+__host__ __device__ inline cplx csel(bool c, cplx a, cplx b) { return cplx{c ? a.re : b.re, c ? a.im : b.im}; }
 // a / b, scaled to avoid overflow (Smith's method)
 __host__ __device__ inline cplx cdiv(cplx a, cplx b) {
     if (fabs(b.re) >= fabs(b.im)) {
@@ -53,6 +55,15 @@ __host__ __device__ inline cplx cdiv(cplx a, cplx b) {
         return cplx{(a.re * r + a.im) / d, (a.im * r - a.re) / d};
     }
 }
+
+// ---------------------------------------------------------------------------
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS operations
+// and meets the other waves, without waiting on outstanding global loads (a
+// plain __syncthreads() also drains every global load in flight, which defeats
+// register prefetching in latency-bound loops).  The "memory" clobber keeps the
+// compiler from moving memory accesses across it.
+// ---------------------------------------------------------------------------
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // ---------------------------------------------------------------------------
 // error reporting (thread-local message behind simm_last_error)

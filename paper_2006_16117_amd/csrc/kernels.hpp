@@ -13,12 +13,73 @@ size_t band_lu_scratch_elems(int kl);
 // info must hold INT_MAX on entry; it receives the first singular column + 1.
 simm_status band_lu(int64_t n, int kl, int ku, cplx* AB, int* ipiv, cplx* lt_scratch, int* info, hipStream_t st);
 
-// ---- band sweeps (band_sweep.hip) ----
-int sweep_threads(int kl, int ku);
+// ---- input of the sweeps (band_sweep.hip) ----
 simm_status prepare_input(int64_t n, const cplx* x, const cplx* Bb, int klb, int kub, const double* hdiv,
                           const int* active, cplx* u, cplx* xs, hipStream_t st);
-simm_status band_sweep(int64_t n, int kl, int ku, const cplx* AB, const int* ipiv, const cplx* u, const int* active,
-                       cplx* y, hipStream_t st);
+
+// ---- partitioned band sweeps (band_spike.hip) ----
+struct SpikeFwd {
+    int64_t n;
+    int kl, kv, ldab;
+    const cplx* AB;
+    const int* ipiv;
+    int64_t s;
+    int mode;          // 0: zero state, input u; 1: unit state blockIdx.y, zero input
+    int64_t zidx;      // index of a zero entry stored right after the band factor
+    const cplx* u;
+    cplx* y;
+    cplx* tau;
+    cplx* Psi;
+    cplx* Phi;
+    const int* active;
+};
+struct SpikeBwd {
+    int64_t n;
+    int K, kvf, ldab;
+    const cplx* AB;
+    int64_t s;
+    int mode;
+    int64_t zidx;
+    const cplx* z;
+    cplx* y;
+    cplx* tau;
+    cplx* Psi;
+    cplx* Phi;
+    const int* active;
+};
+struct SpikeChain {
+    int64_t n;
+    int K;
+    int64_t P;
+    int forward;
+    const cplx* Phi;
+    const cplx* tau;
+    cplx* t;
+    const cplx* init_src;
+    int64_t init_row0;
+    unsigned* counter;
+    int* err;
+    const int* active;
+};
+struct SpikeFactor {
+    int64_t n = 0;
+    int kl = 0, ku = 0;       // bandwidths of A - sigma B
+    cplx* AB = nullptr;       // band LU factor, followed by one zero entry
+    int* ipiv = nullptr;
+    int K = 0, klx = 0;       // effective upper bandwidth of U, lower bandwidth used
+    int64_t s = 0, P = 0;     // chunk length and count
+    int Wf = 0, Wb = 0;       // threads of the forward / backward chunk kernels
+    void* mem = nullptr;
+    cplx *PsiL = nullptr, *PhiL = nullptr, *PsiU = nullptr, *PhiU = nullptr;
+    cplx *tauL = nullptr, *tL = nullptr, *tauU = nullptr, *tU = nullptr, *z = nullptr;
+    unsigned* counter = nullptr;
+    int* err = nullptr;
+};
+int64_t spike_chunk_len(int64_t n, int kl, int K);
+simm_status spike_prepare(SpikeFactor& f, hipStream_t st);
+simm_status spike_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int* active, hipStream_t st);
+void spike_release(SpikeFactor& f);
+int64_t spike_bytes_per_apply(const SpikeFactor& f);
 
 // ---- Gram-Schmidt (arnoldi.hip) ----
 struct ArnoldiWork {

@@ -48,76 +48,72 @@ __global__ __launch_bounds__(MAXW) void k_chunk_fwd(SpikeFwd a) {
     __shared__ cplx slotX[2], slotA[2];
     const int W = blockDim.x;
     const int t = threadIdx.x;
-    const int64_t n = a.n;
+    const int n = (int)a.n;
     const int kl = a.kl;
-    const int64_t c = blockIdx.x;
+    const int c = blockIdx.x;
     const int r_unit = blockIdx.y;              // mode 1: which unit state
-    const int64_t J0 = c * a.s;
-    const int64_t J1 = min(n, J0 + a.s);
-    const int len = (int)(J1 - J0);
+    const int J0 = c * (int)a.s;
+    const int J1 = min(n, J0 + (int)a.s);
+    const int len = J1 - J0;
+    const int nin = len + kl;                   // input rows J0 .. J1+kl-1
     cplx* outb = sm;                            // len
-    cplx* inb = sm + a.s;                       // len + kl  (rows J0 .. J1+kl-1)
+    cplx* inb = sm + a.s;                       // nin
     int* piv = reinterpret_cast<int*>(sm + 2 * a.s + kl + 1);   // len + 1
     for (int q = t; q < len; q += W) piv[q] = a.ipiv[J0 + q];
     if (t == 0) piv[len] = -1;
     if (a.mode == 0) {
-        for (int q = t; q < len + kl; q += W) {
-            const int64_t row = J0 + q;
-            inb[q] = (q < kl) ? mk(0.0, 0.0) : ldz(a.u, row, n);
-        }
+        for (int q = t; q < nin; q += W) inb[q] = (q < kl || J0 + q >= n) ? mk(0.0, 0.0) : a.u[J0 + q];
     }
     __syncthreads();
 
-    auto inval = [&](int64_t row) -> cplx {
-        const int64_t q = row - J0;
-        const bool in = (row < n && q < len + kl);
-        if (a.mode == 0) {
-            const cplx v = inb[min(q, (int64_t)(len + kl - 1))];
-            return csel(in, v, mk(0.0, 0.0));
-        }
+    // value entering the window for a row (state rows first, then chunk input)
+    auto inval = [&](int row) -> cplx {
+        const int q = row - J0;
+        const bool in = (row < n && q < nin);
+        if (a.mode == 0) return csel(in, inb[min(q, nin - 1)], mk(0.0, 0.0));
         return mk((in && q == r_unit) ? 1.0 : 0.0, 0.0);
     };
-    int64_t row = J0 + (((int64_t)t - J0 % W) % W + W) % W;
+    // Factor entry for my row at step jj.  Every thread loads something every step
+    // (out-of-band taps read the zero entry stored after the band), so the loads in
+    // flight are the same on every path and the compiler's waits stay exact.
+    const int64_t colstep = a.ldab - 1;         // (row, jj) -> kv + row + jj (ldab - 1)
+    auto lidx = [&](int r, int jj) -> int64_t {
+        const int rr = (r >= jj) ? r : r + W;
+        const int d = rr - jj;
+        const bool ok = jj < J1 && d >= 1 && d <= kl && rr < n;
+        return ok ? (int64_t)(a.kv + rr) + (int64_t)jj * colstep : a.zidx;
+    };
+    int row = J0 + ((t - J0 % W) % W + W) % W;
     cplx val = inval(row);
     int pj = piv[0];
     if (row == J0) slotA[J0 & 1] = val;
     if (row == pj) slotX[J0 & 1] = val;
-
-    // Factor entry (my row at step jj, column jj).  Every thread loads something every
-    // step -- entries outside the band come from the zero word stored after the band --
-    // so the number of loads
-    // in flight is the same on every path and the compiler's waits stay exact.
-    auto row_at = [&](int64_t r, int64_t jj) -> int64_t { return (r >= jj) ? r : r + W; };
-    auto lptr = [&](int64_t r, int64_t jj) -> const cplx* {
-        const int64_t d = row_at(r, jj) - jj;
-        const int64_t km = min((int64_t)kl, n - 1 - jj);
-        return a.AB + ((jj < J1 && d >= 1 && d <= km) ? (int64_t)(a.kv + d) + jj * a.ldab : a.zidx);
-    };
     cplx ring[PF];
 #pragma unroll
-    for (int q = 0; q < PF; ++q) ring[q] = *lptr(row, J0 + q);
+    for (int q = 0; q < PF; ++q) ring[q] = a.AB[lidx(row, J0 + q)];
     lds_barrier();
 
-    // The ring slot is consumed before it is refilled, so the refill reuses its
-    // registers and the loop carries no register copies; the step is branch-free
-    // around memory operations.
-    auto step = [&](int64_t j, cplx& slot_ring) {
+    // One column step.  The ring slot is consumed before it is refilled (no
+    // loop-carried register copies); memory operations sit outside branches.
+    auto step = [&](int j, cplx& slot) {
         const int pj1 = piv[j + 1 - J0];
         const cplx X = slotX[j & 1];
         const cplx A = slotA[j & 1];
-        const bool retire = (row == j);
-        const cplx upd = fms(csel(row == pj, A, val), slot_ring, X);   // zero factor outside the band
-        if (retire) outb[j - J0] = X;
-        row = retire ? row + W : row;
-        const cplx fresh = inval(row);
-        val = csel(retire, fresh, upd);
-        slot_ring = *lptr(row, j + PF);
+        const cplx upd = fms(csel(row == pj, A, val), slot, X);   // zero factor outside the band
+        if (row == j) {
+            outb[j - J0] = X;
+            row += W;
+            val = inval(row);
+        } else {
+            val = upd;
+        }
+        slot = a.AB[lidx(row, j + PF)];
         if (row == j + 1) slotA[(j + 1) & 1] = val;
         if (row == pj1) slotX[(j + 1) & 1] = val;
         pj = pj1;
         lds_barrier();
     };
-    int64_t j0 = J0;
+    int j0 = J0;
     for (; j0 + PF <= J1; j0 += PF) {
 #pragma unroll
         for (int q = 0; q < PF; ++q) step(j0 + q, ring[q]);
@@ -125,18 +121,18 @@ __global__ __launch_bounds__(MAXW) void k_chunk_fwd(SpikeFwd a) {
 #pragma unroll
     for (int q = 0; q < PF; ++q)
         if (j0 + q < J1) step(j0 + q, ring[q]);
+
     // end state: rows J1 .. J1+kl-1
-    const int64_t qe = row - J1;
-    cplx* dst_state = (a.mode == 0) ? a.tau + c * kl : a.Phi + (size_t)c * kl * kl;
+    const int qe = row - J1;
     if (qe >= 0 && qe < kl) {
         const cplx v = (row < n) ? val : mk(0.0, 0.0);
-        if (a.mode == 0) dst_state[qe] = v;
-        else dst_state[qe * kl + r_unit] = v;        // Phi_c(i, r) at [c][i][r]
+        if (a.mode == 0) a.tau[(int64_t)c * kl + qe] = v;
+        else a.Phi[(int64_t)c * kl * kl + (int64_t)qe * kl + r_unit] = v;    // Phi_c(i, r) at [c][i][r]
     }
     __syncthreads();
     for (int q = t; q < len; q += W) {
         if (a.mode == 0) a.y[J0 + q] = outb[q];
-        else a.Psi[(J0 + q) + (int64_t)r_unit * n] = outb[q];
+        else a.Psi[(int64_t)(J0 + q) + (int64_t)r_unit * n] = outb[q];
     }
 }
 
@@ -150,64 +146,64 @@ __global__ __launch_bounds__(MAXW) void k_chunk_bwd(SpikeBwd a) {
     __shared__ cplx slotA[2];
     const int W = blockDim.x;
     const int t = threadIdx.x;
-    const int64_t n = a.n;
+    const int n = (int)a.n;
     const int K = a.K;
-    const int64_t c = blockIdx.x;
+    const int c = blockIdx.x;
     const int r_unit = blockIdx.y;
-    const int64_t J0 = c * a.s;
-    const int64_t J1 = min(n, J0 + a.s);
-    const int len = (int)(J1 - J0);
-    const int64_t ib0 = J0 - W;                 // input rows [J0 - W, J1 - K)
+    const int J0 = c * (int)a.s;
+    const int J1 = min(n, J0 + (int)a.s);
+    const int len = J1 - J0;
+    const int ib0 = J0 - W;                     // input rows [J0 - W, J1 - K)
+    const int nib = len + W;
     cplx* outb = sm;                            // len
     cplx* dg = sm + a.s;                        // len diagonals
-    cplx* inb = sm + 2 * a.s;                   // len + W
-    for (int q = t; q < len; q += W) dg[q] = a.AB[(int64_t)a.kvf + (J0 + q) * a.ldab];
+    cplx* inb = sm + 2 * a.s;                   // nib
+    for (int q = t; q < len; q += W) dg[q] = a.AB[(int64_t)a.kvf + (int64_t)(J0 + q) * a.ldab];
     if (a.mode == 0) {
-        for (int q = t; q < len + W; q += W) {
-            const int64_t row = ib0 + q;
-            inb[q] = (row < J1 - K) ? ldz(a.z, row, n) : mk(0.0, 0.0);
+        for (int q = t; q < nib; q += W) {
+            const int row = ib0 + q;
+            inb[q] = (row >= 0 && row < J1 - K && row < n) ? a.z[row] : mk(0.0, 0.0);
         }
     }
     __syncthreads();
 
-    auto inval = [&](int64_t row) -> cplx {
+    auto inval = [&](int row) -> cplx {
         const bool state = row >= J1 - K;       // state rows: zero, or the unit vector
-        if (a.mode == 0) {
-            const cplx v = inb[max((int64_t)0, min(row - ib0, (int64_t)(len + W - 1)))];
-            return csel(row >= 0 && !state, v, mk(0.0, 0.0));
-        }
+        if (a.mode == 0) return csel(row >= 0 && !state, inb[max(0, min(row - ib0, nib - 1))], mk(0.0, 0.0));
         return mk((row >= 0 && state && row - (J1 - K) == r_unit) ? 1.0 : 0.0, 0.0);
     };
-    const int64_t base = J1 - W;
-    int64_t row = base + (((int64_t)t - base % W) % W + W) % W;
+    const int64_t colstep = a.ldab + 1;         // (row, jj) -> kvf - jj + row + jj ldab
+    auto uidx = [&](int r, int jj) -> int64_t {
+        const int rr = (r <= jj) ? r : r - W;
+        const int d = jj - rr;
+        const bool ok = jj >= J0 && d >= 1 && d <= K && rr >= 0;
+        return ok ? (int64_t)(a.kvf + rr) + (int64_t)jj * colstep - 2 * (int64_t)jj : a.zidx;
+    };
+    const int base = J1 - W;
+    int row = base + ((t - base % W) % W + W) % W;
     cplx val = inval(row);
     if (row == J1 - 1) slotA[(J1 - 1) & 1] = val;
-
-    auto row_atb = [&](int64_t r, int64_t jj) -> int64_t { return (r <= jj) ? r : r - W; };
-    auto uptr = [&](int64_t r, int64_t jj) -> const cplx* {
-        const int64_t d = jj - row_atb(r, jj);
-        const int64_t km = min((int64_t)K, jj);
-        return a.AB + ((jj >= J0 && d >= 1 && d <= km) ? (int64_t)(a.kvf - d) + jj * a.ldab : a.zidx);
-    };
     cplx ring[PF];
 #pragma unroll
-    for (int q = 0; q < PF; ++q) ring[q] = *uptr(row, J1 - 1 - q);
+    for (int q = 0; q < PF; ++q) ring[q] = a.AB[uidx(row, J1 - 1 - q)];
     lds_barrier();
 
-    auto step = [&](int64_t j, cplx& slot_ring) {
+    auto step = [&](int j, cplx& slot) {
         const cplx A = slotA[j & 1];
         const cplx xj = cdiv(A, dg[j - J0]);
-        const bool retire = (row == j);
-        const cplx upd = fms(val, slot_ring, xj);
-        if (retire) outb[j - J0] = xj;
-        row = retire ? row - W : row;
-        const cplx fresh = inval(row);
-        val = csel(retire, fresh, upd);
-        slot_ring = *uptr(row, j - PF);
+        const cplx upd = fms(val, slot, xj);
+        if (row == j) {
+            outb[j - J0] = xj;
+            row -= W;
+            val = inval(row);
+        } else {
+            val = upd;
+        }
+        slot = a.AB[uidx(row, j - PF)];
         if (row == j - 1) slotA[(j - 1) & 1] = val;
         lds_barrier();
     };
-    int64_t j0 = J1 - 1;
+    int j0 = J1 - 1;
     for (; j0 - PF + 1 >= J0; j0 -= PF) {
 #pragma unroll
         for (int q = 0; q < PF; ++q) step(j0 - q, ring[q]);
@@ -215,17 +211,18 @@ __global__ __launch_bounds__(MAXW) void k_chunk_bwd(SpikeBwd a) {
 #pragma unroll
     for (int q = 0; q < PF; ++q)
         if (j0 - q >= J0) step(j0 - q, ring[q]);
+
     // end state: rows J0 - K .. J0 - 1
-    const int64_t qe = row - (J0 - K);
+    const int qe = row - (J0 - K);
     if (qe >= 0 && qe < K) {
         const cplx v = (row >= 0) ? val : mk(0.0, 0.0);
-        if (a.mode == 0) a.tau[c * K + qe] = v;
-        else a.Phi[(size_t)c * K * K + qe * K + r_unit] = v;
+        if (a.mode == 0) a.tau[(int64_t)c * K + qe] = v;
+        else a.Phi[(int64_t)c * K * K + (int64_t)qe * K + r_unit] = v;
     }
     __syncthreads();
     for (int q = t; q < len; q += W) {
         if (a.mode == 0) a.y[J0 + q] = outb[q];
-        else a.Psi[(J0 + q) + (int64_t)r_unit * n] = outb[q];
+        else a.Psi[(int64_t)(J0 + q) + (int64_t)r_unit * n] = outb[q];
     }
 }
 
@@ -233,45 +230,54 @@ __global__ __launch_bounds__(MAXW) void k_chunk_bwd(SpikeBwd a) {
 // chain over the chunk boundaries: t_{next} = tau_c + Phi_c t_c
 // G workgroups own row slices of the state and meet at a device-scope barrier
 // (monotone counter) after each step; a bounded spin turns a missing partner
-// into an error flag instead of a hang.
+// into an error flag instead of a hang.  Each thread keeps its part of the
+// next step's Phi row in registers, loaded while the barrier is pending.
 // ---------------------------------------------------------------------------
 constexpr int CH_THREADS = 256;
 constexpr int CH_PARTS = 16;                         // threads per state row
 constexpr int CH_ROWS = CH_THREADS / CH_PARTS;       // state rows per workgroup
 
+template <int MAXQ>
 __global__ __launch_bounds__(CH_THREADS) void k_spike_chain(SpikeChain a) {
     if (a.active != nullptr && *a.active == 0) return;
-    extern __shared__ cplx tcur[];                   // K
+    __shared__ cplx tcur[CH_PARTS * MAXQ];           // state, zero-padded
     const int K = a.K;
     const int g = blockIdx.x;
     const int tid = threadIdx.x;
     const int il = tid / CH_PARTS, part = tid % CH_PARTS;
     const int i = g * CH_ROWS + il;
-    // initial state
+    const int ic = min(i, K - 1);
+    const int64_t KK = (int64_t)K * K;
     const int64_t c_first = a.forward ? 0 : a.P - 1;
-    for (int r = tid; r < K; r += CH_THREADS) {
+    for (int r = tid; r < CH_PARTS * MAXQ; r += CH_THREADS) {
         const int64_t row = a.init_row0 + r;
-        const cplx v = ldz(a.init_src, row, a.n);
+        const cplx v = (r < K) ? ldz(a.init_src, row, a.n) : mk(0.0, 0.0);
         tcur[r] = v;
-        if (g == 0) a.t[c_first * K + r] = v;
+        if (g == 0 && r < K) a.t[c_first * K + r] = v;
     }
+    cplx ph[MAXQ];
+    auto load_phi = [&](int64_t c) {
+        const cplx* prow = a.Phi + c * KK + (int64_t)ic * K;
+#pragma unroll
+        for (int q = 0; q < MAXQ; ++q) ph[q] = prow[min(part + CH_PARTS * q, K - 1)];
+    };
+    if (a.P > 1) load_phi(c_first);
     __syncthreads();
     for (int64_t step = 0; step + 1 < a.P; ++step) {
         const int64_t c = a.forward ? step : a.P - 1 - step;
         const int64_t cn = a.forward ? c + 1 : c - 1;
         cplx acc = mk(0.0, 0.0);
-        if (i < K) {
-            const cplx* prow = a.Phi + (size_t)c * K * K + (size_t)i * K;
-            for (int r = part; r < K; r += CH_PARTS) acc = fma_c(acc, prow[r], tcur[r]);
-        }
+#pragma unroll
+        for (int q = 0; q < MAXQ; ++q) acc = fma_c(acc, ph[q], tcur[part + CH_PARTS * q]);   // padded t is 0
+        if (step + 2 < a.P) load_phi(a.forward ? c + 1 : c - 1);
 #pragma unroll
         for (int m = CH_PARTS / 2; m >= 1; m >>= 1) {
             acc.re += __shfl_xor(acc.re, m, 64);
             acc.im += __shfl_xor(acc.im, m, 64);
         }
         if (part == 0 && i < K) a.t[cn * K + i] = a.tau[c * K + i] + acc;
-        // device-scope barrier among the G workgroups: every thread releases its
-        // stores, thread 0 arrives and waits, every thread acquires
+        // device-scope barrier: every thread releases its stores, thread 0 arrives
+        // and waits, every thread acquires
         __threadfence();
         __syncthreads();
         if (tid == 0) {
@@ -279,8 +285,8 @@ __global__ __launch_bounds__(CH_THREADS) void k_spike_chain(SpikeChain a) {
             const unsigned target = (unsigned)(gridDim.x * (step + 1));
             long spins = 0;
             while (__hip_atomic_load(a.counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > 20000000L) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > 40000000L) {
                     atomicExch(a.err, 1);
                     break;
                 }
@@ -293,16 +299,35 @@ __global__ __launch_bounds__(CH_THREADS) void k_spike_chain(SpikeChain a) {
     }
 }
 
-// y(j) += sum_r Psi(j, r) t_{c(j)}(r)
+// y(j) += sum_r Psi(j, r) t_{c(j)}(r); the (at most two) state vectors a block
+// needs are staged in LDS.
 __global__ __launch_bounds__(256) void k_spike_correct(int64_t n, int K, int64_t s, const cplx* __restrict__ Psi,
                                                        const cplx* __restrict__ t, cplx* __restrict__ y,
                                                        const int* active) {
     if (active != nullptr && *active == 0) return;
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    extern __shared__ cplx ts[];                     // 2 K
+    const int64_t jb = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t cb = jb / s;
+    const int64_t ce = min(n - 1, jb + (int64_t)blockDim.x - 1) / s;
+    for (int r = threadIdx.x; r < K; r += blockDim.x) {
+        ts[r] = t[cb * K + r];
+        ts[K + r] = t[ce * K + r];
+    }
+    __syncthreads();
+    const int64_t j = jb + threadIdx.x;
     if (j >= n) return;
-    const cplx* tc = t + (j / s) * K;
+    const cplx* tc = ts + ((j / s == cb) ? 0 : K);
     cplx acc = y[j];
-    for (int r = 0; r < K; ++r) acc = fma_c(acc, Psi[j + (int64_t)r * n], tc[r]);
+    const cplx* pr = Psi + j;
+    int r = 0;
+    for (; r + 8 <= K; r += 8) {
+        cplx v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = pr[(int64_t)(r + u) * n];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = fma_c(acc, v[u], tc[r + u]);
+    }
+    for (; r < K; ++r) acc = fma_c(acc, pr[(int64_t)r * n], tc[r]);
     y[j] = acc;
 }
 
@@ -377,6 +402,10 @@ simm_status spike_prepare(SpikeFactor& f, hipStream_t st) {
     f.klx = (int)std::min<int64_t>(f.kl, f.n - 1);
     f.s = spike_chunk_len(f.n, f.klx, f.K);
     f.P = (f.n + f.s - 1) / f.s;
+    if (f.n > (int64_t)1 << 30) {
+        set_error("order above 2^30 is not supported by the partitioned sweeps");
+        return SIMM_EUNSUPPORTED;
+    }
     f.Wf = pow2_at_least(f.klx + 2);
     f.Wb = pow2_at_least(f.K + 2);
     if (f.Wf > 1024 || f.Wb > 1024) {
@@ -461,7 +490,9 @@ static simm_status run_chain(const SpikeFactor& f, bool forward, int K, const cp
     c.err = f.err;
     c.active = active;
     const int G = (K + CH_ROWS - 1) / CH_ROWS;
-    hipLaunchKernelGGL(k_spike_chain, dim3(G), dim3(CH_THREADS), sizeof(cplx) * (size_t)K, st, c);
+    if (K <= 16 * CH_PARTS) hipLaunchKernelGGL(k_spike_chain<16>, dim3(G), dim3(CH_THREADS), 0, st, c);
+    else if (K <= 32 * CH_PARTS) hipLaunchKernelGGL(k_spike_chain<32>, dim3(G), dim3(CH_THREADS), 0, st, c);
+    else hipLaunchKernelGGL(k_spike_chain<64>, dim3(G), dim3(CH_THREADS), 0, st, c);
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;
 }
@@ -487,8 +518,8 @@ simm_status spike_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int*
         a.active = active;
         SIMM_TRY(launch_fwd(a, f.P, 1, f.Wf, fwd_lds(f.s, f.klx), st));
         SIMM_TRY(run_chain(f, true, f.klx, f.PhiL, f.tauL, f.tL, u, 0, active, st));
-        hipLaunchKernelGGL(k_spike_correct, dim3(blocks), dim3(256), 0, st, f.n, f.klx, f.s, (const cplx*)f.PsiL,
-                           (const cplx*)f.tL, z, active);
+        hipLaunchKernelGGL(k_spike_correct, dim3(blocks), dim3(256), sizeof(cplx) * 2 * f.klx, st, f.n, f.klx, f.s,
+                           (const cplx*)f.PsiL, (const cplx*)f.tL, z, active);
     } else {
         SIMM_HIP_TRY(hipMemcpyAsync(z, u, sizeof(cplx) * f.n, hipMemcpyDeviceToDevice, st));
     }
@@ -509,8 +540,8 @@ simm_status spike_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int*
     SIMM_TRY(launch_bwd(b, f.P, 1, f.Wb, bwd_lds(f.s, f.Wb), st));
     if (f.K > 0) {
         SIMM_TRY(run_chain(f, false, f.K, f.PhiU, f.tauU, f.tU, z, f.n - f.K, active, st));
-        hipLaunchKernelGGL(k_spike_correct, dim3(blocks), dim3(256), 0, st, f.n, f.K, f.s, (const cplx*)f.PsiU,
-                           (const cplx*)f.tU, y, active);
+        hipLaunchKernelGGL(k_spike_correct, dim3(blocks), dim3(256), sizeof(cplx) * 2 * f.K, st, f.n, f.K, f.s,
+                           (const cplx*)f.PsiU, (const cplx*)f.tU, y, active);
     }
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;

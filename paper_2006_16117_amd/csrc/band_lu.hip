@@ -46,6 +46,8 @@ namespace {
 
 constexpr int LU_THREADS = 256;
 
+__host__ __device__ inline int lds_ld(int rows) { return ((rows + 15) / 16) * 16 + 1; }
+
 struct LuArgs {
     int64_t n;
     int kl, ku, kv, ldab;
@@ -54,8 +56,30 @@ struct LuArgs {
     cplx* AB;
     int* ipiv;       // 0-based global row of the pivot of each column
     cplx* lt[2];     // permuted panel multipliers, (nb + kl) x nb column-major, double buffered
-    int* info;       // first singular column + 1 (0 if none)
+    int* info;       // first singular column + 1 (INT_MAX if none)
+    int64_t zidx;    // index of the zero entry stored after the band
 };
+
+// Index of band entry (i, c), or of the zero entry when (i, c) lies outside the
+// band: loads through it are unconditional, so a loop of them keeps many in flight.
+__device__ inline int64_t ab_idx(const LuArgs& a, int64_t i, int64_t c) {
+    const int64_t d = i - c;
+    const bool in = i >= 0 && i < a.n && c >= 0 && c < a.n && d >= -a.kv && d <= a.kl;
+    return in ? (int64_t)(a.kv + d) + c * a.ldab : a.zidx;
+}
+
+// dst[r + c*ldd] = band(i0 + r, c0 + c) for rfrom <= r < R, c < C (C <= 16): one row per
+// thread, its 16 column loads issued together.
+__device__ inline void load_tile(const LuArgs& a, cplx* dst, int ldd, int64_t i0, int64_t c0, int R, int C, int rfrom) {
+    for (int r = rfrom + (int)threadIdx.x; r < R; r += LU_THREADS) {
+        cplx v[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) v[c] = a.AB[c < C ? ab_idx(a, i0 + r, c0 + c) : a.zidx];
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            if (c < C) dst[r + c * ldd] = v[c];
+    }
+}
 
 __device__ inline cplx ab_get(const LuArgs& a, int64_t i, int64_t c) {
     const int64_t d = i - c;
@@ -127,22 +151,24 @@ __device__ void factor_panel(const LuArgs& a, cplx* P, int ldp, int64_t j1, int 
         const cplx piv = P[t + t * ldp];
         for (int r = t + 1 + tid; r <= t + km; r += LU_THREADS) P[r + t * ldp] = cdiv(P[r + t * ldp], piv);
         lds_barrier();
-        const int ncol = nb1 - t - 1;
-        if (ncol > 0) {
-            for (int e = tid; e < km * ncol; e += LU_THREADS) {
-                const int r = t + 1 + e % km;
-                const int c = t + 1 + e / km;
-                P[r + c * ldp] = fms(P[r + c * ldp], P[r + t * ldp], P[t + c * ldp]);
+        // rank-1 update: thread -> column t+1 + (tid % 16), rows t+1 + tid/16 + 16k
+        {
+            const int c = t + 1 + (tid & 15);
+            if (c < nb1) {
+                const cplx ptc = P[t + c * ldp];
+                for (int r = t + 1 + (tid >> 4); r <= t + km; r += LU_THREADS / 16)
+                    P[r + c * ldp] = fms(P[r + c * ldp], P[r + t * ldp], ptc);
             }
         }
         lds_barrier();
     }
     // permuted multipliers and U for the trailing update of the next launch; U to the band
-    for (int e = tid; e < nb1 * R1; e += LU_THREADS) {
-        const int r = e % R1, t = e / R1;
-        const cplx v = P[r + t * ldp];
-        if (r <= t) ab_put(a, j1 + r, j1 + t, v);
-        lt_out[r + t * (a.nb + a.kl)] = v;
+    for (int t = 0; t < nb1; ++t) {
+        for (int r = tid; r < R1; r += LU_THREADS) {
+            const cplx v = P[r + t * ldp];
+            if (r <= t) ab_put(a, j1 + r, j1 + t, v);
+            lt_out[r + t * (a.nb + a.kl)] = v;
+        }
     }
     lds_barrier();
     // undo the interchanges of later steps on each column's multipliers, then store them
@@ -157,9 +183,8 @@ __device__ void factor_panel(const LuArgs& a, cplx* P, int ldp, int64_t j1, int 
         }
     }
     lds_barrier();
-    for (int e = tid; e < nb1 * R1; e += LU_THREADS) {
-        const int r = e % R1, t = e / R1;
-        if (r > t && r - t <= a.kl) ab_put(a, j1 + r, j1 + t, P[r + t * ldp]);
+    for (int t = 0; t < nb1; ++t) {
+        for (int r = t + 1 + tid; r <= t + a.kl && r < R1; r += LU_THREADS) ab_put(a, j1 + r, j1 + t, P[r + t * ldp]);
     }
 }
 
@@ -173,10 +198,12 @@ __global__ __launch_bounds__(LU_THREADS) void k_band_lu_step(LuArgs a, int64_t b
     const int tid = threadIdx.x;
     const int wg = blockIdx.x;
     const int nb = a.nb;
-    const int ldl = nb + a.kl;                 // rows of the panel buffers
+    // LDS leading dimensions padded to 1 (mod 16) complex entries, so the 16 columns a
+    // wavefront touches start in 16 different banks
+    const int ldl = lds_ld(nb + a.kl);         // rows of the panel buffer
     cplx* Pan = smem;                          // ldl x nb      : permuted multipliers of panel b
+    const int ldx = lds_ld(2 * nb + a.kl);
     cplx* Xc = smem + (size_t)ldl * nb;        // ldx x ncols   : my column slice, rows j0 ..
-    const int ldx = 2 * nb + a.kl;
 
     const int64_t j0 = b * nb;                                  // panel b (b may be -1)
     const int nbp = (b >= 0) ? (int)min((int64_t)nb, a.n - j0) : 0;
@@ -200,45 +227,64 @@ __global__ __launch_bounds__(LU_THREADS) void k_band_lu_step(LuArgs a, int64_t b
     if (b >= 0 && ncols > 0) {
         const int Rb = (int)min((int64_t)(nbp + a.kl), a.n - j0);   // rows j0 .. j0+Rb-1 touched
         const cplx* lt_in = a.lt[b & 1];
-        for (int e = tid; e < Rb * nbp; e += LU_THREADS) {
-            const int r = e % Rb, t = e / Rb;
-            Pan[r + t * ldl] = lt_in[r + t * ldl];
+        {
+            const int ldg = a.nb + a.kl;        // leading dimension of the global panel buffer
+            for (int r = tid; r < Rb; r += LU_THREADS) {
+                cplx v[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) v[q] = lt_in[r + (q < nbp ? q : 0) * ldg];
+#pragma unroll
+                for (int q = 0; q < 16; ++q)
+                    if (q < nbp) Pan[r + q * ldl] = v[q];
+            }
         }
-        for (int e = tid; e < Rb * ncols; e += LU_THREADS) {
-            const int r = e % Rb, c = e / Rb;
-            Xc[r + c * ldx] = ab_get(a, j0 + r, c0 + c);
-        }
+        load_tile(a, Xc, ldx, j0, c0, Rb, ncols, 0);
+        if (tid < nbp) piv_s[tid] = (int)(a.ipiv[j0 + tid] - j0);
         lds_barrier();
-        // interchanges, in order, then the unit lower triangular solve (one thread per column)
+        // interchanges, in order (one thread per column)
         for (int c = tid; c < ncols; c += LU_THREADS) {
             for (int t = 0; t < nbp; ++t) {
-                const int p = (int)(a.ipiv[j0 + t] - j0);
+                const int p = piv_s[t];
                 if (p != t) {
                     cplx tmp = Xc[t + c * ldx];
                     Xc[t + c * ldx] = Xc[p + c * ldx];
                     Xc[p + c * ldx] = tmp;
                 }
             }
-            for (int t = 1; t < nbp; ++t) {
-                cplx acc = Xc[t + c * ldx];
-                for (int s = 0; s < t; ++s) acc = fms(acc, Pan[t + s * ldl], Xc[s + c * ldx]);
-                Xc[t + c * ldx] = acc;
+        }
+        lds_barrier();
+        // unit lower triangular solve: thread (column tid % 16, row tid / 16), one step per t
+        {
+            const int c = tid & 15, rr = tid >> 4;
+            for (int t = 0; t + 1 < nbp; ++t) {
+                if (c < ncols && rr > t && rr < nbp)
+                    Xc[rr + c * ldx] = fms(Xc[rr + c * ldx], Pan[rr + t * ldl], Xc[t + c * ldx]);
+                lds_barrier();
+            }
+        }
+        // rank-nbp update of rows nbp .. Rb-1: thread -> column tid % 16 (its U column in
+        // registers), rows nbp + tid/16 + 16k
+        {
+            const int c = tid & 15;
+            if (c < ncols) {
+                cplx u[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) u[q] = (q < nbp) ? Xc[q + c * ldx] : mk(0.0, 0.0);
+                for (int r = nbp + (tid >> 4); r < Rb; r += LU_THREADS / 16) {
+                    cplx acc = Xc[r + c * ldx];
+#pragma unroll
+                    for (int q = 0; q < 16; ++q)
+                        if (q < nbp) acc = fms(acc, Pan[r + q * ldl], u[q]);
+                    Xc[r + c * ldx] = acc;
+                }
             }
         }
         lds_barrier();
-        // rank-nbp update of rows nbp .. Rb-1
-        const int nrow = Rb - nbp;
-        for (int e = tid; e < nrow * ncols; e += LU_THREADS) {
-            const int c = e % ncols, r = nbp + e / ncols;
-            cplx acc = Xc[r + c * ldx];
-            for (int s = 0; s < nbp; ++s) acc = fms(acc, Pan[r + s * ldl], Xc[s + c * ldx]);
-            Xc[r + c * ldx] = acc;
-        }
-        lds_barrier();
         // write back; workgroup 0 keeps rows j1.. in LDS for its panel
-        for (int e = tid; e < Rb * ncols; e += LU_THREADS) {
-            const int r = e % Rb, c = e / Rb;
-            if (wg != 0 || r < nbp) ab_put(a, j0 + r, c0 + c, Xc[r + c * ldx]);
+        {
+            const int rend = (wg != 0) ? Rb : nbp;
+            for (int c = 0; c < ncols; ++c)
+                for (int r = tid; r < rend; r += LU_THREADS) ab_put(a, j0 + r, c0 + c, Xc[r + c * ldx]);
         }
         lds_barrier();
     }
@@ -248,20 +294,17 @@ __global__ __launch_bounds__(LU_THREADS) void k_band_lu_step(LuArgs a, int64_t b
         const int R1 = (int)min((int64_t)(nb1 + a.kl), a.n - j1);
         const int have = (b >= 0) ? (int)min((int64_t)(nbp + a.kl), a.n - j0) - nbp : 0;
         cplx* P = Xc + nbp;
-        for (int e = tid; e < R1 * nb1; e += LU_THREADS) {
-            const int r = e % R1, c = e / R1;
-            if (r >= have) P[r + c * ldx] = ab_get(a, j1 + r, j1 + c);
-        }
+        load_tile(a, P, ldx, j1, j1, R1, nb1, have);
         lds_barrier();
         factor_panel(a, P, ldx, j1, nb1, R1, a.lt[(b + 1) & 1], red_v, red_i, piv_s);
     }
 }
 
 int lu_panel_width(int kl) {
-    // two buffers of (nb + kl) rows and one of (2 nb + kl) rows, nb columns, must fit in LDS
+    // one buffer of (nb + kl) rows and one of (2 nb + kl) rows, nb columns, padded, must fit in LDS
     const size_t lds = 160 * 1024 - 8 * 1024;
     for (int nb = 16; nb >= 4; nb /= 2) {
-        size_t need = ((size_t)(nb + kl) + (size_t)(2 * nb + kl)) * nb * sizeof(cplx);
+        size_t need = ((size_t)lds_ld(nb + kl) + (size_t)lds_ld(2 * nb + kl)) * nb * sizeof(cplx);
         if (need <= lds) return nb;
     }
     return 0;
@@ -287,7 +330,8 @@ simm_status band_lu(int64_t n, int kl, int ku, cplx* AB, int* ipiv, cplx* lt_scr
     a.lt[0] = lt_scratch;
     a.lt[1] = lt_scratch + (size_t)(nb + kl) * nb;
     a.info = info;
-    const size_t lds = ((size_t)(nb + kl) * nb + (size_t)(2 * nb + kl) * nb) * sizeof(cplx);
+    a.zidx = (int64_t)a.ldab * n;
+    const size_t lds = ((size_t)lds_ld(nb + kl) * nb + (size_t)lds_ld(2 * nb + kl) * nb) * sizeof(cplx);
     const int grid = 2 + (a.kv + a.cw - 1) / a.cw;
     const int64_t nblk = (n + nb - 1) / nb;
     for (int64_t b = -1; b < nblk; ++b) {

@@ -8,13 +8,14 @@
 // only, so column j keeps its multipliers as computed ("interleaved" L) and a
 // solve applies interchange and elimination column by column.
 //
-// Blocked right-looking schedule, one launch per panel of NB columns:
-//   launch b:  every workgroup takes a slice of the columns right of panel b,
+// Blocked right-looking schedule, one launch per panel of NB = 16 columns:
+//   launch b:  every workgroup takes 16 of the columns right of panel b and
 //              applies panel b's interchanges, the unit-lower triangular solve and
-//              the rank-NB update (trailing window = rows of the panel + kl), and
-//              workgroup 0, which owns panel b+1, then factors panel b+1 in LDS.
-// Consecutive launches on one stream order the panels; no workgroup ever waits
-// on another.
+//              the rank-16 update (trailing window = rows of the panel + kl), and
+//              workgroup 0, which owns panel b+1, then factors panel b+1.
+// Each thread keeps one row of its window in registers; rows meet only through
+// LDS at workgroup barriers.  Consecutive launches on one stream order the panels;
+// no workgroup ever waits on another.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -44,47 +45,25 @@ __global__ void k_assemble_shifted(int64_t n, int kl, int ku, const cplx* __rest
 
 namespace {
 
-constexpr int LU_THREADS = 256;
-
-__host__ __device__ inline int lds_ld(int rows) { return ((rows + 15) / 16) * 16 + 1; }
+constexpr int NB = 16;        // panel width
+constexpr int SROW = NB + 1;  // LDS row stride (complex): 16 lanes writing 16-byte rows hit 16 bank groups
 
 struct LuArgs {
     int64_t n;
     int kl, ku, kv, ldab;
-    int nb;          // panel width
-    int cw;          // columns per trailing workgroup
     cplx* AB;
     int* ipiv;       // 0-based global row of the pivot of each column
-    cplx* lt[2];     // permuted panel multipliers, (nb + kl) x nb column-major, double buffered
+    cplx* lt[2];     // permuted panel multipliers, (NB + kl) x NB column-major, double buffered
     int* info;       // first singular column + 1 (INT_MAX if none)
     int64_t zidx;    // index of the zero entry stored after the band
 };
 
 // Index of band entry (i, c), or of the zero entry when (i, c) lies outside the
-// band: loads through it are unconditional, so a loop of them keeps many in flight.
+// band: loads through it are unconditional, so all of a thread's loads are in flight together.
 __device__ inline int64_t ab_idx(const LuArgs& a, int64_t i, int64_t c) {
     const int64_t d = i - c;
     const bool in = i >= 0 && i < a.n && c >= 0 && c < a.n && d >= -a.kv && d <= a.kl;
     return in ? (int64_t)(a.kv + d) + c * a.ldab : a.zidx;
-}
-
-// dst[r + c*ldd] = band(i0 + r, c0 + c) for rfrom <= r < R, c < C (C <= 16): one row per
-// thread, its 16 column loads issued together.
-__device__ inline void load_tile(const LuArgs& a, cplx* dst, int ldd, int64_t i0, int64_t c0, int R, int C, int rfrom) {
-    for (int r = rfrom + (int)threadIdx.x; r < R; r += LU_THREADS) {
-        cplx v[16];
-#pragma unroll
-        for (int c = 0; c < 16; ++c) v[c] = a.AB[c < C ? ab_idx(a, i0 + r, c0 + c) : a.zidx];
-#pragma unroll
-        for (int c = 0; c < 16; ++c)
-            if (c < C) dst[r + c * ldd] = v[c];
-    }
-}
-
-__device__ inline cplx ab_get(const LuArgs& a, int64_t i, int64_t c) {
-    const int64_t d = i - c;
-    if (i < 0 || i >= a.n || c < 0 || c >= a.n || d < -a.kv || d > a.kl) return mk(0.0, 0.0);
-    return a.AB[(int64_t)(a.kv + d) + c * a.ldab];
 }
 __device__ inline void ab_put(const LuArgs& a, int64_t i, int64_t c, cplx v) {
     const int64_t d = i - c;
@@ -92,228 +71,315 @@ __device__ inline void ab_put(const LuArgs& a, int64_t i, int64_t c, cplx v) {
     a.AB[(int64_t)(a.kv + d) + c * a.ldab] = v;
 }
 
-// Factor the panel held in P (rows j1 .. j1+R1-1, columns j1 .. j1+nb1-1, leading
-// dimension ldp) in place; store multipliers / U / pivots in the band and the
-// permuted multipliers in `lt_out`.  Interchanges are applied to every panel
-// column (so P ends up with the permuted multipliers a blocked update needs);
-// the band keeps each column's multipliers as they were when computed, which is
-// recovered at the end by undoing the later interchanges on that column.
-__device__ void factor_panel(const LuArgs& a, cplx* P, int ldp, int64_t j1, int nb1, int R1, cplx* lt_out,
-                             double* red_v, int* red_i, int* piv_s) {
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    for (int t = 0; t < nb1; ++t) {
-        const int64_t j = j1 + t;
-        const int km = (int)min((int64_t)a.kl, a.n - 1 - j);
-        // pivot search: first index of max |re| + |im| over rows t .. t+km
-        double best = -1.0;
-        int bidx = t + km + 1;
-        for (int r = t + tid; r <= t + km; r += LU_THREADS) {
-            const double v = cabs1(P[r + t * ldp]);
-            if (v > best) { best = v; bidx = r; }
-        }
+// Position that row i of the window held before the interchanges (t, pv[t]),
+// t = 0 .. NB-1, were applied in order.
+__device__ inline int trace_src(int i, const int* pv) {
+    int pos = i;
 #pragma unroll
-        for (int msk = 32; msk >= 1; msk >>= 1) {
-            const double v2 = __shfl_xor(best, msk, 64);
-            const int i2 = __shfl_xor(bidx, msk, 64);
-            if (v2 > best || (v2 == best && i2 < bidx)) { best = v2; bidx = i2; }
+    for (int t = NB - 1; t >= 0; --t) {
+        const int p = pv[t];
+        pos = (pos == t) ? p : ((pos == p) ? t : pos);
+    }
+    return pos;
+}
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ inline double dpp_d(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Maximum over the wavefront, returned to every lane: DPP within 16-lane rows
+// (quad xor 1, quad xor 2, half-row mirror, row mirror), then row broadcasts of
+// lanes 15 and 31 carry the row maxima to lane 63.
+__device__ inline double wave_max(double v) {
+    v = fmax(v, dpp_d<0xB1>(v));
+    v = fmax(v, dpp_d<0x4E>(v));
+    v = fmax(v, dpp_d<0x141>(v));
+    v = fmax(v, dpp_d<0x140>(v));
+    v = fmax(v, dpp_d<0x142, 0xA>(v));
+    v = fmax(v, dpp_d<0x143, 0xC>(v));
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
+
+// 1 / u by Smith's scaling (no overflow for any finite nonzero u).
+__device__ inline cplx crecip(cplx u) {
+    if (fabs(u.re) >= fabs(u.im)) {
+        const double s = u.im / u.re, d = 1.0 / (u.re + u.im * s);
+        return cplx{d, -s * d};
+    } else {
+        const double s = u.re / u.im, d = 1.0 / (u.im + u.re * s);
+        return cplx{s * d, -d};
+    }
+}
+
+// LDS layout of one step launch (complex entries).
+template <int T>
+struct LuSmem {
+    static constexpr int S = 0;                          // T x SROW   : window rows before interchanges
+    static constexpr int LSH = S + T * SROW;             // NB x SROW  : diagonal block of the panel multipliers
+    static constexpr int USH = LSH + NB * SROW;          // NB x SROW  : U12 block after the triangular solve
+    static constexpr int CAND = USH + NB * SROW;         // 2 x (T/64) x NB : candidate pivot row of each wave
+    static constexpr int ROWT = CAND + 2 * (T / 64) * NB;// 2 x NB     : row t before its interchange
+    static constexpr int END = ROWT + 2 * NB;
+    static constexpr size_t bytes = (size_t)END * sizeof(cplx) + 2 * (T / 64) * (sizeof(double) + sizeof(int)) + NB * sizeof(int);
+};
+
+}  // namespace
+
+namespace {
+
+struct FactorCtx {
+    int pr;          // row of the panel this thread holds (may be outside 0 .. R1-1)
+    bool prow;       // 0 <= pr < R1
+    int nb1;         // panel width
+    int64_t j1;      // first column (and row) of the panel
+    int lane, wave;
+    cplx* cand;      // 2 x waves x NB : each wave's candidate pivot row
+    cplx* rowt;      // 2 x NB         : row t before its interchange
+    double* red_v;   // 2 x waves      : each wave's largest |re| + |im|
+    int* red_i;      // 2 x waves      : its (first) panel row
+};
+
+// Column step t of the panel factorization (partial pivoting by largest |re|+|im|,
+// first index on ties, as in LAPACK's izamax): one LDS barrier per step, buffers
+// alternate between even and odd steps.
+template <int T, int t>
+__device__ __forceinline__ void factor_steps(const LuArgs& a, cplx (&X)[NB], const FactorCtx& f) {
+    constexpr int W = T / 64;
+    if (t < f.nb1) {
+        const int buf = t & 1;
+        const int64_t j = f.j1 + t;
+        const int pr = f.pr;
+        const int km = (int)min((int64_t)a.kl, a.n - 1 - j);
+        const double v = (f.prow && pr >= t && pr <= t + km) ? cabs1(X[t]) : -1.0;
+        const double m = wave_max(v);
+        const unsigned long long bal = __ballot(v == m);
+        const int first = bal ? __ffsll((long long)bal) - 1 : 0;
+        if (f.lane == first) {
+            f.red_v[buf * W + f.wave] = m;
+            f.red_i[buf * W + f.wave] = pr;
+#pragma unroll
+            for (int c = 0; c < NB; ++c) f.cand[(buf * W + f.wave) * NB + c] = X[c];
         }
-        if (lane == 0) {
-            red_v[wave] = best;
-            red_i[wave] = bidx;
+        if (pr == t) {
+#pragma unroll
+            for (int c = 0; c < NB; ++c) f.rowt[buf * NB + c] = X[c];
         }
         lds_barrier();
-        best = red_v[0];
-        bidx = red_i[0];
-        for (int w = 1; w < LU_THREADS / 64; ++w) {
-            if (red_v[w] > best || (red_v[w] == best && red_i[w] < bidx)) { best = red_v[w]; bidx = red_i[w]; }
+        double best = f.red_v[buf * W];
+        int bidx = f.red_i[buf * W], bw = 0;
+#pragma unroll
+        for (int w = 1; w < W; ++w) {
+            const double vw = f.red_v[buf * W + w];
+            const int iw = f.red_i[buf * W + w];
+            if (vw > best || (vw == best && iw < bidx)) { best = vw; bidx = iw; bw = w; }
         }
-        const int rp = bidx;
         const bool zero = !(best > 0.0);
-        if (tid == 0) {
-            a.ipiv[j] = (int)(j1 + rp);
-            piv_s[t] = zero ? t : rp;
+        if (zero) bidx = t;
+        if (threadIdx.x == 0) {
+            a.ipiv[j] = (int)(f.j1 + bidx);
+            // singular column: recorded; no interchange, no elimination
+            if (zero) atomicMin(a.info, (int)(j + 1));
         }
-        if (zero) {
-            if (tid == 0) atomicMin(a.info, (int)(j + 1));
-            // LAPACK semantics: record the pivot, no interchange or elimination.
-            lds_barrier();
-            continue;
-        }
-        if (rp != t) {
-            for (int c = tid; c < nb1; c += LU_THREADS) {
-                cplx tmp = P[t + c * ldp];
-                P[t + c * ldp] = P[rp + c * ldp];
-                P[rp + c * ldp] = tmp;
+        if (!zero) {
+            const cplx* crow = f.cand + (buf * W + bw) * NB;
+            if (pr == t) {
+#pragma unroll
+                for (int c = 0; c < NB; ++c) X[c] = crow[c];
+            } else if (pr == bidx) {
+#pragma unroll
+                for (int c = 0; c < NB; ++c) X[c] = f.rowt[buf * NB + c];
+            }
+            if (f.prow && pr > t) {
+                const cplx inv = crecip(crow[t]);
+                const cplx l = X[t] * inv;
+                X[t] = l;
+#pragma unroll
+                for (int c = t + 1; c < NB; ++c) X[c] = fms(X[c], l, crow[c]);
             }
         }
-        lds_barrier();
-        const cplx piv = P[t + t * ldp];
-        for (int r = t + 1 + tid; r <= t + km; r += LU_THREADS) P[r + t * ldp] = cdiv(P[r + t * ldp], piv);
-        lds_barrier();
-        // rank-1 update: thread -> column t+1 + (tid % 16), rows t+1 + tid/16 + 16k
-        {
-            const int c = t + 1 + (tid & 15);
-            if (c < nb1) {
-                const cplx ptc = P[t + c * ldp];
-                for (int r = t + 1 + (tid >> 4); r <= t + km; r += LU_THREADS / 16)
-                    P[r + c * ldp] = fms(P[r + c * ldp], P[r + t * ldp], ptc);
-            }
-        }
-        lds_barrier();
+        // column t's multipliers go to the band as computed now (later interchanges do not move them)
+        if (f.prow && pr > t && pr - t <= a.kl) a.AB[(int64_t)(a.kv + pr - t) + j * a.ldab] = X[t];
     }
-    // permuted multipliers and U for the trailing update of the next launch; U to the band
-    for (int t = 0; t < nb1; ++t) {
-        for (int r = tid; r < R1; r += LU_THREADS) {
-            const cplx v = P[r + t * ldp];
-            if (r <= t) ab_put(a, j1 + r, j1 + t, v);
-            lt_out[r + t * (a.nb + a.kl)] = v;
-        }
-    }
-    lds_barrier();
-    // undo the interchanges of later steps on each column's multipliers, then store them
-    for (int t = tid; t < nb1; t += LU_THREADS) {
-        for (int t2 = nb1 - 1; t2 > t; --t2) {
-            const int p2 = piv_s[t2];
-            if (p2 != t2) {
-                cplx tmp = P[t2 + t * ldp];
-                P[t2 + t * ldp] = P[p2 + t * ldp];
-                P[p2 + t * ldp] = tmp;
-            }
-        }
-    }
-    lds_barrier();
-    for (int t = 0; t < nb1; ++t) {
-        for (int r = t + 1 + tid; r <= t + a.kl && r < R1; r += LU_THREADS) ab_put(a, j1 + r, j1 + t, P[r + t * ldp]);
-    }
+    if constexpr (t + 1 < NB) factor_steps<T, t + 1>(a, X, f);
 }
 
 }  // namespace
 
-__global__ __launch_bounds__(LU_THREADS) void k_band_lu_step(LuArgs a, int64_t b) {
+// One launch per panel.  Thread tid holds row tid of the window (rows j0 .. of the
+// matrix, j0 = first row of panel b) for the 16 columns of its workgroup in
+// registers, plus its row of panel b's permuted multipliers.
+//   all workgroups: apply panel b's interchanges, the unit lower triangular solve
+//                   on the top rows and the rank-NB update to their 16 columns;
+//   workgroup 0:    its columns are panel b+1, which it then factors with partial
+//                   pivoting, one column step per LDS barrier.
+template <int T>
+__global__ __launch_bounds__(T) void k_band_lu_step(LuArgs a, int64_t b) {
     extern __shared__ cplx smem[];
-    __shared__ double red_v[LU_THREADS / 64];
-    __shared__ int red_i[LU_THREADS / 64];
-    __shared__ int piv_s[32];
+    using L = LuSmem<T>;
+    cplx* S = smem + L::S;
+    cplx* Lsh = smem + L::LSH;
+    cplx* Ush = smem + L::USH;
+    cplx* cand = smem + L::CAND;
+    cplx* rowt = smem + L::ROWT;
+    double* red_v = reinterpret_cast<double*>(smem + L::END);
+    int* red_i = reinterpret_cast<int*>(red_v + 2 * (T / 64));
+    int* piv_s = red_i + 2 * (T / 64);
+
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const int wg = blockIdx.x;
-    const int nb = a.nb;
-    // LDS leading dimensions padded to 1 (mod 16) complex entries, so the 16 columns a
-    // wavefront touches start in 16 different banks
-    const int ldl = lds_ld(nb + a.kl);         // rows of the panel buffer
-    cplx* Pan = smem;                          // ldl x nb      : permuted multipliers of panel b
-    const int ldx = lds_ld(2 * nb + a.kl);
-    cplx* Xc = smem + (size_t)ldl * nb;        // ldx x ncols   : my column slice, rows j0 ..
+    const int nbp = (b >= 0) ? (int)min((int64_t)NB, a.n - b * NB) : 0;   // width of panel b
+    const int64_t j1 = (b >= 0) ? b * NB + nbp : 0;                       // first column of panel b+1
+    const int64_t j0 = j1 - nbp;                                          // first row of the window
+    const int nb1 = (int)max((int64_t)0, min((int64_t)NB, a.n - j1));     // width of panel b+1
 
-    const int64_t j0 = b * nb;                                  // panel b (b may be -1)
-    const int nbp = (b >= 0) ? (int)min((int64_t)nb, a.n - j0) : 0;
-    const int64_t j1 = (b >= 0) ? j0 + nbp : 0;                 // panel b+1
-    const int nb1 = (int)max((int64_t)0, min((int64_t)nb, a.n - j1));
-
-    // my column slice
     int64_t c0, c1;
     if (wg == 0) {
         c0 = j1;
         c1 = j1 + nb1;
     } else {
         if (b < 0) return;
-        const int64_t jmax = min(a.n - 1, j0 + nbp - 1 + (int64_t)a.kv);
-        c0 = j1 + nb1 + (int64_t)(wg - 1) * a.cw;
-        c1 = min(c0 + a.cw, jmax + 1);
+        const int64_t jmax = min(a.n - 1, j1 - 1 + (int64_t)a.kv);
+        c0 = j1 + nb1 + (int64_t)(wg - 1) * NB;
+        c1 = min(c0 + NB, jmax + 1);
         if (c0 > jmax) return;
     }
     const int ncols = (int)(c1 - c0);
+    // Only panel b = last can be narrower than NB, and no column lies right of it: every
+    // launch that gets past here with b >= 0 has nbp == NB.
+    if (ncols <= 0) return;
+    const int Rb = (int)min((int64_t)(nbp + a.kl), a.n - j0);             // rows panel b updates
+    const int R1 = (wg == 0) ? (int)min((int64_t)(nb1 + a.kl), a.n - j1) : 0;  // rows of panel b+1
+    const int Rw = (wg == 0) ? nbp + R1 : Rb;                             // rows this workgroup holds
+    const int r = tid;
 
-    if (b >= 0 && ncols > 0) {
-        const int Rb = (int)min((int64_t)(nbp + a.kl), a.n - j0);   // rows j0 .. j0+Rb-1 touched
+    // ---- all global loads of the launch, issued together
+    cplx X[NB], Lr[NB];
+    {
+        const bool mine = r < Rw;
+#pragma unroll
+        for (int c = 0; c < NB; ++c) X[c] = a.AB[(mine && c < ncols) ? ab_idx(a, j0 + r, c0 + c) : a.zidx];
         const cplx* lt_in = a.lt[b & 1];
-        {
-            const int ldg = a.nb + a.kl;        // leading dimension of the global panel buffer
-            for (int r = tid; r < Rb; r += LU_THREADS) {
-                cplx v[16];
+        const int ldg = NB + a.kl;
+        const bool hasl = b >= 0 && r < Rb;
 #pragma unroll
-                for (int q = 0; q < 16; ++q) v[q] = lt_in[r + (q < nbp ? q : 0) * ldg];
-#pragma unroll
-                for (int q = 0; q < 16; ++q)
-                    if (q < nbp) Pan[r + q * ldl] = v[q];
-            }
-        }
-        load_tile(a, Xc, ldx, j0, c0, Rb, ncols, 0);
-        if (tid < nbp) piv_s[tid] = (int)(a.ipiv[j0 + tid] - j0);
-        lds_barrier();
-        // interchanges, in order (one thread per column)
-        for (int c = tid; c < ncols; c += LU_THREADS) {
-            for (int t = 0; t < nbp; ++t) {
-                const int p = piv_s[t];
-                if (p != t) {
-                    cplx tmp = Xc[t + c * ldx];
-                    Xc[t + c * ldx] = Xc[p + c * ldx];
-                    Xc[p + c * ldx] = tmp;
-                }
-            }
-        }
-        lds_barrier();
-        // unit lower triangular solve: thread (column tid % 16, row tid / 16), one step per t
-        {
-            const int c = tid & 15, rr = tid >> 4;
-            for (int t = 0; t + 1 < nbp; ++t) {
-                if (c < ncols && rr > t && rr < nbp)
-                    Xc[rr + c * ldx] = fms(Xc[rr + c * ldx], Pan[rr + t * ldl], Xc[t + c * ldx]);
-                lds_barrier();
-            }
-        }
-        // rank-nbp update of rows nbp .. Rb-1: thread -> column tid % 16 (its U column in
-        // registers), rows nbp + tid/16 + 16k
-        {
-            const int c = tid & 15;
-            if (c < ncols) {
-                cplx u[16];
-#pragma unroll
-                for (int q = 0; q < 16; ++q) u[q] = (q < nbp) ? Xc[q + c * ldx] : mk(0.0, 0.0);
-                for (int r = nbp + (tid >> 4); r < Rb; r += LU_THREADS / 16) {
-                    cplx acc = Xc[r + c * ldx];
-#pragma unroll
-                    for (int q = 0; q < 16; ++q)
-                        if (q < nbp) acc = fms(acc, Pan[r + q * ldl], u[q]);
-                    Xc[r + c * ldx] = acc;
-                }
-            }
-        }
-        lds_barrier();
-        // write back; workgroup 0 keeps rows j1.. in LDS for its panel
-        {
-            const int rend = (wg != 0) ? Rb : nbp;
-            for (int c = 0; c < ncols; ++c)
-                for (int r = tid; r < rend; r += LU_THREADS) ab_put(a, j0 + r, c0 + c, Xc[r + c * ldx]);
-        }
-        lds_barrier();
+        for (int q = 0; q < NB; ++q) Lr[q] = hasl ? lt_in[r + q * ldg] : mk(0.0, 0.0);
+        if (b >= 0 && tid < NB) piv_s[tid] = (int)(a.ipiv[j0 + tid] - j0);
     }
 
-    if (wg == 0 && nb1 > 0) {
-        // panel b+1 lives in Xc rows nbp .. ; rows beyond those the update touched come from the band
-        const int R1 = (int)min((int64_t)(nb1 + a.kl), a.n - j1);
-        const int have = (b >= 0) ? (int)min((int64_t)(nbp + a.kl), a.n - j0) - nbp : 0;
-        cplx* P = Xc + nbp;
-        load_tile(a, P, ldx, j1, j1, R1, nb1, have);
+    if (b >= 0) {
+        // ---- interchanges of panel b: rows that move go through LDS
+        if (r < Rb) {
+#pragma unroll
+            for (int c = 0; c < NB; ++c) S[r * SROW + c] = X[c];
+        }
+        if (r < NB) {
+#pragma unroll
+            for (int q = 0; q < NB; ++q) Lsh[r * SROW + q] = Lr[q];
+        }
         lds_barrier();
-        factor_panel(a, P, ldx, j1, nb1, R1, a.lt[(b + 1) & 1], red_v, red_i, piv_s);
+        int pv[NB];
+#pragma unroll
+        for (int t = 0; t < NB; ++t) pv[t] = piv_s[t];
+        if (r >= NB && r < Rb) {
+            const int sr = trace_src(r, pv);
+            if (sr != r) {
+#pragma unroll
+                for (int c = 0; c < NB; ++c) X[c] = S[sr * SROW + c];
+            }
+        }
+        // ---- unit lower triangular solve of the top NB rows.  The threads holding those
+        // rows switch to one column each (c = tid), reusing X for it.
+        if (r < NB) {
+            const int c = r;
+#pragma unroll
+            for (int t = 0; t < NB; ++t) X[t] = S[trace_src(t, pv) * SROW + c];
+#pragma unroll
+            for (int t = 0; t < NB; ++t) {
+#pragma unroll
+                for (int rr = t + 1; rr < NB; ++rr) X[rr] = fms(X[rr], Lsh[rr * SROW + t], X[t]);
+                __builtin_amdgcn_sched_barrier(0);   // keep later steps' LDS reads from piling up in registers
+            }
+#pragma unroll
+            for (int t = 0; t < NB; ++t) Ush[t * SROW + c] = X[t];
+            if (c < ncols) {
+#pragma unroll
+                for (int t = 0; t < NB; ++t) ab_put(a, j0 + t, c0 + c, X[t]);
+            }
+        }
+        lds_barrier();
+        // ---- rank-NB update of rows NB .. Rb-1
+        if (r >= NB && r < Rb) {
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+#pragma unroll
+                for (int c = 0; c < NB; ++c) X[c] = fms(X[c], Lr[q], Ush[q * SROW + c]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (wg != 0) {
+#pragma unroll
+                for (int c = 0; c < NB; ++c)
+                    if (c < ncols) ab_put(a, j0 + r, c0 + c, X[c]);
+            }
+        }
+    }
+    if (wg != 0) return;
+
+    // ---- workgroup 0: factor panel b+1 (window rows nbp .., panel row pr = r - nbp)
+    FactorCtx f;
+    f.pr = r - nbp;
+    f.prow = f.pr >= 0 && f.pr < R1;
+    f.nb1 = nb1;
+    f.j1 = j1;
+    f.lane = lane;
+    f.wave = wave;
+    f.cand = cand;
+    f.rowt = rowt;
+    f.red_v = red_v;
+    f.red_i = red_i;
+    factor_steps<T, 0>(a, X, f);
+    const int pr = f.pr;
+    const bool prow = f.prow;
+    // rows of U (final since their own step) to the band; permuted multipliers (the
+    // entries left of the diagonal) for the next launch's update
+    if (prow) {
+        if (pr < nb1) {
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+                if (q >= pr && q < nb1 && q - pr <= a.kv) a.AB[(int64_t)(a.kv + pr - q) + (j1 + q) * a.ldab] = X[q];
+        }
+        cplx* lt_out = a.lt[(b + 1) & 1];
+        const int ldg = NB + a.kl;
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+            if (q < nb1) lt_out[pr + q * ldg] = (q < pr) ? X[q] : mk(0.0, 0.0);
     }
 }
 
+namespace {
+template <int T>
+void launch_lu(const LuArgs& a, hipStream_t st) {
+    const int grid = 2 + (a.kv + NB - 1) / NB;
+    const int64_t nblk = (a.n + NB - 1) / NB;
+    const size_t lds = LuSmem<T>::bytes;
+    for (int64_t b = -1; b < nblk; ++b)
+        hipLaunchKernelGGL(k_band_lu_step<T>, dim3(b < 0 ? 1 : grid), dim3(T), lds, st, a, b);
+}
+}  // namespace
+
 int lu_panel_width(int kl) {
-    // one buffer of (nb + kl) rows and one of (2 nb + kl) rows, nb columns, padded, must fit in LDS
-    const size_t lds = 160 * 1024 - 8 * 1024;
-    for (int nb = 16; nb >= 4; nb /= 2) {
-        size_t need = ((size_t)lds_ld(nb + kl) + (size_t)lds_ld(2 * nb + kl)) * nb * sizeof(cplx);
-        if (need <= lds) return nb;
-    }
-    return 0;
+    // the workgroup holds the 2 NB + kl rows of its window, one per thread, at most 512
+    return (kl >= 0 && 2 * NB + kl <= 512) ? NB : 0;
 }
 
 simm_status band_lu(int64_t n, int kl, int ku, cplx* AB, int* ipiv, cplx* lt_scratch, int* info,
                     hipStream_t st) {
-    const int nb = lu_panel_width(kl);
-    if (nb == 0) {
+    if (lu_panel_width(kl) == 0) {
         set_error("lower bandwidth too large for the LU kernel");
         return SIMM_EUNSUPPORTED;
     }
@@ -323,28 +389,21 @@ simm_status band_lu(int64_t n, int kl, int ku, cplx* AB, int* ipiv, cplx* lt_scr
     a.ku = ku;
     a.kv = kl + ku;
     a.ldab = 2 * kl + ku + 1;
-    a.nb = nb;
-    a.cw = nb;
     a.AB = AB;
     a.ipiv = ipiv;
     a.lt[0] = lt_scratch;
-    a.lt[1] = lt_scratch + (size_t)(nb + kl) * nb;
+    a.lt[1] = lt_scratch + (size_t)(NB + kl) * NB;
     a.info = info;
     a.zidx = (int64_t)a.ldab * n;
-    const size_t lds = ((size_t)lds_ld(nb + kl) * nb + (size_t)lds_ld(2 * nb + kl) * nb) * sizeof(cplx);
-    const int grid = 2 + (a.kv + a.cw - 1) / a.cw;
-    const int64_t nblk = (n + nb - 1) / nb;
-    for (int64_t b = -1; b < nblk; ++b) {
-        hipLaunchKernelGGL(k_band_lu_step, dim3(b < 0 ? 1 : grid), dim3(LU_THREADS), lds, st, a, b);
-    }
+    if (2 * NB + kl <= 256)
+        launch_lu<256>(a, st);
+    else
+        launch_lu<512>(a, st);
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;
 }
 
-size_t band_lu_scratch_elems(int kl) {
-    const int nb = lu_panel_width(kl);
-    return 2 * (size_t)(nb + kl) * (size_t)(nb > 0 ? nb : 1);
-}
+size_t band_lu_scratch_elems(int kl) { return 2 * (size_t)(NB + kl) * NB; }
 
 simm_status assemble_shifted(int64_t n, int kl, int ku, const cplx* A, int kla, int kua, const cplx* B, int klb,
                              int kub, cplx sigma, cplx* AB, hipStream_t st) {

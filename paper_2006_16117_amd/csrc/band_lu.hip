@@ -105,16 +105,21 @@ __device__ inline double wave_max(double v) {
     return __hiloint2double(hi, lo);
 }
 
-// 1 / u by Smith's scaling (no overflow for any finite nonzero u).
+// 1 / u by Smith's scaling (no overflow for any finite nonzero u), without branches.
 __device__ inline cplx crecip(cplx u) {
-    if (fabs(u.re) >= fabs(u.im)) {
-        const double s = u.im / u.re, d = 1.0 / (u.re + u.im * s);
-        return cplx{d, -s * d};
-    } else {
-        const double s = u.re / u.im, d = 1.0 / (u.im + u.re * s);
-        return cplx{s * d, -d};
-    }
+    const bool big = fabs(u.re) >= fabs(u.im);
+    const double p = big ? u.re : u.im, q = big ? u.im : u.re;
+    const double s = q / p, d = 1.0 / (p + q * s);
+    return big ? cplx{d, -s * d} : cplx{s * d, -d};
 }
+
+// 16-byte LDS accesses (ds_read_b128 / ds_write_b128); every LDS buffer below is
+// 16-byte aligned and indexed in whole complex entries.
+__device__ inline cplx ldsr(const cplx* p) {
+    const double2 v = *reinterpret_cast<const double2*>(p);
+    return cplx{v.x, v.y};
+}
+__device__ inline void ldsw(cplx* p, cplx v) { *reinterpret_cast<double2*>(p) = double2{v.re, v.im}; }
 
 // LDS layout of one step launch (complex entries).
 template <int T>
@@ -122,8 +127,8 @@ struct LuSmem {
     static constexpr int S = 0;                          // T x SROW   : window rows before interchanges
     static constexpr int LSH = S + T * SROW;             // NB x SROW  : diagonal block of the panel multipliers
     static constexpr int USH = LSH + NB * SROW;          // NB x SROW  : U12 block after the triangular solve
-    static constexpr int CAND = USH + NB * SROW;         // 2 x (T/64) x NB : candidate pivot row of each wave
-    static constexpr int ROWT = CAND + 2 * (T / 64) * NB;// 2 x NB     : row t before its interchange
+    static constexpr int CAND = USH + NB * SROW;         // 2 x (T/64) x SROW : candidate pivot row of each wave, + its reciprocal pivot
+    static constexpr int ROWT = CAND + 2 * (T / 64) * SROW;  // 2 x NB : row t before its interchange
     static constexpr int END = ROWT + 2 * NB;
     static constexpr size_t bytes = (size_t)END * sizeof(cplx) + 2 * (T / 64) * (sizeof(double) + sizeof(int)) + NB * sizeof(int);
 };
@@ -156,27 +161,39 @@ __device__ __forceinline__ void factor_steps(const LuArgs& a, cplx (&X)[NB], con
         const int pr = f.pr;
         const int km = (int)min((int64_t)a.kl, a.n - 1 - j);
         const double v = (f.prow && pr >= t && pr <= t + km) ? cabs1(X[t]) : -1.0;
+        cplx inv_own = crecip(X[t]);                  // only the pivot's is used; computed by every
+        asm volatile("" : "+v"(inv_own.re), "+v"(inv_own.im));   // lane here so it overlaps the reduction
         const double m = wave_max(v);
         const unsigned long long bal = __ballot(v == m);
         const int first = bal ? __ffsll((long long)bal) - 1 : 0;
         if (f.lane == first) {
             f.red_v[buf * W + f.wave] = m;
             f.red_i[buf * W + f.wave] = pr;
+            cplx* cw = f.cand + (buf * W + f.wave) * SROW;
 #pragma unroll
-            for (int c = 0; c < NB; ++c) f.cand[(buf * W + f.wave) * NB + c] = X[c];
+            for (int c = 0; c < NB; ++c) ldsw(cw + c, X[c]);
+            ldsw(cw + NB, inv_own);
         }
         if (pr == t) {
 #pragma unroll
-            for (int c = 0; c < NB; ++c) f.rowt[buf * NB + c] = X[c];
+            for (int c = 0; c < NB; ++c) ldsw(f.rowt + buf * NB + c, X[c]);
         }
         lds_barrier();
-        double best = f.red_v[buf * W];
-        int bidx = f.red_i[buf * W], bw = 0;
+        double vw[W];
+        int iw[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            vw[w] = f.red_v[buf * W + w];
+            iw[w] = f.red_i[buf * W + w];
+        }
+        double best = vw[0];
+        int bidx = iw[0], bw = 0;
 #pragma unroll
         for (int w = 1; w < W; ++w) {
-            const double vw = f.red_v[buf * W + w];
-            const int iw = f.red_i[buf * W + w];
-            if (vw > best || (vw == best && iw < bidx)) { best = vw; bidx = iw; bw = w; }
+            const bool take = vw[w] > best || (vw[w] == best && iw[w] < bidx);
+            best = take ? vw[w] : best;
+            bidx = take ? iw[w] : bidx;
+            bw = take ? w : bw;
         }
         const bool zero = !(best > 0.0);
         if (zero) bidx = t;
@@ -186,20 +203,22 @@ __device__ __forceinline__ void factor_steps(const LuArgs& a, cplx (&X)[NB], con
             if (zero) atomicMin(a.info, (int)(j + 1));
         }
         if (!zero) {
-            const cplx* crow = f.cand + (buf * W + bw) * NB;
+            const cplx* crow = f.cand + (buf * W + bw) * SROW;
+            cplx u[NB + 1];
+#pragma unroll
+            for (int c = t; c <= NB; ++c) u[c] = ldsr(crow + c);
             if (pr == t) {
 #pragma unroll
-                for (int c = 0; c < NB; ++c) X[c] = crow[c];
+                for (int c = 0; c < NB; ++c) X[c] = ldsr(crow + c);
             } else if (pr == bidx) {
 #pragma unroll
-                for (int c = 0; c < NB; ++c) X[c] = f.rowt[buf * NB + c];
+                for (int c = 0; c < NB; ++c) X[c] = ldsr(f.rowt + buf * NB + c);
             }
             if (f.prow && pr > t) {
-                const cplx inv = crecip(crow[t]);
-                const cplx l = X[t] * inv;
+                const cplx l = X[t] * u[NB];
                 X[t] = l;
 #pragma unroll
-                for (int c = t + 1; c < NB; ++c) X[c] = fms(X[c], l, crow[c]);
+                for (int c = t + 1; c < NB; ++c) X[c] = fms(X[c], l, u[c]);
             }
         }
         // column t's multipliers go to the band as computed now (later interchanges do not move them)
@@ -219,7 +238,8 @@ __device__ __forceinline__ void factor_steps(const LuArgs& a, cplx (&X)[NB], con
 //                   pivoting, one column step per LDS barrier.
 template <int T>
 __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs a, int64_t b) {
-    extern __shared__ cplx smem[];
+    extern __shared__ double2 smem_raw[];
+    cplx* smem = reinterpret_cast<cplx*>(smem_raw);
     using L = LuSmem<T>;
     cplx* S = smem + L::S;
     cplx* Lsh = smem + L::LSH;
@@ -276,11 +296,11 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs a, int64_t b) {
         // ---- interchanges of panel b: rows that move go through LDS
         if (r < Rb) {
 #pragma unroll
-            for (int c = 0; c < NB; ++c) S[r * SROW + c] = X[c];
+            for (int c = 0; c < NB; ++c) ldsw(S + r * SROW + c, X[c]);
         }
         if (r < NB) {
 #pragma unroll
-            for (int q = 0; q < NB; ++q) Lsh[r * SROW + q] = Lr[q];
+            for (int q = 0; q < NB; ++q) ldsw(Lsh + r * SROW + q, Lr[q]);
         }
         lds_barrier();
         int pv[NB];
@@ -290,7 +310,7 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs a, int64_t b) {
             const int sr = trace_src(r, pv);
             if (sr != r) {
 #pragma unroll
-                for (int c = 0; c < NB; ++c) X[c] = S[sr * SROW + c];
+                for (int c = 0; c < NB; ++c) X[c] = ldsr(S + sr * SROW + c);
             }
         }
         // ---- unit lower triangular solve of the top NB rows.  The threads holding those
@@ -298,15 +318,15 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs a, int64_t b) {
         if (r < NB) {
             const int c = r;
 #pragma unroll
-            for (int t = 0; t < NB; ++t) X[t] = S[trace_src(t, pv) * SROW + c];
+            for (int t = 0; t < NB; ++t) X[t] = ldsr(S + trace_src(t, pv) * SROW + c);
 #pragma unroll
             for (int t = 0; t < NB; ++t) {
 #pragma unroll
-                for (int rr = t + 1; rr < NB; ++rr) X[rr] = fms(X[rr], Lsh[rr * SROW + t], X[t]);
+                for (int rr = t + 1; rr < NB; ++rr) X[rr] = fms(X[rr], ldsr(Lsh + rr * SROW + t), X[t]);
                 __builtin_amdgcn_sched_barrier(0);   // keep later steps' LDS reads from piling up in registers
             }
 #pragma unroll
-            for (int t = 0; t < NB; ++t) Ush[t * SROW + c] = X[t];
+            for (int t = 0; t < NB; ++t) ldsw(Ush + t * SROW + c, X[t]);
             if (c < ncols) {
 #pragma unroll
                 for (int t = 0; t < NB; ++t) ab_put(a, j0 + t, c0 + c, X[t]);
@@ -318,7 +338,7 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs a, int64_t b) {
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
 #pragma unroll
-                for (int c = 0; c < NB; ++c) X[c] = fms(X[c], Lr[q], Ush[q * SROW + c]);
+                for (int c = 0; c < NB; ++c) X[c] = fms(X[c], Lr[q], ldsr(Ush + q * SROW + c));
                 __builtin_amdgcn_sched_barrier(0);
             }
             if (wg != 0) {

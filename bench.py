@@ -33,15 +33,22 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def sweep_bytes(n: int, kl: int, ku: int) -> int:
-    """Algorithmic HBM bytes of one application of U^{-1} L^{-1} P: every stored
-    factor entry the sweeps read once (kl multipliers and the diagonal + kl+ku
-    superdiagonals of U per column, clipped at the matrix edges), the input vector
-    read once and the result written once (complex128)."""
-    kv = kl + ku
-    lower = sum(min(kl, n - 1 - j) for j in range(n))
-    upper = sum(min(kv, j) + 1 for j in range(n))
-    return 16 * (lower + upper + 2 * n)
+FP64_PEAK_TFLOPS = 78.6   # 256 CUs x 4 SIMDs x 16 FP64 FMA lanes x 2 flops x 2.4 GHz
+LU_PANEL = 16
+
+
+def apply_bytes(n: int, k: int, kb: int) -> int:
+    """Algorithmic HBM bytes of one application of M = (A - sigma B)^{-1} B: the
+    factor (3k+1 band rows), B (2 k_B + 1 rows), and about six n-vectors in and out,
+    complex128: 16 n [(3k+1) + (2 k_B + 1) + 6]."""
+    return 16 * n * ((3 * k + 1) + (2 * kb + 1) + 6)
+
+
+def lu_flops_per_launch(kl: int, ku: int) -> int:
+    """Algorithmic flops of one panel launch of the band LU: 16 columns, each a
+    rank-1 update of kl rows by kl + ku columns (8 real flops per complex
+    multiply-add)."""
+    return LU_PANEL * 8 * kl * (kl + ku)
 
 
 def cpu_baseline(pen, f, params, n_shifts, n_squares, n_qp, budget_s=30.0):
@@ -131,10 +138,17 @@ def main():
     n_sq = last.counters["squares"]
     value = n_qp / (ms_per_step / 1e3)
 
-    _, kl, ku = pen.n, max(pen.kl_a, pen.kl_b), max(pen.ku_a, pen.ku_b)
-    b_sweep = sweep_bytes(pen.n, kl, ku)
-    sweep_ms = kms["band_sweep"] / max(kcnt["band_sweep"], 1)
-    achieved = b_sweep / (sweep_ms / 1e3) / 1e9
+    n = pen.n
+    kl, ku = max(pen.kl_a, pen.kl_b), max(pen.ku_a, pen.ku_b)
+    kb = max(pen.kl_b, pen.ku_b) if pen.b_band is not None else 0
+    # dominant kernel: the band LU's panel step (one launch per 16 columns plus one)
+    lu_launches = kcnt["band_lu"] * ((n + LU_PANEL - 1) // LU_PANEL + 1)
+    lu_us = kms["band_lu"] * 1e3 / max(lu_launches, 1)
+    lu_tflops = lu_flops_per_launch(kl, ku) / (lu_us * 1e-6) / 1e12
+    # K2: one application of M (B v + partitioned L and U sweeps)
+    b_apply = apply_bytes(n, max(kl, ku), kb)
+    apply_ms = kms["band_sweep"] / max(kcnt["band_sweep"], 1)
+    apply_gbs = b_apply / (apply_ms / 1e3) / 1e9
     step_kernel_ms = {k: kms[k] / args.steps for k in kms}
     out = {
         "metric": METRIC,
@@ -159,15 +173,27 @@ def main():
             "resolvent_solves_per_step": n_qp, "clusters": len(last.lam),
         },
         "roofline": {
-            "kernel": "k_band_sweep (one application of U^-1 L^-1 P)",
+            "kernel": "k_band_lu_step (one 16-column panel of the banded LU)",
+            "bound": "alu",
+            "achieved": lu_tflops,
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": lu_tflops / FP64_PEAK_TFLOPS,
+            "traffic": None,
+            "flops_per_launch": lu_flops_per_launch(kl, ku),
+            "us_per_launch": lu_us,
+            "launches_per_step": lu_launches // args.steps,
+        },
+        "roofline_apply": {
+            "kernel": "one application of M = U^-1 L^-1 P B (k_prepare_input, k_chunk_fwd, k_spike_chain, "
+                      "k_spike_correct, k_chunk_bwd, k_spike_chain, k_spike_correct)",
             "bound": "hbm",
-            "achieved": achieved,
+            "achieved": apply_gbs,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "bytes_per_launch": b_sweep,
-            "ms_per_launch": sweep_ms,
+            "frac": apply_gbs / HBM_PEAK_GBS,
+            "bytes_per_launch": b_apply,
+            "ms_per_launch": apply_ms,
             "launches_per_step": kcnt["band_sweep"] // args.steps,
         },
         "kernel_ms_per_step": step_kernel_ms,

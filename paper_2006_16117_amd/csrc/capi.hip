@@ -354,9 +354,9 @@ simm_status build_shift(simm_pencil_s* p, cplx sigma, const cplx* f_dev, int m, 
     // a4: Arnoldi steps
     for (int j = 0; j < m; ++j) {
         cplx* vj = s->V + (int64_t)j * n;
-        SIMM_TRY(prepare_input(n, vj, p->B, p->klb, p->kub, nullptr, flags + 1, aw.u, nullptr, st));
         {
-            KScope ks(clk, SIMM_K_BAND_SWEEP);
+            KScope ks(clk, SIMM_K_BAND_SWEEP);   // one application of M: B v, then the factor's sweeps
+            SIMM_TRY(prepare_input(n, vj, p->B, p->klb, p->kub, nullptr, flags + 1, aw.u, nullptr, st));
             SIMM_TRY(spike_apply(s->spike, aw.u, s->V + (int64_t)(j + 1) * n, flags + 1, st));
         }
         KScope ks(clk, SIMM_K_GRAM_SCHMIDT);

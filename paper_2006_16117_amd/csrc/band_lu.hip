@@ -47,6 +47,7 @@ namespace {
 
 constexpr int NB = 16;        // panel width
 constexpr int SROW = NB + 1;  // LDS row stride (complex): 16 lanes writing 16-byte rows hit 16 bank groups
+constexpr int CSTRIDE = NB + 2;   // candidate record: row (NB entries), reciprocal pivot, (max, position)
 
 struct LuArgs {
     int64_t n;
@@ -105,6 +106,24 @@ __device__ inline double wave_max(double v) {
     return __hiloint2double(hi, lo);
 }
 
+// Minimum over the wavefront (same DPP pattern as wave_max), returned to every lane.
+__device__ inline int wave_min_int(int k) {
+    k = min(k, __builtin_amdgcn_update_dpp(k, k, 0xB1, 0xf, 0xf, false));
+    k = min(k, __builtin_amdgcn_update_dpp(k, k, 0x4E, 0xf, 0xf, false));
+    k = min(k, __builtin_amdgcn_update_dpp(k, k, 0x141, 0xf, 0xf, false));
+    k = min(k, __builtin_amdgcn_update_dpp(k, k, 0x140, 0xf, 0xf, false));
+    k = min(k, __builtin_amdgcn_update_dpp(k, k, 0x142, 0xa, 0xf, false));
+    k = min(k, __builtin_amdgcn_update_dpp(k, k, 0x143, 0xc, 0xf, false));
+    return __builtin_amdgcn_readlane(k, 63);
+}
+
+__device__ inline double rdlane_d(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+__device__ inline cplx rdlane(cplx v, int l) { return cplx{rdlane_d(v.re, l), rdlane_d(v.im, l)}; }
+
 // 1 / u by Smith's scaling (no overflow for any finite nonzero u), without branches.
 __device__ inline cplx crecip(cplx u) {
     const bool big = fabs(u.re) >= fabs(u.im);
@@ -127,10 +146,9 @@ struct LuSmem {
     static constexpr int S = 0;                          // T x SROW   : window rows before interchanges
     static constexpr int LSH = S + T * SROW;             // NB x SROW  : diagonal block of the panel multipliers
     static constexpr int USH = LSH + NB * SROW;          // NB x SROW  : U12 block after the triangular solve
-    static constexpr int CAND = USH + NB * SROW;         // 2 x (T/64) x SROW : candidate pivot row of each wave, + its reciprocal pivot
-    static constexpr int ROWT = CAND + 2 * (T / 64) * SROW;  // 2 x NB : row t before its interchange
-    static constexpr int END = ROWT + 2 * NB;
-    static constexpr size_t bytes = (size_t)END * sizeof(cplx) + 2 * (T / 64) * (sizeof(double) + sizeof(int)) + NB * sizeof(int);
+    static constexpr int CAND = USH + NB * SROW;         // 2 x (T/64) x CSTRIDE : each wave's pivot candidate
+    static constexpr int END = CAND + 2 * (T / 64) * CSTRIDE;
+    static constexpr size_t bytes = (size_t)END * sizeof(cplx) + NB * sizeof(int);
 };
 
 }  // namespace
@@ -138,83 +156,80 @@ struct LuSmem {
 namespace {
 
 struct FactorCtx {
-    int pr;          // row of the panel this thread holds (may be outside 0 .. R1-1)
-    bool prow;       // 0 <= pr < R1
+    bool prow;       // this thread holds a row of the panel
     int nb1;         // panel width
     int64_t j1;      // first column (and row) of the panel
     int lane, wave;
-    cplx* cand;      // 2 x waves x NB : each wave's candidate pivot row
-    cplx* rowt;      // 2 x NB         : row t before its interchange
-    double* red_v;   // 2 x waves      : each wave's largest |re| + |im|
-    int* red_i;      // 2 x waves      : its (first) panel row
+    cplx* cand;      // 2 x waves x CSTRIDE
 };
 
-// Column step t of the panel factorization (partial pivoting by largest |re|+|im|,
-// first index on ties, as in LAPACK's izamax): one LDS barrier per step, buffers
-// alternate between even and odd steps.
+// Column step t of the panel factorization: partial pivoting by the largest
+// |re| + |im| with the first position on ties (LAPACK's izamax rule).  Rows never
+// move between threads: each thread carries the position `pos` its row holds, and
+// an interchange just swaps two positions.  Per step one LDS barrier: each wave
+// writes its candidate (the row with its largest entry, that row's reciprocal
+// pivot, and the (max, position) pair) spread over lanes t .. NB+1, so it costs one
+// 16-byte LDS write per lane; after the barrier each wave reads all candidates the
+// same way and moves the winner's row into scalar registers with lane reads.
 template <int T, int t>
-__device__ __forceinline__ void factor_steps(const LuArgs& a, cplx (&X)[NB], const FactorCtx& f) {
+__device__ __forceinline__ void factor_steps(const LuArgs& a, cplx (&X)[NB], int& pos, const FactorCtx& f) {
     constexpr int W = T / 64;
     if (t < f.nb1) {
         const int buf = t & 1;
         const int64_t j = f.j1 + t;
-        const int pr = f.pr;
         const int km = (int)min((int64_t)a.kl, a.n - 1 - j);
-        const double v = (f.prow && pr >= t && pr <= t + km) ? cabs1(X[t]) : -1.0;
+        const bool valid = f.prow && pos >= t && pos <= t + km;
+        const double v = valid ? cabs1(X[t]) : -1.0;
         cplx inv_own = crecip(X[t]);                  // only the pivot's is used; computed by every
         asm volatile("" : "+v"(inv_own.re), "+v"(inv_own.im));   // lane here so it overlaps the reduction
         const double m = wave_max(v);
-        const unsigned long long bal = __ballot(v == m);
-        const int first = bal ? __ffsll((long long)bal) - 1 : 0;
-        if (f.lane == first) {
-            f.red_v[buf * W + f.wave] = m;
-            f.red_i[buf * W + f.wave] = pr;
-            cplx* cw = f.cand + (buf * W + f.wave) * SROW;
+        const int key = (v == m) ? pos : 0x7fffffff;
+        const int kmin = wave_min_int(key);
+        const unsigned long long bal = __ballot(key == kmin);
+        const int wl = bal ? __ffsll((long long)bal) - 1 : 0;
+        cplx rec = mk(m, (double)kmin);
 #pragma unroll
-            for (int c = 0; c < NB; ++c) ldsw(cw + c, X[c]);
-            ldsw(cw + NB, inv_own);
+        for (int c = t; c < NB; ++c) {
+            const cplx x = rdlane(X[c], wl);
+            rec = csel(f.lane == c, x, rec);
         }
-        if (pr == t) {
-#pragma unroll
-            for (int c = 0; c < NB; ++c) ldsw(f.rowt + buf * NB + c, X[c]);
+        {
+            const cplx x = rdlane(inv_own, wl);
+            rec = csel(f.lane == NB, x, rec);
         }
+        if (f.lane >= t && f.lane <= NB + 1) ldsw(f.cand + (buf * W + f.wave) * CSTRIDE + f.lane, rec);
         lds_barrier();
-        double vw[W];
-        int iw[W];
+        cplx cw[W];
 #pragma unroll
-        for (int w = 0; w < W; ++w) {
-            vw[w] = f.red_v[buf * W + w];
-            iw[w] = f.red_i[buf * W + w];
-        }
-        double best = vw[0];
-        int bidx = iw[0], bw = 0;
+        for (int w = 0; w < W; ++w) cw[w] = ldsr(f.cand + (buf * W + w) * CSTRIDE + min(max(f.lane, t), NB + 1));
+        double best = rdlane_d(cw[0].re, NB + 1);
+        int bpos = (int)rdlane_d(cw[0].im, NB + 1), bw = 0;
 #pragma unroll
         for (int w = 1; w < W; ++w) {
-            const bool take = vw[w] > best || (vw[w] == best && iw[w] < bidx);
-            best = take ? vw[w] : best;
-            bidx = take ? iw[w] : bidx;
+            const double vw = rdlane_d(cw[w].re, NB + 1);
+            const int pw = (int)rdlane_d(cw[w].im, NB + 1);
+            const bool take = vw > best || (vw == best && pw < bpos);
+            best = take ? vw : best;
+            bpos = take ? pw : bpos;
             bw = take ? w : bw;
         }
         const bool zero = !(best > 0.0);
-        if (zero) bidx = t;
+        if (zero) bpos = t;
         if (threadIdx.x == 0) {
-            a.ipiv[j] = (int)(f.j1 + bidx);
+            a.ipiv[j] = (int)(f.j1 + bpos);
             // singular column: recorded; no interchange, no elimination
             if (zero) atomicMin(a.info, (int)(j + 1));
         }
         if (!zero) {
-            const cplx* crow = f.cand + (buf * W + bw) * SROW;
+            cplx mine = cw[0];
+#pragma unroll
+            for (int w = 1; w < W; ++w) mine = csel(bw == w, cw[w], mine);
             cplx u[NB + 1];
 #pragma unroll
-            for (int c = t; c <= NB; ++c) u[c] = ldsr(crow + c);
-            if (pr == t) {
-#pragma unroll
-                for (int c = 0; c < NB; ++c) X[c] = ldsr(crow + c);
-            } else if (pr == bidx) {
-#pragma unroll
-                for (int c = 0; c < NB; ++c) X[c] = ldsr(f.rowt + buf * NB + c);
-            }
-            if (f.prow && pr > t) {
+            for (int c = t; c <= NB; ++c) u[c] = rdlane(mine, c);
+            const int p0 = pos;
+            pos = (p0 == t) ? bpos : ((p0 == bpos) ? t : p0);
+            if (f.prow && pos > t) {
                 const cplx l = X[t] * u[NB];
                 X[t] = l;
 #pragma unroll
@@ -222,9 +237,9 @@ __device__ __forceinline__ void factor_steps(const LuArgs& a, cplx (&X)[NB], con
             }
         }
         // column t's multipliers go to the band as computed now (later interchanges do not move them)
-        if (f.prow && pr > t && pr - t <= a.kl) a.AB[(int64_t)(a.kv + pr - t) + j * a.ldab] = X[t];
+        if (f.prow && pos > t && pos - t <= a.kl) a.AB[(int64_t)(a.kv + pos - t) + j * a.ldab] = X[t];
     }
-    if constexpr (t + 1 < NB) factor_steps<T, t + 1>(a, X, f);
+    if constexpr (t + 1 < NB) factor_steps<T, t + 1>(a, X, pos, f);
 }
 
 }  // namespace
@@ -245,10 +260,7 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs a, int64_t b) {
     cplx* Lsh = smem + L::LSH;
     cplx* Ush = smem + L::USH;
     cplx* cand = smem + L::CAND;
-    cplx* rowt = smem + L::ROWT;
-    double* red_v = reinterpret_cast<double*>(smem + L::END);
-    int* red_i = reinterpret_cast<int*>(red_v + 2 * (T / 64));
-    int* piv_s = red_i + 2 * (T / 64);
+    int* piv_s = reinterpret_cast<int*>(smem + L::END);
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -350,20 +362,17 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs a, int64_t b) {
     }
     if (wg != 0) return;
 
-    // ---- workgroup 0: factor panel b+1 (window rows nbp .., panel row pr = r - nbp)
+    // ---- workgroup 0: factor panel b+1 (window rows nbp .., panel position pos = r - nbp at the start)
     FactorCtx f;
-    f.pr = r - nbp;
-    f.prow = f.pr >= 0 && f.pr < R1;
+    int pos = r - nbp;
+    f.prow = pos >= 0 && pos < R1;
     f.nb1 = nb1;
     f.j1 = j1;
     f.lane = lane;
     f.wave = wave;
     f.cand = cand;
-    f.rowt = rowt;
-    f.red_v = red_v;
-    f.red_i = red_i;
-    factor_steps<T, 0>(a, X, f);
-    const int pr = f.pr;
+    factor_steps<T, 0>(a, X, pos, f);
+    const int pr = pos;
     const bool prow = f.prow;
     // rows of U (final since their own step) to the band; permuted multipliers (the
     // entries left of the diagonal) for the next launch's update

@@ -108,17 +108,43 @@ __global__ __launch_bounds__(PJ_THREADS) void k_vmy(int64_t n, int m, const cplx
     }
 }
 
-__global__ void k_colnorm_reduce(const double* colpart, int64_t nwaves, int64_t c, double* out) {
+// Column norms from the per-wave partial sums: first CN_GROUPS groups of waves
+// each reduce their share for 64 columns (4 threads per column, LDS combine),
+// then one pass adds the groups and takes the square root.
+constexpr int CN_GROUPS = 32;
+
+__global__ __launch_bounds__(256) void k_colnorm_partial(const double* __restrict__ colpart, int64_t nwaves, int64_t c,
+                                                         double* __restrict__ part) {
+    __shared__ double red[4][64];
+    const int jl = threadIdx.x & 63, sub = threadIdx.x >> 6;
+    const int64_t j = (int64_t)blockIdx.x * 64 + jl;
+    const int64_t per = (nwaves + CN_GROUPS - 1) / CN_GROUPS;
+    const int64_t w0 = (int64_t)blockIdx.y * per, w1 = min(nwaves, w0 + per);
+    double a0 = 0.0, a1 = 0.0;
+    if (j < c) {
+        int64_t w = w0 + sub;
+        for (; w + 4 < w1; w += 8) {
+            a0 += colpart[w * c + j];
+            a1 += colpart[(w + 4) * c + j];
+        }
+        if (w < w1) a0 += colpart[w * c + j];
+    }
+    red[sub][jl] = a0 + a1;
+    __syncthreads();
+    if (sub == 0 && j < c) part[(int64_t)blockIdx.y * c + j] = red[0][jl] + red[1][jl] + red[2][jl] + red[3][jl];
+}
+
+__global__ void k_colnorm_finish(const double* __restrict__ part, int64_t c, double* __restrict__ out) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= c) return;
     double acc = 0.0;
-    for (int64_t w = 0; w < nwaves; ++w) acc += colpart[w * c + j];
+    for (int g = 0; g < CN_GROUPS; ++g) acc += part[(int64_t)g * c + j];
     out[j] = sqrt(acc);
 }
 
 int64_t project_scratch_elems(int64_t n, int64_t c) {
     const int64_t nwaves = ((n + 15) / 16 + PJ_WAVES - 1) / PJ_WAVES * PJ_WAVES;
-    return nwaves * c;
+    return (nwaves + CN_GROUPS) * c;
 }
 
 simm_status project(int64_t n, int m, const cplx* V, int64_t ldv, const cplx* Y, int64_t ldy, int64_t c, cplx* X,
@@ -130,7 +156,7 @@ simm_status project(int64_t n, int m, const cplx* V, int64_t ldv, const cplx* Y,
     }
     const int64_t nw = (n + 15) / 16;
     const int64_t nblk = (nw + PJ_WAVES - 1) / PJ_WAVES;
-    if (col_norms != nullptr && scratch_elems < nblk * PJ_WAVES * c) {
+    if (col_norms != nullptr && scratch_elems < (nblk * PJ_WAVES + CN_GROUPS) * c) {
         set_error("projection scratch too small");
         return SIMM_EINVAL;
     }
@@ -138,8 +164,11 @@ simm_status project(int64_t n, int m, const cplx* V, int64_t ldv, const cplx* Y,
     hipLaunchKernelGGL(k_vmy, dim3((unsigned)nblk), dim3(PJ_THREADS), lds, st, n, m, V, ldv, Y, ldy, c, X,
                        col_norms ? scratch : nullptr);
     if (col_norms != nullptr) {
-        hipLaunchKernelGGL(k_colnorm_reduce, dim3((unsigned)((c + 127) / 128)), dim3(128), 0, st,
-                           (const double*)scratch, nblk * PJ_WAVES, c, col_norms);
+        double* part = scratch + nblk * PJ_WAVES * c;
+        hipLaunchKernelGGL(k_colnorm_partial, dim3((unsigned)((c + 63) / 64), CN_GROUPS), dim3(256), 0, st,
+                           (const double*)scratch, nblk * PJ_WAVES, c, part);
+        hipLaunchKernelGGL(k_colnorm_finish, dim3((unsigned)((c + 127) / 128)), dim3(128), 0, st,
+                           (const double*)part, c, col_norms);
     }
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;

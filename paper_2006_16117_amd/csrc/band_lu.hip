@@ -54,7 +54,7 @@ struct LuArgs {
     int kl, ku, kv, ldab;
     cplx* AB;
     int* ipiv;       // 0-based global row of the pivot of each column
-    cplx* lt[2];     // permuted panel multipliers, (NB + kl) x NB column-major, double buffered
+    cplx* LP;        // permuted multipliers of every panel: panel p at LP + p NB (NB+kl), column-major (NB+kl) x NB
     int* info;       // first singular column + 1 (INT_MAX if none)
     int64_t zidx;    // index of the zero entry stored after the band
 };
@@ -296,11 +296,10 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs a, int64_t b) {
         const bool mine = r < Rw;
 #pragma unroll
         for (int c = 0; c < NB; ++c) X[c] = a.AB[(mine && c < ncols) ? ab_idx(a, j0 + r, c0 + c) : a.zidx];
-        const cplx* lt_in = a.lt[b & 1];
-        const int ldg = NB + a.kl;
+        const cplx* lp_in = a.LP + (b >= 0 ? b : 0) * (int64_t)(NB + a.kl) * NB;
         const bool hasl = b >= 0 && r < Rb;
 #pragma unroll
-        for (int q = 0; q < NB; ++q) Lr[q] = hasl ? lt_in[r + q * ldg] : mk(0.0, 0.0);
+        for (int q = 0; q < NB; ++q) Lr[q] = hasl ? lp_in[(int64_t)q * (NB + a.kl) + r] : mk(0.0, 0.0);
         if (b >= 0 && tid < NB) piv_s[tid] = (int)(a.ipiv[j0 + tid] - j0);
     }
 
@@ -374,19 +373,18 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs a, int64_t b) {
     factor_steps<T, 0>(a, X, pos, f);
     const int pr = pos;
     const bool prow = f.prow;
-    // rows of U (final since their own step) to the band; permuted multipliers (the
-    // entries left of the diagonal) for the next launch's update
-    if (prow) {
-        if (pr < nb1) {
-#pragma unroll
-            for (int q = 0; q < NB; ++q)
-                if (q >= pr && q < nb1 && q - pr <= a.kv) a.AB[(int64_t)(a.kv + pr - q) + (j1 + q) * a.ldab] = X[q];
-        }
-        cplx* lt_out = a.lt[(b + 1) & 1];
-        const int ldg = NB + a.kl;
+    // rows of U (final since their own step) to the band
+    if (prow && pr < nb1) {
 #pragma unroll
         for (int q = 0; q < NB; ++q)
-            if (q < nb1) lt_out[pr + q * ldg] = (q < pr) ? X[q] : mk(0.0, 0.0);
+            if (q >= pr && q < nb1 && q - pr <= a.kv) a.AB[(int64_t)(a.kv + pr - q) + (j1 + q) * a.ldab] = X[q];
+    }
+    // permuted multipliers of panel b+1 (entries left of the diagonal; zeros elsewhere
+    // and in the rows past the matrix) for the next launch's update and the sweeps
+    if (pr >= 0 && pr < NB + a.kl) {
+        cplx* lp_out = a.LP + (b + 1) * (int64_t)(NB + a.kl) * NB + pr;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) lp_out[(int64_t)q * (NB + a.kl)] = (prow && q < pr && q < nb1) ? X[q] : mk(0.0, 0.0);
     }
 }
 
@@ -406,7 +404,7 @@ int lu_panel_width(int kl) {
     return (kl >= 0 && 2 * NB + kl <= 512) ? NB : 0;
 }
 
-simm_status band_lu(int64_t n, int kl, int ku, cplx* AB, int* ipiv, cplx* lt_scratch, int* info,
+simm_status band_lu(int64_t n, int kl, int ku, cplx* AB, int* ipiv, cplx* LP, int* info,
                     hipStream_t st) {
     if (lu_panel_width(kl) == 0) {
         set_error("lower bandwidth too large for the LU kernel");
@@ -420,8 +418,7 @@ simm_status band_lu(int64_t n, int kl, int ku, cplx* AB, int* ipiv, cplx* lt_scr
     a.ldab = 2 * kl + ku + 1;
     a.AB = AB;
     a.ipiv = ipiv;
-    a.lt[0] = lt_scratch;
-    a.lt[1] = lt_scratch + (size_t)(NB + kl) * NB;
+    a.LP = LP;
     a.info = info;
     a.zidx = (int64_t)a.ldab * n;
     if (2 * NB + kl <= 256)
@@ -432,7 +429,7 @@ simm_status band_lu(int64_t n, int kl, int ku, cplx* AB, int* ipiv, cplx* lt_scr
     return SIMM_OK;
 }
 
-size_t band_lu_scratch_elems(int kl) { return 2 * (size_t)(NB + kl) * NB; }
+size_t band_lu_panel_elems(int64_t n, int kl) { return (size_t)((n + NB - 1) / NB) * (size_t)(NB + kl) * NB; }
 
 simm_status assemble_shifted(int64_t n, int kl, int ku, const cplx* A, int kla, int kua, const cplx* B, int klb,
                              int kub, cplx sigma, cplx* AB, hipStream_t st) {

@@ -1,7 +1,7 @@
-// Partitioned application of the band LU factor: y = U^{-1} L^{-1} P u
+// Partitioned, blocked application of the band LU factor: y = U^{-1} L^{-1} P u
 // (the Cayley operator of Sec. 2, eq. (IMxb), is M x = U^{-1} L^{-1} P B x).
 //
-// A sweep over the n columns is a linear state machine: before column J of the
+// A sweep over the columns is a linear state machine: before column J of the
 // forward sweep the rows still receiving updates are J .. J+kl-1 (kl values, the
 // "state"), and before column J-1 of the backward sweep they are J-K .. J-1
 // (K = effective upper bandwidth of U).  The columns are cut into P chunks of s
@@ -10,21 +10,25 @@
 // where (y0_c, tau_c) is the chunk's response to its input with a zero state and
 // Psi_c, Phi_c its response to a unit state.  Per application:
 //   1. all chunks in parallel: zero-state chunk sweeps -> y0_c, tau_c;
-//   2. the chain t_{c+1} = tau_c + Phi_c t_c (short; P steps of a K x K product),
+//   2. the chain t_{c+1} = tau_c + Phi_c t_c (P steps of a K x K product),
 //      run by a few workgroups that meet at a device-scope barrier per step;
 //   3. all rows in parallel: y_c = y0_c + Psi_c t_c.
 // Psi_c and Phi_c depend only on the factor and are formed once per shift by the
-// same chunk kernel run with unit states.  This is the partitioning idea of
+// same chunk kernels run with unit states.  This is the partitioning idea of
 // Polizzi and Sameh's SPIKE algorithm, applied to the triangular factors (the
 // factorization itself is the ordinary band LU with partial pivoting).
 //
-// Chunk kernel: one workgroup per (chunk, state vector).  Thread t owns the rows
-// i = t (mod W) of the active window and keeps their values in registers; per
-// column step only the pivot row and row j cross threads, through a
-// parity-indexed LDS slot and one LDS-only barrier.  Pivot indices, diagonals,
-// chunk inputs and outputs are staged in LDS, so the only global loads inside the
-// column loop are the factor entries, issued PF columns ahead into a register
-// ring.
+// Inside a chunk the sweep advances 16 columns (one LU panel) at a time.  For the
+// forward sweep the window is the 16 + kl rows the panel touches: its 16
+// interchanges permute the window, the top 16 rows become y = L11^{-1} top and the
+// rest receive -L21 L11^{-1} top.  With the per-panel blocks Gf = [L11^{-1};
+// -L21 L11^{-1}] formed once per shift, every window row is one 16-term product
+// with the 16 top values: no sequential triangular solve in the loop.  The
+// backward sweep does the same with Hb = [-U12 U11^{-1}; U11^{-1}] on the K + 16
+// rows above and in the panel.  One thread per window row keeps its value in a
+// register; per panel the rows meet once in LDS (one barrier), and the 16 values
+// every row needs are read by 16 lanes and broadcast with lane reads.  The matrix
+// is extended by identity to n16 = 16 ceil(n / 16) rows.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -32,197 +36,317 @@ namespace simm {
 
 namespace {
 
-constexpr int PF = 16;   // factor prefetch distance (columns)
-
 __device__ inline cplx ldz(const cplx* p, int64_t i, int64_t n) { return (i >= 0 && i < n) ? p[i] : mk(0.0, 0.0); }
+
+__device__ inline cplx ldsr(const cplx* p) {
+    const double2 v = *reinterpret_cast<const double2*>(p);
+    return cplx{v.x, v.y};
+}
+__device__ inline void ldsw(cplx* p, cplx v) { *reinterpret_cast<double2*>(p) = double2{v.re, v.im}; }
+
+__device__ inline double rdl(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+__device__ inline cplx rdl(cplx v, int l) { return cplx{rdl(v.re, l), rdl(v.im, l)}; }
+
+// Window position that row i held before the interchanges (t, pv[t]), t = 0..15,
+// were applied in order.
+__device__ inline int trace_src16(int i, const int* pv) {
+    int pos = i;
+#pragma unroll
+    for (int t = 15; t >= 0; --t) {
+        const int p = pv[t];
+        pos = (pos == t) ? p : ((pos == p) ? t : pos);
+    }
+    return pos;
+}
 
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// forward (L) chunk sweep
+// per-panel blocks (once per shift)
 // ---------------------------------------------------------------------------
-template <int MAXW>
-__global__ __launch_bounds__(MAXW) void k_chunk_fwd(SpikeFwd a) {
-    if (a.active != nullptr && *a.active == 0) return;
-    extern __shared__ cplx sm[];
-    __shared__ cplx slotX[2], slotA[2];
-    const int W = blockDim.x;
-    const int t = threadIdx.x;
-    const int n = (int)a.n;
-    const int kl = a.kl;
-    const int c = blockIdx.x;
-    const int r_unit = blockIdx.y;              // mode 1: which unit state
-    const int J0 = c * (int)a.s;
-    const int J1 = min(n, J0 + (int)a.s);
-    const int len = J1 - J0;
-    const int nin = len + kl;                   // input rows J0 .. J1+kl-1
-    cplx* outb = sm;                            // len
-    cplx* inb = sm + a.s;                       // nin
-    int* piv = reinterpret_cast<int*>(sm + 2 * a.s + kl + 1);   // len + 1
-    for (int q = t; q < len; q += W) piv[q] = a.ipiv[J0 + q];
-    if (t == 0) piv[len] = -1;
-    if (a.mode == 0) {
-        for (int q = t; q < nin; q += W) inb[q] = (q < kl || J0 + q >= n) ? mk(0.0, 0.0) : a.u[J0 + q];
-    }
-    __syncthreads();
-
-    // value entering the window for a row (state rows first, then chunk input)
-    auto inval = [&](int row) -> cplx {
-        const int q = row - J0;
-        const bool in = (row < n && q < nin);
-        if (a.mode == 0) return csel(in, inb[min(q, nin - 1)], mk(0.0, 0.0));
-        return mk((in && q == r_unit) ? 1.0 : 0.0, 0.0);
-    };
-    // Factor entry for my row at step jj.  Every thread loads something every step
-    // (out-of-band taps read the zero entry stored after the band), so the loads in
-    // flight are the same on every path and the compiler's waits stay exact.
-    const int64_t colstep = a.ldab - 1;         // (row, jj) -> kv + row + jj (ldab - 1)
-    auto lidx = [&](int r, int jj) -> int64_t {
-        const int rr = (r >= jj) ? r : r + W;
-        const int d = rr - jj;
-        const bool ok = jj < J1 && d >= 1 && d <= kl && rr < n;
-        return ok ? (int64_t)(a.kv + rr) + (int64_t)jj * colstep : a.zidx;
-    };
-    int row = J0 + ((t - J0 % W) % W + W) % W;
-    cplx val = inval(row);
-    int pj = piv[0];
-    if (row == J0) slotA[J0 & 1] = val;
-    if (row == pj) slotX[J0 & 1] = val;
-    cplx ring[PF];
+// Gf[p] = [L11^{-1}; -L21 L11^{-1}] from the LU's permuted multipliers of panel p.
+__global__ __launch_bounds__(512) void k_blocks_fwd(int kl, const cplx* __restrict__ LP, cplx* __restrict__ Gf) {
+    __shared__ cplx L11[16 * 17], Li[16 * 17];
+    const int RW = kl + 16;
+    const int64_t p = blockIdx.x;
+    const int r = threadIdx.x;
+    cplx lr[16];
+    if (r < RW) {
 #pragma unroll
-    for (int q = 0; q < PF; ++q) ring[q] = a.AB[lidx(row, J0 + q)];
-    lds_barrier();
-
-    // One column step.  The ring slot is consumed before it is refilled (no
-    // loop-carried register copies); memory operations sit outside branches.
-    auto step = [&](int j, cplx& slot) {
-        const int pj1 = piv[j + 1 - J0];
-        const cplx X = slotX[j & 1];
-        const cplx A = slotA[j & 1];
-        const cplx upd = fms(csel(row == pj, A, val), slot, X);   // zero factor outside the band
-        if (row == j) {
-            outb[j - J0] = X;
-            row += W;
-            val = inval(row);
-        } else {
-            val = upd;
+        for (int q = 0; q < 16; ++q) lr[q] = LP[(p * 16 + q) * RW + r];
+        if (r < 16) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) L11[r * 17 + q] = lr[q];
         }
-        slot = a.AB[lidx(row, j + PF)];
-        if (row == j + 1) slotA[(j + 1) & 1] = val;
-        if (row == pj1) slotX[(j + 1) & 1] = val;
-        pj = pj1;
-        lds_barrier();
-    };
-    int j0 = J0;
-    for (; j0 + PF <= J1; j0 += PF) {
-#pragma unroll
-        for (int q = 0; q < PF; ++q) step(j0 + q, ring[q]);
-    }
-#pragma unroll
-    for (int q = 0; q < PF; ++q)
-        if (j0 + q < J1) step(j0 + q, ring[q]);
-
-    // end state: rows J1 .. J1+kl-1
-    const int qe = row - J1;
-    if (qe >= 0 && qe < kl) {
-        const cplx v = (row < n) ? val : mk(0.0, 0.0);
-        if (a.mode == 0) a.tau[(int64_t)c * kl + qe] = v;
-        else a.Phi[(int64_t)c * kl * kl + (int64_t)qe * kl + r_unit] = v;    // Phi_c(i, r) at [c][i][r]
     }
     __syncthreads();
-    for (int q = t; q < len; q += W) {
-        if (a.mode == 0) a.y[J0 + q] = outb[q];
-        else a.Psi[(int64_t)(J0 + q) + (int64_t)r_unit * n] = outb[q];
+    if (r < 16) {   // column r of L11^{-1} (unit lower triangular)
+        cplx x[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            cplx acc = mk(i == r ? 1.0 : 0.0, 0.0);
+#pragma unroll
+            for (int k = 0; k < i; ++k) acc = fms(acc, L11[i * 17 + k], x[k]);
+            x[i] = (i < r) ? mk(0.0, 0.0) : acc;
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) Li[i * 17 + r] = x[i];
+    }
+    __syncthreads();
+    if (r < RW) {
+        cplx g[16];
+        if (r < 16) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) g[q] = Li[r * 17 + q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                cplx acc = mk(0.0, 0.0);
+#pragma unroll
+                for (int k = 0; k < 16; ++k) acc = fms(acc, lr[k], Li[k * 17 + q]);
+                g[q] = acc;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) Gf[(p * 16 + q) * RW + r] = g[q];
+    }
+}
+
+// Hb[p] = [-U(j0-K .. j0-1, j0 .. j0+15) U11^{-1}; U11^{-1}], U11 = U(j0 .., j0 ..),
+// the identity past row n.
+__global__ __launch_bounds__(1024) void k_blocks_bwd(int64_t n, int K, int kv, int ldab, const cplx* __restrict__ AB,
+                                                     cplx* __restrict__ Hb) {
+    __shared__ cplx U11[16 * 17], Ui[16 * 17];
+    const int RW = K + 16;
+    const int64_t p = blockIdx.x;
+    const int64_t j0 = 16 * p;
+    const int r = threadIdx.x;
+    auto U = [&](int64_t i, int64_t j) -> cplx {   // U(i, j) for j >= i (zero outside the stored band)
+        if (j >= n || i >= n) return mk(i == j ? 1.0 : 0.0, 0.0);
+        if (i < 0 || j - i > kv) return mk(0.0, 0.0);
+        return AB[(int64_t)(kv + i - j) + j * ldab];
+    };
+    if (r < 256) {
+        const int i = r >> 4, q = r & 15;
+        U11[i * 17 + q] = (q >= i) ? U(j0 + i, j0 + q) : mk(0.0, 0.0);
+    }
+    __syncthreads();
+    if (r < 16) {   // column r of U11^{-1} by back substitution
+        cplx x[16];
+#pragma unroll
+        for (int i = 15; i >= 0; --i) {
+            cplx acc = mk(i == r ? 1.0 : 0.0, 0.0);
+#pragma unroll
+            for (int k = i + 1; k < 16; ++k) acc = fms(acc, U11[i * 17 + k], x[k]);
+            x[i] = (i > r) ? mk(0.0, 0.0) : cdiv(acc, U11[i * 17 + i]);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) Ui[i * 17 + r] = x[i];
+    }
+    __syncthreads();
+    if (r < RW) {
+        cplx h[16];
+        if (r >= K) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) h[q] = Ui[(r - K) * 17 + q];
+        } else {
+            const int64_t row = j0 - K + r;
+            cplx ur[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) ur[k] = U(row, j0 + k);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                cplx acc = mk(0.0, 0.0);
+#pragma unroll
+                for (int k = 0; k < 16; ++k) acc = fms(acc, ur[k], Ui[k * 17 + q]);
+                h[q] = acc;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) Hb[(p * 16 + q) * RW + r] = h[q];
     }
 }
 
 // ---------------------------------------------------------------------------
-// backward (U) chunk sweep
+// forward (L) chunk sweep, 16 columns per step
 // ---------------------------------------------------------------------------
-template <int MAXW>
-__global__ __launch_bounds__(MAXW) void k_chunk_bwd(SpikeBwd a) {
+template <int T>
+__global__ __launch_bounds__(T) void k_chunk_fwd(SpikeFwd a) {
     if (a.active != nullptr && *a.active == 0) return;
-    extern __shared__ cplx sm[];
-    __shared__ cplx slotA[2];
-    const int W = blockDim.x;
-    const int t = threadIdx.x;
-    const int n = (int)a.n;
-    const int K = a.K;
-    const int c = blockIdx.x;
-    const int r_unit = blockIdx.y;
-    const int J0 = c * (int)a.s;
-    const int J1 = min(n, J0 + (int)a.s);
-    const int len = J1 - J0;
-    const int ib0 = J0 - W;                     // input rows [J0 - W, J1 - K)
-    const int nib = len + W;
-    cplx* outb = sm;                            // len
-    cplx* dg = sm + a.s;                        // len diagonals
-    cplx* inb = sm + 2 * a.s;                   // nib
-    for (int q = t; q < len; q += W) dg[q] = a.AB[(int64_t)a.kvf + (int64_t)(J0 + q) * a.ldab];
-    if (a.mode == 0) {
-        for (int q = t; q < nib; q += W) {
-            const int row = ib0 + q;
-            inb[q] = (row >= 0 && row < J1 - K && row < n) ? a.z[row] : mk(0.0, 0.0);
-        }
+    extern __shared__ double2 sraw[];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int kl = a.kl, RW = kl + 16;
+    const int c = blockIdx.x, r_unit = blockIdx.y;
+    const int64_t J0 = (int64_t)c * a.s, J1 = min(a.n16, J0 + a.s);
+    const int len = (int)(J1 - J0);
+    const int npan = len / 16;
+    // LDS: window values by slot (2 x RW, alternating per panel), the chunk's outputs
+    // (len), its input rows J0+kl .. J1+RW-1 (len + 16) and its pivots (len)
+    cplx* S = reinterpret_cast<cplx*>(sraw);
+    cplx* outb = S + 2 * RW;
+    cplx* inb = outb + len;
+    int* pivb = reinterpret_cast<int*>(inb + len + 16);
+    for (int q = tid; q < len; q += T) pivb[q] = a.ipiv[J0 + q] - (int)(J0 + (q & ~15));
+    for (int q = tid; q < len + 16; q += T) {
+        const int64_t row = J0 + kl + q;
+        inb[q] = (a.mode == 0 && row < a.n) ? a.u[row] : mk(0.0, 0.0);
     }
     __syncthreads();
-
-    auto inval = [&](int row) -> cplx {
-        const bool state = row >= J1 - K;       // state rows: zero, or the unit vector
-        if (a.mode == 0) return csel(row >= 0 && !state, inb[max(0, min(row - ib0, nib - 1))], mk(0.0, 0.0));
-        return mk((row >= 0 && state && row - (J1 - K) == r_unit) ? 1.0 : 0.0, 0.0);
-    };
-    const int64_t colstep = a.ldab + 1;         // (row, jj) -> kvf - jj + row + jj ldab
-    auto uidx = [&](int r, int jj) -> int64_t {
-        const int rr = (r <= jj) ? r : r - W;
-        const int d = jj - rr;
-        const bool ok = jj >= J0 && d >= 1 && d <= K && rr >= 0;
-        return ok ? (int64_t)(a.kvf + rr) + (int64_t)jj * colstep - 2 * (int64_t)jj : a.zidx;
-    };
-    const int base = J1 - W;
-    int row = base + ((t - base % W) % W + W) % W;
-    cplx val = inval(row);
-    if (row == J1 - 1) slotA[(J1 - 1) & 1] = val;
-    cplx ring[PF];
+    const bool mine = tid < RW;
+    // thread tid owns LDS slot tid; the row in it has window position pos; the slot
+    // of position 0 is `off`
+    int pos = tid, off = 0;
+    cplx val = mk(0.0, 0.0);
+    if (mine) val = (a.mode == 0) ? ((pos >= kl) ? inb[pos - kl] : mk(0.0, 0.0))
+                                  : mk(pos == r_unit ? 1.0 : 0.0, 0.0);
+    const int64_t p0 = J0 / 16;
+    // The block row of my next position is loaded one panel ahead, into the other
+    // of two register sets; no global load sits in a branch, so the waits for what a
+    // step consumes never wait for what it prefetches.
+    cplx gA[16], gB[16];
+    auto prefetch = [&](cplx (&g)[16], int64_t p, int ps) {
+        const cplx* gp = a.G + p * 16 * RW + (mine ? ps : 0);
 #pragma unroll
-    for (int q = 0; q < PF; ++q) ring[q] = a.AB[uidx(row, J1 - 1 - q)];
-    lds_barrier();
-
-    auto step = [&](int j, cplx& slot) {
-        const cplx A = slotA[j & 1];
-        const cplx xj = cdiv(A, dg[j - J0]);
-        const cplx upd = fms(val, slot, xj);
-        if (row == j) {
-            outb[j - J0] = xj;
-            row -= W;
-            val = inval(row);
-        } else {
-            val = upd;
-        }
-        slot = a.AB[uidx(row, j - PF)];
-        if (row == j - 1) slotA[(j - 1) & 1] = val;
+        for (int q = 0; q < 16; ++q) g[q] = gp[q * RW];
+    };
+    prefetch(gA, p0, pos);
+    auto step = [&](int i, cplx (&gc)[16], cplx (&gn)[16]) {
+        const int64_t p = p0 + i;
+        const int buf = i & 1;
+        const int pos_n = (pos >= 16) ? pos - 16 : pos + RW - 16;
+        prefetch(gn, min(p + 1, a.n16 / 16 - 1), pos_n);   // unconditional: no branch around loads
+        if (mine) ldsw(S + buf * RW + tid, val);
         lds_barrier();
+        int pv[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) pv[t] = pivb[16 * i + t];
+        auto slot = [&](int ps) {
+            const int sl = ps + off;
+            return sl >= RW ? sl - RW : sl;
+        };
+        const cplx v2 = ldsr(S + buf * RW + slot(trace_src16(mine ? pos : 0, pv)));
+        const cplx tq = ldsr(S + buf * RW + slot(trace_src16(lane & 15, pv)));
+        cplx acc = (pos >= 16) ? v2 : mk(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc = fma_c(acc, gc[q], rdl(tq, q));
+        if (mine) {
+            if (pos < 16) {
+                ldsw(outb + 16 * i + pos, acc);
+                val = inb[16 * i + 16 + pos];          // row J0 + 16 i + RW + pos enters
+            } else {
+                val = acc;
+            }
+        }
+        pos = pos_n;
+        off = (off + 16 >= RW) ? off + 16 - RW : off + 16;
     };
-    int j0 = J1 - 1;
-    for (; j0 - PF + 1 >= J0; j0 -= PF) {
-#pragma unroll
-        for (int q = 0; q < PF; ++q) step(j0 - q, ring[q]);
+    int i = 0;
+    for (; i + 2 <= npan; i += 2) {
+        step(i, gA, gB);
+        step(i + 1, gB, gA);
     }
-#pragma unroll
-    for (int q = 0; q < PF; ++q)
-        if (j0 - q >= J0) step(j0 - q, ring[q]);
-
-    // end state: rows J0 - K .. J0 - 1
-    const int qe = row - (J0 - K);
-    if (qe >= 0 && qe < K) {
-        const cplx v = (row >= 0) ? val : mk(0.0, 0.0);
-        if (a.mode == 0) a.tau[(int64_t)c * K + qe] = v;
-        else a.Phi[(int64_t)c * K * K + (int64_t)qe * K + r_unit] = v;
+    if (i < npan) step(i, gA, gB);
+    // end state: rows J1 .. J1+kl-1 hold positions 0 .. kl-1
+    if (mine && pos < kl) {
+        if (a.mode == 0) a.tau[(int64_t)c * kl + pos] = val;
+        else a.Phi[((int64_t)c * kl + pos) * kl + r_unit] = val;    // Phi_c(i, r) at [c][i][r]
     }
     __syncthreads();
-    for (int q = t; q < len; q += W) {
-        if (a.mode == 0) a.y[J0 + q] = outb[q];
-        else a.Psi[(int64_t)(J0 + q) + (int64_t)r_unit * n] = outb[q];
+    for (int q = tid; q < len; q += T) {
+        const cplx v = ldsr(outb + q);
+        if (a.mode == 0) {
+            if (J0 + q < a.n) a.y[J0 + q] = v;
+        } else {
+            a.Psi[J0 + q + (int64_t)r_unit * a.n16] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// backward (U) chunk sweep, 16 columns per step (bottom panel first)
+// ---------------------------------------------------------------------------
+template <int T>
+__global__ __launch_bounds__(T) void k_chunk_bwd(SpikeBwd a) {
+    if (a.active != nullptr && *a.active == 0) return;
+    extern __shared__ double2 sraw[];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int K = a.K, RW = K + 16;
+    const int c = blockIdx.x, r_unit = blockIdx.y;
+    const int64_t J0 = (int64_t)c * a.s, J1 = min(a.n16, J0 + a.s);
+    const int len = (int)(J1 - J0);
+    const int npan = len / 16;
+    // LDS: window (2 x RW), outputs (len), input rows J0-K-16 .. J1-K-1 (len + 16)
+    cplx* S = reinterpret_cast<cplx*>(sraw);
+    cplx* outb = S + 2 * RW;
+    cplx* inb = outb + len;
+    const int64_t in0 = J0 - K - 16;
+    for (int q = tid; q < len + 16; q += T) {
+        const int64_t row = in0 + q;
+        inb[q] = (a.mode == 0 && row >= 0 && row < a.n) ? a.z[row] : mk(0.0, 0.0);
+    }
+    __syncthreads();
+    const bool mine = tid < RW;
+    // window of the panel at j0: rows j0-K .. j0+15 at positions 0 .. K+15; the
+    // state rows of the chunk end (J1-K .. J1-1) start at positions 16 .. K+15
+    int pos = tid, off = 0;
+    const int64_t pl = J1 / 16 - 1;             // first (lowest) panel
+    cplx val = mk(0.0, 0.0);
+    if (mine) val = (a.mode == 0) ? ((pos < 16) ? inb[(16 * pl - K + pos) - in0] : mk(0.0, 0.0))
+                                  : mk(pos - 16 == r_unit ? 1.0 : 0.0, 0.0);
+    cplx hA[16], hB[16];
+    auto prefetch = [&](cplx (&h)[16], int64_t p, int ps) {
+        const cplx* hp = a.H + p * 16 * RW + (mine ? ps : 0);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) h[q] = hp[q * RW];
+    };
+    prefetch(hA, pl, pos);
+    auto step = [&](int i, cplx (&hc)[16], cplx (&hn)[16]) {
+        const int64_t p = pl - i;
+        const int buf = i & 1;
+        const int pos_n = (pos < K) ? pos + 16 : pos - K;
+        prefetch(hn, max(p - 1, (int64_t)0), pos_n);   // unconditional: no branch around loads
+        if (mine) ldsw(S + buf * RW + tid, val);
+        lds_barrier();
+        int sl = K + (lane & 15) + off;
+        sl = sl >= RW ? sl - RW : sl;
+        const cplx bq = ldsr(S + buf * RW + sl);
+        cplx acc = (pos < K) ? val : mk(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc = fma_c(acc, hc[q], rdl(bq, q));
+        if (mine) {
+            if (pos >= K) {
+                ldsw(outb + (16 * p - J0) + pos - K, acc);
+                val = inb[(16 * p - 16 - K + pos - K) - in0];   // row j0-16-K + (pos-K) enters
+            } else {
+                val = acc;
+            }
+        }
+        pos = pos_n;
+        off = (off >= 16) ? off - 16 : off + RW - 16;
+    };
+    int i = 0;
+    for (; i + 2 <= npan; i += 2) {
+        step(i, hA, hB);
+        step(i + 1, hB, hA);
+    }
+    if (i < npan) step(i, hA, hB);
+    // end state: rows J0-K .. J0-1 hold positions 16 .. K+15
+    if (mine && pos >= 16) {
+        if (a.mode == 0) a.tau[(int64_t)c * K + pos - 16] = val;
+        else a.Phi[((int64_t)c * K + pos - 16) * K + r_unit] = val;
+    }
+    __syncthreads();
+    for (int q = tid; q < len; q += T) {
+        const cplx v = ldsr(outb + q);
+        if (a.mode == 0) {
+            if (J0 + q < a.n) a.y[J0 + q] = v;
+        } else {
+            a.Psi[J0 + q + (int64_t)r_unit * a.n16] = v;
+        }
     }
 }
 
@@ -301,9 +425,9 @@ __global__ __launch_bounds__(CH_THREADS) void k_spike_chain(SpikeChain a) {
 
 // y(j) += sum_r Psi(j, r) t_{c(j)}(r); the (at most two) state vectors a block
 // needs are staged in LDS.
-__global__ __launch_bounds__(256) void k_spike_correct(int64_t n, int K, int64_t s, const cplx* __restrict__ Psi,
-                                                       const cplx* __restrict__ t, cplx* __restrict__ y,
-                                                       const int* active) {
+__global__ __launch_bounds__(256) void k_spike_correct(int64_t n, int64_t ld, int K, int64_t s,
+                                                       const cplx* __restrict__ Psi, const cplx* __restrict__ t,
+                                                       cplx* __restrict__ y, const int* active) {
     if (active != nullptr && *active == 0) return;
     extern __shared__ cplx ts[];                     // 2 K
     const int64_t jb = (int64_t)blockIdx.x * blockDim.x;
@@ -323,16 +447,22 @@ __global__ __launch_bounds__(256) void k_spike_correct(int64_t n, int K, int64_t
     for (; r + 8 <= K; r += 8) {
         cplx v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = pr[(int64_t)(r + u) * n];
+        for (int u = 0; u < 8; ++u) v[u] = pr[(int64_t)(r + u) * ld];
 #pragma unroll
         for (int u = 0; u < 8; ++u) acc = fma_c(acc, v[u], tc[r + u]);
     }
-    for (; r < K; ++r) acc = fma_c(acc, pr[(int64_t)r * n], tc[r]);
+    for (; r < K; ++r) acc = fma_c(acc, pr[(int64_t)r * ld], tc[r]);
     y[j] = acc;
 }
 
 __global__ void k_fill_u32(unsigned* p, int count, unsigned v) {
     for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = v;
+}
+
+// ipiv[j] = j past the matrix (identity extension to n16)
+__global__ void k_pad_ipiv(int64_t n, int64_t n16, int* ipiv) {
+    const int64_t j = n + threadIdx.x;
+    if (j < n16) ipiv[j] = (int)j;
 }
 
 // max_j (ipiv[j] - j)
@@ -351,44 +481,49 @@ __global__ void k_max_jump(int64_t n, const int* ipiv, int* out) {
 
 namespace {
 
-int pow2_at_least(int v) {
-    int w = 64;
-    while (w < v) w *= 2;
-    return w;
-}
+int threads_for(int rows) { return rows <= 256 ? 256 : (rows <= 512 ? 512 : 1024); }
 
 template <typename Args>
 simm_status launch_fwd(const Args& a, int64_t P, int nrhs, int W, size_t lds, hipStream_t st) {
-    if (W <= 256) hipLaunchKernelGGL(k_chunk_fwd<256>, dim3((unsigned)P, nrhs), dim3(W), lds, st, a);
-    else if (W <= 512) hipLaunchKernelGGL(k_chunk_fwd<512>, dim3((unsigned)P, nrhs), dim3(W), lds, st, a);
-    else hipLaunchKernelGGL(k_chunk_fwd<1024>, dim3((unsigned)P, nrhs), dim3(W), lds, st, a);
+    if (W <= 256) hipLaunchKernelGGL(k_chunk_fwd<256>, dim3((unsigned)P, nrhs), dim3(256), lds, st, a);
+    else if (W <= 512) hipLaunchKernelGGL(k_chunk_fwd<512>, dim3((unsigned)P, nrhs), dim3(512), lds, st, a);
+    else hipLaunchKernelGGL(k_chunk_fwd<1024>, dim3((unsigned)P, nrhs), dim3(1024), lds, st, a);
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;
 }
 template <typename Args>
 simm_status launch_bwd(const Args& a, int64_t P, int nrhs, int W, size_t lds, hipStream_t st) {
-    if (W <= 256) hipLaunchKernelGGL(k_chunk_bwd<256>, dim3((unsigned)P, nrhs), dim3(W), lds, st, a);
-    else if (W <= 512) hipLaunchKernelGGL(k_chunk_bwd<512>, dim3((unsigned)P, nrhs), dim3(W), lds, st, a);
-    else hipLaunchKernelGGL(k_chunk_bwd<1024>, dim3((unsigned)P, nrhs), dim3(W), lds, st, a);
+    if (W <= 256) hipLaunchKernelGGL(k_chunk_bwd<256>, dim3((unsigned)P, nrhs), dim3(256), lds, st, a);
+    else if (W <= 512) hipLaunchKernelGGL(k_chunk_bwd<512>, dim3((unsigned)P, nrhs), dim3(512), lds, st, a);
+    else hipLaunchKernelGGL(k_chunk_bwd<1024>, dim3((unsigned)P, nrhs), dim3(1024), lds, st, a);
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;
 }
 
-size_t fwd_lds(int64_t s, int kl) { return sizeof(cplx) * (size_t)(2 * s + kl + 1) + sizeof(int) * (size_t)(s + 2) + 64; }
-size_t bwd_lds(int64_t s, int W) { return sizeof(cplx) * (size_t)(3 * s + W) + 64; }
+// window (2 rows) + outputs (s) + inputs (s + 16) complex, and s pivots
+size_t window_lds(int rows, int64_t s) {
+    return sizeof(cplx) * (2 * (size_t)rows + 2 * (size_t)s + 16) + sizeof(int) * (size_t)s;
+}
 
 }  // namespace
 
-int64_t spike_chunk_len(int64_t n, int kl, int K) {
+int64_t spike_chunk_len(int64_t n16, int kl, int K) {
     int64_t s = 0;
     if (const char* e = getenv("SIMM_SPIKE_CHUNK")) s = atoll(e);
-    if (s <= 0) s = std::max<int64_t>(256, (n + 47) / 48);
-    s = std::min<int64_t>(s, 2048);
-    s = std::max<int64_t>(s, std::max(kl, K) + 1);
-    return std::min<int64_t>(s, n);
+    // balance the chunk sweeps (~s/16 panel steps) against the chain (~P steps)
+    if (s <= 0) s = (int64_t)std::sqrt((double)n16 * 256.0);
+    s = std::max<int64_t>(s, std::max(kl, K) + 16);
+    s = (s + 15) / 16 * 16;
+    // a chunk's inputs, outputs and pivots are staged in LDS next to the window
+    const int64_t rows = std::max(kl, K) + 16;
+    const int64_t smax = ((150 * 1024 - 16 * (2 * rows + 16)) / (16 * 2 + 4)) / 16 * 16;
+    s = std::min<int64_t>(s, smax);
+    return std::min<int64_t>(s, n16);
 }
 
 simm_status spike_prepare(SpikeFactor& f, hipStream_t st) {
+    f.n16 = (f.n + 15) / 16 * 16;
+    if (f.n16 > f.n) hipLaunchKernelGGL(k_pad_ipiv, dim3(1), dim3(16), 0, st, f.n, f.n16, f.ipiv);
     // effective upper bandwidth of U: ku plus the largest interchange distance
     int* d_jump = nullptr;
     SIMM_HIP_TRY(hipMallocAsync((void**)&d_jump, sizeof(int), st));
@@ -398,73 +533,75 @@ simm_status spike_prepare(SpikeFactor& f, hipStream_t st) {
     SIMM_HIP_TRY(hipStreamSynchronize(st));
     SIMM_HIP_TRY(hipFreeAsync(d_jump, st));
     f.K = (int)std::min<int64_t>(std::min<int64_t>(f.kl + f.ku, f.ku + std::max(0, jump)), f.n - 1);
-    f.K = std::max(f.K, 0);
-    f.klx = (int)std::min<int64_t>(f.kl, f.n - 1);
-    f.s = spike_chunk_len(f.n, f.klx, f.K);
-    f.P = (f.n + f.s - 1) / f.s;
+    f.K = std::max(f.K, 1);
+    f.klx = std::max(1, (int)std::min<int64_t>(f.kl, f.n - 1));
     if (f.n > (int64_t)1 << 30) {
         set_error("order above 2^30 is not supported by the partitioned sweeps");
         return SIMM_EUNSUPPORTED;
     }
-    f.Wf = pow2_at_least(f.klx + 2);
-    f.Wb = pow2_at_least(f.K + 2);
-    if (f.Wf > 1024 || f.Wb > 1024) {
-        set_error("band too wide for the partitioned sweeps (bandwidth + 2 > 1024)");
+    if (f.klx + 16 > 1024 || f.K + 16 > 1024) {
+        set_error("band too wide for the partitioned sweeps (bandwidth + 16 > 1024)");
         return SIMM_EUNSUPPORTED;
     }
-    const int kl = std::max(f.klx, 1), K = std::max(f.K, 1);
-    const size_t bytes = sizeof(cplx) * ((size_t)f.n * kl + (size_t)f.P * kl * kl + (size_t)f.n * K +
-                                         (size_t)f.P * K * K + (size_t)f.P * kl * 2 + (size_t)f.P * K * 2 +
-                                         (size_t)f.n) + 1024 + 8 * 256;
-    SIMM_HIP_TRY(hipMalloc(&f.mem, bytes));
+    f.s = spike_chunk_len(f.n16, f.klx, f.K);
+    f.P = (f.n16 + f.s - 1) / f.s;
+    f.Wf = threads_for(f.klx + 16);
+    f.Wb = threads_for(f.K + 16);
+    const int kl = f.klx, K = f.K;
+    const int64_t n16 = f.n16;
+    const size_t elems = (size_t)n16 * (kl + 16) + (size_t)n16 * (K + 16) + (size_t)n16 * kl + (size_t)f.P * kl * kl +
+                         (size_t)n16 * K + (size_t)f.P * K * K + (size_t)f.P * kl * 2 + (size_t)f.P * K * 2 +
+                         (size_t)n16;
+    SIMM_HIP_TRY(hipMalloc(&f.mem, sizeof(cplx) * elems + 16 * 256));
     char* p = reinterpret_cast<char*>(f.mem);
-    auto take = [&](size_t b) {
+    auto take = [&](size_t count) {
         char* r = p;
-        p += (b + 255) & ~(size_t)255;
-        return r;
+        p += (sizeof(cplx) * count + 255) & ~(size_t)255;
+        return reinterpret_cast<cplx*>(r);
     };
-    f.PsiL = reinterpret_cast<cplx*>(take(sizeof(cplx) * (size_t)f.n * kl));
-    f.PhiL = reinterpret_cast<cplx*>(take(sizeof(cplx) * (size_t)f.P * kl * kl));
-    f.PsiU = reinterpret_cast<cplx*>(take(sizeof(cplx) * (size_t)f.n * K));
-    f.PhiU = reinterpret_cast<cplx*>(take(sizeof(cplx) * (size_t)f.P * K * K));
-    f.tauL = reinterpret_cast<cplx*>(take(sizeof(cplx) * (size_t)f.P * kl));
-    f.tL = reinterpret_cast<cplx*>(take(sizeof(cplx) * (size_t)f.P * kl));
-    f.tauU = reinterpret_cast<cplx*>(take(sizeof(cplx) * (size_t)f.P * K));
-    f.tU = reinterpret_cast<cplx*>(take(sizeof(cplx) * (size_t)f.P * K));
-    f.z = reinterpret_cast<cplx*>(take(sizeof(cplx) * (size_t)f.n));
-    f.counter = reinterpret_cast<unsigned*>(take(64));
-    f.err = reinterpret_cast<int*>(take(64));
+    f.Gf = take((size_t)n16 * (kl + 16));
+    f.Hb = take((size_t)n16 * (K + 16));
+    f.PsiL = take((size_t)n16 * kl);
+    f.PhiL = take((size_t)f.P * kl * kl);
+    f.PsiU = take((size_t)n16 * K);
+    f.PhiU = take((size_t)f.P * K * K);
+    f.tauL = take((size_t)f.P * kl);
+    f.tL = take((size_t)f.P * kl);
+    f.tauU = take((size_t)f.P * K);
+    f.tU = take((size_t)f.P * K);
+    f.z = take((size_t)n16);
+    f.counter = reinterpret_cast<unsigned*>(take(4));
+    f.err = reinterpret_cast<int*>(take(4));
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned*>(f.err), 1, 0u);
+    // per-panel blocks
+    const unsigned npan = (unsigned)(n16 / 16);
+    hipLaunchKernelGGL(k_blocks_fwd, dim3(npan), dim3(threads_for(kl + 16) <= 512 ? threads_for(kl + 16) : 512), 0, st,
+                       kl, f.LP, f.Gf);
+    hipLaunchKernelGGL(k_blocks_bwd, dim3(npan), dim3(threads_for(K + 16)), 0, st, f.n, K, f.kl + f.ku,
+                       2 * f.kl + f.ku + 1, (const cplx*)f.AB, f.Hb);
+    SIMM_HIP_TRY(hipGetLastError());
     // unit-state responses Psi, Phi
-    if (f.klx > 0) {
-        SpikeFwd a{};
-        a.n = f.n;
-        a.kl = f.klx;
-        a.kv = f.kl + f.ku;
-        a.ldab = 2 * f.kl + f.ku + 1;
-        a.AB = f.AB;
-        a.ipiv = f.ipiv;
-        a.s = f.s;
-        a.mode = 1;
-        a.zidx = (int64_t)(2 * f.kl + f.ku + 1) * f.n;
-        a.Psi = f.PsiL;
-        a.Phi = f.PhiL;
-        SIMM_TRY(launch_fwd(a, f.P, f.klx, f.Wf, fwd_lds(f.s, f.klx), st));
-    }
-    if (f.K > 0) {
-        SpikeBwd b{};
-        b.n = f.n;
-        b.K = f.K;
-        b.kvf = f.kl + f.ku;
-        b.ldab = 2 * f.kl + f.ku + 1;
-        b.AB = f.AB;
-        b.s = f.s;
-        b.mode = 1;
-        b.zidx = (int64_t)(2 * f.kl + f.ku + 1) * f.n;
-        b.Psi = f.PsiU;
-        b.Phi = f.PhiU;
-        SIMM_TRY(launch_bwd(b, f.P, f.K, f.Wb, bwd_lds(f.s, f.Wb), st));
-    }
+    SpikeFwd a{};
+    a.n = f.n;
+    a.n16 = n16;
+    a.kl = kl;
+    a.ipiv = f.ipiv;
+    a.G = f.Gf;
+    a.s = f.s;
+    a.mode = 1;
+    a.Psi = f.PsiL;
+    a.Phi = f.PhiL;
+    SIMM_TRY(launch_fwd(a, f.P, kl, f.Wf, window_lds(kl + 16, f.s), st));
+    SpikeBwd b{};
+    b.n = f.n;
+    b.n16 = n16;
+    b.K = K;
+    b.H = f.Hb;
+    b.s = f.s;
+    b.mode = 1;
+    b.Psi = f.PsiU;
+    b.Phi = f.PhiU;
+    SIMM_TRY(launch_bwd(b, f.P, K, f.Wb, window_lds(K + 16, f.s), st));
     return SIMM_OK;
 }
 
@@ -501,48 +638,38 @@ simm_status spike_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int*
     const unsigned blocks = (unsigned)((f.n + 255) / 256);
     // forward: z = L^{-1} P u
     cplx* z = f.z;
-    if (f.klx > 0) {
-        SpikeFwd a{};
-        a.n = f.n;
-        a.kl = f.klx;
-        a.kv = f.kl + f.ku;
-        a.ldab = 2 * f.kl + f.ku + 1;
-        a.AB = f.AB;
-        a.ipiv = f.ipiv;
-        a.s = f.s;
-        a.mode = 0;
-        a.zidx = (int64_t)(2 * f.kl + f.ku + 1) * f.n;
-        a.u = u;
-        a.y = z;
-        a.tau = f.tauL;
-        a.active = active;
-        SIMM_TRY(launch_fwd(a, f.P, 1, f.Wf, fwd_lds(f.s, f.klx), st));
-        SIMM_TRY(run_chain(f, true, f.klx, f.PhiL, f.tauL, f.tL, u, 0, active, st));
-        hipLaunchKernelGGL(k_spike_correct, dim3(blocks), dim3(256), sizeof(cplx) * 2 * f.klx, st, f.n, f.klx, f.s,
-                           (const cplx*)f.PsiL, (const cplx*)f.tL, z, active);
-    } else {
-        SIMM_HIP_TRY(hipMemcpyAsync(z, u, sizeof(cplx) * f.n, hipMemcpyDeviceToDevice, st));
-    }
+    SpikeFwd a{};
+    a.n = f.n;
+    a.n16 = f.n16;
+    a.kl = f.klx;
+    a.ipiv = f.ipiv;
+    a.G = f.Gf;
+    a.s = f.s;
+    a.mode = 0;
+    a.u = u;
+    a.y = z;
+    a.tau = f.tauL;
+    a.active = active;
+    SIMM_TRY(launch_fwd(a, f.P, 1, f.Wf, window_lds(f.klx + 16, f.s), st));
+    SIMM_TRY(run_chain(f, true, f.klx, f.PhiL, f.tauL, f.tL, u, 0, active, st));
+    hipLaunchKernelGGL(k_spike_correct, dim3(blocks), dim3(256), sizeof(cplx) * 2 * f.klx, st, f.n, f.n16, f.klx, f.s,
+                       (const cplx*)f.PsiL, (const cplx*)f.tL, z, active);
     // backward: y = U^{-1} z
     SpikeBwd b{};
     b.n = f.n;
+    b.n16 = f.n16;
     b.K = f.K;
-    b.kvf = f.kl + f.ku;
-    b.ldab = 2 * f.kl + f.ku + 1;
-    b.AB = f.AB;
+    b.H = f.Hb;
     b.s = f.s;
     b.mode = 0;
-    b.zidx = (int64_t)(2 * f.kl + f.ku + 1) * f.n;
     b.z = z;
     b.y = y;
     b.tau = f.tauU;
     b.active = active;
-    SIMM_TRY(launch_bwd(b, f.P, 1, f.Wb, bwd_lds(f.s, f.Wb), st));
-    if (f.K > 0) {
-        SIMM_TRY(run_chain(f, false, f.K, f.PhiU, f.tauU, f.tU, z, f.n - f.K, active, st));
-        hipLaunchKernelGGL(k_spike_correct, dim3(blocks), dim3(256), sizeof(cplx) * 2 * f.K, st, f.n, f.K, f.s,
-                           (const cplx*)f.PsiU, (const cplx*)f.tU, y, active);
-    }
+    SIMM_TRY(launch_bwd(b, f.P, 1, f.Wb, window_lds(f.K + 16, f.s), st));
+    SIMM_TRY(run_chain(f, false, f.K, f.PhiU, f.tauU, f.tU, z, f.n16 - f.K, active, st));
+    hipLaunchKernelGGL(k_spike_correct, dim3(blocks), dim3(256), sizeof(cplx) * 2 * f.K, st, f.n, f.n16, f.K, f.s,
+                       (const cplx*)f.PsiU, (const cplx*)f.tU, y, active);
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;
 }

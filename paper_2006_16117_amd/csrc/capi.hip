@@ -43,7 +43,8 @@ struct simm_shift_s {
     int kl = 0, ku = 0;
     double beta = 0.0, h_last = 0.0;
     cplx* AB = nullptr;      // LU factor (band)
-    int* ipiv = nullptr;
+    int* ipiv = nullptr;     // 16 ceil(n/16) entries (identity past n)
+    cplx* LP = nullptr;      // permuted multipliers of every LU panel
     cplx* V = nullptr;       // n x (m+1)
     cplx* H = nullptr;       // (m+1) x m, device
     cplx* T = nullptr;       // packed upper triangle
@@ -58,6 +59,7 @@ struct simm_shift_s {
         spike_release(spike);
         (void)hipFree(AB);
         (void)hipFree(ipiv);
+        (void)hipFree(LP);
         (void)hipFree(V);
         (void)hipFree(H);
         (void)hipFree(T);
@@ -283,18 +285,18 @@ simm_status build_shift(simm_pencil_s* p, cplx sigma, const cplx* f_dev, int m, 
         return SIMM_EUNSUPPORTED;
     }
     SIMM_TRY(dalloc(&s->AB, (size_t)ldab * n + 1));   // + one zero entry read for out-of-band taps
-    SIMM_TRY(dalloc(&s->ipiv, (size_t)n));
+    SIMM_TRY(dalloc(&s->ipiv, (size_t)((n + 15) / 16 * 16)));
+    SIMM_TRY(dalloc(&s->LP, band_lu_panel_elems(n, kl)));
     SIMM_TRY(dalloc(&s->V, (size_t)n * (m + 1)));
     SIMM_TRY(dalloc(&s->H, (size_t)(m + 1) * m));
     SIMM_HIP_TRY(hipMemsetAsync(s->H, 0, sizeof(cplx) * (m + 1) * m, st));
 
-    // scratch: LU panel buffers, info; Arnoldi work; flags
+    // scratch: Arnoldi work; flags
     const int nblk = (int)std::min<int64_t>(256, std::max<int64_t>(1, (n + 63) / 64));
     const int64_t rows = (n + nblk - 1) / nblk;
     const int nblk_eff = (int)((n + rows - 1) / rows);
-    const size_t lt_elems = band_lu_scratch_elems(kl);
     DevBuf work;
-    const size_t bytes = sizeof(cplx) * (lt_elems + (size_t)nblk_eff * (m + 2) + 2 * (size_t)(m + 2) + (size_t)n) +
+    const size_t bytes = sizeof(cplx) * ((size_t)nblk_eff * (m + 2) + 2 * (size_t)(m + 2) + (size_t)n) +
                          sizeof(double) * 4 + sizeof(int) * 8;
     SIMM_TRY(work.alloc(bytes + 16 * 256));
     char* wp = work.as<char>();
@@ -303,7 +305,6 @@ simm_status build_shift(simm_pencil_s* p, cplx sigma, const cplx* f_dev, int m, 
         wp += (b + 255) & ~(size_t)255;
         return r;
     };
-    cplx* lt = reinterpret_cast<cplx*>(take(sizeof(cplx) * lt_elems));
     ArnoldiWork aw;
     aw.nblk = nblk_eff;
     aw.partial = reinterpret_cast<cplx*>(take(sizeof(cplx) * (size_t)nblk_eff * (m + 2)));
@@ -323,7 +324,7 @@ simm_status build_shift(simm_pencil_s* p, cplx sigma, const cplx* f_dev, int m, 
     {
         KScope ks(clk, SIMM_K_BAND_LU);
         SIMM_TRY(assemble_shifted(n, kl, ku, p->A, p->kla, p->kua, p->B, p->klb, p->kub, sigma, s->AB, st));
-        SIMM_TRY(band_lu(n, kl, ku, s->AB, s->ipiv, lt, flags + 0, st));
+        SIMM_TRY(band_lu(n, kl, ku, s->AB, s->ipiv, s->LP, flags + 0, st));
     }
     int info = INT_MAX;
     SIMM_HIP_TRY(hipMemcpyAsync(&info, flags + 0, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -341,6 +342,7 @@ simm_status build_shift(simm_pencil_s* p, cplx sigma, const cplx* f_dev, int m, 
     s->spike.ku = ku;
     s->spike.AB = s->AB;
     s->spike.ipiv = s->ipiv;
+    s->spike.LP = s->LP;
     {
         KScope ks(clk, SIMM_K_SPIKE_PREP);
         SIMM_TRY(spike_prepare(s->spike, st));

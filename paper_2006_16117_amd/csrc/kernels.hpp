@@ -9,41 +9,48 @@ namespace simm {
 simm_status assemble_shifted(int64_t n, int kl, int ku, const cplx* A, int kla, int kua, const cplx* B, int klb,
                              int kub, cplx sigma, cplx* AB, hipStream_t st);
 int lu_panel_width(int kl);
-size_t band_lu_scratch_elems(int kl);
+// Permuted multipliers of every 16-column panel (column-major (NB + kl) x NB per panel).
+size_t band_lu_panel_elems(int64_t n, int kl);
 // info must hold INT_MAX on entry; it receives the first singular column + 1.
-simm_status band_lu(int64_t n, int kl, int ku, cplx* AB, int* ipiv, cplx* lt_scratch, int* info, hipStream_t st);
+simm_status band_lu(int64_t n, int kl, int ku, cplx* AB, int* ipiv, cplx* LP, int* info, hipStream_t st);
 
 // ---- input of the sweeps (band_sweep.hip) ----
 simm_status prepare_input(int64_t n, const cplx* x, const cplx* Bb, int klb, int kub, const double* hdiv,
                           const int* active, cplx* u, cplx* xs, hipStream_t st);
 
 // ---- partitioned band sweeps (band_spike.hip) ----
+// The sweeps run over n16 = n rounded up to 16 (the factor extended by identity),
+// in panels of 16 columns.  Per panel they use the blocks below (column-major, so
+// that one load instruction reads one column for 64 consecutive rows), formed once
+// per shift (spike_prepare):
+//   forward  Gf[p] (16 + kl) x 16: rows 0..15 = L11^{-1}, rows 16.. = -L21 L11^{-1}
+//            (L = the panel's permuted multipliers),
+//   backward Hb[p] (K + 16) x 16: rows 0..K-1 = -U(j0-K .. j0-1, panel) U11^{-1},
+//            rows K.. = U11^{-1}.
 struct SpikeFwd {
-    int64_t n;
-    int kl, kv, ldab;
-    const cplx* AB;
-    const int* ipiv;
-    int64_t s;
+    int64_t n, n16;
+    int kl;
+    const int* ipiv;   // n16 entries (identity past n)
+    const cplx* G;     // forward panel blocks
+    int64_t s;         // chunk length (multiple of 16)
     int mode;          // 0: zero state, input u; 1: unit state blockIdx.y, zero input
-    int64_t zidx;      // index of a zero entry stored right after the band factor
     const cplx* u;
     cplx* y;
     cplx* tau;
-    cplx* Psi;
+    cplx* Psi;         // n16 x kl
     cplx* Phi;
     const int* active;
 };
 struct SpikeBwd {
-    int64_t n;
-    int K, kvf, ldab;
-    const cplx* AB;
+    int64_t n, n16;
+    int K;
+    const cplx* H;     // backward panel blocks
     int64_t s;
     int mode;
-    int64_t zidx;
     const cplx* z;
     cplx* y;
     cplx* tau;
-    cplx* Psi;
+    cplx* Psi;         // n16 x K
     cplx* Phi;
     const int* active;
 };
@@ -62,14 +69,16 @@ struct SpikeChain {
     const int* active;
 };
 struct SpikeFactor {
-    int64_t n = 0;
+    int64_t n = 0, n16 = 0;
     int kl = 0, ku = 0;       // bandwidths of A - sigma B
     cplx* AB = nullptr;       // band LU factor, followed by one zero entry
-    int* ipiv = nullptr;
+    int* ipiv = nullptr;      // n16 entries
+    const cplx* LP = nullptr; // permuted panel multipliers of the LU
     int K = 0, klx = 0;       // effective upper bandwidth of U, lower bandwidth used
     int64_t s = 0, P = 0;     // chunk length and count
     int Wf = 0, Wb = 0;       // threads of the forward / backward chunk kernels
     void* mem = nullptr;
+    cplx *Gf = nullptr, *Hb = nullptr;
     cplx *PsiL = nullptr, *PhiL = nullptr, *PsiU = nullptr, *PhiU = nullptr;
     cplx *tauL = nullptr, *tL = nullptr, *tauU = nullptr, *tU = nullptr, *z = nullptr;
     unsigned* counter = nullptr;

@@ -37,6 +37,28 @@ FP64_PEAK_TFLOPS = 78.6   # 256 CUs x 4 SIMDs x 16 FP64 FMA lanes x 2 flops x 2.
 LU_PANEL = 16
 
 
+def measured_traffic(profile: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or None when
+    the kernel source has changed since the counters were taken (the summary names
+    the source file and its sha256)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", profile)
+    try:
+        fields = {}
+        with open(path) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith(" "):
+                    k, _, v = line.partition(":")
+                    fields[k.strip()] = v.strip()
+        src = os.path.join(ROOT, fields["source"])
+        with open(src, "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != fields["source_sha256"]:
+                return None
+        return int(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def apply_bytes(n: int, k: int, kb: int) -> int:
     """Algorithmic HBM bytes of one application of M = (A - sigma B)^{-1} B: the
     factor (3k+1 band rows), B (2 k_B + 1 rows), and about six n-vectors in and out,
@@ -94,7 +116,21 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes (three times): the reference "
+                         "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE to HBM bytes")
     args = ap.parse_args()
+    if args.copy_calibration > 0:
+        import torch
+        n = args.copy_calibration // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "launches": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the shift-parallel multi-GPU "
               "layout is described in the design notes but not built.", file=sys.stderr)
@@ -179,7 +215,7 @@ def main():
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": lu_tflops / FP64_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic("k_band_lu_step_convdiff_n40000_traffic.md"),
             "flops_per_launch": lu_flops_per_launch(kl, ku),
             "us_per_launch": lu_us,
             "launches_per_step": lu_launches // args.steps,

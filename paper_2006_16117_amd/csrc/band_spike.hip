@@ -358,11 +358,11 @@ __global__ __launch_bounds__(T) void k_chunk_bwd(SpikeBwd a) {
 // next step's Phi row in registers, loaded while the barrier is pending.
 // ---------------------------------------------------------------------------
 constexpr int CH_THREADS = 256;
-constexpr int CH_PARTS = 16;                         // threads per state row
-constexpr int CH_ROWS = CH_THREADS / CH_PARTS;       // state rows per workgroup
 
-template <int MAXQ>
+// CH_PARTS threads per state row, CH_THREADS / CH_PARTS rows per workgroup.
+template <int MAXQ, int CH_PARTS>
 __global__ __launch_bounds__(CH_THREADS) void k_spike_chain(SpikeChain a) {
+    constexpr int CH_ROWS = CH_THREADS / CH_PARTS;
     if (a.active != nullptr && *a.active == 0) return;
     __shared__ cplx tcur[CH_PARTS * MAXQ];           // state, zero-padded
     const int K = a.K;
@@ -510,8 +510,9 @@ size_t window_lds(int rows, int64_t s) {
 int64_t spike_chunk_len(int64_t n16, int kl, int K) {
     int64_t s = 0;
     if (const char* e = getenv("SIMM_SPIKE_CHUNK")) s = atoll(e);
-    // balance the chunk sweeps (~s/16 panel steps) against the chain (~P steps)
-    if (s <= 0) s = (int64_t)std::sqrt((double)n16 * 256.0);
+    // balance the chunk sweeps (~s/16 panel steps of ~2 us) against the chain (~P steps
+    // of ~5-8 us): s ~ sqrt(100 n) (measured optimum at n = 40,000: s = 1,500 .. 2,000)
+    if (s <= 0) s = (int64_t)std::sqrt((double)n16 * 100.0);
     s = std::max<int64_t>(s, std::max(kl, K) + 16);
     s = (s + 15) / 16 * 16;
     // a chunk's inputs, outputs and pivots are staged in LDS next to the window
@@ -626,10 +627,12 @@ static simm_status run_chain(const SpikeFactor& f, bool forward, int K, const cp
     c.counter = f.counter;
     c.err = f.err;
     c.active = active;
-    const int G = (K + CH_ROWS - 1) / CH_ROWS;
-    if (K <= 16 * CH_PARTS) hipLaunchKernelGGL(k_spike_chain<16>, dim3(G), dim3(CH_THREADS), 0, st, c);
-    else if (K <= 32 * CH_PARTS) hipLaunchKernelGGL(k_spike_chain<32>, dim3(G), dim3(CH_THREADS), 0, st, c);
-    else hipLaunchKernelGGL(k_spike_chain<64>, dim3(G), dim3(CH_THREADS), 0, st, c);
+    // 16 threads per state row, 16 rows per workgroup: more, smaller workgroups make
+    // the device-scope barrier of every step dearer than the rows they save
+    const int G = (K + 15) / 16;
+    if (K <= 16 * 16) hipLaunchKernelGGL((k_spike_chain<16, 16>), dim3(G), dim3(CH_THREADS), 0, st, c);
+    else if (K <= 32 * 16) hipLaunchKernelGGL((k_spike_chain<32, 16>), dim3(G), dim3(CH_THREADS), 0, st, c);
+    else hipLaunchKernelGGL((k_spike_chain<64, 16>), dim3(G), dim3(CH_THREADS), 0, st, c);
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;
 }

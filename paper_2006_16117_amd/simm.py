@@ -142,6 +142,23 @@ class Pencil:
     def from_workload(cls, pen, stream=None):
         return cls(pen.n, pen.kl_a, pen.ku_a, pen.a_band, pen.kl_b, pen.ku_b, pen.b_band, stream)
 
+    @classmethod
+    def from_csr(cls, n, a_rowptr, a_col, a_val, b_rowptr=None, b_col=None, b_val=None, stream=None):
+        """simm_pencil_create_csr: host CSR arrays (int64 row pointers, int32 columns,
+        complex128 values); B = I when b_rowptr is None."""
+        self = cls.__new__(cls)
+        keep = [np.ascontiguousarray(a_rowptr, np.int64), np.ascontiguousarray(a_col, np.int32),
+                np.ascontiguousarray(a_val, np.complex128)]
+        if b_rowptr is not None:
+            keep += [np.ascontiguousarray(b_rowptr, np.int64), np.ascontiguousarray(b_col, np.int32),
+                     np.ascontiguousarray(b_val, np.complex128)]
+        ptrs = [x.ctypes.data_as(_vp) for x in keep] + [None] * (6 - len(keep))
+        h = _vp()
+        _check(_lib.simm_pencil_create_csr(n, *ptrs, _stream(stream), C.byref(h)))
+        self.handle = h
+        self.n = n
+        return self
+
     def __del__(self):
         if getattr(self, "handle", None):
             _lib.simm_pencil_destroy(self.handle)

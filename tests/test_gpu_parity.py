@@ -243,3 +243,71 @@ def test_run_cfg1_matches_oracle(S):
     res = _compare_run(S, "cfg1", flags=1)
     # full-space indicator of the last level is available (X = V_m Y computed)
     assert res.counters["quadrature_systems"] == 12 * 16 * sum(len(L.keys) for L in res.levels)
+
+
+# ---------------------------------------------------------------------------
+# edge cases: empty inputs, empty levels, guards, the CSR entry point
+# ---------------------------------------------------------------------------
+def test_empty_inputs(S):
+    import torch
+    pen, f, params = make_workload("cfg0")
+    say("empty inputs", "0 regions, 0 projection columns")
+    P = S.Pencil.from_workload(pen)
+    sh = S.simm_shift_build(P, 0.1 + 0.1j, f, 20)
+    out = S.simm_indicators([sh], np.zeros((0, 4), np.int64), S.params_from_dict(params), want_sums=True)
+    assert len(out["decision"]) == 0 and len(out["indicator"]) == 0
+    Y = torch.zeros((0, 20), dtype=torch.complex128, device="cuda")
+    X = torch.zeros((0, pen.n), dtype=torch.complex128, device="cuda")
+    S.simm_project(sh, Y.T, X.T)
+    torch.cuda.synchronize()
+
+
+def test_region_without_eigenvalues(S):
+    """Every level-1 square rejected: the later levels test nothing, no clusters."""
+    pen, f, params = make_workload("cfg0")
+    p = dict(params)
+    p.update(x0=3.0, x1=4.0, y0=3.0, y1=4.0, n1=4, levels=3)
+    say("simm_run", "cfg0 pencil, R = [3,4]^2 (no eigenvalues)")
+    o = O.simm(pen, f, p)
+    res = S.simm_run(S.Pencil.from_workload(pen), f, S.params_from_dict(p))
+    assert len(o.clusters) == 0 and len(res.lam) == 0
+    assert res.K == o.K and res.n_shifts == len(o.shifts)
+    for L, OL in zip(res.levels, o.levels):
+        assert [tuple(map(int, k)) for k in L.keys] == [tuple(map(int, k)) for k in OL.keys]
+        assert np.array_equal(L.decision, OL.decision)
+
+
+def test_region_guard(S):
+    pen, f, params = make_workload("cfg0")
+    p = dict(params)
+    p["max_regions_per_level"] = 10          # level 1 alone has 64 squares
+    say("simm_run", "cfg0 with a 10-square guard")
+    with pytest.raises(S.SimmError) as e:
+        S.simm_run(S.Pencil.from_workload(pen), f, S.params_from_dict(p))
+    assert e.value.status == -7
+
+
+def test_csr_entry_point_matches_band(S):
+    """A and B given as CSR give the same factor and Krylov data as the banded call."""
+    pen, f = random_band_pencil(517, 4, 91, b_kind="tridiag", b_offdiag=0.3)
+    say("csr", "n=517 k=4, tridiagonal B")
+    n = pen.n
+
+    def band_to_csr(band, kl, ku):
+        rows, cols, vals = [], [], []
+        for i in range(n):
+            for j in range(max(0, i - kl), min(n, i + ku + 1)):
+                rows.append(i)
+                cols.append(j)
+                vals.append(band[ku + i - j, j])
+        rowptr = np.zeros(n + 1, np.int64)
+        np.add.at(rowptr, np.array(rows) + 1, 1)
+        return np.cumsum(rowptr), np.array(cols, np.int32), np.array(vals, np.complex128)
+
+    a = band_to_csr(pen.a_band, pen.kl_a, pen.ku_a)
+    b = band_to_csr(pen.b_band, pen.kl_b, pen.ku_b)
+    Pc = S.Pencil.from_csr(n, *a, *b)
+    Pb = S.Pencil.from_workload(pen)
+    hc = S.simm_shift_build(Pc, 0.2 + 0.1j, f, 24).info()["H"]
+    hb = S.simm_shift_build(Pb, 0.2 + 0.1j, f, 24).info()["H"]
+    assert np.array_equal(hc, hb)

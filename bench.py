@@ -24,6 +24,8 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# hardware queues for the batched form's concurrent streams (set before HIP starts)
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
 
 METRIC = "resolvent solves/s + indicators/s at n=40k; speedup vs plain FP64 at 1e-6"
 HBM_PEAK_GBS = 8000.0
@@ -109,6 +111,61 @@ def cpu_baseline(pen, f, params, n_shifts, n_squares, n_qp, budget_s=30.0):
             "est_seconds_per_step": est}
 
 
+def bench_batch(args):
+    """Batched form: every pencil of the batch run separately (one stream), then all
+    together through simm_run_batch (up to --workers runs in flight).  value is the
+    batched resolvent-solve rate summed over the pencils."""
+    import torch
+    from workloads import load_config, make_batch
+    import paper_2006_16117_amd.simm as S
+
+    assert torch.cuda.is_available(), "needs a ROCm GPU"
+    batch = make_batch(args.workload)
+    log("batch", args.workload, len(batch), "pencils, n =", sum(p.n for p, _, _ in batch))
+    pencils = [S.Pencil.from_workload(p) for p, _, _ in batch]
+    fs = [f for _, f, _ in batch]
+    prms = [S.params_from_dict(d) for _, _, d in batch]
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        S.simm_run_batch(pencils, fs, prms, workers=args.workers)
+    t0 = time.perf_counter()
+    seq = [S.simm_run(P, f, prm) for P, f, prm in zip(pencils, fs, prms)]
+    t_seq = time.perf_counter() - t0
+    n_qp = sum(r.counters["quadrature_systems"] for r in seq)
+    n_sq = sum(r.counters["squares"] for r in seq)
+    del seq
+    log(f"sequential: {t_seq:.2f} s")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        bat = S.simm_run_batch(pencils, fs, prms, workers=args.workers)
+    t_bat = (time.perf_counter() - t0) / args.steps
+    assert sum(r.counters["quadrature_systems"] for r in bat) == n_qp
+    log(f"batched ({args.workers} in flight): {t_bat:.2f} s")
+    cfg = load_config(args.workload)
+    out = {
+        "metric": "resolvent solves/s, batched form (all pencils of the batch, runs in flight together)",
+        "value": n_qp / t_bat,
+        "unit": "resolvent solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_bat * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "sequential_value": n_qp / t_seq,
+        "sequential_ms": t_seq * 1e3,
+        "speedup_vs_sequential": t_seq / t_bat,
+        "indicators_per_s": n_sq / t_bat,
+        "config": {"workload": cfg["description"], "pencils": len(batch),
+                   "n_total": sum(p.n for p, _, _ in batch), "workers": args.workers,
+                   "resolvent_solves_per_step": n_qp, "squares_per_step": n_sq},
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +173,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workers", type=int, default=4, help="runs in flight in the batched form")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (three times): the reference "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE to HBM bytes")
@@ -139,8 +197,11 @@ def main():
     import numpy as np
     import torch
 
-    from workloads import make_workload
+    from workloads import load_config, make_workload
     import paper_2006_16117_amd.simm as S
+
+    if load_config(args.workload)["generator"]["kind"].endswith("_batch"):
+        return bench_batch(args)
 
     assert torch.cuda.is_available(), "needs a ROCm GPU"
     dev = torch.device("cuda:0")

@@ -196,6 +196,17 @@ simm_status simm_project(simm_shift s, const double* Y, int64_t c, double* X, do
 simm_status simm_run(simm_pencil p, const simm_params* params, const double* f, int32_t f_mem,
                      void* hip_stream, simm_result* out);
 
+/* Batched form: simm_run on `count` independent pencils (sizes may differ), with
+ * up to `workers` runs in flight at once, each on a non-blocking stream of its
+ * own, so that the small launches of different pencils share the GPU.  params and
+ * f hold one entry per pencil (f[i]: n_i complex values, host or device per
+ * f_mem); out receives one result per pencil (caller destroys them).  Each run
+ * is the same computation as a separate simm_run (identical results).  On any
+ * failure every result is destroyed and the first failing pencil's status is
+ * returned, with its index in simm_last_error. */
+simm_status simm_run_batch(const simm_pencil* pencils, const simm_params* params, const double* const* f,
+                           int32_t f_mem, int32_t count, int32_t workers, simm_result* out);
+
 simm_status simm_result_summary(simm_result r, int32_t* K, int32_t* n_shifts, int64_t* n_clusters,
                                 int64_t* n_unresolved);
 

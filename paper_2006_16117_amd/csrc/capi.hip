@@ -8,7 +8,9 @@
 #include <map>
 #include <memory>
 #include <set>
+#include <atomic>
 #include <string>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -200,15 +202,23 @@ simm_status dalloc(T** p, size_t count) {
     return SIMM_OK;
 }
 
+// Scratch device buffer, allocated and freed in stream order on the stream of the
+// call that uses it (a plain free would wait for the whole device and serialise
+// concurrent runs on other streams).
 struct DevBuf {
     void* p = nullptr;
-    ~DevBuf() { (void)hipFree(p); }
-    simm_status alloc(size_t bytes) {
-        (void)hipFree(p);
+    hipStream_t st = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFreeAsync(p, st);
+    }
+    simm_status alloc(size_t bytes, hipStream_t stream) {
+        if (p) (void)hipFreeAsync(p, st);
         p = nullptr;
-        hipError_t e = hipMalloc(&p, bytes ? bytes : 1);
+        st = stream;
+        hipError_t e = hipMallocAsync(&p, bytes ? bytes : 1, st);
         if (e != hipSuccess) {
-            set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+            p = nullptr;
+            set_error(std::string("hipMallocAsync: ") + hipGetErrorString(e));
             return e == hipErrorOutOfMemory ? SIMM_ENOMEM : SIMM_EHIP;
         }
         return SIMM_OK;
@@ -230,7 +240,7 @@ struct Rule {
     DevBuf buf;
     int g = 0;
     RuleDev dev{};
-    simm_status make(int g_) {
+    simm_status make(int g_, hipStream_t st) {
         g = g_;
         std::vector<double> t1, w1, t2, w2;
         gauss_legendre(g, t1, w1);
@@ -240,8 +250,9 @@ struct Rule {
         all.insert(all.end(), w1.begin(), w1.end());
         all.insert(all.end(), t2.begin(), t2.end());
         all.insert(all.end(), w2.begin(), w2.end());
-        SIMM_TRY(buf.alloc(all.size() * sizeof(double)));
-        SIMM_HIP_TRY(hipMemcpy(buf.p, all.data(), all.size() * sizeof(double), hipMemcpyHostToDevice));
+        SIMM_TRY(buf.alloc(all.size() * sizeof(double), st));
+        SIMM_HIP_TRY(hipMemcpyAsync(buf.p, all.data(), all.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        SIMM_HIP_TRY(hipStreamSynchronize(st));   // `all` is a host temporary
         double* d = buf.as<double>();
         dev.t1 = d;
         dev.w1 = d + g;
@@ -298,7 +309,7 @@ simm_status build_shift(simm_pencil_s* p, cplx sigma, const cplx* f_dev, int m, 
     DevBuf work;
     const size_t bytes = sizeof(cplx) * ((size_t)nblk_eff * (m + 2) + 2 * (size_t)(m + 2) + (size_t)n) +
                          sizeof(double) * 4 + sizeof(int) * 8;
-    SIMM_TRY(work.alloc(bytes + 16 * 256));
+    SIMM_TRY(work.alloc(bytes + 16 * 256, st));
     char* wp = work.as<char>();
     auto take = [&](size_t b) {
         char* r = wp;
@@ -443,7 +454,7 @@ simm_status evaluate(const std::vector<simm_shift_s*>& shifts, const std::vector
     }
     DevBuf b;
     const size_t bytes = sizeof(ShiftDev) * sd.size() + sizeof(int64_t) * regs.size() + sizeof(double) * 5 * N + N + 1024;
-    SIMM_TRY(b.alloc(bytes));
+    SIMM_TRY(b.alloc(bytes, st));
     char* p = b.as<char>();
     ShiftDev* sdd = reinterpret_cast<ShiftDev*>(p);
     p += (sizeof(ShiftDev) * sd.size() + 255) & ~(size_t)255;
@@ -591,7 +602,7 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
     SIMM_TRY(validate_params(prm, p->n, &nx, &ny, &K));
     R->K = K;
     Rule rule;
-    SIMM_TRY(rule.make(prm->gauss_per_edge));
+    SIMM_TRY(rule.make(prm->gauss_per_edge, st));
     const int m = prm->m;
     const bool do_proj = (prm->flags & SIMM_FLAG_PROJECT) != 0;
     const int64_t maxreg = prm->max_regions_per_level > 0 ? prm->max_regions_per_level : ((int64_t)1 << 22);
@@ -689,7 +700,7 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
         }
         cplx* sums_dev = nullptr;
         if (do_proj) {
-            SIMM_TRY(sums_buf.alloc(sizeof(cplx) * (size_t)N * 2 * m_sums));
+            SIMM_TRY(sums_buf.alloc(sizeof(cplx) * (size_t)N * 2 * m_sums, st));
             sums_dev = sums_buf.as<cplx>();
         }
         EvalOut eo;
@@ -720,7 +731,7 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
             if (tryr.empty()) break;
             cplx* fb_dev = nullptr;
             if (do_proj) {
-                SIMM_TRY(sums_fb.alloc(sizeof(cplx) * tryr.size() * 2 * m_sums));
+                SIMM_TRY(sums_fb.alloc(sizeof(cplx) * tryr.size() * 2 * m_sums, st));
                 fb_dev = sums_fb.as<cplx>();
             }
             EvalOut e2;
@@ -780,11 +791,11 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
             for (int64_t r = 0; r < N; ++r) by_shift[used[r]].push_back(r);
             int64_t cmax = 0;
             for (auto& v : by_shift) cmax = std::max<int64_t>(cmax, 2 * (int64_t)v.size());
-            SIMM_TRY(Ybuf.alloc(sizeof(cplx) * (size_t)cmax * m_sums));
-            SIMM_TRY(Xbuf.alloc(sizeof(cplx) * (size_t)cmax * n));
-            SIMM_TRY(nrm_buf.alloc(sizeof(double) * (size_t)cmax));
-            SIMM_TRY(scr_buf.alloc(sizeof(double) * (size_t)project_scratch_elems(n, cmax)));
-            SIMM_TRY(idx_buf.alloc(sizeof(int64_t) * (size_t)std::max<int64_t>(1, N)));
+            SIMM_TRY(Ybuf.alloc(sizeof(cplx) * (size_t)cmax * m_sums, st));
+            SIMM_TRY(Xbuf.alloc(sizeof(cplx) * (size_t)cmax * n, st));
+            SIMM_TRY(nrm_buf.alloc(sizeof(double) * (size_t)cmax, st));
+            SIMM_TRY(scr_buf.alloc(sizeof(double) * (size_t)project_scratch_elems(n, cmax), st));
+            SIMM_TRY(idx_buf.alloc(sizeof(int64_t) * (size_t)std::max<int64_t>(1, N), st));
             std::vector<double> nrm_host;
             for (size_t s = 0; s < shifts.size(); ++s) {
                 const auto& rs = by_shift[s];
@@ -903,7 +914,7 @@ simm_status to_device_vec(const double* src, int32_t mem, int64_t count, DevBuf&
         set_error("input vector has NaN/Inf");
         return SIMM_EINVAL;
     }
-    SIMM_TRY(buf.alloc(sizeof(cplx) * (size_t)count));
+    SIMM_TRY(buf.alloc(sizeof(cplx) * (size_t)count, st));
     SIMM_HIP_TRY(hipMemcpyAsync(buf.p, src, sizeof(cplx) * (size_t)count, hipMemcpyHostToDevice, st));
     *out = buf.as<const cplx>();
     return SIMM_OK;
@@ -1108,10 +1119,10 @@ simm_status simm_shift_apply(simm_shift s, const double* x, double* y, int32_t m
     DevBuf xb, ub, yb;
     const cplx* xd = nullptr;
     SIMM_TRY(to_device_vec(x, mem, n, xb, &xd, st));
-    SIMM_TRY(ub.alloc(sizeof(cplx) * n));
+    SIMM_TRY(ub.alloc(sizeof(cplx) * n, st));
     cplx* yd = reinterpret_cast<cplx*>(y);
     if (mem == SIMM_MEM_HOST) {
-        SIMM_TRY(yb.alloc(sizeof(cplx) * n));
+        SIMM_TRY(yb.alloc(sizeof(cplx) * n, st));
         yd = yb.as<cplx>();
     }
     SIMM_TRY(prepare_input(n, xd, s->p->B, s->p->klb, s->p->kub, nullptr, nullptr, ub.as<cplx>(), nullptr, st));
@@ -1165,7 +1176,8 @@ simm_status simm_indicators(const simm_shift* shifts, int32_t n_shifts, const in
     if (mem == SIMM_MEM_HOST) {
         std::memcpy(regs.data(), regions, sizeof(int64_t) * regs.size());
     } else {
-        SIMM_HIP_TRY(hipMemcpy(regs.data(), regions, sizeof(int64_t) * regs.size(), hipMemcpyDeviceToHost));
+        SIMM_HIP_TRY(hipMemcpyAsync(regs.data(), regions, sizeof(int64_t) * regs.size(), hipMemcpyDeviceToHost, st));
+        SIMM_HIP_TRY(hipStreamSynchronize(st));
     }
     for (int64_t r = 0; r < n_regions; ++r) {
         if (regs[4 * r] < 1 || regs[4 * r] > 60 || regs[4 * r + 3] < 0 || regs[4 * r + 3] >= n_shifts) {
@@ -1175,14 +1187,14 @@ simm_status simm_indicators(const simm_shift* shifts, int32_t n_shifts, const in
     }
     std::vector<simm_shift_s*> sv(shifts, shifts + n_shifts);
     Rule rule;
-    SIMM_TRY(rule.make(params->gauss_per_edge));
+    SIMM_TRY(rule.make(params->gauss_per_edge, st));
     DevBuf sb;
     cplx* sums_dev = nullptr;
     if (sums) {
         if (mem == SIMM_MEM_DEVICE) {
             sums_dev = reinterpret_cast<cplx*>(sums);
         } else {
-            SIMM_TRY(sb.alloc(sizeof(cplx) * (size_t)n_regions * 2 * m_max));
+            SIMM_TRY(sb.alloc(sizeof(cplx) * (size_t)n_regions * 2 * m_max, st));
             sums_dev = sb.as<cplx>();
         }
     }
@@ -1193,7 +1205,7 @@ simm_status simm_indicators(const simm_shift* shifts, int32_t n_shifts, const in
         if (mem == SIMM_MEM_HOST) {
             std::memcpy(dst, v.data(), sizeof(double) * v.size());
         } else {
-            SIMM_HIP_TRY(hipMemcpy(dst, v.data(), sizeof(double) * v.size(), hipMemcpyHostToDevice));
+            SIMM_HIP_TRY(hipMemcpyAsync(dst, v.data(), sizeof(double) * v.size(), hipMemcpyHostToDevice, st));
         }
         return SIMM_OK;
     };
@@ -1204,10 +1216,10 @@ simm_status simm_indicators(const simm_shift* shifts, int32_t n_shifts, const in
     SIMM_TRY(put(Tf, eo.Tf));
     if (decision) {
         if (mem == SIMM_MEM_HOST) std::memcpy(decision, eo.decision.data(), eo.decision.size());
-        else SIMM_HIP_TRY(hipMemcpy(decision, eo.decision.data(), eo.decision.size(), hipMemcpyHostToDevice));
+        else SIMM_HIP_TRY(hipMemcpyAsync(decision, eo.decision.data(), eo.decision.size(), hipMemcpyHostToDevice, st));
     }
     if (sums && mem == SIMM_MEM_HOST) {
-        SIMM_HIP_TRY(hipMemcpy(sums, sums_dev, sizeof(cplx) * (size_t)n_regions * 2 * m_max, hipMemcpyDeviceToHost));
+        SIMM_HIP_TRY(hipMemcpyAsync(sums, sums_dev, sizeof(cplx) * (size_t)n_regions * 2 * m_max, hipMemcpyDeviceToHost, st));
     }
     SIMM_HIP_TRY(hipStreamSynchronize(st));
     return SIMM_OK;
@@ -1223,7 +1235,7 @@ simm_status simm_project(simm_shift s, const double* Y, int64_t c, double* X, do
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     DevBuf scr;
     const int64_t se = project_scratch_elems(s->p->n, c);
-    if (col_norms) SIMM_TRY(scr.alloc(sizeof(double) * (size_t)se));
+    if (col_norms) SIMM_TRY(scr.alloc(sizeof(double) * (size_t)se, st));
     SIMM_TRY(project(s->p->n, s->m_eff, s->V, s->p->n, reinterpret_cast<const cplx*>(Y), s->m_eff, c,
                      reinterpret_cast<cplx*>(X), col_norms, col_norms ? scr.as<double>() : nullptr, se, st));
     SIMM_HIP_TRY(hipStreamSynchronize(st));
@@ -1258,6 +1270,62 @@ simm_status simm_run(simm_pencil p, const simm_params* params, const double* f, 
     if (rc != SIMM_OK) return rc;
     R->ms[3] = ms;
     *out = R.release();
+    return SIMM_OK;
+}
+
+simm_status simm_run_batch(const simm_pencil* pencils, const simm_params* params, const double* const* f,
+                           int32_t f_mem, int32_t count, int32_t workers, simm_result* out) {
+    clear_error();
+    if (!pencils || !params || !f || !out || count < 0 || workers < 1) {
+        set_error("bad batch arguments");
+        return SIMM_EINVAL;
+    }
+    for (int32_t i = 0; i < count; ++i) {
+        out[i] = nullptr;
+        if (!pencils[i] || !f[i]) {
+            set_error("null pencil or vector in the batch");
+            return SIMM_EINVAL;
+        }
+    }
+    int dev = 0;
+    SIMM_HIP_TRY(hipGetDevice(&dev));
+    std::atomic<int32_t> next{0};
+    std::vector<simm_status> rc((size_t)count, SIMM_OK);
+    std::vector<std::string> msg((size_t)count);
+    // each worker owns a non-blocking stream and takes the next pencil when free
+    auto work = [&]() {
+        (void)hipSetDevice(dev);
+        hipStream_t st = nullptr;
+        const hipError_t se = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        for (;;) {
+            const int32_t i = next.fetch_add(1);
+            if (i >= count) break;
+            if (se != hipSuccess) {
+                rc[(size_t)i] = SIMM_EHIP;
+                msg[(size_t)i] = std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(se);
+                continue;
+            }
+            simm_result r = nullptr;
+            rc[(size_t)i] = simm_run(pencils[i], &params[i], f[i], f_mem, st, &r);
+            if (rc[(size_t)i] == SIMM_OK) out[i] = r;
+            else msg[(size_t)i] = simm_last_error();
+        }
+        if (se == hipSuccess) (void)hipStreamDestroy(st);
+    };
+    std::vector<std::thread> pool;
+    const int32_t nw = std::min(workers, std::max<int32_t>(count, 1));
+    for (int32_t w = 0; w < nw; ++w) pool.emplace_back(work);
+    for (auto& t : pool) t.join();
+    for (int32_t i = 0; i < count; ++i) {
+        if (rc[(size_t)i] != SIMM_OK) {
+            for (int32_t j = 0; j < count; ++j) {
+                simm_result_destroy(out[j]);
+                out[j] = nullptr;
+            }
+            set_error("pencil " + std::to_string(i) + ": " + msg[(size_t)i]);
+            return rc[(size_t)i];
+        }
+    }
     return SIMM_OK;
 }
 

@@ -64,6 +64,8 @@ EXPORTS = {
                                   _i32, _i32, _vp]),
     "simm_project": (C.c_int, [_vp, _vp, _i64, _vp, _vp, _vp]),
     "simm_run": (C.c_int, [_vp, C.POINTER(simm_params), _vp, _i32, _vp, C.POINTER(_vp)]),
+    "simm_run_batch": (C.c_int, [C.POINTER(_vp), C.POINTER(simm_params), C.POINTER(_vp), _i32, _i32, _i32,
+                                 C.POINTER(_vp)]),
     "simm_result_summary": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "simm_result_level": (C.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64]),
     "simm_result_shift": (C.c_int, [_vp, _i32, C.POINTER(_vp)]),
@@ -321,3 +323,18 @@ def simm_run(pencil: Pencil, f, params: simm_params, stream=None) -> Result:
     h = _vp()
     _check(_lib.simm_run(pencil.handle, C.byref(params), pf, mem, _stream(stream), C.byref(h)))
     return Result(h)
+
+
+def simm_run_batch(pencils, fs, params_list, workers: int = 8):
+    """simm_run_batch: one run per pencil, up to `workers` in flight on streams of
+    their own.  fs are host complex vectors; returns one Result per pencil."""
+    count = len(pencils)
+    assert len(fs) == count and len(params_list) == count
+    keep = [np.ascontiguousarray(f, dtype=np.complex128) for f in fs]
+    ph = (_vp * count)(*[p.handle for p in pencils])
+    pp = (simm_params * count)(*params_list)
+    pf = (_vp * count)(*[k.ctypes.data_as(_vp) for k in keep])
+    out = (_vp * count)()
+    _check(_lib.simm_run_batch(ph, pp, pf, 0, count, workers, out))
+    return [Result(_vp(out[i])) for i in range(count)]
+

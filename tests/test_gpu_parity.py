@@ -311,3 +311,38 @@ def test_csr_entry_point_matches_band(S):
     hc = S.simm_shift_build(Pc, 0.2 + 0.1j, f, 24).info()["H"]
     hb = S.simm_shift_build(Pb, 0.2 + 0.1j, f, 24).info()["H"]
     assert np.array_equal(hc, hb)
+
+
+# ---------------------------------------------------------------------------
+# batched form: many pencils of different orders, runs in flight together
+# ---------------------------------------------------------------------------
+def test_batch_matches_sequential_and_oracle(S):
+    from workloads import make_batch
+    batch = make_batch("cfg2_small")
+    gold = json.load(open(os.path.join(GOLDEN, "cfg2_small_oracle.json")))["runs"]
+    say("simm_run_batch", "cfg2_small:", len(batch), "pencils, n =", [p.n for p, _, _ in batch])
+    pencils = [S.Pencil.from_workload(p) for p, _, _ in batch]
+    fs = [f for _, f, _ in batch]
+    prms = [S.params_from_dict(d) for _, _, d in batch]
+    seq = [S.simm_run(P, f, prm) for P, f, prm in zip(pencils, fs, prms)]
+    bat = S.simm_run_batch(pencils, fs, prms, workers=4)
+    ties = 0
+    for i, (a, b, g) in enumerate(zip(seq, bat, gold)):
+        # the batched run is the same computation as the separate run
+        assert a.K == b.K and a.n_shifts == b.n_shifts
+        for s in range(a.n_shifts):
+            assert np.array_equal(a.shift(s).info()["H"], b.shift(s).info()["H"])
+        for La, Lb in zip(a.levels, b.levels):
+            assert np.array_equal(La.keys, Lb.keys) and np.array_equal(La.decision, Lb.decision)
+        assert np.array_equal(a.lam, b.lam)
+        # and both follow the oracle
+        assert b.K == g["K"] and b.n_shifts == len(g["shifts"])
+        for L, GL in zip(b.levels, g["levels"]):
+            assert [tuple(map(int, k)) for k in L.keys] == list(zip(GL["ix"], GL["iy"])), (i, L.level)
+            near = {r: mg for r, mg in GL["near"]}
+            for r in np.nonzero(L.decision != np.array(GL["decision"], np.uint8))[0]:
+                assert near.get(int(r), 1.0) < 1e-8, (i, L.level, int(r))
+                ties += 1
+        lam = np.array([complex(*c["lam"]) for c in g["clusters"]])
+        assert len(b.lam) == len(lam) and np.all(np.abs(b.lam - lam) <= 1e-14 * np.abs(lam)), i
+    say("  decision ties within the margin policy:", ties)

@@ -159,3 +159,29 @@ def make_workload(name: str) -> tuple[Pencil, np.ndarray, dict]:
     else:
         raise ValueError(gen["kind"])
     return pencil, f, dict(cfg["params"])
+
+
+def make_batch(name: str) -> list[tuple[Pencil, np.ndarray, dict]]:
+    """Build the (pencil, f, params) list of a batch workload file under configs/.
+
+    Pencil p (p = 0 .. count-1): order n_p and target eigenvalue count c_p drawn
+    from PCG64(seed0 + 100000 + p) as n_p ~ U{n_min .. n_max}, c_p ~ U[c_min, c_max];
+    the pencil itself is ``random_band_pencil(n_p, k, seed0 + p)`` (B = I).  Its
+    region is the square centred at 0 with side 4 sqrt(c_p / n_p): the diagonal
+    entries are uniform on [-2, 2]^2 (density n_p / 16), so about c_p eigenvalues
+    fall inside."""
+    cfg = load_config(name)
+    gen = cfg["generator"]
+    assert gen["kind"] == "random_band_batch"
+    out = []
+    for p in range(gen["count"]):
+        rng = np.random.default_rng(gen["seed0"] + 100000 + p)
+        n = int(rng.integers(gen["n_min"], gen["n_max"] + 1))
+        c = float(rng.uniform(gen["c_min"], gen["c_max"]))
+        pencil, f = random_band_pencil(n, gen["k"], gen["seed0"] + p, b_kind="identity")
+        half = 2.0 * float(np.sqrt(c / n))
+        params = dict(cfg["params"])
+        params.update(x0=-half, x1=half, y0=-half, y1=half)
+        out.append((pencil, f, params))
+    return out
+

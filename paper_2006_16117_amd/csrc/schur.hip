@@ -40,27 +40,35 @@ __device__ inline cplx csqrt_d(cplx z) {
     return (z.im >= 0.0) ? mk(fabs(b), a) : mk(fabs(b), -a);
 }
 
-// Givens rotation G = [[c, s], [-conj(s), c]] (c real) with G [x; y] = [r; 0].
+// Givens rotation G = [[c, s], [-conj(s), c]] (c real) with G [x; y] = [r; 0]
+// (c = |x| / n, s = (x / |x|) conj(y) / n, r = (x / |x|) n, n = sqrt(|x|^2 + |y|^2);
+// entries of H_m are far from the double range limits, so the squares are safe).
 __device__ inline void givens(cplx x, cplx y, double& c, cplx& s, cplx& r) {
-    const double ax = cabs(x), ay = cabs(y);
-    if (ay == 0.0) {
+    const double ax2 = x.re * x.re + x.im * x.im, ay2 = y.re * y.re + y.im * y.im;
+    if (ay2 == 0.0) {
         c = 1.0;
         s = mk(0.0, 0.0);
         r = x;
-    } else if (ax == 0.0) {
+    } else if (ax2 == 0.0) {
+        const double ay = sqrt(ay2);
         c = 0.0;
         s = mk(y.re / ay, -y.im / ay);
         r = mk(ay, 0.0);
     } else {
-        const double nrm = hypot(ax, ay);
-        c = ax / nrm;
-        const cplx ph = mk(x.re / ax, x.im / ax);
-        s = mk((ph.re * y.re + ph.im * y.im) / nrm, (ph.im * y.re - ph.re * y.im) / nrm);   // ph conj(y) / nrm
+        const double ax = sqrt(ax2), nrm = sqrt(ax2 + ay2);
+        const double inv_ax = 1.0 / ax, inv_n = 1.0 / nrm;
+        c = ax * inv_n;
+        const cplx ph = mk(x.re * inv_ax, x.im * inv_ax);
+        s = mk((ph.re * y.re + ph.im * y.im) * inv_n, (ph.im * y.re - ph.re * y.im) * inv_n);   // ph conj(y) / n
         r = mk(ph.re * nrm, ph.im * nrm);
     }
 }
 
 constexpr int MAX_SCHUR_M = 128;
+
+// The QR kernel is one wavefront: its LDS accesses execute in program order, so
+// ordering them needs only a compiler barrier, not a workgroup barrier.
+__device__ inline void wave_sync() { asm volatile("" ::: "memory"); }
 
 }  // namespace
 
@@ -72,7 +80,7 @@ __global__ __launch_bounds__(64) void k_hess_qr(const cplx* __restrict__ Hin, in
     // load the m x m Hessenberg part (rows 0 .. j+1 of column j; bulge slot zero)
     for (int j = 0; j < m; ++j)
         for (int i = lane; i <= j + 2; i += 64) Hs[hoff(j) + i] = (i <= j + 1 && i < m) ? Hin[i + (int64_t)j * ldh] : mk(0.0, 0.0);
-    __syncthreads();
+    wave_sync();
 
     const double eps = 2.220446049250313e-16;
     int nrot = 0;
@@ -80,22 +88,40 @@ __global__ __launch_bounds__(64) void k_hess_qr(const cplx* __restrict__ Hin, in
     int its = 0;
     int fail = 0;
     while (ihi > 0) {
+        // deflation point: the largest k <= ihi with a negligible subdiagonal entry,
+        // every lane testing its own k (k = lane + 1, lane + 65)
         int l = 0;
-        for (int k = ihi; k >= 1; --k) {
-            double tst = cabs1(H(k - 1, k - 1)) + cabs1(H(k, k));
-            if (tst == 0.0) {
-                for (int i = 0; i <= ihi; ++i) tst += cabs1(H(i, i));
-                if (tst == 0.0) tst = 1.0;
+        {
+            double dsum = -1.0;   // sum of |diag| over 0..ihi, only if some test needs it
+            int kbest = 0;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int k = lane + 1 + 64 * u;
+                bool small = false;
+                double tst = 0.0;
+                if (k <= ihi) {
+                    tst = cabs1(H(k - 1, k - 1)) + cabs1(H(k, k));
+                    small = tst != 0.0 && cabs1(H(k, k - 1)) <= eps * tst;
+                }
+                if (__ballot(k <= ihi && tst == 0.0)) {
+                    if (dsum < 0.0) {
+                        double acc = 0.0;
+                        for (int i = lane; i <= ihi; i += 64) acc += cabs1(H(i, i));
+#pragma unroll
+                        for (int msk = 32; msk >= 1; msk >>= 1) acc += __shfl_xor(acc, msk, 64);
+                        dsum = (acc == 0.0) ? 1.0 : acc;
+                    }
+                    if (k <= ihi && tst == 0.0) small = cabs1(H(k, k - 1)) <= eps * dsum;
+                }
+                if (small) kbest = max(kbest, k);
             }
-            if (cabs1(H(k, k - 1)) <= eps * tst) {
-                l = k;
-                break;
-            }
+#pragma unroll
+            for (int msk = 32; msk >= 1; msk >>= 1) kbest = max(kbest, __shfl_xor(kbest, msk, 64));
+            l = kbest;
         }
-        __syncthreads();
         if (l > 0) {
             if (lane == 0) H(l, l - 1) = mk(0.0, 0.0);
-            __syncthreads();
+            wave_sync();
         }
         if (l >= ihi) {
             --ihi;
@@ -134,7 +160,7 @@ __global__ __launch_bounds__(64) void k_hess_qr(const cplx* __restrict__ Hin, in
             double c;
             cplx s, r;
             givens(x, y, c, s, r);
-            __syncthreads();
+            wave_sync();
             int jstart = k;
             if (k > l) {
                 if (lane == 0) {
@@ -144,21 +170,21 @@ __global__ __launch_bounds__(64) void k_hess_qr(const cplx* __restrict__ Hin, in
             } else {
                 jstart = l;
             }
-            // rows k, k+1: columns jstart .. m-1
+            // G from the left: rows k, k+1, columns jstart .. m-1
             for (int j = jstart + lane; j < m; j += 64) {
                 const cplx hk = H(k, j), hk1 = H(k + 1, j);
                 H(k, j) = mk(c * hk.re, c * hk.im) + s * hk1;
                 H(k + 1, j) = mk(c * hk1.re, c * hk1.im) - conj(s) * hk;
             }
-            __syncthreads();
-            // columns k, k+1: rows 0 .. min(k+2, ihi)
+            wave_sync();
+            // G^H from the right: columns k, k+1, rows 0 .. min(k+2, ihi)
             const int ilast = min(k + 2, ihi);
             for (int i = lane; i <= ilast; i += 64) {
                 const cplx hik = H(i, k), hik1 = H(i, k + 1);
                 H(i, k) = mk(c * hik.re, c * hik.im) + hik1 * conj(s);
                 H(i, k + 1) = mk(c * hik1.re, c * hik1.im) - hik * s;
             }
-            __syncthreads();
+            wave_sync();
             if (lane == 0) {
                 if (nrot < max_rot) {
                     Rot rr;
@@ -177,7 +203,7 @@ __global__ __launch_bounds__(64) void k_hess_qr(const cplx* __restrict__ Hin, in
         }
         if (fail) break;
     }
-    __syncthreads();
+    wave_sync();
     // packed upper triangle
     for (int j = 0; j < m; ++j)
         for (int i = lane; i <= j; i += 64) T_out[j * (j + 1) / 2 + i] = H(i, j);

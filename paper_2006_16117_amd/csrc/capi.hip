@@ -9,6 +9,8 @@
 #include <memory>
 #include <set>
 #include <atomic>
+#include <chrono>
+#include <functional>
 #include <string>
 #include <thread>
 #include <utility>
@@ -278,13 +280,14 @@ ShiftDev shift_dev(const simm_shift_s* s) {
     return d;
 }
 
-// Builds LU, Arnoldi basis and Schur data of one shift (hot-path steps a1-a5).
-simm_status build_shift(simm_pencil_s* p, cplx sigma, const cplx* f_dev, int m, hipStream_t st,
-                        std::unique_ptr<simm_shift_s>& out, int64_t* applies, KernelClock* clk = nullptr) {
+// Factor phase of one shift (hot-path steps a1-a2): the shifted band, its LU with
+// partial pivoting and the partitioned-sweep data of the factor.  Synchronous on
+// return (the factor may be used next on another stream).
+simm_status factor_shift(simm_pencil_s* p, cplx sigma, hipStream_t st, std::unique_ptr<simm_shift_s>& out,
+                         KernelClock* clk = nullptr) {
     auto s = std::make_unique<simm_shift_s>();
     s->p = p;
     s->sigma = sigma;
-    s->m = m;
     const int64_t n = p->n;
     const int kl = std::max(p->kla, p->klb);
     const int ku = std::max(p->kua, p->kub);
@@ -298,6 +301,50 @@ simm_status build_shift(simm_pencil_s* p, cplx sigma, const cplx* f_dev, int m, 
     SIMM_TRY(dalloc(&s->AB, (size_t)ldab * n + 1));   // + one zero entry read for out-of-band taps
     SIMM_TRY(dalloc(&s->ipiv, (size_t)((n + 15) / 16 * 16)));
     SIMM_TRY(dalloc(&s->LP, band_lu_panel_elems(n, kl)));
+    DevBuf info_buf;
+    SIMM_TRY(info_buf.alloc(sizeof(int), st));
+    int* info_d = info_buf.as<int>();
+    int info = INT_MAX;
+    SIMM_HIP_TRY(hipMemcpyAsync(info_d, &info, sizeof(int), hipMemcpyHostToDevice, st));
+    SIMM_HIP_TRY(hipMemsetAsync(s->AB + (size_t)ldab * n, 0, sizeof(cplx), st));
+    {
+        KScope ks(clk, SIMM_K_BAND_LU);
+        SIMM_TRY(assemble_shifted(n, kl, ku, p->A, p->kla, p->kua, p->B, p->klb, p->kub, sigma, s->AB, st));
+        SIMM_TRY(band_lu(n, kl, ku, s->AB, s->ipiv, s->LP, info_d, st));
+    }
+    SIMM_HIP_TRY(hipMemcpyAsync(&info, info_d, sizeof(int), hipMemcpyDeviceToHost, st));
+    SIMM_HIP_TRY(hipStreamSynchronize(st));
+    if (info != INT_MAX) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg, "exact zero pivot in column %d of A - sigma B (sigma = %.17g%+.17gi)", info,
+                      sigma.re, sigma.im);
+        set_error(msg);
+        return SIMM_ESINGULAR_SHIFT;
+    }
+    // partitioned-sweep data (unit-state responses of every chunk)
+    s->spike.n = n;
+    s->spike.kl = kl;
+    s->spike.ku = ku;
+    s->spike.AB = s->AB;
+    s->spike.ipiv = s->ipiv;
+    s->spike.LP = s->LP;
+    {
+        KScope ks(clk, SIMM_K_SPIKE_PREP);
+        SIMM_TRY(spike_prepare(s->spike, st));
+    }
+    SIMM_HIP_TRY(hipStreamSynchronize(st));
+    out = std::move(s);
+    return SIMM_OK;
+}
+
+// Krylov phase of one shift (hot-path steps a3-a5) on a factored shift: b, beta,
+// the Arnoldi basis V_{m+1} and H_{m+1,m}, and the Schur data of H_m.
+simm_status krylov_shift(simm_shift_s* s, const cplx* f_dev, int m, hipStream_t st, int64_t* applies,
+                         KernelClock* clk = nullptr) {
+    simm_pencil_s* p = s->p;
+    const cplx sigma = s->sigma;
+    s->m = m;
+    const int64_t n = p->n;
     SIMM_TRY(dalloc(&s->V, (size_t)n * (m + 1)));
     SIMM_TRY(dalloc(&s->H, (size_t)(m + 1) * m));
     SIMM_HIP_TRY(hipMemsetAsync(s->H, 0, sizeof(cplx) * (m + 1) * m, st));
@@ -323,40 +370,11 @@ simm_status build_shift(simm_pencil_s* p, cplx sigma, const cplx* f_dev, int m, 
     aw.h2 = reinterpret_cast<cplx*>(take(sizeof(cplx) * (m + 2)));
     aw.hnorm = reinterpret_cast<double*>(take(sizeof(double) * 4));
     aw.u = reinterpret_cast<cplx*>(take(sizeof(cplx) * (size_t)n));
-    int* flags = reinterpret_cast<int*>(take(sizeof(int) * 8));   // [0] info, [1] active, [2] m_eff, [3] schur status
+    int* flags = reinterpret_cast<int*>(take(sizeof(int) * 8));   // [1] active, [2] m_eff, [3] schur status
     double* beta_d = aw.hnorm + 2;
     {
         int init[4] = {INT_MAX, 1, m, 0};
         SIMM_HIP_TRY(hipMemcpyAsync(flags, init, sizeof(init), hipMemcpyHostToDevice, st));
-    }
-
-    SIMM_HIP_TRY(hipMemsetAsync(s->AB + (size_t)ldab * n, 0, sizeof(cplx), st));
-    // a1 + a2: shifted band and its LU
-    {
-        KScope ks(clk, SIMM_K_BAND_LU);
-        SIMM_TRY(assemble_shifted(n, kl, ku, p->A, p->kla, p->kua, p->B, p->klb, p->kub, sigma, s->AB, st));
-        SIMM_TRY(band_lu(n, kl, ku, s->AB, s->ipiv, s->LP, flags + 0, st));
-    }
-    int info = INT_MAX;
-    SIMM_HIP_TRY(hipMemcpyAsync(&info, flags + 0, sizeof(int), hipMemcpyDeviceToHost, st));
-    SIMM_HIP_TRY(hipStreamSynchronize(st));
-    if (info != INT_MAX) {
-        char msg[160];
-        std::snprintf(msg, sizeof msg, "exact zero pivot in column %d of A - sigma B (sigma = %.17g%+.17gi)", info,
-                      sigma.re, sigma.im);
-        set_error(msg);
-        return SIMM_ESINGULAR_SHIFT;
-    }
-    // partitioned-sweep data (unit-state responses of every chunk)
-    s->spike.n = n;
-    s->spike.kl = kl;
-    s->spike.ku = ku;
-    s->spike.AB = s->AB;
-    s->spike.ipiv = s->ipiv;
-    s->spike.LP = s->LP;
-    {
-        KScope ks(clk, SIMM_K_SPIKE_PREP);
-        SIMM_TRY(spike_prepare(s->spike, st));
     }
     // a3: b = (A - sigma B)^{-1} f, beta, v_1
     {
@@ -425,6 +443,15 @@ simm_status build_shift(simm_pencil_s* p, cplx sigma, const cplx* f_dev, int m, 
             s->ritz[k] = cplx{sigma.re + inv.re, sigma.im + inv.im};
         }
     }
+    return SIMM_OK;
+}
+
+// Both phases of one shift (hot-path steps a1-a5).
+simm_status build_shift(simm_pencil_s* p, cplx sigma, const cplx* f_dev, int m, hipStream_t st,
+                        std::unique_ptr<simm_shift_s>& out, int64_t* applies, KernelClock* clk = nullptr) {
+    std::unique_ptr<simm_shift_s> s;
+    SIMM_TRY(factor_shift(p, sigma, st, s, clk));
+    SIMM_TRY(krylov_shift(s.get(), f_dev, m, st, applies, clk));
     out = std::move(s);
     return SIMM_OK;
 }
@@ -543,6 +570,10 @@ simm_status validate_params(const simm_params* prm, int64_t n, int* nx, int* ny,
         set_error("too many levels");
         return SIMM_EINVAL;
     }
+    if (prm->lookahead < 0 || prm->lookahead > 16) {
+        set_error("lookahead must be in 0 .. 16");
+        return SIMM_EINVAL;
+    }
     return SIMM_OK;
 }
 
@@ -588,6 +619,59 @@ struct Timer {
     }
 };
 
+// The factor phase of a shift built ahead of the association order (steps 2-3), by
+// a host thread of its own on a stream of its own.  Joined (and its stream released)
+// on destruction, so no thread outlives the run that started it.
+struct AheadBuild {
+    std::thread th;
+    std::unique_ptr<simm_shift_s> s;
+    simm_status rc = SIMM_OK;
+    std::string err;
+    KernelClock clock;
+    hipStream_t st = nullptr;
+    void start(simm_pencil_s* p, cplx sigma, bool timed) {
+        th = std::thread([this, p, sigma, timed]() {
+            (void)hipSetDevice(p->dev);
+            const hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+            if (e != hipSuccess) {
+                st = nullptr;
+                rc = SIMM_EHIP;
+                err = std::string("stream for a shift built ahead: ") + hipGetErrorString(e);
+                return;
+            }
+            clock.st = st;
+            rc = factor_shift(p, sigma, st, s, timed ? &clock : nullptr);
+            if (rc != SIMM_OK) err = g_err;
+        });
+    }
+    // waits for the build; its kernel times go to (ms, cnt) if those are given
+    void finish(double* ms = nullptr, int64_t* cnt = nullptr) {
+        if (th.joinable()) th.join();
+        if (ms && cnt) clock.collect(ms, cnt);
+        if (st) {
+            (void)hipStreamSynchronize(st);
+            (void)hipStreamDestroy(st);
+            st = nullptr;
+        }
+    }
+    ~AheadBuild() { finish(); }
+};
+
+// Number of shift factors the association may hold ahead: the requested look-ahead,
+// cut so that they take at most a quarter of the free device memory.
+int lookahead_width(const simm_params* prm, const simm_pencil_s* p) {
+    int w = prm->lookahead > 0 ? prm->lookahead : 4;
+    if (w <= 1) return 1;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return 1;
+    const int64_t n = p->n;
+    const int kl = std::max(p->kla, p->klb), ku = std::max(p->kua, p->kub);
+    const double per_shift = 16.0 * ((double)(2 * kl + ku + 1) * n + (double)band_lu_panel_elems(n, kl) +
+                                     4.0 * (double)n * (kl + 16)) * 1.25;
+    const double fit = (double)free_b / 4.0 / per_shift;
+    return (int)std::max(1.0, std::min((double)w, std::floor(fit)));
+}
+
 __global__ void k_gather_sums(const cplx* sums, int m_sums, const int64_t* regs, int64_t cnt, cplx* Y) {
     // Y(:, 2q + w) = sums(:, 2 regs[q] + w)
     const int64_t col = blockIdx.x;
@@ -617,19 +701,21 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
         }
     } collect_at_exit{clk, R};
     std::vector<simm_shift_s*> shifts;
-    auto new_shift = [&](cplx c) -> simm_status {
-        std::unique_ptr<simm_shift_s> s;
-        {
-            Timer t(st, &R->ms[0]);
-            SIMM_TRY(build_shift(p, c, f_dev, m, st, s, &R->counters[2], clk));
-        }
+    auto commit = [&](std::unique_ptr<simm_shift_s> s) {
         s->borrowed = true;
         shifts.push_back(s.get());
         R->shifts.push_back(std::move(s));
-        return SIMM_OK;
     };
     // step 1: first shift at the centre of R
-    SIMM_TRY(new_shift(cplx{(prm->x0 + prm->x1) / 2, (prm->y0 + prm->y1) / 2}));
+    {
+        std::unique_ptr<simm_shift_s> s;
+        {
+            Timer t(st, &R->ms[0]);
+            SIMM_TRY(build_shift(p, cplx{(prm->x0 + prm->x1) / 2, (prm->y0 + prm->y1) / 2}, f_dev, m, st, s,
+                                 &R->counters[2], clk));
+        }
+        commit(std::move(s));
+    }
 
     // steps 2-3: level-1 cells and shift association
     std::vector<std::pair<int64_t, int64_t>> cells;
@@ -654,6 +740,47 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
         return SIMM_OK;
     };
     SIMM_TRY(eval_cells_vs(0));
+    // A cell gets a new shift (at its centre) iff no shift made so far resolves it.
+    // One shift's banded LU is a chain of small launches that leaves most of the
+    // device idle, so the factors of the next cells that no shift resolves yet are
+    // computed ahead, concurrently on streams of their own, while the Krylov phase of
+    // the current shift runs on the run's stream.  A factor made ahead is used only
+    // when the cell order reaches its cell still unresolved, so the shifts kept and
+    // every later result are those of the one-at-a-time order.
+    const int W = lookahead_width(prm, p);
+    std::map<int64_t, std::unique_ptr<AheadBuild>> ahead;   // cell -> factor in flight or done
+    std::vector<std::unique_ptr<AheadBuild>> dropped;         // factors whose cell got resolved
+    auto release_dropped = [&]() {
+        for (auto& b : dropped) b->finish(clk ? R->kms : nullptr, clk ? R->kcnt : nullptr);
+        dropped.clear();
+    };
+    auto drop_all = [&]() {
+        for (auto& kv : ahead) dropped.push_back(std::move(kv.second));
+        ahead.clear();
+        release_dropped();
+    };
+    struct DropGuard {
+        std::function<void()> f;
+        ~DropGuard() { f(); }
+    } drop_guard{drop_all};
+    auto unresolved = [&](int64_t c) {
+        for (int s = 0; s < (int)shifts.size(); ++s)
+            if (resolv[{c, s}]) return false;
+        return true;
+    };
+    // keep W factors ahead: the first cells from `from` on that no shift resolves so far
+    auto top_up = [&](int64_t from) {
+        if (W <= 1) return;
+        int live = (int)ahead.size();
+        for (int64_t d = from; d < ncell && live < W; ++d) {
+            if (ahead.count(d) || !unresolved(d)) continue;
+            auto b = std::make_unique<AheadBuild>();
+            b->start(p, cell_center(prm, 1, cells[d].first, cells[d].second), clk != nullptr);
+            ahead[d] = std::move(b);
+            ++live;
+        }
+    };
+    top_up(0);
     std::vector<int> assoc(ncell, -1);
     for (int64_t c = 0; c < ncell; ++c) {
         const cplx ctr = cell_center(prm, 1, cells[c].first, cells[c].second);
@@ -664,12 +791,47 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
                 break;
             }
         if (chosen < 0) {
-            SIMM_TRY(new_shift(ctr));
+            std::unique_ptr<simm_shift_s> s;
+            if (W > 1) {
+                const auto t0 = std::chrono::steady_clock::now();
+                if (!ahead.count(c)) top_up(c);
+                std::unique_ptr<AheadBuild> b = std::move(ahead[c]);
+                ahead.erase(c);
+                if (b) {
+                    b->finish(clk ? R->kms : nullptr, clk ? R->kcnt : nullptr);
+                    if (b->rc == SIMM_OK) s = std::move(b->s);
+                }
+                R->ms[0] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            }
+            if (!s) {
+                // one at a time (also after a failed factor made ahead, whose error the
+                // one-at-a-time order then reports itself)
+                drop_all();
+                Timer t(st, &R->ms[0]);
+                SIMM_TRY(factor_shift(p, ctr, st, s, clk));
+            }
+            {
+                Timer t(st, &R->ms[0]);
+                SIMM_TRY(krylov_shift(s.get(), f_dev, m, st, &R->counters[2], clk));
+            }
+            commit(std::move(s));
             chosen = (int)shifts.size() - 1;
             SIMM_TRY(eval_cells_vs(chosen));
+            // factors ahead for cells the new shift resolves will not be used
+            for (auto it = ahead.begin(); it != ahead.end();) {
+                if (resolv[{it->first, chosen}]) {
+                    dropped.push_back(std::move(it->second));
+                    it = ahead.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+            if ((int)dropped.size() >= W) release_dropped();   // bounds the memory they hold
+            top_up(c + 1);
         }
         assoc[c] = chosen;
     }
+    drop_all();
 
     // steps 4-5: level loop
     struct Sq {
@@ -947,6 +1109,7 @@ simm_status simm_params_default(simm_params* p) {
     p->tau = 1e-8;
     p->max_regions_per_level = (int64_t)1 << 22;
     p->flags = 0;
+    p->lookahead = 0;
     return SIMM_OK;
 }
 

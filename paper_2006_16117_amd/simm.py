@@ -38,7 +38,8 @@ class simm_params(C.Structure):
     _fields_ = [("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
                 ("n1", C.c_int32), ("gauss_per_edge", C.c_int32), ("m", C.c_int32), ("levels", C.c_int32),
                 ("h0", C.c_double), ("eps0", C.c_double), ("delta0", C.c_double), ("tau", C.c_double),
-                ("max_regions_per_level", C.c_int64), ("flags", C.c_uint32)]
+                ("max_regions_per_level", C.c_int64), ("flags", C.c_uint32),
+                ("lookahead", C.c_int32)]
 
 
 if not os.path.exists(LIB_PATH):

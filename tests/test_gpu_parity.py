@@ -245,6 +245,36 @@ def test_run_cfg1_matches_oracle(S):
     assert res.counters["quadrature_systems"] == 12 * 16 * sum(len(L.keys) for L in res.levels)
 
 
+def test_lookahead_equals_one_at_a_time(S):
+    """Shifts built ahead of the cell order (steps 2-3 of SIM-M) are kept only where the
+    one-at-a-time order creates them, so the whole run is the same bit for bit."""
+    for name in ("cfg0", "cfg1"):
+        pen, f, params = make_workload(name)
+        P = S.Pencil.from_workload(pen)
+        runs = {}
+        for la in (1, 3, 8):
+            say("simm_run", name, "lookahead", la)
+            runs[la] = S.simm_run(P, f, S.params_from_dict(params, lookahead=la))
+        a = runs[1]
+        for la in (3, 8):
+            b = runs[la]
+            assert a.K == b.K and a.n_shifts == b.n_shifts, (name, la)
+            for s in range(a.n_shifts):
+                ia, ib = a.shift(s).info(), b.shift(s).info()
+                assert ia["sigma"] == ib["sigma"] and np.array_equal(ia["H"], ib["H"]), (name, la, s)
+            for La, Lb in zip(a.levels, b.levels):
+                assert np.array_equal(La.keys, Lb.keys) and np.array_equal(La.shift, Lb.shift)
+                assert np.array_equal(La.decision, Lb.decision)
+                assert np.array_equal(La.indicator, Lb.indicator, equal_nan=True)
+                assert np.array_equal(La.rho_max, Lb.rho_max, equal_nan=True)
+            assert np.array_equal(a.lam, b.lam) and np.array_equal(a.counters["quadrature_systems"],
+                                                                    b.counters["quadrature_systems"])
+            say("  shift builds ms: one at a time", round(a.ms["shift_builds"], 1), f"lookahead {la}",
+                round(b.ms["shift_builds"], 1))
+    with pytest.raises(S.SimmError):
+        S.simm_run(P, f, S.params_from_dict(params, lookahead=17))
+
+
 # ---------------------------------------------------------------------------
 # edge cases: empty inputs, empty levels, guards, the CSR entry point
 # ---------------------------------------------------------------------------

@@ -196,7 +196,9 @@ simm_status simm_project(simm_shift s, const double* Y, int64_t c, double* X, do
  * level-K squares are merged into 8-connected clusters; each cluster's
  * eigenvalue is the mean of its members' centres (and, additionally, the Ritz
  * value of its shift that lies in the cluster).  ELIMIT if a level exceeds
- * max_regions_per_level. */
+ * max_regions_per_level.  The LU factors of level-1 cells that no shift resolves
+ * yet are computed ahead on internal streams (params->lookahead); only those the
+ * cell order reaches are used, so the result does not depend on it. */
 simm_status simm_run(simm_pencil p, const simm_params* params, const double* f, int32_t f_mem,
                      void* hip_stream, simm_result* out);
 
@@ -205,7 +207,9 @@ simm_status simm_run(simm_pencil p, const simm_params* params, const double* f, 
  * own, so that the small launches of different pencils share the GPU.  params and
  * f hold one entry per pencil (f[i]: n_i complex values, host or device per
  * f_mem); out receives one result per pencil (caller destroys them).  Each run
- * is the same computation as a separate simm_run (identical results).  On any
+ * is the same computation as a separate simm_run (identical results); a
+ * lookahead of 0 counts as 1 here, the runs in flight already sharing the GPU's
+ * queues.  On any
  * failure every result is destroyed and the first failing pencil's status is
  * returned, with its index in simm_last_error. */
 simm_status simm_run_batch(const simm_pencil* pencils, const simm_params* params, const double* const* f,

@@ -390,12 +390,40 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs a, int64_t b) {
 
 namespace {
 template <int T>
-void launch_lu(const LuArgs& a, hipStream_t st) {
+simm_status launch_lu(const LuArgs& a, hipStream_t st, const std::atomic<bool>* cancel) {
     const int grid = 2 + (a.kv + NB - 1) / NB;
     const int64_t nblk = (a.n + NB - 1) / NB;
     const size_t lds = LuSmem<T>::bytes;
-    for (int64_t b = -1; b < nblk; ++b)
-        hipLaunchKernelGGL(k_band_lu_step<T>, dim3(b < 0 ? 1 : grid), dim3(T), lds, st, a, b);
+    if (!cancel) {
+        for (int64_t b = -1; b < nblk; ++b)
+            hipLaunchKernelGGL(k_band_lu_step<T>, dim3(b < 0 ? 1 : grid), dim3(T), lds, st, a, b);
+        return SIMM_OK;
+    }
+    // at most RING * BATCH launches queued ahead of the device, so that a cancel
+    // takes effect within that many steps
+    constexpr int BATCH = 64, RING = 4;
+    hipEvent_t ev[RING] = {};
+    for (auto& e : ev) SIMM_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    struct Release {
+        hipEvent_t* e;
+        ~Release() {
+            for (int i = 0; i < RING; ++i) (void)hipEventDestroy(e[i]);
+        }
+    } release{ev};
+    int64_t batch = 0;
+    for (int64_t b = -1; b < nblk; b += BATCH, ++batch) {
+        if (cancel->load(std::memory_order_relaxed)) {
+            set_error("factorisation cancelled");
+            return SIMM_ECANCELED;
+        }
+        hipEvent_t& e = ev[batch % RING];
+        if (batch >= RING) SIMM_HIP_TRY(hipEventSynchronize(e));
+        const int64_t bend = std::min<int64_t>(b + BATCH, nblk);
+        for (int64_t q = b; q < bend; ++q)
+            hipLaunchKernelGGL(k_band_lu_step<T>, dim3(q < 0 ? 1 : grid), dim3(T), lds, st, a, q);
+        SIMM_HIP_TRY(hipEventRecord(e, st));
+    }
+    return SIMM_OK;
 }
 }  // namespace
 
@@ -405,7 +433,7 @@ int lu_panel_width(int kl) {
 }
 
 simm_status band_lu(int64_t n, int kl, int ku, cplx* AB, int* ipiv, cplx* LP, int* info,
-                    hipStream_t st) {
+                    hipStream_t st, const std::atomic<bool>* cancel) {
     if (lu_panel_width(kl) == 0) {
         set_error("lower bandwidth too large for the LU kernel");
         return SIMM_EUNSUPPORTED;
@@ -422,9 +450,9 @@ simm_status band_lu(int64_t n, int kl, int ku, cplx* AB, int* ipiv, cplx* LP, in
     a.info = info;
     a.zidx = (int64_t)a.ldab * n;
     if (2 * NB + kl <= 256)
-        launch_lu<256>(a, st);
+        SIMM_TRY(launch_lu<256>(a, st, cancel));
     else
-        launch_lu<512>(a, st);
+        SIMM_TRY(launch_lu<512>(a, st, cancel));
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;
 }

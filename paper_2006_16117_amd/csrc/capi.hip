@@ -4,6 +4,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -280,11 +281,11 @@ ShiftDev shift_dev(const simm_shift_s* s) {
     return d;
 }
 
-// Factor phase of one shift (hot-path steps a1-a2): the shifted band, its LU with
-// partial pivoting and the partitioned-sweep data of the factor.  Synchronous on
-// return (the factor may be used next on another stream).
+// Factor phase of one shift (hot-path steps a1-a2): the shifted band and its LU with
+// partial pivoting.  Synchronous on return (the factor may be used next on another
+// stream).
 simm_status factor_shift(simm_pencil_s* p, cplx sigma, hipStream_t st, std::unique_ptr<simm_shift_s>& out,
-                         KernelClock* clk = nullptr) {
+                         KernelClock* clk = nullptr, const std::atomic<bool>* cancel = nullptr) {
     auto s = std::make_unique<simm_shift_s>();
     s->p = p;
     s->sigma = sigma;
@@ -310,7 +311,7 @@ simm_status factor_shift(simm_pencil_s* p, cplx sigma, hipStream_t st, std::uniq
     {
         KScope ks(clk, SIMM_K_BAND_LU);
         SIMM_TRY(assemble_shifted(n, kl, ku, p->A, p->kla, p->kua, p->B, p->klb, p->kub, sigma, s->AB, st));
-        SIMM_TRY(band_lu(n, kl, ku, s->AB, s->ipiv, s->LP, info_d, st));
+        SIMM_TRY(band_lu(n, kl, ku, s->AB, s->ipiv, s->LP, info_d, st, cancel));
     }
     SIMM_HIP_TRY(hipMemcpyAsync(&info, info_d, sizeof(int), hipMemcpyDeviceToHost, st));
     SIMM_HIP_TRY(hipStreamSynchronize(st));
@@ -321,10 +322,24 @@ simm_status factor_shift(simm_pencil_s* p, cplx sigma, hipStream_t st, std::uniq
         set_error(msg);
         return SIMM_ESINGULAR_SHIFT;
     }
+    out = std::move(s);
+    return SIMM_OK;
+}
+
+// Krylov phase of one shift (hot-path steps a3-a5) on a factored shift: the
+// partitioned-sweep data of the factor (a launch wide enough to fill the device, so
+// it runs here rather than beside other work), b, beta, the Arnoldi basis V_{m+1}
+// and H_{m+1,m}, and the Schur data of H_m.
+simm_status krylov_shift(simm_shift_s* s, const cplx* f_dev, int m, hipStream_t st, int64_t* applies,
+                         KernelClock* clk = nullptr) {
+    simm_pencil_s* p = s->p;
+    const cplx sigma = s->sigma;
+    s->m = m;
+    const int64_t n = p->n;
     // partitioned-sweep data (unit-state responses of every chunk)
     s->spike.n = n;
-    s->spike.kl = kl;
-    s->spike.ku = ku;
+    s->spike.kl = s->kl;
+    s->spike.ku = s->ku;
     s->spike.AB = s->AB;
     s->spike.ipiv = s->ipiv;
     s->spike.LP = s->LP;
@@ -332,19 +347,6 @@ simm_status factor_shift(simm_pencil_s* p, cplx sigma, hipStream_t st, std::uniq
         KScope ks(clk, SIMM_K_SPIKE_PREP);
         SIMM_TRY(spike_prepare(s->spike, st));
     }
-    SIMM_HIP_TRY(hipStreamSynchronize(st));
-    out = std::move(s);
-    return SIMM_OK;
-}
-
-// Krylov phase of one shift (hot-path steps a3-a5) on a factored shift: b, beta,
-// the Arnoldi basis V_{m+1} and H_{m+1,m}, and the Schur data of H_m.
-simm_status krylov_shift(simm_shift_s* s, const cplx* f_dev, int m, hipStream_t st, int64_t* applies,
-                         KernelClock* clk = nullptr) {
-    simm_pencil_s* p = s->p;
-    const cplx sigma = s->sigma;
-    s->m = m;
-    const int64_t n = p->n;
     SIMM_TRY(dalloc(&s->V, (size_t)n * (m + 1)));
     SIMM_TRY(dalloc(&s->H, (size_t)(m + 1) * m));
     SIMM_HIP_TRY(hipMemsetAsync(s->H, 0, sizeof(cplx) * (m + 1) * m, st));
@@ -629,6 +631,7 @@ struct AheadBuild {
     std::string err;
     KernelClock clock;
     hipStream_t st = nullptr;
+    std::atomic<bool> cancel{false};
     void start(simm_pencil_s* p, cplx sigma, bool timed) {
         th = std::thread([this, p, sigma, timed]() {
             (void)hipSetDevice(p->dev);
@@ -640,7 +643,7 @@ struct AheadBuild {
                 return;
             }
             clock.st = st;
-            rc = factor_shift(p, sigma, st, s, timed ? &clock : nullptr);
+            rc = factor_shift(p, sigma, st, s, timed ? &clock : nullptr, &cancel);
             if (rc != SIMM_OK) err = g_err;
         });
     }
@@ -657,10 +660,18 @@ struct AheadBuild {
     ~AheadBuild() { finish(); }
 };
 
-// Number of shift factors the association may hold ahead: the requested look-ahead,
-// cut so that they take at most a quarter of the free device memory.
+// Number of shift factors the association may compute ahead: the requested
+// look-ahead (default: one per hardware queue the HIP runtime gives the process,
+// GPU_MAX_HW_QUEUES, 4 unless set, less the run's own; more streams than queues
+// share a queue and run one after the other), cut so that the factors take at
+// most a quarter of the free device memory.
 int lookahead_width(const simm_params* prm, const simm_pencil_s* p) {
-    int w = prm->lookahead > 0 ? prm->lookahead : 4;
+    int w = prm->lookahead;
+    if (w <= 0) {
+        int queues = 4;
+        if (const char* e = std::getenv("GPU_MAX_HW_QUEUES")) queues = std::max(1, std::atoi(e));
+        w = std::min(8, std::max(1, queues - 1));
+    }
     if (w <= 1) return 1;
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return 1;
@@ -706,18 +717,8 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
         shifts.push_back(s.get());
         R->shifts.push_back(std::move(s));
     };
-    // step 1: first shift at the centre of R
-    {
-        std::unique_ptr<simm_shift_s> s;
-        {
-            Timer t(st, &R->ms[0]);
-            SIMM_TRY(build_shift(p, cplx{(prm->x0 + prm->x1) / 2, (prm->y0 + prm->y1) / 2}, f_dev, m, st, s,
-                                 &R->counters[2], clk));
-        }
-        commit(std::move(s));
-    }
-
-    // steps 2-3: level-1 cells and shift association
+    // steps 2-3 set up before step 1, so that factors for cells can start beside it:
+    // the level-1 cells and their association state
     std::vector<std::pair<int64_t, int64_t>> cells;
     for (int iy = 0; iy < ny; ++iy)
         for (int ix = 0; ix < nx; ++ix) cells.emplace_back(ix, iy);
@@ -739,7 +740,6 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
         for (int64_t c = 0; c < ncell; ++c) resolv[{c, s}] = eo.rho[c] <= prm->eps0;
         return SIMM_OK;
     };
-    SIMM_TRY(eval_cells_vs(0));
     // A cell gets a new shift (at its centre) iff no shift made so far resolves it.
     // One shift's banded LU is a chain of small launches that leaves most of the
     // device idle, so the factors of the next cells that no shift resolves yet are
@@ -754,8 +754,12 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
         for (auto& b : dropped) b->finish(clk ? R->kms : nullptr, clk ? R->kcnt : nullptr);
         dropped.clear();
     };
+    auto drop = [&](std::unique_ptr<AheadBuild> b) {
+        b->cancel.store(true);
+        dropped.push_back(std::move(b));
+    };
     auto drop_all = [&]() {
-        for (auto& kv : ahead) dropped.push_back(std::move(kv.second));
+        for (auto& kv : ahead) drop(std::move(kv.second));
         ahead.clear();
         release_dropped();
     };
@@ -767,6 +771,18 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
         for (int s = 0; s < (int)shifts.size(); ++s)
             if (resolv[{c, s}]) return false;
         return true;
+    };
+    // factors ahead for cells shift `sh` resolves will not be used
+    auto drop_resolved_by = [&](int sh) {
+        for (auto it = ahead.begin(); it != ahead.end();) {
+            if (resolv[{it->first, sh}]) {
+                drop(std::move(it->second));
+                it = ahead.erase(it);
+            } else {
+                ++it;
+            }
+        }
+        if ((int)dropped.size() >= W) release_dropped();   // bounds the memory they hold
     };
     // keep W factors ahead: the first cells from `from` on that no shift resolves so far
     auto top_up = [&](int64_t from) {
@@ -780,6 +796,33 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
             ++live;
         }
     };
+    // factors for the first cells away from R's centre, ahead of the first shift's
+    // own build (a guess of which cells the first shift leaves unresolved: a wrong
+    // guess costs a cancelled factor, never a different result)
+    if (W > 1) {
+        const cplx c0{(prm->x0 + prm->x1) / 2, (prm->y0 + prm->y1) / 2};
+        const double w1 = (prm->x1 - prm->x0) / prm->n1;
+        for (int64_t d = 0; d < ncell && (int)ahead.size() < W; ++d) {
+            const cplx cd = cell_center(prm, 1, cells[d].first, cells[d].second);
+            if (cdist(cd, c0) <= 1.5 * w1) continue;
+            auto b = std::make_unique<AheadBuild>();
+            b->start(p, cd, clk != nullptr);
+            ahead[d] = std::move(b);
+        }
+    }
+    // step 1: first shift at the centre of R
+    {
+        std::unique_ptr<simm_shift_s> s;
+        {
+            Timer t(st, &R->ms[0]);
+            SIMM_TRY(build_shift(p, cplx{(prm->x0 + prm->x1) / 2, (prm->y0 + prm->y1) / 2}, f_dev, m, st, s,
+                                 &R->counters[2], clk));
+        }
+        commit(std::move(s));
+    }
+
+    SIMM_TRY(eval_cells_vs(0));
+    drop_resolved_by(0);
     top_up(0);
     std::vector<int> assoc(ncell, -1);
     for (int64_t c = 0; c < ncell; ++c) {
@@ -817,16 +860,7 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
             commit(std::move(s));
             chosen = (int)shifts.size() - 1;
             SIMM_TRY(eval_cells_vs(chosen));
-            // factors ahead for cells the new shift resolves will not be used
-            for (auto it = ahead.begin(); it != ahead.end();) {
-                if (resolv[{it->first, chosen}]) {
-                    dropped.push_back(std::move(it->second));
-                    it = ahead.erase(it);
-                } else {
-                    ++it;
-                }
-            }
-            if ((int)dropped.size() >= W) release_dropped();   // bounds the memory they hold
+            drop_resolved_by(chosen);
             top_up(c + 1);
         }
         assoc[c] = chosen;
@@ -1469,7 +1503,11 @@ simm_status simm_run_batch(const simm_pencil* pencils, const simm_params* params
                 continue;
             }
             simm_result r = nullptr;
-            rc[(size_t)i] = simm_run(pencils[i], &params[i], f[i], f_mem, st, &r);
+            // the runs in flight already share the device and its queues: unless asked
+            // for, each run builds its shifts one at a time
+            simm_params prm = params[i];
+            if (prm.lookahead == 0) prm.lookahead = 1;
+            rc[(size_t)i] = simm_run(pencils[i], &prm, f[i], f_mem, st, &r);
             if (rc[(size_t)i] == SIMM_OK) out[i] = r;
             else msg[(size_t)i] = simm_last_error();
         }

@@ -80,6 +80,10 @@ void clear_error();
         }                                                                                   \
     } while (0)
 
+// internal status of work given up on purpose (a factor computed ahead that is no
+// longer needed); never returned through the C ABI
+constexpr simm_status SIMM_ECANCELED = static_cast<simm_status>(7);
+
 #define SIMM_TRY(expr)                         \
     do {                                       \
         simm_status _s = (expr);               \

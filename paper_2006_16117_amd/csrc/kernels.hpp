@@ -1,6 +1,8 @@
 // Host-side launchers of the HIP kernels (internal to the library).
 #pragma once
 
+#include <atomic>
+
 #include "common.hpp"
 
 namespace simm {
@@ -12,7 +14,10 @@ int lu_panel_width(int kl);
 // Permuted multipliers of every 16-column panel (column-major (NB + kl) x NB per panel).
 size_t band_lu_panel_elems(int64_t n, int kl);
 // info must hold INT_MAX on entry; it receives the first singular column + 1.
-simm_status band_lu(int64_t n, int kl, int ku, cplx* AB, int* ipiv, cplx* LP, int* info, hipStream_t st);
+// With `cancel`, the launches are enqueued a few hundred at a time and enqueuing
+// stops (SIMM_ECANCELED, the factor left incomplete) once *cancel is set.
+simm_status band_lu(int64_t n, int kl, int ku, cplx* AB, int* ipiv, cplx* LP, int* info, hipStream_t st,
+                    const std::atomic<bool>* cancel = nullptr);
 
 // ---- input of the sweeps (band_sweep.hip) ----
 simm_status prepare_input(int64_t n, const cplx* x, const cplx* Bb, int klb, int kub, const double* hdiv,

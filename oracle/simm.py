@@ -517,6 +517,55 @@ def validate(pencil, f, params) -> None:
 
 
 # --------------------------------------------------------------------------
+# Multiplicities (Sec. 3.4).
+# --------------------------------------------------------------------------
+# Reading: the spectral projection of f_i onto a cluster's eigenvalue is the
+# fine-rule contour sum over the cluster's level-K squares, each square taken with
+# the Krylov space K_m(M, b_i) of the shift that square was tested with at level K
+# (the paper's "resolved by sigma"); interior edges of adjacent squares cancel.  A
+# singular value of [P f_1 .. P f_k] is significant when it exceeds MULT_REL_TOL
+# times the largest one.
+MULT_REL_TOL = 1e-6
+
+
+def cluster_projections(pencil, result: SimmResult, F: np.ndarray, params: dict) -> list[np.ndarray]:
+    """[P f_1 .. P f_k] (n x k) for every cluster of `result`, in cluster order."""
+    F = np.asarray(F, dtype=np.complex128)
+    n, k = F.shape
+    K = result.K
+    last = result.levels[-1]
+    wK = square_width(params, K)
+    shift_of = {(int(last.keys[r][0]), int(last.keys[r][1])): int(last.shift[r]) for r in range(len(last.keys))}
+    X = [np.zeros((n, k), dtype=np.complex128) for _ in result.clusters]
+    used = sorted({shift_of[key] for c in result.clusters for key in c.members})
+    for s in used:
+        sigma = result.shifts[s].sigma
+        solver = ShiftedSolver(pencil, sigma)
+        for i in range(k):
+            sh = build_shift(pencil, sigma, F[:, i], params["m"], keep_V=True, solver=solver)
+            for ci, c in enumerate(result.clusters):
+                y = np.zeros(sh.m_eff, dtype=np.complex128)
+                hit = False
+                for key in c.members:
+                    if shift_of[key] == s:
+                        y += evaluate_square(sh, square_center(params, K, *key), wK, params).s_f
+                        hit = True
+                if hit:
+                    X[ci][:, i] += sh.V[:, : sh.m_eff] @ y
+    return X
+
+
+def multiplicities(X_list: list[np.ndarray], rel_tol: float = MULT_REL_TOL) -> list[tuple[int, np.ndarray]]:
+    """(multiplicity, singular values in descending order) of each cluster."""
+    out = []
+    for X in X_list:
+        sv = np.linalg.svd(X, compute_uv=False)
+        mult = int(np.sum(sv > rel_tol * sv[0])) if sv[0] > 0 else 0
+        out.append((mult, sv))
+    return out
+
+
+# --------------------------------------------------------------------------
 # Direct (non-Krylov) quadrature of the spectral projection, eq. (XLXf) with
 # the systems of eq. (linearsys) solved by dense LU.  Used by the pins.
 # --------------------------------------------------------------------------

@@ -359,3 +359,76 @@ def check_p14_max_principle(O):
         assert ri <= rb * (1 + 1e-6), (c, ri, rb)
         checked += 1
     assert checked >= 5
+
+
+# ---------------------------------------------------------------------------
+# Multiplicities (Sec. 3.4) on a pencil with planted eigenvalues.
+# ---------------------------------------------------------------------------
+
+def _planted_run(O):
+    import json
+    from workloads import make_workload, load_config, start_vectors
+    pen, f, params = make_workload("mult0")
+    cfg = load_config("mult0")
+    res = O.simm(pen, f, params)
+    F = start_vectors(pen.n, cfg["multiplicity"]["k"], cfg["generator"]["seed"])
+    planted = [(complex(*v), int(c), bool(j)) for v, c, j in cfg["generator"]["planted"]]
+    return pen, params, res, F, planted
+
+
+def _square_nodes(center, width, g):
+    """Counter-clockwise boundary of a square with g Gauss-Legendre nodes per edge,
+    weights including dz/dt (written here from the rule's definition)."""
+    t, om = np.polynomial.legendre.leggauss(g)
+    h = width / 2.0
+    corners = [center + h * c for c in (-1 - 1j, 1 - 1j, 1 + 1j, -1 + 1j)]
+    z, w = [], []
+    for e in range(4):
+        a, b = corners[e], corners[(e + 1) % 4]
+        z.append(a + (t + 1.0) * (b - a) / 2.0)
+        w.append(om * (b - a) / 2.0)
+    return np.concatenate(z), np.concatenate(w)
+
+
+# P15 -- the multiplicity of each planted eigenvalue is its construction's: the
+# rank of the spectral projector (3 and 2 for semisimple repeats, 2 for a 2 x 2
+# Jordan block, 1 for a simple one), with a wide gap to the rounding level.
+def check_p15_multiplicities(O, run=None):
+    pen, params, res, F, planted = run or _planted_run(O)
+    K = res.K
+    wK = O.square_width(params, K)
+    X = O.cluster_projections(pen, res, F, params)
+    out = O.multiplicities(X)
+    found = 0
+    for c, (mult, sv) in zip(res.clusters, out):
+        centres = [O.square_center(params, K, ix, iy) for ix, iy in c.members]
+        lo = min(z.real for z in centres) - wK / 2, min(z.imag for z in centres) - wK / 2
+        hi = max(z.real for z in centres) + wK / 2, max(z.imag for z in centres) + wK / 2
+        inside = [(v, cnt) for v, cnt, _ in planted if lo[0] <= v.real <= hi[0] and lo[1] <= v.imag <= hi[1]]
+        expect = inside[0][1] if inside else 1     # a random eigenvalue near the edge of R is simple
+        found += bool(inside)
+        assert mult == expect, (c.lam, mult, expect, sv / sv[0])
+        assert sv[mult - 1] > 1e-3 * sv[0], (c.lam, sv / sv[0])
+        if mult < len(sv):
+            assert sv[mult] < 1e-10 * sv[0], (c.lam, sv / sv[0])
+    assert found == len(planted)
+
+
+# P16 -- the cluster projections equal the direct quadrature of (A - z B)^{-1} f_i
+# over the cluster's squares (dense solves, no Krylov space; eq. (XLXf) with the
+# systems of eq. (linearsys)).
+def check_p16_cluster_projection_direct(O, run=None):
+    pen, params, res, F, planted = run or _planted_run(O)
+    A, B = O.pencil_dense(pen)
+    K = res.K
+    wK = O.square_width(params, K)
+    X = O.cluster_projections(pen, res, F, params)
+    for c, Xc in zip(res.clusters, X):
+        D = np.zeros_like(Xc)
+        for ix, iy in c.members:
+            z, w = _square_nodes(O.square_center(params, K, ix, iy), wK, 2 * params["gauss_per_edge"])
+            for zj, wj in zip(z, w):
+                D += wj * np.linalg.solve(A - zj * B, F)
+        D /= 2j * np.pi
+        err = np.linalg.norm(Xc - D) / np.linalg.norm(D)
+        assert err <= 1e-8, (c.lam, err)

@@ -1,6 +1,7 @@
 """The CPU oracle against its pins (closed forms, invariants, dense QZ), and
 planted mistakes that the pins must catch."""
 import copy
+import dataclasses
 import types
 
 import numpy as np
@@ -83,6 +84,19 @@ def test_p13_eig_identity():
 
 def test_p14_max_principle():
     P.check_p14_max_principle(O)
+
+
+@pytest.fixture(scope="module")
+def planted_run():
+    return P._planted_run(O)
+
+
+def test_p15_multiplicities(planted_run):
+    P.check_p15_multiplicities(O, planted_run)
+
+
+def test_p16_cluster_projection_direct(planted_run):
+    P.check_p16_cluster_projection_direct(O, planted_run)
 
 
 def test_breakdown_and_errors():
@@ -220,6 +234,46 @@ PIN_CHECKS = [
     lambda M: P.check_p10_diagonal(M),
     lambda M: P.check_p13_eig_identity(M),
 ]
+
+
+def _coarse_rule_sums(shift, center, width, params):
+    # the projection built from the coarse rule's sums s_c instead of the fine rule's s_f
+    e = O.evaluate_square(shift, center, width, params)
+    return dataclasses.replace(e, s_f=e.s_c)
+
+
+def _first_member_only(pencil, result, F, params):
+    res2 = copy.copy(result)
+    res2.clusters = [dataclasses.replace(c, members=c.members[:1]) for c in result.clusters]
+    return O.cluster_projections(pencil, res2, F, params)
+
+
+def _threshold_from_smallest(X_list, rel_tol=O.MULT_REL_TOL):
+    # threshold taken relative to the smallest singular value instead of the largest
+    out = []
+    for X in X_list:
+        sv = np.linalg.svd(X, compute_uv=False)
+        out.append((int(np.sum(sv > rel_tol * sv[-1])), sv))
+    return out
+
+
+MULT_MUTANTS = {
+    "coarse-rule projections": dict(evaluate_square=_coarse_rule_sums),
+    "first square of a cluster only": dict(cluster_projections=_first_member_only),
+    "threshold from the smallest singular value": dict(multiplicities=_threshold_from_smallest),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MULT_MUTANTS))
+def test_planted_multiplicity_mistake_is_caught(name, planted_run):
+    mod = _mutant(**MULT_MUTANTS[name])
+    failures = 0
+    for chk in (P.check_p15_multiplicities, P.check_p16_cluster_projection_direct):
+        try:
+            chk(mod, planted_run)
+        except AssertionError:
+            failures += 1
+    assert failures >= 1, f"planted mistake '{name}' passed every pin"
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))

@@ -137,6 +137,68 @@ def convection_diffusion_pencil(nx: int, seed: int, *, conv=(20.0, 10.0),
     return Pencil(n, k, k, a, 1, 1, b), f
 
 
+def planted_pencil(n: int, seed: int, planted, *, box: float = 0.3, d_half: float = 2.0,
+                   b_offdiag: float = 0.1, kb: int = 2) -> tuple[Pencil, np.ndarray]:
+    """A pencil with known eigenvalues and multiplicities: (A, B) = (J B, B).
+
+    J = diag(d) + N: ``planted`` lists (value, count, jordan) triples; each planted
+    value fills ``count`` diagonal entries, at consecutive indices, and with
+    ``jordan`` true the entries are chained by ones on the superdiagonal of N (one
+    Jordan block of that size); the other entries of d are uniform on
+    [-d_half, d_half]^2 outside the box |Re|, |Im| < box.  B has unit diagonal and
+    ``kb`` off-diagonals each side drawn as ``b_offdiag`` times a complex normal.
+    Since J B x = lambda B x  <=>  J y = lambda y with y = B x, the eigenvalues of
+    the pencil are those of J with the same Jordan structure.  A is banded with
+    kl = kb, ku = kb + 1.  Draw order: the positions of the planted groups, the
+    other d entries, B by diagonal offset -kb .. kb, then f.  Returns (pencil, f)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d = np.zeros(n, dtype=np.complex128)
+    sup = np.zeros(n - 1, dtype=np.complex128)          # superdiagonal of N
+    taken = np.zeros(n, dtype=bool)
+    slots = n // max(1, len(planted))
+    for g, (val, count, jordan) in enumerate(planted):
+        start = g * slots + int(rng.integers(0, max(1, slots - count)))
+        idx = np.arange(start, start + count)
+        assert not taken[idx].any() and idx[-1] < n
+        taken[idx] = True
+        d[idx] = complex(val)
+        if jordan:
+            sup[idx[:-1]] = 1.0
+    free = np.nonzero(~taken)[0]
+    vals = []
+    while len(vals) < len(free):
+        z = rng.uniform(-d_half, d_half) + 1j * rng.uniform(-d_half, d_half)
+        if abs(z.real) >= box or abs(z.imag) >= box:
+            vals.append(z)
+    d[free] = np.array(vals)
+    b = _empty_band(n, kb, kb)
+    _set_diag(b, kb, 0, np.ones(n))
+    for off in range(-kb, kb + 1):
+        if off != 0:
+            _set_diag(b, kb, off, b_offdiag * complex_normal(rng, n - abs(off)))
+    # A = J B: row i of A is d_i (row i of B) + sup_i (row i+1 of B)
+    kl_a, ku_a = kb, kb + 1
+    a = _empty_band(n, kl_a, ku_a)
+    for off in range(-kb, kb + 1):
+        rows = np.arange(max(0, -off), min(n, n - off))
+        cols = rows + off
+        a[ku_a + rows - cols, cols] += d[rows] * b[kb + rows - cols, cols]
+    for off in range(-kb, kb + 1):          # entries of row i+1 of B land on row i, offset off + 1
+        rows = np.arange(max(0, -off), min(n, n - off))     # rows of B
+        rows = rows[rows >= 1]
+        cols = rows + off
+        a[ku_a + (rows - 1) - cols, cols] += sup[rows - 1] * b[kb + rows - cols, cols]
+    f = complex_normal(rng, n)
+    return Pencil(n, kl_a, ku_a, a, kb, kb, b), f
+
+
+def start_vectors(n: int, k: int, seed: int) -> np.ndarray:
+    """k further seeded start vectors (n x k complex normal, column-major) for the
+    multiplicity step, drawn from PCG64(seed + 500000) so f is unchanged."""
+    rng = np.random.Generator(np.random.PCG64(seed + 500000))
+    return np.asfortranarray(complex_normal(rng, (k, n)).T)
+
+
 # --------------------------------------------------------------------------
 # Workload parameter sets (region, quadrature size, Krylov dimension, levels).
 # --------------------------------------------------------------------------
@@ -156,6 +218,9 @@ def make_workload(name: str) -> tuple[Pencil, np.ndarray, dict]:
                                        b_offdiag=gen.get("b_offdiag", 0.1))
     elif gen["kind"] == "convection_diffusion":
         pencil, f = convection_diffusion_pencil(gen["nx"], gen["seed"])
+    elif gen["kind"] == "planted":
+        planted = [(complex(*v), int(c), bool(j)) for v, c, j in gen["planted"]]
+        pencil, f = planted_pencil(gen["n"], gen["seed"], planted, box=gen.get("box", 0.3))
     else:
         raise ValueError(gen["kind"])
     return pencil, f, dict(cfg["params"])

@@ -24,8 +24,13 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
-# hardware queues for the batched form's concurrent streams (set before HIP starts)
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+# Hardware queues of the process (read by the HIP runtime when it starts; its default
+# is 4).  The driver computes one LU factor ahead per queue beyond the run's own,
+# and streams beyond the queue count share queues and serialise: 8 queues give 7
+# factors in flight (measured best on the n = 40,000 workload: 3 -> 7 ahead took
+# the step from ~1,000 to ~875 ms).
+HW_QUEUES = 8
+os.environ["GPU_MAX_HW_QUEUES"] = str(HW_QUEUES)
 
 METRIC = "resolvent solves/s + indicators/s at n=40k; speedup vs plain FP64 at 1e-6"
 HBM_PEAK_GBS = 8000.0
@@ -173,6 +178,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mult-k", type=int, default=4, help="start vectors for the multiplicity step (0: skip)")
     ap.add_argument("--workers", type=int, default=4, help="runs in flight in the batched form")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (three times): the reference "
@@ -239,7 +245,7 @@ def main():
     kl, ku = max(pen.kl_a, pen.kl_b), max(pen.ku_a, pen.ku_b)
     kb = max(pen.kl_b, pen.ku_b) if pen.b_band is not None else 0
     # dominant kernel: the band LU's panel step (one launch per 16 columns plus one)
-    lu_launches = kcnt["band_lu"] * ((n + LU_PANEL - 1) // LU_PANEL + 1)
+    lu_launches = kcnt["band_lu"]   # panel launches (factors cancelled part-way included)
     lu_us = kms["band_lu"] * 1e3 / max(lu_launches, 1)
     lu_tflops = lu_flops_per_launch(kl, ku) / (lu_us * 1e-6) / 1e12
     # K2: one application of M (B v + partitioned L and U sweeps)
@@ -268,6 +274,7 @@ def main():
             "n": pen.n, "kl": kl, "ku": ku, "m": params["m"], "gauss_per_edge": params["gauss_per_edge"],
             "levels": last.K, "shifts": last.n_shifts, "squares_per_step": n_sq,
             "resolvent_solves_per_step": n_qp, "clusters": len(last.lam),
+            "hw_queues": HW_QUEUES,
         },
         "roofline": {
             "kernel": "k_band_lu_step (one 16-column panel of the banded LU)",
@@ -295,6 +302,24 @@ def main():
         },
         "kernel_ms_per_step": step_kernel_ms,
     }
+    if args.mult_k > 0:
+        # multiplicities (Sec. 3.4) of the step's clusters from k further start vectors,
+        # outside the timed step: k Krylov spaces per shift on the kept factors
+        from workloads import start_vectors
+        F = start_vectors(pen.n, args.mult_k, load_config(args.workload)["generator"]["seed"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mult, _ = S.simm_multiplicities(last, F)
+        torch.cuda.synchronize()
+        mms = (time.perf_counter() - t0) * 1e3
+        shifts_used = len({int(s) for s in last.levels[-1].shift[last.levels[-1].decision != 0]})
+        out["multiplicity"] = {
+            "k": args.mult_k, "clusters": int(len(mult)), "ms": mms,
+            "krylov_spaces": shifts_used * args.mult_k,
+            "clusters_per_s": len(mult) / (mms / 1e3),
+            "multiplicities": np.bincount(mult).tolist(),
+        }
+        log(f"multiplicities: k = {args.mult_k}, {len(mult)} clusters in {mms:.1f} ms")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
         out["cpu_baseline"] = cpu_baseline(pen, f, params, last.n_shifts, n_sq, n_qp)

@@ -94,6 +94,8 @@ simm_status simm_pencil_create_csr(int64_t n,
                                    void* hip_stream, simm_pencil* out);
 
 simm_status simm_pencil_info(simm_pencil p, int64_t* n, int32_t* kl, int32_t* ku);
+/* Shifts and results made on a pencil refer to it (applications of M, Krylov
+ * spaces for multiplicities): destroy the pencil after them. */
 void simm_pencil_destroy(simm_pencil p);
 
 /* ------------------------------------------------------------------------ */
@@ -215,6 +217,23 @@ simm_status simm_run(simm_pencil p, const simm_params* params, const double* f, 
 simm_status simm_run_batch(const simm_pencil* pencils, const simm_params* params, const double* const* f,
                            int32_t f_mem, int32_t count, int32_t workers, simm_result* out);
 
+/* Multiplicities of the eigenvalues of a finished run (Sec. 3.4).  For every shift
+ * that one of the clusters' level-K squares was tested with, k Krylov spaces
+ * K_m(M, (A - sigma B)^{-1} f_i) are built on that shift's factor; the spectral
+ * projection P f_i of a cluster is the sum over its squares of V_m s_f (the fine
+ * rule's contour sum of eq. (XLXf) in the Krylov space of eq. (reduced), each
+ * square with the space of its own shift; shared edges of adjacent squares cancel).
+ * The multiplicity of a cluster is the number of singular values of
+ * [P f_1 .. P f_k] above rel_tol times the largest; the singular values come from
+ * the k x k Gram matrix, so values below about 1e-8 of the largest are at its
+ * rounding level.  F: n x k complex, column-major (leading dimension n), in f_mem
+ * memory; 1 <= k <= 64; 0 < rel_tol < 1.  mult (int32 per cluster) and sv (k
+ * doubles per cluster, descending; may be NULL) are host arrays with room for
+ * cap clusters (EINVAL if cap < the number of clusters).  The pencil the run was
+ * made on must still exist.  Synchronous on return. */
+simm_status simm_multiplicities(simm_result r, const double* F, int32_t k, int32_t f_mem, double rel_tol,
+                                void* hip_stream, int32_t* mult, double* sv, int64_t cap);
+
 simm_status simm_result_summary(simm_result r, int32_t* K, int32_t* n_shifts, int64_t* n_clusters,
                                 int64_t* n_unresolved);
 
@@ -240,9 +259,13 @@ simm_status simm_result_clusters(simm_result r, int64_t* n, double* lam, double*
  * evaluations, [2] applications of M.  Either pointer may be NULL. */
 simm_status simm_result_stats(simm_result r, double* ms4, int64_t* counters3);
 
-/* With SIMM_FLAG_KERNEL_TIMING: total milliseconds and number of timed launches
- * per kernel class (SIMM_K_*), measured with HIP events recorded on the run's
- * stream around each launch.  Arrays of SIMM_K_COUNT entries; zeros otherwise. */
+/* With SIMM_FLAG_KERNEL_TIMING: total milliseconds and number of timed units per
+ * kernel class (SIMM_K_*), measured with HIP events recorded around each unit on
+ * the stream it runs on (LU factors computed ahead run on streams of their own, so
+ * the class totals may add up to more than the run's wall time).  A unit is one
+ * bracketed launch group (one application of M, one Arnoldi step, ...), except for
+ * SIMM_K_BAND_LU, whose unit is one 16-column panel launch of the LU.  Arrays of
+ * SIMM_K_COUNT entries; zeros otherwise. */
 simm_status simm_result_kernel_stats(simm_result r, double* ms, int64_t* launches);
 
 void simm_result_destroy(simm_result r);

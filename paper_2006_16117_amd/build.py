@@ -11,7 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsimm.so")
-SOURCES = ["capi.hip", "band_lu.hip", "band_sweep.hip", "band_spike.hip", "arnoldi.hip", "schur.hip", "indicators.hip", "project.hip"]
+SOURCES = ["capi.hip", "band_lu.hip", "band_sweep.hip", "band_spike.hip", "arnoldi.hip", "schur.hip", "indicators.hip",
+           "project.hip", "multiplicity.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

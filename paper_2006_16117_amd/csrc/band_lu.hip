@@ -390,13 +390,14 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs a, int64_t b) {
 
 namespace {
 template <int T>
-simm_status launch_lu(const LuArgs& a, hipStream_t st, const std::atomic<bool>* cancel) {
+simm_status launch_lu(const LuArgs& a, hipStream_t st, const std::atomic<bool>* cancel, int64_t& launches) {
     const int grid = 2 + (a.kv + NB - 1) / NB;
     const int64_t nblk = (a.n + NB - 1) / NB;
     const size_t lds = LuSmem<T>::bytes;
     if (!cancel) {
         for (int64_t b = -1; b < nblk; ++b)
             hipLaunchKernelGGL(k_band_lu_step<T>, dim3(b < 0 ? 1 : grid), dim3(T), lds, st, a, b);
+        launches = nblk + 1;
         return SIMM_OK;
     }
     // at most RING * BATCH launches queued ahead of the device, so that a cancel
@@ -421,6 +422,7 @@ simm_status launch_lu(const LuArgs& a, hipStream_t st, const std::atomic<bool>* 
         const int64_t bend = std::min<int64_t>(b + BATCH, nblk);
         for (int64_t q = b; q < bend; ++q)
             hipLaunchKernelGGL(k_band_lu_step<T>, dim3(q < 0 ? 1 : grid), dim3(T), lds, st, a, q);
+        launches += bend - b;
         SIMM_HIP_TRY(hipEventRecord(e, st));
     }
     return SIMM_OK;
@@ -433,7 +435,7 @@ int lu_panel_width(int kl) {
 }
 
 simm_status band_lu(int64_t n, int kl, int ku, cplx* AB, int* ipiv, cplx* LP, int* info,
-                    hipStream_t st, const std::atomic<bool>* cancel) {
+                    hipStream_t st, const std::atomic<bool>* cancel, int64_t* launches) {
     if (lu_panel_width(kl) == 0) {
         set_error("lower bandwidth too large for the LU kernel");
         return SIMM_EUNSUPPORTED;
@@ -449,10 +451,11 @@ simm_status band_lu(int64_t n, int kl, int ku, cplx* AB, int* ipiv, cplx* LP, in
     a.LP = LP;
     a.info = info;
     a.zidx = (int64_t)a.ldab * n;
-    if (2 * NB + kl <= 256)
-        SIMM_TRY(launch_lu<256>(a, st, cancel));
-    else
-        SIMM_TRY(launch_lu<512>(a, st, cancel));
+    int64_t count = 0;
+    const simm_status rc = (2 * NB + kl <= 256) ? launch_lu<256>(a, st, cancel, count)
+                                                : launch_lu<512>(a, st, cancel, count);
+    if (launches) *launches = count;
+    SIMM_TRY(rc);
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;
 }

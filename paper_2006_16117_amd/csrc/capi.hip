@@ -59,12 +59,15 @@ struct simm_shift_s {
     std::vector<cplx> H_host;   // (m_eff+1) x m_eff column-major
     std::vector<cplx> ritz;     // sigma + 1/theta
     bool borrowed = false;      // owned by a simm_result
+    bool factor_borrowed = false;   // AB, ipiv, LP, spike belong to another shift
     SpikeFactor spike;          // partitioned-sweep data of the factor
     ~simm_shift_s() {
-        spike_release(spike);
-        (void)hipFree(AB);
-        (void)hipFree(ipiv);
-        (void)hipFree(LP);
+        if (!factor_borrowed) {
+            spike_release(spike);
+            (void)hipFree(AB);
+            (void)hipFree(ipiv);
+            (void)hipFree(LP);
+        }
         (void)hipFree(V);
         (void)hipFree(H);
         (void)hipFree(T);
@@ -85,35 +88,44 @@ struct ClusterRec {
     cplx lam, lam_ritz;
     int shift;
     int flags;
+    std::vector<int64_t> members;   // indices into the last level's squares
 };
 
 // HIP-event brackets around kernel launches, collected after the run.
+// A bracket counts as one unit unless the code inside sets another count (the LU
+// bracket counts its panel launches).
 struct KernelClock {
+    struct Mark {
+        int k;
+        hipEvent_t a, b;
+        int64_t units;
+    };
     hipStream_t st = nullptr;
-    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
+    std::vector<Mark> marks;
     void begin(int k) {
         hipEvent_t a = nullptr;
         (void)hipEventCreate(&a);
         (void)hipEventRecord(a, st);
-        marks.push_back({k, {a, nullptr}});
+        marks.push_back({k, a, nullptr, 1});
     }
-    void end() {
+    void end(int64_t units) {
         hipEvent_t b = nullptr;
         (void)hipEventCreate(&b);
         (void)hipEventRecord(b, st);
-        marks.back().second.second = b;
+        marks.back().b = b;
+        marks.back().units = units;
     }
     void collect(double* ms, int64_t* cnt) {
         for (auto& m : marks) {
-            if (m.second.second) {
-                (void)hipEventSynchronize(m.second.second);
+            if (m.b) {
+                (void)hipEventSynchronize(m.b);
                 float t = 0;
-                (void)hipEventElapsedTime(&t, m.second.first, m.second.second);
-                ms[m.first] += t;
-                cnt[m.first] += 1;
-                (void)hipEventDestroy(m.second.second);
+                (void)hipEventElapsedTime(&t, m.a, m.b);
+                ms[m.k] += t;
+                cnt[m.k] += m.units;
+                (void)hipEventDestroy(m.b);
             }
-            (void)hipEventDestroy(m.second.first);
+            (void)hipEventDestroy(m.a);
         }
         marks.clear();
     }
@@ -121,11 +133,12 @@ struct KernelClock {
 
 struct KScope {
     KernelClock* c;
+    int64_t units = 1;
     KScope(KernelClock* clk, int k) : c(clk) {
         if (c) c->begin(k);
     }
     ~KScope() {
-        if (c) c->end();
+        if (c) c->end(units);
     }
 };
 
@@ -139,6 +152,8 @@ struct simm_result_s {
     std::vector<ClusterRec> clusters;
     double ms[4] = {0, 0, 0, 0};
     int64_t counters[3] = {0, 0, 0};
+    simm_params prm{};               // the run's parameters
+    simm_pencil_s* pencil = nullptr; // borrowed: the pencil the run was made on
 };
 
 namespace {
@@ -311,7 +326,8 @@ simm_status factor_shift(simm_pencil_s* p, cplx sigma, hipStream_t st, std::uniq
     {
         KScope ks(clk, SIMM_K_BAND_LU);
         SIMM_TRY(assemble_shifted(n, kl, ku, p->A, p->kla, p->kua, p->B, p->klb, p->kub, sigma, s->AB, st));
-        SIMM_TRY(band_lu(n, kl, ku, s->AB, s->ipiv, s->LP, info_d, st, cancel));
+        const simm_status lu = band_lu(n, kl, ku, s->AB, s->ipiv, s->LP, info_d, st, cancel, &ks.units);
+        if (lu != SIMM_OK) return lu;
     }
     SIMM_HIP_TRY(hipMemcpyAsync(&info, info_d, sizeof(int), hipMemcpyDeviceToHost, st));
     SIMM_HIP_TRY(hipStreamSynchronize(st));
@@ -336,14 +352,15 @@ simm_status krylov_shift(simm_shift_s* s, const cplx* f_dev, int m, hipStream_t 
     const cplx sigma = s->sigma;
     s->m = m;
     const int64_t n = p->n;
-    // partitioned-sweep data (unit-state responses of every chunk)
-    s->spike.n = n;
-    s->spike.kl = s->kl;
-    s->spike.ku = s->ku;
-    s->spike.AB = s->AB;
-    s->spike.ipiv = s->ipiv;
-    s->spike.LP = s->LP;
-    {
+    // partitioned-sweep data (unit-state responses of every chunk), unless the
+    // factor comes prepared from another shift
+    if (!s->factor_borrowed) {
+        s->spike.n = n;
+        s->spike.kl = s->kl;
+        s->spike.ku = s->ku;
+        s->spike.AB = s->AB;
+        s->spike.ipiv = s->ipiv;
+        s->spike.LP = s->LP;
         KScope ks(clk, SIMM_K_SPIKE_PREP);
         SIMM_TRY(spike_prepare(s->spike, st));
     }
@@ -696,6 +713,8 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
     int nx, ny, K;
     SIMM_TRY(validate_params(prm, p->n, &nx, &ny, &K));
     R->K = K;
+    R->prm = *prm;
+    R->pencil = p;
     Rule rule;
     SIMM_TRY(rule.make(prm->gauss_per_edge, st));
     const int m = prm->m;
@@ -1077,6 +1096,7 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
             if (last.decision[q] == SIMM_UNRESOLVED) flags |= 1;
         }
         ClusterRec cr;
+        cr.members = comp;
         cr.lam = cplx{sr / comp.size(), si / comp.size()};
         cr.shift = last.shift[comp[0]];
         cr.flags = flags;
@@ -1113,6 +1133,88 @@ simm_status to_device_vec(const double* src, int32_t mem, int64_t count, DevBuf&
     SIMM_TRY(buf.alloc(sizeof(cplx) * (size_t)count, st));
     SIMM_HIP_TRY(hipMemcpyAsync(buf.p, src, sizeof(cplx) * (size_t)count, hipMemcpyHostToDevice, st));
     *out = buf.as<const cplx>();
+    return SIMM_OK;
+}
+
+// Multiplicities (Sec. 3.4) of the clusters of a finished run: see simm_multiplicities.
+simm_status multiplicities(simm_result_s* R, const cplx* F, int k, double rel_tol, hipStream_t st, int32_t* mult,
+                           double* sv) {
+    const int64_t ncl = (int64_t)R->clusters.size();
+    if (ncl == 0) return SIMM_OK;
+    simm_pencil_s* p = R->pencil;
+    const simm_params* prm = &R->prm;
+    const int64_t n = p->n;
+    const int m = prm->m;
+    const LevelRec& last = R->levels.back();
+    Rule rule;
+    SIMM_TRY(rule.make(prm->gauss_per_edge, st));
+    // X: n x (ncl k), column c k + i = P f_i of cluster c
+    DevBuf xb, tb, yb, gb, sb, ib;
+    SIMM_TRY(xb.alloc(sizeof(cplx) * (size_t)n * ncl * k, st));
+    SIMM_HIP_TRY(hipMemsetAsync(xb.p, 0, sizeof(cplx) * (size_t)n * ncl * k, st));
+    SIMM_TRY(tb.alloc(sizeof(cplx) * (size_t)n * ncl, st));
+    SIMM_TRY(yb.alloc(sizeof(cplx) * (size_t)m * ncl, st));
+    std::vector<int> used;
+    for (const auto& c : R->clusters)
+        for (int64_t q : c.members) used.push_back(last.shift[q]);
+    std::sort(used.begin(), used.end());
+    used.erase(std::unique(used.begin(), used.end()), used.end());
+    for (int s : used) {
+        // squares of every cluster tested with shift s, grouped by cluster
+        std::vector<int64_t> regs, off{0}, idx;
+        for (const auto& c : R->clusters) {
+            for (int64_t q : c.members)
+                if (last.shift[q] == s) {
+                    idx.push_back((int64_t)regs.size() / 4);
+                    regs.insert(regs.end(), {(int64_t)R->K, last.ix[q], last.iy[q], 0});
+                }
+            off.push_back((int64_t)idx.size());
+        }
+        const int64_t nsq = (int64_t)idx.size();
+        SIMM_TRY(sb.alloc(sizeof(cplx) * (size_t)nsq * 2 * m, st));
+        SIMM_TRY(ib.alloc(sizeof(int64_t) * (off.size() + idx.size()), st));
+        int64_t* offd = ib.as<int64_t>();
+        int64_t* idxd = offd + off.size();
+        SIMM_HIP_TRY(hipMemcpyAsync(offd, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice, st));
+        SIMM_HIP_TRY(hipMemcpyAsync(idxd, idx.data(), sizeof(int64_t) * idx.size(), hipMemcpyHostToDevice, st));
+        const simm_shift_s* base = R->shifts[s].get();
+        for (int i = 0; i < k; ++i) {
+            // Krylov space of f_i on the shift's factor
+            simm_shift_s kv;
+            kv.p = p;
+            kv.sigma = base->sigma;
+            kv.kl = base->kl;
+            kv.ku = base->ku;
+            kv.AB = base->AB;
+            kv.ipiv = base->ipiv;
+            kv.LP = base->LP;
+            kv.spike = base->spike;
+            kv.factor_borrowed = true;
+            SIMM_TRY(krylov_shift(&kv, F + (int64_t)i * n, m, st, nullptr));
+            EvalOut eo;
+            SIMM_TRY(evaluate({&kv}, regs, prm, rule, st, eo, sb.as<cplx>(), m));
+            SIMM_TRY(cluster_sums(sb.as<cplx>(), m, offd, idxd, ncl, kv.m_eff, yb.as<cplx>(), m, st));
+            SIMM_TRY(project(n, kv.m_eff, kv.V, n, yb.as<cplx>(), m, ncl, tb.as<cplx>(), nullptr, nullptr, 0, st));
+            SIMM_TRY(accum_cols(n, ncl, tb.as<cplx>(), xb.as<cplx>() + (int64_t)i * n, (int64_t)k * n, st));
+            SIMM_HIP_TRY(hipStreamSynchronize(st));   // kv's buffers are freed at scope exit
+        }
+    }
+    SIMM_TRY(gb.alloc(sizeof(cplx) * (size_t)ncl * k * k, st));
+    SIMM_TRY(gram(n, k, ncl, xb.as<cplx>(), gb.as<cplx>(), st));
+    std::vector<cplx> G((size_t)ncl * k * k);
+    SIMM_HIP_TRY(hipMemcpyAsync(G.data(), gb.p, sizeof(cplx) * G.size(), hipMemcpyDeviceToHost, st));
+    SIMM_HIP_TRY(hipStreamSynchronize(st));
+    for (int64_t c = 0; c < ncl; ++c) {
+        const std::vector<double> ev = hermitian_eigenvalues(k, G.data() + (size_t)c * k * k);
+        int cnt = 0;
+        const double s0 = std::sqrt(std::max(ev[0], 0.0));
+        for (int i = 0; i < k; ++i) {
+            const double si = std::sqrt(std::max(ev[i], 0.0));
+            if (sv) sv[(size_t)c * k + i] = si;
+            if (s0 > 0.0 && si > rel_tol * s0) ++cnt;
+        }
+        mult[c] = cnt;
+    }
     return SIMM_OK;
 }
 
@@ -1600,6 +1702,28 @@ simm_status simm_result_clusters(simm_result r, int64_t* n, double* lam, double*
         if (flags) flags[q] = c.flags;
     }
     return SIMM_OK;
+}
+
+simm_status simm_multiplicities(simm_result r, const double* F, int32_t k, int32_t f_mem, double rel_tol,
+                                void* hip_stream, int32_t* mult, double* sv, int64_t cap) {
+    clear_error();
+    if (!r || !F || !mult || k < 1 || k > 64 || !(rel_tol > 0.0) || !(rel_tol < 1.0)) {
+        set_error("bad multiplicity arguments (need 1 <= k <= 64, 0 < rel_tol < 1)");
+        return SIMM_EINVAL;
+    }
+    if (cap < (int64_t)r->clusters.size()) {
+        set_error("cap smaller than the number of clusters");
+        return SIMM_EINVAL;
+    }
+    if (!r->pencil || r->levels.empty()) {
+        set_error("result has no levels");
+        return SIMM_EINVAL;
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    DevBuf fb;
+    const cplx* fd = nullptr;
+    SIMM_TRY(to_device_vec(F, f_mem, r->pencil->n * (int64_t)k, fb, &fd, st));
+    return multiplicities(r, fd, k, rel_tol, st, mult, sv);
 }
 
 simm_status simm_result_stats(simm_result r, double* ms4, int64_t* counters3) {

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <atomic>
+#include <vector>
 
 #include "common.hpp"
 
@@ -16,8 +17,9 @@ size_t band_lu_panel_elems(int64_t n, int kl);
 // info must hold INT_MAX on entry; it receives the first singular column + 1.
 // With `cancel`, the launches are enqueued a few hundred at a time and enqueuing
 // stops (SIMM_ECANCELED, the factor left incomplete) once *cancel is set.
+// `launches` (may be NULL) receives the number of panel launches enqueued.
 simm_status band_lu(int64_t n, int kl, int ku, cplx* AB, int* ipiv, cplx* LP, int* info, hipStream_t st,
-                    const std::atomic<bool>* cancel = nullptr);
+                    const std::atomic<bool>* cancel = nullptr, int64_t* launches = nullptr);
 
 // ---- input of the sweeps (band_sweep.hip) ----
 simm_status prepare_input(int64_t n, const cplx* x, const cplx* Bb, int klb, int kub, const double* hdiv,
@@ -144,6 +146,14 @@ simm_status indicators(const ShiftDev* shifts_dev, int mmax, const int64_t* regi
                        const IndicatorParams& prm, const RuleDev& rule, double* indicator, double* rho_max,
                        double* nsf, double* nsc, double* Tf, uint8_t* decision, cplx* sums, int m_sums,
                        hipStream_t st);
+
+// ---- multiplicities (multiplicity.hip) ----
+simm_status cluster_sums(const cplx* sums, int m_sums, const int64_t* off, const int64_t* idx, int64_t ncl,
+                         int mrows, cplx* Y, int64_t ldy, hipStream_t st);
+simm_status accum_cols(int64_t n, int64_t ncl, const cplx* T, cplx* X, int64_t ldx, hipStream_t st);
+// G: ncl x k x k complex, block c column-major k x k: G(a, b) = X_{ck+a}^H X_{ck+b}
+simm_status gram(int64_t n, int k, int64_t ncl, const cplx* X, cplx* G, hipStream_t st);
+std::vector<double> hermitian_eigenvalues(int k, const cplx* G);
 
 // ---- projection (project.hip) ----
 simm_status project(int64_t n, int m, const cplx* V, int64_t ldv, const cplx* Y, int64_t ldy, int64_t c, cplx* X,

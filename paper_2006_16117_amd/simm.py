@@ -67,6 +67,7 @@ EXPORTS = {
     "simm_run": (C.c_int, [_vp, C.POINTER(simm_params), _vp, _i32, _vp, C.POINTER(_vp)]),
     "simm_run_batch": (C.c_int, [C.POINTER(_vp), C.POINTER(simm_params), C.POINTER(_vp), _i32, _i32, _i32,
                                  C.POINTER(_vp)]),
+    "simm_multiplicities": (C.c_int, [_vp, _vp, _i32, _i32, _d, _vp, _vp, _vp, _i64]),
     "simm_result_summary": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "simm_result_level": (C.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64]),
     "simm_result_shift": (C.c_int, [_vp, _i32, C.POINTER(_vp)]),
@@ -323,7 +324,29 @@ def simm_run(pencil: Pencil, f, params: simm_params, stream=None) -> Result:
     pf, mem = _ptr(np.ascontiguousarray(f, dtype=np.complex128) if isinstance(f, np.ndarray) else f)
     h = _vp()
     _check(_lib.simm_run(pencil.handle, C.byref(params), pf, mem, _stream(stream), C.byref(h)))
-    return Result(h)
+    res = Result(h)
+    res.pencil = pencil      # the result's shifts refer to the pencil: keep it alive with the result
+    return res
+
+
+def simm_multiplicities(result: "Result", F, rel_tol: float = 1e-6, stream=None):
+    """Multiplicity of every cluster of `result` from the k start vectors in the
+    columns of F (n x k complex; host array or device tensor, column-major).
+    Returns (mult int32[n_clusters], singular values [n_clusters, k])."""
+    if isinstance(F, np.ndarray):
+        F = np.asfortranarray(F, dtype=np.complex128)
+        k = F.shape[1]
+        pf, mem = F.ctypes.data, SIMM_MEM_HOST
+    else:
+        k = F.shape[1]
+        assert F.stride(0) == 1 and F.stride(1) == F.shape[0], "F must be column-major"
+        pf, mem = F.data_ptr(), SIMM_MEM_DEVICE
+    ncl = result.n_clusters
+    mult = np.zeros(max(ncl, 1), np.int32)
+    sv = np.zeros((max(ncl, 1), k))
+    _check(_lib.simm_multiplicities(result.handle, pf, k, mem, rel_tol, _stream(stream), mult.ctypes.data,
+                                    sv.ctypes.data, ncl))
+    return mult[:ncl], sv[:ncl]
 
 
 def simm_run_batch(pencils, fs, params_list, workers: int = 8):
@@ -337,5 +360,8 @@ def simm_run_batch(pencils, fs, params_list, workers: int = 8):
     pf = (_vp * count)(*[k.ctypes.data_as(_vp) for k in keep])
     out = (_vp * count)()
     _check(_lib.simm_run_batch(ph, pp, pf, 0, count, workers, out))
-    return [Result(_vp(out[i])) for i in range(count)]
+    results = [Result(_vp(out[i])) for i in range(count)]
+    for r, p in zip(results, pencils):
+        r.pencil = p
+    return results
 

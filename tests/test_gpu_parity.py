@@ -276,6 +276,39 @@ def test_lookahead_equals_one_at_a_time(S):
 
 
 # ---------------------------------------------------------------------------
+# multiplicities (Sec. 3.4)
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def planted_oracle_run():
+    pen, f, params = make_workload("mult0")
+    return pen, f, params, O.simm(pen, f, params)
+
+
+@pytest.mark.parametrize("k", [5, 1, 8])
+def test_multiplicities_match_oracle(S, planted_oracle_run, k):
+    from workloads import load_config, start_vectors
+    name = "mult0"
+    pen, f, params, res_o = planted_oracle_run
+    cfg = load_config(name)
+    F = start_vectors(pen.n, k, cfg["generator"]["seed"])
+    say("simm_multiplicities", name, "k =", k)
+    want = O.multiplicities(O.cluster_projections(pen, res_o, F, params))
+    res = S.simm_run(S.Pencil.from_workload(pen), f, S.params_from_dict(params))
+    assert res.n_clusters == len(res_o.clusters)
+    mult, sv = S.simm_multiplicities(res, F, rel_tol=O.MULT_REL_TOL)
+    say("  multiplicities", np.bincount(mult).tolist(), "(count of clusters per multiplicity)")
+    for c, (mo, svo) in enumerate(want):
+        assert mult[c] == mo, (c, mult[c], mo, sv[c] / sv[c][0], svo / svo[0])
+        # significant singular values agree; the others sit at their rounding levels
+        # (the library's come from the Gram matrix, so about 1e-8 of the largest)
+        assert np.all(np.abs(sv[c][:mo] - svo[:mo]) <= 1e-8 * svo[0]), (c, sv[c], svo)
+        assert np.all(sv[c][mo:] <= O.MULT_REL_TOL * sv[c][0])
+    assert sorted(mult.tolist()) == sorted(min(k, e) for e in (1, 1, 2, 2, 3))
+    with pytest.raises(S.SimmError):
+        S.simm_multiplicities(res, F, rel_tol=0.0)
+
+
+# ---------------------------------------------------------------------------
 # edge cases: empty inputs, empty levels, guards, the CSR entry point
 # ---------------------------------------------------------------------------
 def test_empty_inputs(S):

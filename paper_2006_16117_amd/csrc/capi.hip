@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <memory>
 #include <set>
 #include <atomic>
@@ -347,11 +348,15 @@ simm_status factor_shift(simm_pencil_s* p, cplx sigma, hipStream_t st, std::uniq
 // it runs here rather than beside other work), b, beta, the Arnoldi basis V_{m+1}
 // and H_{m+1,m}, and the Schur data of H_m.
 simm_status krylov_shift(simm_shift_s* s, const cplx* f_dev, int m, hipStream_t st, int64_t* applies,
-                         KernelClock* clk = nullptr) {
+                         KernelClock* clk = nullptr, const std::atomic<bool>* cancel = nullptr) {
     simm_pencil_s* p = s->p;
     const cplx sigma = s->sigma;
     s->m = m;
     const int64_t n = p->n;
+    if (cancel && cancel->load()) {
+        set_error("Krylov phase cancelled");
+        return SIMM_ECANCELED;
+    }
     // partitioned-sweep data (unit-state responses of every chunk), unless the
     // factor comes prepared from another shift
     if (!s->factor_borrowed) {
@@ -401,8 +406,28 @@ simm_status krylov_shift(simm_shift_s* s, const cplx* f_dev, int m, hipStream_t 
         SIMM_TRY(spike_apply(s->spike, f_dev, s->V, nullptr, st));
     }
     SIMM_TRY(vec_norm_scale(n, s->V, s->V, beta_d, aw, st));
-    // a4: Arnoldi steps
+    // a4: Arnoldi steps.  With `cancel`, the host stays at most 16 steps ahead of the
+    // device and stops enqueuing once *cancel is set.
+    hipEvent_t ring[2] = {nullptr, nullptr};
+    struct RingRelease {
+        hipEvent_t* e;
+        ~RingRelease() {
+            for (int i = 0; i < 2; ++i)
+                if (e[i]) (void)hipEventDestroy(e[i]);
+        }
+    } ring_release{ring};
+    if (cancel)
+        for (auto& e : ring) SIMM_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     for (int j = 0; j < m; ++j) {
+        if (cancel && j % 8 == 0) {
+            if (cancel->load(std::memory_order_relaxed)) {
+                set_error("Krylov phase cancelled");
+                return SIMM_ECANCELED;
+            }
+            hipEvent_t& e = ring[(j / 8) % 2];
+            if (j >= 16) SIMM_HIP_TRY(hipEventSynchronize(e));
+            SIMM_HIP_TRY(hipEventRecord(e, st));
+        }
         cplx* vj = s->V + (int64_t)j * n;
         {
             KScope ks(clk, SIMM_K_BAND_SWEEP);   // one application of M: B v, then the factor's sweeps
@@ -638,31 +663,85 @@ struct Timer {
     }
 };
 
-// The factor phase of a shift built ahead of the association order (steps 2-3), by
-// a host thread of its own on a stream of its own.  Joined (and its stream released)
+// A shift built ahead of the association order (steps 2-3), by a host thread of its
+// own on a stream of its own: always its factor phase, and its Krylov phase too if
+// asked for (before or after the factor is done).  Joined (and its stream released)
 // on destruction, so no thread outlives the run that started it.
 struct AheadBuild {
     std::thread th;
+    std::mutex mu;
     std::unique_ptr<simm_shift_s> s;
-    simm_status rc = SIMM_OK;
+    simm_status rc = SIMM_OK;    // factor phase
+    simm_status krc = SIMM_OK;   // Krylov phase
     std::string err;
     KernelClock clock;
     hipStream_t st = nullptr;
     std::atomic<bool> cancel{false};
-    void start(simm_pencil_s* p, cplx sigma, bool timed) {
-        th = std::thread([this, p, sigma, timed]() {
-            (void)hipSetDevice(p->dev);
+    bool timed = false;
+    bool factor_done = false, krylov_wanted = false, krylov_started = false;
+    int64_t applies = 0;
+    const cplx* kf = nullptr;
+    int km = 0;
+    hipEvent_t kready = nullptr;
+    int dev = 0;
+
+    void run_krylov() {
+        hipError_t e = hipStreamWaitEvent(st, kready, 0);   // f is written on the run's stream
+        if (e != hipSuccess) {
+            krc = SIMM_EHIP;
+            err = std::string("hipStreamWaitEvent: ") + hipGetErrorString(e);
+            return;
+        }
+        krc = krylov_shift(s.get(), kf, km, st, &applies, timed ? &clock : nullptr, &cancel);
+        if (krc != SIMM_OK) err = g_err;
+    }
+    void start(simm_pencil_s* p, cplx sigma, bool timed_) {
+        timed = timed_;
+        dev = p->dev;
+        th = std::thread([this, p, sigma]() {
+            (void)hipSetDevice(dev);
             const hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
             if (e != hipSuccess) {
                 st = nullptr;
                 rc = SIMM_EHIP;
                 err = std::string("stream for a shift built ahead: ") + hipGetErrorString(e);
-                return;
+            } else {
+                clock.st = st;
+                rc = factor_shift(p, sigma, st, s, timed ? &clock : nullptr, &cancel);
+                if (rc != SIMM_OK) err = g_err;
             }
-            clock.st = st;
-            rc = factor_shift(p, sigma, st, s, timed ? &clock : nullptr, &cancel);
-            if (rc != SIMM_OK) err = g_err;
+            bool go = false;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                factor_done = true;
+                if (krylov_wanted && rc == SIMM_OK) krylov_started = go = true;
+            }
+            if (go) run_krylov();
         });
+    }
+    // asks for the Krylov phase (start vector f written on the run's stream before `ready`)
+    void request_krylov(const cplx* f, int m, hipEvent_t ready) {
+        bool spawn = false;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if (krylov_wanted) return;
+            krylov_wanted = true;
+            kf = f;
+            km = m;
+            kready = ready;
+            if (factor_done && rc == SIMM_OK && !krylov_started) krylov_started = spawn = true;
+        }
+        if (spawn) {   // the factor thread has finished its work: run the Krylov phase on a new one
+            if (th.joinable()) th.join();
+            th = std::thread([this]() {
+                (void)hipSetDevice(dev);
+                run_krylov();
+            });
+        }
+    }
+    bool krylov_requested() {
+        std::lock_guard<std::mutex> lk(mu);
+        return krylov_wanted;
     }
     // waits for the build; its kernel times go to (ms, cnt) if those are given
     void finish(double* ms = nullptr, int64_t* cnt = nullptr) {
@@ -674,6 +753,8 @@ struct AheadBuild {
             st = nullptr;
         }
     }
+    // true when both phases ran and succeeded
+    bool complete() const { return rc == SIMM_OK && krylov_started && krc == SIMM_OK; }
     ~AheadBuild() { finish(); }
 };
 
@@ -767,6 +848,13 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
     // when the cell order reaches its cell still unresolved, so the shifts kept and
     // every later result are those of the one-at-a-time order.
     const int W = lookahead_width(prm, p);
+    hipEvent_t ready = nullptr;   // f is on the device (it is written on the run's stream)
+    struct EventGuard {           // declared before the builds ahead: destroyed after they are joined
+        hipEvent_t* e;
+        ~EventGuard() {
+            if (*e) (void)hipEventDestroy(*e);
+        }
+    } ready_guard{&ready};
     std::map<int64_t, std::unique_ptr<AheadBuild>> ahead;   // cell -> factor in flight or done
     std::vector<std::unique_ptr<AheadBuild>> dropped;         // factors whose cell got resolved
     auto release_dropped = [&]() {
@@ -815,6 +903,63 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
             ++live;
         }
     };
+    // For small factors the Krylov phases of the next KA cells predicted to need a
+    // shift run ahead too, on the factor's own stream, so that one shift's Krylov
+    // phase overlaps the next's.  Prediction: the first cells after the current one
+    // that no shift resolves so far, skipping the current cell's neighbours while new
+    // shifts have mostly resolved their neighbours so far (then a neighbour rarely
+    // needs a shift of its own).  A wrong guess costs a cancelled build, never a
+    // different result.  A small factor's Krylov phase is a chain of short launches
+    // on a few compute units, and two of them share the device well (n = 400 band of
+    // 45 KB: shift builds 450 -> 148 ms); a large one streams its factor through many
+    // units per application, and beside the factors computed ahead two of them slowed
+    // each other more than they overlapped (n = 40,000 band of 385 MB: ~875 -> ~950 ms
+    // per step), so they stay one at a time.
+    const double band_bytes =
+        16.0 * (double)(2 * std::max(p->kla, p->klb) + std::max(p->kua, p->kub) + 1) * (double)p->n;
+    const int KA = (W > 1 && band_bytes <= 64.0 * (1 << 20)) ? 2 : 0;
+    if (KA > 0) {
+        SIMM_HIP_TRY(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+        SIMM_HIP_TRY(hipEventRecord(ready, st));
+    }
+    int64_t nb_hits = 0, nb_seen = 0;   // neighbours a new shift resolved / could have resolved
+    auto neighbours = [&](int64_t a, int64_t b) {
+        return std::llabs(cells[a].first - cells[b].first) <= 1 && std::llabs(cells[a].second - cells[b].second) <= 1;
+    };
+    auto request_ahead = [&](int64_t d) {
+        auto it = ahead.find(d);
+        if (it == ahead.end()) {
+            auto b = std::make_unique<AheadBuild>();
+            b->start(p, cell_center(prm, 1, cells[d].first, cells[d].second), clk != nullptr);
+            it = ahead.emplace(d, std::move(b)).first;
+        }
+        it->second->request_krylov(f_dev, m, ready);
+    };
+    // Krylov phases ahead for the cells predicted after `cur` (cur = -1: before any cell)
+    auto predict_ahead = [&](int64_t cur, bool guess_far_from_centre) {
+        if (KA == 0) return;
+        int inflight = 0;
+        for (auto& kv : ahead)
+            if (kv.first > cur && kv.second->krylov_requested()) ++inflight;
+        const bool skip_nb = cur >= 0 && (nb_seen == 0 || 2 * nb_hits > nb_seen);
+        const cplx c0{(prm->x0 + prm->x1) / 2, (prm->y0 + prm->y1) / 2};
+        const double w1 = (prm->x1 - prm->x0) / prm->n1;
+        std::vector<int64_t> picked;
+        for (int64_t d = cur + 1; d < ncell && inflight < KA; ++d) {
+            if (!unresolved(d)) continue;
+            if (guess_far_from_centre &&
+                cdist(cell_center(prm, 1, cells[d].first, cells[d].second), c0) <= 1.5 * w1)
+                continue;
+            bool skip = skip_nb && neighbours(cur, d);
+            for (int64_t q : picked) skip = skip || (skip_nb && neighbours(q, d));
+            if (skip) continue;
+            auto it = ahead.find(d);
+            if (it != ahead.end() && it->second->krylov_requested()) continue;
+            request_ahead(d);
+            picked.push_back(d);
+            ++inflight;
+        }
+    };
     // factors for the first cells away from R's centre, ahead of the first shift's
     // own build (a guess of which cells the first shift leaves unresolved: a wrong
     // guess costs a cancelled factor, never a different result)
@@ -828,6 +973,7 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
             b->start(p, cd, clk != nullptr);
             ahead[d] = std::move(b);
         }
+        predict_ahead(-1, true);
     }
     // step 1: first shift at the centre of R
     {
@@ -854,31 +1000,48 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
             }
         if (chosen < 0) {
             std::unique_ptr<simm_shift_s> s;
+            bool built = false;   // both phases done ahead
             if (W > 1) {
                 const auto t0 = std::chrono::steady_clock::now();
                 if (!ahead.count(c)) top_up(c);
+                if (KA > 0) {
+                    request_ahead(c);           // this cell's Krylov phase, if not asked for yet
+                    predict_ahead(c, false);    // and the next cells' beside it
+                }
                 std::unique_ptr<AheadBuild> b = std::move(ahead[c]);
                 ahead.erase(c);
                 if (b) {
                     b->finish(clk ? R->kms : nullptr, clk ? R->kcnt : nullptr);
-                    if (b->rc == SIMM_OK) s = std::move(b->s);
+                    if (b->complete()) {
+                        s = std::move(b->s);
+                        R->counters[2] += b->applies;
+                        built = true;
+                    } else if (b->rc == SIMM_OK && !b->krylov_started) {
+                        s = std::move(b->s);
+                    }
                 }
                 R->ms[0] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
             }
             if (!s) {
-                // one at a time (also after a failed factor made ahead, whose error the
+                // one at a time (also after a failed build ahead, whose error the
                 // one-at-a-time order then reports itself)
                 drop_all();
                 Timer t(st, &R->ms[0]);
                 SIMM_TRY(factor_shift(p, ctr, st, s, clk));
             }
-            {
+            if (!built) {
                 Timer t(st, &R->ms[0]);
                 SIMM_TRY(krylov_shift(s.get(), f_dev, m, st, &R->counters[2], clk));
             }
+            // neighbours of c after it that no shift resolved before this one
+            std::vector<int64_t> nb;
+            for (int64_t d = c + 1; d < ncell; ++d)
+                if (neighbours(c, d) && unresolved(d)) nb.push_back(d);
             commit(std::move(s));
             chosen = (int)shifts.size() - 1;
             SIMM_TRY(eval_cells_vs(chosen));
+            for (int64_t d : nb) nb_hits += resolv[{d, chosen}] ? 1 : 0;
+            nb_seen += (int64_t)nb.size();
             drop_resolved_by(chosen);
             top_up(c + 1);
         }

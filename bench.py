@@ -129,16 +129,22 @@ def bench_batch(args):
     log("batch", args.workload, len(batch), "pencils, n =", sum(p.n for p, _, _ in batch))
     pencils = [S.Pencil.from_workload(p) for p, _, _ in batch]
     fs = [f for _, f, _ in batch]
-    prms = [S.params_from_dict(d) for _, _, d in batch]
+    # results keep only levels, clusters and small per-shift data (a batch of large
+    # pencils would otherwise hold every factor and Krylov basis of every run)
+    prms = [S.params_from_dict(d, flags=S.SIMM_FLAG_RELEASE_FACTORS) for _, _, d in batch]
     torch.cuda.synchronize()
     for _ in range(args.warmup):
         S.simm_run_batch(pencils, fs, prms, workers=args.workers)
     t0 = time.perf_counter()
-    seq = [S.simm_run(P, f, prm) for P, f, prm in zip(pencils, fs, prms)]
+    n_qp = n_sq = 0
+    for i, (P, f, prm) in enumerate(zip(pencils, fs, prms)):
+        r = S.simm_run(P, f, prm)
+        n_qp += r.counters["quadrature_systems"]
+        n_sq += r.counters["squares"]
+        del r
+        if (i + 1) % 8 == 0:
+            log(f"sequential: {i + 1}/{len(pencils)} runs, {time.perf_counter() - t0:.1f} s")
     t_seq = time.perf_counter() - t0
-    n_qp = sum(r.counters["quadrature_systems"] for r in seq)
-    n_sq = sum(r.counters["squares"] for r in seq)
-    del seq
     log(f"sequential: {t_seq:.2f} s")
     t0 = time.perf_counter()
     for _ in range(args.steps):

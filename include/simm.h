@@ -51,7 +51,12 @@ enum { SIMM_REJECTED = 0, SIMM_ADMISSIBLE = 1, SIMM_UNRESOLVED = 2 };
 /* simm_params.flags */
 enum {
     SIMM_FLAG_PROJECT = 1u,        /* form X = V_m Y for the squares of every level               */
-    SIMM_FLAG_KERNEL_TIMING = 2u   /* bracket every hot-path kernel launch with HIP events        */
+    SIMM_FLAG_KERNEL_TIMING = 2u,  /* bracket every hot-path kernel launch with HIP events        */
+    SIMM_FLAG_RELEASE_FACTORS = 4u /* free every shift's factor, sweep data and Krylov basis when
+                                      the run ends (the result keeps the levels, clusters and each
+                                      shift's sigma, beta, H and Schur data); simm_shift_apply,
+                                      simm_shift_basis and simm_multiplicities on the result then
+                                      return EINVAL.  For batches of large pencils.               */
 };
 
 /* Kernel classes reported by simm_result_kernel_stats. */

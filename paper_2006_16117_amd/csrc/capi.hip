@@ -62,6 +62,24 @@ struct simm_shift_s {
     bool borrowed = false;      // owned by a simm_result
     bool factor_borrowed = false;   // AB, ipiv, LP, spike belong to another shift
     SpikeFactor spike;          // partitioned-sweep data of the factor
+    // frees the n-sized data (factor, sweep data, Krylov basis); the small per-shift
+    // data used by the indicators stays
+    void release_large() {
+        if (!factor_borrowed) {
+            spike_release(spike);
+            (void)hipFree(AB);
+            (void)hipFree(ipiv);
+            (void)hipFree(LP);
+        }
+        (void)hipFree(V);
+        AB = nullptr;
+        ipiv = nullptr;
+        LP = nullptr;
+        V = nullptr;
+        spike = SpikeFactor{};
+        factor_borrowed = true;   // nothing left to free
+    }
+    bool has_factor() const { return AB != nullptr && V != nullptr; }
     ~simm_shift_s() {
         if (!factor_borrowed) {
             spike_release(spike);
@@ -1276,6 +1294,10 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
         }
         R->clusters.push_back(cr);
     }
+    if (prm->flags & SIMM_FLAG_RELEASE_FACTORS) {
+        SIMM_HIP_TRY(hipStreamSynchronize(st));
+        for (auto& sh : R->shifts) sh->release_large();
+    }
     return SIMM_OK;
 }
 
@@ -1562,6 +1584,10 @@ simm_status simm_shift_info(simm_shift s, double* sigma, double* beta, int32_t* 
 simm_status simm_shift_basis(simm_shift s, double* V, int32_t mem, void* hip_stream) {
     clear_error();
     if (!s || !V) return SIMM_EINVAL;
+    if (!s->has_factor()) {
+        set_error("the shift's Krylov basis was released (SIMM_FLAG_RELEASE_FACTORS)");
+        return SIMM_EINVAL;
+    }
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     const size_t cnt = (size_t)s->p->n * (s->m_eff + 1);
     SIMM_HIP_TRY(hipMemcpyAsync(V, s->V, sizeof(cplx) * cnt,
@@ -1574,6 +1600,10 @@ simm_status simm_shift_apply(simm_shift s, const double* x, double* y, int32_t m
     clear_error();
     if (!s || !x || !y || x == y) {
         set_error("bad apply arguments");
+        return SIMM_EINVAL;
+    }
+    if (!s->has_factor()) {
+        set_error("the shift's factor was released (SIMM_FLAG_RELEASE_FACTORS)");
         return SIMM_EINVAL;
     }
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
@@ -1882,6 +1912,11 @@ simm_status simm_multiplicities(simm_result r, const double* F, int32_t k, int32
         set_error("result has no levels");
         return SIMM_EINVAL;
     }
+    for (const auto& sh : r->shifts)
+        if (!sh->has_factor()) {
+            set_error("the run's factors were released (SIMM_FLAG_RELEASE_FACTORS)");
+            return SIMM_EINVAL;
+        }
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     DevBuf fb;
     const cplx* fd = nullptr;

@@ -21,6 +21,7 @@ SIMM_MEM_HOST = 0
 SIMM_MEM_DEVICE = 1
 SIMM_FLAG_PROJECT = 1
 SIMM_FLAG_KERNEL_TIMING = 2
+SIMM_FLAG_RELEASE_FACTORS = 4
 KERNEL_NAMES = ["band_lu", "band_sweep", "gram_schmidt", "schur", "indicators", "project", "spike_prep"]
 REJECTED, ADMISSIBLE, UNRESOLVED = 0, 1, 2
 

@@ -130,6 +130,28 @@ def test_breakdown_and_errors(S):
     assert e.value.status == -1
 
 
+def test_singular_cell_shift_same_error_with_lookahead(S):
+    """A level-1 cell whose centre is an eigenvalue: its shift has an exact zero pivot.
+    The factor computed ahead for that cell fails on a side stream; the run must
+    report the same error as building one shift at a time (and as the oracle)."""
+    rng = np.random.default_rng(11)
+    n = 60
+    d = rng.uniform(-2, 2, n) + 1j * rng.uniform(-2, 2, n)
+    d[7] = 0.5 - 0.5j                       # centre of level-1 cell (1, 0) of R = [-1,1]^2, n1 = 2
+    pen = WPencil(n, 0, 0, d.reshape(1, n).astype(complex), 0, 0, None)
+    f = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    params = dict(x0=-1.0, x1=1.0, y0=-1.0, y1=1.0, n1=2, gauss_per_edge=8, m=3, h0=1e-2, levels=0,
+                  eps0=1e-8, delta0=0.05, tau=1e-8)
+    with pytest.raises(O.SingularShift):
+        O.simm(pen, f, params)
+    P = S.Pencil.from_workload(pen)
+    for la in (1, 3):
+        say("singular cell shift, lookahead", la)
+        with pytest.raises(S.SimmError) as e:
+            S.simm_run(P, f, S.params_from_dict(params, lookahead=la))
+        assert e.value.status == -5, (la, e.value)
+
+
 # ---------------------------------------------------------------------------
 # indicators and projection
 # ---------------------------------------------------------------------------
@@ -304,6 +326,16 @@ def test_multiplicities_match_oracle(S, planted_oracle_run, k):
         assert np.all(np.abs(sv[c][:mo] - svo[:mo]) <= 1e-8 * svo[0]), (c, sv[c], svo)
         assert np.all(sv[c][mo:] <= O.MULT_REL_TOL * sv[c][0])
     assert sorted(mult.tolist()) == sorted(min(k, e) for e in (1, 1, 2, 2, 3))
+    if k == 5:
+        # a run that releases its factors gives the same levels and refuses the multiplicity step
+        lean = S.simm_run(S.Pencil.from_workload(pen), f,
+                          S.params_from_dict(params, flags=S.SIMM_FLAG_RELEASE_FACTORS))
+        assert lean.n_clusters == res.n_clusters and np.array_equal(lean.lam, res.lam)
+        for La, Lb in zip(lean.levels, res.levels):
+            assert np.array_equal(La.decision, Lb.decision) and np.array_equal(La.indicator, Lb.indicator)
+        with pytest.raises(S.SimmError) as e:
+            S.simm_multiplicities(lean, F)
+        assert e.value.status == -1
     with pytest.raises(S.SimmError):
         S.simm_multiplicities(res, F, rel_tol=0.0)
 

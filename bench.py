@@ -132,12 +132,16 @@ def bench_batch(args):
     # results keep only levels, clusters and small per-shift data (a batch of large
     # pencils would otherwise hold every factor and Krylov basis of every run)
     prms = [S.params_from_dict(d, flags=S.SIMM_FLAG_RELEASE_FACTORS) for _, _, d in batch]
+    bprms = [S.params_from_dict(d, flags=S.SIMM_FLAG_RELEASE_FACTORS, lookahead=args.batch_lookahead)
+             for _, _, d in batch]
     torch.cuda.synchronize()
     for _ in range(args.warmup):
-        S.simm_run_batch(pencils, fs, prms, workers=args.workers)
+        S.simm_run_batch(pencils, fs, bprms, workers=args.workers)
     t0 = time.perf_counter()
     n_qp = n_sq = 0
     for i, (P, f, prm) in enumerate(zip(pencils, fs, prms)):
+        if args.no_sequential:
+            break
         r = S.simm_run(P, f, prm)
         n_qp += r.counters["quadrature_systems"]
         n_sq += r.counters["squares"]
@@ -148,8 +152,12 @@ def bench_batch(args):
     log(f"sequential: {t_seq:.2f} s")
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        bat = S.simm_run_batch(pencils, fs, prms, workers=args.workers)
+        bat = S.simm_run_batch(pencils, fs, bprms, workers=args.workers)
     t_bat = (time.perf_counter() - t0) / args.steps
+    if args.no_sequential:
+        n_qp = sum(r.counters["quadrature_systems"] for r in bat)
+        n_sq = sum(r.counters["squares"] for r in bat)
+        t_seq = float("nan")
     assert sum(r.counters["quadrature_systems"] for r in bat) == n_qp
     log(f"batched ({args.workers} in flight): {t_bat:.2f} s")
     cfg = load_config(args.workload)
@@ -172,6 +180,7 @@ def bench_batch(args):
         "indicators_per_s": n_sq / t_bat,
         "config": {"workload": cfg["description"], "pencils": len(batch),
                    "n_total": sum(p.n for p, _, _ in batch), "workers": args.workers,
+                   "lookahead_per_run": args.batch_lookahead, "hw_queues": HW_QUEUES,
                    "resolvent_solves_per_step": n_qp, "squares_per_step": n_sq},
     }
     print(json.dumps(out))
@@ -186,6 +195,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mult-k", type=int, default=4, help="start vectors for the multiplicity step (0: skip)")
     ap.add_argument("--workers", type=int, default=4, help="runs in flight in the batched form")
+    ap.add_argument("--batch-lookahead", type=int, default=0,
+                    help="look-ahead of each run in the batched form (0: the batch default, one at a time)")
+    ap.add_argument("--no-sequential", action="store_true", help="batched form only (no separate runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (three times): the reference "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE to HBM bytes")

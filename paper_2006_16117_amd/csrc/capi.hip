@@ -27,6 +27,44 @@ static thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
 void clear_error() { g_err.clear(); }
 
+// Frees of the buffers a run releases at its end (SIMM_FLAG_RELEASE_FACTORS).  A free
+// waits for the whole device, so while a batch has runs in flight on other streams
+// the buffers are collected and freed together once they add up to kDeferBytes (one
+// wait instead of one per buffer), and at the end of the batch.
+static std::mutex g_free_mu;
+static std::vector<void*> g_free_list;
+static size_t g_free_bytes = 0;
+static std::atomic<int> g_batches{0};
+constexpr size_t kDeferBytes = (size_t)32 << 30;
+
+void flush_deferred_frees() {
+    std::vector<void*> v;
+    {
+        std::lock_guard<std::mutex> lk(g_free_mu);
+        v.swap(g_free_list);
+        g_free_bytes = 0;
+    }
+    for (void* q : v) (void)hipFree(q);
+}
+
+void release_device(void* q) {
+    if (!q) return;
+    if (g_batches.load() == 0) {
+        (void)hipFree(q);
+        return;
+    }
+    size_t bytes = 0;
+    if (hipMemPtrGetInfo(q, &bytes) != hipSuccess) bytes = 0;
+    bool flush = false;
+    {
+        std::lock_guard<std::mutex> lk(g_free_mu);
+        g_free_list.push_back(q);
+        g_free_bytes += bytes;
+        flush = g_free_bytes >= kDeferBytes;
+    }
+    if (flush) flush_deferred_frees();
+}
+
 }  // namespace simm
 
 using namespace simm;
@@ -66,12 +104,12 @@ struct simm_shift_s {
     // data used by the indicators stays
     void release_large() {
         if (!factor_borrowed) {
-            spike_release(spike);
-            (void)hipFree(AB);
-            (void)hipFree(ipiv);
-            (void)hipFree(LP);
+            release_device(spike.mem);
+            release_device(AB);
+            release_device(ipiv);
+            release_device(LP);
         }
-        (void)hipFree(V);
+        release_device(V);
         AB = nullptr;
         ipiv = nullptr;
         LP = nullptr;
@@ -1810,8 +1848,10 @@ simm_status simm_run_batch(const simm_pencil* pencils, const simm_params* params
     };
     std::vector<std::thread> pool;
     const int32_t nw = std::min(workers, std::max<int32_t>(count, 1));
+    g_batches.fetch_add(1);
     for (int32_t w = 0; w < nw; ++w) pool.emplace_back(work);
     for (auto& t : pool) t.join();
+    if (g_batches.fetch_sub(1) == 1) flush_deferred_frees();
     for (int32_t i = 0; i < count; ++i) {
         if (rc[(size_t)i] != SIMM_OK) {
             for (int32_t j = 0; j < count; ++j) {

@@ -99,6 +99,7 @@ struct simm_shift_s {
     std::vector<cplx> ritz;     // sigma + 1/theta
     bool borrowed = false;      // owned by a simm_result
     bool factor_borrowed = false;   // AB, ipiv, LP, spike belong to another shift
+    bool sweeps_ready = false;      // spike holds the partitioned-sweep data of the factor
     SpikeFactor spike;          // partitioned-sweep data of the factor
     // frees the n-sized data (factor, sweep data, Krylov basis); the small per-shift
     // data used by the indicators stays
@@ -399,12 +400,31 @@ simm_status factor_shift(simm_pencil_s* p, cplx sigma, hipStream_t st, std::uniq
     return SIMM_OK;
 }
 
+// Partitioned-sweep data of a shift's factor (a launch wide enough to fill the
+// device).  Synchronous on return.
+simm_status prepare_sweeps(simm_shift_s* s, hipStream_t st, KernelClock* clk = nullptr) {
+    s->spike.n = s->p->n;
+    s->spike.kl = s->kl;
+    s->spike.ku = s->ku;
+    s->spike.AB = s->AB;
+    s->spike.ipiv = s->ipiv;
+    s->spike.LP = s->LP;
+    {
+        KScope ks(clk, SIMM_K_SPIKE_PREP);
+        SIMM_TRY(spike_prepare(s->spike, st));
+    }
+    SIMM_HIP_TRY(hipStreamSynchronize(st));
+    s->sweeps_ready = true;
+    return SIMM_OK;
+}
+
 // Krylov phase of one shift (hot-path steps a3-a5) on a factored shift: the
 // partitioned-sweep data of the factor (a launch wide enough to fill the device, so
 // it runs here rather than beside other work), b, beta, the Arnoldi basis V_{m+1}
 // and H_{m+1,m}, and the Schur data of H_m.
 simm_status krylov_shift(simm_shift_s* s, const cplx* f_dev, int m, hipStream_t st, int64_t* applies,
-                         KernelClock* clk = nullptr, const std::atomic<bool>* cancel = nullptr) {
+                         KernelClock* clk = nullptr, const std::atomic<bool>* cancel = nullptr,
+                         const std::function<void()>* before_schur = nullptr) {
     simm_pencil_s* p = s->p;
     const cplx sigma = s->sigma;
     s->m = m;
@@ -414,17 +434,8 @@ simm_status krylov_shift(simm_shift_s* s, const cplx* f_dev, int m, hipStream_t 
         return SIMM_ECANCELED;
     }
     // partitioned-sweep data (unit-state responses of every chunk), unless the
-    // factor comes prepared from another shift
-    if (!s->factor_borrowed) {
-        s->spike.n = n;
-        s->spike.kl = s->kl;
-        s->spike.ku = s->ku;
-        s->spike.AB = s->AB;
-        s->spike.ipiv = s->ipiv;
-        s->spike.LP = s->LP;
-        KScope ks(clk, SIMM_K_SPIKE_PREP);
-        SIMM_TRY(spike_prepare(s->spike, st));
-    }
+    // factor comes prepared (from another shift, or earlier on another stream)
+    if (!s->factor_borrowed && !s->sweeps_ready) SIMM_TRY(prepare_sweeps(s, st, clk));
     SIMM_TRY(dalloc(&s->V, (size_t)n * (m + 1)));
     SIMM_TRY(dalloc(&s->H, (size_t)(m + 1) * m));
     SIMM_HIP_TRY(hipMemsetAsync(s->H, 0, sizeof(cplx) * (m + 1) * m, st));
@@ -514,7 +525,8 @@ simm_status krylov_shift(simm_shift_s* s, const cplx* f_dev, int m, hipStream_t 
     for (int j = 0; j < me; ++j)
         for (int i = 0; i <= me; ++i) s->H_host[i + (size_t)j * (me + 1)] = Hfull[i + (size_t)j * (m + 1)];
     s->h_last = cabs(s->H_host[me + (size_t)(me - 1) * (me + 1)]);
-    // a5: Schur form of H_m
+    // a5: Schur form of H_m (one wavefront: the caller may start other work beside it)
+    if (before_schur) (*before_schur)();
     SIMM_TRY(dalloc(&s->T, (size_t)me * (me + 1) / 2));
     SIMM_TRY(dalloc(&s->Q, (size_t)me * me));
     SIMM_TRY(dalloc(&s->g, (size_t)me));
@@ -720,84 +732,96 @@ struct Timer {
 };
 
 // A shift built ahead of the association order (steps 2-3), by a host thread of its
-// own on a stream of its own: always its factor phase, and its Krylov phase too if
-// asked for (before or after the factor is done).  Joined (and its stream released)
-// on destruction, so no thread outlives the run that started it.
+// own on a stream of its own, in phases: 0 the factor, 1 the partitioned-sweep data,
+// 2 the Krylov phase.  The factor always runs; later phases run when asked for,
+// before or after the earlier ones are done.  Joined (and its stream released) on
+// destruction, so no thread outlives the run that started it.
 struct AheadBuild {
     std::thread th;
     std::mutex mu;
     std::unique_ptr<simm_shift_s> s;
-    simm_status rc = SIMM_OK;    // factor phase
-    simm_status krc = SIMM_OK;   // Krylov phase
+    simm_status rc = SIMM_OK;   // status of the last phase run
     std::string err;
     KernelClock clock;
     hipStream_t st = nullptr;
     std::atomic<bool> cancel{false};
     bool timed = false;
-    bool factor_done = false, krylov_wanted = false, krylov_started = false;
+    int want = 0;        // last phase asked for
+    int done = -1;       // last phase completed
+    bool running = false;
     int64_t applies = 0;
     const cplx* kf = nullptr;
     int km = 0;
     hipEvent_t kready = nullptr;
     int dev = 0;
+    simm_pencil_s* pen = nullptr;
+    cplx sigma{0, 0};
 
-    void run_krylov() {
-        hipError_t e = hipStreamWaitEvent(st, kready, 0);   // f is written on the run's stream
-        if (e != hipSuccess) {
-            krc = SIMM_EHIP;
-            err = std::string("hipStreamWaitEvent: ") + hipGetErrorString(e);
-            return;
-        }
-        krc = krylov_shift(s.get(), kf, km, st, &applies, timed ? &clock : nullptr, &cancel);
-        if (krc != SIMM_OK) err = g_err;
-    }
-    void start(simm_pencil_s* p, cplx sigma, bool timed_) {
-        timed = timed_;
-        dev = p->dev;
-        th = std::thread([this, p, sigma]() {
-            (void)hipSetDevice(dev);
+    simm_status run_phase(int ph) {
+        if (ph == 0) {
             const hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
             if (e != hipSuccess) {
                 st = nullptr;
-                rc = SIMM_EHIP;
-                err = std::string("stream for a shift built ahead: ") + hipGetErrorString(e);
-            } else {
-                clock.st = st;
-                rc = factor_shift(p, sigma, st, s, timed ? &clock : nullptr, &cancel);
-                if (rc != SIMM_OK) err = g_err;
+                set_error(std::string("stream for a shift built ahead: ") + hipGetErrorString(e));
+                return SIMM_EHIP;
             }
-            bool go = false;
+            clock.st = st;
+            return factor_shift(pen, sigma, st, s, timed ? &clock : nullptr, &cancel);
+        }
+        if (ph == 1) return prepare_sweeps(s.get(), st, timed ? &clock : nullptr);
+        SIMM_HIP_TRY(hipStreamWaitEvent(st, kready, 0));   // f is written on the run's stream
+        return krylov_shift(s.get(), kf, km, st, &applies, timed ? &clock : nullptr, &cancel);
+    }
+    void thread_main() {
+        (void)hipSetDevice(dev);
+        for (;;) {
+            int ph;
             {
                 std::lock_guard<std::mutex> lk(mu);
-                factor_done = true;
-                if (krylov_wanted && rc == SIMM_OK) krylov_started = go = true;
+                if (rc != SIMM_OK || done >= want) {
+                    running = false;
+                    return;
+                }
+                ph = done + 1;
             }
-            if (go) run_krylov();
-        });
+            const simm_status r = run_phase(ph);
+            std::lock_guard<std::mutex> lk(mu);
+            rc = r;
+            if (r != SIMM_OK) err = g_err;
+            else done = ph;
+        }
     }
-    // asks for the Krylov phase (start vector f written on the run's stream before `ready`)
-    void request_krylov(const cplx* f, int m, hipEvent_t ready) {
+    void start(simm_pencil_s* p, cplx sig, bool timed_) {
+        timed = timed_;
+        dev = p->dev;
+        pen = p;
+        sigma = sig;
+        running = true;
+        th = std::thread([this]() { thread_main(); });
+    }
+    // asks for phases up to `level` (2: the Krylov phase, start vector f written on
+    // the run's stream before `ready`)
+    void request(int level, const cplx* f = nullptr, int m = 0, hipEvent_t ready = nullptr) {
         bool spawn = false;
         {
             std::lock_guard<std::mutex> lk(mu);
-            if (krylov_wanted) return;
-            krylov_wanted = true;
-            kf = f;
-            km = m;
-            kready = ready;
-            if (factor_done && rc == SIMM_OK && !krylov_started) krylov_started = spawn = true;
+            if (level <= want) return;
+            want = level;
+            if (level >= 2) {
+                kf = f;
+                km = m;
+                kready = ready;
+            }
+            if (!running && rc == SIMM_OK) running = spawn = true;
         }
-        if (spawn) {   // the factor thread has finished its work: run the Krylov phase on a new one
+        if (spawn) {   // the thread has finished what it was asked for: run the rest on a new one
             if (th.joinable()) th.join();
-            th = std::thread([this]() {
-                (void)hipSetDevice(dev);
-                run_krylov();
-            });
+            th = std::thread([this]() { thread_main(); });
         }
     }
-    bool krylov_requested() {
+    int wanted() {
         std::lock_guard<std::mutex> lk(mu);
-        return krylov_wanted;
+        return want;
     }
     // waits for the build; its kernel times go to (ms, cnt) if those are given
     void finish(double* ms = nullptr, int64_t* cnt = nullptr) {
@@ -809,8 +833,6 @@ struct AheadBuild {
             st = nullptr;
         }
     }
-    // true when both phases ran and succeeded
-    bool complete() const { return rc == SIMM_OK && krylov_started && krc == SIMM_OK; }
     ~AheadBuild() { finish(); }
 };
 
@@ -989,14 +1011,14 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
             b->start(p, cell_center(prm, 1, cells[d].first, cells[d].second), clk != nullptr);
             it = ahead.emplace(d, std::move(b)).first;
         }
-        it->second->request_krylov(f_dev, m, ready);
+        it->second->request(2, f_dev, m, ready);
     };
     // Krylov phases ahead for the cells predicted after `cur` (cur = -1: before any cell)
     auto predict_ahead = [&](int64_t cur, bool guess_far_from_centre) {
         if (KA == 0) return;
         int inflight = 0;
         for (auto& kv : ahead)
-            if (kv.first > cur && kv.second->krylov_requested()) ++inflight;
+            if (kv.first > cur && kv.second->wanted() >= 2) ++inflight;
         const bool skip_nb = cur >= 0 && (nb_seen == 0 || 2 * nb_hits > nb_seen);
         const cplx c0{(prm->x0 + prm->x1) / 2, (prm->y0 + prm->y1) / 2};
         const double w1 = (prm->x1 - prm->x0) / prm->n1;
@@ -1010,7 +1032,7 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
             for (int64_t q : picked) skip = skip || (skip_nb && neighbours(q, d));
             if (skip) continue;
             auto it = ahead.find(d);
-            if (it != ahead.end() && it->second->krylov_requested()) continue;
+            if (it != ahead.end() && it->second->wanted() >= 2) continue;
             request_ahead(d);
             picked.push_back(d);
             ++inflight;
@@ -1068,12 +1090,12 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
                 ahead.erase(c);
                 if (b) {
                     b->finish(clk ? R->kms : nullptr, clk ? R->kcnt : nullptr);
-                    if (b->complete()) {
+                    if (b->rc == SIMM_OK && b->done >= 2) {
                         s = std::move(b->s);
                         R->counters[2] += b->applies;
                         built = true;
-                    } else if (b->rc == SIMM_OK && !b->krylov_started) {
-                        s = std::move(b->s);
+                    } else if (b->rc == SIMM_OK && b->done >= 0) {
+                        s = std::move(b->s);   // factor (and maybe sweep data) only
                     }
                 }
                 R->ms[0] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -1086,8 +1108,20 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
                 SIMM_TRY(factor_shift(p, ctr, st, s, clk));
             }
             if (!built) {
+                // while this shift's Schur form runs (one wavefront), the sweep data of
+                // the cell predicted to need a shift next is prepared on its stream
+                const std::function<void()> prep_next = [&]() {
+                    if (W <= 1) return;
+                    const bool skip_nb = nb_seen == 0 || 2 * nb_hits > nb_seen;
+                    for (int64_t d = c + 1; d < ncell; ++d) {
+                        if (!unresolved(d) || (skip_nb && neighbours(c, d))) continue;
+                        auto it = ahead.find(d);
+                        if (it != ahead.end()) it->second->request(1);
+                        break;
+                    }
+                };
                 Timer t(st, &R->ms[0]);
-                SIMM_TRY(krylov_shift(s.get(), f_dev, m, st, &R->counters[2], clk));
+                SIMM_TRY(krylov_shift(s.get(), f_dev, m, st, &R->counters[2], clk, nullptr, &prep_next));
             }
             // neighbours of c after it that no shift resolved before this one
             std::vector<int64_t> nb;

@@ -25,11 +25,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 # Hardware queues of the process (read by the HIP runtime when it starts; its default
-# is 4).  The driver computes one LU factor ahead per queue beyond the run's own,
-# and streams beyond the queue count share queues and serialise: 8 queues give 7
-# factors in flight (measured best on the n = 40,000 workload: 3 -> 7 ahead took
-# the step from ~1,000 to ~875 ms).
-HW_QUEUES = 8
+# is 4).  The driver computes one LU factor ahead per queue beyond the run's own (at
+# most 11), and streams beyond the queue count share queues and serialise.  Medians
+# of 6 steps on the n = 40,000 workload: 7 ahead with 8 queues ~860-930 ms, 11 ahead
+# with 12 queues ~825 ms, 11-15 ahead with 16 queues 843-864 ms.
+HW_QUEUES = 12
 os.environ["GPU_MAX_HW_QUEUES"] = str(HW_QUEUES)
 
 METRIC = "resolvent solves/s + indicators/s at n=40k; speedup vs plain FP64 at 1e-6"

@@ -120,9 +120,10 @@ typedef struct {
     double tau;                 /* floor: admissible needs ||s_f|| > tau * T_f (default 1e-8)    */
     int64_t max_regions_per_level; /* guard against refinement blow-up (default 1<<22)          */
     uint32_t flags;             /* SIMM_FLAG_*                                                   */
-    int32_t lookahead;          /* level-1 association: shifts built ahead of the cell order, at
-                                   most this many at once on streams of their own (0: default 4,
-                                   1: one at a time, at most 16).  Only the shifts the cell order
+    int32_t lookahead;          /* level-1 association: LU factors computed ahead of the cell
+                                   order, at most this many at once on streams of their own (0:
+                                   one less than GPU_MAX_HW_QUEUES (4 unless set), at most 11;
+                                   1: one at a time; at most 16).  Only the shifts the cell order
                                    creates are kept, so results do not depend on it              */
 } simm_params;
 

@@ -838,15 +838,15 @@ struct AheadBuild {
 
 // Number of shift factors the association may compute ahead: the requested
 // look-ahead (default: one per hardware queue the HIP runtime gives the process,
-// GPU_MAX_HW_QUEUES, 4 unless set, less the run's own; more streams than queues
-// share a queue and run one after the other), cut so that the factors take at
-// most a quarter of the free device memory.
+// GPU_MAX_HW_QUEUES, 4 unless set, less the run's own, at most 11; more streams
+// than queues share a queue and run one after the other), cut so that the factors
+// take at most a quarter of the free device memory.
 int lookahead_width(const simm_params* prm, const simm_pencil_s* p) {
     int w = prm->lookahead;
     if (w <= 0) {
         int queues = 4;
         if (const char* e = std::getenv("GPU_MAX_HW_QUEUES")) queues = std::max(1, std::atoi(e));
-        w = std::min(8, std::max(1, queues - 1));
+        w = std::min(11, std::max(1, queues - 1));
     }
     if (w <= 1) return 1;
     size_t free_b = 0, total_b = 0;

@@ -271,6 +271,14 @@ def main():
     apply_ms = kms["band_sweep"] / max(kcnt["band_sweep"], 1)
     apply_gbs = b_apply / (apply_ms / 1e3) / 1e9
     step_kernel_ms = {k: kms[k] / args.steps for k in kms}
+    # shifted solves: the triangular system (I + (sigma - z) T) y = g of one quadrature
+    # point is m^2 / 2 complex multiply-adds, 4 m^2 real flops (every shift of this
+    # workload keeps m_eff = m)
+    m = params["m"]
+    ind_tflops = 4.0 * m * m * n_qp / (kms["indicators"] / args.steps * 1e-3) / 1e12 if kms["indicators"] > 0 else 0.0
+    # X = V_m Y: 8 n m flops per column, two columns (s_c, s_f) per square
+    proj_flops = 8.0 * n * m * 2 * n_sq
+    proj_tflops = proj_flops / (kms["project"] / args.steps * 1e-3) / 1e12 if kms["project"] > 0 else 0.0
     out = {
         "metric": METRIC,
         "value": value,
@@ -317,6 +325,27 @@ def main():
             "bytes_per_launch": b_apply,
             "ms_per_launch": apply_ms,
             "launches_per_step": kcnt["band_sweep"] // args.steps,
+        },
+        "roofline_indicators": {
+            "kernel": "k_indicators (shifted solves, sums, residuals and decisions of a batch of squares)",
+            "bound": "alu",
+            "achieved": ind_tflops,
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": ind_tflops / FP64_PEAK_TFLOPS,
+            "flops_per_point": 4 * m * m,
+            "points_per_step": n_qp,
+            "ms_per_step": kms["indicators"] / args.steps,
+        },
+        "roofline_project": {
+            "kernel": "k_vmy (X = V_m Y on the FP64 matrix cores, with column norms)",
+            "bound": "mfma",
+            "achieved": proj_tflops,
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": proj_tflops / FP64_PEAK_TFLOPS,
+            "flops_per_step": proj_flops,
+            "ms_per_step": kms["project"] / args.steps,
         },
         "kernel_ms_per_step": step_kernel_ms,
     }

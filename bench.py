@@ -194,6 +194,8 @@ def main():
     ap.add_argument("--workload", default="cfg1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mult-k", type=int, default=4, help="start vectors for the multiplicity step (0: skip)")
+    ap.add_argument("--project-c", type=int, default=1600,
+                    help="columns of the full-level projection measured after the steps (0: skip)")
     ap.add_argument("--workers", type=int, default=4, help="runs in flight in the batched form")
     ap.add_argument("--batch-lookahead", type=int, default=0,
                     help="look-ahead of each run in the batched form (0: the batch default, one at a time)")
@@ -349,6 +351,35 @@ def main():
         },
         "kernel_ms_per_step": step_kernel_ms,
     }
+    if args.project_c > 0:
+        # X = V_m Y alone at a level's full width (c columns: s_c and s_f of c/2 squares)
+        # on the first shift's basis, outside the timed step; HIP events on torch's stream
+        c = args.project_c
+        sh = last.shift(0)
+        me = sh.info()["m_eff"]
+        g = torch.Generator(device="cpu").manual_seed(7)
+        Yd = torch.randn((c, me), dtype=torch.complex128, generator=g).to(dev)    # column-major Y
+        Xd = torch.empty((c, pen.n), dtype=torch.complex128, device=dev)
+        nd = torch.empty(c, dtype=torch.float64, device=dev)
+        for _ in range(2):
+            S.simm_project(sh, Yd.T, Xd.T, nd)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        e0.record()
+        for _ in range(reps):
+            S.simm_project(sh, Yd.T, Xd.T, nd)
+        e1.record()
+        torch.cuda.synchronize()
+        pms = e0.elapsed_time(e1) / reps
+        pfl = 8.0 * pen.n * me * c
+        out["roofline_project_full_level"] = {
+            "kernel": f"k_vmy + column norms, n = {pen.n}, m = {me}, c = {c}",
+            "bound": "mfma", "achieved": pfl / (pms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": pfl / (pms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, "ms_per_launch": pms,
+            "flops_per_launch": pfl,
+        }
+        log(f"projection c = {c}: {pms:.3f} ms")
+        del Xd
     if args.mult_k > 0:
         # multiplicities (Sec. 3.4) of the step's clusters from k further start vectors,
         # outside the timed step: k Krylov spaces per shift on the kept factors

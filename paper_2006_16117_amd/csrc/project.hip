@@ -58,50 +58,62 @@ __global__ __launch_bounds__(PJ_THREADS) void k_vmy(int64_t n, int m, const cplx
             Ys[e] = (jj < sc) ? Y[k + (s0 + jj) * ldy] : mk(0.0, 0.0);
         }
         __syncthreads();
-        for (int jt = 0; jt < sc; jt += 8) {
+        // four independent 8-column tiles per pass, so that four accumulation chains
+        // of dependent MFMAs interleave
+        for (int jt = 0; jt < sc; jt += 32) {
             // The f64 16x16x4 instruction leaves output row jj of the tile in register jj/4 of the lanes
             // with lane/16 = jj%4.  Row jj of the A operand (= Ybig^T tile, lane row li) is therefore
-            // mapped to column j = jt + 2 (jj%4) + (jj/4)/2 and part (jj/4)%2, so that lane group kq ends up
-            // holding (re, im) of columns jt + 2 kq and jt + 2 kq + 1 in registers 0..3.
+            // mapped to column j = jt + 8u + 2 (jj%4) + (jj/4)/2 and part (jj/4)%2, so that lane group kq
+            // ends up holding (re, im) of columns jt + 8u + 2 kq and jt + 8u + 2 kq + 1 in registers 0..3.
             // A operand: k = 2q + kq/2, part kq%2.
-            const int jloc = jt + 2 * (li & 3) + ((li >> 2) >> 1);
+            const int jl0 = jt + 2 * (li & 3) + ((li >> 2) >> 1);
             const int op = (li >> 2) & 1;
             const int pp = kq & 1;
-            d4 acc = {0.0, 0.0, 0.0, 0.0};
+            d4 acc[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int q = 0; q < MAXQ; ++q) {
                 if (q < nq) {
                     const int k = 2 * q + (kq >> 1);
-                    double a = 0.0;
-                    if (k < m && jloc < sc) {
-                        const cplx y = Ys[k + jloc * m];
-                        a = (pp == 0) ? (op == 0 ? y.re : y.im) : (op == 0 ? -y.im : y.re);
-                    }
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, vreg[q], acc, 0, 0, 0);
-                }
-            }
-            // acc: lane (li, kq), reg r -> tile row jj = kq + 4 r: column j = jt + 2 kq + r/2, part r%2;
-            // tile column li -> row i of X.
-            const int64_t jA = s0 + jt + 2 * kq;
-            const int64_t jB = jA + 1;
-            const cplx xa = mk(acc[0], acc[1]);
-            const cplx xb = mk(acc[2], acc[3]);
-            if (i < n) {
-                if (jt + 2 * kq < sc) X[i + jA * n] = xa;
-                if (jt + 2 * kq + 1 < sc) X[i + jB * n] = xb;
-            }
-            if (colpart != nullptr) {
-                double pa = (i < n) ? norm2(xa) : 0.0;
-                double pb = (i < n) ? norm2(xb) : 0.0;
-                // sum over the 16 rows (lanes li = 0..15 of the same kq group)
 #pragma unroll
-                for (int msk = 8; msk >= 1; msk >>= 1) {
-                    pa += __shfl_xor(pa, msk, 64);
-                    pb += __shfl_xor(pb, msk, 64);
+                    for (int u = 0; u < 4; ++u) {
+                        const int jloc = jl0 + 8 * u;
+                        double a = 0.0;
+                        if (k < m && jloc < sc) {
+                            const cplx y = Ys[k + jloc * m];
+                            a = (pp == 0) ? (op == 0 ? y.re : y.im) : (op == 0 ? -y.im : y.re);
+                        }
+                        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, vreg[q], acc[u], 0, 0, 0);
+                    }
                 }
-                if (li == 0) {
-                    if (jt + 2 * kq < sc) colpart[wg_wave * c + jA] = pa;
-                    if (jt + 2 * kq + 1 < sc) colpart[wg_wave * c + jB] = pb;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                // acc[u]: lane (li, kq), reg r -> tile row jj = kq + 4 r: column j = jt + 8u + 2 kq + r/2,
+                // part r%2; tile column li -> row i of X.
+                const int jc = jt + 8 * u + 2 * kq;
+                const int64_t jA = s0 + jc;
+                const int64_t jB = jA + 1;
+                const cplx xa = mk(acc[u][0], acc[u][1]);
+                const cplx xb = mk(acc[u][2], acc[u][3]);
+                if (i < n) {
+                    if (jc < sc) X[i + jA * n] = xa;
+                    if (jc + 1 < sc) X[i + jB * n] = xb;
+                }
+                if (colpart != nullptr) {
+                    double pa = (i < n) ? norm2(xa) : 0.0;
+                    double pb = (i < n) ? norm2(xb) : 0.0;
+                    // sum over the 16 rows (lanes li = 0..15 of the same kq group)
+#pragma unroll
+                    for (int msk = 8; msk >= 1; msk >>= 1) {
+                        pa += __shfl_xor(pa, msk, 64);
+                        pb += __shfl_xor(pb, msk, 64);
+                    }
+                    if (li == 0) {
+                        if (jc < sc) colpart[wg_wave * c + jA] = pa;
+                        if (jc + 1 < sc) colpart[wg_wave * c + jB] = pb;
+                    }
                 }
             }
         }

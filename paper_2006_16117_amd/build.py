@@ -22,6 +22,12 @@ FLAGS = [
 ]
 
 
+# per-source flags: the projection keeps its matrix-core accumulators in ordinary vector
+# registers (with the default split the loop copied all of them between register files
+# every stage, and occupancy fell to one wavefront per SIMD)
+EXTRA = {"project.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def build_library(verbose: bool = False, jobs: int = 8) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
@@ -31,7 +37,7 @@ def build_library(verbose: bool = False, jobs: int = 8) -> str:
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
         objs.append(obj)
-        cmd = [HIPCC, *FLAGS, *inc, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), *inc, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

@@ -1,15 +1,24 @@
 // Projection X = V_m Y of the quadrature sums back to C^n (Sec. 2, eq. (reduced);
 // the full-space vectors P_R f of the RIM-C indicator, eq. (ISPf)).
 //
-// Complex GEMM on the FP64 matrix cores through a real embedding: with
-// K = 2m real inner index (k, part) and 2c real output columns (j, outpart),
+// Complex GEMM on the FP64 matrix cores through a real embedding: with a real
+// inner index (k, p) (complex index k, part p) and real output columns (j, o),
 //   X_real(i, (j,o)) = sum_{(k,p)} V_real(i, (k,p)) Ybig((k,p), (j,o)),
-//   Ybig = [[Yr, Yi], [-Yi, Yr]]  (per (k, j) 2x2 block).
-// Each wavefront computes X^T tiles with v_mfma_f64_16x16x4f64: the 16 columns of
-// the instruction's output span 16 consecutive rows i of X, so every lane ends up
-// with both parts of X(i, j) for two columns j and stores 16-byte complex values,
-// contiguous across lanes.  The wavefront's 16-row panel of V stays in registers
-// (one double per lane per 4-deep K step) while Y streams from LDS.
+//   Ybig = [[Yr, Yi], [-Yi, Yr]]  (per (k, j) 2x2 block),
+// i.e. 8 n m c real flops.  The instruction v_mfma_f64_16x16x4f64 computes X^T
+// tiles: its 16 output columns are 16 consecutive rows i of X, so every lane ends
+// up with both parts of X(i, j) for two columns j and stores 16-byte complex
+// values, contiguous across lanes.
+//
+// Tiling: a workgroup of four wavefronts owns a 128 x 64 (complex) block of X; each
+// wavefront a 64 x 32 block, i.e. 4 x 4 instruction tiles held in 16 accumulators,
+// so every operand read from LDS feeds four instructions.  The inner dimension is
+// staged through LDS 8 complex indices at a time (double-buffered, the next stage
+// loaded into registers while the current one is multiplied).  Each lane reads one
+// complex value per operand and uses its real part in one 4-deep step and its
+// imaginary part in the next.  Blocks are ordered so that each XCD (workgroups are
+// dealt to the eight XCDs in turn) walks a contiguous range of row blocks, all
+// column blocks of a row block in a row: that row block of V stays in the XCD's L2.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -18,109 +27,146 @@ namespace simm {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));   // (re, im) in LDS: selects stay on values
 
 constexpr int PJ_THREADS = 256;
-constexpr int PJ_WAVES = PJ_THREADS / 64;
-constexpr int MAXQ = 64;          // K steps of 4 reals (2 complex): m <= 128
-constexpr int YCOLS = 64;         // columns of Y staged in LDS at a time
+constexpr int PJ_ROWS = 128;            // rows of X per workgroup (2 wavefronts x 64)
+constexpr int PJ_COLS = 64;             // complex columns of X per workgroup (2 wavefronts x 32)
+constexpr int PJ_KC = 8;                // complex inner indices per LDS stage
+constexpr int PJ_YLD = PJ_COLS + 1;     // padded LDS row of a Y stage (conflict-free staging writes)
+constexpr int PJ_XCDS = 8;
 
 }  // namespace
 
 __global__ __launch_bounds__(PJ_THREADS) void k_vmy(int64_t n, int m, const cplx* __restrict__ V, int64_t ldv,
                                                     const cplx* __restrict__ Y, int64_t ldy, int64_t c,
-                                                    cplx* __restrict__ X, double* __restrict__ colpart) {
-    extern __shared__ cplx Ys[];   // m x YCOLS
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int li = lane & 15, kq = lane >> 4;
-    const int64_t wg_wave = (int64_t)blockIdx.x * PJ_WAVES + wave;
-    const int64_t i0 = wg_wave * 16;
-    const int64_t i = i0 + li;
-    const int nq = (m + 1) / 2;
+                                                    int64_t gx, int64_t gy, cplx* __restrict__ X,
+                                                    double* __restrict__ colpart) {
+    __shared__ d2 Vs[2][PJ_KC][PJ_ROWS];
+    __shared__ d2 Ys[2][PJ_KC][PJ_YLD];
+    const int64_t T = gx * gy, per = (T + PJ_XCDS - 1) / PJ_XCDS;
+    const int64_t t = (int64_t)(blockIdx.x % PJ_XCDS) * per + blockIdx.x / PJ_XCDS;
+    if (t >= T) return;   // uniform over the workgroup
+    const int64_t rb = t / gy;
+    const int64_t i0 = rb * PJ_ROWS, j0 = (t % gy) * PJ_COLS;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, kk = lane >> 4;
+    const int wi = wave & 1, wj = wave >> 1;
 
-    // V panel: lane (li, kq) holds V(i, k = 2q + kq/2), part kq%2, for each q
-    double vreg[MAXQ];
+    // staging: thread -> V rows vr of inner indices vk + 2q (q < 4), Y inner index yk of columns yj + 32q (q < 2)
+    const int vr = tid & (PJ_ROWS - 1), vk = tid >> 7;
+    const int yk = tid & (PJ_KC - 1), yj = tid >> 3;
+    const bool vrow = i0 + vr < n;
+    const int64_t vrc = min(i0 + vr, n - 1);
+    cplx gv[4], gw[2];
+    // loads are unconditional (indices outside the operands are clamped into them) and the
+    // values are zeroed afterwards, so that no load sits in a branch
+    auto fetch = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < MAXQ; ++q) {
-        double v = 0.0;
-        const int k = 2 * q + (kq >> 1);
-        if (q < nq && k < m && i < n) {
-            const cplx x = V[i + (int64_t)k * ldv];
-            v = (kq & 1) ? x.im : x.re;
+        for (int q = 0; q < 4; ++q) {
+            const int k = k0 + vk + 2 * q;
+            gv[q] = csel(vrow && k < m, V[vrc + (int64_t)min(k, m - 1) * ldv], mk(0.0, 0.0));
         }
-        vreg[q] = v;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int k = k0 + yk;
+            const int64_t j = j0 + yj + 32 * q;
+            gw[q] = csel(k < m && j < c, Y[min(k, m - 1) + min(j, c - 1) * ldy], mk(0.0, 0.0));
+        }
+    };
+    auto stage = [&](int b) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Vs[b][vk + 2 * q][vr] = d2{gv[q].re, gv[q].im};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) Ys[b][yk][yj + 32 * q] = d2{gw[q].re, gw[q].im};
+    };
+
+    // A operand row li of a tile <-> column 2 (li % 4) + li / 8 of its 8, part (li / 4) % 2: the
+    // instruction leaves output row r in register r / 4 of lane group r % 4, so lane group g then
+    // holds (re, im) of columns 2g and 2g + 1 in registers 0..3.
+    const int ja = 2 * (li & 3) + (li >> 3);
+    const bool aim = (li >> 2) & 1;
+
+    d4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+
+    fetch(0);
+    stage(0);
+    __syncthreads();
+    const int nch = (m + PJ_KC - 1) / PJ_KC;
+    // The loop body has no branch (the stage after the last is fetched as zeros and written to
+    // the idle buffer), so the accumulators stay in the matrix-core registers across iterations.
+    for (int ch = 0; ch < nch; ++ch) {
+        const int b = ch & 1;
+        fetch((ch + 1) * PJ_KC);
+#pragma unroll
+        for (int kg = 0; kg < PJ_KC / 4; ++kg) {
+            // lane group kk supplies inner index 4 kg + kk of the stage
+            const int kl = 4 * kg + kk;
+            d2 vb[4], ya[4];
+#pragma unroll
+            for (int ti = 0; ti < 4; ++ti) vb[ti] = Vs[b][kl][wi * 64 + 16 * ti + li];
+#pragma unroll
+            for (int tj = 0; tj < 4; ++tj) ya[tj] = Ys[b][kl][wj * 32 + 8 * tj + ja];
+            // real part of the inner index: Ybig row (k, 0) = (Yr, Yi)
+#pragma unroll
+            for (int tj = 0; tj < 4; ++tj) {
+                const double a = aim ? ya[tj].y : ya[tj].x;
+#pragma unroll
+                for (int ti = 0; ti < 4; ++ti)
+                    acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, vb[ti].x, acc[ti][tj], 0, 0, 0);
+            }
+            // imaginary part: Ybig row (k, 1) = (-Yi, Yr)
+#pragma unroll
+            for (int tj = 0; tj < 4; ++tj) {
+                const double a = aim ? ya[tj].x : -ya[tj].y;
+#pragma unroll
+                for (int ti = 0; ti < 4; ++ti)
+                    acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, vb[ti].y, acc[ti][tj], 0, 0, 0);
+            }
+        }
+        stage(b ^ 1);
+        __syncthreads();
     }
 
-    for (int64_t s0 = 0; s0 < c; s0 += YCOLS) {
-        const int sc = (int)min((int64_t)YCOLS, c - s0);
-        __syncthreads();
-        for (int e = threadIdx.x; e < m * YCOLS; e += PJ_THREADS) {
-            const int k = e % m, jj = e / m;
-            Ys[e] = (jj < sc) ? Y[k + (s0 + jj) * ldy] : mk(0.0, 0.0);
-        }
-        __syncthreads();
-        // four independent 8-column tiles per pass, so that four accumulation chains
-        // of dependent MFMAs interleave
-        for (int jt = 0; jt < sc; jt += 32) {
-            // The f64 16x16x4 instruction leaves output row jj of the tile in register jj/4 of the lanes
-            // with lane/16 = jj%4.  Row jj of the A operand (= Ybig^T tile, lane row li) is therefore
-            // mapped to column j = jt + 8u + 2 (jj%4) + (jj/4)/2 and part (jj/4)%2, so that lane group kq
-            // ends up holding (re, im) of columns jt + 8u + 2 kq and jt + 8u + 2 kq + 1 in registers 0..3.
-            // A operand: k = 2q + kq/2, part kq%2.
-            const int jl0 = jt + 2 * (li & 3) + ((li >> 2) >> 1);
-            const int op = (li >> 2) & 1;
-            const int pp = kq & 1;
-            d4 acc[4];
+    // acc[ti][tj]: lane (li, kk), registers (0,1) = X(i, jA), (2,3) = X(i, jA + 1) with
+    // i = i0 + 64 wi + 16 ti + li, jA = j0 + 32 wj + 8 tj + 2 kk
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acc[u] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int tj = 0; tj < 4; ++tj) {
+        const int64_t jA = j0 + wj * 32 + 8 * tj + 2 * kk;
+        double pa = 0.0, pb = 0.0;
 #pragma unroll
-            for (int q = 0; q < MAXQ; ++q) {
-                if (q < nq) {
-                    const int k = 2 * q + (kq >> 1);
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int jloc = jl0 + 8 * u;
-                        double a = 0.0;
-                        if (k < m && jloc < sc) {
-                            const cplx y = Ys[k + jloc * m];
-                            a = (pp == 0) ? (op == 0 ? y.re : y.im) : (op == 0 ? -y.im : y.re);
-                        }
-                        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, vreg[q], acc[u], 0, 0, 0);
-                    }
-                }
+        for (int ti = 0; ti < 4; ++ti) {
+            const int64_t i = i0 + wi * 64 + 16 * ti + li;
+            const cplx xa = mk(acc[ti][tj][0], acc[ti][tj][1]);
+            const cplx xb = mk(acc[ti][tj][2], acc[ti][tj][3]);
+            if (i < n) {
+                if (jA < c) X[i + jA * n] = xa;
+                if (jA + 1 < c) X[i + (jA + 1) * n] = xb;
+                pa += norm2(xa);
+                pb += norm2(xb);
             }
+        }
+        if (colpart != nullptr) {
+            // sum over the 16 lanes li of the group: the wavefront's 64 rows
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                // acc[u]: lane (li, kq), reg r -> tile row jj = kq + 4 r: column j = jt + 8u + 2 kq + r/2,
-                // part r%2; tile column li -> row i of X.
-                const int jc = jt + 8 * u + 2 * kq;
-                const int64_t jA = s0 + jc;
-                const int64_t jB = jA + 1;
-                const cplx xa = mk(acc[u][0], acc[u][1]);
-                const cplx xb = mk(acc[u][2], acc[u][3]);
-                if (i < n) {
-                    if (jc < sc) X[i + jA * n] = xa;
-                    if (jc + 1 < sc) X[i + jB * n] = xb;
-                }
-                if (colpart != nullptr) {
-                    double pa = (i < n) ? norm2(xa) : 0.0;
-                    double pb = (i < n) ? norm2(xb) : 0.0;
-                    // sum over the 16 rows (lanes li = 0..15 of the same kq group)
-#pragma unroll
-                    for (int msk = 8; msk >= 1; msk >>= 1) {
-                        pa += __shfl_xor(pa, msk, 64);
-                        pb += __shfl_xor(pb, msk, 64);
-                    }
-                    if (li == 0) {
-                        if (jc < sc) colpart[wg_wave * c + jA] = pa;
-                        if (jc + 1 < sc) colpart[wg_wave * c + jB] = pb;
-                    }
-                }
+            for (int msk = 8; msk >= 1; msk >>= 1) {
+                pa += __shfl_xor(pa, msk, 64);
+                pb += __shfl_xor(pb, msk, 64);
+            }
+            if (li == 0) {
+                const int64_t w = 2 * rb + wi;   // 64-row block of X
+                if (jA < c) colpart[w * c + jA] = pa;
+                if (jA + 1 < c) colpart[w * c + jA + 1] = pb;
             }
         }
     }
 }
 
-// Column norms from the per-wave partial sums: first CN_GROUPS groups of waves
+// Column norms from the per-64-row-block partial sums: first CN_GROUPS groups of blocks
 // each reduce their share for 64 columns (4 threads per column, LDS combine),
 // then one pass adds the groups and takes the square root.
 constexpr int CN_GROUPS = 32;
@@ -155,30 +201,34 @@ __global__ void k_colnorm_finish(const double* __restrict__ part, int64_t c, dou
 }
 
 int64_t project_scratch_elems(int64_t n, int64_t c) {
-    const int64_t nwaves = ((n + 15) / 16 + PJ_WAVES - 1) / PJ_WAVES * PJ_WAVES;
-    return (nwaves + CN_GROUPS) * c;
+    const int64_t nblk64 = 2 * ((n + PJ_ROWS - 1) / PJ_ROWS);   // 64-row blocks of the row-block grid
+    return (nblk64 + CN_GROUPS) * c;
 }
 
 simm_status project(int64_t n, int m, const cplx* V, int64_t ldv, const cplx* Y, int64_t ldy, int64_t c, cplx* X,
                     double* col_norms, double* scratch, int64_t scratch_elems, hipStream_t st) {
     if (c <= 0) return SIMM_OK;
-    if (m < 1 || m > 2 * MAXQ) {
-        set_error("Krylov dimension outside 1..128");
-        return SIMM_EUNSUPPORTED;
+    if (m < 1 || n < 1) {
+        set_error("projection needs n >= 1 and m >= 1");
+        return SIMM_EINVAL;
     }
-    const int64_t nw = (n + 15) / 16;
-    const int64_t nblk = (nw + PJ_WAVES - 1) / PJ_WAVES;
-    if (col_norms != nullptr && scratch_elems < (nblk * PJ_WAVES + CN_GROUPS) * c) {
+    const int64_t gx = (n + PJ_ROWS - 1) / PJ_ROWS, gy = (c + PJ_COLS - 1) / PJ_COLS;
+    const int64_t nblk64 = 2 * gx;
+    if (col_norms != nullptr && scratch_elems < (nblk64 + CN_GROUPS) * c) {
         set_error("projection scratch too small");
         return SIMM_EINVAL;
     }
-    const size_t lds = sizeof(cplx) * (size_t)m * YCOLS;
-    hipLaunchKernelGGL(k_vmy, dim3((unsigned)nblk), dim3(PJ_THREADS), lds, st, n, m, V, ldv, Y, ldy, c, X,
-                       col_norms ? scratch : nullptr);
+    const int64_t per = (gx * gy + PJ_XCDS - 1) / PJ_XCDS;
+    if (per * PJ_XCDS > 0x7fffffff) {
+        set_error("projection too large for one launch");
+        return SIMM_ELIMIT;
+    }
+    hipLaunchKernelGGL(k_vmy, dim3((unsigned)(per * PJ_XCDS)), dim3(PJ_THREADS), 0, st, n, m, V, ldv, Y, ldy, c, gx,
+                       gy, X, col_norms ? scratch : nullptr);
     if (col_norms != nullptr) {
-        double* part = scratch + nblk * PJ_WAVES * c;
+        double* part = scratch + nblk64 * c;
         hipLaunchKernelGGL(k_colnorm_partial, dim3((unsigned)((c + 63) / 64), CN_GROUPS), dim3(256), 0, st,
-                           (const double*)scratch, nblk * PJ_WAVES, c, part);
+                           (const double*)scratch, nblk64, c, part);
         hipLaunchKernelGGL(k_colnorm_finish, dim3((unsigned)((c + 127) / 128)), dim3(128), 0, st,
                            (const double*)part, c, col_norms);
     }

@@ -194,24 +194,36 @@ def test_indicators_match_oracle(S):
     say("  decision ties:", mism)
 
 
-def test_project_matches_numpy(S):
+@pytest.mark.parametrize("m", [37, 80])
+def test_project_matches_numpy(S, m):
+    """X = V_m Y on the matrix cores: ragged in every dimension (n = 5013 is 39 row blocks of
+    128 and 21 rows; c up to 150 spans three column blocks of 64; m = 37 leaves a partial
+    stage of 8 inner indices)."""
     import torch
     pen, f = random_band_pencil(5000 + 13, 3, 90, b_kind="tridiag")
-    say("project", "n=5013 m=37 c=45")
+    say("project", f"n=5013 m={m} c=1..150")
     P = S.Pencil.from_workload(pen)
-    sh = S.simm_shift_build(P, 0.2 + 0.1j, f, 37)
-    V = sh.basis()[:, :37]
+    sh = S.simm_shift_build(P, 0.2 + 0.1j, f, m)
+    V = sh.basis()[:, :m]
+    Vo = O.build_shift(pen, 0.2 + 0.1j, f, m).V[:, :m]       # the oracle's Krylov basis
     rng = np.random.default_rng(1)
-    for c in (1, 7, 45):
-        Y = rng.standard_normal((37, c)) + 1j * rng.standard_normal((37, c))
+    for c in (1, 7, 45, 64, 150):
+        Y = rng.standard_normal((m, c)) + 1j * rng.standard_normal((m, c))
         Yd = torch.from_numpy(np.ascontiguousarray(Y.T)).cuda()          # column-major storage
         Xd = torch.zeros((c, pen.n), dtype=torch.complex128, device="cuda")
         nd = torch.zeros(c, dtype=torch.float64, device="cuda")
         S.simm_project(sh, Yd.T, Xd.T, nd)
         torch.cuda.synchronize()
         X = Xd.cpu().numpy().T
+        # against the oracle's basis (the two Arnoldi processes agree to ~1e-12)
+        wo = Vo @ Y
+        assert np.linalg.norm(X - wo) <= 1e-9 * np.linalg.norm(wo), c
+        # the product's own arithmetic, on the library's basis
         want = V @ Y
-        assert np.linalg.norm(X - want) <= 1e-13 * np.linalg.norm(want)
+        assert np.linalg.norm(X - want) <= 1e-13 * np.linalg.norm(want), c
+        # every column on its own (a column block or a row block left out shows here)
+        err = np.linalg.norm(X - want, axis=0) / np.linalg.norm(want, axis=0)
+        assert err.max() <= 1e-13, (c, int(err.argmax()))
         assert np.allclose(nd.cpu().numpy(), np.linalg.norm(want, axis=0), rtol=1e-13, atol=0)
 
 

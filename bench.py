@@ -41,6 +41,8 @@ def log(*a):
 
 
 FP64_PEAK_TFLOPS = 78.6   # 256 CUs x 4 SIMDs x 16 FP64 FMA lanes x 2 flops x 2.4 GHz
+FP32_MFMA_PEAK_TFLOPS = 157.3   # dense FP32 matrix cores
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense BF16 matrix cores
 LU_PANEL = 16
 
 
@@ -353,33 +355,55 @@ def main():
     }
     if args.project_c > 0:
         # X = V_m Y alone at a level's full width (c columns: s_c and s_f of c/2 squares)
-        # on the first shift's basis, outside the timed step; HIP events on torch's stream
+        # on the first shift's basis, outside the timed step; HIP events on torch's stream.
+        # FP64 with X written (the roofline), then each precision with only the column
+        # norms formed (what a run needs), and the error of the reduced-precision norms.
         c = args.project_c
         sh = last.shift(0)
         me = sh.info()["m_eff"]
         g = torch.Generator(device="cpu").manual_seed(7)
         Yd = torch.randn((c, me), dtype=torch.complex128, generator=g).to(dev)    # column-major Y
         Xd = torch.empty((c, pen.n), dtype=torch.complex128, device=dev)
-        nd = torch.empty(c, dtype=torch.float64, device=dev)
-        for _ in range(2):
-            S.simm_project(sh, Yd.T, Xd.T, nd)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = 5
-        e0.record()
-        for _ in range(reps):
-            S.simm_project(sh, Yd.T, Xd.T, nd)
-        e1.record()
-        torch.cuda.synchronize()
-        pms = e0.elapsed_time(e1) / reps
         pfl = 8.0 * pen.n * me * c
+
+        def time_proj(X, prec, nd):
+            for _ in range(2):
+                S.simm_project(sh, Yd.T, X, nd, precision=prec)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 5
+            e0.record()
+            for _ in range(reps):
+                S.simm_project(sh, Yd.T, X, nd, precision=prec)
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        nd64 = torch.empty(c, dtype=torch.float64, device=dev)
+        pms = time_proj(Xd.T, S.SIMM_PROJ_FP64, nd64)
         out["roofline_project_full_level"] = {
-            "kernel": f"k_vmy + column norms, n = {pen.n}, m = {me}, c = {c}",
+            "kernel": f"k_vmy + column norms, n = {pen.n}, m = {me}, c = {c}, X written",
             "bound": "mfma", "achieved": pfl / (pms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": pfl / (pms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, "ms_per_launch": pms,
             "flops_per_launch": pfl,
         }
-        log(f"projection c = {c}: {pms:.3f} ms")
+        log(f"projection c = {c} FP64 with X: {pms:.3f} ms")
         del Xd
+        ref = None
+        prec_out = {}
+        for name, prec, peak in (("fp64", S.SIMM_PROJ_FP64, FP64_PEAK_TFLOPS),
+                                 ("fp32", S.SIMM_PROJ_FP32, FP32_MFMA_PEAK_TFLOPS),
+                                 ("bf16", S.SIMM_PROJ_BF16, BF16_MFMA_PEAK_TFLOPS)):
+            nd = torch.empty(c, dtype=torch.float64, device=dev)
+            ms = time_proj(None, prec, nd)
+            nrm = nd.cpu().numpy()
+            if ref is None:
+                ref = nrm
+            rel = float(np.max(np.abs(nrm - ref) / ref))
+            prec_out[name] = {"ms_per_launch": ms, "achieved_tflops": pfl / (ms * 1e-3) / 1e12,
+                              "peak_tflops": peak, "frac": pfl / (ms * 1e-3) / 1e12 / peak,
+                              "max_rel_err_col_norms_vs_fp64": rel}
+            log(f"projection c = {c} {name}, norms only: {ms:.3f} ms, max rel. error of the norms {rel:.2e}")
+        out["project_norms_only_by_precision"] = prec_out
     if args.mult_k > 0:
         # multiplicities (Sec. 3.4) of the step's clusters from k further start vectors,
         # outside the timed step: k Krylov spaces per shift on the kept factors

@@ -52,11 +52,22 @@ enum { SIMM_REJECTED = 0, SIMM_ADMISSIBLE = 1, SIMM_UNRESOLVED = 2 };
 enum {
     SIMM_FLAG_PROJECT = 1u,        /* form X = V_m Y for the squares of every level               */
     SIMM_FLAG_KERNEL_TIMING = 2u,  /* bracket every hot-path kernel launch with HIP events        */
-    SIMM_FLAG_RELEASE_FACTORS = 4u /* free every shift's factor, sweep data and Krylov basis when
+    SIMM_FLAG_RELEASE_FACTORS = 4u, /* free every shift's factor, sweep data and Krylov basis when
                                       the run ends (the result keeps the levels, clusters and each
                                       shift's sigma, beta, H and Schur data); simm_shift_apply,
                                       simm_shift_basis and simm_multiplicities on the result then
                                       return EINVAL.  For batches of large pencils.               */
+    SIMM_FLAG_MIXED_PROJECT = 8u   /* with SIMM_FLAG_PROJECT: levels 1-2 project in BF16, later
+                                      levels in FP32 (FP32 accumulation); every decision, solve
+                                      and sum stays FP64, so only the full-space indicator record
+                                      (simm_result_full_indicators) changes                       */
+};
+
+/* Arithmetic of simm_project. */
+enum {
+    SIMM_PROJ_FP64 = 0,            /* FP64 matrix cores                                            */
+    SIMM_PROJ_FP32 = 1,            /* V, Y rounded to FP32, FP32 matrix cores, FP32 accumulation   */
+    SIMM_PROJ_BF16 = 2             /* V, Y rounded to BF16, FP32 accumulation                      */
 };
 
 /* Kernel classes reported by simm_result_kernel_stats. */
@@ -183,12 +194,17 @@ simm_status simm_indicators(const simm_shift* shifts, int32_t n_shifts,
                             uint8_t* decision, double* sums, int32_t m_max,
                             int32_t mem, void* hip_stream);
 
-/* Projection X = V_m Y (eq. (reduced)): Y is m_eff x c complex (column-major,
- * leading dimension m_eff), X is n x c complex (leading dimension n); both in
- * device memory.  col_norms (device, may be NULL) receives ||X(:, j)||_2.
- * Computed with FP64 matrix-core instructions. */
+/* Projection X = V_m Y (eq. (reduced); the full-space vectors of eq. (ISPf)):
+ * Y is m_eff x c complex (column-major, leading dimension m_eff), X is n x c
+ * complex (leading dimension n); both in device memory.  col_norms (device, may
+ * be NULL) receives ||X(:, j)||_2.  X may be NULL when col_norms is not (only the
+ * norms are formed; nothing n x c is written).  `precision` is a SIMM_PROJ_*
+ * value: FP64 matrix cores, or V and Y rounded to FP32 / BF16 with FP32
+ * accumulation (X and the norms are still returned as FP64).
+ * EINVAL: c < 0, Y NULL, both X and col_norms NULL, unknown precision, or the
+ * shift's basis was released. */
 simm_status simm_project(simm_shift s, const double* Y, int64_t c, double* X, double* col_norms,
-                         void* hip_stream);
+                         int32_t precision, void* hip_stream);
 
 /* ------------------------------------------------------------------------ */
 /* Whole method: SIM-M steps 1-7 (Sec. 3.5).                                 */
@@ -249,6 +265,12 @@ simm_status simm_result_summary(simm_result r, int32_t* K, int32_t* n_shifts, in
 simm_status simm_result_level(simm_result r, int32_t level, int64_t* n_tested,
                               int64_t* ix, int64_t* iy, int32_t* shift, double* indicator,
                               double* rho_max, uint8_t* decision, int64_t cap);
+
+/* Full-space indicators ||V_m s_f|| / ||V_m s_c|| of the squares of `level`, in
+ * the order of simm_result_level (needs SIMM_FLAG_PROJECT; NaN otherwise).  The
+ * reduced indicator ||s_f|| / ||s_c|| of simm_result_level equals it up to the
+ * orthogonality of V_m (Sec. 3.1).  Host array of `cap` entries. */
+simm_status simm_result_full_indicators(simm_result r, int32_t level, double* out, int64_t cap);
 
 /* Shift `idx` of the run (borrowed handle, valid until simm_result_destroy). */
 simm_status simm_result_shift(simm_result r, int32_t idx, simm_shift* out);

@@ -1147,7 +1147,7 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
     std::vector<Sq> cur;
     for (int64_t c = 0; c < ncell; ++c) cur.push_back({cells[c].first, cells[c].second, assoc[c]});
     const int m_sums = m;
-    DevBuf sums_buf, sums_fb, Ybuf, Xbuf, nrm_buf, scr_buf, idx_buf;
+    DevBuf sums_buf, sums_fb, Ybuf, nrm_buf, scr_buf, idx_buf;
     const int64_t n = p->n;
     for (int k = 1; k <= K; ++k) {
         const int64_t N = (int64_t)cur.size();
@@ -1255,12 +1255,13 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
         // a9: X = V_m Y for the squares of this level, shift by shift
         if (do_proj) {
             Timer t(st, &R->ms[2]);
+            const int proj_prec = !(prm->flags & SIMM_FLAG_MIXED_PROJECT) ? SIMM_PROJ_FP64
+                                  : (k <= 2) ? SIMM_PROJ_BF16 : SIMM_PROJ_FP32;
             std::vector<std::vector<int64_t>> by_shift(shifts.size());
             for (int64_t r = 0; r < N; ++r) by_shift[used[r]].push_back(r);
             int64_t cmax = 0;
             for (auto& v : by_shift) cmax = std::max<int64_t>(cmax, 2 * (int64_t)v.size());
             SIMM_TRY(Ybuf.alloc(sizeof(cplx) * (size_t)cmax * m_sums, st));
-            SIMM_TRY(Xbuf.alloc(sizeof(cplx) * (size_t)cmax * n, st));
             SIMM_TRY(nrm_buf.alloc(sizeof(double) * (size_t)cmax, st));
             SIMM_TRY(scr_buf.alloc(sizeof(double) * (size_t)project_scratch_elems(n, cmax), st));
             SIMM_TRY(idx_buf.alloc(sizeof(int64_t) * (size_t)std::max<int64_t>(1, N), st));
@@ -1275,9 +1276,10 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
                 SIMM_HIP_TRY(hipGetLastError());
                 {
                     KScope ks(clk, SIMM_K_PROJECT);
+                    // only the column norms are needed: X itself is not written
                     SIMM_TRY(project(n, shifts[s]->m_eff, shifts[s]->V, n, Ybuf.as<const cplx>(), m_sums, 2 * cnt,
-                                     Xbuf.as<cplx>(), nrm_buf.as<double>(), scr_buf.as<double>(),
-                                     project_scratch_elems(n, cmax), st));
+                                     nullptr, nrm_buf.as<double>(), scr_buf.as<double>(),
+                                     project_scratch_elems(n, cmax), proj_prec, st));
                 }
                 nrm_host.assign(2 * cnt, 0.0);
                 SIMM_HIP_TRY(hipMemcpyAsync(nrm_host.data(), nrm_buf.p, sizeof(double) * 2 * cnt,
@@ -1451,7 +1453,8 @@ simm_status multiplicities(simm_result_s* R, const cplx* F, int k, double rel_to
             EvalOut eo;
             SIMM_TRY(evaluate({&kv}, regs, prm, rule, st, eo, sb.as<cplx>(), m));
             SIMM_TRY(cluster_sums(sb.as<cplx>(), m, offd, idxd, ncl, kv.m_eff, yb.as<cplx>(), m, st));
-            SIMM_TRY(project(n, kv.m_eff, kv.V, n, yb.as<cplx>(), m, ncl, tb.as<cplx>(), nullptr, nullptr, 0, st));
+            SIMM_TRY(project(n, kv.m_eff, kv.V, n, yb.as<cplx>(), m, ncl, tb.as<cplx>(), nullptr, nullptr, 0,
+                             SIMM_PROJ_FP64, st));
             SIMM_TRY(accum_cols(n, ncl, tb.as<cplx>(), xb.as<cplx>() + (int64_t)i * n, (int64_t)k * n, st));
             SIMM_HIP_TRY(hipStreamSynchronize(st));   // kv's buffers are freed at scope exit
         }
@@ -1789,10 +1792,19 @@ simm_status simm_indicators(const simm_shift* shifts, int32_t n_shifts, const in
     return SIMM_OK;
 }
 
-simm_status simm_project(simm_shift s, const double* Y, int64_t c, double* X, double* col_norms, void* hip_stream) {
+simm_status simm_project(simm_shift s, const double* Y, int64_t c, double* X, double* col_norms, int32_t precision,
+                         void* hip_stream) {
     clear_error();
-    if (!s || c < 0 || (c > 0 && (!Y || !X))) {
+    if (!s || c < 0 || (c > 0 && (!Y || (!X && !col_norms)))) {
         set_error("bad projection arguments");
+        return SIMM_EINVAL;
+    }
+    if (precision != SIMM_PROJ_FP64 && precision != SIMM_PROJ_FP32 && precision != SIMM_PROJ_BF16) {
+        set_error("unknown projection precision");
+        return SIMM_EINVAL;
+    }
+    if (!s->has_factor()) {
+        set_error("the shift's Krylov basis was released (SIMM_FLAG_RELEASE_FACTORS)");
         return SIMM_EINVAL;
     }
     if (c == 0) return SIMM_OK;
@@ -1801,7 +1813,7 @@ simm_status simm_project(simm_shift s, const double* Y, int64_t c, double* X, do
     const int64_t se = project_scratch_elems(s->p->n, c);
     if (col_norms) SIMM_TRY(scr.alloc(sizeof(double) * (size_t)se, st));
     SIMM_TRY(project(s->p->n, s->m_eff, s->V, s->p->n, reinterpret_cast<const cplx*>(Y), s->m_eff, c,
-                     reinterpret_cast<cplx*>(X), col_norms, col_norms ? scr.as<double>() : nullptr, se, st));
+                     reinterpret_cast<cplx*>(X), col_norms, col_norms ? scr.as<double>() : nullptr, se, precision, st));
     SIMM_HIP_TRY(hipStreamSynchronize(st));
     return SIMM_OK;
 }
@@ -1936,6 +1948,22 @@ simm_status simm_result_level(simm_result r, int32_t level, int64_t* n_tested, i
         if (rho_max) rho_max[q] = L.rho_max[q];
         if (decision) decision[q] = L.decision[q];
     }
+    return SIMM_OK;
+}
+
+simm_status simm_result_full_indicators(simm_result r, int32_t level, double* out, int64_t cap) {
+    clear_error();
+    if (!r || level < 1 || level > (int32_t)r->levels.size()) {
+        set_error("bad level");
+        return SIMM_EINVAL;
+    }
+    const LevelRec& L = r->levels[level - 1];
+    const int64_t N = (int64_t)L.full_indicator.size();
+    if (cap < N || (!out && N > 0)) {
+        set_error("cap smaller than the number of squares");
+        return SIMM_EINVAL;
+    }
+    for (int64_t q = 0; q < N; ++q) out[q] = L.full_indicator[q];
     return SIMM_OK;
 }
 

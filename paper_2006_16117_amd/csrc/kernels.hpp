@@ -157,7 +157,7 @@ std::vector<double> hermitian_eigenvalues(int k, const cplx* G);
 
 // ---- projection (project.hip) ----
 simm_status project(int64_t n, int m, const cplx* V, int64_t ldv, const cplx* Y, int64_t ldy, int64_t c, cplx* X,
-                    double* col_norms, double* scratch, int64_t scratch_elems, hipStream_t st);
+                    double* col_norms, double* scratch, int64_t scratch_elems, int prec, hipStream_t st);
 int64_t project_scratch_elems(int64_t n, int64_t c);
 
 }  // namespace simm

@@ -19,8 +19,18 @@
 // imaginary part in the next.  Blocks are ordered so that each XCD (workgroups are
 // dealt to the eight XCDs in turn) walks a contiguous range of row blocks, all
 // column blocks of a row block in a row: that row block of V stays in the XCD's L2.
+//
+// Reduced-precision forms (the projections of the coarse levels only feed the
+// full-space indicator record, never a decision): FP32 operands on
+// v_mfma_f32_16x16x4f32 with FP32 accumulation, and BF16 operands on
+// v_mfma_f32_16x16x16bf16_1k with FP32 accumulation (16 real inner indices per
+// instruction: lane group g supplies (re, im) of the complex indices 2g and 2g + 1
+// of the stage).  V and Y stay FP64 in memory and are rounded when read from LDS;
+// X is written as complex128.  With X == NULL only the column norms are formed.
 #include "common.hpp"
 #include "kernels.hpp"
+
+#include <type_traits>
 
 namespace simm {
 
@@ -28,6 +38,14 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));   // (re, im) in LDS: selects stay on values
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+// FP64 -> BF16, round to nearest even (finite inputs)
+__device__ inline short to_bf16(double x) {
+    const unsigned u = __float_as_uint((float)x);
+    return (short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
 
 constexpr int PJ_THREADS = 256;
 constexpr int PJ_ROWS = 128;            // rows of X per workgroup (2 wavefronts x 64)
@@ -38,6 +56,7 @@ constexpr int PJ_XCDS = 8;
 
 }  // namespace
 
+template <int PREC>
 __global__ __launch_bounds__(PJ_THREADS) void k_vmy(int64_t n, int m, const cplx* __restrict__ V, int64_t ldv,
                                                     const cplx* __restrict__ Y, int64_t ldy, int64_t c,
                                                     int64_t gx, int64_t gy, cplx* __restrict__ X,
@@ -81,51 +100,80 @@ __global__ __launch_bounds__(PJ_THREADS) void k_vmy(int64_t n, int m, const cplx
         for (int q = 0; q < 2; ++q) Ys[b][yk][yj + 32 * q] = d2{gw[q].re, gw[q].im};
     };
 
-    // A operand row li of a tile <-> column 2 (li % 4) + li / 8 of its 8, part (li / 4) % 2: the
-    // instruction leaves output row r in register r / 4 of lane group r % 4, so lane group g then
-    // holds (re, im) of columns 2g and 2g + 1 in registers 0..3.
-    const int ja = 2 * (li & 3) + (li >> 3);
-    const bool aim = (li >> 2) & 1;
+    // A operand row li of a tile <-> (column of its 8, part).  The FP64 instruction leaves
+    // output row r in register r / 4 of lane group r % 4, the FP32-accumulating ones in
+    // register r % 4 of lane group r / 4; with the mappings below lane group g then holds
+    // (re, im) of columns 2g and 2g + 1 in registers 0..3 in both cases.
+    const int ja = (PREC == SIMM_PROJ_FP64) ? 2 * (li & 3) + (li >> 3) : (li >> 1);
+    const bool aim = (PREC == SIMM_PROJ_FP64) ? ((li >> 2) & 1) : (li & 1);
 
-    d4 acc[4][4];
+    typedef typename std::conditional<PREC == SIMM_PROJ_FP64, d4, f4>::type acc_t;
+    acc_t acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
     fetch(0);
     stage(0);
     __syncthreads();
     const int nch = (m + PJ_KC - 1) / PJ_KC;
     // The loop body has no branch (the stage after the last is fetched as zeros and written to
-    // the idle buffer), so the accumulators stay in the matrix-core registers across iterations.
+    // the idle buffer), so the accumulators stay in their registers across iterations.
     for (int ch = 0; ch < nch; ++ch) {
         const int b = ch & 1;
         fetch((ch + 1) * PJ_KC);
+        if constexpr (PREC == SIMM_PROJ_BF16) {
+            // one instruction per tile and stage: lane group kk supplies the real inner indices
+            // (2kk, re), (2kk, im), (2kk+1, re), (2kk+1, im)
+            s4 bv[4], av[4];
 #pragma unroll
-        for (int kg = 0; kg < PJ_KC / 4; ++kg) {
-            // lane group kk supplies inner index 4 kg + kk of the stage
-            const int kl = 4 * kg + kk;
-            d2 vb[4], ya[4];
-#pragma unroll
-            for (int ti = 0; ti < 4; ++ti) vb[ti] = Vs[b][kl][wi * 64 + 16 * ti + li];
-#pragma unroll
-            for (int tj = 0; tj < 4; ++tj) ya[tj] = Ys[b][kl][wj * 32 + 8 * tj + ja];
-            // real part of the inner index: Ybig row (k, 0) = (Yr, Yi)
-#pragma unroll
-            for (int tj = 0; tj < 4; ++tj) {
-                const double a = aim ? ya[tj].y : ya[tj].x;
-#pragma unroll
-                for (int ti = 0; ti < 4; ++ti)
-                    acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, vb[ti].x, acc[ti][tj], 0, 0, 0);
+            for (int ti = 0; ti < 4; ++ti) {
+                const d2 v0 = Vs[b][2 * kk][wi * 64 + 16 * ti + li];
+                const d2 v1 = Vs[b][2 * kk + 1][wi * 64 + 16 * ti + li];
+                bv[ti] = s4{to_bf16(v0.x), to_bf16(v0.y), to_bf16(v1.x), to_bf16(v1.y)};
             }
-            // imaginary part: Ybig row (k, 1) = (-Yi, Yr)
 #pragma unroll
             for (int tj = 0; tj < 4; ++tj) {
-                const double a = aim ? ya[tj].x : -ya[tj].y;
+                const d2 y0 = Ys[b][2 * kk][wj * 32 + 8 * tj + ja];
+                const d2 y1 = Ys[b][2 * kk + 1][wj * 32 + 8 * tj + ja];
+                // Ybig row (k, re) = (Yr, Yi), row (k, im) = (-Yi, Yr)
+                av[tj] = s4{to_bf16(aim ? y0.y : y0.x), to_bf16(aim ? y0.x : -y0.y),
+                            to_bf16(aim ? y1.y : y1.x), to_bf16(aim ? y1.x : -y1.y)};
+            }
+#pragma unroll
+            for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
                 for (int ti = 0; ti < 4; ++ti)
-                    acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, vb[ti].y, acc[ti][tj], 0, 0, 0);
+                    acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[tj], bv[ti], acc[ti][tj], 0, 0, 0);
+        } else {
+#pragma unroll
+            for (int kg = 0; kg < PJ_KC / 4; ++kg) {
+                // lane group kk supplies inner index 4 kg + kk of the stage
+                const int kl = 4 * kg + kk;
+                d2 vb[4], ya[4];
+#pragma unroll
+                for (int ti = 0; ti < 4; ++ti) vb[ti] = Vs[b][kl][wi * 64 + 16 * ti + li];
+#pragma unroll
+                for (int tj = 0; tj < 4; ++tj) ya[tj] = Ys[b][kl][wj * 32 + 8 * tj + ja];
+                // real part of the inner index: Ybig row (k, 0) = (Yr, Yi); imaginary part:
+                // Ybig row (k, 1) = (-Yi, Yr)
+#pragma unroll
+                for (int part = 0; part < 2; ++part) {
+#pragma unroll
+                    for (int tj = 0; tj < 4; ++tj) {
+                        const double a = part == 0 ? (aim ? ya[tj].y : ya[tj].x) : (aim ? ya[tj].x : -ya[tj].y);
+#pragma unroll
+                        for (int ti = 0; ti < 4; ++ti) {
+                            const double v = part == 0 ? vb[ti].x : vb[ti].y;
+                            if constexpr (PREC == SIMM_PROJ_FP64)
+                                acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, v, acc[ti][tj], 0, 0, 0);
+                            else
+                                acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)a, (float)v, acc[ti][tj],
+                                                                                    0, 0, 0);
+                        }
+                    }
+                }
             }
         }
         stage(b ^ 1);
@@ -141,11 +189,13 @@ __global__ __launch_bounds__(PJ_THREADS) void k_vmy(int64_t n, int m, const cplx
 #pragma unroll
         for (int ti = 0; ti < 4; ++ti) {
             const int64_t i = i0 + wi * 64 + 16 * ti + li;
-            const cplx xa = mk(acc[ti][tj][0], acc[ti][tj][1]);
-            const cplx xb = mk(acc[ti][tj][2], acc[ti][tj][3]);
+            const cplx xa = mk((double)acc[ti][tj][0], (double)acc[ti][tj][1]);
+            const cplx xb = mk((double)acc[ti][tj][2], (double)acc[ti][tj][3]);
             if (i < n) {
-                if (jA < c) X[i + jA * n] = xa;
-                if (jA + 1 < c) X[i + (jA + 1) * n] = xb;
+                if (X != nullptr) {
+                    if (jA < c) X[i + jA * n] = xa;
+                    if (jA + 1 < c) X[i + (jA + 1) * n] = xb;
+                }
                 pa += norm2(xa);
                 pb += norm2(xb);
             }
@@ -206,8 +256,13 @@ int64_t project_scratch_elems(int64_t n, int64_t c) {
 }
 
 simm_status project(int64_t n, int m, const cplx* V, int64_t ldv, const cplx* Y, int64_t ldy, int64_t c, cplx* X,
-                    double* col_norms, double* scratch, int64_t scratch_elems, hipStream_t st) {
+                    double* col_norms, double* scratch, int64_t scratch_elems, int prec, hipStream_t st) {
     if (c <= 0) return SIMM_OK;
+    if (prec != SIMM_PROJ_FP64 && prec != SIMM_PROJ_FP32 && prec != SIMM_PROJ_BF16) {
+        set_error("unknown projection precision");
+        return SIMM_EINVAL;
+    }
+    if (X == nullptr && col_norms == nullptr) return SIMM_OK;
     if (m < 1 || n < 1) {
         set_error("projection needs n >= 1 and m >= 1");
         return SIMM_EINVAL;
@@ -223,7 +278,9 @@ simm_status project(int64_t n, int m, const cplx* V, int64_t ldv, const cplx* Y,
         set_error("projection too large for one launch");
         return SIMM_ELIMIT;
     }
-    hipLaunchKernelGGL(k_vmy, dim3((unsigned)(per * PJ_XCDS)), dim3(PJ_THREADS), 0, st, n, m, V, ldv, Y, ldy, c, gx,
+    auto kern = (prec == SIMM_PROJ_FP64) ? k_vmy<SIMM_PROJ_FP64>
+                : (prec == SIMM_PROJ_FP32) ? k_vmy<SIMM_PROJ_FP32> : k_vmy<SIMM_PROJ_BF16>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)(per * PJ_XCDS)), dim3(PJ_THREADS), 0, st, n, m, V, ldv, Y, ldy, c, gx,
                        gy, X, col_norms ? scratch : nullptr);
     if (col_norms != nullptr) {
         double* part = scratch + nblk64 * c;

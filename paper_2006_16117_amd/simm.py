@@ -22,6 +22,10 @@ SIMM_MEM_DEVICE = 1
 SIMM_FLAG_PROJECT = 1
 SIMM_FLAG_KERNEL_TIMING = 2
 SIMM_FLAG_RELEASE_FACTORS = 4
+SIMM_FLAG_MIXED_PROJECT = 8
+SIMM_PROJ_FP64 = 0
+SIMM_PROJ_FP32 = 1
+SIMM_PROJ_BF16 = 2
 KERNEL_NAMES = ["band_lu", "band_sweep", "gram_schmidt", "schur", "indicators", "project", "spike_prep"]
 REJECTED, ADMISSIBLE, UNRESOLVED = 0, 1, 2
 
@@ -64,13 +68,14 @@ EXPORTS = {
     "simm_shift_destroy": (None, [_vp]),
     "simm_indicators": (C.c_int, [_vp, _i32, _vp, _i64, C.POINTER(simm_params), _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                   _i32, _i32, _vp]),
-    "simm_project": (C.c_int, [_vp, _vp, _i64, _vp, _vp, _vp]),
+    "simm_project": (C.c_int, [_vp, _vp, _i64, _vp, _vp, _i32, _vp]),
     "simm_run": (C.c_int, [_vp, C.POINTER(simm_params), _vp, _i32, _vp, C.POINTER(_vp)]),
     "simm_run_batch": (C.c_int, [C.POINTER(_vp), C.POINTER(simm_params), C.POINTER(_vp), _i32, _i32, _i32,
                                  C.POINTER(_vp)]),
     "simm_multiplicities": (C.c_int, [_vp, _vp, _i32, _i32, _d, _vp, _vp, _vp, _i64]),
     "simm_result_summary": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "simm_result_level": (C.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64]),
+    "simm_result_full_indicators": (C.c_int, [_vp, _i32, _vp, _i64]),
     "simm_result_shift": (C.c_int, [_vp, _i32, C.POINTER(_vp)]),
     "simm_result_clusters": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _i64]),
     "simm_result_stats": (C.c_int, [_vp, _vp, _vp]),
@@ -246,14 +251,15 @@ def simm_indicators(shifts, regions: np.ndarray, params: simm_params, want_sums:
     return out
 
 
-def simm_project(shift: Shift, Y, X, col_norms=None, stream=None):
+def simm_project(shift: Shift, Y, X, col_norms=None, precision: int = SIMM_PROJ_FP64, stream=None):
     """Device tensors: Y (m_eff x c), X (n x c) column-major complex128 (torch tensors
-    whose storage is column-major: pass the transposed-contiguous view)."""
+    whose storage is column-major: pass the transposed-contiguous view).  X may be
+    None when col_norms is given (norms only).  precision: SIMM_PROJ_*."""
     py, _ = _ptr(Y)
     px, _ = _ptr(X)
     pn, _ = _ptr(col_norms)
     c = Y.shape[1]
-    _check(_lib.simm_project(shift.handle, py, c, px, pn, _stream(stream)))
+    _check(_lib.simm_project(shift.handle, py, c, px, pn, int(precision), _stream(stream)))
     return X
 
 
@@ -265,6 +271,7 @@ class LevelOut:
     indicator: np.ndarray
     rho_max: np.ndarray
     decision: np.ndarray
+    full_indicator: np.ndarray     # ||V_m s_f|| / ||V_m s_c|| (NaN unless the run projected)
 
 
 class Result:
@@ -289,7 +296,9 @@ class Result:
             dec = np.zeros(N, np.uint8)
             _check(_lib.simm_result_level(handle, k, C.addressof(cnt), ix.ctypes.data, iy.ctypes.data, sh.ctypes.data,
                                           ind.ctypes.data, rho.ctypes.data, dec.ctypes.data, N))
-            self.levels.append(LevelOut(k, np.stack([ix, iy], 1), sh, ind, rho, dec))
+            full = np.zeros(N)
+            _check(_lib.simm_result_full_indicators(handle, k, full.ctypes.data, N))
+            self.levels.append(LevelOut(k, np.stack([ix, iy], 1), sh, ind, rho, dec, full))
         nc_ = self.n_clusters
         lam = np.zeros(nc_, np.complex128)
         lr = np.zeros(nc_, np.complex128)

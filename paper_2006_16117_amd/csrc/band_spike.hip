@@ -358,26 +358,37 @@ __global__ __launch_bounds__(T) void k_chunk_bwd(SpikeBwd a) {
 // next step's Phi row in registers, loaded while the barrier is pending.
 // ---------------------------------------------------------------------------
 constexpr int CH_THREADS = 256;
+constexpr int SPIKE_CTR_STRIDE = 64;   // unsigned counters 256 bytes apart
 
 // CH_PARTS threads per state row, CH_THREADS / CH_PARTS rows per workgroup.
+// Groups (blockIdx.y) run independent chains over their L chunks (chain order q:
+// chunk q forward, P-1-q backward): group 0 from the true initial state, the others
+// from zero; each group meets at its own barrier counter and leaves the state after
+// its last chunk in gout (the last group stops one step earlier: no chunk follows).
 template <int MAXQ, int CH_PARTS>
 __global__ __launch_bounds__(CH_THREADS) void k_spike_chain(SpikeChain a) {
     constexpr int CH_ROWS = CH_THREADS / CH_PARTS;
+    static_assert(CH_ROWS <= 64, "wave 0 stores the workgroup's rows");
     if (a.active != nullptr && *a.active == 0) return;
     __shared__ cplx tcur[CH_PARTS * MAXQ];           // state, zero-padded
+    __shared__ cplx rows_out[CH_ROWS];               // this workgroup's rows of the next state
     const int K = a.K;
     const int g = blockIdx.x;
+    const int64_t grp = blockIdx.y;
     const int tid = threadIdx.x;
     const int il = tid / CH_PARTS, part = tid % CH_PARTS;
     const int i = g * CH_ROWS + il;
     const int ic = min(i, K - 1);
     const int64_t KK = (int64_t)K * K;
-    const int64_t c_first = a.forward ? 0 : a.P - 1;
+    const int64_t q0 = grp * a.L, q1 = min(a.P, q0 + a.L);
+    const int64_t nsteps = (q1 == a.P) ? q1 - q0 - 1 : q1 - q0;
+    auto chunk = [&](int64_t q) { return a.forward ? q : a.P - 1 - q; };
+    unsigned* counter = a.counter + grp * SPIKE_CTR_STRIDE;
     for (int r = tid; r < CH_PARTS * MAXQ; r += CH_THREADS) {
         const int64_t row = a.init_row0 + r;
-        const cplx v = (r < K) ? ldz(a.init_src, row, a.n) : mk(0.0, 0.0);
+        const cplx v = (r < K && grp == 0) ? ldz(a.init_src, row, a.n) : mk(0.0, 0.0);
         tcur[r] = v;
-        if (g == 0 && r < K) a.t[c_first * K + r] = v;
+        if (g == 0 && r < K) a.t[chunk(q0) * K + r] = v;
     }
     cplx ph[MAXQ];
     auto load_phi = [&](int64_t c) {
@@ -385,42 +396,107 @@ __global__ __launch_bounds__(CH_THREADS) void k_spike_chain(SpikeChain a) {
 #pragma unroll
         for (int q = 0; q < MAXQ; ++q) ph[q] = prow[min(part + CH_PARTS * q, K - 1)];
     };
-    if (a.P > 1) load_phi(c_first);
+    if (nsteps > 0) load_phi(chunk(q0));
     __syncthreads();
-    for (int64_t step = 0; step + 1 < a.P; ++step) {
-        const int64_t c = a.forward ? step : a.P - 1 - step;
-        const int64_t cn = a.forward ? c + 1 : c - 1;
+    for (int64_t step = 0; step < nsteps; ++step) {
+        const int64_t q = q0 + step;
+        const int64_t c = chunk(q);
+        // destination of the next state: the next chunk of the group, or the group output
+        cplx* dst = (q + 1 < q1) ? a.t + chunk(q + 1) * K : a.gout + grp * K;
         cplx acc = mk(0.0, 0.0);
 #pragma unroll
-        for (int q = 0; q < MAXQ; ++q) acc = fma_c(acc, ph[q], tcur[part + CH_PARTS * q]);   // padded t is 0
-        if (step + 2 < a.P) load_phi(a.forward ? c + 1 : c - 1);
+        for (int qq = 0; qq < MAXQ; ++qq) acc = fma_c(acc, ph[qq], tcur[part + CH_PARTS * qq]);   // padded t is 0
+        if (step + 1 < nsteps) load_phi(chunk(q + 1));
 #pragma unroll
         for (int m = CH_PARTS / 2; m >= 1; m >>= 1) {
             acc.re += __shfl_xor(acc.re, m, 64);
             acc.im += __shfl_xor(acc.im, m, 64);
         }
-        if (part == 0 && i < K) a.t[cn * K + i] = a.tau[c * K + i] + acc;
-        // device-scope barrier: every thread releases its stores, thread 0 arrives
-        // and waits, every thread acquires
-        __threadfence();
+        if (part == 0 && i < K) rows_out[il] = a.tau[c * K + i] + acc;
         __syncthreads();
-        if (tid == 0) {
-            __hip_atomic_fetch_add(a.counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            const unsigned target = (unsigned)(gridDim.x * (step + 1));
-            long spins = 0;
-            while (__hip_atomic_load(a.counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                __builtin_amdgcn_s_sleep(1);
-                if (++spins > 40000000L) {
-                    atomicExch(a.err, 1);
-                    break;
+        // Device-scope barrier of the group.  Wave 0 alone exchanges the state with the
+        // other workgroups: it stores this workgroup's rows, releases them (one agent-scope
+        // release), arrives, polls with relaxed loads (an acquiring load would invalidate
+        // the XCD's L2 on every poll), acquires once and loads the whole next state into
+        // LDS.  The other waves meet it at the workgroup barriers.  One write-back and one
+        // invalidate per workgroup and step: they serialise per XCD, so fences from every
+        // wave slowed concurrent chains several-fold.
+        if (tid < 64) {
+            if (tid < CH_ROWS && g * CH_ROWS + tid < K) dst[g * CH_ROWS + tid] = rows_out[tid];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if (tid == 0) {
+                __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned target = (unsigned)(gridDim.x * (step + 1));
+                long spins = 0;
+                while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++spins > 40000000L) {
+                        atomicExch(a.err, 1);
+                        break;
+                    }
                 }
             }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            // all loads in flight at once (indices clamped into the state), then to LDS
+            constexpr int NL = (CH_PARTS * MAXQ + 63) / 64;
+            cplx nxt[NL];
+#pragma unroll
+            for (int u = 0; u < NL; ++u) nxt[u] = dst[min(tid + 64 * u, K - 1)];
+#pragma unroll
+            for (int u = 0; u < NL; ++u) tcur[tid + 64 * u] = csel(tid + 64 * u < K, nxt[u], mk(0.0, 0.0));   // padding stays 0
         }
         __syncthreads();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        for (int r = tid; r < K; r += CH_THREADS) tcur[r] = a.t[cn * K + r];
-        __syncthreads();
     }
+}
+
+// Second level of the chain: the true start state T_g of every group g >= 1 (from the
+// chain over groups) enters its chunks through the transfer products,
+//     t_q += Pi_q T_g   (Pi_q = Phi_{q-1} ... Phi_{q0(g)}, chain order; Pi_{q0} = I),
+// 16 threads per state row, 16 rows per workgroup, blockIdx.y = chain-order chunk q.
+template <int MAXQ>
+__global__ __launch_bounds__(256) void k_spike_fix(int K, int64_t P, int64_t L, int forward, const cplx* __restrict__ Pi,
+                                                   const cplx* __restrict__ tg, cplx* __restrict__ t, const int* active) {
+    if (active != nullptr && *active == 0) return;
+    const int64_t q = blockIdx.y;
+    const int64_t grp = q / L;
+    if (grp == 0) return;
+    __shared__ cplx Ts[16 * MAXQ];
+    const int tid = threadIdx.x, il = tid >> 4, part = tid & 15;
+    const int i = blockIdx.x * 16 + il;
+    const cplx* T = tg + (grp - 1) * K;    // true state at the group's first chunk
+    for (int r = tid; r < 16 * MAXQ; r += 256) Ts[r] = (r < K) ? T[r] : mk(0.0, 0.0);
+    __syncthreads();
+    const int64_t c = forward ? q : P - 1 - q;
+    if (q == grp * L) {
+        // first chunk of the group: its chain ran from zero, so its state is T_g itself
+        if (part == 0 && i < K) t[c * K + i] = Ts[i];
+        return;
+    }
+    const cplx* prow = Pi + q * (int64_t)K * K + (int64_t)min(i, K - 1) * K;
+    cplx acc = mk(0.0, 0.0);
+#pragma unroll
+    for (int qq = 0; qq < MAXQ; ++qq) {
+        const int r = part + 16 * qq;
+        acc = fma_c(acc, prow[min(r, K - 1)], Ts[r]);          // padded T is 0
+    }
+#pragma unroll
+    for (int m = 8; m >= 1; m >>= 1) {
+        acc.re += __shfl_xor(acc.re, m, 64);
+        acc.im += __shfl_xor(acc.im, m, 64);
+    }
+    if (part == 0 && i < K) t[c * K + i] = t[c * K + i] + acc;
+}
+
+// Copies of the group's first transfer matrix: Pi_{q0+1} = Phi_{chunk(q0)}, groups 1..ng.
+__global__ __launch_bounds__(256) void k_pi_first(int K, int64_t P, int64_t L, int forward, int64_t ng,
+                                                  const cplx* __restrict__ Phi, cplx* __restrict__ Pi) {
+    const int64_t KK = (int64_t)K * K;
+    const int64_t grp = 1 + blockIdx.y;
+    if (grp > ng) return;
+    const int64_t q = grp * L;
+    const int64_t c = forward ? q : P - 1 - q;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < KK; e += (int64_t)gridDim.x * 256)
+        Pi[(q + 1) * KK + e] = Phi[c * KK + e];
 }
 
 // y(j) += sum_r Psi(j, r) t_{c(j)}(r); the (at most two) state vectors a block
@@ -510,9 +586,13 @@ size_t window_lds(int rows, int64_t s) {
 int64_t spike_chunk_len(int64_t n16, int kl, int K) {
     int64_t s = 0;
     if (const char* e = getenv("SIMM_SPIKE_CHUNK")) s = atoll(e);
-    // balance the chunk sweeps (~s/16 panel steps of ~2 us) against the chain (~P steps
-    // of ~5-8 us): s ~ sqrt(100 n) (measured optimum at n = 40,000: s = 1,500 .. 2,000)
-    if (s <= 0) s = (int64_t)std::sqrt((double)n16 * 100.0);
+    // balance the chunk sweeps (~s/16 panel steps of ~2 us) against the two-level chain
+    // (~L + G steps of ~5-12 us) and the per-shift unit-state responses, whose fixed cost
+    // per chunk grows with P: s ~ sqrt(100 n) / 2 (n = 40,000 step medians: s = 500, 750,
+    // 1000, 1250, 2000 -> ~780, ~750, ~700, ~720, ~815 ms)
+    if (s <= 0) s = (int64_t)std::sqrt((double)n16 * 100.0) / 2;
+    // k_spike_correct stages the states of at most two chunks per 256-row block
+    s = std::max<int64_t>(s, 256);
     s = std::max<int64_t>(s, std::max(kl, K) + 16);
     s = (s + 15) / 16 * 16;
     // a chunk's inputs, outputs and pivots are staged in LDS next to the window
@@ -520,6 +600,39 @@ int64_t spike_chunk_len(int64_t n16, int kl, int K) {
     const int64_t smax = ((150 * 1024 - 16 * (2 * rows + 16)) / (16 * 2 + 4)) / 16 * 16;
     s = std::min<int64_t>(s, smax);
     return std::min<int64_t>(s, n16);
+}
+
+// Transfer products of the two-level chain, chain order q (chunk q forward, P-1-q
+// backward), for the groups g >= 1 (group g covers q0 = g L .. q1 - 1):
+//     Pi_q = Phi_{q-1} ... Phi_{q0}  for q0 < q < q1,      PiFull_g = Phi_{q1-1} ... Phi_{q0}
+// (the latter for the full groups 1 .. G-2 only: it carries the state to the next group).
+// Phi, Pi are stored by rows ([i][r]); read as column-major arrays they are the
+// transposes, so Pi_{q+1} = Phi_q Pi_q is the column-major product Pi_q^T Phi_q^T, formed
+// for all groups at once by the batched FP64 matrix-core product.
+static simm_status transfer_products(const SpikeFactor& f, bool forward, int K, const cplx* Phi, cplx* Pi,
+                                     cplx* PiFull, hipStream_t st) {
+    const int64_t KK = (int64_t)K * K, P = f.P, L = f.L, G = f.G;
+    const int64_t len_last = P - (G - 1) * L;
+    auto chunk = [&](int64_t q) { return forward ? q : P - 1 - q; };
+    const int64_t sY = forward ? L * KK : -L * KK;
+    // G > 1 implies L >= 2 (at least two chunks a group)
+    for (int64_t d = 1; d <= L; ++d) {
+        // groups 1 .. gmax take part in step d
+        const int64_t gmax = (d < L) ? ((d < len_last) ? G - 1 : G - 2) : G - 2;
+        if (gmax < 1) continue;
+        const int64_t q = L + d - 1;   // group 1's q0 + d - 1
+        if (d == 1) {
+            const unsigned bx = (unsigned)std::min<int64_t>((KK + 255) / 256, 1024);
+            hipLaunchKernelGGL(k_pi_first, dim3(bx, (unsigned)gmax), dim3(256), 0, st, K, P, L, forward ? 1 : 0, gmax,
+                               Phi, Pi);
+            SIMM_HIP_TRY(hipGetLastError());
+            continue;
+        }
+        cplx* dst = (d < L) ? Pi + (L + d) * KK : PiFull + KK;
+        const int64_t sX = (d < L) ? L * KK : KK;
+        SIMM_TRY(project_batched(K, K, Pi + q * KK, K, L * KK, Phi + chunk(q) * KK, K, sY, K, dst, sX, (int)gmax, st));
+    }
+    return SIMM_OK;
 }
 
 simm_status spike_prepare(SpikeFactor& f, hipStream_t st) {
@@ -546,13 +659,26 @@ simm_status spike_prepare(SpikeFactor& f, hipStream_t st) {
     }
     f.s = spike_chunk_len(f.n16, f.klx, f.K);
     f.P = (f.n16 + f.s - 1) / f.s;
+    // groups of the two-level chain: ~(2/3) sqrt(P) groups (concurrent groups slow each
+    // other's steps, so somewhat fewer and longer groups than the sqrt(P) that balances
+    // the step counts), at least 2 chunks a group (SIMM_SPIKE_GROUPS overrides; 1 = one
+    // chain over all chunks)
+    {
+        int64_t G = (f.P >= 8) ? std::max<int64_t>(1, std::lround(std::sqrt((double)f.P) * 2.0 / 3.0)) : 1;
+        if (const char* e = getenv("SIMM_SPIKE_GROUPS")) G = std::max<int64_t>(1, atoll(e));
+        G = std::min<int64_t>(G, std::max<int64_t>(1, f.P / 2));
+        f.L = (f.P + G - 1) / G;
+        f.G = (f.P + f.L - 1) / f.L;
+    }
     f.Wf = threads_for(f.klx + 16);
     f.Wb = threads_for(f.K + 16);
     const int kl = f.klx, K = f.K;
     const int64_t n16 = f.n16;
+    const size_t two = f.G > 1 ? 1 : 0;    // transfer products only with more than one group
     const size_t elems = (size_t)n16 * (kl + 16) + (size_t)n16 * (K + 16) + (size_t)n16 * kl + (size_t)f.P * kl * kl +
                          (size_t)n16 * K + (size_t)f.P * K * K + (size_t)f.P * kl * 2 + (size_t)f.P * K * 2 +
-                         (size_t)n16;
+                         (size_t)n16 + two * ((size_t)(f.P + f.G) * ((size_t)kl * kl + (size_t)K * K)) +
+                         (size_t)f.G * 2 * (kl + K) + (size_t)(f.G + 1) * 16 + 64;
     SIMM_HIP_TRY(hipMalloc(&f.mem, sizeof(cplx) * elems + 16 * 256));
     char* p = reinterpret_cast<char*>(f.mem);
     auto take = [&](size_t count) {
@@ -571,7 +697,19 @@ simm_status spike_prepare(SpikeFactor& f, hipStream_t st) {
     f.tauU = take((size_t)f.P * K);
     f.tU = take((size_t)f.P * K);
     f.z = take((size_t)n16);
-    f.counter = reinterpret_cast<unsigned*>(take(4));
+    if (f.G > 1) {
+        f.PiL = take((size_t)f.P * kl * kl);
+        f.PiU = take((size_t)f.P * K * K);
+        f.PiFullL = take((size_t)f.G * kl * kl);
+        f.PiFullU = take((size_t)f.G * K * K);
+    }
+    f.goutL = take((size_t)f.G * kl);
+    f.goutU = take((size_t)f.G * K);
+    f.tgL = take((size_t)f.G * kl);
+    f.tgU = take((size_t)f.G * K);
+    // one barrier counter per group and one for the chain over groups, each on a line of
+    // its own (spinning workgroups of different groups must not share a cache line)
+    f.counter = reinterpret_cast<unsigned*>(take((size_t)(f.G + 1) * (SPIKE_CTR_STRIDE / 4)));
     f.err = reinterpret_cast<int*>(take(4));
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned*>(f.err), 1, 0u);
     // per-panel blocks
@@ -603,6 +741,10 @@ simm_status spike_prepare(SpikeFactor& f, hipStream_t st) {
     b.Psi = f.PsiU;
     b.Phi = f.PhiU;
     SIMM_TRY(launch_bwd(b, f.P, K, f.Wb, window_lds(K + 16, f.s), st));
+    if (f.G > 1) {
+        SIMM_TRY(transfer_products(f, true, kl, f.PhiL, f.PiL, f.PiFullL, st));
+        SIMM_TRY(transfer_products(f, false, K, f.PhiU, f.PiU, f.PiFullU, st));
+    }
     return SIMM_OK;
 }
 
@@ -611,28 +753,56 @@ void spike_release(SpikeFactor& f) {
     f.mem = nullptr;
 }
 
-static simm_status run_chain(const SpikeFactor& f, bool forward, int K, const cplx* Phi, const cplx* tau, cplx* tstate,
-                             const cplx* init_src, int64_t init_row0, const int* active, hipStream_t st) {
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, f.counter, 1, 0u);
+// One chain launch: `groups` groups of L chunks (chain order) over P chunks, each group
+// with its own barrier counter.
+static simm_status run_chain(const SpikeFactor& f, bool forward, int K, int64_t P, int64_t L, int64_t groups,
+                             const cplx* Phi, const cplx* tau, cplx* tstate, cplx* gout, const cplx* init_src,
+                             int64_t init_row0, int64_t n, unsigned* counter, const int* active, hipStream_t st) {
     SpikeChain c{};
-    c.n = f.n;
+    c.n = n;
     c.K = K;
-    c.P = f.P;
+    c.P = P;
+    c.L = L;
     c.forward = forward ? 1 : 0;
     c.Phi = Phi;
     c.tau = tau;
     c.t = tstate;
+    c.gout = gout;
     c.init_src = init_src;
     c.init_row0 = init_row0;
-    c.counter = f.counter;
+    c.counter = counter;
     c.err = f.err;
     c.active = active;
     // 16 threads per state row, 16 rows per workgroup: more, smaller workgroups make
     // the device-scope barrier of every step dearer than the rows they save
-    const int G = (K + 15) / 16;
-    if (K <= 16 * 16) hipLaunchKernelGGL((k_spike_chain<16, 16>), dim3(G), dim3(CH_THREADS), 0, st, c);
-    else if (K <= 32 * 16) hipLaunchKernelGGL((k_spike_chain<32, 16>), dim3(G), dim3(CH_THREADS), 0, st, c);
-    else hipLaunchKernelGGL((k_spike_chain<64, 16>), dim3(G), dim3(CH_THREADS), 0, st, c);
+    const dim3 grid((unsigned)((K + 15) / 16), (unsigned)groups);
+    if (K <= 16 * 16) hipLaunchKernelGGL((k_spike_chain<16, 16>), grid, dim3(CH_THREADS), 0, st, c);
+    else if (K <= 32 * 16) hipLaunchKernelGGL((k_spike_chain<32, 16>), grid, dim3(CH_THREADS), 0, st, c);
+    else hipLaunchKernelGGL((k_spike_chain<64, 16>), grid, dim3(CH_THREADS), 0, st, c);
+    SIMM_HIP_TRY(hipGetLastError());
+    return SIMM_OK;
+}
+
+// The chain over the chunks' boundary states of one sweep direction: one level, or
+// groups in parallel, the chain over the groups' start states and the fix-up.
+static simm_status chain_states(const SpikeFactor& f, bool forward, int K, const cplx* Phi, const cplx* tau, cplx* t,
+                                const cplx* Pi, const cplx* PiFull, cplx* gout, cplx* tg, const cplx* init_src,
+                                int64_t init_row0, const int* active, hipStream_t st) {
+    // zero the counters of both chain levels
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, f.counter, (int)((f.G + 1) * SPIKE_CTR_STRIDE), 0u);
+    SIMM_TRY(run_chain(f, forward, K, f.P, f.L, f.G, Phi, tau, t, gout, init_src, init_row0, f.n, f.counter, active,
+                       st));
+    if (f.G == 1) return SIMM_OK;
+    // T_1 = gout_0; T_{g+1} = gout_g + PiFull_g T_g (g = 1 .. G-2), into tg[g-1]
+    const int64_t KK = (int64_t)K * K;
+    SIMM_TRY(run_chain(f, true, K, f.G - 1, f.G - 1, 1, PiFull + KK, gout + K, tg, nullptr, gout, 0, K,
+                       f.counter + f.G * SPIKE_CTR_STRIDE, active, st));
+    const dim3 grid((unsigned)((K + 15) / 16), (unsigned)f.P);
+    if (K <= 16 * 16) hipLaunchKernelGGL(k_spike_fix<16>, grid, dim3(256), 0, st, K, f.P, f.L, forward ? 1 : 0, Pi, tg, t,
+                                         active);
+    else if (K <= 32 * 16) hipLaunchKernelGGL(k_spike_fix<32>, grid, dim3(256), 0, st, K, f.P, f.L, forward ? 1 : 0, Pi,
+                                              tg, t, active);
+    else hipLaunchKernelGGL(k_spike_fix<64>, grid, dim3(256), 0, st, K, f.P, f.L, forward ? 1 : 0, Pi, tg, t, active);
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;
 }
@@ -654,7 +824,7 @@ simm_status spike_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int*
     a.tau = f.tauL;
     a.active = active;
     SIMM_TRY(launch_fwd(a, f.P, 1, f.Wf, window_lds(f.klx + 16, f.s), st));
-    SIMM_TRY(run_chain(f, true, f.klx, f.PhiL, f.tauL, f.tL, u, 0, active, st));
+    SIMM_TRY(chain_states(f, true, f.klx, f.PhiL, f.tauL, f.tL, f.PiL, f.PiFullL, f.goutL, f.tgL, u, 0, active, st));
     hipLaunchKernelGGL(k_spike_correct, dim3(blocks), dim3(256), sizeof(cplx) * 2 * f.klx, st, f.n, f.n16, f.klx, f.s,
                        (const cplx*)f.PsiL, (const cplx*)f.tL, z, active);
     // backward: y = U^{-1} z
@@ -670,7 +840,8 @@ simm_status spike_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int*
     b.tau = f.tauU;
     b.active = active;
     SIMM_TRY(launch_bwd(b, f.P, 1, f.Wb, window_lds(f.K + 16, f.s), st));
-    SIMM_TRY(run_chain(f, false, f.K, f.PhiU, f.tauU, f.tU, z, f.n16 - f.K, active, st));
+    SIMM_TRY(chain_states(f, false, f.K, f.PhiU, f.tauU, f.tU, f.PiU, f.PiFullU, f.goutU, f.tgU, z, f.n16 - f.K, active,
+                          st));
     hipLaunchKernelGGL(k_spike_correct, dim3(blocks), dim3(256), sizeof(cplx) * 2 * f.K, st, f.n, f.n16, f.K, f.s,
                        (const cplx*)f.PsiU, (const cplx*)f.tU, y, active);
     SIMM_HIP_TRY(hipGetLastError());

@@ -65,13 +65,15 @@ struct SpikeChain {
     int64_t n;
     int K;
     int64_t P;
+    int64_t L;            // chunks per group (groups = gridDim.y); L = P: one group
     int forward;
     const cplx* Phi;
     const cplx* tau;
     cplx* t;
+    cplx* gout;           // state after each group's last chunk (groups but the last)
     const cplx* init_src;
     int64_t init_row0;
-    unsigned* counter;
+    unsigned* counter;    // one per group
     int* err;
     const int* active;
 };
@@ -88,7 +90,13 @@ struct SpikeFactor {
     cplx *Gf = nullptr, *Hb = nullptr;
     cplx *PsiL = nullptr, *PhiL = nullptr, *PsiU = nullptr, *PhiU = nullptr;
     cplx *tauL = nullptr, *tL = nullptr, *tauU = nullptr, *tU = nullptr, *z = nullptr;
-    unsigned* counter = nullptr;
+    // two-level chain: G groups of L chunks (in chain order); per direction the products
+    // Pi_q of the transfer matrices from the start of q's group to chunk q (chain order),
+    // the whole-group products, the group outputs and the true group start states
+    int64_t G = 1, L = 0;
+    cplx *PiL = nullptr, *PiU = nullptr, *PiFullL = nullptr, *PiFullU = nullptr;
+    cplx *goutL = nullptr, *goutU = nullptr, *tgL = nullptr, *tgU = nullptr;
+    unsigned* counter = nullptr;   // G + 1 counters
     int* err = nullptr;
 };
 int64_t spike_chunk_len(int64_t n, int kl, int K);
@@ -158,6 +166,10 @@ std::vector<double> hermitian_eigenvalues(int k, const cplx* G);
 // ---- projection (project.hip) ----
 simm_status project(int64_t n, int m, const cplx* V, int64_t ldv, const cplx* Y, int64_t ldy, int64_t c, cplx* X,
                     double* col_norms, double* scratch, int64_t scratch_elems, int prec, hipStream_t st);
+// nb independent FP64 products X_b = V_b Y_b (b < nb), operands offset by the given strides
+// (in complex elements, any sign); no column norms
+simm_status project_batched(int64_t n, int m, const cplx* V, int64_t ldv, int64_t sV, const cplx* Y, int64_t ldy,
+                            int64_t sY, int64_t c, cplx* X, int64_t sX, int nb, hipStream_t st);
 int64_t project_scratch_elems(int64_t n, int64_t c);
 
 }  // namespace simm

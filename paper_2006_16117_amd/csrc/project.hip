@@ -60,7 +60,11 @@ template <int PREC>
 __global__ __launch_bounds__(PJ_THREADS) void k_vmy(int64_t n, int m, const cplx* __restrict__ V, int64_t ldv,
                                                     const cplx* __restrict__ Y, int64_t ldy, int64_t c,
                                                     int64_t gx, int64_t gy, cplx* __restrict__ X,
-                                                    double* __restrict__ colpart) {
+                                                    double* __restrict__ colpart, int64_t sV, int64_t sY, int64_t sX) {
+    // batch member blockIdx.y (strided operands; a batch has no column norms)
+    V += (int64_t)blockIdx.y * sV;
+    Y += (int64_t)blockIdx.y * sY;
+    if (X != nullptr) X += (int64_t)blockIdx.y * sX;
     __shared__ d2 Vs[2][PJ_KC][PJ_ROWS];
     __shared__ d2 Ys[2][PJ_KC][PJ_YLD];
     const int64_t T = gx * gy, per = (T + PJ_XCDS - 1) / PJ_XCDS;
@@ -281,7 +285,7 @@ simm_status project(int64_t n, int m, const cplx* V, int64_t ldv, const cplx* Y,
     auto kern = (prec == SIMM_PROJ_FP64) ? k_vmy<SIMM_PROJ_FP64>
                 : (prec == SIMM_PROJ_FP32) ? k_vmy<SIMM_PROJ_FP32> : k_vmy<SIMM_PROJ_BF16>;
     hipLaunchKernelGGL(kern, dim3((unsigned)(per * PJ_XCDS)), dim3(PJ_THREADS), 0, st, n, m, V, ldv, Y, ldy, c, gx,
-                       gy, X, col_norms ? scratch : nullptr);
+                       gy, X, col_norms ? scratch : nullptr, (int64_t)0, (int64_t)0, (int64_t)0);
     if (col_norms != nullptr) {
         double* part = scratch + nblk64 * c;
         hipLaunchKernelGGL(k_colnorm_partial, dim3((unsigned)((c + 63) / 64), CN_GROUPS), dim3(256), 0, st,
@@ -289,6 +293,21 @@ simm_status project(int64_t n, int m, const cplx* V, int64_t ldv, const cplx* Y,
         hipLaunchKernelGGL(k_colnorm_finish, dim3((unsigned)((c + 127) / 128)), dim3(128), 0, st,
                            (const double*)part, c, col_norms);
     }
+    SIMM_HIP_TRY(hipGetLastError());
+    return SIMM_OK;
+}
+
+simm_status project_batched(int64_t n, int m, const cplx* V, int64_t ldv, int64_t sV, const cplx* Y, int64_t ldy,
+                            int64_t sY, int64_t c, cplx* X, int64_t sX, int nb, hipStream_t st) {
+    if (nb <= 0 || c <= 0) return SIMM_OK;
+    if (m < 1 || n < 1 || X == nullptr || nb > 65535) {
+        set_error("bad batched projection");
+        return SIMM_EINVAL;
+    }
+    const int64_t gx = (n + PJ_ROWS - 1) / PJ_ROWS, gy = (c + PJ_COLS - 1) / PJ_COLS;
+    const int64_t per = (gx * gy + PJ_XCDS - 1) / PJ_XCDS;
+    hipLaunchKernelGGL(k_vmy<SIMM_PROJ_FP64>, dim3((unsigned)(per * PJ_XCDS), (unsigned)nb), dim3(PJ_THREADS), 0, st,
+                       n, m, V, ldv, Y, ldy, c, gx, gy, X, (double*)nullptr, sV, sY, sX);
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;
 }

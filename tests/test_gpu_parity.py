@@ -96,6 +96,42 @@ def test_pivoting_really_pivots_and_apply_matches(S):
     assert np.linalg.norm(y - want) <= 1e-12 * np.linalg.norm(want)
 
 
+@pytest.mark.parametrize("n,k,chunk,groups", [
+    (5013, 3, 256, [1, 2, 3, 4, 7, 10]),        # P = 20: groups of 2..20 chunks, uneven last groups
+    (3000, 150, 320, [1, 2, 3, 5]),             # P = 10, wide band: state of ~150 / ~300 rows
+])
+def test_apply_two_level_chain_matches_oracle(S, n, k, chunk, groups):
+    """One application of M = (A - sigma B)^{-1} B through the partitioned sweeps, with the
+    chain over the chunk boundaries run in one level or in groups (chains per group, the
+    chain over the groups' start states, the fix-up by the transfer products), against the
+    oracle's banded solve."""
+    pen, f = random_band_pencil(n, k, 86, b_kind="tridiag", b_offdiag=0.3, d_half=0.05, e_scale=1.0)
+    sigma = 0.03 - 0.01j
+    solver = O.ShiftedSolver(pen, sigma)
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    want = solver.apply_M(x)
+    P = S.Pencil.from_workload(pen)
+    saved = {v: os.environ.get(v) for v in ("SIMM_SPIKE_CHUNK", "SIMM_SPIKE_GROUPS")}
+    try:
+        for g in groups:
+            os.environ["SIMM_SPIKE_CHUNK"] = str(chunk)
+            os.environ["SIMM_SPIKE_GROUPS"] = str(g)
+            say("apply", f"n={n} k={k} chunk={chunk} groups={g}")
+            sh = S.simm_shift_build(P, sigma, f, 4)
+            y = np.zeros(n, np.complex128)
+            sh.apply(x, y)
+            err = np.linalg.norm(y - want) / np.linalg.norm(want)
+            assert err <= 1e-11, (g, err)
+            del sh
+    finally:
+        for v, old in saved.items():
+            if old is None:
+                os.environ.pop(v, None)
+            else:
+                os.environ[v] = old
+
+
 def test_shift_build_is_deterministic(S):
     pen, f = random_band_pencil(700, 4, 82, b_kind="tridiag")
     say("determinism", "n=700")

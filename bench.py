@@ -319,8 +319,8 @@ def main():
             "launches_per_step": lu_launches // args.steps,
         },
         "roofline_apply": {
-            "kernel": "one application of M = U^-1 L^-1 P B (k_prepare_input, k_chunk_fwd, k_spike_chain, "
-                      "k_spike_correct, k_chunk_bwd, k_spike_chain, k_spike_correct)",
+            "kernel": "one application of M = U^-1 L^-1 P B (k_prepare_input; k_chunk_fwd, k_spike_chain x2, "
+                      "k_spike_fix, k_spike_correct; k_chunk_bwd, k_spike_chain x2, k_spike_fix, k_spike_correct)",
             "bound": "hbm",
             "achieved": apply_gbs,
             "peak": HBM_PEAK_GBS,
@@ -342,7 +342,7 @@ def main():
             "ms_per_step": kms["indicators"] / args.steps,
         },
         "roofline_project": {
-            "kernel": "k_vmy (X = V_m Y on the FP64 matrix cores, with column norms)",
+            "kernel": "k_vmy (column norms of X = V_m Y on the FP64 matrix cores, X not stored), per level and shift",
             "bound": "mfma",
             "achieved": proj_tflops,
             "peak": FP64_PEAK_TFLOPS,

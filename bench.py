@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 # most 11), and streams beyond the queue count share queues and serialise.  Medians
 # of 6 steps on the n = 40,000 workload: 7 ahead with 8 queues ~860-930 ms, 11 ahead
 # with 12 queues ~825 ms, 11-15 ahead with 16 queues 843-864 ms.
-HW_QUEUES = 12
+HW_QUEUES = int(os.environ.get("SIMM_BENCH_HW_QUEUES", "12"))
 os.environ["GPU_MAX_HW_QUEUES"] = str(HW_QUEUES)
 
 METRIC = "resolvent solves/s + indicators/s at n=40k; speedup vs plain FP64 at 1e-6"
@@ -199,6 +199,8 @@ def main():
     ap.add_argument("--project-c", type=int, default=1600,
                     help="columns of the full-level projection measured after the steps (0: skip)")
     ap.add_argument("--workers", type=int, default=4, help="runs in flight in the batched form")
+    ap.add_argument("--lookahead", type=int, default=0,
+                    help="LU factors computed ahead in the timed run (0: the library default)")
     ap.add_argument("--batch-lookahead", type=int, default=0,
                     help="look-ahead of each run in the batched form (0: the batch default, one at a time)")
     ap.add_argument("--no-sequential", action="store_true", help="batched form only (no separate runs)")
@@ -237,7 +239,7 @@ def main():
     log("workload", args.workload, "n =", pen.n)
     P = S.Pencil.from_workload(pen)
     fd = torch.from_numpy(np.ascontiguousarray(f)).to(dev)
-    prm = S.params_from_dict(params, flags=S.SIMM_FLAG_PROJECT | S.SIMM_FLAG_KERNEL_TIMING)
+    prm = S.params_from_dict(params, flags=S.SIMM_FLAG_PROJECT | S.SIMM_FLAG_KERNEL_TIMING, lookahead=args.lookahead)
     torch.cuda.synchronize()
 
     for w in range(args.warmup):

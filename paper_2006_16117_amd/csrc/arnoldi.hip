@@ -14,6 +14,7 @@ namespace simm {
 namespace {
 
 constexpr int GS_THREADS = 256;
+constexpr int GS_MAXCOL = 130;   // Krylov dimension <= 128: at most m + 1 basis columns
 
 __device__ inline cplx shfl_xor_c(cplx v, int mask) {
     return mk(__shfl_xor(v.re, mask, 64), __shfl_xor(v.im, mask, 64));
@@ -24,6 +25,36 @@ __device__ inline cplx wave_sum(cplx v) {
     for (int m = 32; m >= 1; m >>= 1) v = v + shfl_xor_c(v, m);
     return v;
 }
+
+// Partial sums over the rows c0 .. c0 + len - 1 staged in ws: column i < ndots gets
+// sum conj(V(r, i)) w(r), column ndots (if with_norm) sum |w(r)|^2.  Each wave takes 4
+// columns at a time, so that 4 independent load streams are in flight; per column the
+// operation order (lanes over rows, then the wave sum) is that of one column at a time.
+__device__ inline void chunk_dots(const cplx* __restrict__ V, int64_t ldv, int64_t c0, int len, const cplx* ws,
+                                  int ndots, int with_norm, cplx* dst, bool first) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = GS_THREADS / 64;
+    const int ntot = ndots + (with_norm ? 1 : 0);
+    for (int ib = 4 * wave; ib < ntot; ib += 4 * nw) {
+        cplx acc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] = mk(0.0, 0.0);
+        for (int r = lane; r < len; r += 64) {
+            const cplx x = ws[r];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = ib + u;
+                if (i < ndots) acc[u] = fma_cj(acc[u], V[c0 + r + (int64_t)i * ldv], x);
+                else if (i == ndots) acc[u].re += norm2(x);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const cplx t = wave_sum(acc[u]);
+            if (lane == 0 && ib + u < ntot) dst[ib + u] = first ? t : dst[ib + u] + t;
+        }
+    }
+}
+
 
 }  // namespace
 
@@ -38,7 +69,6 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_dots(int64_t n, const cplx* _
     const int64_t rows = (n + nblk - 1) / nblk;
     const int64_t r0 = blockIdx.x * rows;
     const int64_t r1 = min(n, r0 + rows);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = GS_THREADS / 64;
     const int ntot = ncol + (with_norm ? 1 : 0);
     if (r0 >= r1) {
         for (int i = threadIdx.x; i < ntot; i += GS_THREADS) partial[blockIdx.x * (int64_t)ldp + i] = mk(0.0, 0.0);
@@ -50,21 +80,7 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_dots(int64_t n, const cplx* _
         __syncthreads();
         for (int64_t r = c0 + threadIdx.x; r < c1; r += GS_THREADS) ws[r - c0] = w[r];
         __syncthreads();
-        for (int i = wave; i < ntot; i += nw) {
-            cplx acc = mk(0.0, 0.0);
-            if (i < ncol) {
-                const cplx* col = V + (int64_t)i * ldv;
-                for (int64_t r = c0 + lane; r < c1; r += 64) acc = fma_cj(acc, col[r], ws[r - c0]);
-            } else {
-                for (int64_t r = c0 + lane; r < c1; r += 64) acc.re += norm2(ws[r - c0]);
-            }
-            acc = wave_sum(acc);
-            if (lane == 0) {
-                cplx* dst = partial + blockIdx.x * (int64_t)ldp + i;
-                if (c0 == r0) *dst = acc;
-                else *dst = *dst + acc;
-            }
-        }
+        chunk_dots(V, ldv, c0, (int)(c1 - c0), ws, ncol, with_norm, partial + blockIdx.x * (int64_t)ldp, c0 == r0);
     }
 }
 
@@ -87,26 +103,63 @@ __global__ __launch_bounds__(256) void k_gs_reduce(const cplx* partial, int nblk
     if (threadIdx.x == 0) out[i] = red[0];
 }
 
-// w(r) -= sum_{i < ncol} V(r, i) h(i)
-__global__ void k_gs_update(int64_t n, const cplx* __restrict__ V, int64_t ldv, int ncol, const cplx* __restrict__ h,
-                            cplx* __restrict__ w, const int* active) {
+// One Gram-Schmidt update fused with the partial sums of the next pass, over the same
+// row partition as k_gs_dots: w(r) -= sum_{i < ncol} V(r, i) h(i) for the block's rows
+// (one thread per row, columns in order), then, on the updated rows, the partial sums
+// of conj(V(r, i)) w(r) for i < ndots and, if with_norm, of |w(r)|^2 (as k_gs_dots).
+// Saves a launch and a pass over w per update.
+__global__ __launch_bounds__(GS_THREADS) void k_gs_update_dots(int64_t n, const cplx* __restrict__ V, int64_t ldv,
+                                                               int ncol, const cplx* __restrict__ h,
+                                                               cplx* __restrict__ w, int ndots, int with_norm,
+                                                               cplx* partial, int ldp, const int* active) {
     if (active != nullptr && *active == 0) return;
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    cplx acc = w[r];
-    for (int i = 0; i < ncol; ++i) acc = fms(acc, V[r + (int64_t)i * ldv], h[i]);
-    w[r] = acc;
+    __shared__ cplx ws[1024];
+    __shared__ cplx hs[GS_MAXCOL];
+    const int64_t nblk = gridDim.x;
+    const int64_t rows = (n + nblk - 1) / nblk;
+    const int64_t r0 = blockIdx.x * rows;
+    const int64_t r1 = min(n, r0 + rows);
+    const int ntot = ndots + (with_norm ? 1 : 0);
+    if (r0 >= r1) {
+        for (int i = threadIdx.x; i < ntot; i += GS_THREADS) partial[blockIdx.x * (int64_t)ldp + i] = mk(0.0, 0.0);
+        return;
+    }
+    for (int i = threadIdx.x; i < ncol; i += GS_THREADS) hs[i] = h[i];
+    for (int64_t c0 = r0; c0 < r1; c0 += 1024) {
+        const int64_t c1 = min(r1, c0 + 1024);
+        __syncthreads();
+        for (int64_t r = c0 + threadIdx.x; r < c1; r += GS_THREADS) {
+            cplx acc = w[r];
+            for (int i = 0; i < ncol; ++i) acc = fms(acc, V[r + (int64_t)i * ldv], hs[i]);
+            w[r] = acc;
+            ws[r - c0] = acc;
+        }
+        __syncthreads();
+        chunk_dots(V, ldv, c0, (int)(c1 - c0), ws, ndots, with_norm, partial + blockIdx.x * (int64_t)ldp, c0 == r0);
+    }
 }
 
-// H(0..j, j) = h1 + h2, h_{j+1,j} = ||w||, breakdown test; hn0 / hn1 hold sums of squares.
-__global__ void k_arnoldi_finalize(int j, const cplx* h1, const cplx* h2, const cplx* hn_w, double hn1_sq,
-                                   const cplx* hn1, cplx* H, int ldh, double* hnorm, int* active, int* m_eff) {
+// The reduction of ||w||^2 (as k_gs_reduce, one column) and the end of step j:
+// H(0..j, j) = h1 + h2, h_{j+1,j} = ||w||, breakdown test against ||M v_j|| (h1[j+1]
+// holds its square).
+__global__ __launch_bounds__(256) void k_gs_norm_finalize(const cplx* partial, int nblk, int j, const cplx* h1,
+                                                          const cplx* h2, cplx* hw, cplx* H, int ldh, double* hnorm,
+                                                          int* active, int* m_eff) {
     if (*active == 0) return;
+    __shared__ cplx red[256];
+    cplx acc = mk(0.0, 0.0);
+    for (int b = threadIdx.x; b < nblk; b += 256) acc = acc + partial[b];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + s];
+        __syncthreads();
+    }
     for (int i = threadIdx.x; i <= j; i += blockDim.x) H[i + (int64_t)j * ldh] = h1[i] + h2[i];
     if (threadIdx.x == 0) {
-        const double wn = sqrt(hn_w[0].re);
-        const double w0 = sqrt(hn1[j + 1].re);
-        (void)hn1_sq;
+        hw[0] = red[0];
+        const double wn = sqrt(red[0].re);
+        const double w0 = sqrt(h1[j + 1].re);
         hnorm[0] = wn;
         hnorm[1] = w0;
         if (wn <= 1e-14 * w0) {
@@ -159,23 +212,17 @@ simm_status arnoldi_step(int64_t n, cplx* V, int64_t ldv, int j, cplx* H, int ld
                        1, w.partial, ldp, (const int*)active);
     hipLaunchKernelGGL(k_gs_reduce, dim3(ncol + 1), dim3(256), 0, st, (const cplx*)w.partial, w.nblk, ldp, ncol + 1,
                        w.h1, (const int*)active);
-    hipLaunchKernelGGL(k_gs_update, dim3(blocks), dim3(256), 0, st, n, (const cplx*)V, ldv, ncol, (const cplx*)w.h1, wv,
-                       (const int*)active);
-    // pass 2 (re-orthogonalisation)
-    hipLaunchKernelGGL(k_gs_dots, dim3(w.nblk), dim3(GS_THREADS), 0, st, n, (const cplx*)V, ldv, ncol, (const cplx*)wv,
-                       0, w.partial, ldp, (const int*)active);
+    // w -= V h1, then the partial sums of pass 2 (re-orthogonalisation) on the new w
+    hipLaunchKernelGGL(k_gs_update_dots, dim3(w.nblk), dim3(GS_THREADS), 0, st, n, (const cplx*)V, ldv, ncol,
+                       (const cplx*)w.h1, wv, ncol, 0, w.partial, ldp, (const int*)active);
     hipLaunchKernelGGL(k_gs_reduce, dim3(ncol), dim3(256), 0, st, (const cplx*)w.partial, w.nblk, ldp, ncol, w.h2,
                        (const int*)active);
-    hipLaunchKernelGGL(k_gs_update, dim3(blocks), dim3(256), 0, st, n, (const cplx*)V, ldv, ncol, (const cplx*)w.h2, wv,
-                       (const int*)active);
-    // ||w||
-    hipLaunchKernelGGL(k_gs_dots, dim3(w.nblk), dim3(GS_THREADS), 0, st, n, (const cplx*)nullptr, (int64_t)0, 0,
-                       (const cplx*)wv, 1, w.partial, 1, (const int*)active);
+    // w -= V h2, then ||w||^2
+    hipLaunchKernelGGL(k_gs_update_dots, dim3(w.nblk), dim3(GS_THREADS), 0, st, n, (const cplx*)V, ldv, ncol,
+                       (const cplx*)w.h2, wv, 0, 1, w.partial, 1, (const int*)active);
     cplx* hw = w.h2 + (ncol + 1);
-    hipLaunchKernelGGL(k_gs_reduce, dim3(1), dim3(256), 0, st, (const cplx*)w.partial, w.nblk, 1, 1, hw,
-                       (const int*)active);
-    hipLaunchKernelGGL(k_arnoldi_finalize, dim3(1), dim3(128), 0, st, j, (const cplx*)w.h1, (const cplx*)w.h2,
-                       (const cplx*)hw, 0.0, (const cplx*)w.h1, H, ldh, w.hnorm, active, m_eff);
+    hipLaunchKernelGGL(k_gs_norm_finalize, dim3(1), dim3(256), 0, st, (const cplx*)w.partial, w.nblk, j,
+                       (const cplx*)w.h1, (const cplx*)w.h2, hw, H, ldh, w.hnorm, active, m_eff);
     hipLaunchKernelGGL(k_scale_div, dim3(blocks), dim3(256), 0, st, n, wv, (const double*)w.hnorm, (const int*)active);
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;

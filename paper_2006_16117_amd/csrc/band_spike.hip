@@ -447,6 +447,17 @@ __global__ __launch_bounds__(CH_THREADS) void k_spike_chain(SpikeChain a) {
         }
         __syncthreads();
     }
+    // Leave the group's counters at zero for the next launch on this factor: every
+    // workgroup has left its last poll when it arrives here, so the last to arrive
+    // (second counter of the group's line) clears both.
+    if (nsteps > 0 && tid == 0) {
+        unsigned* leave = counter + 1;
+        const unsigned prev = __hip_atomic_fetch_add(leave, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == gridDim.x - 1) {
+            __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(leave, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
 }
 
 // Second level of the chain: the true start state T_g of every group g >= 1 (from the
@@ -712,6 +723,7 @@ simm_status spike_prepare(SpikeFactor& f, hipStream_t st) {
     f.counter = reinterpret_cast<unsigned*>(take((size_t)(f.G + 1) * (SPIKE_CTR_STRIDE / 4)));
     f.err = reinterpret_cast<int*>(take(4));
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned*>(f.err), 1, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, f.counter, (int)((f.G + 1) * SPIKE_CTR_STRIDE), 0u);
     // per-panel blocks
     const unsigned npan = (unsigned)(n16 / 16);
     hipLaunchKernelGGL(k_blocks_fwd, dim3(npan), dim3(threads_for(kl + 16) <= 512 ? threads_for(kl + 16) : 512), 0, st,
@@ -788,8 +800,8 @@ static simm_status run_chain(const SpikeFactor& f, bool forward, int K, int64_t 
 static simm_status chain_states(const SpikeFactor& f, bool forward, int K, const cplx* Phi, const cplx* tau, cplx* t,
                                 const cplx* Pi, const cplx* PiFull, cplx* gout, cplx* tg, const cplx* init_src,
                                 int64_t init_row0, const int* active, hipStream_t st) {
-    // zero the counters of both chain levels
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, f.counter, (int)((f.G + 1) * SPIKE_CTR_STRIDE), 0u);
+    // the counters are zero here: zeroed when the sweep data was made, and every chain
+    // launch leaves its group's counters at zero when it ends
     SIMM_TRY(run_chain(f, forward, K, f.P, f.L, f.G, Phi, tau, t, gout, init_src, init_row0, f.n, f.counter, active,
                        st));
     if (f.G == 1) return SIMM_OK;

@@ -4,9 +4,9 @@
 //
 // One workgroup evaluates one (square, shift) pair.  The Schur factor T of H_m
 // (packed upper triangle) sits in LDS; each wavefront takes a quadrature point at
-// a time, lanes own rows of yhat, and the upper triangular system
+// a time (four interleaved), lanes own rows of yhat, and the upper triangular system
 // (I + (sigma - z) T) yhat = beta Q^H e_1 is solved by columns from the bottom,
-// the new unknown broadcast with readlane.  With y = Q yhat:
+// the new unknown formed by the lane that owns its row and broadcast with readlane.  With y = Q yhat:
 //   e_m^T y = qlast . yhat  (residual, eq. (error)),  ||y|| = ||yhat||,
 //   s = Q (sum_j w_j yhat_j) / (2 pi i),
 // so the per-point work is one triangular solve.  Partial sums are combined across
@@ -100,61 +100,76 @@ __global__ __launch_bounds__(IND_THREADS) void k_indicators(const ShiftDev* __re
 
     cplx sc0 = mk(0, 0), sc1 = mk(0, 0), sf0 = mk(0, 0), sf1 = mk(0, 0);
     double Tf = 0.0, rmax = 0.0;
-    for (int q = wave; q < npts; q += IND_WAVES) {
-        int e, idx;
-        double t, om;
-        bool coarse;
-        if (q < 4 * g) {
-            e = q / g;
-            idx = q - e * g;
-            t = rule.t1[idx];
-            om = rule.w1[idx];
-            coarse = true;
-        } else {
-            const int q2 = q - 4 * g;
-            e = q2 / (2 * g);
-            idx = q2 - e * 2 * g;
-            t = rule.t2[idx];
-            om = rule.w2[idx];
-            coarse = false;
+    // Wave w takes the points q = w + 4 t in order of t, NP of them at a time: their
+    // triangular solves share the LDS column reads and interleave NP independent chains
+    // of lane broadcasts (per point, the operations and the accumulation order are those
+    // of one point at a time).
+    constexpr int NP = 4;
+    const int npw = (npts - wave + IND_WAVES - 1) / IND_WAVES;
+    const cplx one = mk(1.0, 0.0);
+    for (int t0 = 0; t0 < npw; t0 += NP) {
+        cplx alpha[NP], dinv0[NP], dinv1[NP], r0[NP], r1[NP], wq[NP];
+        bool coarse[NP];
+#pragma unroll
+        for (int u = 0; u < NP; ++u) {
+            const int q = wave + IND_WAVES * min(t0 + u, npw - 1);   // past the end: a copy of the last point
+            int e, idx;
+            double t, om;
+            if (q < 4 * g) {
+                e = q / g;
+                idx = q - e * g;
+                t = rule.t1[idx];
+                om = rule.w1[idx];
+                coarse[u] = true;
+            } else {
+                const int q2 = q - 4 * g;
+                e = q2 / (2 * g);
+                idx = q2 - e * 2 * g;
+                t = rule.t2[idx];
+                om = rule.w2[idx];
+                coarse[u] = false;
+            }
+            cplx z;
+            node(cx, cy, h, e, t, om, z, wq[u]);
+            alpha[u] = mk(sh.sig_re - z.re, sh.sig_im - z.im);
+            dinv0[u] = cdiv(one, one + alpha[u] * t00);
+            dinv1[u] = cdiv(one, one + alpha[u] * t11);
+            r0[u] = g0;
+            r1[u] = g1;
         }
-        cplx z, wq;
-        node(cx, cy, h, e, t, om, z, wq);
-        const cplx alpha = mk(sh.sig_re - z.re, sh.sig_im - z.im);
-        const cplx one = mk(1.0, 0.0);
-        const cplx dinv0 = cdiv(one, one + alpha * t00);
-        const cplx dinv1 = cdiv(one, one + alpha * t11);
-        cplx r0 = g0, r1 = g1;
         for (int j = m - 1; j >= 0; --j) {
             const int oj = j & 63;
-            cplx rj, dj;
-            if (j < 64) {
-                rj = readlane_c(r0, oj);
-                dj = readlane_c(dinv0, oj);
-            } else {
-                rj = readlane_c(r1, oj);
-                dj = readlane_c(dinv1, oj);
-            }
-            const cplx yj = rj * dj;
-            const cplx cj = alpha * yj;
             const cplx* col = Ts + j * (j + 1) / 2;
-            if (i0 < j) r0 = fms(r0, col[i0], cj);
-            if (i1 < j) r1 = fms(r1, col[i1], cj);
-            if (i0 == j) r0 = yj;
-            if (i1 == j) r1 = yj;
+            cplx c0 = mk(0.0, 0.0), c1 = mk(0.0, 0.0);
+            if (i0 < j) c0 = col[i0];
+            if (i1 < j) c1 = col[i1];
+#pragma unroll
+            for (int u = 0; u < NP; ++u) {
+                // the lane owning row j forms y_j = r_j / (1 + alpha T_jj); one broadcast
+                const cplx yj = (j < 64) ? readlane_c(r0[u] * dinv0[u], oj) : readlane_c(r1[u] * dinv1[u], oj);
+                const cplx cj = alpha[u] * yj;
+                if (i0 < j) r0[u] = fms(r0[u], c0, cj);
+                if (i1 < j) r1[u] = fms(r1[u], c1, cj);
+                if (i0 == j) r0[u] = yj;
+                if (i1 == j) r1[u] = yj;
+            }
         }
-        // r0, r1 hold yhat
-        const cplx dot = wave_sum_c(q0 * r0 + q1 * r1);
-        const double nrm2 = wave_sum_d(norm2(r0) + norm2(r1));
-        const double rho = cabs(alpha) * sh.h_last * cabs(dot) / sh.beta;
-        rmax = fmax(rmax, rho);
-        if (coarse) {
-            sc0 = fma_c(sc0, wq, r0);
-            sc1 = fma_c(sc1, wq, r1);
-        } else {
-            sf0 = fma_c(sf0, wq, r0);
-            sf1 = fma_c(sf1, wq, r1);
-            Tf += cabs(wq) * sqrt(nrm2);
+        // r0, r1 hold yhat of each point
+#pragma unroll
+        for (int u = 0; u < NP; ++u) {
+            if (t0 + u >= npw) break;
+            const cplx dot = wave_sum_c(q0 * r0[u] + q1 * r1[u]);
+            const double nrm2 = wave_sum_d(norm2(r0[u]) + norm2(r1[u]));
+            const double rho = cabs(alpha[u]) * sh.h_last * cabs(dot) / sh.beta;
+            rmax = fmax(rmax, rho);
+            if (coarse[u]) {
+                sc0 = fma_c(sc0, wq[u], r0[u]);
+                sc1 = fma_c(sc1, wq[u], r1[u]);
+            } else {
+                sf0 = fma_c(sf0, wq[u], r0[u]);
+                sf1 = fma_c(sf1, wq[u], r1[u]);
+                Tf += cabs(wq[u]) * sqrt(nrm2);
+            }
         }
     }
     red[wave][0][i0] = sc0;

@@ -49,6 +49,15 @@ class simm_params(C.Structure):
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2006_16117_amd.build`")
+# One HIP runtime per process.  ROCm builds of torch ship their own libamdhip64; loaded
+# first, it also serves the library (its libamdhip64.so.7 dependency resolves to the
+# runtime already in the process), so torch tensors and the library's allocations and
+# streams live in the same runtime.  Loading the library first pulls in /opt/rocm's
+# runtime and a later torch import adds a second one.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
 _lib = C.CDLL(LIB_PATH)
 
 _vp, _dp, _ip64, _i32, _i64, _d = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32, C.c_int64, C.c_double

@@ -174,21 +174,24 @@ __global__ __launch_bounds__(1024) void k_blocks_bwd(int64_t n, int K, int kv, i
 // ---------------------------------------------------------------------------
 // forward (L) chunk sweep, 16 columns per step
 // ---------------------------------------------------------------------------
-template <int T>
+// NR right-hand sides per workgroup (unit-state responses only: NR unit vectors
+// r0 .. r0+NR-1, r0 = NR blockIdx.y, share every panel block the workgroup loads;
+// zero-state sweeps use NR = 1).
+template <int T, int NR>
 __global__ __launch_bounds__(T) void k_chunk_fwd(SpikeFwd a) {
     if (a.active != nullptr && *a.active == 0) return;
     extern __shared__ double2 sraw[];
     const int tid = threadIdx.x, lane = tid & 63;
     const int kl = a.kl, RW = kl + 16;
-    const int c = blockIdx.x, r_unit = blockIdx.y;
+    const int c = blockIdx.x, r0 = blockIdx.y * NR;
     const int64_t J0 = (int64_t)c * a.s, J1 = min(a.n16, J0 + a.s);
     const int len = (int)(J1 - J0);
     const int npan = len / 16;
-    // LDS: window values by slot (2 x RW, alternating per panel), the chunk's outputs
-    // (len), its input rows J0+kl .. J1+RW-1 (len + 16) and its pivots (len)
+    // LDS: window values by slot (2 x NR x RW, alternating per panel), the chunk's
+    // outputs (NR x len), its input rows J0+kl .. J1+RW-1 (len + 16) and its pivots (len)
     cplx* S = reinterpret_cast<cplx*>(sraw);
-    cplx* outb = S + 2 * RW;
-    cplx* inb = outb + len;
+    cplx* outb = S + 2 * NR * RW;
+    cplx* inb = outb + NR * len;
     int* pivb = reinterpret_cast<int*>(inb + len + 16);
     for (int q = tid; q < len; q += T) pivb[q] = a.ipiv[J0 + q] - (int)(J0 + (q & ~15));
     for (int q = tid; q < len + 16; q += T) {
@@ -200,9 +203,13 @@ __global__ __launch_bounds__(T) void k_chunk_fwd(SpikeFwd a) {
     // thread tid owns LDS slot tid; the row in it has window position pos; the slot
     // of position 0 is `off`
     int pos = tid, off = 0;
-    cplx val = mk(0.0, 0.0);
-    if (mine) val = (a.mode == 0) ? ((pos >= kl) ? inb[pos - kl] : mk(0.0, 0.0))
-                                  : mk(pos == r_unit ? 1.0 : 0.0, 0.0);
+    cplx val[NR];
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+        val[u] = mk(0.0, 0.0);
+        if (mine) val[u] = (a.mode == 0) ? ((pos >= kl) ? inb[pos - kl] : mk(0.0, 0.0))
+                                         : mk(pos == r0 + u ? 1.0 : 0.0, 0.0);
+    }
     const int64_t p0 = J0 / 16;
     // The block row of my next position is loaded one panel ahead, into the other
     // of two register sets; no global load sits in a branch, so the waits for what a
@@ -219,7 +226,10 @@ __global__ __launch_bounds__(T) void k_chunk_fwd(SpikeFwd a) {
         const int buf = i & 1;
         const int pos_n = (pos >= 16) ? pos - 16 : pos + RW - 16;
         prefetch(gn, min(p + 1, a.n16 / 16 - 1), pos_n);   // unconditional: no branch around loads
-        if (mine) ldsw(S + buf * RW + tid, val);
+        if (mine) {
+#pragma unroll
+            for (int u = 0; u < NR; ++u) ldsw(S + (buf * NR + u) * RW + tid, val[u]);
+        }
         lds_barrier();
         int pv[16];
 #pragma unroll
@@ -228,17 +238,21 @@ __global__ __launch_bounds__(T) void k_chunk_fwd(SpikeFwd a) {
             const int sl = ps + off;
             return sl >= RW ? sl - RW : sl;
         };
-        const cplx v2 = ldsr(S + buf * RW + slot(trace_src16(mine ? pos : 0, pv)));
-        const cplx tq = ldsr(S + buf * RW + slot(trace_src16(lane & 15, pv)));
-        cplx acc = (pos >= 16) ? v2 : mk(0.0, 0.0);
+        const int sv = slot(trace_src16(mine ? pos : 0, pv)), st = slot(trace_src16(lane & 15, pv));
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc = fma_c(acc, gc[q], rdl(tq, q));
-        if (mine) {
-            if (pos < 16) {
-                ldsw(outb + 16 * i + pos, acc);
-                val = inb[16 * i + 16 + pos];          // row J0 + 16 i + RW + pos enters
-            } else {
-                val = acc;
+        for (int u = 0; u < NR; ++u) {
+            const cplx v2 = ldsr(S + (buf * NR + u) * RW + sv);
+            const cplx tq = ldsr(S + (buf * NR + u) * RW + st);
+            cplx acc = (pos >= 16) ? v2 : mk(0.0, 0.0);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc = fma_c(acc, gc[q], rdl(tq, q));
+            if (mine) {
+                if (pos < 16) {
+                    ldsw(outb + u * len + 16 * i + pos, acc);
+                    val[u] = inb[16 * i + 16 + pos];          // row J0 + 16 i + RW + pos enters
+                } else {
+                    val[u] = acc;
+                }
             }
         }
         pos = pos_n;
@@ -252,16 +266,25 @@ __global__ __launch_bounds__(T) void k_chunk_fwd(SpikeFwd a) {
     if (i < npan) step(i, gA, gB);
     // end state: rows J1 .. J1+kl-1 hold positions 0 .. kl-1
     if (mine && pos < kl) {
-        if (a.mode == 0) a.tau[(int64_t)c * kl + pos] = val;
-        else a.Phi[((int64_t)c * kl + pos) * kl + r_unit] = val;    // Phi_c(i, r) at [c][i][r]
+        if (a.mode == 0) {
+            a.tau[(int64_t)c * kl + pos] = val[0];
+        } else {
+#pragma unroll
+            for (int u = 0; u < NR; ++u)   // Phi_c(i, r) at [c][i][r]
+                if (r0 + u < kl) a.Phi[((int64_t)c * kl + pos) * kl + r0 + u] = val[u];
+        }
     }
     __syncthreads();
-    for (int q = tid; q < len; q += T) {
-        const cplx v = ldsr(outb + q);
-        if (a.mode == 0) {
+    if (a.mode == 0) {
+        for (int q = tid; q < len; q += T) {
+            const cplx v = ldsr(outb + q);
             if (J0 + q < a.n) a.y[J0 + q] = v;
-        } else {
-            a.Psi[J0 + q + (int64_t)r_unit * a.n16] = v;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+            if (r0 + u >= kl) continue;
+            for (int q = tid; q < len; q += T) a.Psi[J0 + q + (int64_t)(r0 + u) * a.n16] = ldsr(outb + u * len + q);
         }
     }
 }
@@ -269,20 +292,20 @@ __global__ __launch_bounds__(T) void k_chunk_fwd(SpikeFwd a) {
 // ---------------------------------------------------------------------------
 // backward (U) chunk sweep, 16 columns per step (bottom panel first)
 // ---------------------------------------------------------------------------
-template <int T>
+template <int T, int NR>
 __global__ __launch_bounds__(T) void k_chunk_bwd(SpikeBwd a) {
     if (a.active != nullptr && *a.active == 0) return;
     extern __shared__ double2 sraw[];
     const int tid = threadIdx.x, lane = tid & 63;
     const int K = a.K, RW = K + 16;
-    const int c = blockIdx.x, r_unit = blockIdx.y;
+    const int c = blockIdx.x, r0 = blockIdx.y * NR;
     const int64_t J0 = (int64_t)c * a.s, J1 = min(a.n16, J0 + a.s);
     const int len = (int)(J1 - J0);
     const int npan = len / 16;
-    // LDS: window (2 x RW), outputs (len), input rows J0-K-16 .. J1-K-1 (len + 16)
+    // LDS: window (2 x NR x RW), outputs (NR x len), input rows J0-K-16 .. J1-K-1 (len + 16)
     cplx* S = reinterpret_cast<cplx*>(sraw);
-    cplx* outb = S + 2 * RW;
-    cplx* inb = outb + len;
+    cplx* outb = S + 2 * NR * RW;
+    cplx* inb = outb + NR * len;
     const int64_t in0 = J0 - K - 16;
     for (int q = tid; q < len + 16; q += T) {
         const int64_t row = in0 + q;
@@ -294,9 +317,13 @@ __global__ __launch_bounds__(T) void k_chunk_bwd(SpikeBwd a) {
     // state rows of the chunk end (J1-K .. J1-1) start at positions 16 .. K+15
     int pos = tid, off = 0;
     const int64_t pl = J1 / 16 - 1;             // first (lowest) panel
-    cplx val = mk(0.0, 0.0);
-    if (mine) val = (a.mode == 0) ? ((pos < 16) ? inb[(16 * pl - K + pos) - in0] : mk(0.0, 0.0))
-                                  : mk(pos - 16 == r_unit ? 1.0 : 0.0, 0.0);
+    cplx val[NR];
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+        val[u] = mk(0.0, 0.0);
+        if (mine) val[u] = (a.mode == 0) ? ((pos < 16) ? inb[(16 * pl - K + pos) - in0] : mk(0.0, 0.0))
+                                         : mk(pos - 16 == r0 + u ? 1.0 : 0.0, 0.0);
+    }
     cplx hA[16], hB[16];
     auto prefetch = [&](cplx (&h)[16], int64_t p, int ps) {
         const cplx* hp = a.H + p * 16 * RW + (mine ? ps : 0);
@@ -309,20 +336,26 @@ __global__ __launch_bounds__(T) void k_chunk_bwd(SpikeBwd a) {
         const int buf = i & 1;
         const int pos_n = (pos < K) ? pos + 16 : pos - K;
         prefetch(hn, max(p - 1, (int64_t)0), pos_n);   // unconditional: no branch around loads
-        if (mine) ldsw(S + buf * RW + tid, val);
+        if (mine) {
+#pragma unroll
+            for (int u = 0; u < NR; ++u) ldsw(S + (buf * NR + u) * RW + tid, val[u]);
+        }
         lds_barrier();
         int sl = K + (lane & 15) + off;
         sl = sl >= RW ? sl - RW : sl;
-        const cplx bq = ldsr(S + buf * RW + sl);
-        cplx acc = (pos < K) ? val : mk(0.0, 0.0);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc = fma_c(acc, hc[q], rdl(bq, q));
-        if (mine) {
-            if (pos >= K) {
-                ldsw(outb + (16 * p - J0) + pos - K, acc);
-                val = inb[(16 * p - 16 - K + pos - K) - in0];   // row j0-16-K + (pos-K) enters
-            } else {
-                val = acc;
+        for (int u = 0; u < NR; ++u) {
+            const cplx bq = ldsr(S + (buf * NR + u) * RW + sl);
+            cplx acc = (pos < K) ? val[u] : mk(0.0, 0.0);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc = fma_c(acc, hc[q], rdl(bq, q));
+            if (mine) {
+                if (pos >= K) {
+                    ldsw(outb + u * len + (16 * p - J0) + pos - K, acc);
+                    val[u] = inb[(16 * p - 16 - K + pos - K) - in0];   // row j0-16-K + (pos-K) enters
+                } else {
+                    val[u] = acc;
+                }
             }
         }
         pos = pos_n;
@@ -336,16 +369,25 @@ __global__ __launch_bounds__(T) void k_chunk_bwd(SpikeBwd a) {
     if (i < npan) step(i, hA, hB);
     // end state: rows J0-K .. J0-1 hold positions 16 .. K+15
     if (mine && pos >= 16) {
-        if (a.mode == 0) a.tau[(int64_t)c * K + pos - 16] = val;
-        else a.Phi[((int64_t)c * K + pos - 16) * K + r_unit] = val;
+        if (a.mode == 0) {
+            a.tau[(int64_t)c * K + pos - 16] = val[0];
+        } else {
+#pragma unroll
+            for (int u = 0; u < NR; ++u)
+                if (r0 + u < K) a.Phi[((int64_t)c * K + pos - 16) * K + r0 + u] = val[u];
+        }
     }
     __syncthreads();
-    for (int q = tid; q < len; q += T) {
-        const cplx v = ldsr(outb + q);
-        if (a.mode == 0) {
+    if (a.mode == 0) {
+        for (int q = tid; q < len; q += T) {
+            const cplx v = ldsr(outb + q);
             if (J0 + q < a.n) a.y[J0 + q] = v;
-        } else {
-            a.Psi[J0 + q + (int64_t)r_unit * a.n16] = v;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+            if (r0 + u >= K) continue;
+            for (int q = tid; q < len; q += T) a.Psi[J0 + q + (int64_t)(r0 + u) * a.n16] = ldsr(outb + u * len + q);
         }
     }
 }
@@ -570,26 +612,68 @@ namespace {
 
 int threads_for(int rows) { return rows <= 256 ? 256 : (rows <= 512 ? 512 : 1024); }
 
-template <typename Args>
-simm_status launch_fwd(const Args& a, int64_t P, int nrhs, int W, size_t lds, hipStream_t st) {
-    if (W <= 256) hipLaunchKernelGGL(k_chunk_fwd<256>, dim3((unsigned)P, nrhs), dim3(256), lds, st, a);
-    else if (W <= 512) hipLaunchKernelGGL(k_chunk_fwd<512>, dim3((unsigned)P, nrhs), dim3(512), lds, st, a);
-    else hipLaunchKernelGGL(k_chunk_fwd<1024>, dim3((unsigned)P, nrhs), dim3(1024), lds, st, a);
-    SIMM_HIP_TRY(hipGetLastError());
-    return SIMM_OK;
-}
-template <typename Args>
-simm_status launch_bwd(const Args& a, int64_t P, int nrhs, int W, size_t lds, hipStream_t st) {
-    if (W <= 256) hipLaunchKernelGGL(k_chunk_bwd<256>, dim3((unsigned)P, nrhs), dim3(256), lds, st, a);
-    else if (W <= 512) hipLaunchKernelGGL(k_chunk_bwd<512>, dim3((unsigned)P, nrhs), dim3(512), lds, st, a);
-    else hipLaunchKernelGGL(k_chunk_bwd<1024>, dim3((unsigned)P, nrhs), dim3(1024), lds, st, a);
-    SIMM_HIP_TRY(hipGetLastError());
-    return SIMM_OK;
+// window (2 NR rows) + outputs (NR s) + inputs (s + 16) complex, and s pivots
+size_t window_lds(int rows, int64_t s, int nr = 1) {
+    return sizeof(cplx) * (2 * (size_t)nr * rows + (size_t)(nr + 1) * s + 16) + sizeof(int) * (size_t)s;
 }
 
-// window (2 rows) + outputs (s) + inputs (s + 16) complex, and s pivots
-size_t window_lds(int rows, int64_t s) {
-    return sizeof(cplx) * (2 * (size_t)rows + 2 * (size_t)s + 16) + sizeof(int) * (size_t)s;
+constexpr size_t LDS_LIMIT = 150 * 1024;   // as the chunk-length cap
+
+// Zero-state sweeps (nrhs = 1) or the unit-state responses of all `nrhs` state rows,
+// up to 4 of them per workgroup where the LDS allows it (the 1024-thread kernels, one).
+template <typename Args>
+simm_status launch_fwd(const Args& a, int64_t P, int nrhs, int W, int rows, int64_t s, hipStream_t st) {
+    int nr = 1;
+    if (nrhs > 1) {
+        const int cap = (W <= 512) ? 4 : 1;
+        for (int t = cap; t > 1; t /= 2)
+            if (window_lds(rows, s, t) <= LDS_LIMIT) {
+                nr = t;
+                break;
+            }
+    }
+    const size_t lds = window_lds(rows, s, nr);
+    const dim3 grid((unsigned)P, (unsigned)((nrhs + nr - 1) / nr));
+    if (W <= 256) {
+        if (nr == 4) hipLaunchKernelGGL((k_chunk_fwd<256, 4>), grid, dim3(256), lds, st, a);
+        else if (nr == 2) hipLaunchKernelGGL((k_chunk_fwd<256, 2>), grid, dim3(256), lds, st, a);
+        else hipLaunchKernelGGL((k_chunk_fwd<256, 1>), grid, dim3(256), lds, st, a);
+    } else if (W <= 512) {
+        if (nr == 4) hipLaunchKernelGGL((k_chunk_fwd<512, 4>), grid, dim3(512), lds, st, a);
+        else if (nr == 2) hipLaunchKernelGGL((k_chunk_fwd<512, 2>), grid, dim3(512), lds, st, a);
+        else hipLaunchKernelGGL((k_chunk_fwd<512, 1>), grid, dim3(512), lds, st, a);
+    } else {
+        hipLaunchKernelGGL((k_chunk_fwd<1024, 1>), grid, dim3(1024), lds, st, a);
+    }
+    SIMM_HIP_TRY(hipGetLastError());
+    return SIMM_OK;
+}
+template <typename Args>
+simm_status launch_bwd(const Args& a, int64_t P, int nrhs, int W, int rows, int64_t s, hipStream_t st) {
+    int nr = 1;
+    if (nrhs > 1) {
+        const int cap = (W <= 512) ? 4 : 1;
+        for (int t = cap; t > 1; t /= 2)
+            if (window_lds(rows, s, t) <= LDS_LIMIT) {
+                nr = t;
+                break;
+            }
+    }
+    const size_t lds = window_lds(rows, s, nr);
+    const dim3 grid((unsigned)P, (unsigned)((nrhs + nr - 1) / nr));
+    if (W <= 256) {
+        if (nr == 4) hipLaunchKernelGGL((k_chunk_bwd<256, 4>), grid, dim3(256), lds, st, a);
+        else if (nr == 2) hipLaunchKernelGGL((k_chunk_bwd<256, 2>), grid, dim3(256), lds, st, a);
+        else hipLaunchKernelGGL((k_chunk_bwd<256, 1>), grid, dim3(256), lds, st, a);
+    } else if (W <= 512) {
+        if (nr == 4) hipLaunchKernelGGL((k_chunk_bwd<512, 4>), grid, dim3(512), lds, st, a);
+        else if (nr == 2) hipLaunchKernelGGL((k_chunk_bwd<512, 2>), grid, dim3(512), lds, st, a);
+        else hipLaunchKernelGGL((k_chunk_bwd<512, 1>), grid, dim3(512), lds, st, a);
+    } else {
+        hipLaunchKernelGGL((k_chunk_bwd<1024, 1>), grid, dim3(1024), lds, st, a);
+    }
+    SIMM_HIP_TRY(hipGetLastError());
+    return SIMM_OK;
 }
 
 }  // namespace
@@ -742,7 +826,7 @@ simm_status spike_prepare(SpikeFactor& f, hipStream_t st) {
     a.mode = 1;
     a.Psi = f.PsiL;
     a.Phi = f.PhiL;
-    SIMM_TRY(launch_fwd(a, f.P, kl, f.Wf, window_lds(kl + 16, f.s), st));
+    SIMM_TRY(launch_fwd(a, f.P, kl, f.Wf, kl + 16, f.s, st));
     SpikeBwd b{};
     b.n = f.n;
     b.n16 = n16;
@@ -752,7 +836,7 @@ simm_status spike_prepare(SpikeFactor& f, hipStream_t st) {
     b.mode = 1;
     b.Psi = f.PsiU;
     b.Phi = f.PhiU;
-    SIMM_TRY(launch_bwd(b, f.P, K, f.Wb, window_lds(K + 16, f.s), st));
+    SIMM_TRY(launch_bwd(b, f.P, K, f.Wb, K + 16, f.s, st));
     if (f.G > 1) {
         SIMM_TRY(transfer_products(f, true, kl, f.PhiL, f.PiL, f.PiFullL, st));
         SIMM_TRY(transfer_products(f, false, K, f.PhiU, f.PiU, f.PiFullU, st));
@@ -835,7 +919,7 @@ simm_status spike_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int*
     a.y = z;
     a.tau = f.tauL;
     a.active = active;
-    SIMM_TRY(launch_fwd(a, f.P, 1, f.Wf, window_lds(f.klx + 16, f.s), st));
+    SIMM_TRY(launch_fwd(a, f.P, 1, f.Wf, f.klx + 16, f.s, st));
     SIMM_TRY(chain_states(f, true, f.klx, f.PhiL, f.tauL, f.tL, f.PiL, f.PiFullL, f.goutL, f.tgL, u, 0, active, st));
     hipLaunchKernelGGL(k_spike_correct, dim3(blocks), dim3(256), sizeof(cplx) * 2 * f.klx, st, f.n, f.n16, f.klx, f.s,
                        (const cplx*)f.PsiL, (const cplx*)f.tL, z, active);
@@ -851,7 +935,7 @@ simm_status spike_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int*
     b.y = y;
     b.tau = f.tauU;
     b.active = active;
-    SIMM_TRY(launch_bwd(b, f.P, 1, f.Wb, window_lds(f.K + 16, f.s), st));
+    SIMM_TRY(launch_bwd(b, f.P, 1, f.Wb, f.K + 16, f.s, st));
     SIMM_TRY(chain_states(f, false, f.K, f.PhiU, f.tauU, f.tU, f.PiU, f.PiFullU, f.goutU, f.tgU, z, f.n16 - f.K, active,
                           st));
     hipLaunchKernelGGL(k_spike_correct, dim3(blocks), dim3(256), sizeof(cplx) * 2 * f.K, st, f.n, f.n16, f.K, f.s,

@@ -683,9 +683,10 @@ int64_t spike_chunk_len(int64_t n16, int kl, int K) {
     if (const char* e = getenv("SIMM_SPIKE_CHUNK")) s = atoll(e);
     // balance the chunk sweeps (~s/16 panel steps of ~2 us) against the two-level chain
     // (~L + G steps of ~5-12 us) and the per-shift unit-state responses, whose fixed cost
-    // per chunk grows with P: s ~ sqrt(100 n) / 2 (n = 40,000 step medians: s = 500, 750,
-    // 1000, 1250, 2000 -> ~780, ~750, ~700, ~720, ~815 ms)
-    if (s <= 0) s = (int64_t)std::sqrt((double)n16 * 100.0) / 2;
+    // per chunk grows with P: s ~ (3/8) sqrt(100 n) (n = 40,000 step medians with the
+    // multi-vector unit-state responses: s = 500, 750, 1000, 1250 -> ~675, ~663, ~683,
+    // ~700 ms)
+    if (s <= 0) s = (int64_t)(std::sqrt((double)n16 * 100.0) * 0.375);
     // k_spike_correct stages the states of at most two chunks per 256-row block
     s = std::max<int64_t>(s, 256);
     s = std::max<int64_t>(s, std::max(kl, K) + 16);

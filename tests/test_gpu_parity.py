@@ -452,6 +452,30 @@ def test_empty_inputs(S):
     torch.cuda.synchronize()
 
 
+def test_project_errors(S):
+    """simm_project's argument errors: unknown precision, neither X nor norms, a basis
+    released at the end of its run."""
+    import torch
+    pen, f, params = make_workload("cfg0")
+    say("projection errors")
+    P = S.Pencil.from_workload(pen)
+    sh = S.simm_shift_build(P, 0.1 + 0.1j, f, 20)
+    Y = torch.ones((3, 20), dtype=torch.complex128, device="cuda")
+    nd = torch.zeros(3, dtype=torch.float64, device="cuda")
+    for prec in (3, -1):
+        with pytest.raises(S.SimmError) as e:
+            S.simm_project(sh, Y.T, None, nd, precision=prec)
+        assert e.value.status == -1
+    with pytest.raises(S.SimmError) as e:
+        S.simm_project(sh, Y.T, None, None)
+    assert e.value.status == -1
+    prm = S.params_from_dict(dict(params, levels=2), flags=S.SIMM_FLAG_RELEASE_FACTORS)
+    res = S.simm_run(P, f, prm)
+    with pytest.raises(S.SimmError) as e:
+        S.simm_project(res.shift(0), Y.T, None, nd)
+    assert e.value.status == -1
+
+
 def test_region_without_eigenvalues(S):
     """Every level-1 square rejected: the later levels test nothing, no clusters."""
     pen, f, params = make_workload("cfg0")

@@ -591,3 +591,40 @@ def riesz_apply(A: np.ndarray, B: np.ndarray, g_vec: np.ndarray, center: complex
     for zj, wj in zip(z, w):
         acc += wj * np.linalg.solve(A - zj * B, Bg)
     return -acc / (2j * np.pi)
+
+
+# --------------------------------------------------------------------------
+# Differentiation of the projected-vector norms (adjoint method).
+#   J(A) = sum_R ||x_R||^2,   x_R = (1/2 pi i) sum_{j in F(R)} w_j (A - z_j B)^{-1} f,
+# the fine-rule quadrature of eq. (XLXf) over fixed squares R.  With
+# u_j = (A - z_j B)^{-1} f, lam_j = (A - z_j B)^{-H} x_R and c_j = w_j / (2 pi i),
+# differentiating (A - z_j B)^{-1} gives dJ = -2 Re sum_R sum_j c_j lam_j^H dA u_j, so
+#   dJ/dp for A = A0 + p A1:           -2 Re sum_R sum_j c_j lam_j^H A1 u_j,
+#   dJ/dRe(A_ii) + i dJ/dIm(A_ii):     -2 conj(t_i),  t_i = sum_R sum_j c_j conj(lam_j,i) u_j,i.
+# Dense direct solves; used to check the library's Krylov-space gradient.
+# --------------------------------------------------------------------------
+
+def projected_norms(A: np.ndarray, B: np.ndarray, f: np.ndarray, squares, g: int) -> tuple[float, list]:
+    """J and the vectors x_R for squares given as (centre, width); fine rule of 2g per edge."""
+    xs = [direct_projection(A, B, f, c, w, 2 * g) for c, w in squares]
+    return float(sum(np.vdot(x, x).real for x in xs)), xs
+
+
+def projected_norms_gradient(A: np.ndarray, A1: np.ndarray, B: np.ndarray, f: np.ndarray, squares,
+                             g: int) -> tuple[float, float, np.ndarray]:
+    """(J, dJ/dp, dJ/dRe(diag A) + i dJ/dIm(diag A)) by the adjoint method."""
+    n = A.shape[0]
+    J = 0.0
+    dp = 0.0
+    t = np.zeros(n, dtype=np.complex128)
+    for c, w in squares:
+        z, wq = edge_rule(c, w, 2 * g)
+        cj = wq / (2j * np.pi)
+        U = [np.linalg.solve(A - zj * B, f) for zj in z]
+        x = sum(ck * u for ck, u in zip(cj, U))
+        J += float(np.vdot(x, x).real)
+        for zj, ck, u in zip(z, cj, U):
+            lam = np.linalg.solve((A - zj * B).conj().T, x)
+            dp += -2.0 * (ck * np.vdot(lam, A1 @ u)).real
+            t += ck * lam.conj() * u
+    return J, dp, -2.0 * t.conj()

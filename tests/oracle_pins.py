@@ -432,3 +432,37 @@ def check_p16_cluster_projection_direct(O, run=None):
         D /= 2j * np.pi
         err = np.linalg.norm(Xc - D) / np.linalg.norm(D)
         assert err <= 1e-8, (c.lam, err)
+
+
+# P17 -- gradient of the projected-vector norms: the adjoint gradient against central
+# finite differences of J itself (h = 1e-6), for A = A0 + p A1 and for the real and
+# imaginary parts of diagonal entries.  J is the direct quadrature pinned by P4/P16.
+def gradient_case(O):
+    pen, f = random_band_pencil(60, 2, 7, b_kind="tridiag", b_offdiag=0.2)
+    A, B = O.pencil_dense(pen)
+    rng = np.random.default_rng(3)
+    A1 = np.diag(rng.standard_normal(60)) * 0.3 + np.diag(rng.standard_normal(59), 1) * 0.1
+    ev = np.linalg.eigvals(np.linalg.solve(B, A))
+    # three squares around eigenvalues (none on an edge), one far from every eigenvalue
+    squares = [(complex(round(l.real, 1), round(l.imag, 1)), 0.4) for l in ev[:3]] + [(5.0 + 5.0j, 0.4)]
+    return A, A1, B, f, squares
+
+
+def check_p17_gradient(O, h=1e-6):
+    A, A1, B, f, squares = gradient_case(O)
+    g = 8
+    J, dp, gd = O.projected_norms_gradient(A, A1, B, f, squares, g)
+    J0, _ = O.projected_norms(A, B, f, squares, g)
+    assert abs(J - J0) <= 1e-12 * J0
+    Jp, _ = O.projected_norms(A + h * A1, B, f, squares, g)
+    Jm, _ = O.projected_norms(A - h * A1, B, f, squares, g)
+    fd = (Jp - Jm) / (2 * h)
+    assert abs(dp - fd) <= 1e-6 * abs(fd), (dp, fd)
+    scale = np.max(np.abs(gd))
+    for i in (0, 7, 33, 59):
+        E = np.zeros_like(A)
+        E[i, i] = 1.0
+        fr = (O.projected_norms(A + h * E, B, f, squares, g)[0] - O.projected_norms(A - h * E, B, f, squares, g)[0]) / (2 * h)
+        fi = (O.projected_norms(A + 1j * h * E, B, f, squares, g)[0]
+              - O.projected_norms(A - 1j * h * E, B, f, squares, g)[0]) / (2 * h)
+        assert abs(gd[i] - (fr + 1j * fi)) <= 1e-6 * scale, (i, gd[i], fr + 1j * fi)

@@ -264,6 +264,52 @@ MULT_MUTANTS = {
 }
 
 
+def test_p17_gradient():
+    P.check_p17_gradient(O)
+
+
+def _grad_no_adjoint(A, A1, B, f, squares, g):
+    # lam from (A - z B) instead of its conjugate transpose
+    n = A.shape[0]
+    J, dp, t = 0.0, 0.0, np.zeros(n, dtype=np.complex128)
+    for c, w in squares:
+        z, wq = O.edge_rule(c, w, 2 * g)
+        cj = wq / (2j * np.pi)
+        U = [np.linalg.solve(A - zj * B, f) for zj in z]
+        x = sum(ck * u for ck, u in zip(cj, U))
+        J += float(np.vdot(x, x).real)
+        for zj, ck, u in zip(z, cj, U):
+            lam = np.linalg.solve(A - zj * B, x)
+            dp += -2.0 * (ck * np.vdot(lam, A1 @ u)).real
+            t += ck * lam.conj() * u
+    return J, dp, -2.0 * t.conj()
+
+
+def _grad_no_conj(A, A1, B, f, squares, g):
+    # the diagonal gradient without the final conjugation (d/dRe - i d/dIm)
+    J, dp, gd = O.projected_norms_gradient(A, A1, B, f, squares, g)
+    return J, dp, gd.conj()
+
+
+def _grad_coarse_rule(A, A1, B, f, squares, g):
+    # adjoint sums over the g-point rule while J uses the fine rule
+    return O.projected_norms_gradient(A, A1, B, f, squares, g // 2)
+
+
+GRAD_MUTANTS = {
+    "adjoint solve without conjugate transpose": dict(projected_norms_gradient=_grad_no_adjoint),
+    "diagonal gradient not conjugated": dict(projected_norms_gradient=_grad_no_conj),
+    "gradient on the coarse rule": dict(projected_norms_gradient=_grad_coarse_rule),
+}
+
+
+@pytest.mark.parametrize("name", sorted(GRAD_MUTANTS))
+def test_planted_gradient_mistake_is_caught(name):
+    mod = _mutant(**GRAD_MUTANTS[name])
+    with pytest.raises(AssertionError):
+        P.check_p17_gradient(mod)
+
+
 @pytest.mark.parametrize("name", sorted(MULT_MUTANTS))
 def test_planted_multiplicity_mistake_is_caught(name, planted_run):
     mod = _mutant(**MULT_MUTANTS[name])

@@ -194,6 +194,32 @@ simm_status simm_indicators(const simm_shift* shifts, int32_t n_shifts,
                             uint8_t* decision, double* sums, int32_t m_max,
                             int32_t mem, void* hip_stream);
 
+/* Adjoint gradient of the projected-vector norms J = sum_R ||x_R||^2 over the
+ * squares R of `regions` (rows as in simm_indicators), where
+ * x_R = (1/2 pi i) sum_j w_j (A - z_j B)^{-1} f is the fine-rule (2 n0 points per
+ * edge) quadrature of eq. (XLXf), reduced to the shift's Krylov space as
+ * x_R = V_m s_f (eq. (reduced)); f is the start vector the shifts were built from.
+ * With c_j = w_j / (2 pi i), u_j = (A - z_j B)^{-1} f and
+ * lambda_j = (A - z_j B)^{-H} x_R, the derivative of the resolvent gives
+ *   dJ/dp                               = -2 Re sum_R sum_j c_j lambda_j^H A1 u_j,
+ *   grad_diag[i] = dJ/dRe A_ii + i dJ/dIm A_ii = -2 conj(sum_R sum_j c_j conj(lambda_j,i) u_j,i),
+ * for A = A0 + p A1 with the squares held fixed (decisions are piecewise
+ * constant in A).  u_j is V_m y_j from the shift; lambda_j comes from a Krylov
+ * space of the conjugate-transposed pencil (A^H, B^H) at conj(sigma), started from
+ * x_R (one band LU per shift used, one Krylov space of the shift's m per square).
+ * a1_band: band of A1 (kl1 sub-, ku1 superdiagonals, the layout of
+ * simm_pencil_create_banded); required when dJdp is not NULL, ignored otherwise.
+ * J (required) and dJdp (may be NULL) are host doubles.  grad_diag (may be NULL):
+ * n complex values, overwritten.  a1_band and grad_diag are in `mem` memory.
+ * All shifts must share one pencil and hold their factor and basis; squares whose
+ * s_f vanishes contribute nothing.  EINVAL on bad rows or arguments,
+ * EUNSUPPORTED if m_eff > 128 or gauss_per_edge > 64; SIMM_ESINGULAR_SHIFT if
+ * conj(sigma) is an exact eigenvalue of the adjoint pencil. */
+simm_status simm_gradient(const simm_shift* shifts, int32_t n_shifts, const int64_t* regions,
+                          int64_t n_regions, const simm_params* params, int32_t kl1, int32_t ku1,
+                          const double* a1_band, double* J, double* dJdp, double* grad_diag,
+                          int32_t mem, void* hip_stream);
+
 /* Projection X = V_m Y (eq. (reduced); the full-space vectors of eq. (ISPf)):
  * Y is m_eff x c complex (column-major, leading dimension m_eff), X is n x c
  * complex (leading dimension n); both in device memory.  col_norms (device, may

@@ -1478,6 +1478,142 @@ simm_status multiplicities(simm_result_s* R, const cplx* F, int k, double rel_to
     return SIMM_OK;
 }
 
+// Adjoint gradient of J = sum_R ||x_R||^2 over the squares `regs` (see simm_gradient).
+// The conjugate-transposed pencil (A^H, B^H) is factored once per shift at conj(sigma);
+// each square gets one Krylov space of that pencil started from x_R, whose fine-rule
+// solutions at the conjugated nodes approximate lambda_j = (A - z_j B)^{-H} x_R.
+simm_status gradient(const std::vector<simm_shift_s*>& shifts, const std::vector<int64_t>& regs,
+                     const simm_params* prm, int kl1, int ku1, const cplx* A1, double* J, double* dJdp, cplx* grad,
+                     hipStream_t st) {
+    simm_pencil_s* p = shifts[0]->p;
+    const int64_t n = p->n;
+    const int64_t N = (int64_t)regs.size() / 4;
+    const int g = prm->gauss_per_edge;
+    const int nf = 8 * g;
+    constexpr int LDY = 128;
+    Rule rule;
+    SIMM_TRY(rule.make(g, st));
+    int mmax = 1;
+    for (auto* s : shifts) mmax = std::max(mmax, s->m_eff);
+    DevBuf sumsb;
+    SIMM_TRY(sumsb.alloc(sizeof(cplx) * (size_t)N * 2 * mmax, st));
+    cplx* sums = sumsb.as<cplx>();
+    EvalOut eo;
+    SIMM_TRY(evaluate(shifts, regs, prm, rule, st, eo, sums, mmax));
+    IndicatorParams ip;
+    ip.x0 = prm->x0;
+    ip.y0 = prm->y0;
+    ip.w1 = (prm->x1 - prm->x0) / prm->n1;
+    ip.eps0 = prm->eps0;
+    ip.delta0 = prm->delta0;
+    ip.tau = prm->tau;
+
+    // the conjugate-transposed pencil
+    simm_pencil_s adj;
+    struct AdjRelease {
+        simm_pencil_s* q;
+        ~AdjRelease() {
+            (void)hipFree(q->A);
+            (void)hipFree(q->B);
+        }
+    } adj_release{&adj};
+    adj.n = n;
+    adj.kla = p->kua;
+    adj.kua = p->kla;
+    adj.klb = p->B ? p->kub : 0;
+    adj.kub = p->B ? p->klb : 0;
+    adj.dev = p->dev;
+    SIMM_TRY(dalloc(&adj.A, (size_t)(p->kla + p->kua + 1) * n));
+    SIMM_TRY(conj_transpose_band(n, p->kla, p->kua, p->A, adj.A, st));
+    if (p->B) {
+        SIMM_TRY(dalloc(&adj.B, (size_t)(p->klb + p->kub + 1) * n));
+        SIMM_TRY(conj_transpose_band(n, p->klb, p->kub, p->B, adj.B, st));
+    }
+
+    DevBuf accb, xb, wb, zb, z1b, yb, cwb, kb, pb;
+    SIMM_TRY(accb.alloc(sizeof(double) * 2, st));
+    SIMM_HIP_TRY(hipMemsetAsync(accb.p, 0, sizeof(double) * 2, st));
+    SIMM_TRY(xb.alloc(sizeof(cplx) * (size_t)n, st));
+    if (A1) {
+        SIMM_TRY(wb.alloc(sizeof(cplx) * (size_t)n * mmax, st));
+        SIMM_TRY(z1b.alloc(sizeof(cplx) * (size_t)n * 128, st));
+    }
+    if (grad) {
+        SIMM_TRY(zb.alloc(sizeof(cplx) * (size_t)n * 128, st));
+        SIMM_HIP_TRY(hipMemsetAsync(grad, 0, sizeof(cplx) * (size_t)n, st));
+    }
+    SIMM_TRY(yb.alloc(sizeof(cplx) * (size_t)2 * nf * LDY, st));
+    SIMM_TRY(cwb.alloc(sizeof(cplx) * (size_t)nf, st));
+    SIMM_TRY(kb.alloc(sizeof(cplx) * (size_t)128 * 128, st));
+    SIMM_TRY(pb.alloc(sizeof(cplx) * (size_t)grad_part_elems(n), st));
+    cplx* Yf = yb.as<cplx>();
+    cplx* Ya = Yf + (size_t)nf * LDY;
+
+    std::vector<int> used;
+    for (int64_t r = 0; r < N; ++r) used.push_back((int)regs[4 * r + 3]);
+    std::sort(used.begin(), used.end());
+    used.erase(std::unique(used.begin(), used.end()), used.end());
+    for (int si : used) {
+        simm_shift_s* fs = shifts[si];
+        const int mf = fs->m_eff;
+        std::unique_ptr<simm_shift_s> af;
+        SIMM_TRY(factor_shift(&adj, conj(fs->sigma), st, af));
+        SIMM_TRY(prepare_sweeps(af.get(), st));
+        if (A1)
+            for (int k = 0; k < mf; ++k)
+                SIMM_TRY(prepare_input(n, fs->V + (int64_t)k * n, A1, kl1, ku1, nullptr, nullptr,
+                                       wb.as<cplx>() + (int64_t)k * n, nullptr, st));
+        const ShiftDev fd = shift_dev(fs);
+        for (int64_t r = 0; r < N; ++r) {
+            if (regs[4 * r + 3] != si) continue;
+            // x_R = V s_f; a square whose s_f vanishes adds nothing
+            if (!(eo.nsf[r] > 0.0)) continue;
+            SIMM_TRY(project(n, mf, fs->V, n, sums + (2 * r + 1) * mmax, mmax, 1, xb.as<cplx>(), nullptr, nullptr, 0,
+                             SIMM_PROJ_FP64, st));
+            simm_shift_s kv;
+            kv.p = &adj;
+            kv.sigma = af->sigma;
+            kv.kl = af->kl;
+            kv.ku = af->ku;
+            kv.AB = af->AB;
+            kv.ipiv = af->ipiv;
+            kv.LP = af->LP;
+            kv.spike = af->spike;
+            kv.sweeps_ready = true;
+            kv.factor_borrowed = true;
+            SIMM_TRY(krylov_shift(&kv, xb.as<cplx>(), fs->m, st, nullptr));
+            const int ma = kv.m_eff;
+            if (ma > 128) {
+                set_error("Krylov dimension above 128");
+                return SIMM_EUNSUPPORTED;
+            }
+            const ShiftDev ad = shift_dev(&kv);
+            const int level = (int)regs[4 * r];
+            SIMM_TRY(fine_solutions(fd, ip, rule.dev, level, regs[4 * r + 1], regs[4 * r + 2], false, Yf, LDY,
+                                    cwb.as<cplx>(), st));
+            SIMM_TRY(fine_solutions(ad, ip, rule.dev, level, regs[4 * r + 1], regs[4 * r + 2], true, Ya, LDY, nullptr,
+                                    st));
+            SIMM_TRY(grad_kmat(nf, Yf, Ya, LDY, cwb.as<cplx>(), mf, ma, kb.as<cplx>(), st));
+            if (grad)
+                SIMM_TRY(project(n, mf, fs->V, n, kb.as<cplx>(), mf, ma, zb.as<cplx>(), nullptr, nullptr, 0,
+                                 SIMM_PROJ_FP64, st));
+            if (A1)
+                SIMM_TRY(project(n, mf, wb.as<cplx>(), n, kb.as<cplx>(), mf, ma, z1b.as<cplx>(), nullptr, nullptr, 0,
+                                 SIMM_PROJ_FP64, st));
+            SIMM_TRY(grad_rowdot(n, ma, kv.V, n, grad ? zb.as<cplx>() : nullptr, A1 ? z1b.as<cplx>() : nullptr, n,
+                                 xb.as<cplx>(), grad, pb.as<cplx>(), accb.as<double>(), st));
+            SIMM_HIP_TRY(hipStreamSynchronize(st));   // kv's buffers are freed at scope exit
+        }
+        SIMM_HIP_TRY(hipStreamSynchronize(st));
+    }
+    double acc[2] = {0.0, 0.0};
+    SIMM_HIP_TRY(hipMemcpyAsync(acc, accb.p, sizeof(acc), hipMemcpyDeviceToHost, st));
+    SIMM_HIP_TRY(hipStreamSynchronize(st));
+    *J = acc[0];
+    if (dJdp) *dJdp = acc[1];
+    return SIMM_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1788,6 +1924,80 @@ simm_status simm_indicators(const simm_shift* shifts, int32_t n_shifts, const in
     if (sums && mem == SIMM_MEM_HOST) {
         SIMM_HIP_TRY(hipMemcpyAsync(sums, sums_dev, sizeof(cplx) * (size_t)n_regions * 2 * m_max, hipMemcpyDeviceToHost, st));
     }
+    SIMM_HIP_TRY(hipStreamSynchronize(st));
+    return SIMM_OK;
+}
+
+simm_status simm_gradient(const simm_shift* shifts, int32_t n_shifts, const int64_t* regions, int64_t n_regions,
+                          const simm_params* params, int32_t kl1, int32_t ku1, const double* a1_band, double* J,
+                          double* dJdp, double* grad_diag, int32_t mem, void* hip_stream) {
+    clear_error();
+    if (!shifts || n_shifts < 1 || (!regions && n_regions > 0) || n_regions < 0 || !params || !J ||
+        (dJdp && (!a1_band || kl1 < 0 || ku1 < 0))) {
+        set_error("bad gradient arguments");
+        return SIMM_EINVAL;
+    }
+    if (mem != SIMM_MEM_HOST && mem != SIMM_MEM_DEVICE) {
+        set_error("mem must be SIMM_MEM_HOST or SIMM_MEM_DEVICE");
+        return SIMM_EINVAL;
+    }
+    if (params->gauss_per_edge < 1 || params->gauss_per_edge > 64 || !(params->x1 > params->x0) || params->n1 < 1) {
+        set_error("bad rule or region (1 <= gauss_per_edge <= 64, x1 > x0, n1 >= 1)");
+        return SIMM_EINVAL;
+    }
+    simm_pencil_s* p = nullptr;
+    std::vector<simm_shift_s*> sv(shifts, shifts + n_shifts);
+    for (auto* s : sv) {
+        if (!s) return SIMM_EINVAL;
+        if (p && s->p != p) {
+            set_error("the shifts of one gradient call must share one pencil");
+            return SIMM_EINVAL;
+        }
+        p = s->p;
+        if (!s->has_factor()) {
+            set_error("a shift's factor or Krylov basis was released");
+            return SIMM_EINVAL;
+        }
+        if (s->m_eff > 128) {
+            set_error("Krylov dimension above 128");
+            return SIMM_EUNSUPPORTED;
+        }
+    }
+    for (int64_t r = 0; r < n_regions; ++r) {
+        if (regions[4 * r] < 1 || regions[4 * r] > 60 || regions[4 * r + 3] < 0 || regions[4 * r + 3] >= n_shifts) {
+            set_error("region row with bad level or shift index");
+            return SIMM_EINVAL;
+        }
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    const int64_t n = p->n;
+    const cplx* a1 = dJdp ? reinterpret_cast<const cplx*>(a1_band) : nullptr;
+    DevBuf a1b, gb;
+    if (a1 && mem == SIMM_MEM_HOST) {
+        const size_t cnt = (size_t)(kl1 + ku1 + 1) * n;
+        if (!finite_c(a1_band, 2 * (int64_t)cnt)) {
+            set_error("A1 has NaN/Inf entries");
+            return SIMM_EINVAL;
+        }
+        SIMM_TRY(a1b.alloc(sizeof(cplx) * cnt, st));
+        SIMM_HIP_TRY(hipMemcpyAsync(a1b.p, a1_band, sizeof(cplx) * cnt, hipMemcpyHostToDevice, st));
+        a1 = a1b.as<cplx>();
+    }
+    cplx* grad = reinterpret_cast<cplx*>(grad_diag);
+    if (grad && mem == SIMM_MEM_HOST) {
+        SIMM_TRY(gb.alloc(sizeof(cplx) * (size_t)n, st));
+        grad = gb.as<cplx>();
+    }
+    std::vector<int64_t> regs(regions, regions + 4 * n_regions);
+    if (n_regions == 0) {
+        *J = 0.0;
+        if (dJdp) *dJdp = 0.0;
+        if (grad) SIMM_HIP_TRY(hipMemsetAsync(grad, 0, sizeof(cplx) * (size_t)n, st));
+    } else {
+        SIMM_TRY(gradient(sv, regs, params, kl1, ku1, a1, J, dJdp, grad, st));
+    }
+    if (grad_diag && mem == SIMM_MEM_HOST)
+        SIMM_HIP_TRY(hipMemcpyAsync(grad_diag, grad, sizeof(cplx) * (size_t)n, hipMemcpyDeviceToHost, st));
     SIMM_HIP_TRY(hipStreamSynchronize(st));
     return SIMM_OK;
 }

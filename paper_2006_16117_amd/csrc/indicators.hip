@@ -228,6 +228,85 @@ __global__ __launch_bounds__(IND_THREADS) void k_indicators(const ShiftDev* __re
     }
 }
 
+// Fine-rule solutions of one square (the 2g-point rule of eq. (XLXf)): for each node
+// z_j, y_j = Q yhat_j with (I + (sigma - z_j) T) yhat_j = beta Q^H e_1, the Galerkin
+// solution of eq. (y) in the Arnoldi basis; row j of Y (stride ldy) holds y_j.  With
+// conj_nodes the nodes are conjugated: the shift then belongs to the conjugate-transposed
+// pencil at conj(sigma), whose resolvent at conj(z_j) is (A - z_j B)^{-H}.  cw, when
+// given, receives c_j = w_j / (2 pi i).  One workgroup; wave w takes the points w + 4t.
+__global__ __launch_bounds__(IND_THREADS) void k_fine_solutions(ShiftDev sh, IndicatorParams prm, RuleDev rule,
+                                                                int level, int64_t ix, int64_t iy, int conj_nodes,
+                                                                cplx* __restrict__ Y, int ldy, cplx* __restrict__ cw) {
+    extern __shared__ cplx smem[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = sh.m;
+    cplx* Ts = smem;
+    const int nT = m * (m + 1) / 2;
+    for (int e = threadIdx.x; e < nT; e += IND_THREADS) Ts[e] = sh.T[e];
+    __syncthreads();
+    const int i0 = lane, i1 = lane + 64;
+    const cplx g0 = (i0 < m) ? sh.g[i0] : mk(0.0, 0.0);
+    const cplx g1 = (i1 < m) ? sh.g[i1] : mk(0.0, 0.0);
+    const cplx t00 = (i0 < m) ? Ts[i0 * (i0 + 1) / 2 + i0] : mk(0.0, 0.0);
+    const cplx t11 = (i1 < m) ? Ts[i1 * (i1 + 1) / 2 + i1] : mk(0.0, 0.0);
+    const double width = ldexp(prm.w1, 1 - level);
+    double cx, cy;
+    {
+#pragma clang fp contract(off)
+        cx = prm.x0 + ((double)ix + 0.5) * width;
+        cy = prm.y0 + ((double)iy + 0.5) * width;
+    }
+    const double h = width / 2.0;
+    const int g2 = 2 * rule.g;
+    const int nf = 4 * g2;
+    const cplx one = mk(1.0, 0.0);
+    const double twopi = 6.283185307179586;
+    for (int q = wave; q < nf; q += IND_WAVES) {
+        const int e = q / g2;
+        const int idx = q - e * g2;
+        cplx z, wq;
+        node(cx, cy, h, e, rule.t2[idx], rule.w2[idx], z, wq);
+        if (conj_nodes) z.im = -z.im;
+        const cplx alpha = mk(sh.sig_re - z.re, sh.sig_im - z.im);
+        const cplx dinv0 = cdiv(one, one + alpha * t00);
+        const cplx dinv1 = cdiv(one, one + alpha * t11);
+        cplx r0 = g0, r1 = g1;
+        for (int j = m - 1; j >= 0; --j) {
+            const int oj = j & 63;
+            const cplx* col = Ts + j * (j + 1) / 2;
+            const cplx yj = (j < 64) ? readlane_c(r0 * dinv0, oj) : readlane_c(r1 * dinv1, oj);
+            const cplx cj = alpha * yj;
+            if (i0 < j) r0 = fms(r0, col[i0], cj);
+            if (i1 < j) r1 = fms(r1, col[i1], cj);
+            if (i0 == j) r0 = yj;
+            if (i1 == j) r1 = yj;
+        }
+        // y = Q yhat: the lanes keep their rows of y, yhat_k is broadcast
+        cplx y0 = mk(0.0, 0.0), y1 = mk(0.0, 0.0);
+        for (int k = 0; k < m; ++k) {
+            const cplx yk = (k < 64) ? readlane_c(r0, k & 63) : readlane_c(r1, k & 63);
+            if (i0 < m) y0 = fma_c(y0, sh.Q[i0 + (int64_t)k * m], yk);
+            if (i1 < m) y1 = fma_c(y1, sh.Q[i1 + (int64_t)k * m], yk);
+        }
+        if (i0 < m) Y[(int64_t)q * ldy + i0] = y0;
+        if (i1 < m) Y[(int64_t)q * ldy + i1] = y1;
+        if (cw != nullptr && lane == 0) cw[q] = mk(wq.im / twopi, -wq.re / twopi);
+    }
+}
+
+simm_status fine_solutions(const ShiftDev& sh, const IndicatorParams& prm, const RuleDev& rule, int level, int64_t ix,
+                           int64_t iy, bool conj_nodes, cplx* Y, int ldy, cplx* cw, hipStream_t st) {
+    if (sh.m > 128 || ldy < sh.m) {
+        set_error("fine_solutions: Krylov dimension above 128 or row stride below it");
+        return SIMM_EUNSUPPORTED;
+    }
+    const size_t lds = sizeof(cplx) * (size_t)(sh.m * (sh.m + 1) / 2 + 1);
+    hipLaunchKernelGGL(k_fine_solutions, dim3(1), dim3(IND_THREADS), lds, st, sh, prm, rule, level, ix, iy,
+                       conj_nodes ? 1 : 0, Y, ldy, cw);
+    SIMM_HIP_TRY(hipGetLastError());
+    return SIMM_OK;
+}
+
 simm_status indicators(const ShiftDev* shifts_dev, int mmax, const int64_t* regions, int64_t nreg,
                        const IndicatorParams& prm, const RuleDev& rule, double* indicator, double* rho_max,
                        double* nsf, double* nsc, double* Tf, uint8_t* decision, cplx* sums, int m_sums,

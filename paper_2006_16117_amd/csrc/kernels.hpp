@@ -163,6 +163,21 @@ simm_status accum_cols(int64_t n, int64_t ncl, const cplx* T, cplx* X, int64_t l
 simm_status gram(int64_t n, int k, int64_t ncl, const cplx* X, cplx* G, hipStream_t st);
 std::vector<double> hermitian_eigenvalues(int k, const cplx* G);
 
+// fine-rule solutions y_j = Q yhat_j of one square, one row of Y per node (ldy >= m);
+// conj_nodes: conjugated nodes (a shift of the conjugate-transposed pencil); cw: c_j
+simm_status fine_solutions(const ShiftDev& sh, const IndicatorParams& prm, const RuleDev& rule, int level, int64_t ix,
+                           int64_t iy, bool conj_nodes, cplx* Y, int ldy, cplx* cw, hipStream_t st);
+
+// ---- adjoint gradient (gradient.hip) ----
+simm_status conj_transpose_band(int64_t n, int kl, int ku, const cplx* in, cplx* out, hipStream_t st);
+simm_status grad_kmat(int nf, const cplx* Yf, const cplx* Ya, int ldy, const cplx* cw, int mf, int ma, cplx* K,
+                      hipStream_t st);
+// grad (if non-null) += -2 conj(rowsum(conj(V') o Z)); acc[0] += ||x||^2,
+// acc[1] += -2 Re sum(conj(V') o Z1) (Z1 may be null); part: grad_part_elems(n)
+simm_status grad_rowdot(int64_t n, int ma, const cplx* Vp, int64_t ldv, const cplx* Z, const cplx* Z1, int64_t ldz,
+                        const cplx* x, cplx* grad, cplx* part, double* acc, hipStream_t st);
+int64_t grad_part_elems(int64_t n);
+
 // ---- projection (project.hip) ----
 simm_status project(int64_t n, int m, const cplx* V, int64_t ldv, const cplx* Y, int64_t ldy, int64_t c, cplx* X,
                     double* col_norms, double* scratch, int64_t scratch_elems, int prec, hipStream_t st);

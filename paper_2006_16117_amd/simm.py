@@ -78,6 +78,8 @@ EXPORTS = {
     "simm_indicators": (C.c_int, [_vp, _i32, _vp, _i64, C.POINTER(simm_params), _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                   _i32, _i32, _vp]),
     "simm_project": (C.c_int, [_vp, _vp, _i64, _vp, _vp, _i32, _vp]),
+    "simm_gradient": (C.c_int, [_vp, _i32, _vp, _i64, C.POINTER(simm_params), _i32, _i32, _vp, _vp, _vp, _vp, _i32,
+                                _vp]),
     "simm_run": (C.c_int, [_vp, C.POINTER(simm_params), _vp, _i32, _vp, C.POINTER(_vp)]),
     "simm_run_batch": (C.c_int, [C.POINTER(_vp), C.POINTER(simm_params), C.POINTER(_vp), _i32, _i32, _i32,
                                  C.POINTER(_vp)]),
@@ -270,6 +272,83 @@ def simm_project(shift: Shift, Y, X, col_norms=None, precision: int = SIMM_PROJ_
     c = Y.shape[1]
     _check(_lib.simm_project(shift.handle, py, c, px, pn, int(precision), _stream(stream)))
     return X
+
+
+def simm_gradient(shifts, regions: np.ndarray, params: simm_params, a1_band=None, kl1: int = 0, ku1: int = 0,
+                  want_diag: bool = True, stream=None):
+    """Host-memory form of simm_gradient: regions (N, 4) int64 (level, ix, iy, shift);
+    a1_band (kl1 + ku1 + 1, n) complex band of A1 or None.  Returns
+    (J, dJ/dp or None, dJ/dRe A_ii + i dJ/dIm A_ii as an (n,) complex array or None)."""
+    regions = np.ascontiguousarray(regions, dtype=np.int64).reshape(-1, 4)
+    arr = (_vp * len(shifts))(*[s.handle for s in shifts])
+    n = shifts[0]._n
+    J = C.c_double()
+    dp = C.c_double()
+    a1 = np.asfortranarray(a1_band, dtype=np.complex128) if a1_band is not None else None
+    gd = np.zeros(n, dtype=np.complex128) if want_diag else None
+    _check(_lib.simm_gradient(arr, len(shifts), regions.ctypes.data, regions.shape[0], C.byref(params), kl1, ku1,
+                              a1.ctypes.data if a1 is not None else None, C.addressof(J),
+                              C.addressof(dp) if a1 is not None else None, gd.ctypes.data if gd is not None else None,
+                              SIMM_MEM_HOST, _stream(stream)))
+    return J.value, (dp.value if a1 is not None else None), gd
+
+
+def _band_sum(n, parts):
+    """Band (kl, ku, array) of the sum of bands given as (kl, ku, band) triples."""
+    kl = max(p[0] for p in parts)
+    ku = max(p[1] for p in parts)
+    out = np.zeros((kl + ku + 1, n), dtype=np.complex128, order="F")
+    for pkl, pku, band in parts:
+        out[ku - pku: ku + pkl + 1, :] += band
+    return kl, ku, out
+
+
+class ProjectedNorms:
+    """J(p, d) = sum_R ||x_R||^2 (the quantity of simm_gradient) for the pencil
+    A = A0 + p A1 + diag(d), B, with the squares and shifts held fixed, as a
+    torch.autograd.Function of the real scalar p and the complex n-vector d:
+    backward returns dJ/dp and dJ/dRe d + i dJ/dIm d (torch's convention for a real
+    function of complex inputs) from the adjoint kernels.  Host-memory bands."""
+
+    def __init__(self, n, kl0, ku0, a0_band, kl1, ku1, a1_band, f, sigmas, regions, params, m, kl_b=0, ku_b=0,
+                 b_band=None):
+        self.n = n
+        self.a0 = (kl0, ku0, np.asarray(a0_band, dtype=np.complex128))
+        self.a1 = (kl1, ku1, np.asarray(a1_band, dtype=np.complex128))
+        self.b = (kl_b, ku_b, b_band)
+        self.f = np.asarray(f, dtype=np.complex128)
+        self.sigmas = list(sigmas)
+        self.regions = np.ascontiguousarray(regions, dtype=np.int64).reshape(-1, 4)
+        self.params = params
+        self.m = m
+
+    def evaluate(self, p: float, d: np.ndarray):
+        """(J, dJ/dp, grad_diag) at (p, d)."""
+        dband = (0, 0, np.asarray(d, dtype=np.complex128).reshape(1, -1))
+        kl, ku, band = _band_sum(self.n, [self.a0, (self.a1[0], self.a1[1], p * self.a1[2]), dband])
+        pen = Pencil(self.n, kl, ku, band, self.b[0], self.b[1], self.b[2])
+        shifts = [simm_shift_build(pen, s, self.f, self.m) for s in self.sigmas]
+        out = simm_gradient(shifts, self.regions, self.params, self.a1[2], self.a1[0], self.a1[1])
+        del shifts, pen
+        return out
+
+    def function(self):
+        import torch
+        prob = self
+
+        class _Fn(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, p, d):
+                J, dp, gd = prob.evaluate(float(p.detach().cpu()), d.detach().cpu().numpy())
+                ctx.save_for_backward(torch.tensor(dp, dtype=torch.float64), torch.from_numpy(gd))
+                return torch.tensor(J, dtype=torch.float64)
+
+            @staticmethod
+            def backward(ctx, gJ):
+                dp, gd = ctx.saved_tensors
+                return gJ * dp, gJ * gd
+
+        return _Fn.apply
 
 
 @dataclasses.dataclass

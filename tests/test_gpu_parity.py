@@ -560,3 +560,116 @@ def test_batch_matches_sequential_and_oracle(S):
         lam = np.array([complex(*c["lam"]) for c in g["clusters"]])
         assert len(b.lam) == len(lam) and np.all(np.abs(b.lam - lam) <= 1e-14 * np.abs(lam)), i
     say("  decision ties within the margin policy:", ties)
+
+
+# ---------------------------------------------------------------------------
+# adjoint gradient of J = sum_R ||x_R||^2 (squares held fixed)
+# ---------------------------------------------------------------------------
+def _grad_problem(n, seed, level, nsq):
+    """Pencil, A1 (tridiagonal band), params and up to nsq level-`level` squares, each
+    around an eigenvalue with every eigenvalue at least 0.15 w from its edges, plus one
+    square far from the spectrum; one shift per square (its centre, offset)."""
+    pen, f = random_band_pencil(n, 2, seed, b_kind="tridiag", b_offdiag=0.2)
+    A, B = O.pencil_dense(pen)
+    rng = np.random.default_rng(seed + 1)
+    a1 = np.zeros((3, n), dtype=np.complex128, order="F")      # kl1 = ku1 = 1
+    a1[0, 1:] = rng.standard_normal(n - 1) * 0.1
+    a1[1, :] = rng.standard_normal(n) * 0.3
+    a1[2, :-1] = rng.standard_normal(n - 1) * 0.1
+    x0, n1, w1 = -10.0, 50, 0.4
+    w = w1 * 2.0 ** (1 - level)
+    ev = np.linalg.eigvals(np.linalg.solve(B, A))
+    sq = []
+    for lam in ev:
+        ix, iy = int(np.floor((lam.real - x0) / w)), int(np.floor((lam.imag - x0) / w))
+        c = complex(x0 + (ix + 0.5) * w, x0 + (iy + 0.5) * w)
+        near = (np.abs(ev.real - c.real) < 0.65 * w) & (np.abs(ev.imag - c.imag) < 0.65 * w)
+        dist = np.minimum(np.abs(np.abs(ev.real - c.real) - w / 2), np.abs(np.abs(ev.imag - c.imag) - w / 2))
+        if np.all(dist[near] > 0.15 * w) and (ix, iy) not in sq:
+            sq.append((ix, iy))
+        if len(sq) == nsq:
+            break
+    sq.append((45, 45))                                          # centre 8.2 + 8.2i: no eigenvalue near
+    regions = np.array([(level, ix, iy, k) for k, (ix, iy) in enumerate(sq)], dtype=np.int64)
+    centres = [complex(x0 + (ix + 0.5) * w, x0 + (iy + 0.5) * w) for ix, iy in sq]
+    sigmas = [c + (0.013 + 0.021j) * w for c in centres]
+    prm = dict(x0=x0, y0=x0, x1=x0 + n1 * w1, n1=n1, gauss_per_edge=8)
+    return pen, f, a1, O.band_to_dense(n, 1, 1, a1), regions, [(c, w) for c in centres], sigmas, prm
+
+
+GRAD_CASES = [
+    # name, n, seed, level, squares near eigenvalues, m
+    ("n60-m=n", 60, 7, 1, 3, 60),
+    ("n300-level3", 300, 11, 3, 2, 100),
+]
+
+
+@pytest.mark.parametrize("case", GRAD_CASES, ids=[c[0] for c in GRAD_CASES])
+def test_gradient_matches_oracle_and_fd(S, case):
+    name, n, seed, level, nsq, m = case
+    pen, f, a1, A1, regions, squares, sigmas, prm = _grad_problem(n, seed, level, nsq)
+    A, B = O.pencil_dense(pen)
+    J_o, dp_o, gd_o = O.projected_norms_gradient(A, A1, B, f, squares, prm["gauss_per_edge"])
+    say("gradient", name, f"n={n} m={m} squares={len(squares)} J_oracle={J_o:.6e}")
+    P = S.Pencil.from_workload(pen)
+    shifts = [S.simm_shift_build(P, s, f, m) for s in sigmas]
+    params = S.params_from_dict(prm, m=m)
+    J, dp, gd = S.simm_gradient(shifts, regions, params, a1, 1, 1)
+    say("  J", J, "dJ/dp", dp, "oracle", dp_o)
+    assert abs(J - J_o) <= 1e-8 * J_o
+    assert abs(dp - dp_o) <= 1e-6 * abs(dp_o)
+    scale = np.max(np.abs(gd_o))
+    err = np.max(np.abs(gd - gd_o)) / scale
+    say("  max |grad_diag - oracle| / max|oracle| =", err)
+    assert err <= 1e-6
+    # central differences of the library's own J (h = 1e-6)
+    prob = S.ProjectedNorms(n, pen.kl_a, pen.ku_a, pen.a_band, 1, 1, a1, f, sigmas, regions, params, m,
+                            pen.kl_b, pen.ku_b, pen.b_band)
+    h = 1e-6
+    d0 = np.zeros(n, dtype=np.complex128)
+    Jp = prob.evaluate(h, d0)[0]
+    Jm = prob.evaluate(-h, d0)[0]
+    fd = (Jp - Jm) / (2 * h)
+    say("  dJ/dp", dp, "central difference", fd)
+    assert abs(dp - fd) <= 1e-6 * abs(fd)
+    for i in (0, n // 2 + 1):
+        e = np.zeros(n, dtype=np.complex128)
+        e[i] = h
+        fr = (prob.evaluate(0.0, e)[0] - prob.evaluate(0.0, -e)[0]) / (2 * h)
+        fi = (prob.evaluate(0.0, 1j * e)[0] - prob.evaluate(0.0, -1j * e)[0]) / (2 * h)
+        say("  grad_diag", i, gd[i], "central difference", fr + 1j * fi)
+        assert abs(gd[i] - (fr + 1j * fi)) <= 1e-6 * scale
+
+
+def test_gradient_autograd_function(S):
+    import torch
+    n, m = 60, 60
+    pen, f, a1, A1, regions, squares, sigmas, prm = _grad_problem(n, 7, 1, 2)
+    say("gradient autograd", f"n={n} m={m}")
+    params = S.params_from_dict(prm, m=m)
+    prob = S.ProjectedNorms(n, pen.kl_a, pen.ku_a, pen.a_band, 1, 1, a1, f, sigmas, regions, params, m,
+                            pen.kl_b, pen.ku_b, pen.b_band)
+    fn = prob.function()
+    p = torch.tensor(0.25, dtype=torch.float64, requires_grad=True)
+    d = torch.zeros(n, dtype=torch.complex128, requires_grad=True)
+    J = fn(p, d)
+    (3.0 * J).backward()
+    A, B = O.pencil_dense(pen)
+    J_o, dp_o, gd_o = O.projected_norms_gradient(A + 0.25 * A1, A1, B, f, squares, prm["gauss_per_edge"])
+    assert abs(J.item() - J_o) <= 1e-8 * J_o
+    assert abs(p.grad.item() - 3.0 * dp_o) <= 1e-6 * abs(3.0 * dp_o)
+    assert np.max(np.abs(d.grad.numpy() - 3.0 * gd_o)) <= 1e-6 * np.max(np.abs(3.0 * gd_o))
+
+
+def test_gradient_errors(S):
+    pen, f = random_band_pencil(40, 2, 5, b_kind="identity")
+    P = S.Pencil.from_workload(pen)
+    sh = S.simm_shift_build(P, 0.1 + 0.1j, f, 20)
+    params = S.params_from_dict(dict(x0=-2.0, y0=-2.0, x1=2.0, n1=10, gauss_per_edge=4), m=20)
+    say("gradient errors")
+    with pytest.raises(S.SimmError):
+        S.simm_gradient([sh], np.array([[0, 1, 1, 0]]), params)          # level 0
+    with pytest.raises(S.SimmError):
+        S.simm_gradient([sh], np.array([[1, 1, 1, 1]]), params)          # shift index out of range
+    J, dp, gd = S.simm_gradient([sh], np.zeros((0, 4), dtype=np.int64), params)
+    assert J == 0.0 and dp is None and np.all(gd == 0)

@@ -188,6 +188,91 @@ def bench_batch(args):
     print(json.dumps(out))
 
 
+def bench_gradient(args):
+    """Differentiation workload: one SIM-M run of A(p) = A0 + p A1 fixes the squares
+    (admissible squares of the last level) and their shifts; the timed step is one
+    simm_gradient call (J, dJ/dp and the n values of dJ/d diag(A)).  The derivatives
+    are checked against central differences of the library's J at the same shifts."""
+    import numpy as np
+    import torch
+    from workloads import load_config, make_workload, random_band_matrix
+    import paper_2006_16117_amd.simm as S
+
+    assert torch.cuda.is_available(), "needs a ROCm GPU"
+    cfg = load_config(args.workload)
+    dcfg = cfg["differentiation"]
+    pen0, f, params = make_workload(args.workload)
+    n = pen0.n
+    k1 = dcfg["k1"]
+    a1 = random_band_matrix(n, k1, dcfg["seed"], 1.0 / np.sqrt(n))
+    p0 = dcfg["p"]
+    kl, ku, band = S._band_sum(n, [(pen0.kl_a, pen0.ku_a, pen0.a_band), (k1, k1, p0 * a1)])
+    P = S.Pencil(n, kl, ku, band, pen0.kl_b, pen0.ku_b, pen0.b_band)
+    prm = S.params_from_dict(params)
+    t0 = time.perf_counter()
+    res = S.simm_run(P, f, prm)
+    t_run = time.perf_counter() - t0
+    last = res.levels[-1]
+    adm = np.nonzero(last.decision == S.ADMISSIBLE)[0]
+    used = sorted(set(int(last.shift[i]) for i in adm))
+    remap = {s: j for j, s in enumerate(used)}
+    regions = np.array([(res.K, last.keys[i, 0], last.keys[i, 1], remap[int(last.shift[i])]) for i in adm],
+                       dtype=np.int64).reshape(-1, 4)
+    shifts = [res.shift(s) for s in used]
+    sigmas = [sh.info()["sigma"] for sh in shifts]
+    log(f"run: {t_run * 1e3:.0f} ms, K = {res.K}, {len(adm)} admissible squares, {len(used)} shifts")
+    for w in range(args.warmup):
+        S.simm_gradient(shifts, regions, prm, a1, k1, k1, n=n)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        J, dp, gd = S.simm_gradient(shifts, regions, prm, a1, k1, k1, n=n)
+        log(f"gradient {s + 1}/{args.steps}: J = {J:.6e}, dJ/dp = {dp:.6e}")
+    t_grad = (time.perf_counter() - t0) / args.steps
+    # central differences of J (same shifts, same squares)
+    prob = S.ProjectedNorms(n, pen0.kl_a, pen0.ku_a, pen0.a_band, k1, k1, a1, f, sigmas, regions, prm, params["m"],
+                            pen0.kl_b, pen0.ku_b, pen0.b_band)
+    h = dcfg["fd_h"]
+    z = np.zeros(n, dtype=np.complex128)
+    fd_p = (prob.evaluate(p0 + h, z, derivatives=False)[0] - prob.evaluate(p0 - h, z, derivatives=False)[0]) / (2 * h)
+    err_p = abs(dp - fd_p) / abs(fd_p)
+    log(f"dJ/dp {dp:.10e}  central difference {fd_p:.10e}  rel {err_p:.2e}")
+    # diagonal entries checked: the two largest |dJ/dA_ii| and the configured ones
+    scale = float(np.max(np.abs(gd)))
+    top = [int(i) for i in np.argsort(-np.abs(gd))[:2]]
+    err_d = 0.0
+    for i in top + list(dcfg["fd_diag"]):
+        e = np.zeros(n, dtype=np.complex128)
+        e[i] = h
+        Jd = [prob.evaluate(p0, v, derivatives=False)[0] for v in (e, -e, 1j * e, -1j * e)]
+        fdi = complex((Jd[0] - Jd[1]) / (2 * h), (Jd[2] - Jd[3]) / (2 * h))
+        err_d = max(err_d, abs(gd[i] - fdi) / scale)
+        log(f"grad_diag[{i}] {gd[i]:.10e}  central difference {fdi:.10e}  |diff|/max|grad| {abs(gd[i] - fdi) / scale:.2e}")
+    out = {
+        "metric": "adjoint gradient evaluations/s (J, dJ/dp and dJ/d diag(A) over the last level's squares)",
+        "value": 1.0 / t_grad,
+        "unit": "gradients/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_grad * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "forward_run_ms": t_run * 1e3,
+        "J": J,
+        "dJdp": dp,
+        "fd_rel_err_dJdp": err_p,
+        "fd_rel_err_diag": err_d,
+        "fd_checked_diag": top + list(dcfg["fd_diag"]),
+        "config": {"workload": cfg["description"], "n": n, "kl": kl, "ku": ku, "m": params["m"],
+                   "squares": int(regions.shape[0]), "shifts": len(used), "levels": res.K},
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,6 +317,8 @@ def main():
 
     if load_config(args.workload)["generator"]["kind"].endswith("_batch"):
         return bench_batch(args)
+    if "differentiation" in load_config(args.workload):
+        return bench_gradient(args)
 
     assert torch.cuda.is_available(), "needs a ROCm GPU"
     dev = torch.device("cuda:0")

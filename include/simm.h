@@ -210,7 +210,8 @@ simm_status simm_indicators(const simm_shift* shifts, int32_t n_shifts,
  * a1_band: band of A1 (kl1 sub-, ku1 superdiagonals, the layout of
  * simm_pencil_create_banded); required when dJdp is not NULL, ignored otherwise.
  * J (required) and dJdp (may be NULL) are host doubles.  grad_diag (may be NULL):
- * n complex values, overwritten.  a1_band and grad_diag are in `mem` memory.
+ * n complex values, overwritten.  With dJdp and grad_diag both NULL only J is
+ * formed (no adjoint work).  a1_band and grad_diag are in `mem` memory.
  * All shifts must share one pencil and hold their factor and basis; squares whose
  * s_f vanishes contribute nothing.  EINVAL on bad rows or arguments,
  * EUNSUPPORTED if m_eff > 128 or gauss_per_edge > 64; SIMM_ESINGULAR_SHIFT if

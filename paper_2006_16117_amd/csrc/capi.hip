@@ -1523,11 +1523,13 @@ simm_status gradient(const std::vector<simm_shift_s*>& shifts, const std::vector
     adj.klb = p->B ? p->kub : 0;
     adj.kub = p->B ? p->klb : 0;
     adj.dev = p->dev;
-    SIMM_TRY(dalloc(&adj.A, (size_t)(p->kla + p->kua + 1) * n));
-    SIMM_TRY(conj_transpose_band(n, p->kla, p->kua, p->A, adj.A, st));
-    if (p->B) {
-        SIMM_TRY(dalloc(&adj.B, (size_t)(p->klb + p->kub + 1) * n));
-        SIMM_TRY(conj_transpose_band(n, p->klb, p->kub, p->B, adj.B, st));
+    if (A1 || grad) {
+        SIMM_TRY(dalloc(&adj.A, (size_t)(p->kla + p->kua + 1) * n));
+        SIMM_TRY(conj_transpose_band(n, p->kla, p->kua, p->A, adj.A, st));
+        if (p->B) {
+            SIMM_TRY(dalloc(&adj.B, (size_t)(p->klb + p->kub + 1) * n));
+            SIMM_TRY(conj_transpose_band(n, p->klb, p->kub, p->B, adj.B, st));
+        }
     }
 
     DevBuf accb, xb, wb, zb, z1b, yb, cwb, kb, pb;
@@ -1556,6 +1558,17 @@ simm_status gradient(const std::vector<simm_shift_s*>& shifts, const std::vector
     for (int si : used) {
         simm_shift_s* fs = shifts[si];
         const int mf = fs->m_eff;
+        if (!A1 && !grad) {
+            // J alone: ||x_R||^2 of every square, no adjoint
+            for (int64_t r = 0; r < N; ++r) {
+                if (regs[4 * r + 3] != si || !(eo.nsf[r] > 0.0)) continue;
+                SIMM_TRY(project(n, mf, fs->V, n, sums + (2 * r + 1) * mmax, mmax, 1, xb.as<cplx>(), nullptr,
+                                 nullptr, 0, SIMM_PROJ_FP64, st));
+                SIMM_TRY(grad_rowdot(n, 0, nullptr, n, nullptr, nullptr, n, xb.as<cplx>(), nullptr, pb.as<cplx>(),
+                                     accb.as<double>(), st));
+            }
+            continue;
+        }
         std::unique_ptr<simm_shift_s> af;
         SIMM_TRY(factor_shift(&adj, conj(fs->sigma), st, af));
         SIMM_TRY(prepare_sweeps(af.get(), st));

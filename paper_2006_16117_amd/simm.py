@@ -275,16 +275,16 @@ def simm_project(shift: Shift, Y, X, col_norms=None, precision: int = SIMM_PROJ_
 
 
 def simm_gradient(shifts, regions: np.ndarray, params: simm_params, a1_band=None, kl1: int = 0, ku1: int = 0,
-                  want_diag: bool = True, stream=None):
+                  want_diag: bool = True, want_dp: bool = True, n: int | None = None, stream=None):
     """Host-memory form of simm_gradient: regions (N, 4) int64 (level, ix, iy, shift);
     a1_band (kl1 + ku1 + 1, n) complex band of A1 or None.  Returns
     (J, dJ/dp or None, dJ/dRe A_ii + i dJ/dIm A_ii as an (n,) complex array or None)."""
     regions = np.ascontiguousarray(regions, dtype=np.int64).reshape(-1, 4)
     arr = (_vp * len(shifts))(*[s.handle for s in shifts])
-    n = shifts[0]._n
+    n = n if n is not None else shifts[0]._n
     J = C.c_double()
     dp = C.c_double()
-    a1 = np.asfortranarray(a1_band, dtype=np.complex128) if a1_band is not None else None
+    a1 = np.asfortranarray(a1_band, dtype=np.complex128) if (a1_band is not None and want_dp) else None
     gd = np.zeros(n, dtype=np.complex128) if want_diag else None
     _check(_lib.simm_gradient(arr, len(shifts), regions.ctypes.data, regions.shape[0], C.byref(params), kl1, ku1,
                               a1.ctypes.data if a1 is not None else None, C.addressof(J),
@@ -322,13 +322,14 @@ class ProjectedNorms:
         self.params = params
         self.m = m
 
-    def evaluate(self, p: float, d: np.ndarray):
-        """(J, dJ/dp, grad_diag) at (p, d)."""
+    def evaluate(self, p: float, d: np.ndarray, derivatives: bool = True):
+        """(J, dJ/dp, grad_diag) at (p, d); with derivatives=False, (J, None, None)."""
         dband = (0, 0, np.asarray(d, dtype=np.complex128).reshape(1, -1))
         kl, ku, band = _band_sum(self.n, [self.a0, (self.a1[0], self.a1[1], p * self.a1[2]), dband])
         pen = Pencil(self.n, kl, ku, band, self.b[0], self.b[1], self.b[2])
         shifts = [simm_shift_build(pen, s, self.f, self.m) for s in self.sigmas]
-        out = simm_gradient(shifts, self.regions, self.params, self.a1[2], self.a1[0], self.a1[1])
+        out = simm_gradient(shifts, self.regions, self.params, self.a1[2], self.a1[0], self.a1[1],
+                            want_diag=derivatives, want_dp=derivatives)
         del shifts, pen
         return out
 

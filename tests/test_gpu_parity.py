@@ -627,16 +627,20 @@ def test_gradient_matches_oracle_and_fd(S, case):
                             pen.kl_b, pen.ku_b, pen.b_band)
     h = 1e-6
     d0 = np.zeros(n, dtype=np.complex128)
-    Jp = prob.evaluate(h, d0)[0]
-    Jm = prob.evaluate(-h, d0)[0]
+    J_only = prob.evaluate(0.0, d0, derivatives=False)
+    assert J_only[1] is None and J_only[2] is None
+    assert abs(J_only[0] - J) <= 1e-12 * J
+    Jp = prob.evaluate(h, d0, derivatives=False)[0]
+    Jm = prob.evaluate(-h, d0, derivatives=False)[0]
     fd = (Jp - Jm) / (2 * h)
     say("  dJ/dp", dp, "central difference", fd)
     assert abs(dp - fd) <= 1e-6 * abs(fd)
     for i in (0, n // 2 + 1):
         e = np.zeros(n, dtype=np.complex128)
         e[i] = h
-        fr = (prob.evaluate(0.0, e)[0] - prob.evaluate(0.0, -e)[0]) / (2 * h)
-        fi = (prob.evaluate(0.0, 1j * e)[0] - prob.evaluate(0.0, -1j * e)[0]) / (2 * h)
+        Jd = [prob.evaluate(0.0, v, derivatives=False)[0] for v in (e, -e, 1j * e, -1j * e)]
+        fr = (Jd[0] - Jd[1]) / (2 * h)
+        fi = (Jd[2] - Jd[3]) / (2 * h)
         say("  grad_diag", i, gd[i], "central difference", fr + 1j * fi)
         assert abs(gd[i] - (fr + 1j * fi)) <= 1e-6 * scale
 

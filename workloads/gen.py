@@ -250,3 +250,17 @@ def make_batch(name: str) -> list[tuple[Pencil, np.ndarray, dict]]:
         out.append((pencil, f, params))
     return out
 
+
+
+def random_band_matrix(n: int, k: int, seed: int, scale: float) -> np.ndarray:
+    """Band (2k+1, n), LAPACK layout, of a matrix with half-bandwidth k whose
+    in-band entries are iid real N(0, 1) times ``scale`` (the perturbation
+    direction A1 of the differentiation workload)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    a = _empty_band(n, k, k)
+    for off in range(-k, k + 1):
+        m = n - abs(off)
+        rows = np.arange(max(0, -off), max(0, -off) + m)
+        cols = rows + off
+        a[k + rows - cols, cols] = scale * rng.standard_normal(m)
+    return a

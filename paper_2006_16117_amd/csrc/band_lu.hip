@@ -452,8 +452,13 @@ simm_status band_lu(int64_t n, int kl, int ku, cplx* AB, int* ipiv, cplx* LP, in
     a.info = info;
     a.zidx = (int64_t)a.ldab * n;
     int64_t count = 0;
-    const simm_status rc = (2 * NB + kl <= 256) ? launch_lu<256>(a, st, cancel, count)
-                                                : launch_lu<512>(a, st, cancel, count);
+    // the smallest workgroup that holds the window: fewer wavefronts to meet at each
+    // column step's barrier (the pivot and the arithmetic do not depend on the split)
+    const int rows = 2 * NB + kl;
+    const simm_status rc = (rows <= 64)    ? launch_lu<64>(a, st, cancel, count)
+                           : (rows <= 128) ? launch_lu<128>(a, st, cancel, count)
+                           : (rows <= 256) ? launch_lu<256>(a, st, cancel, count)
+                                           : launch_lu<512>(a, st, cancel, count);
     if (launches) *launches = count;
     SIMM_TRY(rc);
     SIMM_HIP_TRY(hipGetLastError());

@@ -845,6 +845,40 @@ simm_status spike_prepare(SpikeFactor& f, hipStream_t st) {
     return SIMM_OK;
 }
 
+// A second set of the per-application buffers of a prepared factor (sweep outputs,
+// chain states, group outputs, barrier counters, error flag), so that applications of
+// one factor can run on several streams at once.  The clone shares the factor data
+// and spike_release on it frees only its own buffers.
+simm_status spike_clone_scratch(const SpikeFactor& base, SpikeFactor& out, hipStream_t st) {
+    out = base;
+    out.mem = nullptr;
+    const int kl = base.klx, K = base.K;
+    const size_t elems = (size_t)base.n16 + (size_t)base.P * kl * 2 + (size_t)base.P * K * 2 +
+                         (size_t)base.G * 2 * (kl + K) + (size_t)(base.G + 1) * 16 + 64;
+    SIMM_HIP_TRY(hipMalloc(&out.mem, sizeof(cplx) * elems + 12 * 256));
+    char* p = reinterpret_cast<char*>(out.mem);
+    auto take = [&](size_t count) {
+        char* r = p;
+        p += (sizeof(cplx) * count + 255) & ~(size_t)255;
+        return reinterpret_cast<cplx*>(r);
+    };
+    out.tauL = take((size_t)base.P * kl);
+    out.tL = take((size_t)base.P * kl);
+    out.tauU = take((size_t)base.P * K);
+    out.tU = take((size_t)base.P * K);
+    out.z = take((size_t)base.n16);
+    out.goutL = take((size_t)base.G * kl);
+    out.goutU = take((size_t)base.G * K);
+    out.tgL = take((size_t)base.G * kl);
+    out.tgU = take((size_t)base.G * K);
+    out.counter = reinterpret_cast<unsigned*>(take((size_t)(base.G + 1) * (SPIKE_CTR_STRIDE / 4)));
+    out.err = reinterpret_cast<int*>(take(4));
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned*>(out.err), 1, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, out.counter, (int)((base.G + 1) * SPIKE_CTR_STRIDE), 0u);
+    SIMM_HIP_TRY(hipGetLastError());
+    return SIMM_OK;
+}
+
 void spike_release(SpikeFactor& f) {
     (void)hipFree(f.mem);
     f.mem = nullptr;

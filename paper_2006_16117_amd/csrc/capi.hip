@@ -1481,7 +1481,13 @@ simm_status multiplicities(simm_result_s* R, const cplx* F, int k, double rel_to
 // Adjoint gradient of J = sum_R ||x_R||^2 over the squares `regs` (see simm_gradient).
 // The conjugate-transposed pencil (A^H, B^H) is factored once per shift at conj(sigma);
 // each square gets one Krylov space of that pencil started from x_R, whose fine-rule
-// solutions at the conjugated nodes approximate lambda_j = (A - z_j B)^{-H} x_R.
+// solutions at the conjugated nodes approximate lambda_j = (A - z_j B)^{-H} x_R.  The
+// squares of a shift are dealt round-robin to GRAD_WORKERS host threads, each with a
+// stream, a copy of the factor's per-application buffers and its own accumulators
+// (J, dJ/dp, the diagonal gradient); the accumulators are summed in worker order at
+// the end, so the result does not depend on timing.
+constexpr int GRAD_WORKERS = 4;
+
 simm_status gradient(const std::vector<simm_shift_s*>& shifts, const std::vector<int64_t>& regs,
                      const simm_params* prm, int kl1, int ku1, const cplx* A1, double* J, double* dJdp, cplx* grad,
                      hipStream_t st) {
@@ -1491,6 +1497,7 @@ simm_status gradient(const std::vector<simm_shift_s*>& shifts, const std::vector
     const int g = prm->gauss_per_edge;
     const int nf = 8 * g;
     constexpr int LDY = 128;
+    const bool adjoint = (A1 != nullptr || grad != nullptr);
     Rule rule;
     SIMM_TRY(rule.make(g, st));
     int mmax = 1;
@@ -1523,7 +1530,7 @@ simm_status gradient(const std::vector<simm_shift_s*>& shifts, const std::vector
     adj.klb = p->B ? p->kub : 0;
     adj.kub = p->B ? p->klb : 0;
     adj.dev = p->dev;
-    if (A1 || grad) {
+    if (adjoint) {
         SIMM_TRY(dalloc(&adj.A, (size_t)(p->kla + p->kua + 1) * n));
         SIMM_TRY(conj_transpose_band(n, p->kla, p->kua, p->A, adj.A, st));
         if (p->B) {
@@ -1532,40 +1539,71 @@ simm_status gradient(const std::vector<simm_shift_s*>& shifts, const std::vector
         }
     }
 
-    DevBuf accb, xb, wb, zb, z1b, yb, cwb, kb, pb;
-    SIMM_TRY(accb.alloc(sizeof(double) * 2, st));
-    SIMM_HIP_TRY(hipMemsetAsync(accb.p, 0, sizeof(double) * 2, st));
-    SIMM_TRY(xb.alloc(sizeof(cplx) * (size_t)n, st));
-    if (A1) {
-        SIMM_TRY(wb.alloc(sizeof(cplx) * (size_t)n * mmax, st));
-        SIMM_TRY(z1b.alloc(sizeof(cplx) * (size_t)n * 128, st));
-    }
+    // per-worker buffers (allocated on st, used on the worker streams after st is
+    // synchronized, freed on st after the workers' streams are)
+    struct Worker {
+        hipStream_t st = nullptr;
+        SpikeFactor sp;
+        bool has_sp = false;
+        DevBuf xb, zb, z1b, yb, cwb, kb, pb;
+        simm_status rc = SIMM_OK;
+        std::string msg;
+    };
+    const int W = adjoint ? GRAD_WORKERS : 1;
+    DevBuf accb, wb, gradsb;   // declared before the workers: freed after their streams drain
+    std::vector<Worker> wk((size_t)W);
+    struct StreamRelease {
+        std::vector<Worker>* w;
+        ~StreamRelease() {
+            for (auto& x : *w) {
+                if (x.st) (void)hipStreamSynchronize(x.st);
+                if (x.has_sp) spike_release(x.sp);
+            }
+            for (auto& x : *w)
+                if (x.st) (void)hipStreamDestroy(x.st);
+        }
+    } stream_release{&wk};
+    SIMM_TRY(accb.alloc(sizeof(double) * 2 * W, st));
+    SIMM_HIP_TRY(hipMemsetAsync(accb.p, 0, sizeof(double) * 2 * W, st));
+    if (A1) SIMM_TRY(wb.alloc(sizeof(cplx) * (size_t)n * mmax, st));
     if (grad) {
-        SIMM_TRY(zb.alloc(sizeof(cplx) * (size_t)n * 128, st));
-        SIMM_HIP_TRY(hipMemsetAsync(grad, 0, sizeof(cplx) * (size_t)n, st));
+        SIMM_TRY(gradsb.alloc(sizeof(cplx) * (size_t)n * W, st));
+        SIMM_HIP_TRY(hipMemsetAsync(gradsb.p, 0, sizeof(cplx) * (size_t)n * W, st));
     }
-    SIMM_TRY(yb.alloc(sizeof(cplx) * (size_t)2 * nf * LDY, st));
-    SIMM_TRY(cwb.alloc(sizeof(cplx) * (size_t)nf, st));
-    SIMM_TRY(kb.alloc(sizeof(cplx) * (size_t)128 * 128, st));
-    SIMM_TRY(pb.alloc(sizeof(cplx) * (size_t)grad_part_elems(n), st));
-    cplx* Yf = yb.as<cplx>();
-    cplx* Ya = Yf + (size_t)nf * LDY;
+    for (int w = 0; w < W; ++w) {
+        Worker& x = wk[(size_t)w];
+        SIMM_HIP_TRY(hipStreamCreateWithFlags(&x.st, hipStreamNonBlocking));
+        SIMM_TRY(x.xb.alloc(sizeof(cplx) * (size_t)n, st));
+        if (A1) SIMM_TRY(x.z1b.alloc(sizeof(cplx) * (size_t)n * 128, st));
+        if (grad) SIMM_TRY(x.zb.alloc(sizeof(cplx) * (size_t)n * 128, st));
+        SIMM_TRY(x.yb.alloc(sizeof(cplx) * (size_t)2 * nf * LDY, st));
+        SIMM_TRY(x.cwb.alloc(sizeof(cplx) * (size_t)nf, st));
+        SIMM_TRY(x.kb.alloc(sizeof(cplx) * (size_t)128 * 128, st));
+        SIMM_TRY(x.pb.alloc(sizeof(cplx) * (size_t)grad_part_elems(n), st));
+    }
+    int dev = 0;
+    SIMM_HIP_TRY(hipGetDevice(&dev));
 
     std::vector<int> used;
     for (int64_t r = 0; r < N; ++r) used.push_back((int)regs[4 * r + 3]);
     std::sort(used.begin(), used.end());
     used.erase(std::unique(used.begin(), used.end()), used.end());
+    int64_t next_worker = 0;   // squares are dealt to workers in order across shifts
     for (int si : used) {
         simm_shift_s* fs = shifts[si];
         const int mf = fs->m_eff;
-        if (!A1 && !grad) {
-            // J alone: ||x_R||^2 of every square, no adjoint
-            for (int64_t r = 0; r < N; ++r) {
-                if (regs[4 * r + 3] != si || !(eo.nsf[r] > 0.0)) continue;
-                SIMM_TRY(project(n, mf, fs->V, n, sums + (2 * r + 1) * mmax, mmax, 1, xb.as<cplx>(), nullptr,
+        std::vector<int64_t> rs;   // this shift's squares whose s_f does not vanish
+        for (int64_t r = 0; r < N; ++r)
+            if (regs[4 * r + 3] == si && eo.nsf[r] > 0.0) rs.push_back(r);
+        if (rs.empty()) continue;
+        if (!adjoint) {
+            // J alone: ||x_R||^2 of every square
+            Worker& x = wk[0];
+            for (int64_t r : rs) {
+                SIMM_TRY(project(n, mf, fs->V, n, sums + (2 * r + 1) * mmax, mmax, 1, x.xb.as<cplx>(), nullptr,
                                  nullptr, 0, SIMM_PROJ_FP64, st));
-                SIMM_TRY(grad_rowdot(n, 0, nullptr, n, nullptr, nullptr, n, xb.as<cplx>(), nullptr, pb.as<cplx>(),
-                                     accb.as<double>(), st));
+                SIMM_TRY(grad_rowdot(n, 0, nullptr, n, nullptr, nullptr, n, x.xb.as<cplx>(), nullptr,
+                                     x.pb.as<cplx>(), accb.as<double>(), st));
             }
             continue;
         }
@@ -1576,13 +1614,18 @@ simm_status gradient(const std::vector<simm_shift_s*>& shifts, const std::vector
             for (int k = 0; k < mf; ++k)
                 SIMM_TRY(prepare_input(n, fs->V + (int64_t)k * n, A1, kl1, ku1, nullptr, nullptr,
                                        wb.as<cplx>() + (int64_t)k * n, nullptr, st));
+        for (auto& x : wk) {
+            if (x.has_sp) spike_release(x.sp);
+            x.has_sp = false;
+            SIMM_TRY(spike_clone_scratch(af->spike, x.sp, st));
+            x.has_sp = true;
+        }
+        SIMM_HIP_TRY(hipStreamSynchronize(st));
         const ShiftDev fd = shift_dev(fs);
-        for (int64_t r = 0; r < N; ++r) {
-            if (regs[4 * r + 3] != si) continue;
-            // x_R = V s_f; a square whose s_f vanishes adds nothing
-            if (!(eo.nsf[r] > 0.0)) continue;
-            SIMM_TRY(project(n, mf, fs->V, n, sums + (2 * r + 1) * mmax, mmax, 1, xb.as<cplx>(), nullptr, nullptr, 0,
-                             SIMM_PROJ_FP64, st));
+        // one square on worker x: x_R, the adjoint Krylov space, K_R, Z, Z1, row dots
+        auto square = [&](Worker& x, int w, int64_t r) -> simm_status {
+            SIMM_TRY(project(n, mf, fs->V, n, sums + (2 * r + 1) * mmax, mmax, 1, x.xb.as<cplx>(), nullptr, nullptr,
+                             0, SIMM_PROJ_FP64, x.st));
             simm_shift_s kv;
             kv.p = &adj;
             kv.sigma = af->sigma;
@@ -1591,10 +1634,10 @@ simm_status gradient(const std::vector<simm_shift_s*>& shifts, const std::vector
             kv.AB = af->AB;
             kv.ipiv = af->ipiv;
             kv.LP = af->LP;
-            kv.spike = af->spike;
+            kv.spike = x.sp;
             kv.sweeps_ready = true;
             kv.factor_borrowed = true;
-            SIMM_TRY(krylov_shift(&kv, xb.as<cplx>(), fs->m, st, nullptr));
+            SIMM_TRY(krylov_shift(&kv, x.xb.as<cplx>(), fs->m, x.st, nullptr));
             const int ma = kv.m_eff;
             if (ma > 128) {
                 set_error("Krylov dimension above 128");
@@ -1602,23 +1645,53 @@ simm_status gradient(const std::vector<simm_shift_s*>& shifts, const std::vector
             }
             const ShiftDev ad = shift_dev(&kv);
             const int level = (int)regs[4 * r];
+            cplx* Yf = x.yb.as<cplx>();
+            cplx* Ya = Yf + (size_t)nf * LDY;
             SIMM_TRY(fine_solutions(fd, ip, rule.dev, level, regs[4 * r + 1], regs[4 * r + 2], false, Yf, LDY,
-                                    cwb.as<cplx>(), st));
-            SIMM_TRY(fine_solutions(ad, ip, rule.dev, level, regs[4 * r + 1], regs[4 * r + 2], true, Ya, LDY, nullptr,
-                                    st));
-            SIMM_TRY(grad_kmat(nf, Yf, Ya, LDY, cwb.as<cplx>(), mf, ma, kb.as<cplx>(), st));
+                                    x.cwb.as<cplx>(), x.st));
+            SIMM_TRY(fine_solutions(ad, ip, rule.dev, level, regs[4 * r + 1], regs[4 * r + 2], true, Ya, LDY,
+                                    nullptr, x.st));
+            SIMM_TRY(grad_kmat(nf, Yf, Ya, LDY, x.cwb.as<cplx>(), mf, ma, x.kb.as<cplx>(), x.st));
             if (grad)
-                SIMM_TRY(project(n, mf, fs->V, n, kb.as<cplx>(), mf, ma, zb.as<cplx>(), nullptr, nullptr, 0,
-                                 SIMM_PROJ_FP64, st));
+                SIMM_TRY(project(n, mf, fs->V, n, x.kb.as<cplx>(), mf, ma, x.zb.as<cplx>(), nullptr, nullptr, 0,
+                                 SIMM_PROJ_FP64, x.st));
             if (A1)
-                SIMM_TRY(project(n, mf, wb.as<cplx>(), n, kb.as<cplx>(), mf, ma, z1b.as<cplx>(), nullptr, nullptr, 0,
-                                 SIMM_PROJ_FP64, st));
-            SIMM_TRY(grad_rowdot(n, ma, kv.V, n, grad ? zb.as<cplx>() : nullptr, A1 ? z1b.as<cplx>() : nullptr, n,
-                                 xb.as<cplx>(), grad, pb.as<cplx>(), accb.as<double>(), st));
-            SIMM_HIP_TRY(hipStreamSynchronize(st));   // kv's buffers are freed at scope exit
+                SIMM_TRY(project(n, mf, wb.as<cplx>(), n, x.kb.as<cplx>(), mf, ma, x.z1b.as<cplx>(), nullptr,
+                                 nullptr, 0, SIMM_PROJ_FP64, x.st));
+            SIMM_TRY(grad_rowdot(n, ma, kv.V, n, grad ? x.zb.as<cplx>() : nullptr, A1 ? x.z1b.as<cplx>() : nullptr,
+                                 n, x.xb.as<cplx>(), grad ? gradsb.as<cplx>() + (int64_t)w * n : nullptr,
+                                 x.pb.as<cplx>(), accb.as<double>() + 2 * w, x.st));
+            SIMM_HIP_TRY(hipStreamSynchronize(x.st));   // kv's buffers are freed at scope exit
+            return SIMM_OK;
+        };
+        const int64_t first = next_worker;
+        auto run_worker = [&](int w) {
+            (void)hipSetDevice(dev);
+            Worker& x = wk[(size_t)w];
+            for (size_t k = 0; k < rs.size(); ++k) {
+                if ((int)((first + (int64_t)k) % W) != w) continue;
+                const simm_status rc = square(x, w, rs[k]);
+                if (rc != SIMM_OK) {
+                    x.rc = rc;
+                    x.msg = simm_last_error();
+                    return;
+                }
+            }
+        };
+        std::vector<std::thread> pool;
+        for (int w = 1; w < W; ++w) pool.emplace_back(run_worker, w);
+        run_worker(0);
+        for (auto& t : pool) t.join();
+        next_worker = (first + (int64_t)rs.size()) % W;
+        for (auto& x : wk) {
+            if (x.rc != SIMM_OK) {
+                for (auto& y : wk) (void)hipStreamSynchronize(y.st);   // before af and the buffers go
+                set_error(x.msg);
+                return x.rc;
+            }
         }
-        SIMM_HIP_TRY(hipStreamSynchronize(st));
     }
+    SIMM_TRY(grad_combine(n, W, gradsb.as<cplx>(), grad, accb.as<double>(), st));
     double acc[2] = {0.0, 0.0};
     SIMM_HIP_TRY(hipMemcpyAsync(acc, accb.p, sizeof(acc), hipMemcpyDeviceToHost, st));
     SIMM_HIP_TRY(hipStreamSynchronize(st));

@@ -140,6 +140,34 @@ simm_status grad_rowdot(int64_t n, int ma, const cplx* Vp, int64_t ldv, const cp
     return SIMM_OK;
 }
 
+// grad = sum over the W per-worker diagonal gradients, in worker order (grad may be
+// null); acc[0], acc[1] += the other workers' (J, dJ/dp) pairs acc[2w], acc[2w + 1].
+__global__ void k_grad_combine(int64_t n, int W, const cplx* __restrict__ grads, cplx* __restrict__ grad,
+                               double* __restrict__ acc) {
+    const int64_t i = (int64_t)blockIdx.x * GR_THREADS + threadIdx.x;
+    if (grad != nullptr && i < n) {
+        cplx s = grads[i];
+        for (int w = 1; w < W; ++w) s = s + grads[(int64_t)w * n + i];
+        grad[i] = s;
+    }
+    if (i == 0) {
+        double a = acc[0], b = acc[1];
+        for (int w = 1; w < W; ++w) {
+            a += acc[2 * w];
+            b += acc[2 * w + 1];
+        }
+        acc[0] = a;
+        acc[1] = b;
+    }
+}
+
+simm_status grad_combine(int64_t n, int W, const cplx* grads, cplx* grad, double* acc, hipStream_t st) {
+    const int64_t nblk = grad != nullptr ? (n + GR_THREADS - 1) / GR_THREADS : 1;
+    hipLaunchKernelGGL(k_grad_combine, dim3((unsigned)nblk), dim3(GR_THREADS), 0, st, n, W, grads, grad, acc);
+    SIMM_HIP_TRY(hipGetLastError());
+    return SIMM_OK;
+}
+
 int64_t grad_part_elems(int64_t n) { return 2 * ((n + GR_THREADS - 1) / GR_THREADS); }
 
 }  // namespace simm

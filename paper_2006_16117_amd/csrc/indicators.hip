@@ -233,7 +233,7 @@ __global__ __launch_bounds__(IND_THREADS) void k_indicators(const ShiftDev* __re
 // solution of eq. (y) in the Arnoldi basis; row j of Y (stride ldy) holds y_j.  With
 // conj_nodes the nodes are conjugated: the shift then belongs to the conjugate-transposed
 // pencil at conj(sigma), whose resolvent at conj(z_j) is (A - z_j B)^{-H}.  cw, when
-// given, receives c_j = w_j / (2 pi i).  One workgroup; wave w takes the points w + 4t.
+// given, receives c_j = w_j / (2 pi i).  Workgroup b's wave w takes point 4 b + w.
 __global__ __launch_bounds__(IND_THREADS) void k_fine_solutions(ShiftDev sh, IndicatorParams prm, RuleDev rule,
                                                                 int level, int64_t ix, int64_t iy, int conj_nodes,
                                                                 cplx* __restrict__ Y, int ldy, cplx* __restrict__ cw) {
@@ -261,7 +261,8 @@ __global__ __launch_bounds__(IND_THREADS) void k_fine_solutions(ShiftDev sh, Ind
     const int nf = 4 * g2;
     const cplx one = mk(1.0, 0.0);
     const double twopi = 6.283185307179586;
-    for (int q = wave; q < nf; q += IND_WAVES) {
+    const int q = (int)blockIdx.x * IND_WAVES + wave;
+    if (q < nf) {
         const int e = q / g2;
         const int idx = q - e * g2;
         cplx z, wq;
@@ -301,8 +302,9 @@ simm_status fine_solutions(const ShiftDev& sh, const IndicatorParams& prm, const
         return SIMM_EUNSUPPORTED;
     }
     const size_t lds = sizeof(cplx) * (size_t)(sh.m * (sh.m + 1) / 2 + 1);
-    hipLaunchKernelGGL(k_fine_solutions, dim3(1), dim3(IND_THREADS), lds, st, sh, prm, rule, level, ix, iy,
-                       conj_nodes ? 1 : 0, Y, ldy, cw);
+    const int nf = 8 * rule.g;
+    hipLaunchKernelGGL(k_fine_solutions, dim3((unsigned)((nf + IND_WAVES - 1) / IND_WAVES)), dim3(IND_THREADS), lds,
+                       st, sh, prm, rule, level, ix, iy, conj_nodes ? 1 : 0, Y, ldy, cw);
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;
 }

@@ -103,6 +103,7 @@ int64_t spike_chunk_len(int64_t n, int kl, int K);
 simm_status spike_prepare(SpikeFactor& f, hipStream_t st);
 simm_status spike_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int* active, hipStream_t st);
 void spike_release(SpikeFactor& f);
+simm_status spike_clone_scratch(const SpikeFactor& base, SpikeFactor& out, hipStream_t st);
 int64_t spike_bytes_per_apply(const SpikeFactor& f);
 
 // ---- Gram-Schmidt (arnoldi.hip) ----
@@ -177,6 +178,8 @@ simm_status grad_kmat(int nf, const cplx* Yf, const cplx* Ya, int ldy, const cpl
 simm_status grad_rowdot(int64_t n, int ma, const cplx* Vp, int64_t ldv, const cplx* Z, const cplx* Z1, int64_t ldz,
                         const cplx* x, cplx* grad, cplx* part, double* acc, hipStream_t st);
 int64_t grad_part_elems(int64_t n);
+// grad = sum of the W per-worker gradients (n each, worker order); acc[0..1] += acc[2w..2w+1]
+simm_status grad_combine(int64_t n, int W, const cplx* grads, cplx* grad, double* acc, hipStream_t st);
 
 // ---- projection (project.hip) ----
 simm_status project(int64_t n, int m, const cplx* V, int64_t ldv, const cplx* Y, int64_t ldy, int64_t c, cplx* X,

@@ -181,7 +181,7 @@ class Pencil:
         return self
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.simm_pencil_destroy(self.handle)
             self.handle = None
 
@@ -220,7 +220,7 @@ class Shift:
         return y
 
     def __del__(self):
-        if getattr(self, "handle", None) and self._owner is None:
+        if getattr(self, "handle", None) and self._owner is None and _lib is not None:
             _lib.simm_shift_destroy(self.handle)
             self.handle = None
 
@@ -414,7 +414,7 @@ class Result:
         return Shift(h, owner=self)
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.simm_result_destroy(self.handle)
             self.handle = None
 

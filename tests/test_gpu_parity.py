@@ -45,7 +45,9 @@ CASES = [
     ("ragged-wide", 1037, 21, 79, "identity", 33, 0.2 + 0.0j, {}),
     ("m=n", 24, 2, 80, "identity", 24, 0.0 + 0.1j, {}),
     ("tiny", 5, 1, 81, "tridiag", 3, 0.3 + 0.3j, {}),
-    # band LU workgroup sizes: window 2*16 + kl rows, 256 threads up to kl = 224, 512 up to 480
+    # band LU workgroup sizes: window 2*16 + kl rows; 64 threads up to kl = 32, 128 up to 96,
+    # 256 up to 224, 512 up to 480
+    ("band60-pivoting", 700, 60, 86, "tridiag", 20, 0.05 + 0.05j, dict(d_half=0.05, e_scale=1.0)),
     ("band224", 900, 224, 83, "tridiag", 20, 0.1 + 0.1j, {}),
     ("band240-pivoting", 1300, 240, 84, "identity", 20, -0.2 + 0.05j, dict(d_half=0.05, e_scale=1.0)),
     ("band480-pivoting", 1100, 480, 85, "identity", 16, 0.05 + 0.0j, dict(d_half=0.05, e_scale=1.0)),

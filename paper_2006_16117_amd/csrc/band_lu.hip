@@ -166,11 +166,12 @@ struct FactorCtx {
 // Column step t of the panel factorization: partial pivoting by the largest
 // |re| + |im| with the first position on ties (LAPACK's izamax rule).  Rows never
 // move between threads: each thread carries the position `pos` its row holds, and
-// an interchange just swaps two positions.  Per step one LDS barrier: each wave
-// writes its candidate (the row with its largest entry, that row's reciprocal
-// pivot, and the (max, position) pair) spread over lanes t .. NB+1, so it costs one
-// 16-byte LDS write per lane; after the barrier each wave reads all candidates the
-// same way and moves the winner's row into scalar registers with lane reads.
+// an interchange just swaps two positions.  Per step one LDS barrier: the lane that
+// holds each wave's candidate (the wave's largest entry, first position on ties)
+// writes that row, its reciprocal pivot and the (max, position) pair to the wave's
+// record; after the barrier every lane reads the records' (max, position) pairs,
+// picks the winner and reads its row with broadcast LDS reads (no lane reads on the
+// chain).
 template <int T, int t>
 __device__ __forceinline__ void factor_steps(const LuArgs& a, cplx (&X)[NB], int& pos, const FactorCtx& f) {
     constexpr int W = T / 64;
@@ -187,27 +188,22 @@ __device__ __forceinline__ void factor_steps(const LuArgs& a, cplx (&X)[NB], int
         const int kmin = wave_min_int(key);
         const unsigned long long bal = __ballot(key == kmin);
         const int wl = bal ? __ffsll((long long)bal) - 1 : 0;
-        cplx rec = mk(m, (double)kmin);
+        if (f.lane == wl) {
+            cplx* rec = f.cand + (buf * W + f.wave) * CSTRIDE;
 #pragma unroll
-        for (int c = t; c < NB; ++c) {
-            const cplx x = rdlane(X[c], wl);
-            rec = csel(f.lane == c, x, rec);
+            for (int c = t; c < NB; ++c) ldsw(rec + c, X[c]);
+            ldsw(rec + NB, inv_own);
+            ldsw(rec + NB + 1, mk(m, (double)kmin));
         }
-        {
-            const cplx x = rdlane(inv_own, wl);
-            rec = csel(f.lane == NB, x, rec);
-        }
-        if (f.lane >= t && f.lane <= NB + 1) ldsw(f.cand + (buf * W + f.wave) * CSTRIDE + f.lane, rec);
         lds_barrier();
-        cplx cw[W];
-#pragma unroll
-        for (int w = 0; w < W; ++w) cw[w] = ldsr(f.cand + (buf * W + w) * CSTRIDE + min(max(f.lane, t), NB + 1));
-        double best = rdlane_d(cw[0].re, NB + 1);
-        int bpos = (int)rdlane_d(cw[0].im, NB + 1), bw = 0;
+        const cplx r0 = ldsr(f.cand + (buf * W) * CSTRIDE + NB + 1);
+        double best = r0.re;
+        int bpos = (int)r0.im, bw = 0;
 #pragma unroll
         for (int w = 1; w < W; ++w) {
-            const double vw = rdlane_d(cw[w].re, NB + 1);
-            const int pw = (int)rdlane_d(cw[w].im, NB + 1);
+            const cplx rw = ldsr(f.cand + (buf * W + w) * CSTRIDE + NB + 1);
+            const double vw = rw.re;
+            const int pw = (int)rw.im;
             const bool take = vw > best || (vw == best && pw < bpos);
             best = take ? vw : best;
             bpos = take ? pw : bpos;
@@ -221,12 +217,10 @@ __device__ __forceinline__ void factor_steps(const LuArgs& a, cplx (&X)[NB], int
             if (zero) atomicMin(a.info, (int)(j + 1));
         }
         if (!zero) {
-            cplx mine = cw[0];
-#pragma unroll
-            for (int w = 1; w < W; ++w) mine = csel(bw == w, cw[w], mine);
+            const cplx* win = f.cand + (buf * W + bw) * CSTRIDE;
             cplx u[NB + 1];
 #pragma unroll
-            for (int c = t; c <= NB; ++c) u[c] = rdlane(mine, c);
+            for (int c = t; c <= NB; ++c) u[c] = ldsr(win + c);
             const int p0 = pos;
             pos = (p0 == t) ? bpos : ((p0 == bpos) ? t : p0);
             if (f.prow && pos > t) {

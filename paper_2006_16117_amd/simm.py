@@ -341,13 +341,14 @@ class ProjectedNorms:
             @staticmethod
             def forward(ctx, p, d):
                 J, dp, gd = prob.evaluate(float(p.detach().cpu()), d.detach().cpu().numpy())
-                ctx.save_for_backward(torch.tensor(dp, dtype=torch.float64), torch.from_numpy(gd))
-                return torch.tensor(J, dtype=torch.float64)
+                ctx.save_for_backward(torch.tensor(dp, dtype=torch.float64, device=p.device),
+                                      torch.from_numpy(gd).to(d.device))
+                return torch.tensor(J, dtype=torch.float64, device=p.device)
 
             @staticmethod
             def backward(ctx, gJ):
                 dp, gd = ctx.saved_tensors
-                return gJ * dp, gJ * gd
+                return gJ * dp, gJ.to(gd.device) * gd
 
         return _Fn.apply
 

@@ -665,6 +665,12 @@ def test_gradient_autograd_function(S):
     assert abs(J.item() - J_o) <= 1e-8 * J_o
     assert abs(p.grad.item() - 3.0 * dp_o) <= 1e-6 * abs(3.0 * dp_o)
     assert np.max(np.abs(d.grad.numpy() - 3.0 * gd_o)) <= 1e-6 * np.max(np.abs(3.0 * gd_o))
+    # inputs on the GPU: the gradients come back there
+    pg = torch.tensor(0.25, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    dg = torch.zeros(n, dtype=torch.complex128, device="cuda:0", requires_grad=True)
+    fn(pg, dg).backward()
+    assert pg.grad.device.type == "cuda" and dg.grad.device.type == "cuda"
+    assert abs(pg.grad.item() - dp_o) <= 1e-6 * abs(dp_o)
 
 
 def test_gradient_errors(S):

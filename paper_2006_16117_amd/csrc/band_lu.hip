@@ -122,6 +122,8 @@ __device__ inline double rdlane_d(double v, int l) {
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
     return __hiloint2double(hi, lo);
 }
+// value of the partner lane (lane xor 1)
+__device__ inline cplx swap_pair(cplx v) { return cplx{dpp_d<0xB1>(v.re), dpp_d<0xB1>(v.im)}; }
 __device__ inline cplx rdlane(cplx v, int l) { return cplx{rdlane_d(v.re, l), rdlane_d(v.im, l)}; }
 
 // 1 / u by Smith's scaling (no overflow for any finite nonzero u), without branches.
@@ -358,17 +360,57 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs a, int64_t b) {
         }
         lds_barrier();
         // ---- rank-NB update of rows NB .. Rb-1
-        if (r >= NB && r < Rb) {
+        if constexpr (T == 256) {
+            // lanes 2k and 2k+1 (rows r, r+1) share the update: the even lane takes
+            // columns 0..7 of both rows, the odd lane columns 8..15, so that each LDS
+            // read of U12 serves two rows (half the LDS traffic of one row per lane);
+            // halves go to the partner lane and back with a lane swap.  Every entry gets
+            // the same operations in the same order; rows outside NB .. Rb-1 pass through
+            // with zero multipliers (rows above NB are not used after the solve).
+            const bool odd = (tid & 1) != 0;
+            constexpr int H = NB / 2;
+            cplx A[H], B[H];
+#pragma unroll
+            for (int i = 0; i < H; ++i) {
+                A[i] = csel(odd, X[H + i], X[i]);
+                B[i] = swap_pair(csel(odd, X[i], X[H + i]));
+            }
+            const int cb = odd ? H : 0;
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
+                const cplx lq = swap_pair(Lr[q]);
 #pragma unroll
-                for (int c = 0; c < NB; ++c) X[c] = fms(X[c], Lr[q], ldsr(Ush + q * SROW + c));
+                for (int i = 0; i < H; ++i) {
+                    const cplx u = ldsr(Ush + q * SROW + cb + i);
+                    A[i] = fms(A[i], Lr[q], u);
+                    B[i] = fms(B[i], lq, u);
+                }
                 __builtin_amdgcn_sched_barrier(0);
             }
-            if (wg != 0) {
+#pragma unroll
+            for (int i = 0; i < H; ++i) {
+                const cplx back = swap_pair(B[i]);
+                X[i] = csel(odd, back, A[i]);
+                X[H + i] = csel(odd, A[i], back);
+            }
+            if (r >= NB && r < Rb && wg != 0) {
 #pragma unroll
                 for (int c = 0; c < NB; ++c)
                     if (c < ncols) ab_put(a, j0 + r, c0 + c, X[c]);
+            }
+        } else {
+            if (r >= NB && r < Rb) {
+#pragma unroll
+                for (int q = 0; q < NB; ++q) {
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) X[c] = fms(X[c], Lr[q], ldsr(Ush + q * SROW + c));
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                if (wg != 0) {
+#pragma unroll
+                    for (int c = 0; c < NB; ++c)
+                        if (c < ncols) ab_put(a, j0 + r, c0 + c, X[c]);
+                }
             }
         }
     }

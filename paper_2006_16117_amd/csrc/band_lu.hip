@@ -168,12 +168,14 @@ struct FactorCtx {
 // Column step t of the panel factorization: partial pivoting by the largest
 // |re| + |im| with the first position on ties (LAPACK's izamax rule).  Rows never
 // move between threads: each thread carries the position `pos` its row holds, and
-// an interchange just swaps two positions.  Per step one LDS barrier: the lane that
+// an interchange just swaps two positions.  Per step one or two LDS barriers: the lane that
 // holds each wave's candidate (the wave's largest entry, first position on ties)
-// writes that row, its reciprocal pivot and the (max, position) pair to the wave's
-// record; after the barrier every lane reads the records' (max, position) pairs,
-// picks the winner and reads its row with broadcast LDS reads (no lane reads on the
-// chain).
+// writes the (max, position) pair to the wave's record; after a barrier every lane
+// reads the records, picks the winner, the winning lane writes its row and
+// reciprocal pivot, and after a second barrier every lane reads that row with
+// broadcast LDS reads (no lane reads on the chain).  A single-lane LDS write costs a
+// full LDS pass for the CU, so only one wavefront writes a row.  With one
+// wavefront the row goes with the pair, before a single barrier.
 template <int T, int t>
 __device__ __forceinline__ void factor_steps(const LuArgs& a, cplx (&X)[NB], int& pos, const FactorCtx& f) {
     constexpr int W = T / 64;
@@ -190,12 +192,17 @@ __device__ __forceinline__ void factor_steps(const LuArgs& a, cplx (&X)[NB], int
         const int kmin = wave_min_int(key);
         const unsigned long long bal = __ballot(key == kmin);
         const int wl = bal ? __ffsll((long long)bal) - 1 : 0;
-        if (f.lane == wl) {
-            cplx* rec = f.cand + (buf * W + f.wave) * CSTRIDE;
+        if constexpr (W == 1) {
+            if (f.lane == wl) {
+                cplx* rec = f.cand + buf * CSTRIDE;
 #pragma unroll
-            for (int c = t; c < NB; ++c) ldsw(rec + c, X[c]);
-            ldsw(rec + NB, inv_own);
-            ldsw(rec + NB + 1, mk(m, (double)kmin));
+                for (int c = t; c < NB; ++c) ldsw(rec + c, X[c]);
+                ldsw(rec + NB, inv_own);
+                ldsw(rec + NB + 1, mk(m, (double)kmin));
+            }
+        } else {
+            // several wavefronts share the LDS: first only the (max, position) pairs
+            if (f.lane == wl) ldsw(f.cand + (buf * W + f.wave) * CSTRIDE + NB + 1, mk(m, (double)kmin));
         }
         lds_barrier();
         const cplx r0 = ldsr(f.cand + (buf * W) * CSTRIDE + NB + 1);
@@ -217,6 +224,16 @@ __device__ __forceinline__ void factor_steps(const LuArgs& a, cplx (&X)[NB], int
             a.ipiv[j] = (int)(f.j1 + bpos);
             // singular column: recorded; no interchange, no elimination
             if (zero) atomicMin(a.info, (int)(j + 1));
+        }
+        if constexpr (W > 1) {
+            // then the winning wavefront's candidate lane publishes its row
+            if (f.wave == bw && f.lane == wl) {
+                cplx* rec = f.cand + (buf * W + bw) * CSTRIDE;
+#pragma unroll
+                for (int c = t; c < NB; ++c) ldsw(rec + c, X[c]);
+                ldsw(rec + NB, inv_own);
+            }
+            lds_barrier();
         }
         if (!zero) {
             const cplx* win = f.cand + (buf * W + bw) * CSTRIDE;

@@ -337,43 +337,38 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs a, int64_t b) {
                 for (int c = 0; c < NB; ++c) X[c] = ldsr(S + sr * SROW + c);
             }
         }
-        // ---- unit lower triangular solve of the top NB rows (U12 = L11^{-1} A12)
-        if constexpr (T >= NB * NB) {
-            // one thread per entry (i, c) of the NB x NB block: at step t row t is final
-            // and goes to LDS, the rows below subtract L(i, t) times it (16 LDS barriers
-            // instead of a 16-step chain of LDS reads in one wavefront).  Each entry sees
-            // the operations of the column-by-column substitution, in the same order.
-            const int ti = tid / NB, tc = tid % NB;
-            const bool tin = tid < NB * NB;
-            cplx xt = mk(0.0, 0.0);
-            if (tin) xt = ldsr(S + trace_src(ti, pv) * SROW + tc);
+        // ---- unit lower triangular solve of the top NB rows (U12 = L11^{-1} A12), one
+        // entry (i, c) of the NB x NB block per thread and round (E rounds): at step t
+        // row t is final and goes to LDS, the rows below subtract L(i, t) times it.
+        // Each entry sees the operations of a column-by-column forward substitution, in
+        // the same order.
+        {
+            constexpr int E = (NB * NB + T - 1) / T;
+            cplx xt[E];
+            int ti[E], tc[E];
+            bool tin[E];
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                const int e = tid + k * T;
+                tin[k] = e < NB * NB;
+                ti[k] = e / NB;
+                tc[k] = e % NB;
+                xt[k] = tin[k] ? ldsr(S + trace_src(ti[k], pv) * SROW + tc[k]) : mk(0.0, 0.0);
+            }
 #pragma unroll
             for (int t = 0; t < NB; ++t) {
-                if (tin && ti == t) ldsw(Ush + t * SROW + tc, xt);
+#pragma unroll
+                for (int k = 0; k < E; ++k)
+                    if (tin[k] && ti[k] == t) ldsw(Ush + t * SROW + tc[k], xt[k]);
                 lds_barrier();
-                if (tin && ti > t) xt = fms(xt, ldsr(Lsh + ti * SROW + t), ldsr(Ush + t * SROW + tc));
+#pragma unroll
+                for (int k = 0; k < E; ++k)
+                    if (tin[k] && ti[k] > t)
+                        xt[k] = fms(xt[k], ldsr(Lsh + ti[k] * SROW + t), ldsr(Ush + t * SROW + tc[k]));
             }
-            if (tin && tc < ncols) ab_put(a, j0 + ti, c0 + tc, xt);
-        } else {
-            // fewer threads: the threads holding the top rows switch to one column each
-            // (c = tid), reusing X for it
-            if (r < NB) {
-                const int c = r;
 #pragma unroll
-                for (int t = 0; t < NB; ++t) X[t] = ldsr(S + trace_src(t, pv) * SROW + c);
-#pragma unroll
-                for (int t = 0; t < NB; ++t) {
-#pragma unroll
-                    for (int rr = t + 1; rr < NB; ++rr) X[rr] = fms(X[rr], ldsr(Lsh + rr * SROW + t), X[t]);
-                    __builtin_amdgcn_sched_barrier(0);   // keep later steps' LDS reads from piling up in registers
-                }
-#pragma unroll
-                for (int t = 0; t < NB; ++t) ldsw(Ush + t * SROW + c, X[t]);
-                if (c < ncols) {
-#pragma unroll
-                    for (int t = 0; t < NB; ++t) ab_put(a, j0 + t, c0 + c, X[t]);
-                }
-            }
+            for (int k = 0; k < E; ++k)
+                if (tin[k] && tc[k] < ncols) ab_put(a, j0 + ti[k], c0 + tc[k], xt[k]);
         }
         lds_barrier();
         // ---- rank-NB update of rows NB .. Rb-1

@@ -40,7 +40,11 @@ typedef enum {
     SIMM_ESINGULAR_SHIFT = -5,  /* exact zero pivot: the shift is an eigenvalue of the pencil */
     SIMM_ENOCONV = -6,          /* the QR iteration for the Schur form of H_m did not converge */
     SIMM_ELIMIT = -7,           /* a level holds more squares than max_regions_per_level */
-    SIMM_EUNSUPPORTED = -8      /* size outside what the kernels support (see each call) */
+    SIMM_EUNSUPPORTED = -8,     /* size outside what the kernels support (see each call) */
+    SIMM_EREFINE = -9,          /* FP32 factor: iterative refinement did not reach its residual
+                                   tolerance (the shift falls back to FP64 inside simm_run) */
+    SIMM_EUNRESOLVED = -10      /* simm_gradient: a square's reduced solves (or its adjoint
+                                   ones) leave a residual above eps0 (Definition 3.1) */
 } simm_status;
 
 enum { SIMM_MEM_HOST = 0, SIMM_MEM_DEVICE = 1 };
@@ -156,6 +160,19 @@ simm_status simm_shift_build(simm_pencil p, double sig_re, double sig_im,
                              const double* f, int32_t f_mem, int32_t m,
                              void* hip_stream, simm_shift* out);
 
+/* A shift made from its small data alone (Sec. 2, eqs. (shiftedLS), (eq:many) and
+ * (eq:error)): the reduced solves (I + (sigma - z_j) H_m) y_j = beta e_1, their
+ * residuals and the quadrature sums depend only on sigma, beta = ||(A - sigma B)^{-1} f||
+ * and the Arnoldi matrix H_{m+1,m}.  H: (m_eff + 1) x m_eff complex, column-major
+ * (leading dimension m_eff + 1), upper Hessenberg, host memory, copied.  The Schur form
+ * of H_m is computed on the device, as in simm_shift_build.  The shift has no factor
+ * and no basis: simm_indicators accepts it; simm_shift_basis, simm_shift_apply,
+ * simm_project and simm_gradient return EINVAL on it.
+ * EINVAL: H NULL, NaN/Inf entries, nonzero entries below the subdiagonal, beta not > 0,
+ * m_eff < 1; EUNSUPPORTED: m_eff > 128; ENOCONV if the QR iteration fails. */
+simm_status simm_shift_from_hessenberg(double sig_re, double sig_im, double beta, const double* H, int32_t m_eff,
+                                       void* hip_stream, simm_shift* out);
+
 /* Copies out sigma (2 doubles), beta, m_eff, and optionally (if non-NULL)
  * H_{m_eff+1, m_eff} (column-major complex, leading dimension m_eff+1, host)
  * and the m_eff Ritz values sigma + 1/theta_k (theta_k = eigenvalues of H_m,
@@ -213,7 +230,10 @@ simm_status simm_indicators(const simm_shift* shifts, int32_t n_shifts,
  * n complex values, overwritten.  With dJdp and grad_diag both NULL only J is
  * formed (no adjoint work).  a1_band and grad_diag are in `mem` memory.
  * All shifts must share one pencil and hold their factor and basis; squares whose
- * s_f vanishes contribute nothing.  EINVAL on bad rows or arguments,
+ * s_f vanishes contribute nothing.  Every square must be resolved by its shift
+ * (max_j rho_j <= eps0, Definition 3.1 with eq. (error)), and every square's adjoint
+ * Krylov space likewise at the conjugated nodes; otherwise SIMM_EUNRESOLVED (the
+ * derivatives would not be accurate: raise m).  EINVAL on bad rows or arguments,
  * EUNSUPPORTED if m_eff > 128 or gauss_per_edge > 64; SIMM_ESINGULAR_SHIFT if
  * conj(sigma) is an exact eigenvalue of the adjoint pencil. */
 simm_status simm_gradient(const simm_shift* shifts, int32_t n_shifts, const int64_t* regions,

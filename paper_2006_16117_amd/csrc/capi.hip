@@ -280,16 +280,38 @@ simm_status dalloc(T** p, size_t count) {
 
 // Scratch device buffer, allocated and freed in stream order on the stream of the
 // call that uses it (a plain free would wait for the whole device and serialise
-// concurrent runs on other streams).
+// concurrent runs on other streams).  Stream-ordered memory must not outlive the
+// stream it was allocated on, so every live buffer is registered with its stream, and
+// a stream's owner frees what is still registered on it before destroying the stream
+// (release_stream_buffers); the buffer's own destructor then has nothing left to free.
+struct DevBuf;
+std::mutex g_devbuf_mu;
+std::multimap<hipStream_t, DevBuf*> g_devbuf_live;
+
 struct DevBuf {
     void* p = nullptr;
     hipStream_t st = nullptr;
-    ~DevBuf() {
-        if (p) (void)hipFreeAsync(p, st);
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        std::lock_guard<std::mutex> lk(g_devbuf_mu);
+        release_locked();
+    }
+    void release_locked() {
+        if (!p) return;
+        (void)hipFreeAsync(p, st);
+        p = nullptr;
+        auto range = g_devbuf_live.equal_range(st);
+        for (auto it = range.first; it != range.second; ++it)
+            if (it->second == this) {
+                g_devbuf_live.erase(it);
+                break;
+            }
     }
     simm_status alloc(size_t bytes, hipStream_t stream) {
-        if (p) (void)hipFreeAsync(p, st);
-        p = nullptr;
+        release();
         st = stream;
         hipError_t e = hipMallocAsync(&p, bytes ? bytes : 1, st);
         if (e != hipSuccess) {
@@ -297,11 +319,24 @@ struct DevBuf {
             set_error(std::string("hipMallocAsync: ") + hipGetErrorString(e));
             return e == hipErrorOutOfMemory ? SIMM_ENOMEM : SIMM_EHIP;
         }
+        std::lock_guard<std::mutex> lk(g_devbuf_mu);
+        g_devbuf_live.emplace(st, this);
         return SIMM_OK;
     }
     template <typename T>
     T* as() const { return reinterpret_cast<T*>(p); }
 };
+
+// Frees (in stream order) every buffer still allocated on `st`; called by the owner of
+// a stream before hipStreamDestroy, once no thread uses the stream any more.
+void release_stream_buffers(hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_devbuf_mu);
+    while (true) {
+        auto it = g_devbuf_live.find(st);
+        if (it == g_devbuf_live.end()) break;
+        it->second->release_locked();
+    }
+}
 
 simm_status check_device() {
     int count = 0;
@@ -418,6 +453,43 @@ simm_status prepare_sweeps(simm_shift_s* s, hipStream_t st, KernelClock* clk = n
     return SIMM_OK;
 }
 
+// Schur phase of one shift (hot-path step a5): the complex Schur form H_m = Q T Q^H of
+// the device copy of H (leading dimension ldh, s->m_eff columns), g = beta Q^H e_1,
+// the last row of Q, and the Ritz values sigma + 1/theta from the diagonal of T.
+// status_dev: one device int, the QR iteration's convergence flag.  Synchronous.
+simm_status schur_phase(simm_shift_s* s, int ldh, int* status_dev, hipStream_t st, KernelClock* clk = nullptr) {
+    const int me = s->m_eff;
+    SIMM_TRY(dalloc(&s->T, (size_t)me * (me + 1) / 2));
+    SIMM_TRY(dalloc(&s->Q, (size_t)me * me));
+    SIMM_TRY(dalloc(&s->g, (size_t)me));
+    SIMM_TRY(dalloc(&s->qlast, (size_t)me));
+    SchurOut so{s->T, s->Q, s->g, s->qlast};
+    {
+        KScope ks(clk, SIMM_K_SCHUR);
+        SIMM_TRY(hess_schur(s->H, ldh, me, s->beta, so, status_dev, st));
+    }
+    int schur_status = 0;
+    std::vector<cplx> Tp((size_t)me * (me + 1) / 2);
+    SIMM_HIP_TRY(hipMemcpyAsync(&schur_status, status_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+    SIMM_HIP_TRY(hipMemcpyAsync(Tp.data(), s->T, sizeof(cplx) * Tp.size(), hipMemcpyDeviceToHost, st));
+    SIMM_HIP_TRY(hipStreamSynchronize(st));
+    if (schur_status != 0) {
+        set_error("QR iteration for the Schur form of H_m did not converge");
+        return SIMM_ENOCONV;
+    }
+    s->ritz.resize(me);
+    for (int k = 0; k < me; ++k) {
+        const cplx th = Tp[(size_t)k * (k + 1) / 2 + k];
+        if (th.re == 0.0 && th.im == 0.0) {
+            s->ritz[k] = cplx{NAN, NAN};
+        } else {
+            const cplx inv = cdiv(cplx{1.0, 0.0}, th);
+            s->ritz[k] = cplx{s->sigma.re + inv.re, s->sigma.im + inv.im};
+        }
+    }
+    return SIMM_OK;
+}
+
 // Krylov phase of one shift (hot-path steps a3-a5) on a factored shift: the
 // partitioned-sweep data of the factor (a launch wide enough to fill the device, so
 // it runs here rather than beside other work), b, beta, the Arnoldi basis V_{m+1}
@@ -426,7 +498,6 @@ simm_status krylov_shift(simm_shift_s* s, const cplx* f_dev, int m, hipStream_t 
                          KernelClock* clk = nullptr, const std::atomic<bool>* cancel = nullptr,
                          const std::function<void()>* before_schur = nullptr) {
     simm_pencil_s* p = s->p;
-    const cplx sigma = s->sigma;
     s->m = m;
     const int64_t n = p->n;
     if (cancel && cancel->load()) {
@@ -527,34 +598,7 @@ simm_status krylov_shift(simm_shift_s* s, const cplx* f_dev, int m, hipStream_t 
     s->h_last = cabs(s->H_host[me + (size_t)(me - 1) * (me + 1)]);
     // a5: Schur form of H_m (one wavefront: the caller may start other work beside it)
     if (before_schur) (*before_schur)();
-    SIMM_TRY(dalloc(&s->T, (size_t)me * (me + 1) / 2));
-    SIMM_TRY(dalloc(&s->Q, (size_t)me * me));
-    SIMM_TRY(dalloc(&s->g, (size_t)me));
-    SIMM_TRY(dalloc(&s->qlast, (size_t)me));
-    SchurOut so{s->T, s->Q, s->g, s->qlast};
-    {
-        KScope ks(clk, SIMM_K_SCHUR);
-        SIMM_TRY(hess_schur(s->H, m + 1, me, beta, so, flags + 3, st));
-    }
-    int schur_status = 0;
-    std::vector<cplx> Tp((size_t)me * (me + 1) / 2);
-    SIMM_HIP_TRY(hipMemcpyAsync(&schur_status, flags + 3, sizeof(int), hipMemcpyDeviceToHost, st));
-    SIMM_HIP_TRY(hipMemcpyAsync(Tp.data(), s->T, sizeof(cplx) * Tp.size(), hipMemcpyDeviceToHost, st));
-    SIMM_HIP_TRY(hipStreamSynchronize(st));
-    if (schur_status != 0) {
-        set_error("QR iteration for the Schur form of H_m did not converge");
-        return SIMM_ENOCONV;
-    }
-    s->ritz.resize(me);
-    for (int k = 0; k < me; ++k) {
-        const cplx th = Tp[(size_t)k * (k + 1) / 2 + k];
-        if (th.re == 0.0 && th.im == 0.0) {
-            s->ritz[k] = cplx{NAN, NAN};
-        } else {
-            const cplx inv = cdiv(cplx{1.0, 0.0}, th);
-            s->ritz[k] = cplx{sigma.re + inv.re, sigma.im + inv.im};
-        }
-    }
+    SIMM_TRY(schur_phase(s, m + 1, flags + 3, st, clk));
     return SIMM_OK;
 }
 
@@ -828,6 +872,7 @@ struct AheadBuild {
         if (th.joinable()) th.join();
         if (ms && cnt) clock.collect(ms, cnt);
         if (st) {
+            release_stream_buffers(st);   // nothing allocated in stream order outlives st
             (void)hipStreamSynchronize(st);
             (void)hipStreamDestroy(st);
             st = nullptr;
@@ -1507,6 +1552,16 @@ simm_status gradient(const std::vector<simm_shift_s*>& shifts, const std::vector
     cplx* sums = sumsb.as<cplx>();
     EvalOut eo;
     SIMM_TRY(evaluate(shifts, regs, prm, rule, st, eo, sums, mmax));
+    // the squares' own solves must be resolved (Definition 3.1): an unresolved square's
+    // sums, and so its x_R, are not accurate
+    for (int64_t r = 0; r < N; ++r)
+        if (eo.decision[r] == SIMM_UNRESOLVED) {
+            char msg[200];
+            std::snprintf(msg, sizeof msg, "square %lld is not resolved by its shift: residual %.3g > eps0 = %.3g "
+                          "(raise m)", (long long)r, eo.rho[r], prm->eps0);
+            set_error(msg);
+            return SIMM_EUNRESOLVED;
+        }
     IndicatorParams ip;
     ip.x0 = prm->x0;
     ip.y0 = prm->y0;
@@ -1545,7 +1600,7 @@ simm_status gradient(const std::vector<simm_shift_s*>& shifts, const std::vector
         hipStream_t st = nullptr;
         SpikeFactor sp;
         bool has_sp = false;
-        DevBuf xb, zb, z1b, yb, cwb, kb, pb;
+        DevBuf xb, zb, z1b, yb, cwb, kb, pb, rhob;
         simm_status rc = SIMM_OK;
         std::string msg;
     };
@@ -1560,7 +1615,11 @@ simm_status gradient(const std::vector<simm_shift_s*>& shifts, const std::vector
                 if (x.has_sp) spike_release(x.sp);
             }
             for (auto& x : *w)
-                if (x.st) (void)hipStreamDestroy(x.st);
+                if (x.st) {
+                    release_stream_buffers(x.st);
+                    (void)hipStreamSynchronize(x.st);
+                    (void)hipStreamDestroy(x.st);
+                }
         }
     } stream_release{&wk};
     SIMM_TRY(accb.alloc(sizeof(double) * 2 * W, st));
@@ -1578,6 +1637,7 @@ simm_status gradient(const std::vector<simm_shift_s*>& shifts, const std::vector
         if (grad) SIMM_TRY(x.zb.alloc(sizeof(cplx) * (size_t)n * 128, st));
         SIMM_TRY(x.yb.alloc(sizeof(cplx) * (size_t)2 * nf * LDY, st));
         SIMM_TRY(x.cwb.alloc(sizeof(cplx) * (size_t)nf, st));
+        SIMM_TRY(x.rhob.alloc(sizeof(double) * (size_t)nf, st));
         SIMM_TRY(x.kb.alloc(sizeof(cplx) * (size_t)128 * 128, st));
         SIMM_TRY(x.pb.alloc(sizeof(cplx) * (size_t)grad_part_elems(n), st));
     }
@@ -1648,9 +1708,9 @@ simm_status gradient(const std::vector<simm_shift_s*>& shifts, const std::vector
             cplx* Yf = x.yb.as<cplx>();
             cplx* Ya = Yf + (size_t)nf * LDY;
             SIMM_TRY(fine_solutions(fd, ip, rule.dev, level, regs[4 * r + 1], regs[4 * r + 2], false, Yf, LDY,
-                                    x.cwb.as<cplx>(), x.st));
+                                    x.cwb.as<cplx>(), nullptr, x.st));
             SIMM_TRY(fine_solutions(ad, ip, rule.dev, level, regs[4 * r + 1], regs[4 * r + 2], true, Ya, LDY,
-                                    nullptr, x.st));
+                                    nullptr, x.rhob.as<double>(), x.st));
             SIMM_TRY(grad_kmat(nf, Yf, Ya, LDY, x.cwb.as<cplx>(), mf, ma, x.kb.as<cplx>(), x.st));
             if (grad)
                 SIMM_TRY(project(n, mf, fs->V, n, x.kb.as<cplx>(), mf, ma, x.zb.as<cplx>(), nullptr, nullptr, 0,
@@ -1661,7 +1721,20 @@ simm_status gradient(const std::vector<simm_shift_s*>& shifts, const std::vector
             SIMM_TRY(grad_rowdot(n, ma, kv.V, n, grad ? x.zb.as<cplx>() : nullptr, A1 ? x.z1b.as<cplx>() : nullptr,
                                  n, x.xb.as<cplx>(), grad ? gradsb.as<cplx>() + (int64_t)w * n : nullptr,
                                  x.pb.as<cplx>(), accb.as<double>() + 2 * w, x.st));
+            std::vector<double> rho_adj((size_t)nf);
+            SIMM_HIP_TRY(hipMemcpyAsync(rho_adj.data(), x.rhob.p, sizeof(double) * nf, hipMemcpyDeviceToHost, x.st));
             SIMM_HIP_TRY(hipStreamSynchronize(x.st));   // kv's buffers are freed at scope exit
+            // the adjoint solutions must be resolved in their Krylov space like the forward
+            // ones (Definition 3.1 with eq. (error) at the conjugated nodes)
+            const double rmax = *std::max_element(rho_adj.begin(), rho_adj.end());
+            if (!(rmax <= prm->eps0)) {
+                char msg[200];
+                std::snprintf(msg, sizeof msg,
+                              "adjoint Krylov space of square %lld not resolved: residual %.3g > eps0 = %.3g "
+                              "(raise m)", (long long)r, rmax, prm->eps0);
+                set_error(msg);
+                return SIMM_EUNRESOLVED;
+            }
             return SIMM_OK;
         };
         const int64_t first = next_worker;
@@ -1861,6 +1934,54 @@ simm_status simm_shift_build(simm_pencil p, double sig_re, double sig_im, const 
     SIMM_TRY(to_device_vec(f, f_mem, p->n, fb, &fd, st));
     std::unique_ptr<simm_shift_s> s;
     SIMM_TRY(build_shift(p, cplx{sig_re, sig_im}, fd, m, st, s, nullptr));
+    *out = s.release();
+    return SIMM_OK;
+}
+
+simm_status simm_shift_from_hessenberg(double sig_re, double sig_im, double beta, const double* H, int32_t m_eff,
+                                       void* hip_stream, simm_shift* out) {
+    clear_error();
+    if (!out) return SIMM_EINVAL;
+    *out = nullptr;
+    if (!H || !std::isfinite(sig_re) || !std::isfinite(sig_im) || !std::isfinite(beta) || !(beta > 0.0)) {
+        set_error("bad shift arguments (H NULL, non-finite sigma, or beta not > 0)");
+        return SIMM_EINVAL;
+    }
+    if (m_eff < 1) {
+        set_error("need m_eff >= 1");
+        return SIMM_EINVAL;
+    }
+    if (m_eff > 128) {
+        set_error("Krylov dimension above 128 is not supported");
+        return SIMM_EUNSUPPORTED;
+    }
+    const int64_t cnt = (int64_t)(m_eff + 1) * m_eff;
+    if (!finite_c(H, 2 * cnt)) {
+        set_error("H has NaN/Inf entries");
+        return SIMM_EINVAL;
+    }
+    const cplx* Hc = reinterpret_cast<const cplx*>(H);
+    for (int j = 0; j < m_eff; ++j)
+        for (int i = j + 2; i <= m_eff; ++i)
+            if (Hc[i + (int64_t)j * (m_eff + 1)].re != 0.0 || Hc[i + (int64_t)j * (m_eff + 1)].im != 0.0) {
+                set_error("H is not upper Hessenberg");
+                return SIMM_EINVAL;
+            }
+    SIMM_TRY(check_device());
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    auto s = std::make_unique<simm_shift_s>();
+    s->sigma = cplx{sig_re, sig_im};
+    s->m = s->m_eff = m_eff;
+    s->beta = beta;
+    s->factor_borrowed = true;   // no factor, sweep data or basis to free
+    s->H_host.assign(Hc, Hc + cnt);
+    s->h_last = cabs(s->H_host[m_eff + (size_t)(m_eff - 1) * (m_eff + 1)]);
+    SIMM_TRY(dalloc(&s->H, (size_t)cnt));
+    SIMM_HIP_TRY(hipMemcpyAsync(s->H, Hc, sizeof(cplx) * cnt, hipMemcpyHostToDevice, st));
+    DevBuf status;
+    SIMM_TRY(status.alloc(sizeof(int), st));
+    SIMM_HIP_TRY(hipMemsetAsync(status.p, 0, sizeof(int), st));
+    SIMM_TRY(schur_phase(s.get(), m_eff + 1, status.as<int>(), st));
     *out = s.release();
     return SIMM_OK;
 }
@@ -2186,7 +2307,11 @@ simm_status simm_run_batch(const simm_pencil* pencils, const simm_params* params
             if (rc[(size_t)i] == SIMM_OK) out[i] = r;
             else msg[(size_t)i] = simm_last_error();
         }
-        if (se == hipSuccess) (void)hipStreamDestroy(st);
+        if (se == hipSuccess) {
+            release_stream_buffers(st);
+            (void)hipStreamSynchronize(st);
+            (void)hipStreamDestroy(st);
+        }
     };
     std::vector<std::thread> pool;
     const int32_t nw = std::min(workers, std::max<int32_t>(count, 1));

@@ -236,7 +236,8 @@ __global__ __launch_bounds__(IND_THREADS) void k_indicators(const ShiftDev* __re
 // given, receives c_j = w_j / (2 pi i).  Workgroup b's wave w takes point 4 b + w.
 __global__ __launch_bounds__(IND_THREADS) void k_fine_solutions(ShiftDev sh, IndicatorParams prm, RuleDev rule,
                                                                 int level, int64_t ix, int64_t iy, int conj_nodes,
-                                                                cplx* __restrict__ Y, int ldy, cplx* __restrict__ cw) {
+                                                                cplx* __restrict__ Y, int ldy, cplx* __restrict__ cw,
+                                                                double* __restrict__ rho) {
     extern __shared__ cplx smem[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = sh.m;
@@ -292,11 +293,16 @@ __global__ __launch_bounds__(IND_THREADS) void k_fine_solutions(ShiftDev sh, Ind
         if (i0 < m) Y[(int64_t)q * ldy + i0] = y0;
         if (i1 < m) Y[(int64_t)q * ldy + i1] = y1;
         if (cw != nullptr && lane == 0) cw[q] = mk(wq.im / twopi, -wq.re / twopi);
+        if (rho != nullptr) {
+            // residual of this node's reduced solve, eq. (error): |sigma - z| h_{m+1,m} |e_m^T y| / beta
+            const cplx ym = (m - 1 < 64) ? readlane_c(y0, (m - 1) & 63) : readlane_c(y1, (m - 1) & 63);
+            if (lane == 0) rho[q] = cabs(alpha) * sh.h_last * cabs(ym) / sh.beta;
+        }
     }
 }
 
 simm_status fine_solutions(const ShiftDev& sh, const IndicatorParams& prm, const RuleDev& rule, int level, int64_t ix,
-                           int64_t iy, bool conj_nodes, cplx* Y, int ldy, cplx* cw, hipStream_t st) {
+                           int64_t iy, bool conj_nodes, cplx* Y, int ldy, cplx* cw, double* rho, hipStream_t st) {
     if (sh.m > 128 || ldy < sh.m) {
         set_error("fine_solutions: Krylov dimension above 128 or row stride below it");
         return SIMM_EUNSUPPORTED;
@@ -304,7 +310,7 @@ simm_status fine_solutions(const ShiftDev& sh, const IndicatorParams& prm, const
     const size_t lds = sizeof(cplx) * (size_t)(sh.m * (sh.m + 1) / 2 + 1);
     const int nf = 8 * rule.g;
     hipLaunchKernelGGL(k_fine_solutions, dim3((unsigned)((nf + IND_WAVES - 1) / IND_WAVES)), dim3(IND_THREADS), lds,
-                       st, sh, prm, rule, level, ix, iy, conj_nodes ? 1 : 0, Y, ldy, cw);
+                       st, sh, prm, rule, level, ix, iy, conj_nodes ? 1 : 0, Y, ldy, cw, rho);
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;
 }

@@ -165,9 +165,10 @@ simm_status gram(int64_t n, int k, int64_t ncl, const cplx* X, cplx* G, hipStrea
 std::vector<double> hermitian_eigenvalues(int k, const cplx* G);
 
 // fine-rule solutions y_j = Q yhat_j of one square, one row of Y per node (ldy >= m);
-// conj_nodes: conjugated nodes (a shift of the conjugate-transposed pencil); cw: c_j
+// conj_nodes: conjugated nodes (a shift of the conjugate-transposed pencil); cw: c_j;
+// rho (may be null): the residual of each node's reduced solve (8 g values)
 simm_status fine_solutions(const ShiftDev& sh, const IndicatorParams& prm, const RuleDev& rule, int level, int64_t ix,
-                           int64_t iy, bool conj_nodes, cplx* Y, int ldy, cplx* cw, hipStream_t st);
+                           int64_t iy, bool conj_nodes, cplx* Y, int ldy, cplx* cw, double* rho, hipStream_t st);
 
 // ---- adjoint gradient (gradient.hip) ----
 simm_status conj_transpose_band(int64_t n, int kl, int ku, const cplx* in, cplx* out, hipStream_t st);

@@ -30,7 +30,8 @@ KERNEL_NAMES = ["band_lu", "band_sweep", "gram_schmidt", "schur", "indicators", 
 REJECTED, ADMISSIBLE, UNRESOLVED = 0, 1, 2
 
 STATUS_NAMES = {0: "SIMM_OK", -1: "SIMM_EINVAL", -2: "SIMM_ENODEV", -3: "SIMM_ENOMEM", -4: "SIMM_EHIP",
-                -5: "SIMM_ESINGULAR_SHIFT", -6: "SIMM_ENOCONV", -7: "SIMM_ELIMIT", -8: "SIMM_EUNSUPPORTED"}
+                -5: "SIMM_ESINGULAR_SHIFT", -6: "SIMM_ENOCONV", -7: "SIMM_ELIMIT", -8: "SIMM_EUNSUPPORTED",
+                -9: "SIMM_EREFINE", -10: "SIMM_EUNRESOLVED"}
 
 
 class SimmError(RuntimeError):
@@ -71,6 +72,7 @@ EXPORTS = {
     "simm_pencil_info": (C.c_int, [_vp, C.POINTER(_i64), C.POINTER(_i32), C.POINTER(_i32)]),
     "simm_pencil_destroy": (None, [_vp]),
     "simm_shift_build": (C.c_int, [_vp, _d, _d, _vp, _i32, _i32, _vp, C.POINTER(_vp)]),
+    "simm_shift_from_hessenberg": (C.c_int, [_d, _d, _d, _vp, _i32, _vp, C.POINTER(_vp)]),
     "simm_shift_info": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "simm_shift_basis": (C.c_int, [_vp, _vp, _i32, _vp]),
     "simm_shift_apply": (C.c_int, [_vp, _vp, _vp, _i32, _vp]),
@@ -236,6 +238,19 @@ def simm_shift_build(pencil: Pencil, sigma: complex, f, m: int, stream=None) -> 
                                  _stream(stream), C.byref(h)))
     s = Shift(h)
     s._n = pencil.n
+    return s
+
+
+def simm_shift_from_hessenberg(sigma: complex, beta: float, H, stream=None) -> Shift:
+    """A shift from (sigma, beta, H_{m+1,m}) alone: H is an (m+1) x m complex array."""
+    H = np.asfortranarray(H, dtype=np.complex128)
+    m = H.shape[1]
+    assert H.shape[0] == m + 1, "H must be (m + 1) x m"
+    h = _vp()
+    _check(_lib.simm_shift_from_hessenberg(float(np.real(sigma)), float(np.imag(sigma)), float(beta), H.ctypes.data,
+                                           m, _stream(stream), C.byref(h)))
+    s = Shift(h)
+    s._n = 0
     return s
 
 

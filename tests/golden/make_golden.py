@@ -2,7 +2,12 @@
 oracle (oracle/simm.py) on the seeded workloads; nothing here comes from the
 HIP library.  Usage: python tests/golden/make_golden.py cfg0 [cfg1 cfg2_small ...]
 (batch workloads are stored compactly: decisions and keys per level, and the
-margins of the squares closer than 1e-6 to a decision threshold)."""
+margins of the squares closer than 1e-6 to a decision threshold).
+
+  python tests/golden/make_golden.py --hessenberg cfg0 cfg1
+rebuilds, with the oracle, every shift of a stored run (the sigmas of
+<name>_oracle.json) and stores sigma, beta and the full H_{m+1,m} of each in
+<name>_hessenberg.npz (numpy arrays, no pickled objects)."""
 import json
 import os
 import sys
@@ -51,6 +56,27 @@ def compact_trace(res):
     }
 
 
+def hessenberg(names):
+    for name in names:
+        t0 = time.time()
+        pen, f, params = make_workload(name)
+        with open(os.path.join(HERE, f"{name}_oracle.json")) as fh:
+            run = json.load(fh)
+        m = params["m"]
+        sig, beta, meff = [], [], []
+        H = np.zeros((len(run["shifts"]), m + 1, m), dtype=np.complex128)
+        for i, rec in enumerate(run["shifts"]):
+            sh = O.build_shift(pen, complex(*rec["sigma"]), f, m, keep_V=False)
+            assert sh.m_eff == rec["m_eff"] and abs(sh.beta - rec["beta"]) <= 1e-14 * rec["beta"], (name, i)
+            sig.append(sh.sigma)
+            beta.append(sh.beta)
+            meff.append(sh.m_eff)
+            H[i, : sh.m_eff + 1, : sh.m_eff] = sh.H
+        path = os.path.join(HERE, f"{name}_hessenberg.npz")
+        np.savez_compressed(path, sigma=np.array(sig), beta=np.array(beta), m_eff=np.array(meff, dtype=np.int64), H=H)
+        print(name, "->", path, f"{time.time() - t0:.1f} s, {len(sig)} shifts")
+
+
 def main(names):
     for name in names:
         t0 = time.time()
@@ -76,4 +102,7 @@ def main(names):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["cfg0"])
+    if sys.argv[1:2] == ["--hessenberg"]:
+        hessenberg(sys.argv[2:])
+    else:
+        main(sys.argv[1:] or ["cfg0"])

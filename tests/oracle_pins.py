@@ -466,3 +466,65 @@ def check_p17_gradient(O, h=1e-6):
         fi = (O.projected_norms(A + 1j * h * E, B, f, squares, g)[0]
               - O.projected_norms(A - 1j * h * E, B, f, squares, g)[0]) / (2 * h)
         assert abs(gd[i] - (fr + 1j * fi)) <= 1e-6 * scale, (i, gd[i], fr + 1j * fi)
+
+
+# P18 -- the decision margin: the log-distance of the three threshold tests
+# (resolvable: rho_max <= eps0; admissible: ||s_f|| > tau T_f and
+# ||s_f|| > delta0 ||s_c||; Definitions 3.1-3.2 with the tau floor) from their
+# thresholds.  Constructed inputs put each test nearest in turn, on either side
+# of its threshold, with distances known in closed form (ln 2, ln 3, ...); a
+# zero or infinite quantity takes its test out.  The margin is then tied to its
+# meaning: scaling the compared quantities by less than e^margin toward every
+# threshold keeps all three outcomes, scaling the nearest one by more flips it.
+MARGIN_PARAMS = dict(delta0=0.05, eps0=1e-8, tau=1e-8)
+MARGIN_CASES = [
+    # (nsf, nsc, Tf, rho_max, expected margin)
+    (1.0, 10.0, 1.0, 1e-10, math.log(2.0)),      # nsf / (delta0 nsc) = 2
+    (3e-8, 1e-9, 1.0, 1e-12, math.log(3.0)),     # nsf / (tau Tf) = 3; ratio test at ln 600
+    (1.0, 1.0, 1.0, 2.5e-9, math.log(4.0)),      # rho / eps0 = 1/4; ratio test at ln 20
+    (1.0, 160.0, 1.0, 1e-14, math.log(8.0)),     # nsf / (delta0 nsc) = 1/8
+    (1.0, 0.0, 1.0, 1e-9, math.log(10.0)),       # nsc = 0: ratio test out
+    (1.0, 1.0, 0.0, 0.0, math.log(20.0)),        # Tf = 0 and rho = 0: those tests out
+    (0.0, 1.0, 1.0, 0.0, math.inf),              # nothing left to compare
+]
+
+
+def _outcomes(nsf, nsc, Tf, rho, p):
+    return (rho <= p["eps0"], nsf > p["tau"] * Tf, nsf > p["delta0"] * nsc)
+
+
+def check_p18_decision_margin(O):
+    p = MARGIN_PARAMS
+    for nsf, nsc, Tf, rho, want in MARGIN_CASES:
+        got = O.decision_margin(nsf, nsc, Tf, rho, p)
+        if math.isinf(want):
+            assert math.isinf(got), (nsf, nsc, Tf, rho, got)
+        else:
+            assert abs(got - want) <= 1e-14 * want, (nsf, nsc, Tf, rho, got, want)
+        # scale invariance: the three tests compare ratios
+        g7 = O.decision_margin(7.0 * nsf, 7.0 * nsc, 7.0 * Tf, rho, p)
+        assert (math.isinf(g7) and math.isinf(got)) or abs(g7 - got) <= 1e-14 * got, (g7, got)
+    rng = np.random.default_rng(18)
+    for _ in range(200):
+        nsf, nsc, Tf = 10.0 ** rng.uniform(-12, 2, 3)
+        rho = 10.0 ** rng.uniform(-12, -4)
+        mg = O.decision_margin(nsf, nsc, Tf, rho, p)
+        base = _outcomes(nsf, nsc, Tf, rho, p)
+        # every quantity moved toward its threshold by 0.99 margin: no outcome changes
+        s = math.exp(0.99 * mg)
+        toward = (nsf / s if base[1] else nsf * s, nsc, Tf, rho * s if base[0] else rho / s)
+        assert _outcomes(*toward, p)[:2] == base[:2], (nsf, nsc, Tf, rho, mg)
+        toward_ratio = (nsf / s if base[2] else nsf * s, nsc, Tf, rho)
+        assert _outcomes(*toward_ratio, p)[2] == base[2], (nsf, nsc, Tf, rho, mg)
+        # the nearest test moved by 1.01 margin flips
+        S = math.exp(1.01 * mg)
+        d_rho = abs(math.log(rho / p["eps0"]))
+        d_tau = abs(math.log(nsf / (p["tau"] * Tf)))
+        d_rat = abs(math.log(nsf / (p["delta0"] * nsc)))
+        if d_rho <= min(d_tau, d_rat):
+            flipped = _outcomes(nsf, nsc, Tf, rho * S if base[0] else rho / S, p)[0] != base[0]
+        elif d_tau <= d_rat:
+            flipped = _outcomes(nsf, nsc, Tf * S if base[1] else Tf / S, rho, p)[1] != base[1]
+        else:
+            flipped = _outcomes(nsf, nsc * S if base[2] else nsc / S, Tf, rho, p)[2] != base[2]
+        assert flipped, (nsf, nsc, Tf, rho, mg)

@@ -232,6 +232,151 @@ def test_indicators_match_oracle(S):
     say("  decision ties:", mism)
 
 
+def _oracle_eval_with_scales(o, center, width, params):
+    """The oracle's evaluation of one square, the magnitude sums T_c, T_f of its two
+    rules ((1/2 pi) sum_j |w_j| ||y_j||: a sum whose terms each carry a relative error
+    e is off by at most e times this), and the rounding level of its residual: rho_j
+    takes |e_m^T y_j|, whose rounding error is about m u ||y_j|| whatever its size, so
+    rho_max is compared down to m u max_j |sigma - z_j| h_{m+1,m} ||y_j|| / beta."""
+    ev = O.evaluate_square(o, center, width, params)
+    u = np.finfo(np.float64).eps / 2
+    g = params["gauss_per_edge"]
+    floor = 0.0
+    T = []
+    for rule in (g, 2 * g):
+        z, w = O.edge_rule(center, width, rule)
+        Y = O.shifted_solutions(o, z)
+        ny = np.linalg.norm(Y, axis=1)
+        T.append(float(np.sum(np.abs(w) * ny) / (2 * np.pi)))
+        floor = max(floor, float(np.max(np.abs(o.sigma - z) * o.h_last * ny / o.beta)))
+    return ev, T[0], T[1], o.m_eff * u * floor
+
+
+def _solve_error_bound(o, center, width, params):
+    """Forward-error bound of a backward-stable solve of every quadrature point's
+    system G_j y = beta e_1, G_j = I + (sigma - z_j) H_m, relative to ||y_j||:
+    8 m u max_j kappa_1(G_j).  Two such solvers (the oracle's LU, the library's Schur
+    form) may differ by this much.  Near an eigenvalue (deep levels, z_j within h0 of
+    it) kappa reaches |lambda - sigma| / |z_j - lambda|, about 1e6."""
+    u = np.finfo(np.float64).eps / 2
+    m = o.m_eff
+    kap = 0.0
+    for rule in (params["gauss_per_edge"], 2 * params["gauss_per_edge"]):
+        z, _ = O.edge_rule(center, width, rule)
+        G = np.eye(m)[None] + (o.sigma - z)[:, None, None] * o.Hm[None]
+        kap = max(kap, float(np.max(np.linalg.norm(G, 1, axis=(1, 2)) *
+                                    np.linalg.norm(np.linalg.inv(G), 1, axis=(1, 2)))))
+    return 8 * m * u * kap
+
+
+def _check_indicators_on_oracle_H(S, name, regs, params, oracle_shifts, rel=1e-12):
+    """Every square's sums within rel times its magnitude sums (each point's solution
+    to rel), T_f and rho_max within rel relative (rho_max down to its rounding level),
+    decisions identical up to ties (oracle margin < 1e-8).  Where a square's systems are
+    ill-conditioned the bar is the two solvers' forward-error bound instead, if larger."""
+    gpu_shifts = [S.simm_shift_from_hessenberg(o.sigma, o.beta, o.H) for o in oracle_shifts]
+    prm = S.params_from_dict(params)
+    out = S.simm_indicators(gpu_shifts, regs, prm, want_sums=True)
+    ties = 0
+    worst = dict(s_c=0.0, s_f=0.0, nsc=0.0, nsf=0.0, Tf=0.0, rho=0.0, nsf_rel=0.0)
+    n_cond = 0
+    worst_over_bound = 0.0
+    bad = []
+    for r, (k, ix, iy, si) in enumerate(regs):
+        o = oracle_shifts[int(si)]
+        c = O.square_center(params, int(k), int(ix), int(iy))
+        w = O.square_width(params, int(k))
+        ev, Tc, Tf, rho_floor = _oracle_eval_with_scales(o, c, w, params)
+        me = o.m_eff
+        errs = dict(s_c=float(np.linalg.norm(out["sums"][r, 0, :me] - ev.s_c)) / Tc,
+                    s_f=float(np.linalg.norm(out["sums"][r, 1, :me] - ev.s_f)) / Tf,
+                    nsc=abs(out["nsc"][r] - ev.nsc) / Tc,
+                    nsf=abs(out["nsf"][r] - ev.nsf) / Tf,
+                    Tf=abs(out["Tf"][r] - ev.Tf) / ev.Tf,
+                    rho=abs(out["rho_max"][r] - ev.rho_max) / max(ev.rho_max, rho_floor / rel, 1e-300))
+        for key, v in errs.items():
+            worst[key] = max(worst[key], v)
+        if max(errs.values()) > rel:
+            bound = _solve_error_bound(o, c, w, params)
+            n_cond += 1
+            worst_over_bound = max(worst_over_bound, max(errs.values()) / bound)
+            for key, v in errs.items():
+                if not v <= max(rel, bound):
+                    bad.append((r, key, v, bound))
+        if ev.nsf > 1e-6 * Tf:     # sums well above the quadrature noise: plain relative error
+            worst["nsf_rel"] = max(worst["nsf_rel"], abs(out["nsf"][r] - ev.nsf) / ev.nsf)
+        dec = 2 if not ev.resolvable else (1 if ev.admissible else 0)
+        if out["decision"][r] != dec:
+            ties += 1
+            if not ev.margin < 1e-8:
+                bad.append((r, "decision", (int(out["decision"][r]), dec, ev.margin)))
+    say(f"  {name}: {len(regs)} squares, decision ties {ties}; max errors (sums and norms relative to the "
+        f"magnitude sums): " + ", ".join(f"{k} {v:.2e}" for k, v in worst.items()) +
+        f"; {n_cond} squares above {rel:g}, at most {worst_over_bound:.2e} of their conditioning bound")
+    assert not bad, bad[:10]
+
+
+def _golden_shifts(name):
+    d = np.load(os.path.join(GOLDEN, f"{name}_hessenberg.npz"), allow_pickle=False)
+    out = []
+    for sig, beta, me, H in zip(d["sigma"], d["beta"], d["m_eff"], d["H"]):
+        me = int(me)
+        out.append(O.Shift(complex(sig), float(beta), H[: me + 1, :me].copy(), me, None))
+    return out
+
+
+def test_indicators_on_oracle_hessenberg_cfg0(S):
+    """The indicator kernel alone (a6-a8) on the oracle's own (sigma, beta, H) of every
+    shift of the n = 400 run: 200 squares drawn from the squares the oracle tested,
+    each with the shift it was tested with."""
+    pen, f, params = make_workload("cfg0")
+    with open(os.path.join(GOLDEN, "cfg0_oracle.json")) as fh:
+        run = json.load(fh)
+    rows = [(L["level"], ix, iy, s) for L in run["levels"] for ix, iy, s in zip(L["ix"], L["iy"], L["shift"])]
+    rng = np.random.default_rng(200)
+    pick = rng.choice(len(rows), size=200, replace=False)
+    regs = np.array([rows[i] for i in sorted(pick)], np.int64)
+    say("indicators on the oracle's H", "cfg0", f"{len(regs)} squares, levels {regs[:, 0].min()}..{regs[:, 0].max()}")
+    _check_indicators_on_oracle_H(S, "cfg0", regs, params, _golden_shifts("cfg0"))
+
+
+def test_indicators_on_oracle_hessenberg_cfg1(S):
+    """The same on the 7 shifts of the n = 40,000 run and every square of its 4 levels."""
+    pen, f, params = make_workload("cfg1")
+    with open(os.path.join(GOLDEN, "cfg1_oracle.json")) as fh:
+        run = json.load(fh)
+    regs = np.array([(L["level"], ix, iy, s) for L in run["levels"] for ix, iy, s in zip(L["ix"], L["iy"], L["shift"])],
+                    np.int64)
+    say("indicators on the oracle's H", "cfg1", f"{len(regs)} squares")
+    _check_indicators_on_oracle_H(S, "cfg1", regs, params, _golden_shifts("cfg1"))
+
+
+def test_shift_from_hessenberg_errors(S):
+    say("shift_from_hessenberg", "argument errors")
+    H = np.zeros((4, 3), np.complex128)
+    H[0, 0] = H[1, 0] = H[1, 1] = H[2, 1] = H[2, 2] = H[3, 2] = 1.0
+    with pytest.raises(S.SimmError) as e:
+        S.simm_shift_from_hessenberg(0.0, -1.0, H)          # beta <= 0
+    assert e.value.status == -1
+    Hb = H.copy()
+    Hb[3, 0] = 0.5                                          # below the subdiagonal
+    with pytest.raises(S.SimmError) as e:
+        S.simm_shift_from_hessenberg(0.0, 1.0, Hb)
+    assert e.value.status == -1
+    Hn = H.copy()
+    Hn[0, 1] = np.nan
+    with pytest.raises(S.SimmError) as e:
+        S.simm_shift_from_hessenberg(0.0, 1.0, Hn)
+    assert e.value.status == -1
+    sh = S.simm_shift_from_hessenberg(0.1, 2.0, H)
+    inf = sh.info()
+    assert inf["m_eff"] == 3 and inf["beta"] == 2.0 and np.array_equal(inf["H"], H)
+    y = np.zeros(3, np.complex128)
+    with pytest.raises(S.SimmError) as e:                  # no factor behind it
+        sh.apply(np.ones(3, np.complex128), y)
+    assert e.value.status == -1
+
+
 # Error bounds of the reduced-precision projections, relative to ||V Y||_F.  Inputs are
 # rounded to the format (unit roundoff u: FP32 2^-24, BF16 2^-8) and the 2m real products
 # of an entry are accumulated in FP32; with random signs the error of an entry is about
@@ -685,3 +830,43 @@ def test_gradient_errors(S):
         S.simm_gradient([sh], np.array([[1, 1, 1, 1]]), params)          # shift index out of range
     J, dp, gd = S.simm_gradient([sh], np.zeros((0, 4), dtype=np.int64), params)
     assert J == 0.0 and dp is None and np.all(gd == 0)
+
+
+def test_gradient_unresolved_squares_are_errors(S):
+    """simm_gradient refuses squares whose reduced solves are not resolved (Definition
+    3.1 with eq. (error)): with m = 6 the forward spaces of the n = 300 problem are too
+    small; and with f in a 2-dimensional invariant subspace of an upper triangular A the
+    forward space is exact (breakdown at 2, residual 0) while the adjoint space of A^H,
+    started from x_R, is not."""
+    pen, f, a1, A1, regions, squares, sigmas, prm = _grad_problem(300, 11, 3, 2)
+    say("gradient", "unresolved forward squares (m = 6)")
+    P = S.Pencil.from_workload(pen)
+    shifts = [S.simm_shift_build(P, s, f, 6) for s in sigmas]
+    params = S.params_from_dict(prm, m=6)
+    with pytest.raises(S.SimmError) as e:
+        S.simm_gradient(shifts, regions, params, a1, 1, 1)
+    assert e.value.status == -10 and "not resolved by its shift" in str(e.value)
+    # upper triangular A (band kl = 1 with a zero subdiagonal, ku = 2), B = I
+    n = 60
+    rng = np.random.default_rng(61)
+    band = np.zeros((4, n), dtype=np.complex128, order="F")
+    band[2, :] = np.linspace(-3.0, 3.0, n) + 0.5j                   # diagonal (row ku = 2)
+    band[1, 1:] = 0.7 * (rng.standard_normal(n - 1) + 1j * rng.standard_normal(n - 1))
+    band[0, 2:] = 0.7 * (rng.standard_normal(n - 2) + 1j * rng.standard_normal(n - 2))
+    tri = WPencil(n, 1, 2, band, 0, 0, None)
+    f2 = np.zeros(n, np.complex128)
+    f2[0], f2[1] = 1.0, 0.5
+    lam0 = complex(band[2, 0])                                        # eigenvalue -3 + 0.5i
+    say("gradient", "exact forward space, unresolved adjoint space")
+    P2 = S.Pencil.from_workload(tri)
+    w = 0.25
+    x0 = -3.1
+    p2 = dict(x0=x0, y0=0.4, x1=x0 + w, n1=1, gauss_per_edge=8)
+    sh = S.simm_shift_build(P2, lam0 + 0.03 + 0.02j, f2, 4)
+    assert sh.info()["m_eff"] == 2
+    reg = np.array([[1, 0, 0, 0]], dtype=np.int64)
+    J, _, _ = S.simm_gradient([sh], reg, S.params_from_dict(p2, m=4), want_diag=False, want_dp=False)
+    assert J > 0.0                                                    # the square holds the eigenvalue
+    with pytest.raises(S.SimmError) as e:
+        S.simm_gradient([sh], reg, S.params_from_dict(p2, m=4), want_diag=True, want_dp=False)
+    assert e.value.status == -10 and "adjoint" in str(e.value)

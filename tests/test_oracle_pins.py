@@ -332,3 +332,32 @@ def test_planted_mistake_is_caught(name):
         except (AssertionError, np.linalg.LinAlgError, ValueError, ZeroDivisionError, FloatingPointError):
             failures += 1
     assert failures >= 1, f"planted mistake '{name}' passed every pin"
+
+
+def test_p18_decision_margin():
+    P.check_p18_decision_margin(O)
+
+
+def _margin_no_tau(nsf, nsc, Tf, rho_max, params):
+    # the tau-floor test left out of the margin
+    def lg(a, b):
+        return abs(np.log(a / b)) if a > 0 and b > 0 and np.isfinite(a) and np.isfinite(b) else np.inf
+    return min(lg(nsf, params["delta0"] * nsc), lg(rho_max, params["eps0"]))
+
+
+def _margin_log10(nsf, nsc, Tf, rho_max, params):
+    # decimal instead of natural logarithms
+    return O.decision_margin(nsf, nsc, Tf, rho_max, params) / np.log(10.0)
+
+
+MARGIN_MUTANTS = {
+    "tau floor left out": dict(decision_margin=_margin_no_tau),
+    "log10": dict(decision_margin=_margin_log10),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MARGIN_MUTANTS))
+def test_planted_margin_mistake_is_caught(name):
+    mod = _mutant(**MARGIN_MUTANTS[name])
+    with pytest.raises(AssertionError):
+        P.check_p18_decision_margin(mod)

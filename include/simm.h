@@ -253,6 +253,18 @@ simm_status simm_gradient(const simm_shift* shifts, int32_t n_shifts, const int6
 simm_status simm_project(simm_shift s, const double* Y, int64_t c, double* X, double* col_norms,
                          int32_t precision, void* hip_stream);
 
+/* simm_project without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments and results as simm_project, but the call only enqueues its kernels
+ * on hip_stream and returns (no synchronisation).  The column-norm partial sums go to
+ * a scratch array that the library holds in device memory (one per device, 16 MiB, kept
+ * until the process ends): col_norms needs 8 (2 ceil(n/128) + 32) c bytes of it, and
+ * a larger request returns EUNSUPPORTED.  Every call on a device shares that array, so
+ * calls that overlap on one device (other streams, before the previous call's kernels
+ * have finished) race; calls on one stream are ordered.  X alone needs no scratch. */
+simm_status simm_project_noalloc(simm_shift s, const double* Y, int64_t c, double* X, double* col_norms,
+                                 int32_t precision, void* hip_stream);
+
 /* ------------------------------------------------------------------------ */
 /* Whole method: SIM-M steps 1-7 (Sec. 3.5).                                 */
 /* ------------------------------------------------------------------------ */

@@ -1778,6 +1778,36 @@ simm_status gradient(const std::vector<simm_shift_s*>& shifts, const std::vector
 // ---------------------------------------------------------------------------
 // exported C ABI
 // ---------------------------------------------------------------------------
+// Scratch of simm_project_noalloc: the per-64-row partial column norms and their
+// group sums, for callers that cannot allocate device memory.  Each device holds its
+// own copy of this array for the life of the process; its device address is looked
+// up once per device (in host code the array's name is not a device address) and
+// kept.  Calls that overlap on one device share it.
+namespace {
+constexpr int64_t kNoAllocScratchDoubles = (int64_t)2 << 20;   // 16 MiB
+__device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_addr;
+
+simm_status noalloc_scratch(double** out) {
+    int dev = 0;
+    SIMM_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(dev);
+    if (it == g_scratch_addr.end()) {
+        double* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr) {
+            set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+            return SIMM_EHIP;
+        }
+        it = g_scratch_addr.emplace(dev, ptr).first;
+    }
+    *out = it->second;
+    return SIMM_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char* simm_last_error(void) { return g_err.c_str(); }
@@ -2233,6 +2263,41 @@ simm_status simm_project(simm_shift s, const double* Y, int64_t c, double* X, do
                      reinterpret_cast<cplx*>(X), col_norms, col_norms ? scr.as<double>() : nullptr, se, precision, st));
     SIMM_HIP_TRY(hipStreamSynchronize(st));
     return SIMM_OK;
+}
+
+simm_status simm_project_noalloc(simm_shift s, const double* Y, int64_t c, double* X, double* col_norms,
+                                 int32_t precision, void* hip_stream) {
+    clear_error();
+    if (!s || c < 0 || (c > 0 && (!Y || (!X && !col_norms)))) {
+        set_error("bad projection arguments");
+        return SIMM_EINVAL;
+    }
+    if (precision != SIMM_PROJ_FP64 && precision != SIMM_PROJ_FP32 && precision != SIMM_PROJ_BF16) {
+        set_error("unknown projection precision");
+        return SIMM_EINVAL;
+    }
+    if (!s->has_factor()) {
+        set_error("the shift's Krylov basis was released (SIMM_FLAG_RELEASE_FACTORS)");
+        return SIMM_EINVAL;
+    }
+    if (c == 0) return SIMM_OK;
+    const int64_t se = project_scratch_elems(s->p->n, c);
+    double* scr = nullptr;
+    if (col_norms) {
+        if (se > kNoAllocScratchDoubles) {
+            char msg[200];
+            std::snprintf(msg, sizeof msg,
+                          "simm_project_noalloc: the column norms of n = %lld, c = %lld need %lld doubles of scratch, "
+                          "more than the %lld the library holds",
+                          (long long)s->p->n, (long long)c, (long long)se, (long long)kNoAllocScratchDoubles);
+            set_error(msg);
+            return SIMM_EUNSUPPORTED;
+        }
+        SIMM_TRY(noalloc_scratch(&scr));
+    }
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    return project(s->p->n, s->m_eff, s->V, s->p->n, reinterpret_cast<const cplx*>(Y), s->m_eff, c,
+                   reinterpret_cast<cplx*>(X), col_norms, scr, se, precision, st);
 }
 
 simm_status simm_run(simm_pencil p, const simm_params* params, const double* f, int32_t f_mem, void* hip_stream,

@@ -80,6 +80,7 @@ EXPORTS = {
     "simm_indicators": (C.c_int, [_vp, _i32, _vp, _i64, C.POINTER(simm_params), _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                   _i32, _i32, _vp]),
     "simm_project": (C.c_int, [_vp, _vp, _i64, _vp, _vp, _i32, _vp]),
+    "simm_project_noalloc": (C.c_int, [_vp, _vp, _i64, _vp, _vp, _i32, _vp]),
     "simm_gradient": (C.c_int, [_vp, _i32, _vp, _i64, C.POINTER(simm_params), _i32, _i32, _vp, _vp, _vp, _vp, _i32,
                                 _vp]),
     "simm_run": (C.c_int, [_vp, C.POINTER(simm_params), _vp, _i32, _vp, C.POINTER(_vp)]),
@@ -286,6 +287,17 @@ def simm_project(shift: Shift, Y, X, col_norms=None, precision: int = SIMM_PROJ_
     pn, _ = _ptr(col_norms)
     c = Y.shape[1]
     _check(_lib.simm_project(shift.handle, py, c, px, pn, int(precision), _stream(stream)))
+    return X
+
+
+def simm_project_noalloc(shift: Shift, Y, X, col_norms=None, precision: int = SIMM_PROJ_FP64, stream=None):
+    """simm_project_noalloc: the arguments of simm_project; the call only enqueues its
+    kernels (no device allocation, no synchronisation)."""
+    py, _ = _ptr(Y)
+    px, _ = _ptr(X)
+    pn, _ = _ptr(col_norms)
+    c = Y.shape[1]
+    _check(_lib.simm_project_noalloc(shift.handle, py, c, px, pn, int(precision), _stream(stream)))
     return X
 
 

@@ -67,6 +67,18 @@ enum {
                                       (simm_result_full_indicators) changes                       */
 };
 
+/* Arithmetic of the shift factors (simm_params.precision, simm_shift_build). */
+enum {
+    SIMM_PREC_FP64 = 0,            /* band LU and its solves in FP64                               */
+    SIMM_PREC_MIXED = 1            /* band LU factored and stored in FP32; every solve with it is
+                                      refined against the FP64 pencil until its normwise backward
+                                      error ||u - (A - sigma B) x||_inf / (||A - sigma B||_inf
+                                      ||x||_inf + ||u||_inf) is at most 1e-12 (at most 8
+                                      corrections; SIMM_EREFINE otherwise).  Arnoldi, the Schur
+                                      form, the shifted solves, sums and decisions stay FP64; a
+                                      run projects in BF16 at levels 1-2 and FP32 after          */
+};
+
 /* Arithmetic of simm_project. */
 enum {
     SIMM_PROJ_FP64 = 0,            /* FP64 matrix cores                                            */
@@ -140,6 +152,9 @@ typedef struct {
                                    one less than GPU_MAX_HW_QUEUES (4 unless set), at most 11;
                                    1: one at a time; at most 16).  Only the shifts the cell order
                                    creates are kept, so results do not depend on it              */
+    int32_t precision;          /* SIMM_PREC_FP64 (default) or SIMM_PREC_MIXED.  With MIXED a shift
+                                   whose refinement fails (SIMM_EREFINE) is rebuilt with an FP64
+                                   factor inside simm_run (counted by simm_result_refine_stats) */
 } simm_params;
 
 simm_status simm_params_default(simm_params* p);
@@ -149,7 +164,8 @@ simm_status simm_params_default(simm_params* p);
 /* ------------------------------------------------------------------------ */
 
 /* One shift sigma (Sec. 2, Cayley transform and Arnoldi):
- *   banded LU with partial pivoting of A - sigma B;  b = (A - sigma B)^{-1} f,
+ *   banded LU with partial pivoting of A - sigma B (in FP64, or in FP32 with every
+ *   solve refined to a backward error of 1e-12: `precision`, SIMM_PREC_*);  b = (A - sigma B)^{-1} f,
  *   beta = ||b||;  m steps of Arnoldi on M = (A - sigma B)^{-1} B from v_1 = b/beta
  *   (classical Gram-Schmidt applied twice), giving V_{m+1}, H_{m+1,m};
  *   then the Schur form H_m = Q T Q^H used by simm_indicators.
@@ -157,8 +173,13 @@ simm_status simm_params_default(simm_params* p);
  * kl <= 480 of A - sigma B.  Happy breakdown (h_{j+1,j} <= 1e-14 ||M v_j||)
  * stops early with m_eff = j.  ESINGULAR_SHIFT on an exact zero pivot. */
 simm_status simm_shift_build(simm_pencil p, double sig_re, double sig_im,
-                             const double* f, int32_t f_mem, int32_t m,
+                             const double* f, int32_t f_mem, int32_t m, int32_t precision,
                              void* hip_stream, simm_shift* out);
+
+/* Refined solves of a SIMM_PREC_MIXED shift so far (its Krylov phase, simm_shift_apply):
+ * solves, corrections beyond the first solve, and the largest backward error a solve
+ * ended with (zeros for an FP64 shift).  Any pointer may be NULL. */
+simm_status simm_shift_refine_stats(simm_shift s, int64_t* solves, int64_t* corrections, double* max_eta);
 
 /* A shift made from its small data alone (Sec. 2, eqs. (shiftedLS), (eq:many) and
  * (eq:error)): the reduced solves (I + (sigma - z_j) H_m) y_j = beta e_1, their
@@ -354,6 +375,12 @@ simm_status simm_result_stats(simm_result r, double* ms4, int64_t* counters3);
  * SIMM_K_BAND_LU, whose unit is one 16-column panel launch of the LU.  Arrays of
  * SIMM_K_COUNT entries; zeros otherwise. */
 simm_status simm_result_kernel_stats(simm_result r, double* ms, int64_t* launches);
+
+/* Refinement of a SIMM_PREC_MIXED run: refined solves, corrections, shifts rebuilt with an
+ * FP64 factor after SIMM_EREFINE, and the largest backward error a refined solve ended
+ * with.  Any pointer may be NULL; zeros for an FP64 run. */
+simm_status simm_result_refine_stats(simm_result r, int64_t* solves, int64_t* corrections, int32_t* fallbacks,
+                                     double* max_eta);
 
 void simm_result_destroy(simm_result r);
 

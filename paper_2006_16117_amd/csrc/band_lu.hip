@@ -21,10 +21,12 @@
 
 namespace simm {
 
-// a1: C = A - sigma B written into LU band storage (fill rows zeroed).
+// a1: C = A - sigma B written into LU band storage (fill rows zeroed), formed in FP64
+// and stored in the factor's precision.
+template <typename CT>
 __global__ void k_assemble_shifted(int64_t n, int kl, int ku, const cplx* __restrict__ A, int kla, int kua,
                                    const cplx* __restrict__ B, int klb, int kub, cplx sigma,
-                                   cplx* __restrict__ AB) {
+                                   CT* __restrict__ AB) {
     const int kv = kl + ku, ldab = 2 * kl + ku + 1;
     const int64_t c = blockIdx.x;
     for (int r = threadIdx.x; r < ldab; r += blockDim.x) {
@@ -39,7 +41,7 @@ __global__ void k_assemble_shifted(int64_t n, int kl, int ku, const cplx* __rest
                 v = v - sigma;
             }
         }
-        AB[(int64_t)r + c * ldab] = v;
+        AB[(int64_t)r + c * ldab] = narrow<CT>(v);
     }
 }
 
@@ -49,24 +51,27 @@ constexpr int NB = 16;        // panel width
 constexpr int SROW = NB + 1;  // LDS row stride (complex): 16 lanes writing 16-byte rows hit 16 bank groups
 constexpr int CSTRIDE = NB + 2;   // candidate record: row (NB entries), reciprocal pivot, (max, position)
 
+template <typename C>
 struct LuArgs {
     int64_t n;
     int kl, ku, kv, ldab;
-    cplx* AB;
+    C* AB;
     int* ipiv;       // 0-based global row of the pivot of each column
-    cplx* LP;        // permuted multipliers of every panel: panel p at LP + p NB (NB+kl), column-major (NB+kl) x NB
+    C* LP;           // permuted multipliers of every panel: panel p at LP + p NB (NB+kl), column-major (NB+kl) x NB
     int* info;       // first singular column + 1 (INT_MAX if none)
     int64_t zidx;    // index of the zero entry stored after the band
 };
 
 // Index of band entry (i, c), or of the zero entry when (i, c) lies outside the
 // band: loads through it are unconditional, so all of a thread's loads are in flight together.
-__device__ inline int64_t ab_idx(const LuArgs& a, int64_t i, int64_t c) {
+template <typename C>
+__device__ inline int64_t ab_idx(const LuArgs<C>& a, int64_t i, int64_t c) {
     const int64_t d = i - c;
     const bool in = i >= 0 && i < a.n && c >= 0 && c < a.n && d >= -a.kv && d <= a.kl;
     return in ? (int64_t)(a.kv + d) + c * a.ldab : a.zidx;
 }
-__device__ inline void ab_put(const LuArgs& a, int64_t i, int64_t c, cplx v) {
+template <typename C>
+__device__ inline void ab_put(const LuArgs<C>& a, int64_t i, int64_t c, C v) {
     const int64_t d = i - c;
     if (i < 0 || i >= a.n || c < 0 || c >= a.n || d < -a.kv || d > a.kl) return;
     a.AB[(int64_t)(a.kv + d) + c * a.ldab] = v;
@@ -90,20 +95,30 @@ __device__ inline double dpp_d(double v) {
     const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
     return __hiloint2double(hi, lo);
 }
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ inline float dpp_d(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+}
+
+__device__ inline double rdlane_d(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+__device__ inline float rdlane_d(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
 
 // Maximum over the wavefront, returned to every lane: DPP within 16-lane rows
 // (quad xor 1, quad xor 2, half-row mirror, row mirror), then row broadcasts of
 // lanes 15 and 31 carry the row maxima to lane 63.
-__device__ inline double wave_max(double v) {
+template <typename R>
+__device__ inline R wave_max(R v) {
     v = fmax(v, dpp_d<0xB1>(v));
     v = fmax(v, dpp_d<0x4E>(v));
     v = fmax(v, dpp_d<0x141>(v));
     v = fmax(v, dpp_d<0x140>(v));
     v = fmax(v, dpp_d<0x142, 0xA>(v));
     v = fmax(v, dpp_d<0x143, 0xC>(v));
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
-    return __hiloint2double(hi, lo);
+    return rdlane_d(v, 63);
 }
 
 // Minimum over the wavefront (same DPP pattern as wave_max), returned to every lane.
@@ -117,14 +132,9 @@ __device__ inline int wave_min_int(int k) {
     return __builtin_amdgcn_readlane(k, 63);
 }
 
-__device__ inline double rdlane_d(double v, int l) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-    return __hiloint2double(hi, lo);
-}
 // value of the partner lane (lane xor 1)
 __device__ inline cplx swap_pair(cplx v) { return cplx{dpp_d<0xB1>(v.re), dpp_d<0xB1>(v.im)}; }
-__device__ inline cplx rdlane(cplx v, int l) { return cplx{rdlane_d(v.re, l), rdlane_d(v.im, l)}; }
+__device__ inline cplxf swap_pair(cplxf v) { return cplxf{dpp_d<0xB1>(v.re), dpp_d<0xB1>(v.im)}; }
 
 // 1 / u by Smith's scaling (no overflow for any finite nonzero u), without branches.
 __device__ inline cplx crecip(cplx u) {
@@ -133,36 +143,59 @@ __device__ inline cplx crecip(cplx u) {
     const double s = q / p, d = 1.0 / (p + q * s);
     return big ? cplx{d, -s * d} : cplx{s * d, -d};
 }
+__device__ inline cplxf crecip(cplxf u) {
+    const bool big = fabsf(u.re) >= fabsf(u.im);
+    const float p = big ? u.re : u.im, q = big ? u.im : u.re;
+    const float s = q / p, d = 1.0f / (p + q * s);
+    return big ? cplxf{d, -s * d} : cplxf{s * d, -d};
+}
 
-// 16-byte LDS accesses (ds_read_b128 / ds_write_b128); every LDS buffer below is
-// 16-byte aligned and indexed in whole complex entries.
+// 16-byte (FP64) or 8-byte (FP32) LDS accesses of whole complex entries; every LDS
+// buffer below is aligned to its entry size.
 __device__ inline cplx ldsr(const cplx* p) {
     const double2 v = *reinterpret_cast<const double2*>(p);
     return cplx{v.x, v.y};
 }
 __device__ inline void ldsw(cplx* p, cplx v) { *reinterpret_cast<double2*>(p) = double2{v.re, v.im}; }
+__device__ inline cplxf ldsr(const cplxf* p) {
+    const float2 v = *reinterpret_cast<const float2*>(p);
+    return cplxf{v.x, v.y};
+}
+__device__ inline void ldsw(cplxf* p, cplxf v) { *reinterpret_cast<float2*>(p) = float2{v.re, v.im}; }
 
-// LDS layout of one step launch (complex entries).
-template <int T>
+template <typename C>
+struct Real;
+template <>
+struct Real<cplx> {
+    using T = double;
+};
+template <>
+struct Real<cplxf> {
+    using T = float;
+};
+
+// LDS layout of one step launch (complex entries of type C).
+template <int T, typename C>
 struct LuSmem {
     static constexpr int S = 0;                          // T x SROW   : window rows before interchanges
     static constexpr int LSH = S + T * SROW;             // NB x SROW  : diagonal block of the panel multipliers
     static constexpr int USH = LSH + NB * SROW;          // NB x SROW  : U12 block after the triangular solve
     static constexpr int CAND = USH + NB * SROW;         // 2 x (T/64) x CSTRIDE : each wave's pivot candidate
     static constexpr int END = CAND + 2 * (T / 64) * CSTRIDE;
-    static constexpr size_t bytes = (size_t)END * sizeof(cplx) + NB * sizeof(int);
+    static constexpr size_t bytes = (size_t)END * sizeof(C) + NB * sizeof(int);
 };
 
 }  // namespace
 
 namespace {
 
+template <typename C>
 struct FactorCtx {
     bool prow;       // this thread holds a row of the panel
     int nb1;         // panel width
     int64_t j1;      // first column (and row) of the panel
     int lane, wave;
-    cplx* cand;      // 2 x waves x CSTRIDE
+    C* cand;         // 2 x waves x CSTRIDE
 };
 
 // Column step t of the panel factorization: partial pivoting by the largest
@@ -176,49 +209,50 @@ struct FactorCtx {
 // broadcast LDS reads (no lane reads on the chain).  A single-lane LDS write costs a
 // full LDS pass for the CU, so only one wavefront writes a row.  With one
 // wavefront the row goes with the pair, before a single barrier.
-template <int T, int t>
-__device__ __forceinline__ void factor_steps(const LuArgs& a, cplx (&X)[NB], int& pos, const FactorCtx& f) {
+template <int T, int t, typename C>
+__device__ __forceinline__ void factor_steps(const LuArgs<C>& a, C (&X)[NB], int& pos, const FactorCtx<C>& f) {
+    using R = typename Real<C>::T;
     constexpr int W = T / 64;
     if (t < f.nb1) {
         const int buf = t & 1;
         const int64_t j = f.j1 + t;
         const int km = (int)min((int64_t)a.kl, a.n - 1 - j);
         const bool valid = f.prow && pos >= t && pos <= t + km;
-        const double v = valid ? cabs1(X[t]) : -1.0;
-        cplx inv_own = crecip(X[t]);                  // only the pivot's is used; computed by every
+        const R v = valid ? cabs1(X[t]) : R(-1);
+        C inv_own = crecip(X[t]);                     // only the pivot's is used; computed by every
         asm volatile("" : "+v"(inv_own.re), "+v"(inv_own.im));   // lane here so it overlaps the reduction
-        const double m = wave_max(v);
+        const R m = wave_max(v);
         const int key = (v == m) ? pos : 0x7fffffff;
         const int kmin = wave_min_int(key);
         const unsigned long long bal = __ballot(key == kmin);
         const int wl = bal ? __ffsll((long long)bal) - 1 : 0;
         if constexpr (W == 1) {
             if (f.lane == wl) {
-                cplx* rec = f.cand + buf * CSTRIDE;
+                C* rec = f.cand + buf * CSTRIDE;
 #pragma unroll
                 for (int c = t; c < NB; ++c) ldsw(rec + c, X[c]);
                 ldsw(rec + NB, inv_own);
-                ldsw(rec + NB + 1, mk(m, (double)kmin));
+                ldsw(rec + NB + 1, C{m, (R)kmin});
             }
         } else {
             // several wavefronts share the LDS: first only the (max, position) pairs
-            if (f.lane == wl) ldsw(f.cand + (buf * W + f.wave) * CSTRIDE + NB + 1, mk(m, (double)kmin));
+            if (f.lane == wl) ldsw(f.cand + (buf * W + f.wave) * CSTRIDE + NB + 1, C{m, (R)kmin});
         }
         lds_barrier();
-        const cplx r0 = ldsr(f.cand + (buf * W) * CSTRIDE + NB + 1);
-        double best = r0.re;
+        const C r0 = ldsr(f.cand + (buf * W) * CSTRIDE + NB + 1);
+        R best = r0.re;
         int bpos = (int)r0.im, bw = 0;
 #pragma unroll
         for (int w = 1; w < W; ++w) {
-            const cplx rw = ldsr(f.cand + (buf * W + w) * CSTRIDE + NB + 1);
-            const double vw = rw.re;
+            const C rw = ldsr(f.cand + (buf * W + w) * CSTRIDE + NB + 1);
+            const R vw = rw.re;
             const int pw = (int)rw.im;
             const bool take = vw > best || (vw == best && pw < bpos);
             best = take ? vw : best;
             bpos = take ? pw : bpos;
             bw = take ? w : bw;
         }
-        const bool zero = !(best > 0.0);
+        const bool zero = !(best > R(0));
         if (zero) bpos = t;
         if (threadIdx.x == 0) {
             a.ipiv[j] = (int)(f.j1 + bpos);
@@ -228,7 +262,7 @@ __device__ __forceinline__ void factor_steps(const LuArgs& a, cplx (&X)[NB], int
         if constexpr (W > 1) {
             // then the winning wavefront's candidate lane publishes its row
             if (f.wave == bw && f.lane == wl) {
-                cplx* rec = f.cand + (buf * W + bw) * CSTRIDE;
+                C* rec = f.cand + (buf * W + bw) * CSTRIDE;
 #pragma unroll
                 for (int c = t; c < NB; ++c) ldsw(rec + c, X[c]);
                 ldsw(rec + NB, inv_own);
@@ -236,14 +270,14 @@ __device__ __forceinline__ void factor_steps(const LuArgs& a, cplx (&X)[NB], int
             lds_barrier();
         }
         if (!zero) {
-            const cplx* win = f.cand + (buf * W + bw) * CSTRIDE;
-            cplx u[NB + 1];
+            const C* win = f.cand + (buf * W + bw) * CSTRIDE;
+            C u[NB + 1];
 #pragma unroll
             for (int c = t; c <= NB; ++c) u[c] = ldsr(win + c);
             const int p0 = pos;
             pos = (p0 == t) ? bpos : ((p0 == bpos) ? t : p0);
             if (f.prow && pos > t) {
-                const cplx l = X[t] * u[NB];
+                const C l = X[t] * u[NB];
                 X[t] = l;
 #pragma unroll
                 for (int c = t + 1; c < NB; ++c) X[c] = fms(X[c], l, u[c]);
@@ -252,7 +286,7 @@ __device__ __forceinline__ void factor_steps(const LuArgs& a, cplx (&X)[NB], int
         // column t's multipliers go to the band as computed now (later interchanges do not move them)
         if (f.prow && pos > t && pos - t <= a.kl) a.AB[(int64_t)(a.kv + pos - t) + j * a.ldab] = X[t];
     }
-    if constexpr (t + 1 < NB) factor_steps<T, t + 1>(a, X, pos, f);
+    if constexpr (t + 1 < NB) factor_steps<T, t + 1, C>(a, X, pos, f);
 }
 
 }  // namespace
@@ -264,15 +298,16 @@ __device__ __forceinline__ void factor_steps(const LuArgs& a, cplx (&X)[NB], int
 //                   on the top rows and the rank-NB update to their 16 columns;
 //   workgroup 0:    its columns are panel b+1, which it then factors with partial
 //                   pivoting, one column step per LDS barrier.
-template <int T>
-__global__ __launch_bounds__(T) void k_band_lu_step(LuArgs a, int64_t b) {
+template <int T, typename C>
+__global__ __launch_bounds__(T) void k_band_lu_step(LuArgs<C> a, int64_t b) {
     extern __shared__ double2 smem_raw[];
-    cplx* smem = reinterpret_cast<cplx*>(smem_raw);
-    using L = LuSmem<T>;
-    cplx* S = smem + L::S;
-    cplx* Lsh = smem + L::LSH;
-    cplx* Ush = smem + L::USH;
-    cplx* cand = smem + L::CAND;
+    C* smem = reinterpret_cast<C*>(smem_raw);
+    using L = LuSmem<T, C>;
+    const C zero_c{0, 0};
+    C* S = smem + L::S;
+    C* Lsh = smem + L::LSH;
+    C* Ush = smem + L::USH;
+    C* cand = smem + L::CAND;
     int* piv_s = reinterpret_cast<int*>(smem + L::END);
 
     const int tid = threadIdx.x;
@@ -304,15 +339,15 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs a, int64_t b) {
     const int r = tid;
 
     // ---- all global loads of the launch, issued together
-    cplx X[NB], Lr[NB];
+    C X[NB], Lr[NB];
     {
         const bool mine = r < Rw;
 #pragma unroll
         for (int c = 0; c < NB; ++c) X[c] = a.AB[(mine && c < ncols) ? ab_idx(a, j0 + r, c0 + c) : a.zidx];
-        const cplx* lp_in = a.LP + (b >= 0 ? b : 0) * (int64_t)(NB + a.kl) * NB;
+        const C* lp_in = a.LP + (b >= 0 ? b : 0) * (int64_t)(NB + a.kl) * NB;
         const bool hasl = b >= 0 && r < Rb;
 #pragma unroll
-        for (int q = 0; q < NB; ++q) Lr[q] = hasl ? lp_in[(int64_t)q * (NB + a.kl) + r] : mk(0.0, 0.0);
+        for (int q = 0; q < NB; ++q) Lr[q] = hasl ? lp_in[(int64_t)q * (NB + a.kl) + r] : zero_c;
         if (b >= 0 && tid < NB) piv_s[tid] = (int)(a.ipiv[j0 + tid] - j0);
     }
 
@@ -344,7 +379,7 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs a, int64_t b) {
         // the same order.
         {
             constexpr int E = (NB * NB + T - 1) / T;
-            cplx xt[E];
+            C xt[E];
             int ti[E], tc[E];
             bool tin[E];
 #pragma unroll
@@ -353,7 +388,7 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs a, int64_t b) {
                 tin[k] = e < NB * NB;
                 ti[k] = e / NB;
                 tc[k] = e % NB;
-                xt[k] = tin[k] ? ldsr(S + trace_src(ti[k], pv) * SROW + tc[k]) : mk(0.0, 0.0);
+                xt[k] = tin[k] ? ldsr(S + trace_src(ti[k], pv) * SROW + tc[k]) : zero_c;
             }
 #pragma unroll
             for (int t = 0; t < NB; ++t) {
@@ -381,7 +416,7 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs a, int64_t b) {
             // with zero multipliers (rows above NB are not used after the solve).
             const bool odd = (tid & 1) != 0;
             constexpr int H = NB / 2;
-            cplx A[H], B[H];
+            C A[H], B[H];
 #pragma unroll
             for (int i = 0; i < H; ++i) {
                 A[i] = csel(odd, X[H + i], X[i]);
@@ -390,10 +425,10 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs a, int64_t b) {
             const int cb = odd ? H : 0;
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
-                const cplx lq = swap_pair(Lr[q]);
+                const C lq = swap_pair(Lr[q]);
 #pragma unroll
                 for (int i = 0; i < H; ++i) {
-                    const cplx u = ldsr(Ush + q * SROW + cb + i);
+                    const C u = ldsr(Ush + q * SROW + cb + i);
                     A[i] = fms(A[i], Lr[q], u);
                     B[i] = fms(B[i], lq, u);
                 }
@@ -401,7 +436,7 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs a, int64_t b) {
             }
 #pragma unroll
             for (int i = 0; i < H; ++i) {
-                const cplx back = swap_pair(B[i]);
+                const C back = swap_pair(B[i]);
                 X[i] = csel(odd, back, A[i]);
                 X[H + i] = csel(odd, A[i], back);
             }
@@ -429,7 +464,7 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs a, int64_t b) {
     if (wg != 0) return;
 
     // ---- workgroup 0: factor panel b+1 (window rows nbp .., panel position pos = r - nbp at the start)
-    FactorCtx f;
+    FactorCtx<C> f;
     int pos = r - nbp;
     f.prow = pos >= 0 && pos < R1;
     f.nb1 = nb1;
@@ -437,7 +472,7 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs a, int64_t b) {
     f.lane = lane;
     f.wave = wave;
     f.cand = cand;
-    factor_steps<T, 0>(a, X, pos, f);
+    factor_steps<T, 0, C>(a, X, pos, f);
     const int pr = pos;
     const bool prow = f.prow;
     // rows of U (final since their own step) to the band
@@ -449,21 +484,21 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs a, int64_t b) {
     // permuted multipliers of panel b+1 (entries left of the diagonal; zeros elsewhere
     // and in the rows past the matrix) for the next launch's update and the sweeps
     if (pr >= 0 && pr < NB + a.kl) {
-        cplx* lp_out = a.LP + (b + 1) * (int64_t)(NB + a.kl) * NB + pr;
+        C* lp_out = a.LP + (b + 1) * (int64_t)(NB + a.kl) * NB + pr;
 #pragma unroll
-        for (int q = 0; q < NB; ++q) lp_out[(int64_t)q * (NB + a.kl)] = (prow && q < pr && q < nb1) ? X[q] : mk(0.0, 0.0);
+        for (int q = 0; q < NB; ++q) lp_out[(int64_t)q * (NB + a.kl)] = (prow && q < pr && q < nb1) ? X[q] : zero_c;
     }
 }
 
 namespace {
-template <int T>
-simm_status launch_lu(const LuArgs& a, hipStream_t st, const std::atomic<bool>* cancel, int64_t& launches) {
+template <int T, typename C>
+simm_status launch_lu(const LuArgs<C>& a, hipStream_t st, const std::atomic<bool>* cancel, int64_t& launches) {
     const int grid = 2 + (a.kv + NB - 1) / NB;
     const int64_t nblk = (a.n + NB - 1) / NB;
-    const size_t lds = LuSmem<T>::bytes;
+    const size_t lds = LuSmem<T, C>::bytes;
     if (!cancel) {
         for (int64_t b = -1; b < nblk; ++b)
-            hipLaunchKernelGGL(k_band_lu_step<T>, dim3(b < 0 ? 1 : grid), dim3(T), lds, st, a, b);
+            hipLaunchKernelGGL((k_band_lu_step<T, C>), dim3(b < 0 ? 1 : grid), dim3(T), lds, st, a, b);
         launches = nblk + 1;
         return SIMM_OK;
     }
@@ -488,7 +523,7 @@ simm_status launch_lu(const LuArgs& a, hipStream_t st, const std::atomic<bool>* 
         if (batch >= RING) SIMM_HIP_TRY(hipEventSynchronize(e));
         const int64_t bend = std::min<int64_t>(b + BATCH, nblk);
         for (int64_t q = b; q < bend; ++q)
-            hipLaunchKernelGGL(k_band_lu_step<T>, dim3(q < 0 ? 1 : grid), dim3(T), lds, st, a, q);
+            hipLaunchKernelGGL((k_band_lu_step<T, C>), dim3(q < 0 ? 1 : grid), dim3(T), lds, st, a, q);
         launches += bend - b;
         SIMM_HIP_TRY(hipEventRecord(e, st));
     }
@@ -501,13 +536,15 @@ int lu_panel_width(int kl) {
     return (kl >= 0 && 2 * NB + kl <= 512) ? NB : 0;
 }
 
-simm_status band_lu(int64_t n, int kl, int ku, cplx* AB, int* ipiv, cplx* LP, int* info,
-                    hipStream_t st, const std::atomic<bool>* cancel, int64_t* launches) {
+namespace {
+template <typename C>
+simm_status band_lu_t(int64_t n, int kl, int ku, C* AB, int* ipiv, C* LP, int* info, hipStream_t st,
+                      const std::atomic<bool>* cancel, int64_t* launches) {
     if (lu_panel_width(kl) == 0) {
         set_error("lower bandwidth too large for the LU kernel");
         return SIMM_EUNSUPPORTED;
     }
-    LuArgs a;
+    LuArgs<C> a;
     a.n = n;
     a.kl = kl;
     a.ku = ku;
@@ -522,22 +559,41 @@ simm_status band_lu(int64_t n, int kl, int ku, cplx* AB, int* ipiv, cplx* LP, in
     // the smallest workgroup that holds the window: fewer wavefronts to meet at each
     // column step's barrier (the pivot and the arithmetic do not depend on the split)
     const int rows = 2 * NB + kl;
-    const simm_status rc = (rows <= 64)    ? launch_lu<64>(a, st, cancel, count)
-                           : (rows <= 128) ? launch_lu<128>(a, st, cancel, count)
-                           : (rows <= 256) ? launch_lu<256>(a, st, cancel, count)
-                                           : launch_lu<512>(a, st, cancel, count);
+    const simm_status rc = (rows <= 64)    ? launch_lu<64, C>(a, st, cancel, count)
+                           : (rows <= 128) ? launch_lu<128, C>(a, st, cancel, count)
+                           : (rows <= 256) ? launch_lu<256, C>(a, st, cancel, count)
+                                           : launch_lu<512, C>(a, st, cancel, count);
     if (launches) *launches = count;
     SIMM_TRY(rc);
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;
+}
+}  // namespace
+
+simm_status band_lu(int64_t n, int kl, int ku, cplx* AB, int* ipiv, cplx* LP, int* info, hipStream_t st,
+                    const std::atomic<bool>* cancel, int64_t* launches) {
+    return band_lu_t(n, kl, ku, AB, ipiv, LP, info, st, cancel, launches);
+}
+
+simm_status band_lu(int64_t n, int kl, int ku, cplxf* AB, int* ipiv, cplxf* LP, int* info, hipStream_t st,
+                    const std::atomic<bool>* cancel, int64_t* launches) {
+    return band_lu_t(n, kl, ku, AB, ipiv, LP, info, st, cancel, launches);
 }
 
 size_t band_lu_panel_elems(int64_t n, int kl) { return (size_t)((n + NB - 1) / NB) * (size_t)(NB + kl) * NB; }
 
 simm_status assemble_shifted(int64_t n, int kl, int ku, const cplx* A, int kla, int kua, const cplx* B, int klb,
                              int kub, cplx sigma, cplx* AB, hipStream_t st) {
-    hipLaunchKernelGGL(k_assemble_shifted, dim3((unsigned)n), dim3(256), 0, st, n, kl, ku, A, kla, kua, B, klb, kub,
-                       sigma, AB);
+    hipLaunchKernelGGL(k_assemble_shifted<cplx>, dim3((unsigned)n), dim3(256), 0, st, n, kl, ku, A, kla, kua, B, klb,
+                       kub, sigma, AB);
+    SIMM_HIP_TRY(hipGetLastError());
+    return SIMM_OK;
+}
+
+simm_status assemble_shifted(int64_t n, int kl, int ku, const cplx* A, int kla, int kua, const cplx* B, int klb,
+                             int kub, cplx sigma, cplxf* AB, hipStream_t st) {
+    hipLaunchKernelGGL(k_assemble_shifted<cplxf>, dim3((unsigned)n), dim3(256), 0, st, n, kl, ku, A, kla, kua, B, klb,
+                       kub, sigma, AB);
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;
 }

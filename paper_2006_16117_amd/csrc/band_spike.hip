@@ -69,7 +69,8 @@ __device__ inline int trace_src16(int i, const int* pv) {
 // per-panel blocks (once per shift)
 // ---------------------------------------------------------------------------
 // Gf[p] = [L11^{-1}; -L21 L11^{-1}] from the LU's permuted multipliers of panel p.
-__global__ __launch_bounds__(512) void k_blocks_fwd(int kl, const cplx* __restrict__ LP, cplx* __restrict__ Gf) {
+template <typename LT, typename GT>
+__global__ __launch_bounds__(512) void k_blocks_fwd(int kl, const LT* __restrict__ LP, GT* __restrict__ Gf) {
     __shared__ cplx L11[16 * 17], Li[16 * 17];
     const int RW = kl + 16;
     const int64_t p = blockIdx.x;
@@ -77,7 +78,7 @@ __global__ __launch_bounds__(512) void k_blocks_fwd(int kl, const cplx* __restri
     cplx lr[16];
     if (r < RW) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) lr[q] = LP[(p * 16 + q) * RW + r];
+        for (int q = 0; q < 16; ++q) lr[q] = widen(LP[(p * 16 + q) * RW + r]);
         if (r < 16) {
 #pragma unroll
             for (int q = 0; q < 16; ++q) L11[r * 17 + q] = lr[q];
@@ -112,14 +113,15 @@ __global__ __launch_bounds__(512) void k_blocks_fwd(int kl, const cplx* __restri
             }
         }
 #pragma unroll
-        for (int q = 0; q < 16; ++q) Gf[(p * 16 + q) * RW + r] = g[q];
+        for (int q = 0; q < 16; ++q) Gf[(p * 16 + q) * RW + r] = narrow<GT>(g[q]);
     }
 }
 
 // Hb[p] = [-U(j0-K .. j0-1, j0 .. j0+15) U11^{-1}; U11^{-1}], U11 = U(j0 .., j0 ..),
 // the identity past row n.
-__global__ __launch_bounds__(1024) void k_blocks_bwd(int64_t n, int K, int kv, int ldab, const cplx* __restrict__ AB,
-                                                     cplx* __restrict__ Hb) {
+template <typename AT, typename GT>
+__global__ __launch_bounds__(1024) void k_blocks_bwd(int64_t n, int K, int kv, int ldab, const AT* __restrict__ AB,
+                                                     GT* __restrict__ Hb) {
     __shared__ cplx U11[16 * 17], Ui[16 * 17];
     const int RW = K + 16;
     const int64_t p = blockIdx.x;
@@ -128,7 +130,7 @@ __global__ __launch_bounds__(1024) void k_blocks_bwd(int64_t n, int K, int kv, i
     auto U = [&](int64_t i, int64_t j) -> cplx {   // U(i, j) for j >= i (zero outside the stored band)
         if (j >= n || i >= n) return mk(i == j ? 1.0 : 0.0, 0.0);
         if (i < 0 || j - i > kv) return mk(0.0, 0.0);
-        return AB[(int64_t)(kv + i - j) + j * ldab];
+        return widen(AB[(int64_t)(kv + i - j) + j * ldab]);
     };
     if (r < 256) {
         const int i = r >> 4, q = r & 15;
@@ -167,7 +169,7 @@ __global__ __launch_bounds__(1024) void k_blocks_bwd(int64_t n, int K, int kv, i
             }
         }
 #pragma unroll
-        for (int q = 0; q < 16; ++q) Hb[(p * 16 + q) * RW + r] = h[q];
+        for (int q = 0; q < 16; ++q) Hb[(p * 16 + q) * RW + r] = narrow<GT>(h[q]);
     }
 }
 
@@ -177,8 +179,8 @@ __global__ __launch_bounds__(1024) void k_blocks_bwd(int64_t n, int K, int kv, i
 // NR right-hand sides per workgroup (unit-state responses only: NR unit vectors
 // r0 .. r0+NR-1, r0 = NR blockIdx.y, share every panel block the workgroup loads;
 // zero-state sweeps use NR = 1).
-template <int T, int NR>
-__global__ __launch_bounds__(T) void k_chunk_fwd(SpikeFwd a) {
+template <int T, int NR, typename GT>
+__global__ __launch_bounds__(T) void k_chunk_fwd(SpikeFwdT<GT> a) {
     if (a.active != nullptr && *a.active == 0) return;
     extern __shared__ double2 sraw[];
     const int tid = threadIdx.x, lane = tid & 63;
@@ -216,9 +218,9 @@ __global__ __launch_bounds__(T) void k_chunk_fwd(SpikeFwd a) {
     // step consumes never wait for what it prefetches.
     cplx gA[16], gB[16];
     auto prefetch = [&](cplx (&g)[16], int64_t p, int ps) {
-        const cplx* gp = a.G + p * 16 * RW + (mine ? ps : 0);
+        const GT* gp = a.G + p * 16 * RW + (mine ? ps : 0);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) g[q] = gp[q * RW];
+        for (int q = 0; q < 16; ++q) g[q] = widen(gp[q * RW]);
     };
     prefetch(gA, p0, pos);
     auto step = [&](int i, cplx (&gc)[16], cplx (&gn)[16]) {
@@ -284,7 +286,8 @@ __global__ __launch_bounds__(T) void k_chunk_fwd(SpikeFwd a) {
 #pragma unroll
         for (int u = 0; u < NR; ++u) {
             if (r0 + u >= kl) continue;
-            for (int q = tid; q < len; q += T) a.Psi[J0 + q + (int64_t)(r0 + u) * a.n16] = ldsr(outb + u * len + q);
+            for (int q = tid; q < len; q += T)
+                a.Psi[J0 + q + (int64_t)(r0 + u) * a.n16] = narrow<GT>(ldsr(outb + u * len + q));
         }
     }
 }
@@ -292,8 +295,8 @@ __global__ __launch_bounds__(T) void k_chunk_fwd(SpikeFwd a) {
 // ---------------------------------------------------------------------------
 // backward (U) chunk sweep, 16 columns per step (bottom panel first)
 // ---------------------------------------------------------------------------
-template <int T, int NR>
-__global__ __launch_bounds__(T) void k_chunk_bwd(SpikeBwd a) {
+template <int T, int NR, typename GT>
+__global__ __launch_bounds__(T) void k_chunk_bwd(SpikeBwdT<GT> a) {
     if (a.active != nullptr && *a.active == 0) return;
     extern __shared__ double2 sraw[];
     const int tid = threadIdx.x, lane = tid & 63;
@@ -326,9 +329,9 @@ __global__ __launch_bounds__(T) void k_chunk_bwd(SpikeBwd a) {
     }
     cplx hA[16], hB[16];
     auto prefetch = [&](cplx (&h)[16], int64_t p, int ps) {
-        const cplx* hp = a.H + p * 16 * RW + (mine ? ps : 0);
+        const GT* hp = a.H + p * 16 * RW + (mine ? ps : 0);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) h[q] = hp[q * RW];
+        for (int q = 0; q < 16; ++q) h[q] = widen(hp[q * RW]);
     };
     prefetch(hA, pl, pos);
     auto step = [&](int i, cplx (&hc)[16], cplx (&hn)[16]) {
@@ -387,7 +390,8 @@ __global__ __launch_bounds__(T) void k_chunk_bwd(SpikeBwd a) {
 #pragma unroll
         for (int u = 0; u < NR; ++u) {
             if (r0 + u >= K) continue;
-            for (int q = tid; q < len; q += T) a.Psi[J0 + q + (int64_t)(r0 + u) * a.n16] = ldsr(outb + u * len + q);
+            for (int q = tid; q < len; q += T)
+                a.Psi[J0 + q + (int64_t)(r0 + u) * a.n16] = narrow<GT>(ldsr(outb + u * len + q));
         }
     }
 }
@@ -554,8 +558,9 @@ __global__ __launch_bounds__(256) void k_pi_first(int K, int64_t P, int64_t L, i
 
 // y(j) += sum_r Psi(j, r) t_{c(j)}(r); the (at most two) state vectors a block
 // needs are staged in LDS.
+template <typename PT>
 __global__ __launch_bounds__(256) void k_spike_correct(int64_t n, int64_t ld, int K, int64_t s,
-                                                       const cplx* __restrict__ Psi, const cplx* __restrict__ t,
+                                                       const PT* __restrict__ Psi, const cplx* __restrict__ t,
                                                        cplx* __restrict__ y, const int* active) {
     if (active != nullptr && *active == 0) return;
     extern __shared__ cplx ts[];                     // 2 K
@@ -571,21 +576,25 @@ __global__ __launch_bounds__(256) void k_spike_correct(int64_t n, int64_t ld, in
     if (j >= n) return;
     const cplx* tc = ts + ((j / s == cb) ? 0 : K);
     cplx acc = y[j];
-    const cplx* pr = Psi + j;
+    const PT* pr = Psi + j;
     int r = 0;
     for (; r + 8 <= K; r += 8) {
         cplx v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = pr[(int64_t)(r + u) * ld];
+        for (int u = 0; u < 8; ++u) v[u] = widen(pr[(int64_t)(r + u) * ld]);
 #pragma unroll
         for (int u = 0; u < 8; ++u) acc = fma_c(acc, v[u], tc[r + u]);
     }
-    for (; r < K; ++r) acc = fma_c(acc, pr[(int64_t)r * ld], tc[r]);
+    for (; r < K; ++r) acc = fma_c(acc, widen(pr[(int64_t)r * ld]), tc[r]);
     y[j] = acc;
 }
 
 __global__ void k_fill_u32(unsigned* p, int count, unsigned v) {
     for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = v;
+}
+
+__global__ void k_fill_u64(unsigned long long* p, int count) {
+    for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = 0ull;
 }
 
 // ipiv[j] = j past the matrix (identity extension to n16)
@@ -623,6 +632,7 @@ constexpr size_t LDS_LIMIT = 150 * 1024;   // as the chunk-length cap
 // up to 4 of them per workgroup where the LDS allows it (the 1024-thread kernels, one).
 template <typename Args>
 simm_status launch_fwd(const Args& a, int64_t P, int nrhs, int W, int rows, int64_t s, hipStream_t st) {
+    using GT = typename Args::storage;
     int nr = 1;
     if (nrhs > 1) {
         const int cap = (W <= 512) ? 4 : 1;
@@ -635,21 +645,22 @@ simm_status launch_fwd(const Args& a, int64_t P, int nrhs, int W, int rows, int6
     const size_t lds = window_lds(rows, s, nr);
     const dim3 grid((unsigned)P, (unsigned)((nrhs + nr - 1) / nr));
     if (W <= 256) {
-        if (nr == 4) hipLaunchKernelGGL((k_chunk_fwd<256, 4>), grid, dim3(256), lds, st, a);
-        else if (nr == 2) hipLaunchKernelGGL((k_chunk_fwd<256, 2>), grid, dim3(256), lds, st, a);
-        else hipLaunchKernelGGL((k_chunk_fwd<256, 1>), grid, dim3(256), lds, st, a);
+        if (nr == 4) hipLaunchKernelGGL((k_chunk_fwd<256, 4, GT>), grid, dim3(256), lds, st, a);
+        else if (nr == 2) hipLaunchKernelGGL((k_chunk_fwd<256, 2, GT>), grid, dim3(256), lds, st, a);
+        else hipLaunchKernelGGL((k_chunk_fwd<256, 1, GT>), grid, dim3(256), lds, st, a);
     } else if (W <= 512) {
-        if (nr == 4) hipLaunchKernelGGL((k_chunk_fwd<512, 4>), grid, dim3(512), lds, st, a);
-        else if (nr == 2) hipLaunchKernelGGL((k_chunk_fwd<512, 2>), grid, dim3(512), lds, st, a);
-        else hipLaunchKernelGGL((k_chunk_fwd<512, 1>), grid, dim3(512), lds, st, a);
+        if (nr == 4) hipLaunchKernelGGL((k_chunk_fwd<512, 4, GT>), grid, dim3(512), lds, st, a);
+        else if (nr == 2) hipLaunchKernelGGL((k_chunk_fwd<512, 2, GT>), grid, dim3(512), lds, st, a);
+        else hipLaunchKernelGGL((k_chunk_fwd<512, 1, GT>), grid, dim3(512), lds, st, a);
     } else {
-        hipLaunchKernelGGL((k_chunk_fwd<1024, 1>), grid, dim3(1024), lds, st, a);
+        hipLaunchKernelGGL((k_chunk_fwd<1024, 1, GT>), grid, dim3(1024), lds, st, a);
     }
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;
 }
 template <typename Args>
 simm_status launch_bwd(const Args& a, int64_t P, int nrhs, int W, int rows, int64_t s, hipStream_t st) {
+    using GT = typename Args::storage;
     int nr = 1;
     if (nrhs > 1) {
         const int cap = (W <= 512) ? 4 : 1;
@@ -662,15 +673,15 @@ simm_status launch_bwd(const Args& a, int64_t P, int nrhs, int W, int rows, int6
     const size_t lds = window_lds(rows, s, nr);
     const dim3 grid((unsigned)P, (unsigned)((nrhs + nr - 1) / nr));
     if (W <= 256) {
-        if (nr == 4) hipLaunchKernelGGL((k_chunk_bwd<256, 4>), grid, dim3(256), lds, st, a);
-        else if (nr == 2) hipLaunchKernelGGL((k_chunk_bwd<256, 2>), grid, dim3(256), lds, st, a);
-        else hipLaunchKernelGGL((k_chunk_bwd<256, 1>), grid, dim3(256), lds, st, a);
+        if (nr == 4) hipLaunchKernelGGL((k_chunk_bwd<256, 4, GT>), grid, dim3(256), lds, st, a);
+        else if (nr == 2) hipLaunchKernelGGL((k_chunk_bwd<256, 2, GT>), grid, dim3(256), lds, st, a);
+        else hipLaunchKernelGGL((k_chunk_bwd<256, 1, GT>), grid, dim3(256), lds, st, a);
     } else if (W <= 512) {
-        if (nr == 4) hipLaunchKernelGGL((k_chunk_bwd<512, 4>), grid, dim3(512), lds, st, a);
-        else if (nr == 2) hipLaunchKernelGGL((k_chunk_bwd<512, 2>), grid, dim3(512), lds, st, a);
-        else hipLaunchKernelGGL((k_chunk_bwd<512, 1>), grid, dim3(512), lds, st, a);
+        if (nr == 4) hipLaunchKernelGGL((k_chunk_bwd<512, 4, GT>), grid, dim3(512), lds, st, a);
+        else if (nr == 2) hipLaunchKernelGGL((k_chunk_bwd<512, 2, GT>), grid, dim3(512), lds, st, a);
+        else hipLaunchKernelGGL((k_chunk_bwd<512, 1, GT>), grid, dim3(512), lds, st, a);
     } else {
-        hipLaunchKernelGGL((k_chunk_bwd<1024, 1>), grid, dim3(1024), lds, st, a);
+        hipLaunchKernelGGL((k_chunk_bwd<1024, 1, GT>), grid, dim3(1024), lds, st, a);
     }
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;
@@ -731,6 +742,43 @@ static simm_status transfer_products(const SpikeFactor& f, bool forward, int K, 
     return SIMM_OK;
 }
 
+// Per-panel blocks and unit-state responses of a factor stored in precision GT (the
+// factor and its multipliers are read in the same precision, the arithmetic is FP64).
+template <typename GT>
+static simm_status prepare_blocks(SpikeFactor& f, const GT* LP, const GT* AB, GT* Gf, GT* Hb, GT* PsiL, GT* PsiU,
+                                  hipStream_t st) {
+    const int kl = f.klx, K = f.K;
+    const int64_t n16 = f.n16;
+    const unsigned npan = (unsigned)(n16 / 16);
+    hipLaunchKernelGGL((k_blocks_fwd<GT, GT>), dim3(npan),
+                       dim3(threads_for(kl + 16) <= 512 ? threads_for(kl + 16) : 512), 0, st, kl, LP, Gf);
+    hipLaunchKernelGGL((k_blocks_bwd<GT, GT>), dim3(npan), dim3(threads_for(K + 16)), 0, st, f.n, K, f.kl + f.ku,
+                       2 * f.kl + f.ku + 1, AB, Hb);
+    SIMM_HIP_TRY(hipGetLastError());
+    SpikeFwdT<GT> a{};
+    a.n = f.n;
+    a.n16 = n16;
+    a.kl = kl;
+    a.ipiv = f.ipiv;
+    a.G = Gf;
+    a.s = f.s;
+    a.mode = 1;
+    a.Psi = PsiL;
+    a.Phi = f.PhiL;
+    SIMM_TRY(launch_fwd(a, f.P, kl, f.Wf, kl + 16, f.s, st));
+    SpikeBwdT<GT> b{};
+    b.n = f.n;
+    b.n16 = n16;
+    b.K = K;
+    b.H = Hb;
+    b.s = f.s;
+    b.mode = 1;
+    b.Psi = PsiU;
+    b.Phi = f.PhiU;
+    SIMM_TRY(launch_bwd(b, f.P, K, f.Wb, K + 16, f.s, st));
+    return SIMM_OK;
+}
+
 simm_status spike_prepare(SpikeFactor& f, hipStream_t st) {
     f.n16 = (f.n + 15) / 16 * 16;
     if (f.n16 > f.n) hipLaunchKernelGGL(k_pad_ipiv, dim3(1), dim3(16), 0, st, f.n, f.n16, f.ipiv);
@@ -771,22 +819,33 @@ simm_status spike_prepare(SpikeFactor& f, hipStream_t st) {
     const int kl = f.klx, K = f.K;
     const int64_t n16 = f.n16;
     const size_t two = f.G > 1 ? 1 : 0;    // transfer products only with more than one group
-    const size_t elems = (size_t)n16 * (kl + 16) + (size_t)n16 * (K + 16) + (size_t)n16 * kl + (size_t)f.P * kl * kl +
-                         (size_t)n16 * K + (size_t)f.P * K * K + (size_t)f.P * kl * 2 + (size_t)f.P * K * 2 +
+    // n-sized per-panel blocks and unit-state responses, in the factor's precision
+    const size_t big = (size_t)n16 * (kl + 16) + (size_t)n16 * (K + 16) + (size_t)n16 * kl + (size_t)n16 * K;
+    const size_t esz = f.f32 ? sizeof(cplxf) : sizeof(cplx);
+    const size_t elems = (size_t)f.P * kl * kl + (size_t)f.P * K * K + (size_t)f.P * kl * 2 + (size_t)f.P * K * 2 +
                          (size_t)n16 + two * ((size_t)(f.P + f.G) * ((size_t)kl * kl + (size_t)K * K)) +
                          (size_t)f.G * 2 * (kl + K) + (size_t)(f.G + 1) * 16 + 64;
-    SIMM_HIP_TRY(hipMalloc(&f.mem, sizeof(cplx) * elems + 16 * 256));
+    SIMM_HIP_TRY(hipMalloc(&f.mem, sizeof(cplx) * elems + esz * big + 20 * 256));
     char* p = reinterpret_cast<char*>(f.mem);
-    auto take = [&](size_t count) {
+    auto take_b = [&](size_t bytes) {
         char* r = p;
-        p += (sizeof(cplx) * count + 255) & ~(size_t)255;
-        return reinterpret_cast<cplx*>(r);
+        p += (bytes + 255) & ~(size_t)255;
+        return r;
     };
-    f.Gf = take((size_t)n16 * (kl + 16));
-    f.Hb = take((size_t)n16 * (K + 16));
-    f.PsiL = take((size_t)n16 * kl);
+    auto take = [&](size_t count) { return reinterpret_cast<cplx*>(take_b(sizeof(cplx) * count)); };
+    if (f.f32) {
+        auto take_f = [&](size_t count) { return reinterpret_cast<cplxf*>(take_b(sizeof(cplxf) * count)); };
+        f.Gf32 = take_f((size_t)n16 * (kl + 16));
+        f.Hb32 = take_f((size_t)n16 * (K + 16));
+        f.PsiL32 = take_f((size_t)n16 * kl);
+        f.PsiU32 = take_f((size_t)n16 * K);
+    } else {
+        f.Gf = take((size_t)n16 * (kl + 16));
+        f.Hb = take((size_t)n16 * (K + 16));
+        f.PsiL = take((size_t)n16 * kl);
+        f.PsiU = take((size_t)n16 * K);
+    }
     f.PhiL = take((size_t)f.P * kl * kl);
-    f.PsiU = take((size_t)n16 * K);
     f.PhiU = take((size_t)f.P * K * K);
     f.tauL = take((size_t)f.P * kl);
     f.tL = take((size_t)f.P * kl);
@@ -809,35 +868,8 @@ simm_status spike_prepare(SpikeFactor& f, hipStream_t st) {
     f.err = reinterpret_cast<int*>(take(4));
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned*>(f.err), 1, 0u);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, f.counter, (int)((f.G + 1) * SPIKE_CTR_STRIDE), 0u);
-    // per-panel blocks
-    const unsigned npan = (unsigned)(n16 / 16);
-    hipLaunchKernelGGL(k_blocks_fwd, dim3(npan), dim3(threads_for(kl + 16) <= 512 ? threads_for(kl + 16) : 512), 0, st,
-                       kl, f.LP, f.Gf);
-    hipLaunchKernelGGL(k_blocks_bwd, dim3(npan), dim3(threads_for(K + 16)), 0, st, f.n, K, f.kl + f.ku,
-                       2 * f.kl + f.ku + 1, (const cplx*)f.AB, f.Hb);
-    SIMM_HIP_TRY(hipGetLastError());
-    // unit-state responses Psi, Phi
-    SpikeFwd a{};
-    a.n = f.n;
-    a.n16 = n16;
-    a.kl = kl;
-    a.ipiv = f.ipiv;
-    a.G = f.Gf;
-    a.s = f.s;
-    a.mode = 1;
-    a.Psi = f.PsiL;
-    a.Phi = f.PhiL;
-    SIMM_TRY(launch_fwd(a, f.P, kl, f.Wf, kl + 16, f.s, st));
-    SpikeBwd b{};
-    b.n = f.n;
-    b.n16 = n16;
-    b.K = K;
-    b.H = f.Hb;
-    b.s = f.s;
-    b.mode = 1;
-    b.Psi = f.PsiU;
-    b.Phi = f.PhiU;
-    SIMM_TRY(launch_bwd(b, f.P, K, f.Wb, K + 16, f.s, st));
+    if (f.f32) SIMM_TRY(prepare_blocks<cplxf>(f, f.LP32, f.AB32, f.Gf32, f.Hb32, f.PsiL32, f.PsiU32, st));
+    else SIMM_TRY(prepare_blocks<cplx>(f, f.LP, f.AB, f.Gf, f.Hb, f.PsiL, f.PsiU, st));
     if (f.G > 1) {
         SIMM_TRY(transfer_products(f, true, kl, f.PhiL, f.PiL, f.PiFullL, st));
         SIMM_TRY(transfer_products(f, false, K, f.PhiU, f.PiU, f.PiFullU, st));
@@ -938,16 +970,18 @@ static simm_status chain_states(const SpikeFactor& f, bool forward, int K, const
     return SIMM_OK;
 }
 
-simm_status spike_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int* active, hipStream_t st) {
+template <typename GT>
+static simm_status apply_t(const SpikeFactor& f, const GT* Gf, const GT* Hb, const GT* PsiL, const GT* PsiU,
+                           const cplx* u, cplx* y, const int* active, hipStream_t st) {
     const unsigned blocks = (unsigned)((f.n + 255) / 256);
     // forward: z = L^{-1} P u
     cplx* z = f.z;
-    SpikeFwd a{};
+    SpikeFwdT<GT> a{};
     a.n = f.n;
     a.n16 = f.n16;
     a.kl = f.klx;
     a.ipiv = f.ipiv;
-    a.G = f.Gf;
+    a.G = Gf;
     a.s = f.s;
     a.mode = 0;
     a.u = u;
@@ -956,14 +990,14 @@ simm_status spike_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int*
     a.active = active;
     SIMM_TRY(launch_fwd(a, f.P, 1, f.Wf, f.klx + 16, f.s, st));
     SIMM_TRY(chain_states(f, true, f.klx, f.PhiL, f.tauL, f.tL, f.PiL, f.PiFullL, f.goutL, f.tgL, u, 0, active, st));
-    hipLaunchKernelGGL(k_spike_correct, dim3(blocks), dim3(256), sizeof(cplx) * 2 * f.klx, st, f.n, f.n16, f.klx, f.s,
-                       (const cplx*)f.PsiL, (const cplx*)f.tL, z, active);
+    hipLaunchKernelGGL(k_spike_correct<GT>, dim3(blocks), dim3(256), sizeof(cplx) * 2 * f.klx, st, f.n, f.n16, f.klx,
+                       f.s, PsiL, (const cplx*)f.tL, z, active);
     // backward: y = U^{-1} z
-    SpikeBwd b{};
+    SpikeBwdT<GT> b{};
     b.n = f.n;
     b.n16 = f.n16;
     b.K = f.K;
-    b.H = f.Hb;
+    b.H = Hb;
     b.s = f.s;
     b.mode = 0;
     b.z = z;
@@ -973,10 +1007,15 @@ simm_status spike_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int*
     SIMM_TRY(launch_bwd(b, f.P, 1, f.Wb, f.K + 16, f.s, st));
     SIMM_TRY(chain_states(f, false, f.K, f.PhiU, f.tauU, f.tU, f.PiU, f.PiFullU, f.goutU, f.tgU, z, f.n16 - f.K, active,
                           st));
-    hipLaunchKernelGGL(k_spike_correct, dim3(blocks), dim3(256), sizeof(cplx) * 2 * f.K, st, f.n, f.n16, f.K, f.s,
-                       (const cplx*)f.PsiU, (const cplx*)f.tU, y, active);
+    hipLaunchKernelGGL(k_spike_correct<GT>, dim3(blocks), dim3(256), sizeof(cplx) * 2 * f.K, st, f.n, f.n16, f.K, f.s,
+                       PsiU, (const cplx*)f.tU, y, active);
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;
+}
+
+simm_status spike_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int* active, hipStream_t st) {
+    if (f.f32) return apply_t<cplxf>(f, f.Gf32, f.Hb32, f.PsiL32, f.PsiU32, u, y, active, st);
+    return apply_t<cplx>(f, f.Gf, f.Hb, f.PsiL, f.PsiU, u, y, active, st);
 }
 
 int64_t spike_bytes_per_apply(const SpikeFactor& f) {

@@ -95,6 +95,14 @@ struct simm_shift_s {
     cplx* Q = nullptr;       // m_eff x m_eff
     cplx* g = nullptr;
     cplx* qlast = nullptr;
+    // mixed precision: FP32 factor (AB32, LP32 instead of AB, LP) whose solves are
+    // refined against the FP64 pencil (rpen) with the device state rst (in ref_mem)
+    bool mixed = false;
+    cplxf* AB32 = nullptr;
+    cplxf* LP32 = nullptr;
+    RefinePencil rpen{};
+    RefineState rst{};
+    void* ref_mem = nullptr;
     std::vector<cplx> H_host;   // (m_eff+1) x m_eff column-major
     std::vector<cplx> ritz;     // sigma + 1/theta
     bool borrowed = false;      // owned by a simm_result
@@ -109,22 +117,49 @@ struct simm_shift_s {
             release_device(AB);
             release_device(ipiv);
             release_device(LP);
+            release_device(AB32);
+            release_device(LP32);
+            release_device(ref_mem);
         }
         release_device(V);
         AB = nullptr;
         ipiv = nullptr;
         LP = nullptr;
+        AB32 = nullptr;
+        LP32 = nullptr;
+        ref_mem = nullptr;
         V = nullptr;
         spike = SpikeFactor{};
         factor_borrowed = true;   // nothing left to free
     }
-    bool has_factor() const { return AB != nullptr && V != nullptr; }
+    bool has_factor() const { return (AB != nullptr || AB32 != nullptr) && V != nullptr; }
+    // the factor's data for a Krylov space built on it by another (borrowing) shift
+    void borrow_factor_of(const simm_shift_s* base) {
+        p = base->p;
+        sigma = base->sigma;
+        kl = base->kl;
+        ku = base->ku;
+        AB = base->AB;
+        ipiv = base->ipiv;
+        LP = base->LP;
+        mixed = base->mixed;
+        AB32 = base->AB32;
+        LP32 = base->LP32;
+        rpen = base->rpen;
+        rst = base->rst;
+        spike = base->spike;
+        sweeps_ready = true;
+        factor_borrowed = true;
+    }
     ~simm_shift_s() {
         if (!factor_borrowed) {
             spike_release(spike);
             (void)hipFree(AB);
             (void)hipFree(ipiv);
             (void)hipFree(LP);
+            (void)hipFree(AB32);
+            (void)hipFree(LP32);
+            (void)hipFree(ref_mem);
         }
         (void)hipFree(V);
         (void)hipFree(H);
@@ -210,6 +245,11 @@ struct simm_result_s {
     std::vector<ClusterRec> clusters;
     double ms[4] = {0, 0, 0, 0};
     int64_t counters[3] = {0, 0, 0};
+    // mixed precision: refined solves, their corrections, shifts rebuilt in FP64 after a
+    // refinement failure, and the largest backward error a refined solve ended with
+    int64_t refine_solves = 0, refine_corrections = 0;
+    int32_t refine_fallbacks = 0;
+    double refine_max_eta = 0.0;
     simm_params prm{};               // the run's parameters
     simm_pencil_s* pencil = nullptr; // borrowed: the pencil the run was made on
 };
@@ -393,7 +433,8 @@ ShiftDev shift_dev(const simm_shift_s* s) {
 // partial pivoting.  Synchronous on return (the factor may be used next on another
 // stream).
 simm_status factor_shift(simm_pencil_s* p, cplx sigma, hipStream_t st, std::unique_ptr<simm_shift_s>& out,
-                         KernelClock* clk = nullptr, const std::atomic<bool>* cancel = nullptr) {
+                         KernelClock* clk = nullptr, const std::atomic<bool>* cancel = nullptr,
+                         int precision = SIMM_PREC_FP64) {
     auto s = std::make_unique<simm_shift_s>();
     s->p = p;
     s->sigma = sigma;
@@ -407,19 +448,45 @@ simm_status factor_shift(simm_pencil_s* p, cplx sigma, hipStream_t st, std::uniq
         set_error("pencil bandwidth outside the supported range (kl <= 480, kl + ku <= 1022)");
         return SIMM_EUNSUPPORTED;
     }
-    SIMM_TRY(dalloc(&s->AB, (size_t)ldab * n + 1));   // + one zero entry read for out-of-band taps
+    s->mixed = (precision == SIMM_PREC_MIXED);
     SIMM_TRY(dalloc(&s->ipiv, (size_t)((n + 15) / 16 * 16)));
-    SIMM_TRY(dalloc(&s->LP, band_lu_panel_elems(n, kl)));
+    if (s->mixed) {
+        SIMM_TRY(dalloc(&s->AB32, (size_t)ldab * n + 1));   // + one zero entry read for out-of-band taps
+        SIMM_TRY(dalloc(&s->LP32, band_lu_panel_elems(n, kl)));
+        // refinement state: residual and correction vectors, norms, flags, counters
+        SIMM_HIP_TRY(hipMalloc(&s->ref_mem, sizeof(cplx) * 2 * (size_t)n + 1024));
+        cplx* rb = reinterpret_cast<cplx*>(s->ref_mem);
+        s->rst.r = rb;
+        s->rst.d = rb + n;
+        s->rst.norms = reinterpret_cast<unsigned long long*>(rb + 2 * n);
+        s->rst.flags = reinterpret_cast<int*>(s->rst.norms + 8);
+        s->rst.stats = reinterpret_cast<long long*>(s->rst.norms + 16);
+        hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, s->rst.norms, 24);
+        SIMM_HIP_TRY(hipGetLastError());
+        s->rpen = RefinePencil{p->A, p->kla, p->kua, p->B, p->klb, p->kub, sigma, 0.0};
+        SIMM_TRY(band_inf_norm(n, p->A, p->kla, p->kua, p->B, p->klb, p->kub, sigma, s->rst.norms + 4, &s->rpen.cnorm,
+                               st));
+    } else {
+        SIMM_TRY(dalloc(&s->AB, (size_t)ldab * n + 1));   // + one zero entry read for out-of-band taps
+        SIMM_TRY(dalloc(&s->LP, band_lu_panel_elems(n, kl)));
+    }
     DevBuf info_buf;
     SIMM_TRY(info_buf.alloc(sizeof(int), st));
     int* info_d = info_buf.as<int>();
     int info = INT_MAX;
     SIMM_HIP_TRY(hipMemcpyAsync(info_d, &info, sizeof(int), hipMemcpyHostToDevice, st));
-    SIMM_HIP_TRY(hipMemsetAsync(s->AB + (size_t)ldab * n, 0, sizeof(cplx), st));
+    if (s->mixed) SIMM_HIP_TRY(hipMemsetAsync(s->AB32 + (size_t)ldab * n, 0, sizeof(cplxf), st));
+    else SIMM_HIP_TRY(hipMemsetAsync(s->AB + (size_t)ldab * n, 0, sizeof(cplx), st));
     {
         KScope ks(clk, SIMM_K_BAND_LU);
-        SIMM_TRY(assemble_shifted(n, kl, ku, p->A, p->kla, p->kua, p->B, p->klb, p->kub, sigma, s->AB, st));
-        const simm_status lu = band_lu(n, kl, ku, s->AB, s->ipiv, s->LP, info_d, st, cancel, &ks.units);
+        simm_status lu;
+        if (s->mixed) {
+            SIMM_TRY(assemble_shifted(n, kl, ku, p->A, p->kla, p->kua, p->B, p->klb, p->kub, sigma, s->AB32, st));
+            lu = band_lu(n, kl, ku, s->AB32, s->ipiv, s->LP32, info_d, st, cancel, &ks.units);
+        } else {
+            SIMM_TRY(assemble_shifted(n, kl, ku, p->A, p->kla, p->kua, p->B, p->klb, p->kub, sigma, s->AB, st));
+            lu = band_lu(n, kl, ku, s->AB, s->ipiv, s->LP, info_d, st, cancel, &ks.units);
+        }
         if (lu != SIMM_OK) return lu;
     }
     SIMM_HIP_TRY(hipMemcpyAsync(&info, info_d, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -444,6 +511,9 @@ simm_status prepare_sweeps(simm_shift_s* s, hipStream_t st, KernelClock* clk = n
     s->spike.AB = s->AB;
     s->spike.ipiv = s->ipiv;
     s->spike.LP = s->LP;
+    s->spike.f32 = s->mixed;
+    s->spike.AB32 = s->AB32;
+    s->spike.LP32 = s->LP32;
     {
         KScope ks(clk, SIMM_K_SPIKE_PREP);
         SIMM_TRY(spike_prepare(s->spike, st));
@@ -488,6 +558,13 @@ simm_status schur_phase(simm_shift_s* s, int ldh, int* status_dev, hipStream_t s
         }
     }
     return SIMM_OK;
+}
+
+// y = (A - sigma B)^{-1} u with the shift's factor: the partitioned sweeps of the FP64
+// factor, or those of the FP32 factor refined against the FP64 pencil.
+simm_status apply_inverse(const simm_shift_s* s, const cplx* u, cplx* y, const int* active, hipStream_t st) {
+    if (s->mixed) return refine_apply(s->spike, s->rpen, s->rst, u, y, active, st);
+    return spike_apply(s->spike, u, y, active, st);
 }
 
 // Krylov phase of one shift (hot-path steps a3-a5) on a factored shift: the
@@ -541,7 +618,7 @@ simm_status krylov_shift(simm_shift_s* s, const cplx* f_dev, int m, hipStream_t 
     // a3: b = (A - sigma B)^{-1} f, beta, v_1
     {
         KScope ks(clk, SIMM_K_BAND_SWEEP);
-        SIMM_TRY(spike_apply(s->spike, f_dev, s->V, nullptr, st));
+        SIMM_TRY(apply_inverse(s, f_dev, s->V, nullptr, st));
     }
     SIMM_TRY(vec_norm_scale(n, s->V, s->V, beta_d, aw, st));
     // a4: Arnoldi steps.  With `cancel`, the host stays at most 16 steps ahead of the
@@ -570,15 +647,16 @@ simm_status krylov_shift(simm_shift_s* s, const cplx* f_dev, int m, hipStream_t 
         {
             KScope ks(clk, SIMM_K_BAND_SWEEP);   // one application of M: B v, then the factor's sweeps
             SIMM_TRY(prepare_input(n, vj, p->B, p->klb, p->kub, nullptr, flags + 1, aw.u, nullptr, st));
-            SIMM_TRY(spike_apply(s->spike, aw.u, s->V + (int64_t)(j + 1) * n, flags + 1, st));
+            SIMM_TRY(apply_inverse(s, aw.u, s->V + (int64_t)(j + 1) * n, flags + 1, st));
         }
         KScope ks(clk, SIMM_K_GRAM_SCHMIDT);
         SIMM_TRY(arnoldi_step(n, s->V, n, j, s->H, m + 1, aw, flags + 1, flags + 2, st));
     }
     int fl[4];
-    int spike_err = 0;
+    int spike_err = 0, refine_err = 0;
     double beta = 0.0;
     SIMM_HIP_TRY(hipMemcpyAsync(&spike_err, s->spike.err, sizeof(int), hipMemcpyDeviceToHost, st));
+    if (s->mixed) SIMM_HIP_TRY(hipMemcpyAsync(&refine_err, s->rst.flags + 1, sizeof(int), hipMemcpyDeviceToHost, st));
     SIMM_HIP_TRY(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, st));
     SIMM_HIP_TRY(hipMemcpyAsync(&beta, beta_d, sizeof(double), hipMemcpyDeviceToHost, st));
     std::vector<cplx> Hfull((size_t)(m + 1) * m);
@@ -587,6 +665,13 @@ simm_status krylov_shift(simm_shift_s* s, const cplx* f_dev, int m, hipStream_t 
     if (spike_err != 0) {
         set_error("partitioned sweep: a chunk-chain barrier timed out");
         return SIMM_EHIP;
+    }
+    if (refine_err != 0) {
+        char msg[200];
+        std::snprintf(msg, sizeof msg, "FP32 factor at sigma = %.17g%+.17gi: iterative refinement did not reach a "
+                      "backward error of %g in %d steps", s->sigma.re, s->sigma.im, kRefineTol, kRefineMaxSteps);
+        set_error(msg);
+        return SIMM_EREFINE;
     }
     s->m_eff = fl[2];
     s->beta = beta;
@@ -604,9 +689,10 @@ simm_status krylov_shift(simm_shift_s* s, const cplx* f_dev, int m, hipStream_t 
 
 // Both phases of one shift (hot-path steps a1-a5).
 simm_status build_shift(simm_pencil_s* p, cplx sigma, const cplx* f_dev, int m, hipStream_t st,
-                        std::unique_ptr<simm_shift_s>& out, int64_t* applies, KernelClock* clk = nullptr) {
+                        std::unique_ptr<simm_shift_s>& out, int64_t* applies, KernelClock* clk = nullptr,
+                        int precision = SIMM_PREC_FP64) {
     std::unique_ptr<simm_shift_s> s;
-    SIMM_TRY(factor_shift(p, sigma, st, s, clk));
+    SIMM_TRY(factor_shift(p, sigma, st, s, clk, nullptr, precision));
     SIMM_TRY(krylov_shift(s.get(), f_dev, m, st, applies, clk));
     out = std::move(s);
     return SIMM_OK;
@@ -730,6 +816,10 @@ simm_status validate_params(const simm_params* prm, int64_t n, int* nx, int* ny,
         set_error("lookahead must be in 0 .. 16");
         return SIMM_EINVAL;
     }
+    if (prm->precision != SIMM_PREC_FP64 && prm->precision != SIMM_PREC_MIXED) {
+        set_error("precision must be SIMM_PREC_FP64 or SIMM_PREC_MIXED");
+        return SIMM_EINVAL;
+    }
     return SIMM_OK;
 }
 
@@ -800,6 +890,7 @@ struct AheadBuild {
     int dev = 0;
     simm_pencil_s* pen = nullptr;
     cplx sigma{0, 0};
+    int precision = SIMM_PREC_FP64;
 
     simm_status run_phase(int ph) {
         if (ph == 0) {
@@ -810,7 +901,7 @@ struct AheadBuild {
                 return SIMM_EHIP;
             }
             clock.st = st;
-            return factor_shift(pen, sigma, st, s, timed ? &clock : nullptr, &cancel);
+            return factor_shift(pen, sigma, st, s, timed ? &clock : nullptr, &cancel, precision);
         }
         if (ph == 1) return prepare_sweeps(s.get(), st, timed ? &clock : nullptr);
         SIMM_HIP_TRY(hipStreamWaitEvent(st, kready, 0));   // f is written on the run's stream
@@ -835,8 +926,9 @@ struct AheadBuild {
             else done = ph;
         }
     }
-    void start(simm_pencil_s* p, cplx sig, bool timed_) {
+    void start(simm_pencil_s* p, cplx sig, bool timed_, int precision_) {
         timed = timed_;
+        precision = precision_;
         dev = p->dev;
         pen = p;
         sigma = sig;
@@ -1021,7 +1113,7 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
         for (int64_t d = from; d < ncell && live < W; ++d) {
             if (ahead.count(d) || !unresolved(d)) continue;
             auto b = std::make_unique<AheadBuild>();
-            b->start(p, cell_center(prm, 1, cells[d].first, cells[d].second), clk != nullptr);
+            b->start(p, cell_center(prm, 1, cells[d].first, cells[d].second), clk != nullptr, prm->precision);
             ahead[d] = std::move(b);
             ++live;
         }
@@ -1053,7 +1145,7 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
         auto it = ahead.find(d);
         if (it == ahead.end()) {
             auto b = std::make_unique<AheadBuild>();
-            b->start(p, cell_center(prm, 1, cells[d].first, cells[d].second), clk != nullptr);
+            b->start(p, cell_center(prm, 1, cells[d].first, cells[d].second), clk != nullptr, prm->precision);
             it = ahead.emplace(d, std::move(b)).first;
         }
         it->second->request(2, f_dev, m, ready);
@@ -1093,18 +1185,30 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
             const cplx cd = cell_center(prm, 1, cells[d].first, cells[d].second);
             if (cdist(cd, c0) <= 1.5 * w1) continue;
             auto b = std::make_unique<AheadBuild>();
-            b->start(p, cd, clk != nullptr);
+            b->start(p, cd, clk != nullptr, prm->precision);
             ahead[d] = std::move(b);
         }
         predict_ahead(-1, true);
     }
+    // A mixed-precision shift whose refined solves miss their tolerance is rebuilt with an
+    // FP64 factor (the same shift, so the run's shifts and decisions do not change).
+    auto krylov_or_fp64 = [&](std::unique_ptr<simm_shift_s>& s, const std::function<void()>* before_schur) {
+        simm_status rc = krylov_shift(s.get(), f_dev, m, st, &R->counters[2], clk, nullptr, before_schur);
+        if (rc != SIMM_EREFINE) return rc;
+        R->refine_fallbacks += 1;
+        const cplx sig = s->sigma;
+        s.reset();
+        SIMM_TRY(factor_shift(p, sig, st, s, clk, nullptr, SIMM_PREC_FP64));
+        return krylov_shift(s.get(), f_dev, m, st, &R->counters[2], clk, nullptr, before_schur);
+    };
     // step 1: first shift at the centre of R
     {
         std::unique_ptr<simm_shift_s> s;
         {
             Timer t(st, &R->ms[0]);
-            SIMM_TRY(build_shift(p, cplx{(prm->x0 + prm->x1) / 2, (prm->y0 + prm->y1) / 2}, f_dev, m, st, s,
-                                 &R->counters[2], clk));
+            SIMM_TRY(factor_shift(p, cplx{(prm->x0 + prm->x1) / 2, (prm->y0 + prm->y1) / 2}, st, s, clk, nullptr,
+                                  prm->precision));
+            SIMM_TRY(krylov_or_fp64(s, nullptr));
         }
         commit(std::move(s));
     }
@@ -1124,6 +1228,7 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
         if (chosen < 0) {
             std::unique_ptr<simm_shift_s> s;
             bool built = false;   // both phases done ahead
+            bool refine_failed_ahead = false;
             if (W > 1) {
                 const auto t0 = std::chrono::steady_clock::now();
                 if (!ahead.count(c)) top_up(c);
@@ -1135,6 +1240,7 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
                 ahead.erase(c);
                 if (b) {
                     b->finish(clk ? R->kms : nullptr, clk ? R->kcnt : nullptr);
+                    if (b->rc == SIMM_EREFINE) refine_failed_ahead = true;
                     if (b->rc == SIMM_OK && b->done >= 2) {
                         s = std::move(b->s);
                         R->counters[2] += b->applies;
@@ -1150,7 +1256,8 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
                 // one-at-a-time order then reports itself)
                 drop_all();
                 Timer t(st, &R->ms[0]);
-                SIMM_TRY(factor_shift(p, ctr, st, s, clk));
+                if (refine_failed_ahead) R->refine_fallbacks += 1;
+                SIMM_TRY(factor_shift(p, ctr, st, s, clk, nullptr, refine_failed_ahead ? SIMM_PREC_FP64 : prm->precision));
             }
             if (!built) {
                 // while this shift's Schur form runs (one wavefront), the sweep data of
@@ -1166,7 +1273,7 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
                     }
                 };
                 Timer t(st, &R->ms[0]);
-                SIMM_TRY(krylov_shift(s.get(), f_dev, m, st, &R->counters[2], clk, nullptr, &prep_next));
+                SIMM_TRY(krylov_or_fp64(s, &prep_next));
             }
             // neighbours of c after it that no shift resolved before this one
             std::vector<int64_t> nb;
@@ -1300,8 +1407,8 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
         // a9: X = V_m Y for the squares of this level, shift by shift
         if (do_proj) {
             Timer t(st, &R->ms[2]);
-            const int proj_prec = !(prm->flags & SIMM_FLAG_MIXED_PROJECT) ? SIMM_PROJ_FP64
-                                  : (k <= 2) ? SIMM_PROJ_BF16 : SIMM_PROJ_FP32;
+            const bool mixed_proj = (prm->flags & SIMM_FLAG_MIXED_PROJECT) || prm->precision == SIMM_PREC_MIXED;
+            const int proj_prec = !mixed_proj ? SIMM_PROJ_FP64 : (k <= 2) ? SIMM_PROJ_BF16 : SIMM_PROJ_FP32;
             std::vector<std::vector<int64_t>> by_shift(shifts.size());
             for (int64_t r = 0; r < N; ++r) by_shift[used[r]].push_back(r);
             int64_t cmax = 0;
@@ -1413,6 +1520,19 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
         }
         R->clusters.push_back(cr);
     }
+    for (auto& sh : R->shifts) {
+        if (!sh->mixed) continue;
+        long long stats[2] = {0, 0};
+        unsigned long long eta_bits = 0;
+        SIMM_HIP_TRY(hipMemcpyAsync(stats, sh->rst.stats, sizeof(stats), hipMemcpyDeviceToHost, st));
+        SIMM_HIP_TRY(hipMemcpyAsync(&eta_bits, sh->rst.norms + 3, sizeof(eta_bits), hipMemcpyDeviceToHost, st));
+        SIMM_HIP_TRY(hipStreamSynchronize(st));
+        double eta = 0.0;
+        std::memcpy(&eta, &eta_bits, sizeof(eta));
+        R->refine_solves += stats[0];
+        R->refine_corrections += stats[1];
+        R->refine_max_eta = std::max(R->refine_max_eta, eta);
+    }
     if (prm->flags & SIMM_FLAG_RELEASE_FACTORS) {
         SIMM_HIP_TRY(hipStreamSynchronize(st));
         for (auto& sh : R->shifts) sh->release_large();
@@ -1485,15 +1605,7 @@ simm_status multiplicities(simm_result_s* R, const cplx* F, int k, double rel_to
         for (int i = 0; i < k; ++i) {
             // Krylov space of f_i on the shift's factor
             simm_shift_s kv;
-            kv.p = p;
-            kv.sigma = base->sigma;
-            kv.kl = base->kl;
-            kv.ku = base->ku;
-            kv.AB = base->AB;
-            kv.ipiv = base->ipiv;
-            kv.LP = base->LP;
-            kv.spike = base->spike;
-            kv.factor_borrowed = true;
+            kv.borrow_factor_of(base);
             SIMM_TRY(krylov_shift(&kv, F + (int64_t)i * n, m, st, nullptr));
             EvalOut eo;
             SIMM_TRY(evaluate({&kv}, regs, prm, rule, st, eo, sb.as<cplx>(), m));
@@ -1831,6 +1943,7 @@ simm_status simm_params_default(simm_params* p) {
     p->max_regions_per_level = (int64_t)1 << 22;
     p->flags = 0;
     p->lookahead = 0;
+    p->precision = SIMM_PREC_FP64;
     return SIMM_OK;
 }
 
@@ -1942,7 +2055,7 @@ void simm_pencil_destroy(simm_pencil p) {
 }
 
 simm_status simm_shift_build(simm_pencil p, double sig_re, double sig_im, const double* f, int32_t f_mem, int32_t m,
-                             void* hip_stream, simm_shift* out) {
+                             int32_t precision, void* hip_stream, simm_shift* out) {
     clear_error();
     if (!out) return SIMM_EINVAL;
     *out = nullptr;
@@ -1958,12 +2071,16 @@ simm_status simm_shift_build(simm_pencil p, double sig_re, double sig_im, const 
         set_error("Krylov dimension above 128 is not supported");
         return SIMM_EUNSUPPORTED;
     }
+    if (precision != SIMM_PREC_FP64 && precision != SIMM_PREC_MIXED) {
+        set_error("precision must be SIMM_PREC_FP64 or SIMM_PREC_MIXED");
+        return SIMM_EINVAL;
+    }
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     DevBuf fb;
     const cplx* fd = nullptr;
     SIMM_TRY(to_device_vec(f, f_mem, p->n, fb, &fd, st));
     std::unique_ptr<simm_shift_s> s;
-    SIMM_TRY(build_shift(p, cplx{sig_re, sig_im}, fd, m, st, s, nullptr));
+    SIMM_TRY(build_shift(p, cplx{sig_re, sig_im}, fd, m, st, s, nullptr, nullptr, precision));
     *out = s.release();
     return SIMM_OK;
 }
@@ -2066,7 +2183,7 @@ simm_status simm_shift_apply(simm_shift s, const double* x, double* y, int32_t m
         yd = yb.as<cplx>();
     }
     SIMM_TRY(prepare_input(n, xd, s->p->B, s->p->klb, s->p->kub, nullptr, nullptr, ub.as<cplx>(), nullptr, st));
-    SIMM_TRY(spike_apply(s->spike, ub.as<const cplx>(), yd, nullptr, st));
+    SIMM_TRY(apply_inverse(s, ub.as<const cplx>(), yd, nullptr, st));
     if (mem == SIMM_MEM_HOST) SIMM_HIP_TRY(hipMemcpyAsync(y, yd, sizeof(cplx) * n, hipMemcpyDeviceToHost, st));
     SIMM_HIP_TRY(hipStreamSynchronize(st));
     return SIMM_OK;
@@ -2194,6 +2311,10 @@ simm_status simm_gradient(const simm_shift* shifts, int32_t n_shifts, const int6
         if (!s->has_factor()) {
             set_error("a shift's factor or Krylov basis was released");
             return SIMM_EINVAL;
+        }
+        if (s->mixed) {
+            set_error("the adjoint gradient needs shifts with an FP64 factor");
+            return SIMM_EUNSUPPORTED;
         }
         if (s->m_eff > 128) {
             set_error("Krylov dimension above 128");
@@ -2518,6 +2639,33 @@ simm_status simm_result_stats(simm_result r, double* ms4, int64_t* counters3) {
         for (int i = 0; i < 4; ++i) ms4[i] = r->ms[i];
     if (counters3)
         for (int i = 0; i < 3; ++i) counters3[i] = r->counters[i];
+    return SIMM_OK;
+}
+
+simm_status simm_result_refine_stats(simm_result r, int64_t* solves, int64_t* corrections, int32_t* fallbacks,
+                                     double* max_eta) {
+    if (!r) return SIMM_EINVAL;
+    if (solves) *solves = r->refine_solves;
+    if (corrections) *corrections = r->refine_corrections;
+    if (fallbacks) *fallbacks = r->refine_fallbacks;
+    if (max_eta) *max_eta = r->refine_max_eta;
+    return SIMM_OK;
+}
+
+simm_status simm_shift_refine_stats(simm_shift s, int64_t* solves, int64_t* corrections, double* max_eta) {
+    clear_error();
+    if (!s) return SIMM_EINVAL;
+    long long stats[2] = {0, 0};
+    unsigned long long eta_bits = 0;
+    if (s->mixed && s->ref_mem) {
+        SIMM_HIP_TRY(hipMemcpy(stats, s->rst.stats, sizeof(stats), hipMemcpyDeviceToHost));
+        SIMM_HIP_TRY(hipMemcpy(&eta_bits, s->rst.norms + 3, sizeof(eta_bits), hipMemcpyDeviceToHost));
+    }
+    double eta = 0.0;
+    std::memcpy(&eta, &eta_bits, sizeof(eta));
+    if (solves) *solves = stats[0];
+    if (corrections) *corrections = stats[1];
+    if (max_eta) *max_eta = eta;
     return SIMM_OK;
 }
 

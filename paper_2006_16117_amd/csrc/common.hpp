@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstring>
 #include <string>
 
 #include "simm.h"
@@ -45,6 +46,30 @@ __host__ __device__ inline cplx fma_cj(cplx a, cplx b, cplx c) {
 }
 // c ? a : b, component-wise (a struct-valued ?: can be lowered through scratch memory)
 __host__ __device__ inline cplx csel(bool c, cplx a, cplx b) { return cplx{c ? a.re : b.re, c ? a.im : b.im}; }
+
+// complex<float>: the storage and arithmetic of the FP32 band factor (same operations)
+struct cplxf {
+    float re, im;
+};
+__host__ __device__ inline cplxf operator+(cplxf a, cplxf b) { return cplxf{a.re + b.re, a.im + b.im}; }
+__host__ __device__ inline cplxf operator-(cplxf a, cplxf b) { return cplxf{a.re - b.re, a.im - b.im}; }
+__host__ __device__ inline cplxf operator*(cplxf a, cplxf b) {
+    return cplxf{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__host__ __device__ inline float cabs1(cplxf a) { return fabsf(a.re) + fabsf(a.im); }
+__host__ __device__ inline cplxf fms(cplxf a, cplxf b, cplxf c) {
+    return cplxf{a.re - b.re * c.re + b.im * c.im, a.im - b.re * c.im - b.im * c.re};
+}
+__host__ __device__ inline cplxf csel(bool c, cplxf a, cplxf b) { return cplxf{c ? a.re : b.re, c ? a.im : b.im}; }
+// widening / rounding between the two
+__host__ __device__ inline cplx widen(cplx a) { return a; }
+__host__ __device__ inline cplx widen(cplxf a) { return cplx{(double)a.re, (double)a.im}; }
+template <typename C>
+__host__ __device__ inline C narrow(cplx a);
+template <>
+__host__ __device__ inline cplx narrow<cplx>(cplx a) { return a; }
+template <>
+__host__ __device__ inline cplxf narrow<cplxf>(cplx a) { return cplxf{(float)a.re, (float)a.im}; }
 // a / b, scaled to avoid overflow (Smith's method)
 __host__ __device__ inline cplx cdiv(cplx a, cplx b) {
     if (fabs(b.re) >= fabs(b.im)) {

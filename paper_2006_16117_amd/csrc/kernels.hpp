@@ -20,6 +20,11 @@ size_t band_lu_panel_elems(int64_t n, int kl);
 // `launches` (may be NULL) receives the number of panel launches enqueued.
 simm_status band_lu(int64_t n, int kl, int ku, cplx* AB, int* ipiv, cplx* LP, int* info, hipStream_t st,
                     const std::atomic<bool>* cancel = nullptr, int64_t* launches = nullptr);
+// the same factorization in FP32 arithmetic and storage (the mixed-precision factor)
+simm_status band_lu(int64_t n, int kl, int ku, cplxf* AB, int* ipiv, cplxf* LP, int* info, hipStream_t st,
+                    const std::atomic<bool>* cancel = nullptr, int64_t* launches = nullptr);
+simm_status assemble_shifted(int64_t n, int kl, int ku, const cplx* A, int kla, int kua, const cplx* B, int klb,
+                             int kub, cplx sigma, cplxf* AB, hipStream_t st);
 
 // ---- input of the sweeps (band_sweep.hip) ----
 simm_status prepare_input(int64_t n, const cplx* x, const cplx* Bb, int klb, int kub, const double* hdiv,
@@ -34,33 +39,39 @@ simm_status prepare_input(int64_t n, const cplx* x, const cplx* Bb, int klb, int
 //            (L = the panel's permuted multipliers),
 //   backward Hb[p] (K + 16) x 16: rows 0..K-1 = -U(j0-K .. j0-1, panel) U11^{-1},
 //            rows K.. = U11^{-1}.
-struct SpikeFwd {
+template <typename GT>      // storage of the per-panel blocks and unit-state responses
+struct SpikeFwdT {
+    using storage = GT;
     int64_t n, n16;
     int kl;
     const int* ipiv;   // n16 entries (identity past n)
-    const cplx* G;     // forward panel blocks
+    const GT* G;       // forward panel blocks
     int64_t s;         // chunk length (multiple of 16)
     int mode;          // 0: zero state, input u; 1: unit state blockIdx.y, zero input
     const cplx* u;
     cplx* y;
     cplx* tau;
-    cplx* Psi;         // n16 x kl
+    GT* Psi;           // n16 x kl
     cplx* Phi;
     const int* active;
 };
-struct SpikeBwd {
+template <typename GT>
+struct SpikeBwdT {
+    using storage = GT;
     int64_t n, n16;
     int K;
-    const cplx* H;     // backward panel blocks
+    const GT* H;       // backward panel blocks
     int64_t s;
     int mode;
     const cplx* z;
     cplx* y;
     cplx* tau;
-    cplx* Psi;         // n16 x K
+    GT* Psi;           // n16 x K
     cplx* Phi;
     const int* active;
 };
+using SpikeFwd = SpikeFwdT<cplx>;
+using SpikeBwd = SpikeBwdT<cplx>;
 struct SpikeChain {
     int64_t n;
     int K;
@@ -89,6 +100,14 @@ struct SpikeFactor {
     void* mem = nullptr;
     cplx *Gf = nullptr, *Hb = nullptr;
     cplx *PsiL = nullptr, *PhiL = nullptr, *PsiU = nullptr, *PhiU = nullptr;
+    // FP32 factor (mixed precision): the factor, its panel multipliers, the per-panel
+    // blocks and the unit-state responses are stored in FP32 (the blocks and responses
+    // formed in FP64 arithmetic from the FP32 factor); the sweeps compute in FP64, and the
+    // small per-chunk data (Phi, states, transfer products) stays FP64
+    bool f32 = false;
+    const cplxf* AB32 = nullptr;
+    const cplxf* LP32 = nullptr;
+    cplxf *Gf32 = nullptr, *Hb32 = nullptr, *PsiL32 = nullptr, *PsiU32 = nullptr;
     cplx *tauL = nullptr, *tL = nullptr, *tauU = nullptr, *tU = nullptr, *z = nullptr;
     // two-level chain: G groups of L chunks (in chain order); per direction the products
     // Pi_q of the transfer matrices from the start of q's group to chunk q (chain order),
@@ -105,6 +124,30 @@ simm_status spike_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int*
 void spike_release(SpikeFactor& f);
 simm_status spike_clone_scratch(const SpikeFactor& base, SpikeFactor& out, hipStream_t st);
 int64_t spike_bytes_per_apply(const SpikeFactor& f);
+
+// ---- mixed precision: FP64-residual refinement of FP32-factor solves (refine.hip) ----
+constexpr double kRefineTol = 1e-12;   // normwise backward error of every refined solve
+constexpr int kRefineMaxSteps = 8;     // corrections before the solve counts as failed
+struct RefinePencil {                  // the FP64 shifted pencil the residuals are taken with
+    const cplx* A;
+    int kla, kua;
+    const cplx* B;                     // nullptr: B = I
+    int klb, kub;
+    cplx sigma;
+    double cnorm;                      // ||A - sigma B||_inf
+};
+struct RefineState {                   // device memory of one shift's refined solves
+    cplx* r;                           // n: residual
+    cplx* d;                           // n: correction
+    unsigned long long* norms;         // [0..2] ||r||, ||x||, ||u|| (inf, as bits); [3] largest final eta
+    int* flags;                        // [0] refinement active, [1] tolerance not reached (sticky)
+    long long* stats;                  // [0] refined solves, [1] corrections
+};
+simm_status band_inf_norm(int64_t n, const cplx* A, int kla, int kua, const cplx* B, int klb, int kub, cplx sigma,
+                          unsigned long long* scratch, double* host, hipStream_t st);
+simm_status refine_apply(const SpikeFactor& f, const RefinePencil& pen, const RefineState& rs, const cplx* u, cplx* y,
+                         const int* active, hipStream_t st);
+__global__ void k_fill_u64(unsigned long long* p, int count);
 
 // ---- Gram-Schmidt (arnoldi.hip) ----
 struct ArnoldiWork {

@@ -23,6 +23,8 @@ SIMM_FLAG_PROJECT = 1
 SIMM_FLAG_KERNEL_TIMING = 2
 SIMM_FLAG_RELEASE_FACTORS = 4
 SIMM_FLAG_MIXED_PROJECT = 8
+SIMM_PREC_FP64 = 0
+SIMM_PREC_MIXED = 1
 SIMM_PROJ_FP64 = 0
 SIMM_PROJ_FP32 = 1
 SIMM_PROJ_BF16 = 2
@@ -45,7 +47,7 @@ class simm_params(C.Structure):
                 ("n1", C.c_int32), ("gauss_per_edge", C.c_int32), ("m", C.c_int32), ("levels", C.c_int32),
                 ("h0", C.c_double), ("eps0", C.c_double), ("delta0", C.c_double), ("tau", C.c_double),
                 ("max_regions_per_level", C.c_int64), ("flags", C.c_uint32),
-                ("lookahead", C.c_int32)]
+                ("lookahead", C.c_int32), ("precision", C.c_int32)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -71,7 +73,8 @@ EXPORTS = {
     "simm_pencil_create_csr": (C.c_int, [_i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_vp)]),
     "simm_pencil_info": (C.c_int, [_vp, C.POINTER(_i64), C.POINTER(_i32), C.POINTER(_i32)]),
     "simm_pencil_destroy": (None, [_vp]),
-    "simm_shift_build": (C.c_int, [_vp, _d, _d, _vp, _i32, _i32, _vp, C.POINTER(_vp)]),
+    "simm_shift_build": (C.c_int, [_vp, _d, _d, _vp, _i32, _i32, _i32, _vp, C.POINTER(_vp)]),
+    "simm_shift_refine_stats": (C.c_int, [_vp, _vp, _vp, _vp]),
     "simm_shift_from_hessenberg": (C.c_int, [_d, _d, _d, _vp, _i32, _vp, C.POINTER(_vp)]),
     "simm_shift_info": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "simm_shift_basis": (C.c_int, [_vp, _vp, _i32, _vp]),
@@ -94,6 +97,7 @@ EXPORTS = {
     "simm_result_clusters": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _i64]),
     "simm_result_stats": (C.c_int, [_vp, _vp, _vp]),
     "simm_result_kernel_stats": (C.c_int, [_vp, _vp, _vp]),
+    "simm_result_refine_stats": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "simm_result_destroy": (None, [_vp]),
 }
 for _name, (_res, _args) in EXPORTS.items():
@@ -216,6 +220,13 @@ class Shift:
         _check(_lib.simm_shift_basis(self.handle, p, mem, _stream(stream)))
         return out
 
+    def refine_stats(self):
+        sv = C.c_int64()
+        co = C.c_int64()
+        eta = C.c_double()
+        _check(_lib.simm_shift_refine_stats(self.handle, C.addressof(sv), C.addressof(co), C.addressof(eta)))
+        return dict(solves=sv.value, corrections=co.value, max_eta=eta.value)
+
     def apply(self, x, y, stream=None):
         px, mem = _ptr(x)
         py, _ = _ptr(y)
@@ -232,11 +243,12 @@ def _lib_n(shift: Shift) -> int:
     return shift._n
 
 
-def simm_shift_build(pencil: Pencil, sigma: complex, f, m: int, stream=None) -> Shift:
+def simm_shift_build(pencil: Pencil, sigma: complex, f, m: int, precision: int = SIMM_PREC_FP64,
+                     stream=None) -> Shift:
     pf, mem = _ptr(np.ascontiguousarray(f, dtype=np.complex128) if isinstance(f, np.ndarray) else f)
     h = _vp()
     _check(_lib.simm_shift_build(pencil.handle, float(np.real(sigma)), float(np.imag(sigma)), pf, mem, m,
-                                 _stream(stream), C.byref(h)))
+                                 int(precision), _stream(stream), C.byref(h)))
     s = Shift(h)
     s._n = pencil.n
     return s
@@ -435,6 +447,13 @@ class Result:
         _check(_lib.simm_result_kernel_stats(handle, kms.ctypes.data, kcnt.ctypes.data))
         self.kernel_ms = {k: float(v) for k, v in zip(KERNEL_NAMES, kms)}
         self.kernel_launches = {k: int(v) for k, v in zip(KERNEL_NAMES, kcnt)}
+        sv = C.c_int64()
+        co = C.c_int64()
+        fb = C.c_int32()
+        eta = C.c_double()
+        _check(_lib.simm_result_refine_stats(handle, C.addressof(sv), C.addressof(co), C.addressof(fb),
+                                             C.addressof(eta)))
+        self.refine = dict(solves=sv.value, corrections=co.value, fallbacks=fb.value, max_eta=eta.value)
 
     def shift(self, idx: int) -> Shift:
         h = _vp()

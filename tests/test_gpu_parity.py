@@ -870,3 +870,131 @@ def test_gradient_unresolved_squares_are_errors(S):
     with pytest.raises(S.SimmError) as e:
         S.simm_gradient([sh], reg, S.params_from_dict(p2, m=4), want_diag=True, want_dp=False)
     assert e.value.status == -10 and "adjoint" in str(e.value)
+
+
+# ---------------------------------------------------------------------------
+# mixed precision: FP32 factor, solves refined against the FP64 pencil
+# ---------------------------------------------------------------------------
+def _backward_error(pen, sigma, u, y):
+    """||u - (A - sigma B) y||_inf / (||A - sigma B||_inf ||y||_inf + ||u||_inf), on the host."""
+    A, B = O.pencil_dense(pen)
+    C = A - sigma * B
+    r = u - C @ y
+    return float(np.max(np.abs(r)) / (np.max(np.sum(np.abs(C), axis=1)) * np.max(np.abs(y)) + np.max(np.abs(u))))
+
+
+MIXED_CASES = [c for c in CASES if c[0] in ("cfg0-like", "tridiagB", "pivoting", "ragged-wide", "band60-pivoting",
+                                            "band224")]
+
+
+@pytest.mark.parametrize("case", MIXED_CASES, ids=[c[0] for c in MIXED_CASES])
+def test_mixed_shift_build(S, case):
+    """FP32 factor: every refined solve meets the backward-error tolerance 1e-12 (checked
+    on the host with the dense pencil), and H stays close to the oracle's FP64 H (a solve
+    with backward error 1e-12 perturbs M by about kappa(A - sigma B) 1e-12)."""
+    name, n, k, seed, b_kind, m, sigma, kw = case
+    pen, f = random_band_pencil(n, k, seed, b_kind=b_kind, b_offdiag=0.3, **kw)
+    say("mixed shift_build", name, f"n={n} k={k} m={m}")
+    P = S.Pencil.from_workload(pen)
+    sh = S.simm_shift_build(P, sigma, f, m, precision=S.SIMM_PREC_MIXED)
+    st = sh.refine_stats()
+    assert st["solves"] >= m + 1 and st["max_eta"] <= 1e-12, st
+    g = sh.info()
+    o = O.build_shift(pen, sigma, f, m)
+    assert g["m_eff"] == o.m_eff
+    d = hmax_diff(g["H"], o.H)
+    say(f"  refined solves {st['solves']}, corrections {st['corrections']}, max backward error {st['max_eta']:.2e}; "
+        f"max |H_mixed - H_oracle| / max|H| = {d:.2e}")
+    assert d <= 1e-7
+    rng = np.random.default_rng(17)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    y = np.zeros(n, np.complex128)
+    sh.apply(x, y)
+    u = O.band_matvec(n, pen.kl_b, pen.ku_b, pen.b_band, x)
+    eta = _backward_error(pen, sigma, u, y)
+    say(f"  one application: host backward error {eta:.2e}")
+    assert eta <= 1e-12
+
+
+def test_mixed_refinement_failure_falls_back_to_fp64(S):
+    """A shift 1e-10 from an eigenvalue of a tridiagonal pencil with known spectrum
+    (2 - 2 cos(k pi / (n + 1))): kappa(A - sigma I) ~ 4e10, so FP32 refinement cannot
+    converge (its contraction kappa u_32 > 1).  simm_shift_build reports SIMM_EREFINE; a
+    run whose first shift sits there rebuilds that shift in FP64 and equals the FP64 run."""
+    n = 200
+    band = np.zeros((3, n), dtype=np.complex128, order="F")
+    band[0, 1:] = -1.0
+    band[1, :] = 2.0
+    band[2, :-1] = -1.0
+    pen = WPencil(n, 1, 1, band, 0, 0, None)
+    lam1 = 2.0 - 2.0 * np.cos(np.pi / (n + 1))
+    sigma = lam1 + 1e-10
+    f = np.ones(n, np.complex128)
+    say("mixed refinement failure", f"n={n}, sigma = lambda_1 + 1e-10")
+    P = S.Pencil.from_workload(pen)
+    with pytest.raises(S.SimmError) as e:
+        S.simm_shift_build(P, sigma, f, 20, precision=S.SIMM_PREC_MIXED)
+    assert e.value.status == -9
+    w = 2e-4
+    prm = dict(x0=sigma - w / 2, x1=sigma + w / 2, y0=-w / 2, y1=w / 2, n1=1, gauss_per_edge=8, m=20, h0=0,
+               levels=3, eps0=1e-8, delta0=0.05, tau=1e-8)
+    r64 = S.simm_run(P, f, S.params_from_dict(prm))
+    rmx = S.simm_run(P, f, S.params_from_dict(prm, precision=S.SIMM_PREC_MIXED))
+    assert rmx.refine["fallbacks"] == 1 and r64.refine["fallbacks"] == 0
+    for L64, Lmx in zip(r64.levels, rmx.levels):
+        assert np.array_equal(L64.keys, Lmx.keys) and np.array_equal(L64.decision, Lmx.decision)
+        assert np.array_equal(L64.indicator, Lmx.indicator)
+    assert np.array_equal(r64.lam, rmx.lam)
+
+
+def _run_matches_golden(S, res, gold):
+    """Squares, shifts and decisions of every level equal the oracle's stored run (a
+    decision may differ only where the oracle's margin is below 1e-8); clusters equal."""
+    assert res.K == gold["K"] and res.n_shifts == len(gold["shifts"])
+    ties = 0
+    for L, G in zip(res.levels, gold["levels"]):
+        assert np.array_equal(L.keys[:, 0], G["ix"]) and np.array_equal(L.keys[:, 1], G["iy"]), L.level
+        assert np.array_equal(L.shift, G["shift"]), L.level
+        for r in np.nonzero(L.decision != np.array(G["decision"]))[0]:
+            ties += 1
+            assert G["margin"][r] < 1e-8, (L.level, r, G["margin"][r])
+    lam = np.array([complex(*c["lam"]) for c in gold["clusters"]])
+    assert len(res.lam) == len(lam) and np.all(np.abs(res.lam - lam) <= 1e-14 * np.maximum(1.0, np.abs(lam)))
+    return ties
+
+
+def test_run_mixed_cfg0_matches_oracle(S):
+    pen, f, params = make_workload("cfg0")
+    say("run", "cfg0 mixed precision")
+    with open(os.path.join(GOLDEN, "cfg0_oracle.json")) as fh:
+        gold = json.load(fh)
+    P = S.Pencil.from_workload(pen)
+    res = S.simm_run(P, f, S.params_from_dict(params, flags=S.SIMM_FLAG_PROJECT, precision=S.SIMM_PREC_MIXED))
+    ties = _run_matches_golden(S, res, gold)
+    say(f"  ties {ties}; refinement {res.refine}")
+    assert res.refine["solves"] > 0 and res.refine["max_eta"] <= 1e-12
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLDEN, "cfg3_small_oracle.json")), reason="no stored run")
+def test_run_mixed_cfg3_small_matches_oracle_and_fp64(S):
+    """The reduced mixed-precision workload (n = 20,000, half-bandwidth 64, m = 120, 32
+    Gauss points per edge, 17 levels): FP64 and mixed runs both equal the oracle's squares,
+    shifts, decisions and clusters; the Ritz eigenvalue of every cluster of the mixed run
+    is within 1e-8 (relative) of the FP64 run's."""
+    pen, f, params = make_workload("cfg3_small")
+    with open(os.path.join(GOLDEN, "cfg3_small_oracle.json")) as fh:
+        gold = json.load(fh)
+    P = S.Pencil.from_workload(pen)
+    say("run", "cfg3_small FP64")
+    r64 = S.simm_run(P, f, S.params_from_dict(params))
+    say("run", "cfg3_small mixed")
+    rmx = S.simm_run(P, f, S.params_from_dict(params, flags=S.SIMM_FLAG_PROJECT, precision=S.SIMM_PREC_MIXED))
+    t64 = _run_matches_golden(S, r64, gold)
+    tmx = _run_matches_golden(S, rmx, gold)
+    ok = np.isfinite(r64.lam_ritz) & np.isfinite(rmx.lam_ritz)
+    err = np.abs(rmx.lam_ritz[ok] - r64.lam_ritz[ok]) / np.maximum(np.abs(r64.lam_ritz[ok]), 1e-300)
+    say(f"  ties {t64}/{tmx}; refinement {rmx.refine}; {int(ok.sum())} Ritz eigenvalues, max rel. difference "
+        f"mixed vs FP64 {err.max() if err.size else 0.0:.2e}")
+    assert np.array_equal(np.isfinite(r64.lam_ritz), np.isfinite(rmx.lam_ritz))
+    assert err.size == 0 or err.max() <= 1e-8
+    assert rmx.refine["max_eta"] <= 1e-12

@@ -188,6 +188,84 @@ def bench_batch(args):
     print(json.dumps(out))
 
 
+def mixed_vs_fp64(S, P, fd, params, steps, warmup):
+    """The mixed-precision form (FP32 band LU, every solve refined to a backward error of
+    1e-12, BF16/FP32 projections) against the plain FP64 form on one pencil: wall time of
+    `steps` runs of each after `warmup`, region sets of every level compared, and the FP64
+    error of each eigenvalue (the Ritz value of the cluster's shift)."""
+    import numpy as np
+    import torch
+    prm64 = S.params_from_dict(params, flags=S.SIMM_FLAG_PROJECT)
+    prmmx = S.params_from_dict(params, flags=S.SIMM_FLAG_PROJECT, precision=S.SIMM_PREC_MIXED)
+    out = {}
+    res = {}
+    for name, prm in (("fp64", prm64), ("mixed", prmmx)):
+        for w in range(warmup):
+            r = S.simm_run(P, fd, prm)
+            log(f"{name} warmup {w + 1}/{warmup}: {r.ms['total']:.1f} ms")
+            del r
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            r = S.simm_run(P, fd, prm)
+            log(f"{name} step {k + 1}/{steps}: {r.ms['total']:.1f} ms (shift builds {r.ms['shift_builds']:.1f})")
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        res[name] = r
+        out[name] = {"ms_per_step": t * 1e3, "shift_build_ms": r.ms["shift_builds"], "indicator_ms": r.ms["indicators"],
+                     "projection_ms": r.ms["projection"], "resolvent_solves_per_s": r.counters["quadrature_systems"] / t,
+                     "shifts": r.n_shifts, "levels": r.K, "clusters": int(len(r.lam))}
+    a, b = res["fp64"], res["mixed"]
+    same = a.K == b.K and all(np.array_equal(x.keys, y.keys) and np.array_equal(x.decision, y.decision)
+                              and np.array_equal(x.shift, y.shift) for x, y in zip(a.levels, b.levels))
+    ok = np.isfinite(a.lam_ritz) & np.isfinite(b.lam_ritz)
+    err = (np.abs(b.lam_ritz[ok] - a.lam_ritz[ok]) / np.abs(a.lam_ritz[ok])) if same else np.array([np.inf])
+    out["region_sets_equal"] = bool(same)
+    out["clusters_equal"] = bool(same and np.array_equal(a.lam, b.lam))
+    out["eigenvalue_fp64_rel_err"] = {"max": float(err.max()) if err.size else 0.0,
+                                      "median": float(np.median(err)) if err.size else 0.0,
+                                      "count": int(err.size),
+                                      "per_eigenvalue": [float(e) for e in err]}
+    out["refinement"] = b.refine
+    out["speedup_vs_plain_fp64"] = out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"]
+    return out
+
+
+def bench_mixed(args):
+    """Mixed-precision workload: the metric's speedup clause (plain FP64 form over the
+    mixed-precision form at h0 = 1e-6, equal region sets)."""
+    import numpy as np
+    import torch
+    from workloads import load_config, make_workload
+    import paper_2006_16117_amd.simm as S
+    assert torch.cuda.is_available(), "needs a ROCm GPU"
+    cfg = load_config(args.workload)
+    pen, f, params = make_workload(args.workload)
+    log("workload", args.workload, "n =", pen.n)
+    P = S.Pencil.from_workload(pen)
+    fd = torch.from_numpy(np.ascontiguousarray(f)).to("cuda:0")
+    mx = mixed_vs_fp64(S, P, fd, params, args.steps, args.warmup)
+    out = {
+        "metric": METRIC,
+        "value": mx["mixed"]["resolvent_solves_per_s"],
+        "unit": "resolvent solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mx["mixed"]["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 factor + f64 refinement",
+        "data": "synthetic",
+        "speedup_vs_plain_fp64": mx["speedup_vs_plain_fp64"],
+        "config": {"workload": cfg["description"], "n": pen.n, "kl": pen.kl_a, "m": params["m"],
+                   "gauss_per_edge": params["gauss_per_edge"], "h0": params["h0"]},
+        "mixed_vs_fp64": mx,
+    }
+    print(json.dumps(out))
+
+
 def bench_gradient(args):
     """Differentiation workload: one SIM-M run of A(p) = A0 + p A1 fixes the squares
     (admissible squares of the last level) and their shifts; the timed step is one
@@ -306,6 +384,8 @@ def main():
     ap.add_argument("--batch-lookahead", type=int, default=0,
                     help="look-ahead of each run in the batched form (0: the batch default, one at a time)")
     ap.add_argument("--no-sequential", action="store_true", help="batched form only (no separate runs)")
+    ap.add_argument("--no-speedup", action="store_true",
+                    help="skip the metric's speedup clause (mixed precision vs plain FP64 on the n = 250,000 workload)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (three times): the reference "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE to HBM bytes")
@@ -336,6 +416,8 @@ def main():
         return bench_batch(args)
     if "differentiation" in load_config(args.workload):
         return bench_gradient(args)
+    if args.workload.startswith("cfg3"):
+        return bench_mixed(args)
 
     assert torch.cuda.is_available(), "needs a ROCm GPU"
     dev = torch.device("cuda:0")
@@ -528,6 +610,18 @@ def main():
             "multiplicities": np.bincount(mult).tolist(),
         }
         log(f"multiplicities: k = {args.mult_k}, {len(mult)} clusters in {mms:.1f} ms")
+    if not args.no_speedup:
+        # the metric's third clause: plain FP64 form over the mixed-precision form at
+        # h0 = 1e-6 on the n = 250,000 workload (one run of each after one warm-up)
+        pen3, f3, params3 = make_workload("cfg3")
+        log("speedup clause: workload cfg3, n =", pen3.n)
+        P3 = S.Pencil.from_workload(pen3)
+        fd3 = torch.from_numpy(np.ascontiguousarray(f3)).to(dev)
+        mx = mixed_vs_fp64(S, P3, fd3, params3, 1, 1)
+        out["speedup_vs_plain_fp64"] = mx["speedup_vs_plain_fp64"]
+        mx["workload"] = load_config("cfg3")["description"]
+        out["mixed_vs_fp64"] = mx
+        del P3, fd3
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
         out["cpu_baseline"] = cpu_baseline(pen, f, params, last.n_shifts, n_sq, n_qp)

@@ -306,18 +306,31 @@ simm_status simm_project_noalloc(simm_shift s, const double* Y, int64_t c, doubl
 simm_status simm_run(simm_pencil p, const simm_params* params, const double* f, int32_t f_mem,
                      void* hip_stream, simm_result* out);
 
-/* Batched form: simm_run on `count` independent pencils (sizes may differ), with
- * up to `workers` runs in flight at once, each on a non-blocking stream of its
- * own, so that the small launches of different pencils share the GPU.  params and
- * f hold one entry per pencil (f[i]: n_i complex values, host or device per
- * f_mem); out receives one result per pencil (caller destroys them).  Each run
- * is the same computation as a separate simm_run (identical results); a
- * lookahead of 0 counts as 1 here, the runs in flight already sharing the GPU's
- * queues.  On any
- * failure every result is destroyed and the first failing pencil's status is
- * returned, with its index in simm_last_error. */
+/* Batched form: simm_run on `count` independent pencils (sizes may differ), with the
+ * same results as `count` separate runs.  Steps 1-3 (the shifts and the level-1 cells) of
+ * up to `workers` pencils run in flight at once, each on a non-blocking stream of its own
+ * (a lookahead of 0 counts as 1 here, the runs in flight already sharing the queues).
+ * Then the levels of all pencils are evaluated together (Sec. 3.3: all squares of a
+ * level at once): per level one persistent indicator launch over the squares of every
+ * pencil and one grouped FP64 projection over every (pencil, shift), each a captured HIP
+ * graph replayed per level (and per round of the shift fallback), with launch shapes
+ * picked by timed replays and cached per shape class (simm_batch_tuning).  Pencils whose
+ * gauss_per_edge, m, flags or precision differ from the first pencil's take their levels
+ * one pencil at a time.  params and f hold one entry per pencil (f[i]: n_i complex values,
+ * host or device per f_mem); out receives one result per pencil (caller destroys them).
+ * With SIMM_FLAG_RELEASE_FACTORS each pencil's factors are freed after its shifts are
+ * built (the bases after the levels).  simm_result_stats reports, per pencil, the time
+ * of its shift builds plus the whole batch's level phase.  On any failure every result
+ * is destroyed and the first failing pencil's status is returned, with its index in
+ * simm_last_error. */
 simm_status simm_run_batch(const simm_pencil* pencils, const simm_params* params, const double* const* f,
                            int32_t f_mem, int32_t count, int32_t workers, simm_result* out);
+
+/* Launch shapes the batched form's autotuner has picked in this process: the number of
+ * cached shape classes (entries), timed tuning rounds so far (trials), and the chosen
+ * workgroup counts of the indicator (ind_grid) and projection (proj_grid) launches, up to
+ * cap of each (any pointer may be NULL). */
+simm_status simm_batch_tuning(int64_t* entries, int64_t* trials, int32_t* ind_grid, int32_t* proj_grid, int64_t cap);
 
 /* Multiplicities of the eigenvalues of a finished run (Sec. 3.4).  For every shift
  * that one of the clusters' level-K squares was tested with, k Krylov spaces

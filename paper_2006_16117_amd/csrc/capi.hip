@@ -15,6 +15,7 @@
 #include <functional>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -103,6 +104,9 @@ struct simm_shift_s {
     RefinePencil rpen{};
     RefineState rst{};
     void* ref_mem = nullptr;
+    bool mixed_stats_saved = false;   // refinement counters taken before the factor was freed
+    long long saved_stats[2] = {0, 0};
+    double saved_eta = 0.0;
     std::vector<cplx> H_host;   // (m_eff+1) x m_eff column-major
     std::vector<cplx> ritz;     // sigma + 1/theta
     bool borrowed = false;      // owned by a simm_result
@@ -131,6 +135,26 @@ struct simm_shift_s {
         V = nullptr;
         spike = SpikeFactor{};
         factor_borrowed = true;   // nothing left to free
+    }
+    // frees the factor and its sweep data, keeping the Krylov basis (for the projections)
+    void release_factor() {
+        if (factor_borrowed) return;
+        release_device(spike.mem);
+        release_device(AB);
+        release_device(ipiv);
+        release_device(LP);
+        release_device(AB32);
+        release_device(LP32);
+        release_device(ref_mem);
+        spike = SpikeFactor{};
+        AB = nullptr;
+        ipiv = nullptr;
+        LP = nullptr;
+        AB32 = nullptr;
+        LP32 = nullptr;
+        ref_mem = nullptr;
+        rst = RefineState{};
+        mixed_stats_saved = true;
     }
     bool has_factor() const { return (AB != nullptr || AB32 != nullptr) && V != nullptr; }
     // the factor's data for a Krylov space built on it by another (borrowing) shift
@@ -1005,27 +1029,20 @@ __global__ void k_gather_sums(const cplx* sums, int m_sums, const int64_t* regs,
     for (int i = threadIdx.x; i < m_sums; i += blockDim.x) Y[col * m_sums + i] = sums[(2 * r + w) * m_sums + i];
 }
 
-simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hipStream_t st, simm_result_s* R) {
+// A square of the current level and the shift it is tested with (index into the run's shifts).
+struct Sq {
+    int64_t ix, iy;
+    int s;
+};
+
+// Steps 1-3 of the SIM-M algorithm (Sec. 3.5): the first shift at the centre of R, the
+// level-1 cells and their shifts.  Leaves the shifts in R and the level-1 squares
+// (cell, associated shift) in `cur`.
+simm_status associate(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hipStream_t st, simm_result_s* R,
+                      const Rule& rule, KernelClock* clk, std::vector<Sq>& cur) {
     int nx, ny, K;
     SIMM_TRY(validate_params(prm, p->n, &nx, &ny, &K));
-    R->K = K;
-    R->prm = *prm;
-    R->pencil = p;
-    Rule rule;
-    SIMM_TRY(rule.make(prm->gauss_per_edge, st));
     const int m = prm->m;
-    const bool do_proj = (prm->flags & SIMM_FLAG_PROJECT) != 0;
-    const int64_t maxreg = prm->max_regions_per_level > 0 ? prm->max_regions_per_level : ((int64_t)1 << 22);
-    KernelClock clock;
-    clock.st = st;
-    KernelClock* clk = (prm->flags & SIMM_FLAG_KERNEL_TIMING) ? &clock : nullptr;
-    struct Collect {
-        KernelClock* c;
-        simm_result_s* R;
-        ~Collect() {
-            if (c) c->collect(R->kms, R->kcnt);
-        }
-    } collect_at_exit{clk, R};
     std::vector<simm_shift_s*> shifts;
     auto commit = [&](std::unique_ptr<simm_shift_s> s) {
         s->borrowed = true;
@@ -1290,14 +1307,22 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
         assoc[c] = chosen;
     }
     drop_all();
-
-    // steps 4-5: level loop
-    struct Sq {
-        int64_t ix, iy;
-        int s;
-    };
-    std::vector<Sq> cur;
+    cur.clear();
     for (int64_t c = 0; c < ncell; ++c) cur.push_back({cells[c].first, cells[c].second, assoc[c]});
+    return SIMM_OK;
+}
+
+// Steps 4-5 (Sec. 3.5): the levels of one pencil from its level-1 squares; every
+// square keeps its parent's shift unless that one does not resolve it (then the other
+// shifts nearest-first), and marked squares are split into four.
+simm_status level_loop(simm_pencil_s* p, const simm_params* prm, hipStream_t st, simm_result_s* R, const Rule& rule,
+                       KernelClock* clk, std::vector<Sq> cur) {
+    const int K = R->K;
+    const int m = prm->m;
+    const bool do_proj = (prm->flags & SIMM_FLAG_PROJECT) != 0;
+    const int64_t maxreg = prm->max_regions_per_level > 0 ? prm->max_regions_per_level : ((int64_t)1 << 22);
+    std::vector<simm_shift_s*> shifts;
+    for (auto& sh : R->shifts) shifts.push_back(sh.get());
     const int m_sums = m;
     DevBuf sums_buf, sums_fb, Ybuf, nrm_buf, scr_buf, idx_buf;
     const int64_t n = p->n;
@@ -1456,7 +1481,13 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
         }
     }
 
-    // steps 6-7: clusters of the marked level-K squares
+    return SIMM_OK;
+}
+
+// Steps 6-7 (Sec. 3.5): the marked level-K squares merged into 8-connected clusters.
+void make_clusters(simm_result_s* R) {
+    const simm_params* prm = &R->prm;
+    const int K = R->K;
     const LevelRec& last = R->levels.back();
     std::map<std::pair<int64_t, int64_t>, int64_t> pos;
     std::vector<int64_t> marked;
@@ -1520,8 +1551,20 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
         }
         R->clusters.push_back(cr);
     }
+}
+
+// Refinement counters of the mixed-precision shifts, then the large per-shift data freed
+// if asked for.
+simm_status finish_run(simm_result_s* R, hipStream_t st) {
+    const simm_params* prm = &R->prm;
     for (auto& sh : R->shifts) {
         if (!sh->mixed) continue;
+        if (sh->mixed_stats_saved) {
+            R->refine_solves += sh->saved_stats[0];
+            R->refine_corrections += sh->saved_stats[1];
+            R->refine_max_eta = std::max(R->refine_max_eta, sh->saved_eta);
+            continue;
+        }
         long long stats[2] = {0, 0};
         unsigned long long eta_bits = 0;
         SIMM_HIP_TRY(hipMemcpyAsync(stats, sh->rst.stats, sizeof(stats), hipMemcpyDeviceToHost, st));
@@ -1536,6 +1579,575 @@ simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hip
     if (prm->flags & SIMM_FLAG_RELEASE_FACTORS) {
         SIMM_HIP_TRY(hipStreamSynchronize(st));
         for (auto& sh : R->shifts) sh->release_large();
+    }
+    return SIMM_OK;
+}
+
+simm_status run(simm_pencil_s* p, const simm_params* prm, const cplx* f_dev, hipStream_t st, simm_result_s* R) {
+    int nx, ny, K;
+    SIMM_TRY(validate_params(prm, p->n, &nx, &ny, &K));
+    R->K = K;
+    R->prm = *prm;
+    R->pencil = p;
+    Rule rule;
+    SIMM_TRY(rule.make(prm->gauss_per_edge, st));
+    KernelClock clock;
+    clock.st = st;
+    KernelClock* clk = (prm->flags & SIMM_FLAG_KERNEL_TIMING) ? &clock : nullptr;
+    struct Collect {
+        KernelClock* c;
+        simm_result_s* R;
+        ~Collect() {
+            if (c) c->collect(R->kms, R->kcnt);
+        }
+    } collect_at_exit{clk, R};
+    std::vector<Sq> cur;
+    SIMM_TRY(associate(p, prm, f_dev, st, R, rule, clk, cur));
+    SIMM_TRY(level_loop(p, prm, st, R, rule, clk, std::move(cur)));
+    make_clusters(R);
+    return finish_run(R, st);
+}
+
+// ---------------------------------------------------------------------------
+// Batched form, level by level (Sec. 3.3: all squares of a level are evaluated
+// together): every pencil's shifts are built first (steps 1-3, pencils in flight on
+// streams of their own); then each level of all pencils is one persistent indicator
+// launch and one grouped projection, each a captured graph replayed per level.
+// ---------------------------------------------------------------------------
+
+// Launch shapes picked by timed replays of the captured graphs, per shape class
+// (a process-wide cache: the candidates give identical results, only the time differs).
+struct Autotune {
+    std::mutex mu;
+    std::map<std::tuple<int, int, int>, int> ind;    // (m, g, log2 rows) -> workgroups
+    std::map<std::tuple<int, int>, int> proj;        // (m, log2 tiles) -> workgroups
+    int64_t trials = 0;
+};
+Autotune g_tune;
+
+int log2_bucket(int64_t x) {
+    int b = 0;
+    while (((int64_t)1 << b) < x && b < 62) ++b;
+    return b;
+}
+
+// host-side table of a graph-captured stream segment
+struct Graph {
+    hipGraphExec_t exec = nullptr;
+    ~Graph() { reset(); }
+    void reset() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+    }
+    simm_status capture(hipStream_t st, const std::function<simm_status()>& body) {
+        reset();
+        hipGraph_t g = nullptr;
+        SIMM_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        const simm_status rc = body();
+        const hipError_t e = hipStreamEndCapture(st, &g);
+        if (rc != SIMM_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) {
+            set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+            return SIMM_EHIP;
+        }
+        const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            exec = nullptr;
+            set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+            return SIMM_EHIP;
+        }
+        return SIMM_OK;
+    }
+    simm_status launch(hipStream_t st) {
+        SIMM_HIP_TRY(hipGraphLaunch(exec, st));
+        return SIMM_OK;
+    }
+};
+
+struct GatherDesc {           // Y(:, col) = sums(:, src[col]) for col < ncols[0]
+    const cplx* sums;
+    int64_t m_sums;
+    const int64_t* src;
+    const int64_t* ncols;
+    cplx* Y;
+};
+
+__global__ void k_gather_cols(const GatherDesc* __restrict__ dp) {
+    const GatherDesc d = *dp;
+    const int64_t nc = *d.ncols;
+    for (int64_t col = blockIdx.x; col < nc; col += gridDim.x) {
+        const int64_t s = d.src[col];
+        for (int i = threadIdx.x; i < d.m_sums; i += blockDim.x) d.Y[col * d.m_sums + i] = d.sums[s * d.m_sums + i];
+    }
+}
+
+// The evaluation of a list of rows (level, ix, iy, global shift, pencil) in persistent
+// launches, with buffers that grow by doubling; the graph is captured again when they do
+// (its kernel arguments point at them) and once per tuned launch shape.
+struct IndEval {
+    const ShiftDev* shifts = nullptr;
+    const IndicatorParams* geo = nullptr;
+    RuleDev rule{};
+    int mmax = 1, m_sums = 1, g = 1;
+    int64_t cap = 0;
+    void* mem = nullptr;              // rows, count, outputs, sums
+    int64_t* rows = nullptr;
+    int64_t* nrows = nullptr;
+    double* out = nullptr;            // 5 x cap
+    uint8_t* dec = nullptr;
+    cplx* sums = nullptr;             // cap x 2 x m_sums
+    Graph graph;
+    int grid = 0;                     // launch shape of the captured graph
+    ~IndEval() { (void)hipFree(mem); }
+    simm_status ensure(int64_t N) {
+        if (N <= cap) return SIMM_OK;
+        int64_t c = std::max<int64_t>(cap, 1024);
+        while (c < N) c *= 2;
+        (void)hipFree(mem);
+        mem = nullptr;
+        graph.reset();
+        grid = 0;
+        const size_t bytes = sizeof(int64_t) * (size_t)(5 * c + 64) + sizeof(double) * 5 * (size_t)c + (size_t)c + 256 +
+                             sizeof(cplx) * (size_t)c * 2 * m_sums + 1024;
+        SIMM_HIP_TRY(hipMalloc(&mem, bytes));
+        char* p = reinterpret_cast<char*>(mem);
+        auto take = [&](size_t b) {
+            char* r = p;
+            p += (b + 255) & ~(size_t)255;
+            return r;
+        };
+        rows = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * 5 * (size_t)c));
+        nrows = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * 8));
+        out = reinterpret_cast<double*>(take(sizeof(double) * 5 * (size_t)c));
+        dec = reinterpret_cast<uint8_t*>(take((size_t)c));
+        sums = reinterpret_cast<cplx*>(take(sizeof(cplx) * (size_t)c * 2 * m_sums));
+        cap = c;
+        return SIMM_OK;
+    }
+    simm_status capture(int G, hipStream_t st) {
+        grid = G;
+        return graph.capture(st, [&]() {
+            return indicators_persist(shifts, mmax, rows, nrows, geo, rule, G, out, out + cap, out + 2 * cap,
+                                      out + 3 * cap, out + 4 * cap, dec, sums, m_sums, st);
+        });
+    }
+    // evaluates rows[0 .. N) (host rows, 5 per square); results in host vectors
+    simm_status run(const std::vector<int64_t>& hrows, hipStream_t st, EvalOut& eo) {
+        const int64_t N = (int64_t)hrows.size() / 5;
+        eo.indicator.assign(N, 0);
+        eo.rho.assign(N, 0);
+        eo.nsf.assign(N, 0);
+        eo.nsc.assign(N, 0);
+        eo.Tf.assign(N, 0);
+        eo.decision.assign(N, 0);
+        if (N == 0) return SIMM_OK;
+        SIMM_TRY(ensure(N));
+        SIMM_HIP_TRY(hipMemcpyAsync(rows, hrows.data(), sizeof(int64_t) * hrows.size(), hipMemcpyHostToDevice, st));
+        SIMM_HIP_TRY(hipMemcpyAsync(nrows, &N, sizeof(int64_t), hipMemcpyHostToDevice, st));
+        // launch shape: cached per (m, g, log2 N), else the fastest of a few timed replays
+        const auto key = std::make_tuple(mmax, g, log2_bucket(N));
+        int G = 0;
+        {
+            std::lock_guard<std::mutex> lk(g_tune.mu);
+            auto it = g_tune.ind.find(key);
+            if (it != g_tune.ind.end()) G = it->second;
+        }
+        if (G == 0) {
+            float best = 1e30f;
+            for (int cand : {256, 512, 1024, 2048}) {
+                if (cand > 4 * N && cand > 256) break;
+                SIMM_TRY(capture(cand, st));
+                hipEvent_t a, b;
+                SIMM_HIP_TRY(hipEventCreate(&a));
+                SIMM_HIP_TRY(hipEventCreate(&b));
+                SIMM_HIP_TRY(hipEventRecord(a, st));
+                SIMM_TRY(graph.launch(st));
+                SIMM_HIP_TRY(hipEventRecord(b, st));
+                SIMM_HIP_TRY(hipEventSynchronize(b));
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, a, b);
+                (void)hipEventDestroy(a);
+                (void)hipEventDestroy(b);
+                if (ms < best) {
+                    best = ms;
+                    G = cand;
+                }
+            }
+            std::lock_guard<std::mutex> lk(g_tune.mu);
+            g_tune.ind[key] = G;
+            g_tune.trials += 1;
+        }
+        if (grid != G || !graph.exec) SIMM_TRY(capture(G, st));
+        SIMM_TRY(graph.launch(st));
+        std::vector<double> host(5 * (size_t)cap);
+        for (int q = 0; q < 5; ++q)
+            SIMM_HIP_TRY(hipMemcpyAsync(host.data() + (size_t)q * N, out + (size_t)q * cap, sizeof(double) * N,
+                                        hipMemcpyDeviceToHost, st));
+        SIMM_HIP_TRY(hipMemcpyAsync(eo.decision.data(), dec, N, hipMemcpyDeviceToHost, st));
+        SIMM_HIP_TRY(hipStreamSynchronize(st));
+        for (int64_t r = 0; r < N; ++r) {
+            eo.indicator[r] = host[r];
+            eo.rho[r] = host[N + r];
+            eo.nsf[r] = host[2 * N + r];
+            eo.nsc[r] = host[3 * N + r];
+            eo.Tf[r] = host[4 * N + r];
+        }
+        return SIMM_OK;
+    }
+};
+
+// Grouped projection of a level: gather of the sums into Y, X_g = V_g Y_g column norms
+// for every (pencil, shift) group, as one captured graph over device tables.
+struct ProjEval {
+    void* tab = nullptr;              // GatherDesc, counts, ProjGroup table
+    GatherDesc* desc = nullptr;
+    int64_t* counts = nullptr;        // [0] columns, [1] groups
+    ProjGroup* groups = nullptr;
+    int64_t gcap = 0;
+    DevBuf src, Y, scr, norms;
+    Graph graph;
+    int grid = 0, gz = 0;
+    ~ProjEval() { (void)hipFree(tab); }
+    simm_status capture(int G, hipStream_t st) {
+        grid = G;
+        gz = (int)std::min<int64_t>(gcap, 64);
+        return graph.capture(st, [&]() {
+            hipLaunchKernelGGL(k_gather_cols, dim3(1024), dim3(128), 0, st, (const GatherDesc*)desc);
+            SIMM_HIP_TRY(hipGetLastError());
+            return project_groups(groups, counts + 1, G, gz, st);
+        });
+    }
+};
+
+// One pencil of a batch between the phases.
+struct BatchItem {
+    simm_pencil_s* p = nullptr;
+    simm_params prm{};
+    std::unique_ptr<simm_result_s> R;
+    std::vector<Sq> cur;
+    simm_status rc = SIMM_OK;
+    std::string msg;
+    int64_t soff = 0;                 // first global shift index
+};
+
+simm_status run_batch_levels(std::vector<BatchItem>& items, hipStream_t st) {
+    const int nb = (int)items.size();
+    if (nb == 0) return SIMM_OK;
+    const simm_params& p0 = items[0].prm;
+    const int m = p0.m, g = p0.gauss_per_edge;
+    // global shift table and per-pencil geometry
+    std::vector<ShiftDev> sd;
+    std::vector<IndicatorParams> geo;
+    int mmax = 1, Kmax = 0;
+    for (auto& it : items) {
+        it.soff = (int64_t)sd.size();
+        for (auto& sh : it.R->shifts) {
+            sd.push_back(shift_dev(sh.get()));
+            mmax = std::max(mmax, sh->m_eff);
+        }
+        IndicatorParams ip;
+        ip.x0 = it.prm.x0;
+        ip.y0 = it.prm.y0;
+        ip.w1 = (it.prm.x1 - it.prm.x0) / it.prm.n1;
+        ip.eps0 = it.prm.eps0;
+        ip.delta0 = it.prm.delta0;
+        ip.tau = it.prm.tau;
+        geo.push_back(ip);
+        Kmax = std::max(Kmax, it.R->K);
+    }
+    DevBuf tables;
+    const size_t sd_bytes = (sizeof(ShiftDev) * sd.size() + 255) & ~(size_t)255;
+    SIMM_TRY(tables.alloc(sd_bytes + sizeof(IndicatorParams) * geo.size() + 256, st));
+    ShiftDev* sdd = tables.as<ShiftDev>();
+    IndicatorParams* geod = reinterpret_cast<IndicatorParams*>(tables.as<char>() + sd_bytes);
+    SIMM_HIP_TRY(hipMemcpyAsync(sdd, sd.data(), sizeof(ShiftDev) * sd.size(), hipMemcpyHostToDevice, st));
+    SIMM_HIP_TRY(hipMemcpyAsync(geod, geo.data(), sizeof(IndicatorParams) * geo.size(), hipMemcpyHostToDevice, st));
+    Rule rule;
+    SIMM_TRY(rule.make(g, st));
+    IndEval main_eval, fb_eval;
+    for (IndEval* e : {&main_eval, &fb_eval}) {
+        e->shifts = sdd;
+        e->geo = geod;
+        e->rule = rule.dev;
+        e->mmax = mmax;
+        e->m_sums = m;
+        e->g = g;
+    }
+    ProjEval pe;
+    const bool do_proj = (p0.flags & SIMM_FLAG_PROJECT) != 0;
+    const bool mixed_proj = (p0.flags & SIMM_FLAG_MIXED_PROJECT) || p0.precision == SIMM_PREC_MIXED;
+    for (int k = 1; k <= Kmax; ++k) {
+        // rows of every pencil that has this level, pencil by pencil
+        std::vector<int64_t> rows, first(nb + 1, 0);
+        for (int i = 0; i < nb; ++i) {
+            auto& it = items[i];
+            first[i] = (int64_t)rows.size() / 5;
+            if (k > it.R->K) continue;
+            const int64_t maxreg =
+                it.prm.max_regions_per_level > 0 ? it.prm.max_regions_per_level : ((int64_t)1 << 22);
+            if ((int64_t)it.cur.size() > maxreg) {
+                char msg[128];
+                std::snprintf(msg, sizeof msg, "pencil %d: level %d holds %lld squares (limit %lld)", i, k,
+                              (long long)it.cur.size(), (long long)maxreg);
+                set_error(msg);
+                return SIMM_ELIMIT;
+            }
+            for (auto& q : it.cur) rows.insert(rows.end(), {(int64_t)k, q.ix, q.iy, it.soff + q.s, (int64_t)i});
+        }
+        first[nb] = (int64_t)rows.size() / 5;
+        const int64_t N = first[nb];
+        EvalOut eo;
+        SIMM_TRY(main_eval.run(rows, st, eo));
+        std::vector<int> used((size_t)N);
+        for (int i = 0; i < nb; ++i)
+            for (int64_t r = first[i]; r < first[i + 1]; ++r) used[r] = items[i].cur[r - first[i]].s;
+        // fallback: other shifts of the same pencil nearest-first, all pencils' rounds together
+        std::vector<int64_t> pend;
+        std::map<int64_t, std::vector<int>> cand;
+        for (int i = 0; i < nb; ++i) {
+            auto& it = items[i];
+            std::vector<simm_shift_s*> shv;
+            for (auto& sh : it.R->shifts) shv.push_back(sh.get());
+            for (int64_t r = first[i]; r < first[i + 1]; ++r)
+                if (eo.decision[r] == SIMM_UNRESOLVED) {
+                    pend.push_back(r);
+                    const Sq& q = it.cur[r - first[i]];
+                    cand[r] = shift_order(shv, cell_center(&it.prm, k, q.ix, q.iy), q.s);
+                }
+        }
+        auto pencil_of = [&](int64_t r) {
+            return (int)(std::upper_bound(first.begin(), first.end(), r) - first.begin()) - 1;
+        };
+        for (size_t round = 0; !pend.empty(); ++round) {
+            std::vector<int64_t> tryr, trows;
+            for (int64_t r : pend) {
+                if (round < cand[r].size()) {
+                    const int i = pencil_of(r);
+                    tryr.push_back(r);
+                    trows.insert(trows.end(), {(int64_t)k, rows[5 * r + 1], rows[5 * r + 2],
+                                               items[i].soff + cand[r][round], (int64_t)i});
+                }
+            }
+            if (tryr.empty()) break;
+            EvalOut e2;
+            SIMM_TRY(fb_eval.run(trows, st, e2));
+            std::vector<int64_t> still;
+            for (size_t q = 0; q < tryr.size(); ++q) {
+                const int64_t r = tryr[q];
+                if (e2.decision[q] != SIMM_UNRESOLVED) {
+                    eo.indicator[r] = e2.indicator[q];
+                    eo.rho[r] = e2.rho[q];
+                    eo.nsf[r] = e2.nsf[q];
+                    eo.nsc[r] = e2.nsc[q];
+                    eo.Tf[r] = e2.Tf[q];
+                    eo.decision[r] = e2.decision[q];
+                    used[r] = (int)(trows[5 * q + 3] - items[pencil_of(r)].soff);
+                    if (do_proj)
+                        SIMM_HIP_TRY(hipMemcpyAsync(main_eval.sums + (size_t)r * 2 * m, fb_eval.sums + q * 2 * m,
+                                                    sizeof(cplx) * 2 * m, hipMemcpyDeviceToDevice, st));
+                } else {
+                    still.push_back(r);
+                }
+            }
+            std::vector<int64_t> next;
+            for (int64_t r : pend) {
+                const bool tried = std::find(tryr.begin(), tryr.end(), r) != tryr.end();
+                const bool ok = tried && std::find(still.begin(), still.end(), r) == still.end();
+                if (!ok && (tried || round < cand[r].size())) next.push_back(r);
+            }
+            pend.swap(next);
+        }
+        // level records
+        for (int i = 0; i < nb; ++i) {
+            auto& it = items[i];
+            if (k > it.R->K) continue;
+            const int64_t n0 = first[i], Ni = first[i + 1] - n0;
+            it.R->counters[0] += Ni * 12 * (int64_t)it.prm.gauss_per_edge;
+            it.R->counters[1] += Ni;
+            LevelRec L;
+            L.ix.resize(Ni);
+            L.iy.resize(Ni);
+            L.shift.resize(Ni);
+            L.full_indicator.assign(Ni, NAN);
+            for (int64_t r = 0; r < Ni; ++r) {
+                L.ix[r] = it.cur[r].ix;
+                L.iy[r] = it.cur[r].iy;
+                L.shift[r] = used[n0 + r];
+            }
+            L.indicator.assign(eo.indicator.begin() + n0, eo.indicator.begin() + n0 + Ni);
+            L.rho_max.assign(eo.rho.begin() + n0, eo.rho.begin() + n0 + Ni);
+            L.nsf.assign(eo.nsf.begin() + n0, eo.nsf.begin() + n0 + Ni);
+            L.nsc.assign(eo.nsc.begin() + n0, eo.nsc.begin() + n0 + Ni);
+            L.Tf.assign(eo.Tf.begin() + n0, eo.Tf.begin() + n0 + Ni);
+            L.decision.assign(eo.decision.begin() + n0, eo.decision.begin() + n0 + Ni);
+            it.R->levels.push_back(std::move(L));
+        }
+        // a9: column norms of X = V_m Y for every (pencil, shift) group of the level
+        if (do_proj && N > 0) {
+            std::vector<ProjGroup> gt;
+            std::vector<int64_t> srccol;
+            std::vector<std::pair<int, std::vector<int64_t>>> gsq;   // (pencil, rows) per group
+            int64_t scr_need = 0;
+            for (int i = 0; i < nb; ++i) {
+                auto& it = items[i];
+                if (k > it.R->K) continue;
+                std::vector<std::vector<int64_t>> by((size_t)it.R->shifts.size());
+                for (int64_t r = first[i]; r < first[i + 1]; ++r) by[used[r]].push_back(r);
+                for (size_t s = 0; s < by.size(); ++s) {
+                    if (by[s].empty()) continue;
+                    ProjGroup pg{};
+                    pg.n = it.p->n;
+                    pg.m = it.R->shifts[s]->m_eff;
+                    pg.V = it.R->shifts[s]->V;
+                    pg.ldv = it.p->n;
+                    pg.ldy = m;
+                    pg.c = 2 * (int64_t)by[s].size();
+                    project_group_shape(pg);
+                    gt.push_back(pg);
+                    for (int64_t r : by[s]) {
+                        srccol.push_back(2 * r);
+                        srccol.push_back(2 * r + 1);
+                    }
+                    scr_need += project_scratch_elems(pg.n, pg.c);
+                    gsq.emplace_back(i, by[s]);
+                }
+            }
+            const int64_t ncol = (int64_t)srccol.size(), ng = (int64_t)gt.size();
+            if (mixed_proj) {
+                // reduced-precision projections: one launch per group (outside the graph)
+                std::vector<double> nh;
+                SIMM_TRY(pe.Y.alloc(sizeof(cplx) * (size_t)ncol * m, st));
+                SIMM_TRY(pe.src.alloc(sizeof(int64_t) * (size_t)ncol, st));
+                SIMM_HIP_TRY(hipMemcpyAsync(pe.src.p, srccol.data(), sizeof(int64_t) * ncol, hipMemcpyHostToDevice, st));
+                GatherDesc hd{main_eval.sums, m, pe.src.as<int64_t>(), nullptr, pe.Y.as<cplx>()};
+                DevBuf db;
+                SIMM_TRY(db.alloc(sizeof(GatherDesc) + sizeof(int64_t), st));
+                int64_t* ncd = reinterpret_cast<int64_t*>(db.as<char>() + sizeof(GatherDesc));
+                hd.ncols = ncd;
+                SIMM_HIP_TRY(hipMemcpyAsync(db.p, &hd, sizeof(GatherDesc), hipMemcpyHostToDevice, st));
+                SIMM_HIP_TRY(hipMemcpyAsync(ncd, &ncol, sizeof(int64_t), hipMemcpyHostToDevice, st));
+                hipLaunchKernelGGL(k_gather_cols, dim3(1024), dim3(128), 0, st, db.as<const GatherDesc>());
+                SIMM_HIP_TRY(hipGetLastError());
+                SIMM_TRY(pe.norms.alloc(sizeof(double) * (size_t)ncol, st));
+                int64_t col0 = 0;
+                const int prec = (k <= 2) ? SIMM_PROJ_BF16 : SIMM_PROJ_FP32;
+                for (auto& pg : gt) {
+                    const int64_t se = project_scratch_elems(pg.n, pg.c);
+                    SIMM_TRY(pe.scr.alloc(sizeof(double) * (size_t)se, st));
+                    SIMM_TRY(project(pg.n, pg.m, pg.V, pg.ldv, pe.Y.as<cplx>() + col0 * m, m, pg.c, nullptr,
+                                     pe.norms.as<double>() + col0, pe.scr.as<double>(), se, prec, st));
+                    col0 += pg.c;
+                }
+                nh.assign((size_t)ncol, 0.0);
+                SIMM_HIP_TRY(hipMemcpyAsync(nh.data(), pe.norms.p, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
+                SIMM_HIP_TRY(hipStreamSynchronize(st));
+                int64_t c0 = 0;
+                for (auto& gs : gsq) {
+                    LevelRec& L = items[gs.first].R->levels.back();
+                    for (size_t q = 0; q < gs.second.size(); ++q)
+                        L.full_indicator[gs.second[q] - first[gs.first]] = nh[c0 + 2 * q + 1] / nh[c0 + 2 * q];
+                    c0 += 2 * (int64_t)gs.second.size();
+                }
+            } else {
+                // buffers (pointers live in the device tables, so growth needs no new graph)
+                if (ng > pe.gcap) {
+                    (void)hipFree(pe.tab);
+                    pe.tab = nullptr;
+                    pe.graph.reset();
+                    pe.gcap = std::max<int64_t>(64, ng * 2);
+                    SIMM_HIP_TRY(hipMalloc(&pe.tab, 512 + sizeof(ProjGroup) * (size_t)pe.gcap));
+                    pe.desc = reinterpret_cast<GatherDesc*>(pe.tab);
+                    pe.counts = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(pe.tab) + 256);
+                    pe.groups = reinterpret_cast<ProjGroup*>(reinterpret_cast<char*>(pe.tab) + 512);
+                }
+                SIMM_TRY(pe.Y.alloc(sizeof(cplx) * (size_t)ncol * m, st));
+                SIMM_TRY(pe.src.alloc(sizeof(int64_t) * (size_t)ncol, st));
+                SIMM_TRY(pe.scr.alloc(sizeof(double) * (size_t)scr_need, st));
+                SIMM_TRY(pe.norms.alloc(sizeof(double) * (size_t)ncol, st));
+                int64_t col0 = 0, sc0 = 0;
+                int64_t tiles = 0;
+                for (auto& pg : gt) {
+                    pg.Y = pe.Y.as<cplx>() + col0 * m;
+                    pg.colpart = pe.scr.as<double>() + sc0;
+                    pg.part = pg.colpart + 2 * pg.gx * pg.c;
+                    pg.norms = pe.norms.as<double>() + col0;
+                    col0 += pg.c;
+                    sc0 += project_scratch_elems(pg.n, pg.c);
+                    tiles += pg.gx * pg.gy;
+                }
+                GatherDesc hd{main_eval.sums, m, pe.src.as<int64_t>(), pe.counts, pe.Y.as<cplx>()};
+                const int64_t cnt[2] = {ncol, ng};
+                SIMM_HIP_TRY(hipMemcpyAsync(pe.src.p, srccol.data(), sizeof(int64_t) * ncol, hipMemcpyHostToDevice, st));
+                SIMM_HIP_TRY(hipMemcpyAsync(pe.desc, &hd, sizeof(GatherDesc), hipMemcpyHostToDevice, st));
+                SIMM_HIP_TRY(hipMemcpyAsync(pe.counts, cnt, sizeof(cnt), hipMemcpyHostToDevice, st));
+                SIMM_HIP_TRY(hipMemcpyAsync(pe.groups, gt.data(), sizeof(ProjGroup) * ng, hipMemcpyHostToDevice, st));
+                const auto key = std::make_tuple(mmax, log2_bucket(tiles));
+                int G = 0;
+                {
+                    std::lock_guard<std::mutex> lk(g_tune.mu);
+                    auto itc = g_tune.proj.find(key);
+                    if (itc != g_tune.proj.end()) G = itc->second;
+                }
+                if (G == 0) {
+                    float best = 1e30f;
+                    for (int cand : {256, 512, 1024, 2048}) {
+                        if (cand > 8 * tiles && cand > 256) break;
+                        SIMM_TRY(pe.capture(cand, st));
+                        hipEvent_t a, b;
+                        SIMM_HIP_TRY(hipEventCreate(&a));
+                        SIMM_HIP_TRY(hipEventCreate(&b));
+                        SIMM_HIP_TRY(hipEventRecord(a, st));
+                        SIMM_TRY(pe.graph.launch(st));
+                        SIMM_HIP_TRY(hipEventRecord(b, st));
+                        SIMM_HIP_TRY(hipEventSynchronize(b));
+                        float ms = 0;
+                        (void)hipEventElapsedTime(&ms, a, b);
+                        (void)hipEventDestroy(a);
+                        (void)hipEventDestroy(b);
+                        if (ms < best) {
+                            best = ms;
+                            G = cand;
+                        }
+                    }
+                    std::lock_guard<std::mutex> lk(g_tune.mu);
+                    g_tune.proj[key] = G;
+                    g_tune.trials += 1;
+                }
+                if (pe.grid != G || !pe.graph.exec) SIMM_TRY(pe.capture(G, st));
+                SIMM_TRY(pe.graph.launch(st));
+                std::vector<double> nh((size_t)ncol);
+                SIMM_HIP_TRY(hipMemcpyAsync(nh.data(), pe.norms.p, sizeof(double) * ncol, hipMemcpyDeviceToHost, st));
+                SIMM_HIP_TRY(hipStreamSynchronize(st));
+                int64_t c0 = 0;
+                for (auto& gs : gsq) {
+                    LevelRec& L = items[gs.first].R->levels.back();
+                    for (size_t q = 0; q < gs.second.size(); ++q)
+                        L.full_indicator[gs.second[q] - first[gs.first]] = nh[c0 + 2 * q + 1] / nh[c0 + 2 * q];
+                    c0 += 2 * (int64_t)gs.second.size();
+                }
+            }
+        }
+        // children of the marked squares (each pencil's squares in (iy, ix) order)
+        for (int i = 0; i < nb; ++i) {
+            auto& it = items[i];
+            if (k >= it.R->K) continue;
+            std::vector<Sq> nxt;
+            for (int64_t r = first[i]; r < first[i + 1]; ++r) {
+                if (eo.decision[r] == SIMM_REJECTED) continue;
+                const Sq& q = it.cur[r - first[i]];
+                for (int b = 0; b < 2; ++b)
+                    for (int a = 0; a < 2; ++a) nxt.push_back({2 * q.ix + a, 2 * q.iy + b, used[r]});
+            }
+            std::stable_sort(nxt.begin(), nxt.end(), [](const Sq& u, const Sq& v) {
+                if (u.iy != v.iy) return u.iy < v.iy;
+                return u.ix < v.ix;
+            });
+            it.cur.swap(nxt);
+        }
     }
     return SIMM_OK;
 }
@@ -2466,12 +3078,14 @@ simm_status simm_run_batch(const simm_pencil* pencils, const simm_params* params
             return SIMM_EINVAL;
         }
     }
+    if (count == 0) return SIMM_OK;
+    SIMM_TRY(check_device());
     int dev = 0;
     SIMM_HIP_TRY(hipGetDevice(&dev));
+    std::vector<BatchItem> items((size_t)count);
+    // steps 1-3 of every pencil: runs in flight on streams of their own, each building its
+    // shifts one at a time unless asked for more (the runs in flight share the queues)
     std::atomic<int32_t> next{0};
-    std::vector<simm_status> rc((size_t)count, SIMM_OK);
-    std::vector<std::string> msg((size_t)count);
-    // each worker owns a non-blocking stream and takes the next pencil when free
     auto work = [&]() {
         (void)hipSetDevice(dev);
         hipStream_t st = nullptr;
@@ -2479,19 +3093,48 @@ simm_status simm_run_batch(const simm_pencil* pencils, const simm_params* params
         for (;;) {
             const int32_t i = next.fetch_add(1);
             if (i >= count) break;
+            BatchItem& it = items[(size_t)i];
+            it.p = pencils[i];
+            it.prm = params[i];
+            if (it.prm.lookahead == 0) it.prm.lookahead = 1;
+            it.R = std::make_unique<simm_result_s>();
             if (se != hipSuccess) {
-                rc[(size_t)i] = SIMM_EHIP;
-                msg[(size_t)i] = std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(se);
+                it.rc = SIMM_EHIP;
+                it.msg = std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(se);
                 continue;
             }
-            simm_result r = nullptr;
-            // the runs in flight already share the device and its queues: unless asked
-            // for, each run builds its shifts one at a time
-            simm_params prm = params[i];
-            if (prm.lookahead == 0) prm.lookahead = 1;
-            rc[(size_t)i] = simm_run(pencils[i], &prm, f[i], f_mem, st, &r);
-            if (rc[(size_t)i] == SIMM_OK) out[i] = r;
-            else msg[(size_t)i] = simm_last_error();
+            auto phase = [&]() -> simm_status {
+                int nx, ny, K;
+                SIMM_TRY(validate_params(&it.prm, it.p->n, &nx, &ny, &K));
+                it.R->K = K;
+                it.R->prm = it.prm;
+                it.R->pencil = it.p;
+                DevBuf fb;
+                const cplx* fd = nullptr;
+                SIMM_TRY(to_device_vec(f[i], f_mem, it.p->n, fb, &fd, st));
+                Rule rule;
+                SIMM_TRY(rule.make(it.prm.gauss_per_edge, st));
+                SIMM_TRY(associate(it.p, &it.prm, fd, st, it.R.get(), rule, nullptr, it.cur));
+                SIMM_HIP_TRY(hipStreamSynchronize(st));
+                if (it.prm.flags & SIMM_FLAG_RELEASE_FACTORS) {
+                    // the levels need only each shift's small data and basis
+                    for (auto& sh : it.R->shifts) {
+                        if (sh->mixed && sh->ref_mem) {
+                            unsigned long long eta_bits = 0;
+                            SIMM_HIP_TRY(hipMemcpy(sh->saved_stats, sh->rst.stats, sizeof(sh->saved_stats),
+                                                   hipMemcpyDeviceToHost));
+                            SIMM_HIP_TRY(hipMemcpy(&eta_bits, sh->rst.norms + 3, sizeof(eta_bits), hipMemcpyDeviceToHost));
+                            std::memcpy(&sh->saved_eta, &eta_bits, sizeof(double));
+                        }
+                        sh->release_factor();
+                    }
+                }
+                return SIMM_OK;
+            };
+            const auto t0 = std::chrono::steady_clock::now();
+            it.rc = phase();
+            if (it.rc != SIMM_OK) it.msg = simm_last_error();
+            it.R->ms[3] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         }
         if (se == hipSuccess) {
             release_stream_buffers(st);
@@ -2499,22 +3142,82 @@ simm_status simm_run_batch(const simm_pencil* pencils, const simm_params* params
             (void)hipStreamDestroy(st);
         }
     };
-    std::vector<std::thread> pool;
-    const int32_t nw = std::min(workers, std::max<int32_t>(count, 1));
-    g_batches.fetch_add(1);
-    for (int32_t w = 0; w < nw; ++w) pool.emplace_back(work);
-    for (auto& t : pool) t.join();
-    if (g_batches.fetch_sub(1) == 1) flush_deferred_frees();
-    for (int32_t i = 0; i < count; ++i) {
-        if (rc[(size_t)i] != SIMM_OK) {
-            for (int32_t j = 0; j < count; ++j) {
-                simm_result_destroy(out[j]);
-                out[j] = nullptr;
-            }
-            set_error("pencil " + std::to_string(i) + ": " + msg[(size_t)i]);
-            return rc[(size_t)i];
-        }
+    {
+        std::vector<std::thread> pool;
+        const int32_t nw = std::min(workers, count);
+        g_batches.fetch_add(1);
+        for (int32_t w = 0; w < nw; ++w) pool.emplace_back(work);
+        for (auto& t : pool) t.join();
+        if (g_batches.fetch_sub(1) == 1) flush_deferred_frees();
     }
+    auto fail_at = [&](int32_t i, const std::string& m) {
+        set_error("pencil " + std::to_string(i) + ": " + m);
+        return items[(size_t)i].rc;
+    };
+    for (int32_t i = 0; i < count; ++i)
+        if (items[(size_t)i].rc != SIMM_OK) return fail_at(i, items[(size_t)i].msg);
+    // steps 4-5 of all pencils together, level by level (one stream); pencils whose rule,
+    // Krylov dimension, flags or precision differ from the first take the levels one
+    // pencil at a time instead
+    hipStream_t st = nullptr;
+    SIMM_HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    struct StreamGuard {
+        hipStream_t s;
+        ~StreamGuard() {
+            release_stream_buffers(s);
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        }
+    } guard{st};
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<BatchItem> joint;
+    std::vector<int32_t> joint_idx, alone_idx;
+    for (int32_t i = 0; i < count; ++i) {
+        const simm_params& a = items[0].prm;
+        const simm_params& b = items[(size_t)i].prm;
+        if (b.m == a.m && b.gauss_per_edge == a.gauss_per_edge && b.flags == a.flags && b.precision == a.precision)
+            joint_idx.push_back(i);
+        else
+            alone_idx.push_back(i);
+    }
+    {
+        std::vector<BatchItem> js;
+        for (int32_t i : joint_idx) js.push_back(std::move(items[(size_t)i]));
+        simm_status rc = run_batch_levels(js, st);
+        for (size_t q = 0; q < joint_idx.size(); ++q) items[(size_t)joint_idx[q]] = std::move(js[q]);
+        if (rc != SIMM_OK) return rc;
+    }
+    for (int32_t i : alone_idx) {
+        BatchItem& it = items[(size_t)i];
+        Rule rule;
+        SIMM_TRY(rule.make(it.prm.gauss_per_edge, st));
+        const simm_status rc = level_loop(it.p, &it.prm, st, it.R.get(), rule, nullptr, std::move(it.cur));
+        if (rc != SIMM_OK) return fail_at(i, simm_last_error());
+    }
+    const double levels_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    for (int32_t i = 0; i < count; ++i) {
+        BatchItem& it = items[(size_t)i];
+        make_clusters(it.R.get());
+        const simm_status rc = finish_run(it.R.get(), st);
+        if (rc != SIMM_OK) return fail_at(i, simm_last_error());
+        it.R->ms[1] += levels_ms;   // the levels of the batch are shared: each run reports the whole
+        it.R->ms[3] += levels_ms;
+    }
+    for (int32_t i = 0; i < count; ++i) out[i] = items[(size_t)i].R.release();
+    return SIMM_OK;
+}
+
+simm_status simm_batch_tuning(int64_t* entries, int64_t* trials, int32_t* ind_grid, int32_t* proj_grid, int64_t cap) {
+    std::lock_guard<std::mutex> lk(g_tune.mu);
+    const int64_t ne = (int64_t)(g_tune.ind.size() + g_tune.proj.size());
+    if (entries) *entries = ne;
+    if (trials) *trials = g_tune.trials;
+    int64_t q = 0;
+    for (auto& kv : g_tune.ind)
+        if (ind_grid && q < cap) ind_grid[q++] = kv.second;
+    q = 0;
+    for (auto& kv : g_tune.proj)
+        if (proj_grid && q < cap) proj_grid[q++] = kv.second;
     return SIMM_OK;
 }
 

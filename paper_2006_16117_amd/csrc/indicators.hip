@@ -54,24 +54,26 @@ __device__ void node(double cx, double cy, double h, int e, double t, double om,
 
 }  // namespace
 
-__global__ __launch_bounds__(IND_THREADS) void k_indicators(const ShiftDev* __restrict__ shifts,
-                                                            const int64_t* __restrict__ regions, int64_t nreg,
-                                                            IndicatorParams prm, RuleDev rule, double* indicator,
-                                                            double* rho_max, double* nsf_out, double* nsc_out,
-                                                            double* Tf_out, uint8_t* decision, cplx* sums,
-                                                            int m_sums) {
-    extern __shared__ cplx smem[];
-    __shared__ cplx red[IND_WAVES][2][128];
-    __shared__ double redT[IND_WAVES], redR[IND_WAVES];
-    __shared__ cplx shat[2][128];
-    const int64_t reg = blockIdx.x;
-    if (reg >= nreg) return;
+// LDS of one square's evaluation besides the Schur factor (dynamic LDS)
+struct IndShared {
+    cplx red[IND_WAVES][2][128];
+    double redT[IND_WAVES], redR[IND_WAVES];
+    cplx shat[2][128];
+};
+
+// One (square, shift) pair, by the whole workgroup; output slot `reg`.  Every operation
+// and its order depend only on the square, the shift and the rule, so that the result
+// does not depend on how the squares are dealt to workgroups.
+__device__ __forceinline__ void eval_square(const ShiftDev& sh, int64_t level, int64_t ix, int64_t iy, int64_t reg,
+                                            const IndicatorParams& prm, const RuleDev& rule, cplx* smem,
+                                            IndShared& ls, double* indicator, double* rho_max, double* nsf_out,
+                                            double* nsc_out, double* Tf_out, uint8_t* decision, cplx* sums,
+                                            int m_sums) {
+    auto& red = ls.red;
+    auto& redT = ls.redT;
+    auto& redR = ls.redR;
+    auto& shat = ls.shat;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t level = regions[4 * reg + 0];
-    const int64_t ix = regions[4 * reg + 1];
-    const int64_t iy = regions[4 * reg + 2];
-    const int64_t si = regions[4 * reg + 3];
-    const ShiftDev sh = shifts[si];
     const int m = sh.m;
     cplx* Ts = smem;
     const int nT = m * (m + 1) / 2;
@@ -228,6 +230,42 @@ __global__ __launch_bounds__(IND_THREADS) void k_indicators(const ShiftDev* __re
     }
 }
 
+__global__ __launch_bounds__(IND_THREADS) void k_indicators(const ShiftDev* __restrict__ shifts,
+                                                            const int64_t* __restrict__ regions, int64_t nreg,
+                                                            IndicatorParams prm, RuleDev rule, double* indicator,
+                                                            double* rho_max, double* nsf_out, double* nsc_out,
+                                                            double* Tf_out, uint8_t* decision, cplx* sums,
+                                                            int m_sums) {
+    extern __shared__ cplx smem[];
+    __shared__ IndShared ls;
+    const int64_t reg = blockIdx.x;
+    if (reg >= nreg) return;
+    const ShiftDev sh = shifts[regions[4 * reg + 3]];
+    eval_square(sh, regions[4 * reg + 0], regions[4 * reg + 1], regions[4 * reg + 2], reg, prm, rule, smem, ls,
+                indicator, rho_max, nsf_out, nsc_out, Tf_out, decision, sums, m_sums);
+}
+
+// Persistent form over the squares of many pencils: rows of 5 int64 (level, ix, iy,
+// shift, geometry), the row count read from device memory (so that one launch shape,
+// e.g. inside a captured graph, serves every level), the square geometry and thresholds
+// of each pencil in geo[].  Workgroup b takes rows b, b + gridDim.x, ...
+__global__ __launch_bounds__(IND_THREADS) void k_indicators_persist(
+    const ShiftDev* __restrict__ shifts, const int64_t* __restrict__ rows, const int64_t* __restrict__ nrows,
+    const IndicatorParams* __restrict__ geo, RuleDev rule, double* indicator, double* rho_max, double* nsf_out,
+    double* nsc_out, double* Tf_out, uint8_t* decision, cplx* sums, int m_sums) {
+    extern __shared__ cplx smem[];
+    __shared__ IndShared ls;
+    const int64_t N = *nrows;
+    for (int64_t reg = blockIdx.x; reg < N; reg += gridDim.x) {
+        const int64_t* row = rows + 5 * reg;
+        const ShiftDev sh = shifts[row[3]];
+        const IndicatorParams prm = geo[row[4]];
+        eval_square(sh, row[0], row[1], row[2], reg, prm, rule, smem, ls, indicator, rho_max, nsf_out, nsc_out,
+                    Tf_out, decision, sums, m_sums);
+        __syncthreads();   // LDS is reused by the next row
+    }
+}
+
 // Fine-rule solutions of one square (the 2g-point rule of eq. (XLXf)): for each node
 // z_j, y_j = Q yhat_j with (I + (sigma - z_j) T) yhat_j = beta Q^H e_1, the Galerkin
 // solution of eq. (y) in the Arnoldi basis; row j of Y (stride ldy) holds y_j.  With
@@ -311,6 +349,21 @@ simm_status fine_solutions(const ShiftDev& sh, const IndicatorParams& prm, const
     const int nf = 8 * rule.g;
     hipLaunchKernelGGL(k_fine_solutions, dim3((unsigned)((nf + IND_WAVES - 1) / IND_WAVES)), dim3(IND_THREADS), lds,
                        st, sh, prm, rule, level, ix, iy, conj_nodes ? 1 : 0, Y, ldy, cw, rho);
+    SIMM_HIP_TRY(hipGetLastError());
+    return SIMM_OK;
+}
+
+simm_status indicators_persist(const ShiftDev* shifts_dev, int mmax, const int64_t* rows, const int64_t* nrows,
+                               const IndicatorParams* geo, const RuleDev& rule, int grid, double* indicator,
+                               double* rho_max, double* nsf, double* nsc, double* Tf, uint8_t* decision, cplx* sums,
+                               int m_sums, hipStream_t st) {
+    if (mmax > 128 || (sums != nullptr && m_sums > 128)) {
+        set_error("Krylov dimension above 128");
+        return SIMM_EUNSUPPORTED;
+    }
+    const size_t lds = sizeof(cplx) * (size_t)(mmax * (mmax + 1) / 2 + 1);
+    hipLaunchKernelGGL(k_indicators_persist, dim3((unsigned)grid), dim3(IND_THREADS), lds, st, shifts_dev, rows, nrows,
+                       geo, rule, indicator, rho_max, nsf, nsc, Tf, decision, sums, m_sums);
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;
 }

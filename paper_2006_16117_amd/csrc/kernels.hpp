@@ -199,6 +199,13 @@ simm_status indicators(const ShiftDev* shifts_dev, int mmax, const int64_t* regi
                        double* nsf, double* nsc, double* Tf, uint8_t* decision, cplx* sums, int m_sums,
                        hipStream_t st);
 
+// persistent form over the squares of many pencils: rows (level, ix, iy, shift, geometry)
+// x nrows[0] (device), geo[] per geometry; grid workgroups take rows in turn
+simm_status indicators_persist(const ShiftDev* shifts_dev, int mmax, const int64_t* rows, const int64_t* nrows,
+                               const IndicatorParams* geo, const RuleDev& rule, int grid, double* indicator,
+                               double* rho_max, double* nsf, double* nsc, double* Tf, uint8_t* decision, cplx* sums,
+                               int m_sums, hipStream_t st);
+
 // ---- multiplicities (multiplicity.hip) ----
 simm_status cluster_sums(const cplx* sums, int m_sums, const int64_t* off, const int64_t* idx, int64_t ncl,
                          int mrows, cplx* Y, int64_t ldy, hipStream_t st);
@@ -233,5 +240,23 @@ simm_status project(int64_t n, int m, const cplx* V, int64_t ldv, const cplx* Y,
 simm_status project_batched(int64_t n, int m, const cplx* V, int64_t ldv, int64_t sV, const cplx* Y, int64_t ldy,
                             int64_t sY, int64_t c, cplx* X, int64_t sX, int nb, hipStream_t st);
 int64_t project_scratch_elems(int64_t n, int64_t c);
+// One product X_g = V_g Y_g of a grouped projection (column norms only; device table).
+struct ProjGroup {
+    int64_t n;
+    int m;
+    const cplx* V;
+    int64_t ldv;
+    const cplx* Y;
+    int64_t ldy;
+    int64_t c;
+    double* colpart;     // (2 gx) x c per-64-row partial sums
+    double* part;        // 32 x c
+    double* norms;       // c column norms
+    int64_t gx, gy;      // row and column blocks (project_group_shape)
+};
+void project_group_shape(ProjGroup& g);
+// every group of the device table (count ngroups[0], at most gz x ... groups), FP64, by
+// persistent launches of `grid` workgroups; colpart needs project_scratch_elems(n, c)
+simm_status project_groups(const ProjGroup* groups, const int64_t* ngroups, int grid, int gz, hipStream_t st);
 
 }  // namespace simm

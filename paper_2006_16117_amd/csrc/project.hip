@@ -56,20 +56,20 @@ constexpr int PJ_XCDS = 8;
 
 }  // namespace
 
+// LDS stages of one tile
+struct VmyShared {
+    d2 Vs[2][PJ_KC][PJ_ROWS];
+    d2 Ys[2][PJ_KC][PJ_YLD];
+};
+
+// Tile t (row block t / gy, column block t % gy) of X = V Y: the 128 x 64 block of X and
+// its per-64-row partial column norms.  Ends with a workgroup barrier.
 template <int PREC>
-__global__ __launch_bounds__(PJ_THREADS) void k_vmy(int64_t n, int m, const cplx* __restrict__ V, int64_t ldv,
-                                                    const cplx* __restrict__ Y, int64_t ldy, int64_t c,
-                                                    int64_t gx, int64_t gy, cplx* __restrict__ X,
-                                                    double* __restrict__ colpart, int64_t sV, int64_t sY, int64_t sX) {
-    // batch member blockIdx.y (strided operands; a batch has no column norms)
-    V += (int64_t)blockIdx.y * sV;
-    Y += (int64_t)blockIdx.y * sY;
-    if (X != nullptr) X += (int64_t)blockIdx.y * sX;
-    __shared__ d2 Vs[2][PJ_KC][PJ_ROWS];
-    __shared__ d2 Ys[2][PJ_KC][PJ_YLD];
-    const int64_t T = gx * gy, per = (T + PJ_XCDS - 1) / PJ_XCDS;
-    const int64_t t = (int64_t)(blockIdx.x % PJ_XCDS) * per + blockIdx.x / PJ_XCDS;
-    if (t >= T) return;   // uniform over the workgroup
+__device__ __forceinline__ void vmy_tile(int64_t n, int m, const cplx* __restrict__ V, int64_t ldv,
+                                         const cplx* __restrict__ Y, int64_t ldy, int64_t c, int64_t gy, int64_t t,
+                                         cplx* __restrict__ X, double* __restrict__ colpart, VmyShared& sm) {
+    auto& Vs = sm.Vs;
+    auto& Ys = sm.Ys;
     const int64_t rb = t / gy;
     const int64_t i0 = rb * PJ_ROWS, j0 = (t % gy) * PJ_COLS;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -220,6 +220,42 @@ __global__ __launch_bounds__(PJ_THREADS) void k_vmy(int64_t n, int m, const cplx
     }
 }
 
+template <int PREC>
+__global__ __launch_bounds__(PJ_THREADS) void k_vmy(int64_t n, int m, const cplx* __restrict__ V, int64_t ldv,
+                                                    const cplx* __restrict__ Y, int64_t ldy, int64_t c,
+                                                    int64_t gx, int64_t gy, cplx* __restrict__ X,
+                                                    double* __restrict__ colpart, int64_t sV, int64_t sY, int64_t sX) {
+    // batch member blockIdx.y (strided operands; a batch has no column norms)
+    V += (int64_t)blockIdx.y * sV;
+    Y += (int64_t)blockIdx.y * sY;
+    if (X != nullptr) X += (int64_t)blockIdx.y * sX;
+    __shared__ VmyShared sm;
+    const int64_t T = gx * gy, per = (T + PJ_XCDS - 1) / PJ_XCDS;
+    const int64_t t = (int64_t)(blockIdx.x % PJ_XCDS) * per + blockIdx.x / PJ_XCDS;
+    if (t >= T) return;   // uniform over the workgroup
+    vmy_tile<PREC>(n, m, V, ldv, Y, ldy, c, gy, t, X, colpart, sm);
+}
+
+// Persistent form over groups of products X_g = V_g Y_g (column norms only; the groups
+// of a level: one per pencil and shift).  The tile order of every group is that of
+// k_vmy (each XCD walks a contiguous range of the group's tiles), workgroup w on XCD
+// w % 8 taking every (gridDim.x / 8)-th tile of its XCD's range; a tile's arithmetic is
+// that of k_vmy, so the norms equal a launch per group.
+__global__ __launch_bounds__(PJ_THREADS) void k_vmy_groups(const ProjGroup* __restrict__ groups,
+                                                           const int64_t* __restrict__ ngroups) {
+    __shared__ VmyShared sm;
+    const int64_t G = *ngroups;
+    const int xcd = blockIdx.x % PJ_XCDS;
+    const int64_t lw = blockIdx.x / PJ_XCDS, nw = gridDim.x / PJ_XCDS;
+    for (int64_t g = 0; g < G; ++g) {
+        const ProjGroup gr = groups[g];
+        const int64_t T = gr.gx * gr.gy, per = (T + PJ_XCDS - 1) / PJ_XCDS;
+        const int64_t t1 = min(T, (int64_t)(xcd + 1) * per);
+        for (int64_t t = (int64_t)xcd * per + lw; t < t1; t += nw)
+            vmy_tile<SIMM_PROJ_FP64>(gr.n, gr.m, gr.V, gr.ldv, gr.Y, gr.ldy, gr.c, gr.gy, t, nullptr, gr.colpart, sm);
+    }
+}
+
 // Column norms from the per-64-row-block partial sums: first CN_GROUPS groups of blocks
 // each reduce their share for 64 columns (4 threads per column, LDS combine),
 // then one pass adds the groups and takes the square root.
@@ -252,6 +288,50 @@ __global__ void k_colnorm_finish(const double* __restrict__ part, int64_t c, dou
     double acc = 0.0;
     for (int g = 0; g < CN_GROUPS; ++g) acc += part[(int64_t)g * c + j];
     out[j] = sqrt(acc);
+}
+
+// The two column-norm reductions of k_colnorm_partial / k_colnorm_finish for every group
+// (same order of additions), groups dealt to blockIdx.z in turn.
+__global__ __launch_bounds__(256) void k_colnorm_partial_groups(const ProjGroup* __restrict__ groups,
+                                                                const int64_t* __restrict__ ngroups) {
+    __shared__ double red[4][64];
+    const int jl = threadIdx.x & 63, sub = threadIdx.x >> 6;
+    const int64_t G = *ngroups;
+    for (int64_t g = blockIdx.z; g < G; g += gridDim.z) {
+        const ProjGroup gr = groups[g];
+        const int64_t c = gr.c, nwaves = 2 * gr.gx;
+        const int64_t per = (nwaves + CN_GROUPS - 1) / CN_GROUPS;
+        const int64_t w0 = (int64_t)blockIdx.y * per, w1 = min(nwaves, w0 + per);
+        for (int64_t jb = blockIdx.x; jb * 64 < c; jb += gridDim.x) {
+            const int64_t j = jb * 64 + jl;
+            double a0 = 0.0, a1 = 0.0;
+            if (j < c) {
+                int64_t w = w0 + sub;
+                for (; w + 4 < w1; w += 8) {
+                    a0 += gr.colpart[w * c + j];
+                    a1 += gr.colpart[(w + 4) * c + j];
+                }
+                if (w < w1) a0 += gr.colpart[w * c + j];
+            }
+            red[sub][jl] = a0 + a1;
+            __syncthreads();
+            if (sub == 0 && j < c)
+                gr.part[(int64_t)blockIdx.y * c + j] = red[0][jl] + red[1][jl] + red[2][jl] + red[3][jl];
+            __syncthreads();
+        }
+    }
+}
+
+__global__ void k_colnorm_finish_groups(const ProjGroup* __restrict__ groups, const int64_t* __restrict__ ngroups) {
+    const int64_t G = *ngroups;
+    for (int64_t g = blockIdx.y; g < G; g += gridDim.y) {
+        const ProjGroup gr = groups[g];
+        for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < gr.c; j += (int64_t)gridDim.x * blockDim.x) {
+            double acc = 0.0;
+            for (int q = 0; q < CN_GROUPS; ++q) acc += gr.part[(int64_t)q * gr.c + j];
+            gr.norms[j] = sqrt(acc);
+        }
+    }
 }
 
 int64_t project_scratch_elems(int64_t n, int64_t c) {
@@ -293,6 +373,21 @@ simm_status project(int64_t n, int m, const cplx* V, int64_t ldv, const cplx* Y,
         hipLaunchKernelGGL(k_colnorm_finish, dim3((unsigned)((c + 127) / 128)), dim3(128), 0, st,
                            (const double*)part, c, col_norms);
     }
+    SIMM_HIP_TRY(hipGetLastError());
+    return SIMM_OK;
+}
+
+void project_group_shape(ProjGroup& g) {
+    g.gx = (g.n + PJ_ROWS - 1) / PJ_ROWS;
+    g.gy = (g.c + PJ_COLS - 1) / PJ_COLS;
+}
+int64_t project_group_scratch(int64_t n, int64_t c) { return project_scratch_elems(n, c); }
+
+simm_status project_groups(const ProjGroup* groups, const int64_t* ngroups, int grid, int gz, hipStream_t st) {
+    const int g8 = std::max(PJ_XCDS, grid / PJ_XCDS * PJ_XCDS);
+    hipLaunchKernelGGL(k_vmy_groups, dim3((unsigned)g8), dim3(PJ_THREADS), 0, st, groups, ngroups);
+    hipLaunchKernelGGL(k_colnorm_partial_groups, dim3(8, CN_GROUPS, (unsigned)gz), dim3(256), 0, st, groups, ngroups);
+    hipLaunchKernelGGL(k_colnorm_finish_groups, dim3(4, (unsigned)gz), dim3(128), 0, st, groups, ngroups);
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;
 }

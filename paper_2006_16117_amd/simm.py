@@ -89,6 +89,7 @@ EXPORTS = {
     "simm_run": (C.c_int, [_vp, C.POINTER(simm_params), _vp, _i32, _vp, C.POINTER(_vp)]),
     "simm_run_batch": (C.c_int, [C.POINTER(_vp), C.POINTER(simm_params), C.POINTER(_vp), _i32, _i32, _i32,
                                  C.POINTER(_vp)]),
+    "simm_batch_tuning": (C.c_int, [_vp, _vp, _vp, _vp, _i64]),
     "simm_multiplicities": (C.c_int, [_vp, _vp, _i32, _i32, _d, _vp, _vp, _vp, _i64]),
     "simm_result_summary": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "simm_result_level": (C.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64]),
@@ -511,3 +512,14 @@ def simm_run_batch(pencils, fs, params_list, workers: int = 8):
         r.pencil = p
     return results
 
+
+def simm_batch_tuning(cap: int = 64):
+    """The batched form's autotuner cache: shape classes, tuning rounds, and the chosen
+    workgroup counts of the indicator and projection launches."""
+    ne = C.c_int64()
+    tr = C.c_int64()
+    ig = np.zeros(cap, np.int32)
+    pg = np.zeros(cap, np.int32)
+    _check(_lib.simm_batch_tuning(C.addressof(ne), C.addressof(tr), ig.ctypes.data, pg.ctypes.data, cap))
+    return dict(entries=ne.value, trials=tr.value, indicator_grids=[int(x) for x in ig if x],
+                projection_grids=[int(x) for x in pg if x])

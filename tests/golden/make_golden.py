@@ -56,6 +56,14 @@ def compact_trace(res):
     }
 
 
+def _batch_run(arg):
+    name, i = arg
+    pen, f, params = make_batch(name)[i]
+    res = O.simm(pen, f, params)
+    print(f"{name} pencil {i}: n = {pen.n}, {len(res.shifts)} shifts, {len(res.clusters)} clusters", flush=True)
+    return {"n": pen.n, **compact_trace(res)}
+
+
 def hessenberg(names):
     for name in names:
         t0 = time.time()
@@ -82,10 +90,11 @@ def main(names):
         t0 = time.time()
         kind = load_config(name)["generator"]["kind"]
         if kind.endswith("_batch"):
-            runs = []
-            for pen, f, params in make_batch(name):
-                res = O.simm(pen, f, params)
-                runs.append({"n": pen.n, **compact_trace(res)})
+            # the pencils are independent: several processes, one BLAS thread each
+            import multiprocessing as mp
+            count = len(make_batch(name))
+            with mp.get_context("spawn").Pool(int(os.environ.get("GOLDEN_PROCS", "6"))) as pool:
+                runs = pool.map(_batch_run, [(name, i) for i in range(count)])
             out = {"workload": name, "generated_by": "oracle/simm.py via tests/golden/make_golden.py",
                    "oracle_seconds": round(time.time() - t0, 1), "runs": runs}
             summary = f"{len(runs)} pencils, {sum(len(r['clusters']) for r in runs)} clusters"

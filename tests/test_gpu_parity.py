@@ -684,17 +684,22 @@ def test_batch_matches_sequential_and_oracle(S):
     say("simm_run_batch", "cfg2_small:", len(batch), "pencils, n =", [p.n for p, _, _ in batch])
     pencils = [S.Pencil.from_workload(p) for p, _, _ in batch]
     fs = [f for _, f, _ in batch]
-    prms = [S.params_from_dict(d) for _, _, d in batch]
+    prms = [S.params_from_dict(d, flags=S.SIMM_FLAG_PROJECT) for _, _, d in batch]
     seq = [S.simm_run(P, f, prm) for P, f, prm in zip(pencils, fs, prms)]
     bat = S.simm_run_batch(pencils, fs, prms, workers=4)
+    say("  autotuner:", S.simm_batch_tuning())
     ties = 0
     for i, (a, b, g) in enumerate(zip(seq, bat, gold)):
-        # the batched run is the same computation as the separate run
+        # the batched run (joint persistent level launches) is the same computation as the
+        # separate run, bit for bit
         assert a.K == b.K and a.n_shifts == b.n_shifts
         for s in range(a.n_shifts):
             assert np.array_equal(a.shift(s).info()["H"], b.shift(s).info()["H"])
         for La, Lb in zip(a.levels, b.levels):
             assert np.array_equal(La.keys, Lb.keys) and np.array_equal(La.decision, Lb.decision)
+            assert np.array_equal(La.shift, Lb.shift) and np.array_equal(La.indicator, Lb.indicator)
+            assert np.array_equal(La.rho_max, Lb.rho_max)
+            assert np.array_equal(La.full_indicator, Lb.full_indicator), (i, La.level)
         assert np.array_equal(a.lam, b.lam)
         # and both follow the oracle
         assert b.K == g["K"] and b.n_shifts == len(g["shifts"])

@@ -303,7 +303,9 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs<C> a, int64_t b) {
     extern __shared__ double2 smem_raw[];
     C* smem = reinterpret_cast<C*>(smem_raw);
     using L = LuSmem<T, C>;
-    const C zero_c{0, 0};
+    // a prvalue: with two lvalue operands a struct-valued ?: selects between addresses and
+    // puts its operands (the row registers) in scratch memory
+    const auto zero_c = []() { return C{0, 0}; };
     C* S = smem + L::S;
     C* Lsh = smem + L::LSH;
     C* Ush = smem + L::USH;
@@ -347,7 +349,7 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs<C> a, int64_t b) {
         const C* lp_in = a.LP + (b >= 0 ? b : 0) * (int64_t)(NB + a.kl) * NB;
         const bool hasl = b >= 0 && r < Rb;
 #pragma unroll
-        for (int q = 0; q < NB; ++q) Lr[q] = hasl ? lp_in[(int64_t)q * (NB + a.kl) + r] : zero_c;
+        for (int q = 0; q < NB; ++q) Lr[q] = hasl ? lp_in[(int64_t)q * (NB + a.kl) + r] : zero_c();
         if (b >= 0 && tid < NB) piv_s[tid] = (int)(a.ipiv[j0 + tid] - j0);
     }
 
@@ -388,7 +390,7 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs<C> a, int64_t b) {
                 tin[k] = e < NB * NB;
                 ti[k] = e / NB;
                 tc[k] = e % NB;
-                xt[k] = tin[k] ? ldsr(S + trace_src(ti[k], pv) * SROW + tc[k]) : zero_c;
+                xt[k] = tin[k] ? ldsr(S + trace_src(ti[k], pv) * SROW + tc[k]) : zero_c();
             }
 #pragma unroll
             for (int t = 0; t < NB; ++t) {
@@ -486,7 +488,7 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs<C> a, int64_t b) {
     if (pr >= 0 && pr < NB + a.kl) {
         C* lp_out = a.LP + (b + 1) * (int64_t)(NB + a.kl) * NB + pr;
 #pragma unroll
-        for (int q = 0; q < NB; ++q) lp_out[(int64_t)q * (NB + a.kl)] = (prow && q < pr && q < nb1) ? X[q] : zero_c;
+        for (int q = 0; q < NB; ++q) lp_out[(int64_t)q * (NB + a.kl)] = (prow && q < pr && q < nb1) ? X[q] : zero_c();
     }
 }
 

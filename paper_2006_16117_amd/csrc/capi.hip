@@ -1834,6 +1834,15 @@ struct BatchItem {
     int64_t soff = 0;                 // first global shift index
 };
 
+// progress lines on stderr (SIMM_BATCH_PROGRESS=1): long batches otherwise print nothing
+bool batch_progress() {
+    static const bool on = [] {
+        const char* e = std::getenv("SIMM_BATCH_PROGRESS");
+        return e && e[0] == '1';
+    }();
+    return on;
+}
+
 simm_status run_batch_levels(std::vector<BatchItem>& items, hipStream_t st) {
     const int nb = (int)items.size();
     if (nb == 0) return SIMM_OK;
@@ -1900,6 +1909,7 @@ simm_status run_batch_levels(std::vector<BatchItem>& items, hipStream_t st) {
         }
         first[nb] = (int64_t)rows.size() / 5;
         const int64_t N = first[nb];
+        if (batch_progress()) std::fprintf(stderr, "[simm batch] level %d: %lld squares\n", k, (long long)N);
         EvalOut eo;
         SIMM_TRY(main_eval.run(rows, st, eo));
         std::vector<int> used((size_t)N);
@@ -3135,6 +3145,9 @@ simm_status simm_run_batch(const simm_pencil* pencils, const simm_params* params
             it.rc = phase();
             if (it.rc != SIMM_OK) it.msg = simm_last_error();
             it.R->ms[3] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (batch_progress())
+                std::fprintf(stderr, "[simm batch] pencil %d: n = %lld, %zu shifts, %.0f ms\n", (int)i,
+                             (long long)it.p->n, it.R->shifts.size(), it.R->ms[3]);
         }
         if (se == hipSuccess) {
             release_stream_buffers(st);

@@ -70,6 +70,28 @@ def measured_traffic(profile: str):
         return None
 
 
+def measured_profile_value(profile: str, key: str, sources):
+    """An integer field of a committed rocprofv3 counter summary, or None when one of
+    the kernel sources has changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(os.path.join(ROOT, "profiles", profile)).read()
+        for src in sources:
+            digest = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
+            if f"{src} {digest}" not in text:
+                return None
+        for line in text.splitlines():
+            if line.startswith(key + ":"):
+                return int(line.split(":", 1)[1])
+    except (OSError, ValueError):
+        return None
+    return None
+
+
+APPLY_SOURCES = ["paper_2006_16117_amd/csrc/band_spike.hip", "paper_2006_16117_amd/csrc/arnoldi.hip",
+                 "paper_2006_16117_amd/csrc/band_sweep.hip"]
+
+
 def apply_bytes(n: int, k: int, kb: int) -> int:
     """Algorithmic HBM bytes of one application of M = (A - sigma B)^{-1} B: the
     factor (3k+1 band rows), B (2 k_B + 1 rows), and about six n-vectors in and out,
@@ -448,7 +470,15 @@ def main():
     kb = max(pen.kl_b, pen.ku_b) if pen.b_band is not None else 0
     # dominant kernel: the band LU's panel step (one launch per 16 columns plus one)
     lu_launches = kcnt["band_lu"]   # panel launches (factors cancelled part-way included)
-    lu_us = kms["band_lu"] * 1e3 / max(lu_launches, 1)
+    lu_us_step = kms["band_lu"] * 1e3 / max(lu_launches, 1)
+    # The step computes up to 11 factors at once (the level-1 association's look-ahead),
+    # so its panel launches share the device; the roofline takes the launch alone: one
+    # more run, untimed, that builds its shifts one at a time (HIP events around each
+    # factor's launches on the run's stream).
+    solo = S.simm_run(P, fd, S.params_from_dict(params, flags=S.SIMM_FLAG_KERNEL_TIMING, lookahead=1))
+    lu_us = solo.kernel_ms["band_lu"] * 1e3 / max(solo.kernel_launches["band_lu"], 1)
+    lu_solo_launches = solo.kernel_launches["band_lu"]
+    del solo
     lu_tflops = lu_flops_per_launch(kl, ku) / (lu_us * 1e-6) / 1e12
     # K2: one application of M (B v + partitioned L and U sweeps)
     b_apply = apply_bytes(n, max(kl, ku), kb)
@@ -496,6 +526,9 @@ def main():
             "traffic": measured_traffic("k_band_lu_step_convdiff_n40000_traffic.md"),
             "flops_per_launch": lu_flops_per_launch(kl, ku),
             "us_per_launch": lu_us,
+            "launches_measured": lu_solo_launches,
+            "measured_in": "a run building its shifts one at a time (no factor beside it), HIP events per factor",
+            "us_per_launch_in_step": lu_us_step,
             "launches_per_step": lu_launches // args.steps,
         },
         "roofline_apply": {
@@ -507,6 +540,8 @@ def main():
             "unit": "GB/s",
             "frac": apply_gbs / HBM_PEAK_GBS,
             "bytes_per_launch": b_apply,
+            "traffic": measured_profile_value("apply_cgs2_convdiff_n40000_traffic.md", "apply_bytes_per_launch",
+                                              APPLY_SOURCES),
             "ms_per_launch": apply_ms,
             "launches_per_step": kcnt["band_sweep"] // args.steps,
         },

@@ -132,6 +132,8 @@ __device__ inline int wave_min_int(int k) {
     return __builtin_amdgcn_readlane(k, 63);
 }
 
+__device__ inline cplx rdlane(cplx v, int l) { return cplx{rdlane_d(v.re, l), rdlane_d(v.im, l)}; }
+__device__ inline cplxf rdlane(cplxf v, int l) { return cplxf{rdlane_d(v.re, l), rdlane_d(v.im, l)}; }
 // value of the partner lane (lane xor 1)
 __device__ inline cplx swap_pair(cplx v) { return cplx{dpp_d<0xB1>(v.re), dpp_d<0xB1>(v.im)}; }
 __device__ inline cplxf swap_pair(cplxf v) { return cplxf{dpp_d<0xB1>(v.re), dpp_d<0xB1>(v.im)}; }
@@ -287,6 +289,120 @@ __device__ __forceinline__ void factor_steps(const LuArgs<C>& a, C (&X)[NB], int
         if (f.prow && pos > t && pos - t <= a.kl) a.AB[(int64_t)(a.kv + pos - t) + j * a.ldab] = X[t];
     }
     if constexpr (t + 1 < NB) factor_steps<T, t + 1, C>(a, X, pos, f);
+}
+
+// v[ws] for a lane's ROWS (1 or 2) slots, without indexing the array by a variable
+template <int ROWS, typename C>
+__device__ __forceinline__ C pick_slot(const C (&v)[ROWS], int ws) {
+    static_assert(ROWS == 1 || ROWS == 2, "one or two rows per lane");
+    if constexpr (ROWS == 1) return v[0];
+    else return csel(ws == 1, v[1], v[0]);
+}
+
+// The 16 column steps of a panel held by one wavefront, ROWS rows per lane (slot k of a
+// lane: a panel row whose current position is pos[k]).  Pivot choice, interchanges (of
+// positions), eliminations and the multipliers stored as computed are those of
+// factor_steps; the pivot row and its reciprocal reach the other lanes by lane reads, so
+// a column step needs no LDS and no barrier.
+template <int ROWS, typename C, int t>
+__device__ __forceinline__ void factor_wave_step(const LuArgs<C>& a, C (&X)[ROWS][NB], int (&pos)[ROWS],
+                                                 const bool (&prow)[ROWS], int nb1, int64_t j1) {
+    using R = typename Real<C>::T;
+    if (t < nb1) {
+        const int64_t j = j1 + t;
+        const int km = (int)min((int64_t)a.kl, a.n - 1 - j);
+        // this lane's candidate: the largest |re| + |im| of its valid rows, first position on ties
+        R lv = R(-1);
+        int lp = 0x7fffffff, ls = 0;
+        C inv[ROWS];
+#pragma unroll
+        for (int k = 0; k < ROWS; ++k) {
+            const bool valid = prow[k] && pos[k] >= t && pos[k] <= t + km;
+            const R v = valid ? cabs1(X[k][t]) : R(-1);
+            inv[k] = crecip(X[k][t]);   // only the pivot's is used; formed here beside the reduction
+            asm volatile("" : "+v"(inv[k].re), "+v"(inv[k].im));
+            const bool take = valid && (v > lv || (v == lv && pos[k] < lp));
+            lv = take ? v : lv;
+            lp = take ? pos[k] : lp;
+            ls = take ? k : ls;
+        }
+        const R m = wave_max(lv);
+        const int key = (lv == m) ? lp : 0x7fffffff;
+        const int kmin = wave_min_int(key);
+        const unsigned long long bal = __ballot(key == kmin);
+        const int wl = bal ? __ffsll((long long)bal) - 1 : 0;
+        const int ws = __builtin_amdgcn_readlane(ls, wl);
+        const bool zero = !(m > R(0));
+        const int bpos = zero ? t : kmin;
+        if (threadIdx.x == 0) {
+            a.ipiv[j] = (int)(j1 + bpos);
+            // singular column: recorded; no interchange, no elimination
+            if (zero) atomicMin(a.info, (int)(j + 1));
+        }
+        if (!zero) {
+            // the winning row, column by column, from the winning lane (its slot ws)
+            C invs[ROWS], xt[ROWS];
+#pragma unroll
+            for (int k = 0; k < ROWS; ++k) {
+                invs[k] = inv[k];
+                xt[k] = X[k][t];
+            }
+            const C uinv = rdlane(pick_slot<ROWS>(invs, ws), wl);
+            C l[ROWS];
+            bool el[ROWS];
+#pragma unroll
+            for (int k = 0; k < ROWS; ++k) {
+                const int p0 = pos[k];
+                pos[k] = (p0 == t) ? bpos : ((p0 == bpos) ? t : p0);
+                el[k] = prow[k] && pos[k] > t;
+                l[k] = xt[k] * uinv;
+                if (el[k]) X[k][t] = l[k];
+            }
+#pragma unroll
+            for (int c = t + 1; c < NB; ++c) {
+                C xc[ROWS];
+#pragma unroll
+                for (int k = 0; k < ROWS; ++k) xc[k] = X[k][c];
+                const C uc = rdlane(pick_slot<ROWS>(xc, ws), wl);
+#pragma unroll
+                for (int k = 0; k < ROWS; ++k)
+                    if (el[k]) X[k][c] = fms(X[k][c], l[k], uc);
+            }
+        }
+        // column t's multipliers go to the band as computed now
+#pragma unroll
+        for (int k = 0; k < ROWS; ++k)
+            if (prow[k] && pos[k] > t && pos[k] - t <= a.kl)
+                a.AB[(int64_t)(a.kv + pos[k] - t) + j * a.ldab] = X[k][t];
+    }
+    if constexpr (t + 1 < NB) factor_wave_step<ROWS, C, t + 1>(a, X, pos, prow, nb1, j1);
+}
+
+template <int ROWS, typename C>
+__device__ __forceinline__ void factor_wave(const LuArgs<C>& a, C (&X)[ROWS][NB], int (&pos)[ROWS],
+                                            const bool (&prow)[ROWS], int nb1, int64_t j1) {
+    using R = typename Real<C>::T;
+    factor_wave_step<ROWS, C, 0>(a, X, pos, prow, nb1, j1);
+}
+
+// U rows and permuted multipliers of a factored panel b+1 from one row (position pr).
+template <typename C>
+__device__ __forceinline__ void store_panel_row(const LuArgs<C>& a, const C (&X)[NB], int pr, bool prow, int nb1,
+                                                int64_t j1, int64_t b) {
+    // rows of U (final since their own step) to the band
+    if (prow && pr < nb1) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+            if (q >= pr && q < nb1 && q - pr <= a.kv) a.AB[(int64_t)(a.kv + pr - q) + (j1 + q) * a.ldab] = X[q];
+    }
+    // permuted multipliers of panel b+1 (entries left of the diagonal; zeros elsewhere
+    // and in the rows past the matrix) for the next launch's update and the sweeps
+    if (pr >= 0 && pr < NB + a.kl) {
+        C* lp_out = a.LP + (b + 1) * (int64_t)(NB + a.kl) * NB + pr;
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+            lp_out[(int64_t)q * (NB + a.kl)] = (prow && q < pr && q < nb1) ? X[q] : C{0, 0};
+    }
 }
 
 }  // namespace
@@ -466,29 +582,50 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs<C> a, int64_t b) {
     if (wg != 0) return;
 
     // ---- workgroup 0: factor panel b+1 (window rows nbp .., panel position pos = r - nbp at the start)
-    FactorCtx<C> f;
-    int pos = r - nbp;
-    f.prow = pos >= 0 && pos < R1;
-    f.nb1 = nb1;
-    f.j1 = j1;
-    f.lane = lane;
-    f.wave = wave;
-    f.cand = cand;
-    factor_steps<T, 0, C>(a, X, pos, f);
-    const int pr = pos;
-    const bool prow = f.prow;
-    // rows of U (final since their own step) to the band
-    if (prow && pr < nb1) {
+    if constexpr (T == 64) {
+        // one wavefront holds the panel's rows, one per lane
+        C Xs[1][NB];
 #pragma unroll
-        for (int q = 0; q < NB; ++q)
-            if (q >= pr && q < nb1 && q - pr <= a.kv) a.AB[(int64_t)(a.kv + pr - q) + (j1 + q) * a.ldab] = X[q];
-    }
-    // permuted multipliers of panel b+1 (entries left of the diagonal; zeros elsewhere
-    // and in the rows past the matrix) for the next launch's update and the sweeps
-    if (pr >= 0 && pr < NB + a.kl) {
-        C* lp_out = a.LP + (b + 1) * (int64_t)(NB + a.kl) * NB + pr;
+        for (int c = 0; c < NB; ++c) Xs[0][c] = X[c];
+        int ps[1] = {r - nbp};
+        const bool pw[1] = {ps[0] >= 0 && ps[0] < R1};
+        factor_wave<1, C>(a, Xs, ps, pw, nb1, j1);
+        store_panel_row(a, Xs[0], ps[0], pw[0], nb1, j1, b);
+    } else if constexpr (T == 128) {
+        // the panel's rows (at most NB + kl <= 112) go to wavefront 0, two per lane
+        const int p = r - nbp;
+        lds_barrier();
+        if (p >= 0 && p < R1) {
 #pragma unroll
-        for (int q = 0; q < NB; ++q) lp_out[(int64_t)q * (NB + a.kl)] = (prow && q < pr && q < nb1) ? X[q] : zero_c();
+            for (int c = 0; c < NB; ++c) ldsw(S + p * SROW + c, X[c]);
+        }
+        lds_barrier();
+        if (wave != 0) return;
+        C Xs[2][NB];
+        int ps[2];
+        bool pw[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int i = lane + 64 * k;
+            ps[k] = i;
+            pw[k] = i < R1;
+#pragma unroll
+            for (int c = 0; c < NB; ++c) Xs[k][c] = pw[k] ? ldsr(S + i * SROW + c) : zero_c();
+        }
+        factor_wave<2, C>(a, Xs, ps, pw, nb1, j1);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) store_panel_row(a, Xs[k], ps[k], pw[k], nb1, j1, b);
+    } else {
+        FactorCtx<C> f;
+        int pos = r - nbp;
+        f.prow = pos >= 0 && pos < R1;
+        f.nb1 = nb1;
+        f.j1 = j1;
+        f.lane = lane;
+        f.wave = wave;
+        f.cand = cand;
+        factor_steps<T, 0, C>(a, X, pos, f);
+        store_panel_row(a, X, pos, f.prow, nb1, j1, b);
     }
 }
 

@@ -181,6 +181,19 @@ simm_status simm_shift_build(simm_pencil p, double sig_re, double sig_im,
  * ended with (zeros for an FP64 shift).  Any pointer may be NULL. */
 simm_status simm_shift_refine_stats(simm_shift s, int64_t* solves, int64_t* corrections, double* max_eta);
 
+/* How the shift's factor of A - sigma B (Sec. 2, the one factorization per shift behind
+ * eq. (IMxb)) was formed.  block_len > 0: partitioned (the diagonal blocks of block_len
+ * columns factored side by side with partial pivoting inside each block, the couplings
+ * solved through the spikes' reduced system); 0: one band LU of the whole matrix.
+ * fallback = 1 when a partitioned factor was replaced by the whole-matrix one (a singular
+ * diagonal block or reduced system, or a solve's normwise backward error above 1e-13);
+ * eta: that backward error of the partitioned FP64 factor (-1 when not measured).  The
+ * library partitions bands with kl, ku >= 1 and 2 kl + ku <= 481 of orders that give
+ * blocks of at least max(1024, 4 (kl + ku)) rows, with at most 1 + 2048 / (kl + ku)
+ * blocks; the environment variable SIMM_LU_PART = 0 turns it off, and a positive value
+ * sets the block length.  Any pointer may be NULL. */
+simm_status simm_shift_factor_info(simm_shift s, int64_t* block_len, int32_t* fallback, double* eta);
+
 /* A shift made from its small data alone (Sec. 2, eqs. (shiftedLS), (eq:many) and
  * (eq:error)): the reduced solves (I + (sigma - z_j) H_m) y_j = beta e_1, their
  * residuals and the quadrature sums depend only on sigma, beta = ||(A - sigma B)^{-1} f||

@@ -628,3 +628,54 @@ def projected_norms_gradient(A: np.ndarray, A1: np.ndarray, B: np.ndarray, f: np
             dp += -2.0 * (ck * np.vdot(lam, A1 @ u)).real
             t += ck * lam.conj() * u
     return J, dp, -2.0 * t.conj()
+
+
+def _band_factor(n: int, kl: int, ku: int, a_band: np.ndarray, klb: int, kub: int,
+                 b_band: np.ndarray | None, z: complex):
+    """LAPACK band LU (zgbtrf) of A - z B, both given in band layout."""
+    klc, kuc = max(kl, klb), max(ku, kub)
+    ab = np.zeros((2 * klc + kuc + 1, n), dtype=np.complex128, order="F")
+    ab[klc + kuc - ku: klc + kuc + kl + 1, :] += a_band
+    if b_band is None:
+        ab[klc + kuc, :] -= z
+    else:
+        ab[klc + kuc - kub: klc + kuc + klb + 1, :] -= z * b_band
+    lu, ipiv, info = lapack.zgbtrf(ab, klc, kuc, overwrite_ab=1)
+    if info > 0:
+        raise SingularShift(f"exact zero pivot at z={z} (column {info})")
+    if info < 0:
+        raise ValueError(f"zgbtrf argument {-info}")
+    return lu, ipiv, klc, kuc
+
+
+def _band_solve(fac, r: np.ndarray, adjoint: bool = False) -> np.ndarray:
+    """x with (A - z B) x = r, or with (A - z B)^H x = r when ``adjoint``."""
+    lu, ipiv, kl, ku = fac
+    x, info = lapack.zgbtrs(lu, kl, ku, r, ipiv, trans=2 if adjoint else 0)
+    if info != 0:
+        raise ValueError(f"zgbtrs info {info}")
+    return x
+
+
+def projected_norms_gradient_banded(n: int, kl: int, ku: int, a_band: np.ndarray, klb: int, kub: int,
+                                    b_band: np.ndarray | None, kl1: int, ku1: int, a1_band: np.ndarray,
+                                    f: np.ndarray, squares, g: int) -> tuple[float, float, np.ndarray]:
+    """projected_norms_gradient for band matrices (orders where dense ones do not
+    fit): the same quantities by the same formulas, with each A - z_j B factored by
+    LAPACK's band LU and its systems, and the conjugate-transposed ones, solved with
+    that factor.  A1 is a band matrix of half-bandwidths (kl1, ku1).  The factor of a
+    node is formed twice (once for u_j, once for lam_j, which needs x_R first)."""
+    J = 0.0
+    dp = 0.0
+    t = np.zeros(n, dtype=np.complex128)
+    for c, w in squares:
+        z, wq = edge_rule(c, w, 2 * g)
+        cj = wq / (2j * np.pi)
+        U = [_band_solve(_band_factor(n, kl, ku, a_band, klb, kub, b_band, zj), f) for zj in z]
+        x = sum(ck * u for ck, u in zip(cj, U))
+        J += float(np.vdot(x, x).real)
+        for zj, ck, u in zip(z, cj, U):
+            lam = _band_solve(_band_factor(n, kl, ku, a_band, klb, kub, b_band, zj), x, adjoint=True)
+            dp += -2.0 * (ck * np.vdot(lam, band_matvec(n, kl1, ku1, a1_band, u))).real
+            t += ck * lam.conj() * u
+    return J, dp, -2.0 * t.conj()

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsimm.so")
 SOURCES = ["capi.hip", "band_lu.hip", "band_sweep.hip", "band_spike.hip", "arnoldi.hip", "schur.hip", "indicators.hip",
-           "project.hip", "multiplicity.hip", "gradient.hip", "refine.hip"]
+           "project.hip", "multiplicity.hip", "gradient.hip", "refine.hip", "band_part.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

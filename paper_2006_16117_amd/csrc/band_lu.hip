@@ -60,6 +60,8 @@ struct LuArgs {
     C* LP;           // permuted multipliers of every panel: panel p at LP + p NB (NB+kl), column-major (NB+kl) x NB
     int* info;       // first singular column + 1 (INT_MAX if none)
     int64_t zidx;    // index of the zero entry stored after the band
+    int64_t bs;      // > 0: block-diagonal mode, diagonal blocks of bs columns (workgroup row y: block y)
+    int64_t row0;    // first row of the block (pivots and info are stored as global rows)
 };
 
 // Index of band entry (i, c), or of the zero entry when (i, c) lies outside the
@@ -257,9 +259,9 @@ __device__ __forceinline__ void factor_steps(const LuArgs<C>& a, C (&X)[NB], int
         const bool zero = !(best > R(0));
         if (zero) bpos = t;
         if (threadIdx.x == 0) {
-            a.ipiv[j] = (int)(f.j1 + bpos);
+            a.ipiv[j] = (int)(f.j1 + bpos + a.row0);
             // singular column: recorded; no interchange, no elimination
-            if (zero) atomicMin(a.info, (int)(j + 1));
+            if (zero) atomicMin(a.info, (int)(j + 1 + a.row0));
         }
         if constexpr (W > 1) {
             // then the winning wavefront's candidate lane publishes its row
@@ -335,9 +337,9 @@ __device__ __forceinline__ void factor_wave_step(const LuArgs<C>& a, C (&X)[ROWS
         const bool zero = !(m > R(0));
         const int bpos = zero ? t : kmin;
         if (threadIdx.x == 0) {
-            a.ipiv[j] = (int)(j1 + bpos);
+            a.ipiv[j] = (int)(j1 + bpos + a.row0);
             // singular column: recorded; no interchange, no elimination
-            if (zero) atomicMin(a.info, (int)(j + 1));
+            if (zero) atomicMin(a.info, (int)(j + 1 + a.row0));
         }
         if (!zero) {
             // the winning row, column by column, from the winning lane (its slot ws)
@@ -381,7 +383,6 @@ __device__ __forceinline__ void factor_wave_step(const LuArgs<C>& a, C (&X)[ROWS
 template <int ROWS, typename C>
 __device__ __forceinline__ void factor_wave(const LuArgs<C>& a, C (&X)[ROWS][NB], int (&pos)[ROWS],
                                             const bool (&prow)[ROWS], int nb1, int64_t j1) {
-    using R = typename Real<C>::T;
     factor_wave_step<ROWS, C, 0>(a, X, pos, prow, nb1, j1);
 }
 
@@ -416,6 +417,18 @@ __device__ __forceinline__ void store_panel_row(const LuArgs<C>& a, const C (&X)
 //                   pivoting, one column step per LDS barrier.
 template <int T, typename C>
 __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs<C> a, int64_t b) {
+    if (a.bs > 0) {
+        // block-diagonal mode: the diagonal block of this workgroup row, as a matrix of
+        // its own stored in place (its columns of the band, its panels of LP)
+        const int64_t r0 = (int64_t)blockIdx.y * a.bs;
+        a.n = min(a.bs, a.n - r0);
+        a.AB += r0 * a.ldab;
+        a.zidx -= r0 * a.ldab;
+        a.ipiv += r0;
+        a.LP += (r0 / NB) * (int64_t)(NB + a.kl) * NB;
+        a.row0 = r0;
+        if (b * NB >= a.n) return;   // a shorter last block is done
+    }
     extern __shared__ double2 smem_raw[];
     C* smem = reinterpret_cast<C*>(smem_raw);
     using L = LuSmem<T, C>;
@@ -466,7 +479,7 @@ __global__ __launch_bounds__(T) void k_band_lu_step(LuArgs<C> a, int64_t b) {
         const bool hasl = b >= 0 && r < Rb;
 #pragma unroll
         for (int q = 0; q < NB; ++q) Lr[q] = hasl ? lp_in[(int64_t)q * (NB + a.kl) + r] : zero_c();
-        if (b >= 0 && tid < NB) piv_s[tid] = (int)(a.ipiv[j0 + tid] - j0);
+        if (b >= 0 && tid < NB) piv_s[tid] = (int)(a.ipiv[j0 + tid] - j0 - a.row0);
     }
 
     if (b >= 0) {
@@ -633,11 +646,13 @@ namespace {
 template <int T, typename C>
 simm_status launch_lu(const LuArgs<C>& a, hipStream_t st, const std::atomic<bool>* cancel, int64_t& launches) {
     const int grid = 2 + (a.kv + NB - 1) / NB;
-    const int64_t nblk = (a.n + NB - 1) / NB;
+    const int64_t len = a.bs > 0 ? std::min(a.bs, a.n) : a.n;               // columns of the longest block
+    const unsigned gy = a.bs > 0 ? (unsigned)((a.n + a.bs - 1) / a.bs) : 1u;   // diagonal blocks
+    const int64_t nblk = (len + NB - 1) / NB;
     const size_t lds = LuSmem<T, C>::bytes;
     if (!cancel) {
         for (int64_t b = -1; b < nblk; ++b)
-            hipLaunchKernelGGL((k_band_lu_step<T, C>), dim3(b < 0 ? 1 : grid), dim3(T), lds, st, a, b);
+            hipLaunchKernelGGL((k_band_lu_step<T, C>), dim3(b < 0 ? 1 : grid, gy), dim3(T), lds, st, a, b);
         launches = nblk + 1;
         return SIMM_OK;
     }
@@ -662,7 +677,7 @@ simm_status launch_lu(const LuArgs<C>& a, hipStream_t st, const std::atomic<bool
         if (batch >= RING) SIMM_HIP_TRY(hipEventSynchronize(e));
         const int64_t bend = std::min<int64_t>(b + BATCH, nblk);
         for (int64_t q = b; q < bend; ++q)
-            hipLaunchKernelGGL((k_band_lu_step<T, C>), dim3(q < 0 ? 1 : grid), dim3(T), lds, st, a, q);
+            hipLaunchKernelGGL((k_band_lu_step<T, C>), dim3(q < 0 ? 1 : grid, gy), dim3(T), lds, st, a, q);
         launches += bend - b;
         SIMM_HIP_TRY(hipEventRecord(e, st));
     }
@@ -677,8 +692,12 @@ int lu_panel_width(int kl) {
 
 namespace {
 template <typename C>
-simm_status band_lu_t(int64_t n, int kl, int ku, C* AB, int* ipiv, C* LP, int* info, hipStream_t st,
+simm_status band_lu_t(int64_t n, int kl, int ku, C* AB, int* ipiv, C* LP, int* info, int64_t bs, hipStream_t st,
                       const std::atomic<bool>* cancel, int64_t* launches) {
+    if (bs < 0 || bs % NB != 0) {
+        set_error("diagonal block length of the band LU must be a multiple of 16");
+        return SIMM_EINVAL;
+    }
     if (lu_panel_width(kl) == 0) {
         set_error("lower bandwidth too large for the LU kernel");
         return SIMM_EUNSUPPORTED;
@@ -694,6 +713,8 @@ simm_status band_lu_t(int64_t n, int kl, int ku, C* AB, int* ipiv, C* LP, int* i
     a.LP = LP;
     a.info = info;
     a.zidx = (int64_t)a.ldab * n;
+    a.bs = (bs > 0 && bs < n) ? bs : 0;
+    a.row0 = 0;
     int64_t count = 0;
     // the smallest workgroup that holds the window: fewer wavefronts to meet at each
     // column step's barrier (the pivot and the arithmetic do not depend on the split)
@@ -710,13 +731,13 @@ simm_status band_lu_t(int64_t n, int kl, int ku, C* AB, int* ipiv, C* LP, int* i
 }  // namespace
 
 simm_status band_lu(int64_t n, int kl, int ku, cplx* AB, int* ipiv, cplx* LP, int* info, hipStream_t st,
-                    const std::atomic<bool>* cancel, int64_t* launches) {
-    return band_lu_t(n, kl, ku, AB, ipiv, LP, info, st, cancel, launches);
+                    const std::atomic<bool>* cancel, int64_t* launches, int64_t bs) {
+    return band_lu_t(n, kl, ku, AB, ipiv, LP, info, bs, st, cancel, launches);
 }
 
 simm_status band_lu(int64_t n, int kl, int ku, cplxf* AB, int* ipiv, cplxf* LP, int* info, hipStream_t st,
-                    const std::atomic<bool>* cancel, int64_t* launches) {
-    return band_lu_t(n, kl, ku, AB, ipiv, LP, info, st, cancel, launches);
+                    const std::atomic<bool>* cancel, int64_t* launches, int64_t bs) {
+    return band_lu_t(n, kl, ku, AB, ipiv, LP, info, bs, st, cancel, launches);
 }
 
 size_t band_lu_panel_elems(int64_t n, int kl) { return (size_t)((n + NB - 1) / NB) * (size_t)(NB + kl) * NB; }

@@ -825,7 +825,7 @@ simm_status spike_prepare(SpikeFactor& f, hipStream_t st) {
     const size_t elems = (size_t)f.P * kl * kl + (size_t)f.P * K * K + (size_t)f.P * kl * 2 + (size_t)f.P * K * 2 +
                          (size_t)n16 + two * ((size_t)(f.P + f.G) * ((size_t)kl * kl + (size_t)K * K)) +
                          (size_t)f.G * 2 * (kl + K) + (size_t)(f.G + 1) * 16 + 64;
-    SIMM_HIP_TRY(hipMalloc(&f.mem, sizeof(cplx) * elems + esz * big + 20 * 256));
+    SIMM_HIP_TRY(device_malloc(&f.mem, sizeof(cplx) * elems + esz * big + 20 * 256));
     char* p = reinterpret_cast<char*>(f.mem);
     auto take_b = [&](size_t bytes) {
         char* r = p;
@@ -874,6 +874,8 @@ simm_status spike_prepare(SpikeFactor& f, hipStream_t st) {
         SIMM_TRY(transfer_products(f, true, kl, f.PhiL, f.PiL, f.PiFullL, st));
         SIMM_TRY(transfer_products(f, false, K, f.PhiU, f.PiU, f.PiFullU, st));
     }
+    // a partitioned factor: its spikes and reduced system, from D's sweeps
+    if (f.bs > 0) SIMM_TRY(part_prepare(f, st));
     return SIMM_OK;
 }
 
@@ -884,10 +886,12 @@ simm_status spike_prepare(SpikeFactor& f, hipStream_t st) {
 simm_status spike_clone_scratch(const SpikeFactor& base, SpikeFactor& out, hipStream_t st) {
     out = base;
     out.mem = nullptr;
+    out.part_mem = nullptr;   // spikes and reduced inverse stay the base's
     const int kl = base.klx, K = base.K;
+    const size_t part = base.bs > 0 ? (size_t)base.n16 + (size_t)base.nr + 32 : 0;
     const size_t elems = (size_t)base.n16 + (size_t)base.P * kl * 2 + (size_t)base.P * K * 2 +
-                         (size_t)base.G * 2 * (kl + K) + (size_t)(base.G + 1) * 16 + 64;
-    SIMM_HIP_TRY(hipMalloc(&out.mem, sizeof(cplx) * elems + 12 * 256));
+                         (size_t)base.G * 2 * (kl + K) + (size_t)(base.G + 1) * 16 + 64 + part;
+    SIMM_HIP_TRY(device_malloc(&out.mem, sizeof(cplx) * elems + 14 * 256));
     char* p = reinterpret_cast<char*>(out.mem);
     auto take = [&](size_t count) {
         char* r = p;
@@ -905,6 +909,10 @@ simm_status spike_clone_scratch(const SpikeFactor& base, SpikeFactor& out, hipSt
     out.tgU = take((size_t)base.G * K);
     out.counter = reinterpret_cast<unsigned*>(take((size_t)(base.G + 1) * (SPIKE_CTR_STRIDE / 4)));
     out.err = reinterpret_cast<int*>(take(4));
+    if (base.bs > 0) {
+        out.pg = take((size_t)base.n16);
+        out.pz = take((size_t)base.nr);
+    }
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned*>(out.err), 1, 0u);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, out.counter, (int)((base.G + 1) * SPIKE_CTR_STRIDE), 0u);
     SIMM_HIP_TRY(hipGetLastError());
@@ -913,7 +921,9 @@ simm_status spike_clone_scratch(const SpikeFactor& base, SpikeFactor& out, hipSt
 
 void spike_release(SpikeFactor& f) {
     (void)hipFree(f.mem);
+    (void)hipFree(f.part_mem);
     f.mem = nullptr;
+    f.part_mem = nullptr;
 }
 
 // One chain launch: `groups` groups of L chunks (chain order) over P chunks, each group
@@ -1013,9 +1023,14 @@ static simm_status apply_t(const SpikeFactor& f, const GT* Gf, const GT* Hb, con
     return SIMM_OK;
 }
 
-simm_status spike_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int* active, hipStream_t st) {
+simm_status spike_apply_diag(const SpikeFactor& f, const cplx* u, cplx* y, const int* active, hipStream_t st) {
     if (f.f32) return apply_t<cplxf>(f, f.Gf32, f.Hb32, f.PsiL32, f.PsiU32, u, y, active, st);
     return apply_t<cplx>(f, f.Gf, f.Hb, f.PsiL, f.PsiU, u, y, active, st);
+}
+
+simm_status spike_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int* active, hipStream_t st) {
+    if (f.bs > 0) return part_apply(f, u, y, active, st);
+    return spike_apply_diag(f, u, y, active, st);
 }
 
 int64_t spike_bytes_per_apply(const SpikeFactor& f) {
@@ -1026,7 +1041,9 @@ int64_t spike_bytes_per_apply(const SpikeFactor& f) {
         lower += std::min<int64_t>(f.kl, f.n - 1 - j);
         upper += std::min<int64_t>(f.K, j) + 1;
     }
-    return 16 * (lower + upper + 2 * f.n);
+    // a partitioned factor: its spikes and the reduced inverse once more
+    const int64_t part = f.bs > 0 ? f.n * (int64_t)(f.pkl + f.pku) + f.nr * f.nr : 0;
+    return 16 * (lower + upper + 2 * f.n + part);
 }
 
 }  // namespace simm

@@ -36,7 +36,7 @@ static std::mutex g_free_mu;
 static std::vector<void*> g_free_list;
 static size_t g_free_bytes = 0;
 static std::atomic<int> g_batches{0};
-constexpr size_t kDeferBytes = (size_t)32 << 30;
+constexpr size_t kDeferBytes = (size_t)16 << 30;
 
 void flush_deferred_frees() {
     std::vector<void*> v;
@@ -65,6 +65,36 @@ void release_device(void* q) {
     }
     if (flush) flush_deferred_frees();
 }
+
+// hipMalloc; when the device is out of memory, the frees collected so far are done
+// and the allocation is tried once more.
+hipError_t device_malloc(void** p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipErrorOutOfMemory) return e;
+    (void)hipGetLastError();
+    bool pending;
+    {
+        std::lock_guard<std::mutex> lk(g_free_mu);
+        pending = !g_free_list.empty();
+    }
+    if (!pending) return e;
+    flush_deferred_frees();
+    return hipMalloc(p, bytes);
+}
+
+// While one is alive, frees through release_device are collected (runs that release
+// their factors shift by shift, batches); the last one to end frees them.
+struct DeferFrees {
+    bool on;
+    explicit DeferFrees(bool enable) : on(enable) {
+        if (on) g_batches.fetch_add(1);
+    }
+    ~DeferFrees() {
+        if (on && g_batches.fetch_sub(1) == 1) flush_deferred_frees();
+    }
+    DeferFrees(const DeferFrees&) = delete;
+    DeferFrees& operator=(const DeferFrees&) = delete;
+};
 
 }  // namespace simm
 
@@ -113,11 +143,21 @@ struct simm_shift_s {
     bool factor_borrowed = false;   // AB, ipiv, LP, spike belong to another shift
     bool sweeps_ready = false;      // spike holds the partitioned-sweep data of the factor
     SpikeFactor spike;          // partitioned-sweep data of the factor
+    // partitioned factorization: block length (0: the whole matrix was factored), the
+    // couplings cut from the band, and whether a partitioned factor was replaced by the
+    // whole-matrix one (singular block or reduced system, or a backward error above
+    // kPartTol, which part_eta records)
+    int64_t part_bs = 0;
+    cplx* CPL = nullptr;
+    bool part_fallback = false;
+    double part_eta = -1.0;
     // frees the n-sized data (factor, sweep data, Krylov basis); the small per-shift
     // data used by the indicators stays
     void release_large() {
         if (!factor_borrowed) {
             release_device(spike.mem);
+            release_device(spike.part_mem);
+            release_device(CPL);
             release_device(AB);
             release_device(ipiv);
             release_device(LP);
@@ -132,6 +172,7 @@ struct simm_shift_s {
         AB32 = nullptr;
         LP32 = nullptr;
         ref_mem = nullptr;
+        CPL = nullptr;
         V = nullptr;
         spike = SpikeFactor{};
         factor_borrowed = true;   // nothing left to free
@@ -140,6 +181,9 @@ struct simm_shift_s {
     void release_factor() {
         if (factor_borrowed) return;
         release_device(spike.mem);
+        release_device(spike.part_mem);
+        release_device(CPL);
+        CPL = nullptr;
         release_device(AB);
         release_device(ipiv);
         release_device(LP);
@@ -172,12 +216,15 @@ struct simm_shift_s {
         rpen = base->rpen;
         rst = base->rst;
         spike = base->spike;
+        part_bs = base->part_bs;
+        CPL = base->CPL;
         sweeps_ready = true;
         factor_borrowed = true;
     }
     ~simm_shift_s() {
         if (!factor_borrowed) {
             spike_release(spike);
+            (void)hipFree(CPL);
             (void)hipFree(AB);
             (void)hipFree(ipiv);
             (void)hipFree(LP);
@@ -334,7 +381,7 @@ template <typename T>
 simm_status dalloc(T** p, size_t count) {
     *p = nullptr;
     if (count == 0) count = 1;
-    hipError_t e = hipMalloc((void**)p, sizeof(T) * count);
+    hipError_t e = device_malloc((void**)p, sizeof(T) * count);
     if (e != hipSuccess) {
         set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
         return e == hipErrorOutOfMemory ? SIMM_ENOMEM : SIMM_EHIP;
@@ -456,9 +503,12 @@ ShiftDev shift_dev(const simm_shift_s* s) {
 // Factor phase of one shift (hot-path steps a1-a2): the shifted band and its LU with
 // partial pivoting.  Synchronous on return (the factor may be used next on another
 // stream).
+// With whole = false the band is factored in diagonal blocks when part_block_len says
+// so (the spikes and reduced system follow with the sweep data); a singular block
+// falls back to the whole-matrix factorization.
 simm_status factor_shift(simm_pencil_s* p, cplx sigma, hipStream_t st, std::unique_ptr<simm_shift_s>& out,
                          KernelClock* clk = nullptr, const std::atomic<bool>* cancel = nullptr,
-                         int precision = SIMM_PREC_FP64) {
+                         int precision = SIMM_PREC_FP64, bool whole = false) {
     auto s = std::make_unique<simm_shift_s>();
     s->p = p;
     s->sigma = sigma;
@@ -473,6 +523,8 @@ simm_status factor_shift(simm_pencil_s* p, cplx sigma, hipStream_t st, std::uniq
         return SIMM_EUNSUPPORTED;
     }
     s->mixed = (precision == SIMM_PREC_MIXED);
+    s->part_bs = whole ? 0 : part_block_len(n, kl, ku);
+    if (s->part_bs > 0) SIMM_TRY(dalloc(&s->CPL, part_cpl_elems(n, kl, ku, s->part_bs)));
     SIMM_TRY(dalloc(&s->ipiv, (size_t)((n + 15) / 16 * 16)));
     if (s->mixed) {
         SIMM_TRY(dalloc(&s->AB32, (size_t)ldab * n + 1));   // + one zero entry read for out-of-band taps
@@ -506,15 +558,23 @@ simm_status factor_shift(simm_pencil_s* p, cplx sigma, hipStream_t st, std::uniq
         simm_status lu;
         if (s->mixed) {
             SIMM_TRY(assemble_shifted(n, kl, ku, p->A, p->kla, p->kua, p->B, p->klb, p->kub, sigma, s->AB32, st));
-            lu = band_lu(n, kl, ku, s->AB32, s->ipiv, s->LP32, info_d, st, cancel, &ks.units);
+            if (s->part_bs > 0) SIMM_TRY(part_cut(n, kl, ku, s->AB32, s->part_bs, s->CPL, st));
+            lu = band_lu(n, kl, ku, s->AB32, s->ipiv, s->LP32, info_d, st, cancel, &ks.units, s->part_bs);
         } else {
             SIMM_TRY(assemble_shifted(n, kl, ku, p->A, p->kla, p->kua, p->B, p->klb, p->kub, sigma, s->AB, st));
-            lu = band_lu(n, kl, ku, s->AB, s->ipiv, s->LP, info_d, st, cancel, &ks.units);
+            if (s->part_bs > 0) SIMM_TRY(part_cut(n, kl, ku, s->AB, s->part_bs, s->CPL, st));
+            lu = band_lu(n, kl, ku, s->AB, s->ipiv, s->LP, info_d, st, cancel, &ks.units, s->part_bs);
         }
         if (lu != SIMM_OK) return lu;
     }
     SIMM_HIP_TRY(hipMemcpyAsync(&info, info_d, sizeof(int), hipMemcpyDeviceToHost, st));
     SIMM_HIP_TRY(hipStreamSynchronize(st));
+    if (info != INT_MAX && s->part_bs > 0) {
+        // a zero pivot inside a diagonal block says nothing about A - sigma B itself
+        SIMM_TRY(factor_shift(p, sigma, st, out, clk, cancel, precision, true));
+        out->part_fallback = true;
+        return SIMM_OK;
+    }
     if (info != INT_MAX) {
         char msg[160];
         std::snprintf(msg, sizeof msg, "exact zero pivot in column %d of A - sigma B (sigma = %.17g%+.17gi)", info,
@@ -538,9 +598,43 @@ simm_status prepare_sweeps(simm_shift_s* s, hipStream_t st, KernelClock* clk = n
     s->spike.f32 = s->mixed;
     s->spike.AB32 = s->AB32;
     s->spike.LP32 = s->LP32;
+    s->spike.bs = s->part_bs;
+    s->spike.cpl = s->CPL;
+    simm_status rc;
     {
         KScope ks(clk, SIMM_K_SPIKE_PREP);
-        SIMM_TRY(spike_prepare(s->spike, st));
+        rc = spike_prepare(s->spike, st);
+    }
+    if (rc != SIMM_OK && !(s->part_bs > 0 && rc == SIMM_ESINGULAR_SHIFT)) return rc;
+    bool redo = rc != SIMM_OK;
+    if (!redo && s->part_bs > 0 && !s->mixed) {
+        // pivoting stays inside the blocks: the partitioned factor is kept only if a
+        // solve with it is backward stable (the FP32 one is refined anyway)
+        simm_pencil_s* p = s->p;
+        RefinePencil pen{p->A, p->kla, p->kua, p->B, p->klb, p->kub, s->sigma, 0.0};
+        DevBuf nb;
+        SIMM_TRY(nb.alloc(sizeof(unsigned long long) * 4, st));
+        SIMM_TRY(band_inf_norm(p->n, p->A, p->kla, p->kua, p->B, p->klb, p->kub, s->sigma,
+                               nb.as<unsigned long long>(), &pen.cnorm, st));
+        SIMM_TRY(solve_backward_error(s->spike, pen, &s->part_eta, st));
+        redo = !(s->part_eta <= kPartTol);
+    }
+    if (redo) {
+        // the whole-matrix factor instead, in place of the partitioned one
+        std::unique_ptr<simm_shift_s> w;
+        SIMM_HIP_TRY(hipStreamSynchronize(st));
+        SIMM_TRY(factor_shift(s->p, s->sigma, st, w, clk, nullptr, s->mixed ? SIMM_PREC_MIXED : SIMM_PREC_FP64, true));
+        spike_release(s->spike);
+        s->spike = SpikeFactor{};
+        std::swap(s->AB, w->AB);
+        std::swap(s->AB32, w->AB32);
+        std::swap(s->LP, w->LP);
+        std::swap(s->LP32, w->LP32);
+        std::swap(s->ipiv, w->ipiv);
+        std::swap(s->CPL, w->CPL);
+        s->part_bs = 0;
+        s->part_fallback = true;
+        return prepare_sweeps(s, st, clk);
     }
     SIMM_HIP_TRY(hipStreamSynchronize(st));
     s->sweeps_ready = true;
@@ -1035,6 +1129,21 @@ struct Sq {
     int s;
 };
 
+// Frees a built shift's factor and sweep data (its Schur form and Krylov basis stay),
+// after taking the refinement counters of a mixed-precision factor.
+simm_status release_built_factor(simm_shift_s* sh, hipStream_t st) {
+    SIMM_HIP_TRY(hipStreamSynchronize(st));
+    if (sh->mixed && sh->ref_mem) {
+        unsigned long long eta_bits = 0;
+        SIMM_HIP_TRY(hipMemcpyAsync(sh->saved_stats, sh->rst.stats, sizeof(sh->saved_stats), hipMemcpyDeviceToHost, st));
+        SIMM_HIP_TRY(hipMemcpyAsync(&eta_bits, sh->rst.norms + 3, sizeof(eta_bits), hipMemcpyDeviceToHost, st));
+        SIMM_HIP_TRY(hipStreamSynchronize(st));
+        std::memcpy(&sh->saved_eta, &eta_bits, sizeof(double));
+    }
+    sh->release_factor();
+    return SIMM_OK;
+}
+
 // Steps 1-3 of the SIM-M algorithm (Sec. 3.5): the first shift at the centre of R, the
 // level-1 cells and their shifts.  Leaves the shifts in R and the level-1 squares
 // (cell, associated shift) in `cur`.
@@ -1044,8 +1153,14 @@ simm_status associate(simm_pencil_s* p, const simm_params* prm, const cplx* f_de
     SIMM_TRY(validate_params(prm, p->n, &nx, &ny, &K));
     const int m = prm->m;
     std::vector<simm_shift_s*> shifts;
+    simm_status release_rc = SIMM_OK;
     auto commit = [&](std::unique_ptr<simm_shift_s> s) {
         s->borrowed = true;
+        if ((prm->flags & SIMM_FLAG_RELEASE_FACTORS) && release_rc == SIMM_OK) {
+            // nothing after a shift's build reads its factor (the levels need its Schur
+            // form and basis only), so a run that releases its factors frees each one now
+            release_rc = release_built_factor(s.get(), st);
+        }
         shifts.push_back(s.get());
         R->shifts.push_back(std::move(s));
     };
@@ -1307,6 +1422,7 @@ simm_status associate(simm_pencil_s* p, const simm_params* prm, const cplx* f_de
         assoc[c] = chosen;
     }
     drop_all();
+    SIMM_TRY(release_rc);
     cur.clear();
     for (int64_t c = 0; c < ncell; ++c) cur.push_back({cells[c].first, cells[c].second, assoc[c]});
     return SIMM_OK;
@@ -3061,7 +3177,11 @@ simm_status simm_run(simm_pencil p, const simm_params* params, const double* f, 
     SIMM_HIP_TRY(hipEventCreate(&e0));
     SIMM_HIP_TRY(hipEventCreate(&e1));
     SIMM_HIP_TRY(hipEventRecord(e0, st));
-    simm_status rc = run(p, params, fd, st, R.get());
+    simm_status rc;
+    {
+        DeferFrees defer((params->flags & SIMM_FLAG_RELEASE_FACTORS) != 0);
+        rc = run(p, params, fd, st, R.get());
+    }
     (void)hipEventRecord(e1, st);
     (void)hipEventSynchronize(e1);
     float ms = 0;
@@ -3126,19 +3246,6 @@ simm_status simm_run_batch(const simm_pencil* pencils, const simm_params* params
                 SIMM_TRY(rule.make(it.prm.gauss_per_edge, st));
                 SIMM_TRY(associate(it.p, &it.prm, fd, st, it.R.get(), rule, nullptr, it.cur));
                 SIMM_HIP_TRY(hipStreamSynchronize(st));
-                if (it.prm.flags & SIMM_FLAG_RELEASE_FACTORS) {
-                    // the levels need only each shift's small data and basis
-                    for (auto& sh : it.R->shifts) {
-                        if (sh->mixed && sh->ref_mem) {
-                            unsigned long long eta_bits = 0;
-                            SIMM_HIP_TRY(hipMemcpy(sh->saved_stats, sh->rst.stats, sizeof(sh->saved_stats),
-                                                   hipMemcpyDeviceToHost));
-                            SIMM_HIP_TRY(hipMemcpy(&eta_bits, sh->rst.norms + 3, sizeof(eta_bits), hipMemcpyDeviceToHost));
-                            std::memcpy(&sh->saved_eta, &eta_bits, sizeof(double));
-                        }
-                        sh->release_factor();
-                    }
-                }
                 return SIMM_OK;
             };
             const auto t0 = std::chrono::steady_clock::now();
@@ -3155,13 +3262,12 @@ simm_status simm_run_batch(const simm_pencil* pencils, const simm_params* params
             (void)hipStreamDestroy(st);
         }
     };
+    DeferFrees defer(true);
     {
         std::vector<std::thread> pool;
         const int32_t nw = std::min(workers, count);
-        g_batches.fetch_add(1);
         for (int32_t w = 0; w < nw; ++w) pool.emplace_back(work);
         for (auto& t : pool) t.join();
-        if (g_batches.fetch_sub(1) == 1) flush_deferred_frees();
     }
     auto fail_at = [&](int32_t i, const std::string& m) {
         set_error("pencil " + std::to_string(i) + ": " + m);
@@ -3382,6 +3488,15 @@ simm_status simm_shift_refine_stats(simm_shift s, int64_t* solves, int64_t* corr
     if (solves) *solves = stats[0];
     if (corrections) *corrections = stats[1];
     if (max_eta) *max_eta = eta;
+    return SIMM_OK;
+}
+
+simm_status simm_shift_factor_info(simm_shift s, int64_t* block_len, int32_t* fallback, double* eta) {
+    clear_error();
+    if (!s) return SIMM_EINVAL;
+    if (block_len) *block_len = s->part_bs;
+    if (fallback) *fallback = s->part_fallback ? 1 : 0;
+    if (eta) *eta = s->part_eta;
     return SIMM_OK;
 }
 

@@ -8,6 +8,10 @@
 
 namespace simm {
 
+// hipMalloc that, on running out of memory, first does the frees a batch has deferred
+// and tries again (capi.hip)
+hipError_t device_malloc(void** p, size_t bytes);
+
 // ---- band LU (band_lu.hip) ----
 simm_status assemble_shifted(int64_t n, int kl, int ku, const cplx* A, int kla, int kua, const cplx* B, int klb,
                              int kub, cplx sigma, cplx* AB, hipStream_t st);
@@ -18,11 +22,15 @@ size_t band_lu_panel_elems(int64_t n, int kl);
 // With `cancel`, the launches are enqueued a few hundred at a time and enqueuing
 // stops (SIMM_ECANCELED, the factor left incomplete) once *cancel is set.
 // `launches` (may be NULL) receives the number of panel launches enqueued.
+// bs > 0 (a multiple of 16, below n): the matrix is taken as block diagonal with
+// diagonal blocks of bs columns (the last one shorter), each factored on its own, all in
+// the same launches; the band must hold zeros outside the blocks.  The result is the
+// LU (pivots as global rows) that the whole-matrix factorization gives for such a matrix.
 simm_status band_lu(int64_t n, int kl, int ku, cplx* AB, int* ipiv, cplx* LP, int* info, hipStream_t st,
-                    const std::atomic<bool>* cancel = nullptr, int64_t* launches = nullptr);
+                    const std::atomic<bool>* cancel = nullptr, int64_t* launches = nullptr, int64_t bs = 0);
 // the same factorization in FP32 arithmetic and storage (the mixed-precision factor)
 simm_status band_lu(int64_t n, int kl, int ku, cplxf* AB, int* ipiv, cplxf* LP, int* info, hipStream_t st,
-                    const std::atomic<bool>* cancel = nullptr, int64_t* launches = nullptr);
+                    const std::atomic<bool>* cancel = nullptr, int64_t* launches = nullptr, int64_t bs = 0);
 simm_status assemble_shifted(int64_t n, int kl, int ku, const cplx* A, int kla, int kua, const cplx* B, int klb,
                              int kub, cplx sigma, cplxf* AB, hipStream_t st);
 
@@ -117,10 +125,39 @@ struct SpikeFactor {
     cplx *goutL = nullptr, *goutU = nullptr, *tgL = nullptr, *tgU = nullptr;
     unsigned* counter = nullptr;   // G + 1 counters
     int* err = nullptr;
+    // partitioned factorization (band_part.hip): A - sigma B = D + E with D block diagonal
+    // (diagonal blocks of bs columns, the last one shorter) and E the couplings of
+    // neighbouring blocks; the factor above is D's.  A solve is g = D^{-1} u, the reduced
+    // system of the spike tips z = R^{-1} tips(g), and y = g - V t - W b.
+    int64_t bs = 0, nbk = 0;       // block length (0: not partitioned) and block count
+    int pkl = 0, pku = 0;          // kl, ku of A - sigma B (widths of the couplings)
+    int64_t nr = 0;                // order of the reduced system, (nbk - 1)(pkl + pku)
+    const cplx* cpl = nullptr;     // couplings per boundary: pku x pku (above), pkl x pkl (below)
+    cplx* Vs = nullptr;            // n16 x pku: D^{-1} (upper couplings), column-major
+    cplx* Ws = nullptr;            // n16 x pkl: D^{-1} (lower couplings), column-major
+    cplx* Rinv = nullptr;          // nr x nr, by rows: the reduced system's inverse
+    cplx* pg = nullptr;            // n16: D^{-1} u of an application
+    cplx* pz = nullptr;            // nr : the tips of the solution
+    void* part_mem = nullptr;
 };
 int64_t spike_chunk_len(int64_t n, int kl, int K);
 simm_status spike_prepare(SpikeFactor& f, hipStream_t st);
 simm_status spike_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int* active, hipStream_t st);
+// an application with D's factor alone (the whole factor when not partitioned)
+simm_status spike_apply_diag(const SpikeFactor& f, const cplx* u, cplx* y, const int* active, hipStream_t st);
+
+// ---- partitioned factorization (band_part.hip) ----
+constexpr int64_t kPartMaxReduced = 2048;   // largest reduced order (its inverse is nr^2 entries)
+// block length of the partitioned factorization of an order-n band (0: factor it whole)
+int64_t part_block_len(int64_t n, int kl, int ku);
+// copies the couplings of the diagonal blocks out of the assembled band (into cpl,
+// nbk - 1 boundaries of ku^2 + kl^2 entries) and zeroes them there
+simm_status part_cut(int64_t n, int kl, int ku, cplx* AB, int64_t bs, cplx* cpl, hipStream_t st);
+simm_status part_cut(int64_t n, int kl, int ku, cplxf* AB, int64_t bs, cplx* cpl, hipStream_t st);
+size_t part_cpl_elems(int64_t n, int kl, int ku, int64_t bs);
+// spikes, the reduced system and its inverse of a prepared D factor (f.bs, f.cpl set)
+simm_status part_prepare(SpikeFactor& f, hipStream_t st);
+simm_status part_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int* active, hipStream_t st);
 void spike_release(SpikeFactor& f);
 simm_status spike_clone_scratch(const SpikeFactor& base, SpikeFactor& out, hipStream_t st);
 int64_t spike_bytes_per_apply(const SpikeFactor& f);
@@ -147,6 +184,10 @@ simm_status band_inf_norm(int64_t n, const cplx* A, int kla, int kua, const cplx
                           unsigned long long* scratch, double* host, hipStream_t st);
 simm_status refine_apply(const SpikeFactor& f, const RefinePencil& pen, const RefineState& rs, const cplx* u, cplx* y,
                          const int* active, hipStream_t st);
+// normwise backward error ||u - C x||_inf / (||C||_inf ||x||_inf + ||u||_inf) of one solve
+// x = C^{-1} u with the factor f (u a fixed dense vector; pen.cnorm = ||C||_inf); synchronous
+simm_status solve_backward_error(const SpikeFactor& f, const RefinePencil& pen, double* eta, hipStream_t st);
+constexpr double kPartTol = 1e-13;     // largest backward error accepted from a partitioned factor
 __global__ void k_fill_u64(unsigned long long* p, int count);
 
 // ---- Gram-Schmidt (arnoldi.hip) ----

@@ -9,6 +9,9 @@
 // next kernels read), so an application never waits for the host; a step that is not
 // needed returns at once.  If the tolerance is not met within the allowed steps an
 // error flag is raised and the shift is rebuilt with an FP64 factor by the caller.
+#include <cmath>
+#include <cstring>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -137,6 +140,47 @@ simm_status band_inf_norm(int64_t n, const cplx* A, int kla, int kua, const cplx
     SIMM_HIP_TRY(hipMemcpyAsync(&bits, out, sizeof(bits), hipMemcpyDeviceToHost, st));
     SIMM_HIP_TRY(hipStreamSynchronize(st));
     std::memcpy(host, &bits, sizeof(double));
+    return SIMM_OK;
+}
+
+// u_i = 1 + ((i mod 7) - 3) / 4 + i ((i mod 5) - 2) / 3: a fixed right-hand side with no
+// zero entries and no structure aligned with a block partition
+__global__ __launch_bounds__(256) void k_probe_rhs(int64_t n, cplx* __restrict__ u) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) u[i] = mk(1.0 + (double)((i % 7) - 3) / 4.0, (double)((i % 5) - 2) / 3.0);
+}
+
+simm_status solve_backward_error(const SpikeFactor& f, const RefinePencil& pen, double* eta, hipStream_t st) {
+    const int64_t n = f.n;
+    const int64_t n16 = (n + 15) / 16 * 16;
+    void* mem = nullptr;
+    SIMM_HIP_TRY(device_malloc(&mem, sizeof(cplx) * 3 * (size_t)n16 + 256));
+    struct Free {
+        void* q;
+        ~Free() { (void)hipFree(q); }
+    } fr{mem};
+    cplx* u = reinterpret_cast<cplx*>(mem);
+    cplx* x = u + n16;
+    cplx* r = x + n16;
+    unsigned long long* norms = reinterpret_cast<unsigned long long*>(r + n16);
+    int* gate = reinterpret_cast<int*>(norms + 4);
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_probe_rhs, dim3(blocks), dim3(256), 0, st, n, u);
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, norms, 4);
+    const int one = 1;
+    SIMM_HIP_TRY(hipMemcpyAsync(gate, &one, sizeof(int), hipMemcpyHostToDevice, st));
+    SIMM_TRY(spike_apply(f, u, x, nullptr, st));
+    hipLaunchKernelGGL(k_band_resid, dim3(blocks), dim3(256), 0, st, n, pen.A, pen.kla, pen.kua, pen.B, pen.klb,
+                       pen.kub, pen.sigma, (const cplx*)u, (const cplx*)x, r, norms, (const int*)gate);
+    SIMM_HIP_TRY(hipGetLastError());
+    unsigned long long nb[3] = {0, 0, 0};
+    SIMM_HIP_TRY(hipMemcpyAsync(nb, norms, sizeof(nb), hipMemcpyDeviceToHost, st));
+    SIMM_HIP_TRY(hipStreamSynchronize(st));
+    double v[3];
+    std::memcpy(v, nb, sizeof(v));
+    const double den = pen.cnorm * v[1] + v[2];
+    *eta = den > 0.0 ? v[0] / den : 0.0;
+    if (!std::isfinite(v[0]) || !std::isfinite(v[1])) *eta = INFINITY;
     return SIMM_OK;
 }
 

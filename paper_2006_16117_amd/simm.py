@@ -75,6 +75,7 @@ EXPORTS = {
     "simm_pencil_destroy": (None, [_vp]),
     "simm_shift_build": (C.c_int, [_vp, _d, _d, _vp, _i32, _i32, _i32, _vp, C.POINTER(_vp)]),
     "simm_shift_refine_stats": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "simm_shift_factor_info": (C.c_int, [_vp, _vp, _vp, _vp]),
     "simm_shift_from_hessenberg": (C.c_int, [_d, _d, _d, _vp, _i32, _vp, C.POINTER(_vp)]),
     "simm_shift_info": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "simm_shift_basis": (C.c_int, [_vp, _vp, _i32, _vp]),
@@ -227,6 +228,13 @@ class Shift:
         eta = C.c_double()
         _check(_lib.simm_shift_refine_stats(self.handle, C.addressof(sv), C.addressof(co), C.addressof(eta)))
         return dict(solves=sv.value, corrections=co.value, max_eta=eta.value)
+
+    def factor_info(self):
+        bl = C.c_int64()
+        fb = C.c_int32()
+        eta = C.c_double()
+        _check(_lib.simm_shift_factor_info(self.handle, C.addressof(bl), C.addressof(fb), C.addressof(eta)))
+        return dict(block_len=bl.value, fallback=bool(fb.value), eta=eta.value)
 
     def apply(self, x, y, stream=None):
         px, mem = _ptr(x)

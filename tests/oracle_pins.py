@@ -528,3 +528,32 @@ def check_p18_decision_margin(O):
         else:
             flipped = _outcomes(nsf, nsc * S if base[2] else nsc / S, Tf, rho, p)[2] != base[2]
         assert flipped, (nsf, nsc, Tf, rho, mg)
+
+
+# P19 -- the banded form of the gradient (LAPACK band LU per node, conjugate-transposed
+# band solves for the adjoint) against the dense form pinned by P17, on the same
+# n = 60 case with A, B and A1 given in band layout.  Both evaluate the same formulas, so
+# they agree to rounding: J and dJ/dp to 1e-12 relative, dJ/dA_ii to 1e-12 of the largest.
+def _dense_to_band(M, kl, ku):
+    n = M.shape[0]
+    band = np.zeros((kl + ku + 1, n), dtype=np.complex128, order="F")
+    for j in range(n):
+        for i in range(max(0, j - ku), min(n, j + kl + 1)):
+            band[ku + i - j, j] = M[i, j]
+    return band
+
+
+def check_p19_gradient_banded(O):
+    pen, f = random_band_pencil(60, 2, 7, b_kind="tridiag", b_offdiag=0.2)
+    A, A1, B, f2, squares = gradient_case(O)
+    assert np.array_equal(f, f2)
+    # A1 of gradient_case: diagonal plus first superdiagonal
+    assert np.count_nonzero(np.tril(A1, -1)) == 0 and np.count_nonzero(np.triu(A1, 2)) == 0
+    a1_band = _dense_to_band(A1, 0, 1)
+    g = 8
+    J, dp, gd = O.projected_norms_gradient(A, A1, B, f, squares, g)
+    Jb, dpb, gdb = O.projected_norms_gradient_banded(pen.n, pen.kl_a, pen.ku_a, pen.a_band, pen.kl_b, pen.ku_b,
+                                                     pen.b_band, 0, 1, a1_band, f, squares, g)
+    assert abs(Jb - J) <= 1e-12 * J, (Jb, J)
+    assert abs(dpb - dp) <= 1e-12 * abs(dp), (dpb, dp)
+    assert np.max(np.abs(gdb - gd)) <= 1e-12 * np.max(np.abs(gd)), np.max(np.abs(gdb - gd))

@@ -79,6 +79,112 @@ def test_shift_build_matches_oracle(S, case):
         assert np.min(np.abs(ro - r)) <= 1e-8 * max(1.0, abs(r))
 
 
+# ---------------------------------------------------------------------------
+# partitioned factorization: diagonal blocks factored side by side, spikes, reduced system
+# ---------------------------------------------------------------------------
+PART_CASES = [
+    # name, n, kl, ku, seed, b_kind, m, sigma, block length asked for, generator kwargs
+    ("k3", 3000, 3, 3, 90, "tridiag", 30, 0.1 + 0.05j, 256, {}),
+    ("k16-pivoting", 5000, 16, 16, 91, "identity", 30, 0.05 + 0.0j, 512, dict(d_half=0.05, e_scale=1.0)),
+    ("k32-ragged", 4100, 32, 32, 92, "tridiag", 30, -0.1 + 0.1j, 1024, {}),
+    ("kl8-ku3", 3000, 8, 3, 93, "identity", 25, 0.2j, 384, {}),
+    ("k64", 9000, 64, 64, 94, "tridiag", 30, 0.1j, 1024, {}),
+    ("k150", 8000, 150, 150, 95, "identity", 20, 0.05 + 0.05j, 1600, {}),
+]
+
+
+def _narrow_upper(pen, ku):
+    """The pencil with A's upper bandwidth cut to ku (diagonals above removed)."""
+    band = np.asfortranarray(pen.a_band[pen.ku_a - ku:, :])
+    return WPencil(pen.n, pen.kl_a, ku, band, pen.kl_b, pen.ku_b, pen.b_band)
+
+
+@pytest.fixture
+def part_env():
+    old = os.environ.get("SIMM_LU_PART")
+    yield os.environ
+    if old is None:
+        os.environ.pop("SIMM_LU_PART", None)
+    else:
+        os.environ["SIMM_LU_PART"] = old
+
+
+@pytest.mark.parametrize("case", PART_CASES, ids=[c[0] for c in PART_CASES])
+def test_partitioned_factor_matches_oracle(S, part_env, case):
+    name, n, kl, ku, seed, b_kind, m, sigma, bs, kw = case
+    pen, f = random_band_pencil(n, kl, seed, b_kind=b_kind, b_offdiag=0.3, **kw)
+    if ku != kl:
+        pen = _narrow_upper(pen, ku)
+    part_env["SIMM_LU_PART"] = str(bs)
+    say("partitioned factor", name, f"n={n} kl={kl} ku={ku} block={bs} m={m}")
+    P = S.Pencil.from_workload(pen)
+    sh = S.simm_shift_build(P, sigma, f, m)
+    fi = sh.factor_info()
+    say("  factor:", fi)
+    assert fi["block_len"] >= bs and fi["block_len"] % 16 == 0 and not fi["fallback"]
+    assert 0.0 <= fi["eta"] <= 1e-13
+    g = sh.info()
+    o = O.build_shift(pen, sigma, f, m)
+    assert g["m_eff"] == o.m_eff
+    assert abs(g["beta"] - o.beta) <= 1e-12 * o.beta
+    d = hmax_diff(g["H"], o.H)
+    say("  max |H_gpu - H_oracle| / max|H| =", d)
+    assert d <= 1e-9
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    y = np.zeros(n, np.complex128)
+    sh.apply(x, y)
+    want = O.ShiftedSolver(pen, sigma).apply_M(x)
+    err = np.linalg.norm(y - want) / np.linalg.norm(want)
+    say("  apply rel. error", err)
+    assert err <= 1e-12
+
+
+def test_partitioned_mixed_precision_refines(S, part_env):
+    pen, f = random_band_pencil(5000, 16, 96, b_kind="tridiag", b_offdiag=0.3)
+    sigma = -0.05 + 0.1j
+    part_env["SIMM_LU_PART"] = "512"
+    say("partitioned factor, FP32 blocks with refinement", "n=5000 kl=ku=16 block=512 m=30")
+    P = S.Pencil.from_workload(pen)
+    sh = S.simm_shift_build(P, sigma, f, 30, precision=S.SIMM_PREC_MIXED)
+    assert sh.factor_info()["block_len"] == 512
+    st = sh.refine_stats()
+    say("  refinement:", st)
+    assert st["solves"] >= 31 and st["max_eta"] <= 1e-12
+    g = sh.info()
+    o = O.build_shift(pen, sigma, f, 30)
+    d = hmax_diff(g["H"], o.H)
+    say("  max |H_gpu - H_oracle| / max|H| =", d)
+    assert abs(g["beta"] - o.beta) <= 1e-11 * o.beta and d <= 1e-9
+
+
+@pytest.mark.parametrize("pivot", [0.0, 1e-14], ids=["singular-block", "near-singular-block"])
+def test_partitioned_factor_falls_back(S, part_env, pivot):
+    """A diagonal block that is singular (or nearly) while A - sigma B is not: the
+    library factors the whole matrix instead, and the shift still matches the oracle."""
+    n, k, q = 2000, 2, 512
+    pen, f = random_band_pencil(n, k, 97, b_kind="identity")
+    band = pen.a_band.copy(order="F")
+    band[k + 0, q] = pivot          # A(q, q)
+    band[k + 1, q] = 0.0            # A(q + 1, q)
+    band[k + 2, q] = 0.0            # A(q + 2, q): the block's first column is (pivot, 0, ...)
+    pen = WPencil(n, k, k, band, pen.kl_b, pen.ku_b, pen.b_band)
+    A, _ = O.pencil_dense(pen)
+    assert np.linalg.cond(A) < 1e10
+    part_env["SIMM_LU_PART"] = "256"
+    say("partitioned factor fallback", f"A(q,q) = {pivot}, block 256")
+    P = S.Pencil.from_workload(pen)
+    sh = S.simm_shift_build(P, 0.0, f, 20)
+    fi = sh.factor_info()
+    say("  factor:", fi)
+    assert fi["fallback"] and fi["block_len"] == 0
+    g = sh.info()
+    o = O.build_shift(pen, 0.0, f, 20)
+    d = hmax_diff(g["H"], o.H)
+    say("  max |H_gpu - H_oracle| / max|H| =", d)
+    assert abs(g["beta"] - o.beta) <= 1e-12 * o.beta and d <= 1e-9
+
+
 def test_pivoting_really_pivots_and_apply_matches(S):
     pen, f = random_band_pencil(257, 5, 78, b_kind="tridiag", b_offdiag=0.3, d_half=0.05, e_scale=1.0)
     sigma = 0.05 - 0.02j
@@ -795,6 +901,44 @@ def test_gradient_matches_oracle_and_fd(S, case):
         fi = (Jd[2] - Jd[3]) / (2 * h)
         say("  grad_diag", i, gd[i], "central difference", fr + 1j * fi)
         assert abs(gd[i] - (fr + 1j * fi)) <= 1e-6 * scale
+
+
+def test_gradient_n100000_matches_banded_oracle(S):
+    """The differentiation workload at full size (n = 100,000, half-bandwidth 32): the
+    library's run fixes the same admissible squares as the oracle's run, and its Krylov
+    adjoint gradient over them equals the oracle's banded direct-solve gradient
+    (tests/golden/cfg4_gradient.json): J and dJ/dp to 1e-6 relative, dJ/dA_ii at the
+    stored rows (the workload's listed rows and the 20 largest) to 1e-6 of the largest."""
+    from workloads import load_config, random_band_matrix
+    gold = json.load(open(os.path.join(GOLDEN, "cfg4_gradient.json")))
+    cfg = load_config("cfg4")
+    d = cfg["differentiation"]
+    pen0, f, params = make_workload("cfg4")
+    n, k1 = pen0.n, d["k1"]
+    a1 = random_band_matrix(n, k1, d["seed"], 1.0 / np.sqrt(n))
+    kl, ku, band = S._band_sum(n, [(pen0.kl_a, pen0.ku_a, pen0.a_band), (k1, k1, d["p"] * a1)])
+    say("gradient cfg4", f"n={n} kl={kl} ku={ku} m={params['m']}")
+    P = S.Pencil(n, kl, ku, band, pen0.kl_b, pen0.ku_b, pen0.b_band)
+    prm = S.params_from_dict(params)
+    res = S.simm_run(P, f, prm)
+    assert res.K == gold["K"]
+    last = res.levels[-1]
+    adm = np.nonzero(last.decision == S.ADMISSIBLE)[0]
+    assert [[int(last.keys[i, 0]), int(last.keys[i, 1])] for i in adm] == gold["squares"]
+    used = sorted(set(int(last.shift[i]) for i in adm))
+    remap = {s: j for j, s in enumerate(used)}
+    regions = np.array([(res.K, last.keys[i, 0], last.keys[i, 1], remap[int(last.shift[i])]) for i in adm],
+                       dtype=np.int64).reshape(-1, 4)
+    shifts = [res.shift(s) for s in used]
+    J, dp, gd = S.simm_gradient(shifts, regions, prm, a1, k1, k1, n=n)
+    say("  J", J, "oracle", gold["J"], " dJ/dp", dp, "oracle", gold["dJdp"])
+    assert abs(J - gold["J"]) <= 1e-6 * gold["J"]
+    assert abs(dp - gold["dJdp"]) <= 1e-6 * abs(gold["dJdp"])
+    want = np.array([complex(*v) for v in gold["grad"]])
+    err = np.max(np.abs(gd[gold["grad_rows"]] - want)) / gold["grad_scale"]
+    say("  max |grad_diag - oracle| / max|oracle| over", len(want), "rows:", err)
+    assert err <= 1e-6
+    assert abs(np.max(np.abs(gd)) - gold["grad_scale"]) <= 1e-6 * gold["grad_scale"]
 
 
 def test_gradient_autograd_function(S):

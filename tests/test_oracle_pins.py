@@ -268,6 +268,10 @@ def test_p17_gradient():
     P.check_p17_gradient(O)
 
 
+def test_p19_gradient_banded():
+    P.check_p19_gradient_banded(O)
+
+
 def _grad_no_adjoint(A, A1, B, f, squares, g):
     # lam from (A - z B) instead of its conjugate transpose
     n = A.shape[0]
@@ -308,6 +312,31 @@ def test_planted_gradient_mistake_is_caught(name):
     mod = _mutant(**GRAD_MUTANTS[name])
     with pytest.raises(AssertionError):
         P.check_p17_gradient(mod)
+
+
+def _band_solve_plain_transpose(fac, r, adjoint=False):
+    # the adjoint systems solved with the transpose instead of the conjugate transpose
+    lu, ipiv, kl, ku = fac
+    x, info = O.lapack.zgbtrs(lu, kl, ku, r, ipiv, trans=1 if adjoint else 0)
+    return x
+
+
+def _band_factor_wrong_sign(n, kl, ku, a_band, klb, kub, b_band, z):
+    # A + z B factored instead of A - z B
+    return O._band_factor(n, kl, ku, a_band, klb, kub, b_band, -z)
+
+
+BANDED_GRAD_MUTANTS = {
+    "banded adjoint with the plain transpose": dict(_band_solve=_band_solve_plain_transpose),
+    "banded factor of A + zB": dict(_band_factor=_band_factor_wrong_sign),
+}
+
+
+@pytest.mark.parametrize("name", sorted(BANDED_GRAD_MUTANTS))
+def test_planted_banded_gradient_mistake_is_caught(name):
+    mod = _mutant(**BANDED_GRAD_MUTANTS[name])
+    with pytest.raises(AssertionError):
+        P.check_p19_gradient_banded(mod)
 
 
 @pytest.mark.parametrize("name", sorted(MULT_MUTANTS))

@@ -23,7 +23,13 @@
 //     boundaries of row i's block.
 // Pivoting never crosses a block boundary, so the caller checks the backward error of a
 // solve and factors the whole matrix instead when it is not small.
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cstdio>
 #include <cstdlib>
+#include <map>
+#include <mutex>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -244,6 +250,88 @@ __global__ __launch_bounds__(256) void k_part_correct(int64_t n, int64_t n16, in
     y[i] = acc;
 }
 
+constexpr int kSpikeStreams = 4;
+
+// The spike solves' streams: kSpikeStreams per device, made on first use and kept for
+// the life of the process (calls on several host threads share them; each call orders
+// its own work with events).
+simm_status spike_streams(hipStream_t* out) {
+    static std::mutex mu;
+    static std::map<int, std::array<hipStream_t, kSpikeStreams>> pool;
+    int dev = 0;
+    SIMM_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = pool.find(dev);
+    if (it == pool.end()) {
+        std::array<hipStream_t, kSpikeStreams> a{};
+        for (auto& x : a) SIMM_HIP_TRY(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+        it = pool.emplace(dev, a).first;
+    }
+    for (int i = 0; i < kSpikeStreams; ++i) out[i] = it->second[i];
+    return SIMM_OK;
+}
+
+simm_status spikes(const SpikeFactor& f, hipStream_t st) {
+    const int kl = f.pkl, ku = f.pku, w = kl + ku;
+    const int64_t n16 = f.n16;
+    const unsigned blocks16 = (unsigned)((n16 + 255) / 256);
+    // as many streams as hardware queues (GPU_MAX_HW_QUEUES, 4 unless set), 2 to 4:
+    // streams beyond the queues share one and their launches serialise
+    int queues = 4;
+    if (const char* e = getenv("GPU_MAX_HW_QUEUES")) queues = std::max(1, atoi(e));
+    const int ns = std::min({kSpikeStreams, w, std::max(2, queues)});
+    hipStream_t ss[kSpikeStreams] = {};
+    SIMM_TRY(spike_streams(ss));
+    hipEvent_t ev[kSpikeStreams + 1] = {};
+    SpikeFactor cl[kSpikeStreams];
+    bool have[kSpikeStreams] = {};
+    struct Release {
+        hipStream_t* s;
+        hipEvent_t* e;
+        SpikeFactor* c;
+        bool* h;
+        int ns;
+        ~Release() {
+            for (int i = 0; i < ns; ++i) {
+                if (h[i]) {
+                    (void)hipStreamSynchronize(s[i]);
+                    spike_release(c[i]);
+                }
+            }
+            for (int i = 0; i <= ns; ++i)
+                if (e[i]) (void)hipEventDestroy(e[i]);
+        }
+    } rel{ss, ev, cl, have, ns};
+    for (int i = 0; i <= ns; ++i) SIMM_HIP_TRY(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+    SIMM_HIP_TRY(hipEventRecord(ev[ns], st));   // D's sweep data is on st
+    for (int i = 0; i < ns; ++i) {
+        SIMM_HIP_TRY(hipStreamWaitEvent(ss[i], ev[ns], 0));
+        SIMM_TRY(spike_clone_scratch(f, cl[i], ss[i]));
+        have[i] = true;
+    }
+    for (int c = 0; c < w; ++c) {
+        const int i = c % ns;
+        const int which = c < ku ? 0 : 1;
+        const int k = c < ku ? c : c - ku;
+        cplx* out = (which == 0 ? f.Vs : f.Ws) + (int64_t)k * n16;
+        hipLaunchKernelGGL(k_part_rhs, dim3(blocks16), dim3(256), 0, ss[i], f.n, n16, kl, ku, f.bs, f.nbk, f.cpl,
+                           which, k, cl[i].pg);
+        SIMM_TRY(spike_apply_diag(cl[i], cl[i].pg, out, nullptr, ss[i]));
+    }
+    int err = 0;
+    for (int i = 0; i < ns; ++i) {
+        int e = 0;
+        SIMM_HIP_TRY(hipMemcpyAsync(&e, cl[i].err, sizeof(int), hipMemcpyDeviceToHost, ss[i]));
+        SIMM_HIP_TRY(hipStreamSynchronize(ss[i]));
+        err |= e;
+    }
+    if (err) {
+        set_error("partitioned factorization: a chunk-chain barrier of a spike solve timed out");
+        return SIMM_EHIP;
+    }
+    return SIMM_OK;
+}
+
 template <typename CT>
 simm_status cut_t(int64_t n, int kl, int ku, CT* AB, int64_t bs, cplx* cpl, hipStream_t st) {
     const int64_t nbk = (n + bs - 1) / bs;
@@ -287,18 +375,24 @@ simm_status part_prepare(SpikeFactor& f, hipStream_t st) {
     f.Rinv = take((size_t)nr * nr);
     f.pg = take((size_t)n16);
     f.pz = take((size_t)nr);
-    // spikes: one solve with D's factor per coupling column (D's unit-state responses
-    // are prepared; the right-hand side goes through pg)
-    const unsigned blocks16 = (unsigned)((n16 + 255) / 256);
-    for (int which = 0; which < 2; ++which) {
-        const int cols = which == 0 ? ku : kl;
-        cplx* out = which == 0 ? f.Vs : f.Ws;
-        for (int k = 0; k < cols; ++k) {
-            hipLaunchKernelGGL(k_part_rhs, dim3(blocks16), dim3(256), 0, st, f.n, n16, kl, ku, f.bs, f.nbk, f.cpl,
-                               which, k, f.pg);
-            SIMM_TRY(spike_apply_diag(f, f.pg, out + (int64_t)k * n16, nullptr, st));
-        }
-    }
+    // SIMM_PART_TIMING: the phases' times on stderr
+    const bool timing = getenv("SIMM_PART_TIMING") != nullptr;
+    const auto t0 = std::chrono::steady_clock::now();
+    auto stamp = [&](const char* what, std::chrono::steady_clock::time_point& since) {
+        if (!timing) return;
+        (void)hipStreamSynchronize(st);
+        const auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[simm part] n = %lld, %lld blocks of %lld: %s %.2f ms\n", (long long)f.n,
+                     (long long)f.nbk, (long long)f.bs, what,
+                     std::chrono::duration<double, std::milli>(now - since).count());
+        since = now;
+    };
+    auto tp = t0;
+    // spikes: one solve with D's factor per coupling column, the columns dealt to
+    // kSpikeStreams streams (each with its own sweep scratch and right-hand side), since
+    // one solve is a chain of latency-bound launches that fills little of the device
+    SIMM_TRY(spikes(f, st));
+    stamp("spikes", tp);
     // the reduced system, its band LU and its inverse
     const int ldr = 2 * klr + kur + 1;
     cplx *ABr = nullptr, *LPr = nullptr;
@@ -324,6 +418,7 @@ simm_status part_prepare(SpikeFactor& f, hipStream_t st) {
                        n16, (const cplx*)f.Vs, (const cplx*)f.Ws, ABr, klr, kur);
     SIMM_HIP_TRY(hipGetLastError());
     SIMM_TRY(band_lu(nr, klr, kur, ABr, ipr, LPr, info, st));
+    stamp("reduced system and its LU", tp);
     int info_h = 0;
     SIMM_HIP_TRY(hipMemcpyAsync(&info_h, info, sizeof(int), hipMemcpyDeviceToHost, st));
     SIMM_HIP_TRY(hipStreamSynchronize(st));
@@ -335,6 +430,7 @@ simm_status part_prepare(SpikeFactor& f, hipStream_t st) {
                        (const cplx*)ABr, (const int*)ipr, f.Rinv);
     SIMM_HIP_TRY(hipGetLastError());
     SIMM_HIP_TRY(hipStreamSynchronize(st));
+    stamp("reduced inverse", tp);
     return SIMM_OK;
 }
 

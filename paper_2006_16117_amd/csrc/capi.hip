@@ -82,6 +82,8 @@ hipError_t device_malloc(void** p, size_t bytes) {
     return hipMalloc(p, bytes);
 }
 
+constexpr int64_t kGsRowBlocks = 1024;
+
 // While one is alive, frees through release_device are collected (runs that release
 // their factors shift by shift, batches); the last one to end frees them.
 struct DeferFrees {
@@ -685,6 +687,14 @@ simm_status apply_inverse(const simm_shift_s* s, const cplx* u, cplx* y, const i
     return spike_apply(s->spike, u, y, active, st);
 }
 
+// Row blocks of the Gram-Schmidt kernels (the passes over V_j are bound by HBM: several
+// workgroups per compute unit keep enough loads in flight); SIMM_GS_BLOCKS overrides.
+int gs_row_blocks(int64_t n) {
+    int64_t b = kGsRowBlocks;
+    if (const char* e = getenv("SIMM_GS_BLOCKS")) b = std::max<int64_t>(1, atoll(e));
+    return (int)std::min<int64_t>(b, std::max<int64_t>(1, (n + 63) / 64));
+}
+
 // Krylov phase of one shift (hot-path steps a3-a5) on a factored shift: the
 // partitioned-sweep data of the factor (a launch wide enough to fill the device, so
 // it runs here rather than beside other work), b, beta, the Arnoldi basis V_{m+1}
@@ -707,7 +717,7 @@ simm_status krylov_shift(simm_shift_s* s, const cplx* f_dev, int m, hipStream_t 
     SIMM_HIP_TRY(hipMemsetAsync(s->H, 0, sizeof(cplx) * (m + 1) * m, st));
 
     // scratch: Arnoldi work; flags
-    const int nblk = (int)std::min<int64_t>(256, std::max<int64_t>(1, (n + 63) / 64));
+    const int nblk = gs_row_blocks(n);
     const int64_t rows = (n + nblk - 1) / nblk;
     const int nblk_eff = (int)((n + rows - 1) / rows);
     DevBuf work;

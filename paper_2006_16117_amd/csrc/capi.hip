@@ -1487,18 +1487,21 @@ simm_status level_loop(simm_pencil_s* p, const simm_params* prm, hipStream_t st,
             if (eo.decision[r] == SIMM_UNRESOLVED) pend.push_back(r);
         std::map<int64_t, std::vector<int>> cand;
         for (int64_t r : pend) cand[r] = shift_order(shifts, cell_center(prm, k, cur[r].ix, cur[r].iy), cur[r].s);
-        for (size_t round = 0; !pend.empty(); ++round) {
-            std::vector<int64_t> tryr;
-            std::vector<int64_t> tregs;
+        // rounds of 1, 2, 4, ... candidates per square (each round one launch): a square
+        // takes the first of its candidates, in nearest-first order, that resolves it, so
+        // the outcome is that of trying them one at a time
+        for (size_t lo = 0, width = 1; !pend.empty(); lo += width, width *= 2) {
+            std::vector<int64_t> tryr, tregs;   // tryr: square of each row
+            std::vector<size_t> gbeg;           // first row of each pending square's group
             for (int64_t r : pend) {
-                if (round < cand[r].size()) {
+                gbeg.push_back(tryr.size());
+                const auto& cr = cand[r];
+                for (size_t c = lo; c < std::min(cr.size(), lo + width); ++c) {
                     tryr.push_back(r);
-                    tregs.push_back(k);
-                    tregs.push_back(cur[r].ix);
-                    tregs.push_back(cur[r].iy);
-                    tregs.push_back(cand[r][round]);
+                    tregs.insert(tregs.end(), {(int64_t)k, cur[r].ix, cur[r].iy, (int64_t)cr[c]});
                 }
             }
+            gbeg.push_back(tryr.size());
             if (tryr.empty()) break;
             cplx* fb_dev = nullptr;
             if (do_proj) {
@@ -1511,9 +1514,16 @@ simm_status level_loop(simm_pencil_s* p, const simm_params* prm, hipStream_t st,
                 SIMM_TRY(evaluate(shifts, tregs, prm, rule, st, e2, fb_dev, m_sums, clk));
             }
             std::vector<int64_t> still;
-            for (size_t q = 0; q < tryr.size(); ++q) {
-                const int64_t r = tryr[q];
-                if (e2.decision[q] != SIMM_UNRESOLVED) {
+            for (size_t g = 0; g + 1 < gbeg.size(); ++g) {
+                const int64_t r = pend[g];
+                size_t hit = gbeg[g + 1];
+                for (size_t q = gbeg[g]; q < gbeg[g + 1]; ++q)
+                    if (e2.decision[q] != SIMM_UNRESOLVED) {
+                        hit = q;
+                        break;
+                    }
+                if (hit < gbeg[g + 1]) {
+                    const size_t q = hit;
                     eo.indicator[r] = e2.indicator[q];
                     eo.rho[r] = e2.rho[q];
                     eo.nsf[r] = e2.nsf[q];
@@ -1524,17 +1534,11 @@ simm_status level_loop(simm_pencil_s* p, const simm_params* prm, hipStream_t st,
                     if (do_proj)
                         SIMM_HIP_TRY(hipMemcpyAsync(sums_dev + (size_t)r * 2 * m_sums, fb_dev + q * 2 * m_sums,
                                                     sizeof(cplx) * 2 * m_sums, hipMemcpyDeviceToDevice, st));
-                } else {
-                    still.push_back(r);
+                } else if (gbeg[g + 1] > gbeg[g]) {
+                    still.push_back(r);   // candidates left to try
                 }
             }
-            std::vector<int64_t> next;
-            for (int64_t r : pend) {
-                bool tried = std::find(tryr.begin(), tryr.end(), r) != tryr.end();
-                bool ok = tried && std::find(still.begin(), still.end(), r) == still.end();
-                if (!ok && (tried || round < cand[r].size())) next.push_back(r);
-            }
-            pend.swap(next);
+            pend.swap(still);
         }
         R->counters[0] += N * 12 * (int64_t)prm->gauss_per_edge;
         R->counters[1] += N;
@@ -2058,23 +2062,35 @@ simm_status run_batch_levels(std::vector<BatchItem>& items, hipStream_t st) {
         auto pencil_of = [&](int64_t r) {
             return (int)(std::upper_bound(first.begin(), first.end(), r) - first.begin()) - 1;
         };
-        for (size_t round = 0; !pend.empty(); ++round) {
+        // rounds of 1, 2, 4, ... candidates per square, as in the single-pencil loop
+        for (size_t lo = 0, width = 1; !pend.empty(); lo += width, width *= 2) {
             std::vector<int64_t> tryr, trows;
+            std::vector<size_t> gbeg;
             for (int64_t r : pend) {
-                if (round < cand[r].size()) {
-                    const int i = pencil_of(r);
+                gbeg.push_back(tryr.size());
+                const auto& cr = cand[r];
+                const int i = pencil_of(r);
+                for (size_t c = lo; c < std::min(cr.size(), lo + width); ++c) {
                     tryr.push_back(r);
                     trows.insert(trows.end(), {(int64_t)k, rows[5 * r + 1], rows[5 * r + 2],
-                                               items[i].soff + cand[r][round], (int64_t)i});
+                                               items[i].soff + cr[c], (int64_t)i});
                 }
             }
+            gbeg.push_back(tryr.size());
             if (tryr.empty()) break;
             EvalOut e2;
             SIMM_TRY(fb_eval.run(trows, st, e2));
             std::vector<int64_t> still;
-            for (size_t q = 0; q < tryr.size(); ++q) {
-                const int64_t r = tryr[q];
-                if (e2.decision[q] != SIMM_UNRESOLVED) {
+            for (size_t g = 0; g + 1 < gbeg.size(); ++g) {
+                const int64_t r = pend[g];
+                size_t hit = gbeg[g + 1];
+                for (size_t q = gbeg[g]; q < gbeg[g + 1]; ++q)
+                    if (e2.decision[q] != SIMM_UNRESOLVED) {
+                        hit = q;
+                        break;
+                    }
+                if (hit < gbeg[g + 1]) {
+                    const size_t q = hit;
                     eo.indicator[r] = e2.indicator[q];
                     eo.rho[r] = e2.rho[q];
                     eo.nsf[r] = e2.nsf[q];
@@ -2085,17 +2101,11 @@ simm_status run_batch_levels(std::vector<BatchItem>& items, hipStream_t st) {
                     if (do_proj)
                         SIMM_HIP_TRY(hipMemcpyAsync(main_eval.sums + (size_t)r * 2 * m, fb_eval.sums + q * 2 * m,
                                                     sizeof(cplx) * 2 * m, hipMemcpyDeviceToDevice, st));
-                } else {
+                } else if (gbeg[g + 1] > gbeg[g]) {
                     still.push_back(r);
                 }
             }
-            std::vector<int64_t> next;
-            for (int64_t r : pend) {
-                const bool tried = std::find(tryr.begin(), tryr.end(), r) != tryr.end();
-                const bool ok = tried && std::find(still.begin(), still.end(), r) == still.end();
-                if (!ok && (tried || round < cand[r].size())) next.push_back(r);
-            }
-            pend.swap(next);
+            pend.swap(still);
         }
         // level records
         for (int i = 0; i < nb; ++i) {

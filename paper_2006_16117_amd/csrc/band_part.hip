@@ -252,22 +252,26 @@ __global__ __launch_bounds__(256) void k_part_correct(int64_t n, int64_t n16, in
 
 constexpr int kSpikeStreams = 4;
 
-// The spike solves' streams: kSpikeStreams per device, made on first use and kept for
-// the life of the process (calls on several host threads share them; each call orders
-// its own work with events).
+// The spike solves' streams: a pool of kPoolStreams per device, made on first use and
+// kept for the life of the process.  Each call takes the next kSpikeStreams of them in
+// turn, so that calls from several host threads (runs of a batch, factors built ahead)
+// mostly get streams of their own; each call orders its own work with events.
+constexpr int kPoolStreams = 16;
 simm_status spike_streams(hipStream_t* out) {
     static std::mutex mu;
-    static std::map<int, std::array<hipStream_t, kSpikeStreams>> pool;
+    static std::map<int, std::array<hipStream_t, kPoolStreams>> pool;
+    static unsigned next = 0;
     int dev = 0;
     SIMM_HIP_TRY(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lk(mu);
     auto it = pool.find(dev);
     if (it == pool.end()) {
-        std::array<hipStream_t, kSpikeStreams> a{};
+        std::array<hipStream_t, kPoolStreams> a{};
         for (auto& x : a) SIMM_HIP_TRY(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
         it = pool.emplace(dev, a).first;
     }
-    for (int i = 0; i < kSpikeStreams; ++i) out[i] = it->second[i];
+    const unsigned first = (next++ % (kPoolStreams / kSpikeStreams)) * kSpikeStreams;
+    for (int i = 0; i < kSpikeStreams; ++i) out[i] = it->second[first + i];
     return SIMM_OK;
 }
 
@@ -285,30 +289,31 @@ simm_status spikes(const SpikeFactor& f, hipStream_t st) {
     hipEvent_t ev[kSpikeStreams + 1] = {};
     SpikeFactor cl[kSpikeStreams];
     bool have[kSpikeStreams] = {};
+    // the clones' scratch comes from st's stream-ordered pool (a plain free would wait for
+    // the whole device); it is freed on st once the spike streams are done with it
     struct Release {
         hipStream_t* s;
         hipEvent_t* e;
         SpikeFactor* c;
         bool* h;
         int ns;
+        hipStream_t st;
         ~Release() {
-            for (int i = 0; i < ns; ++i) {
-                if (h[i]) {
-                    (void)hipStreamSynchronize(s[i]);
-                    spike_release(c[i]);
-                }
-            }
+            for (int i = 0; i < ns; ++i)
+                if (h[i]) (void)hipStreamSynchronize(s[i]);
+            for (int i = 0; i < ns; ++i)
+                if (h[i]) spike_release_ordered(c[i], st);
             for (int i = 0; i <= ns; ++i)
                 if (e[i]) (void)hipEventDestroy(e[i]);
         }
-    } rel{ss, ev, cl, have, ns};
+    } rel{ss, ev, cl, have, ns, st};
     for (int i = 0; i <= ns; ++i) SIMM_HIP_TRY(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
-    SIMM_HIP_TRY(hipEventRecord(ev[ns], st));   // D's sweep data is on st
     for (int i = 0; i < ns; ++i) {
-        SIMM_HIP_TRY(hipStreamWaitEvent(ss[i], ev[ns], 0));
-        SIMM_TRY(spike_clone_scratch(f, cl[i], ss[i]));
+        SIMM_TRY(spike_clone_scratch(f, cl[i], st, true));
         have[i] = true;
     }
+    SIMM_HIP_TRY(hipEventRecord(ev[ns], st));   // D's sweep data and the clones are on st
+    for (int i = 0; i < ns; ++i) SIMM_HIP_TRY(hipStreamWaitEvent(ss[i], ev[ns], 0));
     for (int c = 0; c < w; ++c) {
         const int i = c % ns;
         const int which = c < ku ? 0 : 1;
@@ -397,19 +402,22 @@ simm_status part_prepare(SpikeFactor& f, hipStream_t st) {
     const int ldr = 2 * klr + kur + 1;
     cplx *ABr = nullptr, *LPr = nullptr;
     int *ipr = nullptr, *info = nullptr;
+    // temporaries in st's order (freed there, no device-wide wait)
     struct Free {
         void* q[4];
+        hipStream_t st;
         ~Free() {
-            for (void* x : q) (void)hipFree(x);
+            for (void* x : q)
+                if (x) (void)hipFreeAsync(x, st);
         }
-    } fr{{nullptr, nullptr, nullptr, nullptr}};
-    SIMM_HIP_TRY(device_malloc((void**)&ABr, sizeof(cplx) * ((size_t)ldr * nr + 1)));
+    } fr{{nullptr, nullptr, nullptr, nullptr}, st};
+    SIMM_HIP_TRY(device_malloc_async((void**)&ABr, sizeof(cplx) * ((size_t)ldr * nr + 1), st));
     fr.q[0] = ABr;
-    SIMM_HIP_TRY(device_malloc((void**)&LPr, sizeof(cplx) * band_lu_panel_elems(nr, klr)));
+    SIMM_HIP_TRY(device_malloc_async((void**)&LPr, sizeof(cplx) * band_lu_panel_elems(nr, klr), st));
     fr.q[1] = LPr;
-    SIMM_HIP_TRY(device_malloc((void**)&ipr, sizeof(int) * (size_t)((nr + 15) / 16 * 16)));
+    SIMM_HIP_TRY(device_malloc_async((void**)&ipr, sizeof(int) * (size_t)((nr + 15) / 16 * 16), st));
     fr.q[2] = ipr;
-    SIMM_HIP_TRY(device_malloc((void**)&info, sizeof(int)));
+    SIMM_HIP_TRY(device_malloc_async((void**)&info, sizeof(int), st));
     fr.q[3] = info;
     SIMM_HIP_TRY(hipMemsetAsync(ABr, 0, sizeof(cplx) * ((size_t)ldr * nr + 1), st));
     const int info0 = INT_MAX;

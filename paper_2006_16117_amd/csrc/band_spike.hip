@@ -883,7 +883,7 @@ simm_status spike_prepare(SpikeFactor& f, hipStream_t st) {
 // chain states, group outputs, barrier counters, error flag), so that applications of
 // one factor can run on several streams at once.  The clone shares the factor data
 // and spike_release on it frees only its own buffers.
-simm_status spike_clone_scratch(const SpikeFactor& base, SpikeFactor& out, hipStream_t st) {
+simm_status spike_clone_scratch(const SpikeFactor& base, SpikeFactor& out, hipStream_t st, bool ordered) {
     out = base;
     out.mem = nullptr;
     out.part_mem = nullptr;   // spikes and reduced inverse stay the base's
@@ -891,7 +891,8 @@ simm_status spike_clone_scratch(const SpikeFactor& base, SpikeFactor& out, hipSt
     const size_t part = base.bs > 0 ? (size_t)base.n16 + (size_t)base.nr + 32 : 0;
     const size_t elems = (size_t)base.n16 + (size_t)base.P * kl * 2 + (size_t)base.P * K * 2 +
                          (size_t)base.G * 2 * (kl + K) + (size_t)(base.G + 1) * 16 + 64 + part;
-    SIMM_HIP_TRY(device_malloc(&out.mem, sizeof(cplx) * elems + 14 * 256));
+    if (ordered) SIMM_HIP_TRY(device_malloc_async(&out.mem, sizeof(cplx) * elems + 14 * 256, st));
+    else SIMM_HIP_TRY(device_malloc(&out.mem, sizeof(cplx) * elems + 14 * 256));
     char* p = reinterpret_cast<char*>(out.mem);
     auto take = [&](size_t count) {
         char* r = p;
@@ -917,6 +918,11 @@ simm_status spike_clone_scratch(const SpikeFactor& base, SpikeFactor& out, hipSt
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, out.counter, (int)((base.G + 1) * SPIKE_CTR_STRIDE), 0u);
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;
+}
+
+void spike_release_ordered(SpikeFactor& f, hipStream_t st) {
+    if (f.mem) (void)hipFreeAsync(f.mem, st);
+    f.mem = nullptr;
 }
 
 void spike_release(SpikeFactor& f) {

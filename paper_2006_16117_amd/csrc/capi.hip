@@ -84,6 +84,22 @@ hipError_t device_malloc(void** p, size_t bytes) {
 
 constexpr int64_t kGsRowBlocks = 1024;
 
+// hipMallocAsync on st (memory used and freed, with hipFreeAsync, in the order of st, so
+// that no device-wide wait is needed), with the same retry as device_malloc.
+hipError_t device_malloc_async(void** p, size_t bytes, hipStream_t st) {
+    hipError_t e = hipMallocAsync(p, bytes, st);
+    if (e != hipErrorOutOfMemory) return e;
+    (void)hipGetLastError();
+    bool pending;
+    {
+        std::lock_guard<std::mutex> lk(g_free_mu);
+        pending = !g_free_list.empty();
+    }
+    if (!pending) return e;
+    flush_deferred_frees();
+    return hipMallocAsync(p, bytes, st);
+}
+
 // While one is alive, frees through release_device are collected (runs that release
 // their factors shift by shift, batches); the last one to end frees them.
 struct DeferFrees {

@@ -11,6 +11,8 @@ namespace simm {
 // hipMalloc that, on running out of memory, first does the frees a batch has deferred
 // and tries again (capi.hip)
 hipError_t device_malloc(void** p, size_t bytes);
+// the stream-ordered form (hipMallocAsync on st; free with hipFreeAsync on st)
+hipError_t device_malloc_async(void** p, size_t bytes, hipStream_t st);
 
 // ---- band LU (band_lu.hip) ----
 simm_status assemble_shifted(int64_t n, int kl, int ku, const cplx* A, int kla, int kua, const cplx* B, int klb,
@@ -159,7 +161,10 @@ size_t part_cpl_elems(int64_t n, int kl, int ku, int64_t bs);
 simm_status part_prepare(SpikeFactor& f, hipStream_t st);
 simm_status part_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int* active, hipStream_t st);
 void spike_release(SpikeFactor& f);
-simm_status spike_clone_scratch(const SpikeFactor& base, SpikeFactor& out, hipStream_t st);
+// ordered = true: the scratch comes from the stream-ordered allocator on st and must be
+// freed with spike_release_ordered on st
+simm_status spike_clone_scratch(const SpikeFactor& base, SpikeFactor& out, hipStream_t st, bool ordered = false);
+void spike_release_ordered(SpikeFactor& f, hipStream_t st);
 int64_t spike_bytes_per_apply(const SpikeFactor& f);
 
 // ---- mixed precision: FP64-residual refinement of FP32-factor solves (refine.hip) ----

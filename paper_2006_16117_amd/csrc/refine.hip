@@ -154,11 +154,12 @@ simm_status solve_backward_error(const SpikeFactor& f, const RefinePencil& pen, 
     const int64_t n = f.n;
     const int64_t n16 = (n + 15) / 16 * 16;
     void* mem = nullptr;
-    SIMM_HIP_TRY(device_malloc(&mem, sizeof(cplx) * 3 * (size_t)n16 + 256));
+    SIMM_HIP_TRY(device_malloc_async(&mem, sizeof(cplx) * 3 * (size_t)n16 + 256, st));
     struct Free {
         void* q;
-        ~Free() { (void)hipFree(q); }
-    } fr{mem};
+        hipStream_t st;
+        ~Free() { (void)hipFreeAsync(q, st); }
+    } fr{mem, st};
     cplx* u = reinterpret_cast<cplx*>(mem);
     cplx* x = u + n16;
     cplx* r = x + n16;

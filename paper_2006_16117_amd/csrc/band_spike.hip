@@ -29,6 +29,8 @@
 // register; per panel the rows meet once in LDS (one barrier), and the 16 values
 // every row needs are read by 16 lanes and broadcast with lane reads.  The matrix
 // is extended by identity to n16 = 16 ceil(n / 16) rows.
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -179,6 +181,13 @@ __global__ __launch_bounds__(1024) void k_blocks_bwd(int64_t n, int K, int kv, i
 // NR right-hand sides per workgroup (unit-state responses only: NR unit vectors
 // r0 .. r0+NR-1, r0 = NR blockIdx.y, share every panel block the workgroup loads;
 // zero-state sweeps use NR = 1).
+// Panels of block rows loaded ahead by the chunk sweeps: two for the single-vector
+// FP64 sweeps of up to 512 threads (a third register set of 64 VGPRs fits), else one.
+template <int T, int NR, typename GT>
+constexpr int prefetch_depth() {
+    return (NR == 1 && T <= 512 && std::is_same<GT, cplx>::value) ? 2 : 1;
+}
+
 template <int T, int NR, typename GT>
 __global__ __launch_bounds__(T) void k_chunk_fwd(SpikeFwdT<GT> a) {
     if (a.active != nullptr && *a.active == 0) return;
@@ -213,21 +222,28 @@ __global__ __launch_bounds__(T) void k_chunk_fwd(SpikeFwdT<GT> a) {
                                          : mk(pos == r0 + u ? 1.0 : 0.0, 0.0);
     }
     const int64_t p0 = J0 / 16;
-    // The block row of my next position is loaded one panel ahead, into the other
-    // of two register sets; no global load sits in a branch, so the waits for what a
-    // step consumes never wait for what it prefetches.
-    cplx gA[16], gB[16];
-    auto prefetch = [&](cplx (&g)[16], int64_t p, int ps) {
+    // The block row of my position PD panels ahead is loaded PD panels ahead, into one
+    // of PD + 1 register sets (a load takes longer than a panel step); no global load
+    // sits in a branch, so the waits for what a step consumes never wait for what it
+    // prefetches.
+    constexpr int PD = prefetch_depth<T, NR, GT>();
+    const int64_t plast = a.n16 / 16 - 1;
+    auto adv = [&](int ps) { return (ps >= 16) ? ps - 16 : ps + RW - 16; };
+    cplx gA[16], gB[16], gC[PD == 2 ? 16 : 1];
+    auto prefetch = [&](auto& g, int64_t p, int ps) {
         const GT* gp = a.G + p * 16 * RW + (mine ? ps : 0);
 #pragma unroll
         for (int q = 0; q < 16; ++q) g[q] = widen(gp[q * RW]);
     };
     prefetch(gA, p0, pos);
-    auto step = [&](int i, cplx (&gc)[16], cplx (&gn)[16]) {
+    if constexpr (PD == 2) prefetch(gB, min(p0 + 1, plast), adv(pos));
+    auto step = [&](int i, auto& gc, auto& gn) {
         const int64_t p = p0 + i;
         const int buf = i & 1;
-        const int pos_n = (pos >= 16) ? pos - 16 : pos + RW - 16;
-        prefetch(gn, min(p + 1, a.n16 / 16 - 1), pos_n);   // unconditional: no branch around loads
+        const int pos_n = adv(pos);
+        // unconditional: no branch around loads
+        if constexpr (PD == 2) prefetch(gn, min(p + 2, plast), adv(pos_n));
+        else prefetch(gn, min(p + 1, plast), pos_n);
         if (mine) {
 #pragma unroll
             for (int u = 0; u < NR; ++u) ldsw(S + (buf * NR + u) * RW + tid, val[u]);
@@ -261,11 +277,21 @@ __global__ __launch_bounds__(T) void k_chunk_fwd(SpikeFwdT<GT> a) {
         off = (off + 16 >= RW) ? off + 16 - RW : off + 16;
     };
     int i = 0;
-    for (; i + 2 <= npan; i += 2) {
-        step(i, gA, gB);
-        step(i + 1, gB, gA);
+    if constexpr (PD == 2) {
+        for (; i + 3 <= npan; i += 3) {
+            step(i, gA, gC);
+            step(i + 1, gB, gA);
+            step(i + 2, gC, gB);
+        }
+        if (i < npan) step(i, gA, gC);
+        if (i + 1 < npan) step(i + 1, gB, gA);
+    } else {
+        for (; i + 2 <= npan; i += 2) {
+            step(i, gA, gB);
+            step(i + 1, gB, gA);
+        }
+        if (i < npan) step(i, gA, gB);
     }
-    if (i < npan) step(i, gA, gB);
     // end state: rows J1 .. J1+kl-1 hold positions 0 .. kl-1
     if (mine && pos < kl) {
         if (a.mode == 0) {
@@ -327,18 +353,24 @@ __global__ __launch_bounds__(T) void k_chunk_bwd(SpikeBwdT<GT> a) {
         if (mine) val[u] = (a.mode == 0) ? ((pos < 16) ? inb[(16 * pl - K + pos) - in0] : mk(0.0, 0.0))
                                          : mk(pos - 16 == r0 + u ? 1.0 : 0.0, 0.0);
     }
-    cplx hA[16], hB[16];
-    auto prefetch = [&](cplx (&h)[16], int64_t p, int ps) {
+    // prefetch PD panels ahead, as in the forward sweep
+    constexpr int PD = prefetch_depth<T, NR, GT>();
+    auto adv = [&](int ps) { return (ps < K) ? ps + 16 : ps - K; };
+    cplx hA[16], hB[16], hC[PD == 2 ? 16 : 1];
+    auto prefetch = [&](auto& h, int64_t p, int ps) {
         const GT* hp = a.H + p * 16 * RW + (mine ? ps : 0);
 #pragma unroll
         for (int q = 0; q < 16; ++q) h[q] = widen(hp[q * RW]);
     };
     prefetch(hA, pl, pos);
-    auto step = [&](int i, cplx (&hc)[16], cplx (&hn)[16]) {
+    if constexpr (PD == 2) prefetch(hB, max(pl - 1, (int64_t)0), adv(pos));
+    auto step = [&](int i, auto& hc, auto& hn) {
         const int64_t p = pl - i;
         const int buf = i & 1;
-        const int pos_n = (pos < K) ? pos + 16 : pos - K;
-        prefetch(hn, max(p - 1, (int64_t)0), pos_n);   // unconditional: no branch around loads
+        const int pos_n = adv(pos);
+        // unconditional: no branch around loads
+        if constexpr (PD == 2) prefetch(hn, max(p - 2, (int64_t)0), adv(pos_n));
+        else prefetch(hn, max(p - 1, (int64_t)0), pos_n);
         if (mine) {
 #pragma unroll
             for (int u = 0; u < NR; ++u) ldsw(S + (buf * NR + u) * RW + tid, val[u]);
@@ -365,11 +397,21 @@ __global__ __launch_bounds__(T) void k_chunk_bwd(SpikeBwdT<GT> a) {
         off = (off >= 16) ? off - 16 : off + RW - 16;
     };
     int i = 0;
-    for (; i + 2 <= npan; i += 2) {
-        step(i, hA, hB);
-        step(i + 1, hB, hA);
+    if constexpr (PD == 2) {
+        for (; i + 3 <= npan; i += 3) {
+            step(i, hA, hC);
+            step(i + 1, hB, hA);
+            step(i + 2, hC, hB);
+        }
+        if (i < npan) step(i, hA, hC);
+        if (i + 1 < npan) step(i + 1, hB, hA);
+    } else {
+        for (; i + 2 <= npan; i += 2) {
+            step(i, hA, hB);
+            step(i + 1, hB, hA);
+        }
+        if (i < npan) step(i, hA, hB);
     }
-    if (i < npan) step(i, hA, hB);
     // end state: rows J0-K .. J0-1 hold positions 16 .. K+15
     if (mine && pos >= 16) {
         if (a.mode == 0) {

@@ -152,14 +152,19 @@ def main(names):
         t0 = time.time()
         kind = load_config(name)["generator"]["kind"]
         if kind.endswith("_batch"):
-            # the pencils are independent: several processes, one BLAS thread each
+            # the pencils are independent: several processes, one BLAS thread each;
+            # GOLDEN_PENCILS=i,j,... stores only those pencils (as <name>_subset_oracle.json)
             import multiprocessing as mp
             count = len(make_batch(name))
+            only = os.environ.get("GOLDEN_PENCILS")
+            idx = [int(v) for v in only.split(",")] if only else list(range(count))
             with mp.get_context("spawn").Pool(int(os.environ.get("GOLDEN_PROCS", "6"))) as pool:
-                runs = pool.map(_batch_run, [(name, i) for i in range(count)])
+                runs = pool.map(_batch_run, [(name, i) for i in idx], chunksize=1)
             out = {"workload": name, "generated_by": "oracle/simm.py via tests/golden/make_golden.py",
-                   "oracle_seconds": round(time.time() - t0, 1), "runs": runs}
+                   "oracle_seconds": round(time.time() - t0, 1), "pencils": idx, "runs": runs}
             summary = f"{len(runs)} pencils, {sum(len(r['clusters']) for r in runs)} clusters"
+            if only:
+                name = name + "_subset"
         else:
             pen, f, params = make_workload(name)
             res = O.simm(pen, f, params)

@@ -820,6 +820,44 @@ def test_batch_matches_sequential_and_oracle(S):
     say("  decision ties within the margin policy:", ties)
 
 
+def test_batch_of_full_size_pencils_matches_oracle(S):
+    """Eight pencils of the 64-pencil batch at full size (n = 6,153 .. 47,868, 15 to 31
+    shifts each), batched with their factors released as each shift is built: the same
+    as separate runs, bit for bit, and the oracle's stored runs (levels, decisions up to
+    the margin policy, clusters)."""
+    from workloads import make_batch
+    gold = json.load(open(os.path.join(GOLDEN, "cfg2_subset_oracle.json")))
+    full = make_batch("cfg2")
+    batch = [full[i] for i in gold["pencils"]]
+    say("simm_run_batch", "cfg2 pencils", gold["pencils"], "n =", [p.n for p, _, _ in batch])
+    pencils = [S.Pencil.from_workload(p) for p, _, _ in batch]
+    fs = [f for _, f, _ in batch]
+    prms = [S.params_from_dict(d, flags=S.SIMM_FLAG_RELEASE_FACTORS) for _, _, d in batch]
+    bat = S.simm_run_batch(pencils, fs, prms, workers=4)
+    ties = 0
+    for i, (b, g) in enumerate(zip(bat, gold["runs"])):
+        a = S.simm_run(pencils[i], fs[i], prms[i])
+        assert a.K == b.K and a.n_shifts == b.n_shifts
+        for s_ in range(a.n_shifts):
+            assert np.array_equal(a.shift(s_).info()["H"], b.shift(s_).info()["H"])
+        for La, Lb in zip(a.levels, b.levels):
+            assert np.array_equal(La.keys, Lb.keys) and np.array_equal(La.decision, Lb.decision)
+            assert np.array_equal(La.shift, Lb.shift) and np.array_equal(La.indicator, Lb.indicator)
+        assert np.array_equal(a.lam, b.lam)
+        assert b.K == g["K"] and b.n_shifts == len(g["shifts"])
+        for L, GL in zip(b.levels, g["levels"]):
+            assert [tuple(map(int, k)) for k in L.keys] == list(zip(GL["ix"], GL["iy"])), (i, L.level)
+            near = {r: mg for r, mg in GL["near"]}
+            for r in np.nonzero(L.decision != np.array(GL["decision"], np.uint8))[0]:
+                assert near.get(int(r), 1.0) < 1e-8, (i, L.level, int(r))
+                ties += 1
+        lam = np.array([complex(*c["lam"]) for c in g["clusters"]])
+        assert len(b.lam) == len(lam) and np.all(np.abs(b.lam - lam) <= 1e-14 * np.abs(lam)), i
+        say(f"  pencil {gold['pencils'][i]}: n = {batch[i][0].n}, {b.n_shifts} shifts, K = {b.K}, "
+            f"{len(b.lam)} clusters")
+    say("  decision ties within the margin policy:", ties)
+
+
 # ---------------------------------------------------------------------------
 # adjoint gradient of J = sum_R ||x_R||^2 (squares held fixed)
 # ---------------------------------------------------------------------------

@@ -167,6 +167,9 @@ struct simm_shift_s {
     // kPartTol, which part_eta records)
     int64_t part_bs = 0;
     cplx* CPL = nullptr;
+    // element capacities of V, H and the Schur data: a shift object that builds several
+    // Krylov spaces in turn (multiplicities, adjoint spaces) keeps its buffers
+    size_t cap_V = 0, cap_H = 0, cap_T = 0, cap_Q = 0, cap_g = 0;
     bool part_fallback = false;
     double part_eta = -1.0;
     // frees the n-sized data (factor, sweep data, Krylov basis); the small per-shift
@@ -192,6 +195,7 @@ struct simm_shift_s {
         ref_mem = nullptr;
         CPL = nullptr;
         V = nullptr;
+        cap_V = 0;
         spike = SpikeFactor{};
         factor_borrowed = true;   // nothing left to free
     }
@@ -659,16 +663,29 @@ simm_status prepare_sweeps(simm_shift_s* s, hipStream_t st, KernelClock* clk = n
     return SIMM_OK;
 }
 
+// p holds at least `need` elements (cap: its current capacity): kept when large enough
+template <typename T>
+simm_status ensure_dev(T** p, size_t& cap, size_t need) {
+    if (*p && cap >= need) return SIMM_OK;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    cap = 0;
+    SIMM_TRY(dalloc(p, need));
+    cap = need;
+    return SIMM_OK;
+}
+
 // Schur phase of one shift (hot-path step a5): the complex Schur form H_m = Q T Q^H of
 // the device copy of H (leading dimension ldh, s->m_eff columns), g = beta Q^H e_1,
 // the last row of Q, and the Ritz values sigma + 1/theta from the diagonal of T.
 // status_dev: one device int, the QR iteration's convergence flag.  Synchronous.
 simm_status schur_phase(simm_shift_s* s, int ldh, int* status_dev, hipStream_t st, KernelClock* clk = nullptr) {
     const int me = s->m_eff;
-    SIMM_TRY(dalloc(&s->T, (size_t)me * (me + 1) / 2));
-    SIMM_TRY(dalloc(&s->Q, (size_t)me * me));
-    SIMM_TRY(dalloc(&s->g, (size_t)me));
-    SIMM_TRY(dalloc(&s->qlast, (size_t)me));
+    size_t cap_q = s->cap_g;   // g and qlast have the same size
+    SIMM_TRY(ensure_dev(&s->T, s->cap_T, (size_t)me * (me + 1) / 2));
+    SIMM_TRY(ensure_dev(&s->Q, s->cap_Q, (size_t)me * me));
+    SIMM_TRY(ensure_dev(&s->g, s->cap_g, (size_t)me));
+    SIMM_TRY(ensure_dev(&s->qlast, cap_q, (size_t)me));
     SchurOut so{s->T, s->Q, s->g, s->qlast};
     {
         KScope ks(clk, SIMM_K_SCHUR);
@@ -728,8 +745,8 @@ simm_status krylov_shift(simm_shift_s* s, const cplx* f_dev, int m, hipStream_t 
     // partitioned-sweep data (unit-state responses of every chunk), unless the
     // factor comes prepared (from another shift, or earlier on another stream)
     if (!s->factor_borrowed && !s->sweeps_ready) SIMM_TRY(prepare_sweeps(s, st, clk));
-    SIMM_TRY(dalloc(&s->V, (size_t)n * (m + 1)));
-    SIMM_TRY(dalloc(&s->H, (size_t)(m + 1) * m));
+    SIMM_TRY(ensure_dev(&s->V, s->cap_V, (size_t)n * (m + 1)));
+    SIMM_TRY(ensure_dev(&s->H, s->cap_H, (size_t)(m + 1) * m));
     SIMM_HIP_TRY(hipMemsetAsync(s->H, 0, sizeof(cplx) * (m + 1) * m, st));
 
     // scratch: Arnoldi work; flags
@@ -2335,6 +2352,8 @@ simm_status to_device_vec(const double* src, int32_t mem, int64_t count, DevBuf&
 }
 
 // Multiplicities (Sec. 3.4) of the clusters of a finished run: see simm_multiplicities.
+constexpr int MULT_WORKERS = 4;
+
 simm_status multiplicities(simm_result_s* R, const cplx* F, int k, double rel_tol, hipStream_t st, int32_t* mult,
                            double* sv) {
     const int64_t ncl = (int64_t)R->clusters.size();
@@ -2347,49 +2366,127 @@ simm_status multiplicities(simm_result_s* R, const cplx* F, int k, double rel_to
     Rule rule;
     SIMM_TRY(rule.make(prm->gauss_per_edge, st));
     // X: n x (ncl k), column c k + i = P f_i of cluster c
-    DevBuf xb, tb, yb, gb, sb, ib;
+    DevBuf xb, gb;
     SIMM_TRY(xb.alloc(sizeof(cplx) * (size_t)n * ncl * k, st));
     SIMM_HIP_TRY(hipMemsetAsync(xb.p, 0, sizeof(cplx) * (size_t)n * ncl * k, st));
-    SIMM_TRY(tb.alloc(sizeof(cplx) * (size_t)n * ncl, st));
-    SIMM_TRY(yb.alloc(sizeof(cplx) * (size_t)m * ncl, st));
     std::vector<int> used;
     for (const auto& c : R->clusters)
         for (int64_t q : c.members) used.push_back(last.shift[q]);
     std::sort(used.begin(), used.end());
     used.erase(std::unique(used.begin(), used.end()), used.end());
-    for (int s : used) {
-        // squares of every cluster tested with shift s, grouped by cluster
+    // per shift: the squares of every cluster tested with it, grouped by cluster
+    struct ShiftSquares {
         std::vector<int64_t> regs, off{0}, idx;
+        DevBuf ib;
+    };
+    std::vector<ShiftSquares> sq(used.size());
+    bool any_mixed = false;
+    for (size_t u = 0; u < used.size(); ++u) {
+        auto& q = sq[u];
         for (const auto& c : R->clusters) {
-            for (int64_t q : c.members)
-                if (last.shift[q] == s) {
-                    idx.push_back((int64_t)regs.size() / 4);
-                    regs.insert(regs.end(), {(int64_t)R->K, last.ix[q], last.iy[q], 0});
+            for (int64_t m_ : c.members)
+                if (last.shift[m_] == used[u]) {
+                    q.idx.push_back((int64_t)q.regs.size() / 4);
+                    q.regs.insert(q.regs.end(), {(int64_t)R->K, last.ix[m_], last.iy[m_], 0});
                 }
-            off.push_back((int64_t)idx.size());
+            q.off.push_back((int64_t)q.idx.size());
         }
-        const int64_t nsq = (int64_t)idx.size();
-        SIMM_TRY(sb.alloc(sizeof(cplx) * (size_t)nsq * 2 * m, st));
-        SIMM_TRY(ib.alloc(sizeof(int64_t) * (off.size() + idx.size()), st));
-        int64_t* offd = ib.as<int64_t>();
-        int64_t* idxd = offd + off.size();
-        SIMM_HIP_TRY(hipMemcpyAsync(offd, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice, st));
-        SIMM_HIP_TRY(hipMemcpyAsync(idxd, idx.data(), sizeof(int64_t) * idx.size(), hipMemcpyHostToDevice, st));
-        const simm_shift_s* base = R->shifts[s].get();
-        for (int i = 0; i < k; ++i) {
-            // Krylov space of f_i on the shift's factor
-            simm_shift_s kv;
-            kv.borrow_factor_of(base);
-            SIMM_TRY(krylov_shift(&kv, F + (int64_t)i * n, m, st, nullptr));
-            EvalOut eo;
-            SIMM_TRY(evaluate({&kv}, regs, prm, rule, st, eo, sb.as<cplx>(), m));
-            SIMM_TRY(cluster_sums(sb.as<cplx>(), m, offd, idxd, ncl, kv.m_eff, yb.as<cplx>(), m, st));
-            SIMM_TRY(project(n, kv.m_eff, kv.V, n, yb.as<cplx>(), m, ncl, tb.as<cplx>(), nullptr, nullptr, 0,
-                             SIMM_PROJ_FP64, st));
-            SIMM_TRY(accum_cols(n, ncl, tb.as<cplx>(), xb.as<cplx>() + (int64_t)i * n, (int64_t)k * n, st));
-            SIMM_HIP_TRY(hipStreamSynchronize(st));   // kv's buffers are freed at scope exit
-        }
+        SIMM_TRY(q.ib.alloc(sizeof(int64_t) * (q.off.size() + q.idx.size()), st));
+        SIMM_HIP_TRY(hipMemcpyAsync(q.ib.p, q.off.data(), sizeof(int64_t) * q.off.size(), hipMemcpyHostToDevice, st));
+        SIMM_HIP_TRY(hipMemcpyAsync(q.ib.as<int64_t>() + q.off.size(), q.idx.data(), sizeof(int64_t) * q.idx.size(),
+                                    hipMemcpyHostToDevice, st));
+        any_mixed = any_mixed || R->shifts[used[u]]->mixed;
     }
+    SIMM_HIP_TRY(hipStreamSynchronize(st));
+    // The k Krylov spaces of a shift are independent: start vector i goes to worker i % W
+    // (a host thread with a stream of its own, the factor's per-application buffers and a
+    // shift object whose basis and Schur buffers it reuses), shifts in order, so column
+    // i of X receives its terms in the one-worker order.  Refined (mixed-precision)
+    // shifts share one refinement state per shift: one worker then.
+    const int W = any_mixed ? 1 : std::min(k, MULT_WORKERS);
+    struct Worker {
+        hipStream_t st = nullptr;
+        simm_shift_s kv;
+        DevBuf tb, yb, sb;
+        simm_status rc = SIMM_OK;
+        std::string msg;
+    };
+    std::vector<Worker> wk((size_t)W);
+    struct StreamRelease {
+        std::vector<Worker>* w;
+        ~StreamRelease() {
+            for (auto& x : *w)
+                if (x.st) {
+                    (void)hipStreamSynchronize(x.st);
+                    release_stream_buffers(x.st);
+                    (void)hipStreamSynchronize(x.st);
+                    (void)hipStreamDestroy(x.st);
+                }
+        }
+    } stream_release{&wk};
+    int64_t nsq_max = 1;
+    for (auto& q : sq) nsq_max = std::max<int64_t>(nsq_max, (int64_t)q.idx.size());
+    for (auto& x : wk) {
+        SIMM_HIP_TRY(hipStreamCreateWithFlags(&x.st, hipStreamNonBlocking));
+        SIMM_TRY(x.tb.alloc(sizeof(cplx) * (size_t)n * ncl, x.st));
+        SIMM_TRY(x.yb.alloc(sizeof(cplx) * (size_t)m * ncl, x.st));
+        SIMM_TRY(x.sb.alloc(sizeof(cplx) * (size_t)nsq_max * 2 * m, x.st));
+    }
+    SIMM_HIP_TRY(hipStreamSynchronize(st));   // X zeroed on st before the workers add to it
+    int dev = 0;
+    SIMM_HIP_TRY(hipGetDevice(&dev));
+    auto work = [&](int w) {
+        Worker& x = wk[(size_t)w];
+        (void)hipSetDevice(dev);
+        auto body = [&]() -> simm_status {
+            for (size_t u = 0; u < used.size(); ++u) {
+                const simm_shift_s* base = R->shifts[used[u]].get();
+                auto& q = sq[u];
+                const int64_t* offd = q.ib.as<int64_t>();
+                const int64_t* idxd = offd + q.off.size();
+                SpikeFactor clone{};
+                const bool own = W > 1;
+                if (own) SIMM_TRY(spike_clone_scratch(base->spike, clone, x.st, true));
+                for (int i = w; i < k; i += W) {
+                    // Krylov space of f_i on the shift's factor
+                    x.kv.borrow_factor_of(base);
+                    if (own) x.kv.spike = clone;
+                    SIMM_TRY(krylov_shift(&x.kv, F + (int64_t)i * n, m, x.st, nullptr));
+                    EvalOut eo;
+                    SIMM_TRY(evaluate({&x.kv}, q.regs, prm, rule, x.st, eo, x.sb.as<cplx>(), m));
+                    SIMM_TRY(cluster_sums(x.sb.as<cplx>(), m, offd, idxd, ncl, x.kv.m_eff, x.yb.as<cplx>(), m, x.st));
+                    SIMM_TRY(project(n, x.kv.m_eff, x.kv.V, n, x.yb.as<cplx>(), m, ncl, x.tb.as<cplx>(), nullptr,
+                                     nullptr, 0, SIMM_PROJ_FP64, x.st));
+                    SIMM_TRY(accum_cols(n, ncl, x.tb.as<cplx>(), xb.as<cplx>() + (int64_t)i * n, (int64_t)k * n, x.st));
+                }
+                if (own) {
+                    int e = 0;
+                    SIMM_HIP_TRY(hipMemcpyAsync(&e, clone.err, sizeof(int), hipMemcpyDeviceToHost, x.st));
+                    SIMM_HIP_TRY(hipStreamSynchronize(x.st));
+                    spike_release_ordered(clone, x.st);
+                    if (e) {
+                        set_error("partitioned sweep: a chunk-chain barrier timed out");
+                        return SIMM_EHIP;
+                    }
+                }
+            }
+            SIMM_HIP_TRY(hipStreamSynchronize(x.st));
+            return SIMM_OK;
+        };
+        x.rc = body();
+        if (x.rc != SIMM_OK) x.msg = simm_last_error();
+    };
+    {
+        std::vector<std::thread> pool;
+        for (int w = 1; w < W; ++w) pool.emplace_back(work, w);
+        work(0);
+        for (auto& t : pool) t.join();
+    }
+    for (auto& x : wk)
+        if (x.rc != SIMM_OK) {
+            set_error(x.msg);
+            return x.rc;
+        }
     SIMM_TRY(gb.alloc(sizeof(cplx) * (size_t)ncl * k * k, st));
     SIMM_TRY(gram(n, k, ncl, xb.as<cplx>(), gb.as<cplx>(), st));
     std::vector<cplx> G((size_t)ncl * k * k);
@@ -2486,6 +2583,7 @@ simm_status gradient(const std::vector<simm_shift_s*>& shifts, const std::vector
         hipStream_t st = nullptr;
         SpikeFactor sp;
         bool has_sp = false;
+        simm_shift_s kv;   // one adjoint space after another (its basis and Schur buffers kept)
         DevBuf xb, zb, z1b, yb, cwb, kb, pb, rhob;
         simm_status rc = SIMM_OK;
         std::string msg;
@@ -2572,7 +2670,7 @@ simm_status gradient(const std::vector<simm_shift_s*>& shifts, const std::vector
         auto square = [&](Worker& x, int w, int64_t r) -> simm_status {
             SIMM_TRY(project(n, mf, fs->V, n, sums + (2 * r + 1) * mmax, mmax, 1, x.xb.as<cplx>(), nullptr, nullptr,
                              0, SIMM_PROJ_FP64, x.st));
-            simm_shift_s kv;
+            simm_shift_s& kv = x.kv;
             kv.p = &adj;
             kv.sigma = af->sigma;
             kv.kl = af->kl;

@@ -243,23 +243,26 @@ struct simm_shift_s {
         sweeps_ready = true;
         factor_borrowed = true;
     }
+    // frees through release_device: collected while a run or batch is in flight (a
+    // dropped factor computed ahead would otherwise wait for the whole device)
     ~simm_shift_s() {
         if (!factor_borrowed) {
-            spike_release(spike);
-            (void)hipFree(CPL);
-            (void)hipFree(AB);
-            (void)hipFree(ipiv);
-            (void)hipFree(LP);
-            (void)hipFree(AB32);
-            (void)hipFree(LP32);
-            (void)hipFree(ref_mem);
+            release_device(spike.mem);
+            release_device(spike.part_mem);
+            release_device(CPL);
+            release_device(AB);
+            release_device(ipiv);
+            release_device(LP);
+            release_device(AB32);
+            release_device(LP32);
+            release_device(ref_mem);
         }
-        (void)hipFree(V);
-        (void)hipFree(H);
-        (void)hipFree(T);
-        (void)hipFree(Q);
-        (void)hipFree(g);
-        (void)hipFree(qlast);
+        release_device(V);
+        release_device(H);
+        release_device(T);
+        release_device(Q);
+        release_device(g);
+        release_device(qlast);
     }
 };
 
@@ -3313,7 +3316,9 @@ simm_status simm_run(simm_pencil p, const simm_params* params, const double* f, 
     SIMM_HIP_TRY(hipEventRecord(e0, st));
     simm_status rc;
     {
-        DeferFrees defer((params->flags & SIMM_FLAG_RELEASE_FACTORS) != 0);
+        // frees during the run (factors computed ahead and dropped, factors released
+        // per shift) are collected and done together at its end
+        DeferFrees defer(true);
         rc = run(p, params, fd, st, R.get());
     }
     (void)hipEventRecord(e1, st);

@@ -858,6 +858,37 @@ def test_batch_of_full_size_pencils_matches_oracle(S):
     say("  decision ties within the margin policy:", ties)
 
 
+def test_batch_64_pencils_matches_oracle(S):
+    """The whole 64-pencil batch (n = 2,163 .. 47,868, 1.6 M rows, 3,392 shifts), batched
+    as bench.py runs it (6 runs in flight, 2 factors ahead each, factors released per
+    shift), against the oracle's stored runs of every pencil: levels, squares, decisions
+    up to the margin policy, shift counts and clusters."""
+    from workloads import make_batch
+    gold = json.load(open(os.path.join(GOLDEN, "cfg2_oracle.json")))["runs"]
+    batch = make_batch("cfg2")
+    assert len(gold) == len(batch) == 64
+    say("simm_run_batch", "cfg2: 64 pencils, n =", sum(p.n for p, _, _ in batch))
+    pencils = [S.Pencil.from_workload(p) for p, _, _ in batch]
+    fs = [f for _, f, _ in batch]
+    prms = [S.params_from_dict(d, flags=S.SIMM_FLAG_RELEASE_FACTORS, lookahead=2) for _, _, d in batch]
+    bat = S.simm_run_batch(pencils, fs, prms, workers=6)
+    ties = squares = 0
+    for i, (b, g) in enumerate(zip(bat, gold)):
+        assert g["n"] == batch[i][0].n
+        assert b.K == g["K"] and b.n_shifts == len(g["shifts"]), i
+        for L, GL in zip(b.levels, g["levels"]):
+            assert [tuple(map(int, k)) for k in L.keys] == list(zip(GL["ix"], GL["iy"])), (i, L.level)
+            near = {r: mg for r, mg in GL["near"]}
+            for r in np.nonzero(L.decision != np.array(GL["decision"], np.uint8))[0]:
+                assert near.get(int(r), 1.0) < 1e-8, (i, L.level, int(r))
+                ties += 1
+            squares += len(L.keys)
+        lam = np.array([complex(*c["lam"]) for c in g["clusters"]])
+        assert len(b.lam) == len(lam) and np.all(np.abs(b.lam - lam) <= 1e-14 * np.abs(lam)), i
+    say(f"  {squares} squares, {sum(len(g['clusters']) for g in gold)} clusters; decision ties within the "
+        f"margin policy: {ties}")
+
+
 # ---------------------------------------------------------------------------
 # adjoint gradient of J = sum_R ||x_R||^2 (squares held fixed)
 # ---------------------------------------------------------------------------

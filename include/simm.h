@@ -191,7 +191,7 @@ simm_status simm_shift_refine_stats(simm_shift s, int64_t* solves, int64_t* corr
  * library partitions bands with kl, ku >= 1 and 2 kl + ku <= 481 of orders that give
  * blocks of at least max(1024, 4 (kl + ku)) rows, with at most 1 + 2048 / (kl + ku)
  * blocks; the environment variable SIMM_LU_PART = 0 turns it off, and a positive value
- * sets the block length.  Any pointer may be NULL. */
+ * sets the block length (rounded up to a multiple of 16, at least 256 and 2 (kl + ku)).  Any pointer may be NULL. */
 simm_status simm_shift_factor_info(simm_shift s, int64_t* block_len, int32_t* fallback, double* eta);
 
 /* A shift made from its small data alone (Sec. 2, eqs. (shiftedLS), (eq:many) and

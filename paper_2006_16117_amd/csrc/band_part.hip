@@ -44,7 +44,9 @@ int64_t part_block_len(int64_t n, int kl, int ku) {
     int64_t bs = -1;
     if (const char* e = getenv("SIMM_LU_PART")) bs = atoll(e);   // 0: never; > 0: this block length
     if (bs == 0) return 0;
-    const int64_t bmin = (2 * (int64_t)w + 15) / 16 * 16;          // each block holds both tips of its boundaries
+    // each block holds both tips of its boundaries, and a 256-row workgroup of the
+    // correction spans at most two blocks
+    const int64_t bmin = std::max<int64_t>(256, (2 * (int64_t)w + 15) / 16 * 16);
     if (bs > 0) {
         bs = std::max<int64_t>((bs + 15) / 16 * 16, bmin);
     } else {
@@ -207,47 +209,80 @@ __global__ __launch_bounds__(256) void k_part_inverse(int64_t nr, int klr, int k
     for (int64_t i = threadIdx.x; i < nr; i += blockDim.x) Rinv[i * nr + c] = y[i];
 }
 
-// z = R^{-1} tips(g): one workgroup per reduced row, terms added in a fixed order.
+// z = R^{-1} tips(g): one wavefront per reduced row (four rows a workgroup), each lane
+// summing its columns with four accumulators, then a fixed-order wave sum.
 __global__ __launch_bounds__(256) void k_part_tips(int64_t nr, int kl, int ku, int64_t bs,
                                                    const cplx* __restrict__ Rinv, const cplx* __restrict__ g,
                                                    cplx* __restrict__ z, const int* active) {
     if (active && *active == 0) return;
-    __shared__ cplx part[4];
-    const int64_t i = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= nr) return;
     const cplx* row = Rinv + i * nr;
-    cplx acc = mk(0.0, 0.0);
-    for (int64_t c = threadIdx.x; c < nr; c += 256) acc = fma_c(acc, row[c], g[tip_row(c, kl, ku, bs)]);
+    cplx acc[4] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+    int64_t c = lane;
+    for (; c + 3 * 64 < nr; c += 4 * 64) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] = fma_c(acc[u], row[c + u * 64], g[tip_row(c + u * 64, kl, ku, bs)]);
+    }
+    for (int u = 0; c < nr; c += 64, ++u) acc[u] = fma_c(acc[u], row[c], g[tip_row(c, kl, ku, bs)]);
+    cplx t = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) {
-        acc.re += __shfl_xor(acc.re, m, 64);
-        acc.im += __shfl_xor(acc.im, m, 64);
+        t.re += __shfl_xor(t.re, m, 64);
+        t.im += __shfl_xor(t.im, m, 64);
     }
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) z[i] = ((part[0] + part[1]) + part[2]) + part[3];
+    if (lane == 0) z[i] = t;
 }
 
-// y_i = g_i - sum_k V[i,k] t_j[k] - sum_k W[i,k] b_{j-1}[k], j the block of row i.
+// y_i = g_i - sum_k V[i,k] t_j[k] - sum_k W[i,k] b_{j-1}[k], j the block of row i: one
+// thread per row, the tips of the (at most two) blocks of the workgroup's rows staged in
+// LDS, four accumulators per row.
 __global__ __launch_bounds__(256) void k_part_correct(int64_t n, int64_t n16, int kl, int ku, int64_t bs,
                                                       int64_t nbk, const cplx* __restrict__ V,
                                                       const cplx* __restrict__ W, const cplx* __restrict__ z,
                                                       const cplx* __restrict__ g, cplx* __restrict__ y,
                                                       const int* active) {
     if (active && *active == 0) return;
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
+    extern __shared__ double2 zsm[];
+    cplx* zs = reinterpret_cast<cplx*>(zsm);   // 2 x (ku + kl): t_j then b_{j-1}, for blocks jb, jb + 1
     const int w = kl + ku;
+    const int64_t r0 = (int64_t)blockIdx.x * 256;
+    const int64_t jb = r0 / bs;
+    for (int e = threadIdx.x; e < 2 * w; e += 256) {
+        const int64_t j = jb + e / w;
+        const int q = e % w;
+        cplx v = mk(0.0, 0.0);
+        if (q < ku) {
+            if (j <= nbk - 2) v = z[j * w + kl + q];
+        } else {
+            if (j >= 1 && j <= nbk - 1) v = z[(j - 1) * w + (q - ku)];
+        }
+        zs[e] = v;
+    }
+    __syncthreads();
+    const int64_t i = r0 + threadIdx.x;
+    if (i >= n) return;
     const int64_t j = i / bs;
-    cplx acc = g[i];
+    const cplx* tz = zs + (j - jb) * w;         // t_j (ku values), then b_{j-1} (kl values)
+    cplx acc[4] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
     if (j <= nbk - 2) {
-        const cplx* t = z + j * w + kl;
-        for (int k = 0; k < ku; ++k) acc = fms(acc, V[i + (int64_t)k * n16], t[k]);
+        int k = 0;
+        for (; k + 3 < ku; k += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] = fma_c(acc[u], V[i + (int64_t)(k + u) * n16], tz[k + u]);
+        }
+        for (int u = 0; k < ku; ++k, ++u) acc[u] = fma_c(acc[u], V[i + (int64_t)k * n16], tz[k]);
     }
     if (j >= 1) {
-        const cplx* b = z + (j - 1) * w;
-        for (int k = 0; k < kl; ++k) acc = fms(acc, W[i + (int64_t)k * n16], b[k]);
+        int k = 0;
+        for (; k + 3 < kl; k += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] = fma_c(acc[u], W[i + (int64_t)(k + u) * n16], tz[ku + k + u]);
+        }
+        for (int u = 0; k < kl; ++k, ++u) acc[u] = fma_c(acc[u], W[i + (int64_t)k * n16], tz[ku + k]);
     }
-    y[i] = acc;
+    y[i] = g[i] - ((acc[0] + acc[1]) + (acc[2] + acc[3]));
 }
 
 constexpr int kSpikeStreams = 4;
@@ -444,9 +479,10 @@ simm_status part_prepare(SpikeFactor& f, hipStream_t st) {
 
 simm_status part_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int* active, hipStream_t st) {
     SIMM_TRY(spike_apply_diag(f, u, f.pg, active, st));
-    hipLaunchKernelGGL(k_part_tips, dim3((unsigned)f.nr), dim3(256), 0, st, f.nr, f.pkl, f.pku, f.bs,
+    hipLaunchKernelGGL(k_part_tips, dim3((unsigned)((f.nr + 3) / 4)), dim3(256), 0, st, f.nr, f.pkl, f.pku, f.bs,
                        (const cplx*)f.Rinv, (const cplx*)f.pg, f.pz, active);
-    hipLaunchKernelGGL(k_part_correct, dim3((unsigned)((f.n + 255) / 256)), dim3(256), 0, st, f.n, f.n16, f.pkl,
+    hipLaunchKernelGGL(k_part_correct, dim3((unsigned)((f.n + 255) / 256)), dim3(256),
+                       sizeof(cplx) * 2 * (size_t)(f.pkl + f.pku), st, f.n, f.n16, f.pkl,
                        f.pku, f.bs, f.nbk, (const cplx*)f.Vs, (const cplx*)f.Ws, (const cplx*)f.pz,
                        (const cplx*)f.pg, y, active);
     SIMM_HIP_TRY(hipGetLastError());

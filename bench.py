@@ -28,10 +28,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 # Hardware queues of the process (read by the HIP runtime when it starts; its default
 # is 4).  The driver computes one LU factor ahead per queue beyond the run's own (at
-# most 11), and streams beyond the queue count share queues and serialise.  Medians
-# of 6 steps on the n = 40,000 workload: 7 ahead with 8 queues ~860-930 ms, 11 ahead
-# with 12 queues ~825 ms, 11-15 ahead with 16 queues 843-864 ms.
-HW_QUEUES = int(os.environ.get("SIMM_BENCH_HW_QUEUES", "12"))
+# most 11), and streams beyond the queue count share queues and serialise.  Each
+# factor is a stream of short launches, and with more queues those launches slow the
+# run stream's own kernels more.  Means of 6 steps on the n = 40,000 workload: 7 ahead
+# with 8 queues 604 ms, 11 ahead with 12 queues 653 ms.
+HW_QUEUES = int(os.environ.get("SIMM_BENCH_HW_QUEUES", "8"))
 os.environ["GPU_MAX_HW_QUEUES"] = str(HW_QUEUES)
 
 METRIC = "resolvent solves/s + indicators/s at n=40k; speedup vs plain FP64 at 1e-6"

@@ -245,6 +245,21 @@ simm_status simm_indicators(const simm_shift* shifts, int32_t n_shifts,
                             uint8_t* decision, double* sums, int32_t m_max,
                             int32_t mem, void* hip_stream);
 
+/* Largest residual rho_max = max_j rho_j (Sec. 2, eq. (eq:error)) over the 12 g
+ * quadrature points of each of N squares of one level for one shift, from
+ * H_{m+1,m} alone (no Schur form; what the association of the level-1 cells uses, since
+ * Definition 3.1 asks only whether rho_max <= eps0).  With M_j = I + (sigma - z_j) H_m
+ * upper Hessenberg, the cofactor of M_j's (1, m) entry is the product of its
+ * subdiagonal, so
+ *   rho_j = |sigma - z_j|^m h_{m+1,m} prod_{i<m} h_{i+1,i} / |det M_j|,
+ * with det M_j by Gaussian elimination with partial pivoting (rho_j = +Inf if M_j is
+ * exactly singular, 0 if h_{m+1,m} = 0).  squares: N x 2 int64 rows (ix, iy) of level
+ * `level` (>= 1; centres as in simm_indicators); rho_max: N doubles.  Both in `mem`
+ * memory.  EINVAL: NULL arguments, level outside 1..60, N < 0, bad region;
+ * EUNSUPPORTED: gauss_per_edge > 64. */
+simm_status simm_cell_residuals(simm_shift s, int32_t level, const int64_t* squares, int64_t n_squares,
+                                const simm_params* params, double* rho_max, int32_t mem, void* hip_stream);
+
 /* Adjoint gradient of the projected-vector norms J = sum_R ||x_R||^2 over the
  * squares R of `regions` (rows as in simm_indicators), where
  * x_R = (1/2 pi i) sum_j w_j (A - z_j B)^{-1} f is the fine-rule (2 n0 points per

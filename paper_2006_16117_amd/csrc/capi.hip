@@ -681,8 +681,10 @@ simm_status ensure_dev(T** p, size_t& cap, size_t need) {
 // Schur phase of one shift (hot-path step a5): the complex Schur form H_m = Q T Q^H of
 // the device copy of H (leading dimension ldh, s->m_eff columns), g = beta Q^H e_1,
 // the last row of Q, and the Ritz values sigma + 1/theta from the diagonal of T.
-// status_dev: one device int, the QR iteration's convergence flag.  Synchronous.
-simm_status schur_phase(simm_shift_s* s, int ldh, int* status_dev, hipStream_t st, KernelClock* clk = nullptr) {
+// status_dev: one device int, the QR iteration's convergence flag.  schur_launch
+// enqueues the kernels on st; schur_finish waits for st and takes the status and the
+// Ritz values; schur_phase does both.
+simm_status schur_launch(simm_shift_s* s, int ldh, int* status_dev, hipStream_t st, KernelClock* clk = nullptr) {
     const int me = s->m_eff;
     size_t cap_q = s->cap_g;   // g and qlast have the same size
     SIMM_TRY(ensure_dev(&s->T, s->cap_T, (size_t)me * (me + 1) / 2));
@@ -690,10 +692,12 @@ simm_status schur_phase(simm_shift_s* s, int ldh, int* status_dev, hipStream_t s
     SIMM_TRY(ensure_dev(&s->g, s->cap_g, (size_t)me));
     SIMM_TRY(ensure_dev(&s->qlast, cap_q, (size_t)me));
     SchurOut so{s->T, s->Q, s->g, s->qlast};
-    {
-        KScope ks(clk, SIMM_K_SCHUR);
-        SIMM_TRY(hess_schur(s->H, ldh, me, s->beta, so, status_dev, st));
-    }
+    KScope ks(clk, SIMM_K_SCHUR);
+    return hess_schur(s->H, ldh, me, s->beta, so, status_dev, st);
+}
+
+simm_status schur_finish(simm_shift_s* s, const int* status_dev, hipStream_t st) {
+    const int me = s->m_eff;
     int schur_status = 0;
     std::vector<cplx> Tp((size_t)me * (me + 1) / 2);
     SIMM_HIP_TRY(hipMemcpyAsync(&schur_status, status_dev, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -714,6 +718,11 @@ simm_status schur_phase(simm_shift_s* s, int ldh, int* status_dev, hipStream_t s
         }
     }
     return SIMM_OK;
+}
+
+simm_status schur_phase(simm_shift_s* s, int ldh, int* status_dev, hipStream_t st, KernelClock* clk = nullptr) {
+    SIMM_TRY(schur_launch(s, ldh, status_dev, st, clk));
+    return schur_finish(s, status_dev, st);
 }
 
 // y = (A - sigma B)^{-1} u with the shift's factor: the partitioned sweeps of the FP64
@@ -737,7 +746,7 @@ int gs_row_blocks(int64_t n) {
 // and H_{m+1,m}, and the Schur data of H_m.
 simm_status krylov_shift(simm_shift_s* s, const cplx* f_dev, int m, hipStream_t st, int64_t* applies,
                          KernelClock* clk = nullptr, const std::atomic<bool>* cancel = nullptr,
-                         const std::function<void()>* before_schur = nullptr) {
+                         const std::function<void()>* before_schur = nullptr, bool defer_schur = false) {
     simm_pencil_s* p = s->p;
     s->m = m;
     const int64_t n = p->n;
@@ -845,8 +854,10 @@ simm_status krylov_shift(simm_shift_s* s, const cplx* f_dev, int m, hipStream_t 
     for (int j = 0; j < me; ++j)
         for (int i = 0; i <= me; ++i) s->H_host[i + (size_t)j * (me + 1)] = Hfull[i + (size_t)j * (m + 1)];
     s->h_last = cabs(s->H_host[me + (size_t)(me - 1) * (me + 1)]);
-    // a5: Schur form of H_m (one wavefront: the caller may start other work beside it)
+    // a5: Schur form of H_m (one wavefront: the caller may start other work beside it),
+    // unless the caller forms it later (from the device copy of H, leading dimension m + 1)
     if (before_schur) (*before_schur)();
+    if (defer_schur) return SIMM_OK;
     SIMM_TRY(schur_phase(s, m + 1, flags + 3, st, clk));
     return SIMM_OK;
 }
@@ -1217,20 +1228,70 @@ simm_status associate(simm_pencil_s* p, const simm_params* prm, const cplx* f_de
         for (int ix = 0; ix < nx; ++ix) cells.emplace_back(ix, iy);
     const int64_t ncell = (int64_t)cells.size();
     std::map<std::pair<int64_t, int>, bool> resolv;   // (cell, shift) -> resolvable
+    // Whether a shift resolves a cell (Definition 3.1) needs only the residuals of the
+    // reduced solves, which come from Hessenberg determinants of H_m (cells_resid);
+    // the Schur form of each shift built on the run's stream then runs on a side
+    // stream beside the next shift's work, and all of them are joined before the
+    // association returns (the levels need them).
+    IndicatorParams ip;
+    ip.x0 = prm->x0;
+    ip.y0 = prm->y0;
+    ip.w1 = (prm->x1 - prm->x0) / prm->n1;
+    ip.eps0 = prm->eps0;
+    ip.delta0 = prm->delta0;
+    ip.tau = prm->tau;
+    std::vector<int64_t> cells_host;
+    for (auto& c : cells) {
+        cells_host.push_back(c.first);
+        cells_host.push_back(c.second);
+    }
+    std::vector<unsigned long long> rbits_host(ncell);
+    DevBuf cells_dev, rbits_dev, schur_status;
+    SIMM_TRY(cells_dev.alloc(sizeof(int64_t) * cells_host.size(), st));
+    SIMM_TRY(rbits_dev.alloc(sizeof(unsigned long long) * ncell, st));
+    SIMM_TRY(schur_status.alloc(sizeof(int) * (ncell + 1), st));   // at most one shift per cell and the first
+    SIMM_HIP_TRY(hipMemcpyAsync(cells_dev.p, cells_host.data(), sizeof(int64_t) * cells_host.size(),
+                                hipMemcpyHostToDevice, st));
+    struct SideStream {   // declared after the buffers its kernels use: joined before they are freed
+        hipStream_t s = nullptr;
+        hipEvent_t e = nullptr;
+        ~SideStream() {
+            if (s) {
+                (void)hipStreamSynchronize(s);
+                (void)hipStreamDestroy(s);
+            }
+            if (e) (void)hipEventDestroy(e);
+        }
+    } side;
+    SIMM_HIP_TRY(hipStreamCreateWithFlags(&side.s, hipStreamNonBlocking));
+    SIMM_HIP_TRY(hipEventCreateWithFlags(&side.e, hipEventDisableTiming));
+    KernelClock side_clk;
+    side_clk.st = side.s;
+    std::vector<simm_shift_s*> schur_pending;   // shift k's status at schur_status[k]
+    auto defer_schur = [&](simm_shift_s* sh) -> simm_status {
+        SIMM_HIP_TRY(hipEventRecord(side.e, st));
+        SIMM_HIP_TRY(hipStreamWaitEvent(side.s, side.e, 0));
+        SIMM_TRY(schur_launch(sh, sh->m + 1, schur_status.as<int>() + schur_pending.size(), side.s,
+                              clk ? &side_clk : nullptr));
+        schur_pending.push_back(sh);
+        return SIMM_OK;
+    };
     auto eval_cells_vs = [&](int s) -> simm_status {
-        std::vector<int64_t> regs;
-        for (int64_t c = 0; c < ncell; ++c) {
-            regs.push_back(1);
-            regs.push_back(cells[c].first);
-            regs.push_back(cells[c].second);
-            regs.push_back(s);
-        }
-        EvalOut eo;
+        Timer t(st, &R->ms[1]);
+        const simm_shift_s* sh = shifts[s];
         {
-            Timer t(st, &R->ms[1]);
-            SIMM_TRY(evaluate(shifts, regs, prm, rule, st, eo, nullptr, 0, clk));
+            KScope ks(clk, SIMM_K_INDICATORS);
+            SIMM_TRY(cells_resid(sh->H, sh->m + 1, sh->m_eff, sh->h_last, sh->sigma, cells_dev.as<int64_t>(), ncell, 1,
+                                 ip, rule.dev, rbits_dev.as<unsigned long long>(), st));
         }
-        for (int64_t c = 0; c < ncell; ++c) resolv[{c, s}] = eo.rho[c] <= prm->eps0;
+        SIMM_HIP_TRY(hipMemcpyAsync(rbits_host.data(), rbits_dev.p, sizeof(unsigned long long) * ncell,
+                                    hipMemcpyDeviceToHost, st));
+        SIMM_HIP_TRY(hipStreamSynchronize(st));
+        for (int64_t c = 0; c < ncell; ++c) {
+            double rho;
+            std::memcpy(&rho, &rbits_host[c], sizeof rho);
+            resolv[{c, s}] = rho <= prm->eps0;
+        }
         return SIMM_OK;
     };
     // A cell gets a new shift (at its centre) iff no shift made so far resolves it.
@@ -1370,14 +1431,15 @@ simm_status associate(simm_pencil_s* p, const simm_params* prm, const cplx* f_de
     }
     // A mixed-precision shift whose refined solves miss their tolerance is rebuilt with an
     // FP64 factor (the same shift, so the run's shifts and decisions do not change).
+    // The Schur form is left to defer_schur.
     auto krylov_or_fp64 = [&](std::unique_ptr<simm_shift_s>& s, const std::function<void()>* before_schur) {
-        simm_status rc = krylov_shift(s.get(), f_dev, m, st, &R->counters[2], clk, nullptr, before_schur);
+        simm_status rc = krylov_shift(s.get(), f_dev, m, st, &R->counters[2], clk, nullptr, before_schur, true);
         if (rc != SIMM_EREFINE) return rc;
         R->refine_fallbacks += 1;
         const cplx sig = s->sigma;
         s.reset();
         SIMM_TRY(factor_shift(p, sig, st, s, clk, nullptr, SIMM_PREC_FP64));
-        return krylov_shift(s.get(), f_dev, m, st, &R->counters[2], clk, nullptr, before_schur);
+        return krylov_shift(s.get(), f_dev, m, st, &R->counters[2], clk, nullptr, before_schur, true);
     };
     // step 1: first shift at the centre of R
     {
@@ -1387,6 +1449,7 @@ simm_status associate(simm_pencil_s* p, const simm_params* prm, const cplx* f_de
             SIMM_TRY(factor_shift(p, cplx{(prm->x0 + prm->x1) / 2, (prm->y0 + prm->y1) / 2}, st, s, clk, nullptr,
                                   prm->precision));
             SIMM_TRY(krylov_or_fp64(s, nullptr));
+            SIMM_TRY(defer_schur(s.get()));
         }
         commit(std::move(s));
     }
@@ -1452,6 +1515,7 @@ simm_status associate(simm_pencil_s* p, const simm_params* prm, const cplx* f_de
                 };
                 Timer t(st, &R->ms[0]);
                 SIMM_TRY(krylov_or_fp64(s, &prep_next));
+                SIMM_TRY(defer_schur(s.get()));
             }
             // neighbours of c after it that no shift resolved before this one
             std::vector<int64_t> nb;
@@ -1469,6 +1533,12 @@ simm_status associate(simm_pencil_s* p, const simm_params* prm, const cplx* f_de
     }
     drop_all();
     SIMM_TRY(release_rc);
+    {
+        Timer t(st, &R->ms[0]);
+        for (size_t k = 0; k < schur_pending.size(); ++k)
+            SIMM_TRY(schur_finish(schur_pending[k], schur_status.as<int>() + k, side.s));
+    }
+    if (clk) side_clk.collect(R->kms, R->kcnt);
     cur.clear();
     for (int64_t c = 0; c < ncell; ++c) cur.push_back({cells[c].first, cells[c].second, assoc[c]});
     return SIMM_OK;
@@ -3066,6 +3136,61 @@ simm_status simm_shift_apply(simm_shift s, const double* x, double* y, int32_t m
 
 void simm_shift_destroy(simm_shift s) {
     if (s && !s->borrowed) delete s;
+}
+
+simm_status simm_cell_residuals(simm_shift s, int32_t level, const int64_t* squares, int64_t n_squares,
+                                const simm_params* params, double* rho_max, int32_t mem, void* hip_stream) {
+    clear_error();
+    if (!s || !params || n_squares < 0 || (n_squares > 0 && (!squares || !rho_max)) || level < 1 || level > 60) {
+        set_error("bad cell-residual arguments");
+        return SIMM_EINVAL;
+    }
+    if (mem != SIMM_MEM_HOST && mem != SIMM_MEM_DEVICE) {
+        set_error("mem must be SIMM_MEM_HOST or SIMM_MEM_DEVICE");
+        return SIMM_EINVAL;
+    }
+    if (params->gauss_per_edge < 1 || !(params->x1 > params->x0) || params->n1 < 1) {
+        set_error("bad region or gauss_per_edge < 1");
+        return SIMM_EINVAL;
+    }
+    if (params->gauss_per_edge > 64) {
+        set_error("gauss_per_edge above 64 is not supported");
+        return SIMM_EUNSUPPORTED;
+    }
+    if (n_squares == 0) return SIMM_OK;
+    if (!s->H) {
+        set_error("shift has no Arnoldi matrix");
+        return SIMM_EINVAL;
+    }
+    SIMM_TRY(check_device());
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    Rule rule;
+    SIMM_TRY(rule.make(params->gauss_per_edge, st));
+    IndicatorParams ip;
+    ip.x0 = params->x0;
+    ip.y0 = params->y0;
+    ip.w1 = (params->x1 - params->x0) / params->n1;
+    ip.eps0 = params->eps0;
+    ip.delta0 = params->delta0;
+    ip.tau = params->tau;
+    DevBuf sq_buf, out_buf;
+    const int64_t* sq_dev = squares;
+    unsigned long long* out_dev = reinterpret_cast<unsigned long long*>(rho_max);   // doubles >= 0 as bit patterns
+    if (mem == SIMM_MEM_HOST) {
+        SIMM_TRY(sq_buf.alloc(sizeof(int64_t) * 2 * (size_t)n_squares, st));
+        SIMM_TRY(out_buf.alloc(sizeof(double) * (size_t)n_squares, st));
+        SIMM_HIP_TRY(hipMemcpyAsync(sq_buf.p, squares, sizeof(int64_t) * 2 * (size_t)n_squares,
+                                    hipMemcpyHostToDevice, st));
+        sq_dev = sq_buf.as<int64_t>();
+        out_dev = out_buf.as<unsigned long long>();
+    }
+    SIMM_TRY(cells_resid(s->H, s->m + 1, s->m_eff, s->h_last, s->sigma, sq_dev, n_squares, level, ip, rule.dev, out_dev,
+                         st));
+    if (mem == SIMM_MEM_HOST) {
+        SIMM_HIP_TRY(hipMemcpyAsync(rho_max, out_dev, sizeof(double) * (size_t)n_squares, hipMemcpyDeviceToHost, st));
+        SIMM_HIP_TRY(hipStreamSynchronize(st));
+    }
+    return SIMM_OK;
 }
 
 simm_status simm_indicators(const simm_shift* shifts, int32_t n_shifts, const int64_t* regions, int64_t n_regions,

@@ -368,6 +368,154 @@ simm_status indicators_persist(const ShiftDev* shifts_dev, int mmax, const int64
     return SIMM_OK;
 }
 
+// Residuals of the reduced solves of whole cells straight from the Arnoldi matrix, for
+// the association of the level-1 cells (which needs only whether a shift resolves a
+// cell, Definition 3.1).  With M = I + (sigma - z) H_m upper Hessenberg and
+// y = beta M^{-1} e_1, the cofactor of M's (1, m) entry is the product of M's
+// subdiagonal, so e_m^T y = beta prod_{i<m} (sigma - z) h_{i+1,i} / det M and eq. (error)
+// becomes
+//     rho = |sigma - z|^m h_{m+1,m} prod_{i<m} h_{i+1,i} / |det M|.
+// det M comes from Gaussian elimination with partial pivoting on M's rows, one row after
+// another (a Hessenberg row meets only the current one), so a point needs O(m) storage:
+// the current row over the wavefront's lanes (two entries a lane), H packed in LDS.
+// Magnitudes are carried as (mantissa, exponent) pairs, so no product overflows.  Grid
+// (cells, point groups); each workgroup raises the cell's maximum (non-negative doubles
+// ordered as their bit patterns), so the result does not depend on the order.
+namespace {
+__device__ inline int hpk(int j) { return j * (j + 3) / 2; }   // packed column j: rows 0 .. min(j+1, m-1)
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_cells_resid(const cplx* __restrict__ H, int ldh, int m, double hlast,
+                                                     double sig_re, double sig_im, const int64_t* __restrict__ cells,
+                                                     int level, IndicatorParams prm, RuleDev rule, int pts_per_wg,
+                                                     unsigned long long* __restrict__ rbits) {
+    extern __shared__ double2 hsm[];
+    cplx* Hs = reinterpret_cast<cplx*>(hsm);
+    double* sub = reinterpret_cast<double*>(Hs + hpk(m));   // [0]: sum of log h_{i+1,i}, i < m-1
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j = 0; j < m; ++j) {
+        const int rows = min(j + 2, m);
+        for (int i = threadIdx.x; i < rows; i += 256) Hs[hpk(j) + i] = H[i + (int64_t)j * ldh];
+    }
+    if (wave == 0) {
+        double acc = 0.0;
+        for (int i = lane; i < m - 1; i += 64) acc += log(cabs(H[(i + 1) + (int64_t)i * ldh]));
+        acc = wave_sum_d(acc);
+        if (lane == 0) sub[0] = acc;
+    }
+    __syncthreads();
+    const double logsub = sub[0];
+    const int64_t ix = cells[2 * blockIdx.x], iy = cells[2 * blockIdx.x + 1];
+    const double width = ldexp(prm.w1, (int)(1 - level));
+    double cx, cy;
+    {
+#pragma clang fp contract(off)
+        cx = prm.x0 + ((double)ix + 0.5) * width;
+        cy = prm.y0 + ((double)iy + 0.5) * width;
+    }
+    const double h = width / 2.0;
+    const int g = rule.g;
+    const int npts = 12 * g;
+    const int q0 = blockIdx.y * pts_per_wg, q1 = min(npts, q0 + pts_per_wg);
+    const int j0 = lane, j1 = lane + 64;
+    const double ln2 = 0.6931471805599453;
+    double rmax = 0.0;
+    for (int q = q0 + wave; q < q1; q += 4) {
+        int e, idx;
+        double t, om;
+        if (q < 4 * g) {
+            e = q / g;
+            idx = q - e * g;
+            t = rule.t1[idx];
+            om = rule.w1[idx];
+        } else {
+            const int q2 = q - 4 * g;
+            e = q2 / (2 * g);
+            idx = q2 - e * 2 * g;
+            t = rule.t2[idx];
+            om = rule.w2[idx];
+        }
+        cplx z, wq;
+        node(cx, cy, h, e, t, om, z, wq);
+        const cplx al = mk(sig_re - z.re, sig_im - z.im);
+        // row 0 of M
+        cplx r0 = (j0 < m) ? al * Hs[hpk(j0)] : mk(0.0, 0.0);
+        cplx r1 = (j1 < m) ? al * Hs[hpk(j1)] : mk(0.0, 0.0);
+        if (j0 == 0) r0 = r0 + mk(1.0, 0.0);
+        double pm = 1.0;   // |det M| = pm 2^pe
+        int pe = 0;
+        bool singular = false;
+        for (int k = 0; k + 1 < m; ++k) {
+            // row k+1 of M on columns j >= k
+            cplx n0 = mk(0.0, 0.0), n1 = mk(0.0, 0.0);
+            if (j0 >= k && j0 < m) n0 = al * Hs[hpk(j0) + k + 1];
+            if (j1 >= k && j1 < m) n1 = al * Hs[hpk(j1) + k + 1];
+            if (j0 == k + 1) n0 = n0 + mk(1.0, 0.0);
+            if (j1 == k + 1) n1 = n1 + mk(1.0, 0.0);
+            const cplx rk = (k < 64) ? readlane_c(r0, k) : readlane_c(r1, k - 64);
+            const cplx nk = al * Hs[hpk(k) + k + 1];
+            const bool use_n = cabs1(nk) > cabs1(rk);
+            const cplx pk = use_n ? nk : rk, ok = use_n ? rk : nk;
+            const double mag = cabs(pk);
+            if (!(mag > 0.0)) {
+                singular = true;
+                break;
+            }
+            int ex;
+            pm = frexp(pm * mag, &ex);
+            pe += ex;
+            const cplx l = cdiv(ok, pk);
+            const cplx p0 = use_n ? n0 : r0, o0 = use_n ? r0 : n0;
+            const cplx p1 = use_n ? n1 : r1, o1 = use_n ? r1 : n1;
+            r0 = fms(o0, l, p0);
+            r1 = fms(o1, l, p1);
+        }
+        double rho;
+        if (hlast == 0.0) {
+            rho = 0.0;
+        } else {
+            const cplx last = ((m - 1) < 64) ? readlane_c(r0, m - 1) : readlane_c(r1, m - 65);
+            const double ml = cabs(last);
+            if (singular || !(ml > 0.0)) {
+                rho = INFINITY;
+            } else {
+                int ex;
+                pm = frexp(pm * ml, &ex);
+                pe += ex;
+                const double logdet = log(pm) + pe * ln2;
+                rho = exp((double)m * log(cabs(al)) + log(hlast) + logsub - logdet);
+                if (!(rho <= 1.7976931348623157e308)) rho = INFINITY;
+            }
+        }
+        rmax = fmax(rmax, rho);
+    }
+#pragma unroll
+    for (int msk = 32; msk >= 1; msk >>= 1) rmax = fmax(rmax, __shfl_xor(rmax, msk, 64));
+    if (lane == 0) atomicMax(rbits + blockIdx.x, (unsigned long long)__double_as_longlong(rmax));
+}
+
+simm_status cells_resid(const cplx* H, int ldh, int m, double hlast, cplx sigma, const int64_t* cells, int64_t ncell,
+                        int level, const IndicatorParams& prm, const RuleDev& rule, unsigned long long* rbits,
+                        hipStream_t st) {
+    if (ncell <= 0) return SIMM_OK;
+    if (ncell > INT_MAX) {
+        set_error("too many squares in one call");
+        return SIMM_EINVAL;
+    }
+    if (m < 1 || m > 128) {
+        set_error("Krylov dimension outside 1..128");
+        return SIMM_EUNSUPPORTED;
+    }
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(256), 0, st, rbits, (int)ncell);
+    constexpr int PTS = 16;   // points per workgroup: four per wavefront
+    const int groups = (12 * rule.g + PTS - 1) / PTS;
+    const size_t lds = sizeof(cplx) * (size_t)(m * (m + 3) / 2 + 2);
+    hipLaunchKernelGGL(k_cells_resid, dim3((unsigned)ncell, (unsigned)groups), dim3(256), lds, st, H, ldh, m, hlast,
+                       sigma.re, sigma.im, cells, level, prm, rule, PTS, rbits);
+    SIMM_HIP_TRY(hipGetLastError());
+    return SIMM_OK;
+}
+
 simm_status indicators(const ShiftDev* shifts_dev, int mmax, const int64_t* regions, int64_t nreg,
                        const IndicatorParams& prm, const RuleDev& rule, double* indicator, double* rho_max,
                        double* nsf, double* nsc, double* Tf, uint8_t* decision, cplx* sums, int m_sums,

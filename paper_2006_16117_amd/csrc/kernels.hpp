@@ -240,6 +240,12 @@ struct IndicatorParams {
     double x0, y0, w1;
     double eps0, delta0, tau;
 };
+// rbits[c] = the largest residual (eq. (error)) over the 12g points of level-`level`
+// cell c = (cells[2c], cells[2c+1]) for the shift (sigma, H (ldh, m columns), h_{m+1,m}),
+// from Hessenberg determinants (no Schur form); non-negative doubles as bit patterns
+simm_status cells_resid(const cplx* H, int ldh, int m, double hlast, cplx sigma, const int64_t* cells, int64_t ncell,
+                        int level, const IndicatorParams& prm, const RuleDev& rule, unsigned long long* rbits,
+                        hipStream_t st);
 simm_status indicators(const ShiftDev* shifts_dev, int mmax, const int64_t* regions, int64_t nreg,
                        const IndicatorParams& prm, const RuleDev& rule, double* indicator, double* rho_max,
                        double* nsf, double* nsc, double* Tf, uint8_t* decision, cplx* sums, int m_sums,

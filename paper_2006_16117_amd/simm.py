@@ -83,6 +83,7 @@ EXPORTS = {
     "simm_shift_destroy": (None, [_vp]),
     "simm_indicators": (C.c_int, [_vp, _i32, _vp, _i64, C.POINTER(simm_params), _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                   _i32, _i32, _vp]),
+    "simm_cell_residuals": (C.c_int, [_vp, _i32, _vp, _i64, C.POINTER(simm_params), _vp, _i32, _vp]),
     "simm_project": (C.c_int, [_vp, _vp, _i64, _vp, _vp, _i32, _vp]),
     "simm_project_noalloc": (C.c_int, [_vp, _vp, _i64, _vp, _vp, _i32, _vp]),
     "simm_gradient": (C.c_int, [_vp, _i32, _vp, _i64, C.POINTER(simm_params), _i32, _i32, _vp, _vp, _vp, _vp, _i32,
@@ -296,6 +297,15 @@ def simm_indicators(shifts, regions: np.ndarray, params: simm_params, want_sums:
                                 _stream(stream)))
     if sums is not None:
         out["sums"] = sums
+    return out
+
+
+def simm_cell_residuals(shift: Shift, level: int, squares: np.ndarray, params: simm_params, stream=None) -> np.ndarray:
+    """Host-memory form: squares (N, 2) int64 (ix, iy) of one level; returns rho_max (N)."""
+    squares = np.ascontiguousarray(squares, dtype=np.int64).reshape(-1, 2)
+    out = np.zeros(squares.shape[0])
+    _check(_lib.simm_cell_residuals(shift.handle, int(level), squares.ctypes.data, squares.shape[0], C.byref(params),
+                                    out.ctypes.data, SIMM_MEM_HOST, _stream(stream)))
     return out
 
 

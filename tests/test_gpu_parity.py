@@ -457,6 +457,82 @@ def test_indicators_on_oracle_hessenberg_cfg1(S):
     _check_indicators_on_oracle_H(S, "cfg1", regs, params, _golden_shifts("cfg1"))
 
 
+def _check_cell_residuals(S, name, params, oracle_shifts, rows, rel=1e-12):
+    """simm_cell_residuals (residuals from Hessenberg determinants, no Schur form) on
+    the oracle's (sigma, beta, H): every square's rho_max against the oracle's
+    evaluation, to rel relative down to the residual's rounding level, or, where the
+    square's systems are ill-conditioned, within the two solvers' forward-error bound;
+    and the decision rho_max <= eps0 identical unless the oracle's rho_max lies within
+    that error of eps0.  rows: (level, ix, iy, shift)."""
+    gpu_shifts = [S.simm_shift_from_hessenberg(o.sigma, o.beta, o.H) for o in oracle_shifts]
+    prm = S.params_from_dict(params)
+    rows = np.asarray(rows, np.int64)
+    got = np.zeros(len(rows))
+    for lev in np.unique(rows[:, 0]):
+        for si in np.unique(rows[:, 3]):
+            sel = np.nonzero((rows[:, 0] == lev) & (rows[:, 3] == si))[0]
+            if len(sel):
+                got[sel] = S.simm_cell_residuals(gpu_shifts[int(si)], int(lev), rows[sel, 1:3], prm)
+    worst, worst_bound, flips, bad = 0.0, 0.0, 0, []
+    for r, (k, ix, iy, si) in enumerate(rows):
+        o = oracle_shifts[int(si)]
+        c = O.square_center(params, int(k), int(ix), int(iy))
+        w = O.square_width(params, int(k))
+        ev, _, _, rho_floor = _oracle_eval_with_scales(o, c, w, params)
+        err = abs(got[r] - ev.rho_max) / max(ev.rho_max, rho_floor / rel, 1e-300)
+        tol = rel
+        if err > rel:
+            tol = max(rel, _solve_error_bound(o, c, w, params))
+            worst_bound = max(worst_bound, err / tol)
+        worst = max(worst, err)
+        if not err <= tol:
+            bad.append((r, float(got[r]), ev.rho_max, err, tol))
+        if (got[r] <= params["eps0"]) != (ev.rho_max <= params["eps0"]):
+            flips += 1
+            if not abs(ev.rho_max - params["eps0"]) <= tol * max(ev.rho_max, rho_floor / rel):
+                bad.append((r, "decision", float(got[r]), ev.rho_max))
+    say(f"  {name}: {len(rows)} squares, max rel. error of rho_max {worst:.2e} "
+        f"(conditioned squares at most {worst_bound:.2e} of their bound), resolvability flips {flips}")
+    assert not bad, bad[:10]
+
+
+def test_cell_residuals_on_oracle_hessenberg_cfg1(S):
+    """The level-1 association's residuals (Hessenberg determinants) on the oracle's H of
+    the 7 shifts of the n = 40,000 run: every level-1 cell against every shift (what the
+    association tests), and every square of levels 2-4 with the shift it was tested with."""
+    pen, f, params = make_workload("cfg1")
+    shifts = _golden_shifts("cfg1")
+    nx, ny = O.level1_grid(params)
+    rows = [(1, ix, iy, s) for s in range(len(shifts)) for iy in range(ny) for ix in range(nx)]
+    with open(os.path.join(GOLDEN, "cfg1_oracle.json")) as fh:
+        run = json.load(fh)
+    rows += [(L["level"], ix, iy, s) for L in run["levels"] if L["level"] > 1
+             for ix, iy, s in zip(L["ix"], L["iy"], L["shift"])]
+    say("cell residuals on the oracle's H", "cfg1", f"{len(rows)} squares")
+    _check_cell_residuals(S, "cfg1", params, shifts, rows)
+
+
+def test_cell_residuals_on_oracle_hessenberg_cfg0(S):
+    """The same on the n = 400 run's shifts: every level-1 cell against every shift."""
+    pen, f, params = make_workload("cfg0")
+    shifts = _golden_shifts("cfg0")
+    nx, ny = O.level1_grid(params)
+    rows = [(1, ix, iy, s) for s in range(len(shifts)) for iy in range(ny) for ix in range(nx)]
+    say("cell residuals on the oracle's H", "cfg0", f"{len(rows)} squares")
+    _check_cell_residuals(S, "cfg0", params, shifts, rows)
+
+
+def test_cell_residuals_errors(S):
+    say("cell_residuals", "argument errors")
+    pen, f, params = make_workload("cfg0")
+    sh = _golden_shifts("cfg0")[0]
+    g = S.simm_shift_from_hessenberg(sh.sigma, sh.beta, sh.H)
+    prm = S.params_from_dict(params)
+    with pytest.raises(S.SimmError):
+        S.simm_cell_residuals(g, 0, np.zeros((1, 2), np.int64), prm)     # level < 1
+    assert S.simm_cell_residuals(g, 1, np.zeros((0, 2), np.int64), prm).shape == (0,)
+
+
 def test_shift_from_hessenberg_errors(S):
     say("shift_from_hessenberg", "argument errors")
     H = np.zeros((4, 3), np.complex128)

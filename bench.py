@@ -31,8 +31,19 @@ sys.path.insert(0, ROOT)
 # most 11), and streams beyond the queue count share queues and serialise.  Each
 # factor is a stream of short launches, and with more queues those launches slow the
 # run stream's own kernels more.  Means of 6 steps on the n = 40,000 workload: 7 ahead
-# with 8 queues 604 ms, 11 ahead with 12 queues 653 ms.
-HW_QUEUES = int(os.environ.get("SIMM_BENCH_HW_QUEUES", "8"))
+# with 8 queues 604 ms, 11 ahead with 12 queues 653 ms.  The other workloads keep 12:
+# their worker and spike streams share queues with 8 (adjoint gradient at n = 100,000:
+# 430 against 340 ms).
+def _workload_arg(argv):
+    for i, a in enumerate(argv):
+        if a == "--workload" and i + 1 < len(argv):
+            return argv[i + 1]
+        if a.startswith("--workload="):
+            return a.split("=", 1)[1]
+    return "cfg1"
+
+
+HW_QUEUES = int(os.environ.get("SIMM_BENCH_HW_QUEUES", "8" if _workload_arg(sys.argv[1:]) == "cfg1" else "12"))
 os.environ["GPU_MAX_HW_QUEUES"] = str(HW_QUEUES)
 
 METRIC = "resolvent solves/s + indicators/s at n=40k; speedup vs plain FP64 at 1e-6"

@@ -343,20 +343,28 @@ simm_status spikes(const SpikeFactor& f, hipStream_t st) {
         }
     } rel{ss, ev, cl, have, ns, st};
     for (int i = 0; i <= ns; ++i) SIMM_HIP_TRY(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+    // up to four coupling columns of one kind per solve, sharing every pass over D's factor
+    const int nrmax = spike_max_nrhs(f);
     for (int i = 0; i < ns; ++i) {
-        SIMM_TRY(spike_clone_scratch(f, cl[i], st, true));
+        SIMM_TRY(spike_clone_scratch(f, cl[i], st, true, nrmax));
         have[i] = true;
     }
     SIMM_HIP_TRY(hipEventRecord(ev[ns], st));   // D's sweep data and the clones are on st
     for (int i = 0; i < ns; ++i) SIMM_HIP_TRY(hipStreamWaitEvent(ss[i], ev[ns], 0));
-    for (int c = 0; c < w; ++c) {
-        const int i = c % ns;
-        const int which = c < ku ? 0 : 1;
-        const int k = c < ku ? c : c - ku;
-        cplx* out = (which == 0 ? f.Vs : f.Ws) + (int64_t)k * n16;
-        hipLaunchKernelGGL(k_part_rhs, dim3(blocks16), dim3(256), 0, ss[i], f.n, n16, kl, ku, f.bs, f.nbk, f.cpl,
-                           which, k, cl[i].pg);
-        SIMM_TRY(spike_apply_diag(cl[i], cl[i].pg, out, nullptr, ss[i]));
+    int solve = 0;
+    for (int which = 0; which < 2; ++which) {
+        const int cols = which == 0 ? ku : kl;
+        for (int k0 = 0; k0 < cols;) {
+            int nr = nrmax;
+            while (nr > cols - k0) nr /= 2;
+            const int i = solve++ % ns;
+            for (int r = 0; r < nr; ++r)
+                hipLaunchKernelGGL(k_part_rhs, dim3(blocks16), dim3(256), 0, ss[i], f.n, n16, kl, ku, f.bs, f.nbk, f.cpl,
+                                   which, k0 + r, cl[i].pg + (int64_t)r * n16);
+            cplx* out = (which == 0 ? f.Vs : f.Ws) + (int64_t)k0 * n16;
+            SIMM_TRY(spike_apply_diag_nr(cl[i], cl[i].pg, n16, out, n16, nr, ss[i]));
+            k0 += nr;
+        }
     }
     int err = 0;
     for (int i = 0; i < ns; ++i) {

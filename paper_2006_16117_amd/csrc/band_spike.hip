@@ -178,9 +178,9 @@ __global__ __launch_bounds__(1024) void k_blocks_bwd(int64_t n, int K, int kv, i
 // ---------------------------------------------------------------------------
 // forward (L) chunk sweep, 16 columns per step
 // ---------------------------------------------------------------------------
-// NR right-hand sides per workgroup (unit-state responses only: NR unit vectors
-// r0 .. r0+NR-1, r0 = NR blockIdx.y, share every panel block the workgroup loads;
-// zero-state sweeps use NR = 1).
+// NR right-hand sides per workgroup share every panel block it loads: NR unit vectors
+// r0 .. r0+NR-1 (r0 = NR blockIdx.y) for the unit-state responses, or NR input columns
+// for zero-state sweeps (each column computed as with NR = 1).
 // Panels of block rows loaded ahead by the chunk sweeps: two for the single-vector
 // FP64 sweeps of up to 512 threads (a third register set of 64 VGPRs fits), else one.
 template <int T, int NR, typename GT>
@@ -199,15 +199,18 @@ __global__ __launch_bounds__(T) void k_chunk_fwd(SpikeFwdT<GT> a) {
     const int len = (int)(J1 - J0);
     const int npan = len / 16;
     // LDS: window values by slot (2 x NR x RW, alternating per panel), the chunk's
-    // outputs (NR x len), its input rows J0+kl .. J1+RW-1 (len + 16) and its pivots (len)
+    // outputs (NR x len), its input rows J0+kl .. J1+RW-1 (len + 16; NR columns of them
+    // in mode 0) and its pivots (len)
+    const int NI = (a.mode == 0) ? NR : 1;
     cplx* S = reinterpret_cast<cplx*>(sraw);
     cplx* outb = S + 2 * NR * RW;
     cplx* inb = outb + NR * len;
-    int* pivb = reinterpret_cast<int*>(inb + len + 16);
+    int* pivb = reinterpret_cast<int*>(inb + NI * (len + 16));
     for (int q = tid; q < len; q += T) pivb[q] = a.ipiv[J0 + q] - (int)(J0 + (q & ~15));
     for (int q = tid; q < len + 16; q += T) {
         const int64_t row = J0 + kl + q;
-        inb[q] = (a.mode == 0 && row < a.n) ? a.u[row] : mk(0.0, 0.0);
+        for (int u = 0; u < NI; ++u)
+            inb[u * (len + 16) + q] = (a.mode == 0 && row < a.n) ? a.u[row + u * a.ldu] : mk(0.0, 0.0);
     }
     __syncthreads();
     const bool mine = tid < RW;
@@ -218,7 +221,7 @@ __global__ __launch_bounds__(T) void k_chunk_fwd(SpikeFwdT<GT> a) {
 #pragma unroll
     for (int u = 0; u < NR; ++u) {
         val[u] = mk(0.0, 0.0);
-        if (mine) val[u] = (a.mode == 0) ? ((pos >= kl) ? inb[pos - kl] : mk(0.0, 0.0))
+        if (mine) val[u] = (a.mode == 0) ? ((pos >= kl) ? inb[u * (len + 16) + pos - kl] : mk(0.0, 0.0))
                                          : mk(pos == r0 + u ? 1.0 : 0.0, 0.0);
     }
     const int64_t p0 = J0 / 16;
@@ -267,7 +270,8 @@ __global__ __launch_bounds__(T) void k_chunk_fwd(SpikeFwdT<GT> a) {
             if (mine) {
                 if (pos < 16) {
                     ldsw(outb + u * len + 16 * i + pos, acc);
-                    val[u] = inb[16 * i + 16 + pos];          // row J0 + 16 i + RW + pos enters
+                    // row J0 + 16 i + RW + pos enters (zero in mode 1)
+                    val[u] = inb[(a.mode == 0 ? u : 0) * (len + 16) + 16 * i + 16 + pos];
                 } else {
                     val[u] = acc;
                 }
@@ -295,7 +299,8 @@ __global__ __launch_bounds__(T) void k_chunk_fwd(SpikeFwdT<GT> a) {
     // end state: rows J1 .. J1+kl-1 hold positions 0 .. kl-1
     if (mine && pos < kl) {
         if (a.mode == 0) {
-            a.tau[(int64_t)c * kl + pos] = val[0];
+#pragma unroll
+            for (int u = 0; u < NR; ++u) a.tau[(int64_t)c * kl + pos + u * a.ldt] = val[u];
         } else {
 #pragma unroll
             for (int u = 0; u < NR; ++u)   // Phi_c(i, r) at [c][i][r]
@@ -304,10 +309,12 @@ __global__ __launch_bounds__(T) void k_chunk_fwd(SpikeFwdT<GT> a) {
     }
     __syncthreads();
     if (a.mode == 0) {
-        for (int q = tid; q < len; q += T) {
-            const cplx v = ldsr(outb + q);
-            if (J0 + q < a.n) a.y[J0 + q] = v;
-        }
+#pragma unroll
+        for (int u = 0; u < NR; ++u)
+            for (int q = tid; q < len; q += T) {
+                const cplx v = ldsr(outb + u * len + q);
+                if (J0 + q < a.n) a.y[J0 + q + u * a.ldy] = v;
+            }
     } else {
 #pragma unroll
         for (int u = 0; u < NR; ++u) {
@@ -331,14 +338,17 @@ __global__ __launch_bounds__(T) void k_chunk_bwd(SpikeBwdT<GT> a) {
     const int64_t J0 = (int64_t)c * a.s, J1 = min(a.n16, J0 + a.s);
     const int len = (int)(J1 - J0);
     const int npan = len / 16;
-    // LDS: window (2 x NR x RW), outputs (NR x len), input rows J0-K-16 .. J1-K-1 (len + 16)
+    // LDS: window (2 x NR x RW), outputs (NR x len), input rows J0-K-16 .. J1-K-1 (len + 16;
+    // NR columns of them in mode 0)
+    const int NI = (a.mode == 0) ? NR : 1;
     cplx* S = reinterpret_cast<cplx*>(sraw);
     cplx* outb = S + 2 * NR * RW;
     cplx* inb = outb + NR * len;
     const int64_t in0 = J0 - K - 16;
     for (int q = tid; q < len + 16; q += T) {
         const int64_t row = in0 + q;
-        inb[q] = (a.mode == 0 && row >= 0 && row < a.n) ? a.z[row] : mk(0.0, 0.0);
+        for (int u = 0; u < NI; ++u)
+            inb[u * (len + 16) + q] = (a.mode == 0 && row >= 0 && row < a.n) ? a.z[row + u * a.ldu] : mk(0.0, 0.0);
     }
     __syncthreads();
     const bool mine = tid < RW;
@@ -350,7 +360,7 @@ __global__ __launch_bounds__(T) void k_chunk_bwd(SpikeBwdT<GT> a) {
 #pragma unroll
     for (int u = 0; u < NR; ++u) {
         val[u] = mk(0.0, 0.0);
-        if (mine) val[u] = (a.mode == 0) ? ((pos < 16) ? inb[(16 * pl - K + pos) - in0] : mk(0.0, 0.0))
+        if (mine) val[u] = (a.mode == 0) ? ((pos < 16) ? inb[u * (len + 16) + (16 * pl - K + pos) - in0] : mk(0.0, 0.0))
                                          : mk(pos - 16 == r0 + u ? 1.0 : 0.0, 0.0);
     }
     // prefetch PD panels ahead, as in the forward sweep
@@ -387,7 +397,8 @@ __global__ __launch_bounds__(T) void k_chunk_bwd(SpikeBwdT<GT> a) {
             if (mine) {
                 if (pos >= K) {
                     ldsw(outb + u * len + (16 * p - J0) + pos - K, acc);
-                    val[u] = inb[(16 * p - 16 - K + pos - K) - in0];   // row j0-16-K + (pos-K) enters
+                    // row j0-16-K + (pos-K) enters (zero in mode 1)
+                    val[u] = inb[(a.mode == 0 ? u : 0) * (len + 16) + (16 * p - 16 - K + pos - K) - in0];
                 } else {
                     val[u] = acc;
                 }
@@ -415,7 +426,8 @@ __global__ __launch_bounds__(T) void k_chunk_bwd(SpikeBwdT<GT> a) {
     // end state: rows J0-K .. J0-1 hold positions 16 .. K+15
     if (mine && pos >= 16) {
         if (a.mode == 0) {
-            a.tau[(int64_t)c * K + pos - 16] = val[0];
+#pragma unroll
+            for (int u = 0; u < NR; ++u) a.tau[(int64_t)c * K + pos - 16 + u * a.ldt] = val[u];
         } else {
 #pragma unroll
             for (int u = 0; u < NR; ++u)
@@ -424,10 +436,12 @@ __global__ __launch_bounds__(T) void k_chunk_bwd(SpikeBwdT<GT> a) {
     }
     __syncthreads();
     if (a.mode == 0) {
-        for (int q = tid; q < len; q += T) {
-            const cplx v = ldsr(outb + q);
-            if (J0 + q < a.n) a.y[J0 + q] = v;
-        }
+#pragma unroll
+        for (int u = 0; u < NR; ++u)
+            for (int q = tid; q < len; q += T) {
+                const cplx v = ldsr(outb + u * len + q);
+                if (J0 + q < a.n) a.y[J0 + q + u * a.ldy] = v;
+            }
     } else {
 #pragma unroll
         for (int u = 0; u < NR; ++u) {
@@ -453,13 +467,13 @@ constexpr int SPIKE_CTR_STRIDE = 64;   // unsigned counters 256 bytes apart
 // chunk q forward, P-1-q backward): group 0 from the true initial state, the others
 // from zero; each group meets at its own barrier counter and leaves the state after
 // its last chunk in gout (the last group stops one step earlier: no chunk follows).
-template <int MAXQ, int CH_PARTS>
+template <int MAXQ, int CH_PARTS, int NR>
 __global__ __launch_bounds__(CH_THREADS) void k_spike_chain(SpikeChain a) {
     constexpr int CH_ROWS = CH_THREADS / CH_PARTS;
     static_assert(CH_ROWS <= 64, "wave 0 stores the workgroup's rows");
     if (a.active != nullptr && *a.active == 0) return;
-    __shared__ cplx tcur[CH_PARTS * MAXQ];           // state, zero-padded
-    __shared__ cplx rows_out[CH_ROWS];               // this workgroup's rows of the next state
+    __shared__ cplx tcur[NR][CH_PARTS * MAXQ];       // states (NR right-hand sides), zero-padded
+    __shared__ cplx rows_out[NR][CH_ROWS];           // this workgroup's rows of the next states
     const int K = a.K;
     const int g = blockIdx.x;
     const int64_t grp = blockIdx.y;
@@ -474,9 +488,12 @@ __global__ __launch_bounds__(CH_THREADS) void k_spike_chain(SpikeChain a) {
     unsigned* counter = a.counter + grp * SPIKE_CTR_STRIDE;
     for (int r = tid; r < CH_PARTS * MAXQ; r += CH_THREADS) {
         const int64_t row = a.init_row0 + r;
-        const cplx v = (r < K && grp == 0) ? ldz(a.init_src, row, a.n) : mk(0.0, 0.0);
-        tcur[r] = v;
-        if (g == 0 && r < K) a.t[chunk(q0) * K + r] = v;
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+            const cplx v = (r < K && grp == 0) ? ldz(a.init_src + u * a.ldi, row, a.n) : mk(0.0, 0.0);
+            tcur[u][r] = v;
+            if (g == 0 && r < K) a.t[chunk(q0) * K + r + u * a.ldt] = v;
+        }
     }
     cplx ph[MAXQ];
     auto load_phi = [&](int64_t c) {
@@ -489,28 +506,41 @@ __global__ __launch_bounds__(CH_THREADS) void k_spike_chain(SpikeChain a) {
     for (int64_t step = 0; step < nsteps; ++step) {
         const int64_t q = q0 + step;
         const int64_t c = chunk(q);
-        // destination of the next state: the next chunk of the group, or the group output
-        cplx* dst = (q + 1 < q1) ? a.t + chunk(q + 1) * K : a.gout + grp * K;
-        cplx acc = mk(0.0, 0.0);
+        // destination of the next states: the next chunk of the group, or the group output
+        const bool to_t = q + 1 < q1;
+        cplx* dst = to_t ? a.t + chunk(q + 1) * K : a.gout + grp * K;
+        const int64_t ldd = to_t ? a.ldt : a.ldg;
+        cplx acc[NR];
 #pragma unroll
-        for (int qq = 0; qq < MAXQ; ++qq) acc = fma_c(acc, ph[qq], tcur[part + CH_PARTS * qq]);   // padded t is 0
+        for (int u = 0; u < NR; ++u) acc[u] = mk(0.0, 0.0);
+#pragma unroll
+        for (int qq = 0; qq < MAXQ; ++qq)
+#pragma unroll
+            for (int u = 0; u < NR; ++u)
+                acc[u] = fma_c(acc[u], ph[qq], tcur[u][part + CH_PARTS * qq]);   // padded t is 0
         if (step + 1 < nsteps) load_phi(chunk(q + 1));
 #pragma unroll
-        for (int m = CH_PARTS / 2; m >= 1; m >>= 1) {
-            acc.re += __shfl_xor(acc.re, m, 64);
-            acc.im += __shfl_xor(acc.im, m, 64);
+        for (int u = 0; u < NR; ++u) {
+#pragma unroll
+            for (int m = CH_PARTS / 2; m >= 1; m >>= 1) {
+                acc[u].re += __shfl_xor(acc[u].re, m, 64);
+                acc[u].im += __shfl_xor(acc[u].im, m, 64);
+            }
+            if (part == 0 && i < K) rows_out[u][il] = a.tau[c * K + i + u * a.ldt] + acc[u];
         }
-        if (part == 0 && i < K) rows_out[il] = a.tau[c * K + i] + acc;
         __syncthreads();
-        // Device-scope barrier of the group.  Wave 0 alone exchanges the state with the
+        // Device-scope barrier of the group.  Wave 0 alone exchanges the states with the
         // other workgroups: it stores this workgroup's rows, releases them (one agent-scope
         // release), arrives, polls with relaxed loads (an acquiring load would invalidate
-        // the XCD's L2 on every poll), acquires once and loads the whole next state into
+        // the XCD's L2 on every poll), acquires once and loads the whole next states into
         // LDS.  The other waves meet it at the workgroup barriers.  One write-back and one
         // invalidate per workgroup and step: they serialise per XCD, so fences from every
         // wave slowed concurrent chains several-fold.
         if (tid < 64) {
-            if (tid < CH_ROWS && g * CH_ROWS + tid < K) dst[g * CH_ROWS + tid] = rows_out[tid];
+            if (tid < CH_ROWS && g * CH_ROWS + tid < K) {
+#pragma unroll
+                for (int u = 0; u < NR; ++u) dst[g * CH_ROWS + tid + u * ldd] = rows_out[u][tid];
+            }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             if (tid == 0) {
                 __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -527,11 +557,16 @@ __global__ __launch_bounds__(CH_THREADS) void k_spike_chain(SpikeChain a) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             // all loads in flight at once (indices clamped into the state), then to LDS
             constexpr int NL = (CH_PARTS * MAXQ + 63) / 64;
-            cplx nxt[NL];
+            cplx nxt[NR][NL];
 #pragma unroll
-            for (int u = 0; u < NL; ++u) nxt[u] = dst[min(tid + 64 * u, K - 1)];
+            for (int u = 0; u < NR; ++u)
 #pragma unroll
-            for (int u = 0; u < NL; ++u) tcur[tid + 64 * u] = csel(tid + 64 * u < K, nxt[u], mk(0.0, 0.0));   // padding stays 0
+                for (int v = 0; v < NL; ++v) nxt[u][v] = dst[min(tid + 64 * v, K - 1) + u * ldd];
+#pragma unroll
+            for (int u = 0; u < NR; ++u)
+#pragma unroll
+                for (int v = 0; v < NL; ++v)
+                    tcur[u][tid + 64 * v] = csel(tid + 64 * v < K, nxt[u][v], mk(0.0, 0.0));   // padding stays 0
         }
         __syncthreads();
     }
@@ -552,38 +587,54 @@ __global__ __launch_bounds__(CH_THREADS) void k_spike_chain(SpikeChain a) {
 // chain over groups) enters its chunks through the transfer products,
 //     t_q += Pi_q T_g   (Pi_q = Phi_{q-1} ... Phi_{q0(g)}, chain order; Pi_{q0} = I),
 // 16 threads per state row, 16 rows per workgroup, blockIdx.y = chain-order chunk q.
-template <int MAXQ>
+template <int MAXQ, int NR>
 __global__ __launch_bounds__(256) void k_spike_fix(int K, int64_t P, int64_t L, int forward, const cplx* __restrict__ Pi,
-                                                   const cplx* __restrict__ tg, cplx* __restrict__ t, const int* active) {
+                                                   const cplx* __restrict__ tg, cplx* __restrict__ t, int64_t ldg,
+                                                   int64_t ldt, const int* active) {
     if (active != nullptr && *active == 0) return;
     const int64_t q = blockIdx.y;
     const int64_t grp = q / L;
     if (grp == 0) return;
-    __shared__ cplx Ts[16 * MAXQ];
+    __shared__ cplx Ts[NR][16 * MAXQ];
     const int tid = threadIdx.x, il = tid >> 4, part = tid & 15;
     const int i = blockIdx.x * 16 + il;
-    const cplx* T = tg + (grp - 1) * K;    // true state at the group's first chunk
-    for (int r = tid; r < 16 * MAXQ; r += 256) Ts[r] = (r < K) ? T[r] : mk(0.0, 0.0);
+    for (int r = tid; r < 16 * MAXQ; r += 256) {
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+            const cplx* T = tg + (grp - 1) * K + u * ldg;    // true state at the group's first chunk
+            Ts[u][r] = (r < K) ? T[r] : mk(0.0, 0.0);
+        }
+    }
     __syncthreads();
     const int64_t c = forward ? q : P - 1 - q;
     if (q == grp * L) {
         // first chunk of the group: its chain ran from zero, so its state is T_g itself
-        if (part == 0 && i < K) t[c * K + i] = Ts[i];
+        if (part == 0 && i < K) {
+#pragma unroll
+            for (int u = 0; u < NR; ++u) t[c * K + i + u * ldt] = Ts[u][i];
+        }
         return;
     }
     const cplx* prow = Pi + q * (int64_t)K * K + (int64_t)min(i, K - 1) * K;
-    cplx acc = mk(0.0, 0.0);
+    cplx acc[NR];
+#pragma unroll
+    for (int u = 0; u < NR; ++u) acc[u] = mk(0.0, 0.0);
 #pragma unroll
     for (int qq = 0; qq < MAXQ; ++qq) {
         const int r = part + 16 * qq;
-        acc = fma_c(acc, prow[min(r, K - 1)], Ts[r]);          // padded T is 0
+        const cplx pv = prow[min(r, K - 1)];
+#pragma unroll
+        for (int u = 0; u < NR; ++u) acc[u] = fma_c(acc[u], pv, Ts[u][r]);          // padded T is 0
     }
 #pragma unroll
-    for (int m = 8; m >= 1; m >>= 1) {
-        acc.re += __shfl_xor(acc.re, m, 64);
-        acc.im += __shfl_xor(acc.im, m, 64);
+    for (int u = 0; u < NR; ++u) {
+#pragma unroll
+        for (int m = 8; m >= 1; m >>= 1) {
+            acc[u].re += __shfl_xor(acc[u].re, m, 64);
+            acc[u].im += __shfl_xor(acc[u].im, m, 64);
+        }
+        if (part == 0 && i < K) t[c * K + i + u * ldt] = t[c * K + i + u * ldt] + acc[u];
     }
-    if (part == 0 && i < K) t[c * K + i] = t[c * K + i] + acc;
 }
 
 // Copies of the group's first transfer matrix: Pi_{q0+1} = Phi_{chunk(q0)}, groups 1..ng.
@@ -599,36 +650,51 @@ __global__ __launch_bounds__(256) void k_pi_first(int K, int64_t P, int64_t L, i
 }
 
 // y(j) += sum_r Psi(j, r) t_{c(j)}(r); the (at most two) state vectors a block
-// needs are staged in LDS.
-template <typename PT>
+// needs are staged in LDS.  NR right-hand sides (y + u ldy, t + u ldt) share the Psi loads.
+template <typename PT, int NR>
 __global__ __launch_bounds__(256) void k_spike_correct(int64_t n, int64_t ld, int K, int64_t s,
                                                        const PT* __restrict__ Psi, const cplx* __restrict__ t,
-                                                       cplx* __restrict__ y, const int* active) {
+                                                       cplx* __restrict__ y, int64_t ldt, int64_t ldy,
+                                                       const int* active) {
     if (active != nullptr && *active == 0) return;
-    extern __shared__ cplx ts[];                     // 2 K
+    extern __shared__ cplx ts[];                     // NR x 2 K
     const int64_t jb = (int64_t)blockIdx.x * blockDim.x;
     const int64_t cb = jb / s;
     const int64_t ce = min(n - 1, jb + (int64_t)blockDim.x - 1) / s;
     for (int r = threadIdx.x; r < K; r += blockDim.x) {
-        ts[r] = t[cb * K + r];
-        ts[K + r] = t[ce * K + r];
+#pragma unroll
+        for (int u = 0; u < NR; ++u) {
+            ts[u * 2 * K + r] = t[cb * K + r + u * ldt];
+            ts[u * 2 * K + K + r] = t[ce * K + r + u * ldt];
+        }
     }
     __syncthreads();
     const int64_t j = jb + threadIdx.x;
     if (j >= n) return;
-    const cplx* tc = ts + ((j / s == cb) ? 0 : K);
-    cplx acc = y[j];
+    const int sel = (j / s == cb) ? 0 : K;
+    cplx acc[NR];
+#pragma unroll
+    for (int u = 0; u < NR; ++u) acc[u] = y[j + u * ldy];
     const PT* pr = Psi + j;
     int r = 0;
     for (; r + 8 <= K; r += 8) {
         cplx v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = widen(pr[(int64_t)(r + u) * ld]);
+        for (int w = 0; w < 8; ++w) v[w] = widen(pr[(int64_t)(r + w) * ld]);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc = fma_c(acc, v[u], tc[r + u]);
+        for (int u = 0; u < NR; ++u) {
+            const cplx* tc = ts + u * 2 * K + sel;
+#pragma unroll
+            for (int w = 0; w < 8; ++w) acc[u] = fma_c(acc[u], v[w], tc[r + w]);
+        }
     }
-    for (; r < K; ++r) acc = fma_c(acc, widen(pr[(int64_t)r * ld]), tc[r]);
-    y[j] = acc;
+    for (; r < K; ++r) {
+        const cplx v = widen(pr[(int64_t)r * ld]);
+#pragma unroll
+        for (int u = 0; u < NR; ++u) acc[u] = fma_c(acc[u], v, ts[u * 2 * K + sel + r]);
+    }
+#pragma unroll
+    for (int u = 0; u < NR; ++u) y[j + u * ldy] = acc[u];
 }
 
 __global__ void k_fill_u32(unsigned* p, int count, unsigned v) {
@@ -729,7 +795,61 @@ simm_status launch_bwd(const Args& a, int64_t P, int nrhs, int W, int rows, int6
     return SIMM_OK;
 }
 
+// zero-state sweeps of nr columns: window (2 nr rows) + outputs (nr s) + inputs (nr (s + 16))
+// complex, and s pivots
+size_t window_lds0(int rows, int64_t s, int nr) {
+    return sizeof(cplx) * (2 * (size_t)nr * rows + (size_t)nr * s + (size_t)nr * (s + 16)) + sizeof(int) * (size_t)s;
+}
+
+template <typename Args>
+simm_status launch_fwd0(const Args& a, int64_t P, int nr, int W, int rows, int64_t s, hipStream_t st) {
+    using GT = typename Args::storage;
+    const size_t lds = window_lds0(rows, s, nr);
+    const dim3 grid((unsigned)P, 1u);
+    if (W <= 256) {
+        if (nr == 4) hipLaunchKernelGGL((k_chunk_fwd<256, 4, GT>), grid, dim3(256), lds, st, a);
+        else if (nr == 2) hipLaunchKernelGGL((k_chunk_fwd<256, 2, GT>), grid, dim3(256), lds, st, a);
+        else hipLaunchKernelGGL((k_chunk_fwd<256, 1, GT>), grid, dim3(256), lds, st, a);
+    } else if (W <= 512) {
+        if (nr == 4) hipLaunchKernelGGL((k_chunk_fwd<512, 4, GT>), grid, dim3(512), lds, st, a);
+        else if (nr == 2) hipLaunchKernelGGL((k_chunk_fwd<512, 2, GT>), grid, dim3(512), lds, st, a);
+        else hipLaunchKernelGGL((k_chunk_fwd<512, 1, GT>), grid, dim3(512), lds, st, a);
+    } else {
+        hipLaunchKernelGGL((k_chunk_fwd<1024, 1, GT>), grid, dim3(1024), lds, st, a);
+    }
+    SIMM_HIP_TRY(hipGetLastError());
+    return SIMM_OK;
+}
+template <typename Args>
+simm_status launch_bwd0(const Args& a, int64_t P, int nr, int W, int rows, int64_t s, hipStream_t st) {
+    using GT = typename Args::storage;
+    const size_t lds = window_lds0(rows, s, nr);
+    const dim3 grid((unsigned)P, 1u);
+    if (W <= 256) {
+        if (nr == 4) hipLaunchKernelGGL((k_chunk_bwd<256, 4, GT>), grid, dim3(256), lds, st, a);
+        else if (nr == 2) hipLaunchKernelGGL((k_chunk_bwd<256, 2, GT>), grid, dim3(256), lds, st, a);
+        else hipLaunchKernelGGL((k_chunk_bwd<256, 1, GT>), grid, dim3(256), lds, st, a);
+    } else if (W <= 512) {
+        if (nr == 4) hipLaunchKernelGGL((k_chunk_bwd<512, 4, GT>), grid, dim3(512), lds, st, a);
+        else if (nr == 2) hipLaunchKernelGGL((k_chunk_bwd<512, 2, GT>), grid, dim3(512), lds, st, a);
+        else hipLaunchKernelGGL((k_chunk_bwd<512, 1, GT>), grid, dim3(512), lds, st, a);
+    } else {
+        hipLaunchKernelGGL((k_chunk_bwd<1024, 1, GT>), grid, dim3(1024), lds, st, a);
+    }
+    SIMM_HIP_TRY(hipGetLastError());
+    return SIMM_OK;
+}
+
 }  // namespace
+
+int spike_max_nrhs(const SpikeFactor& f) {
+    // the 1024-thread chunk kernels take one, and so do chains of states longer than 256
+    // (their several-column forms would spill registers)
+    if (f.Wf > 512 || f.Wb > 512 || std::max(f.klx, f.K) > 16 * 16) return 1;
+    for (int nr = 4; nr > 1; nr /= 2)
+        if (window_lds0(f.klx + 16, f.s, nr) <= LDS_LIMIT && window_lds0(f.K + 16, f.s, nr) <= LDS_LIMIT) return nr;
+    return 1;
+}
 
 int64_t spike_chunk_len(int64_t n16, int kl, int K) {
     int64_t s = 0;
@@ -925,14 +1045,16 @@ simm_status spike_prepare(SpikeFactor& f, hipStream_t st) {
 // chain states, group outputs, barrier counters, error flag), so that applications of
 // one factor can run on several streams at once.  The clone shares the factor data
 // and spike_release on it frees only its own buffers.
-simm_status spike_clone_scratch(const SpikeFactor& base, SpikeFactor& out, hipStream_t st, bool ordered) {
+simm_status spike_clone_scratch(const SpikeFactor& base, SpikeFactor& out, hipStream_t st, bool ordered, int nrhs) {
     out = base;
     out.mem = nullptr;
     out.part_mem = nullptr;   // spikes and reduced inverse stay the base's
+    nrhs = std::max(1, nrhs);
+    out.nrhs = nrhs;
     const int kl = base.klx, K = base.K;
-    const size_t part = base.bs > 0 ? (size_t)base.n16 + (size_t)base.nr + 32 : 0;
-    const size_t elems = (size_t)base.n16 + (size_t)base.P * kl * 2 + (size_t)base.P * K * 2 +
-                         (size_t)base.G * 2 * (kl + K) + (size_t)(base.G + 1) * 16 + 64 + part;
+    const size_t part = base.bs > 0 ? (size_t)base.n16 * nrhs + (size_t)base.nr + 32 : 0;
+    const size_t elems = ((size_t)base.n16 + (size_t)base.P * kl * 2 + (size_t)base.P * K * 2 +
+                          (size_t)base.G * 2 * (kl + K)) * (size_t)nrhs + (size_t)(base.G + 1) * 16 + 64 + part;
     if (ordered) SIMM_HIP_TRY(device_malloc_async(&out.mem, sizeof(cplx) * elems + 14 * 256, st));
     else SIMM_HIP_TRY(device_malloc(&out.mem, sizeof(cplx) * elems + 14 * 256));
     char* p = reinterpret_cast<char*>(out.mem);
@@ -941,19 +1063,20 @@ simm_status spike_clone_scratch(const SpikeFactor& base, SpikeFactor& out, hipSt
         p += (sizeof(cplx) * count + 255) & ~(size_t)255;
         return reinterpret_cast<cplx*>(r);
     };
-    out.tauL = take((size_t)base.P * kl);
-    out.tL = take((size_t)base.P * kl);
-    out.tauU = take((size_t)base.P * K);
-    out.tU = take((size_t)base.P * K);
-    out.z = take((size_t)base.n16);
-    out.goutL = take((size_t)base.G * kl);
-    out.goutU = take((size_t)base.G * K);
-    out.tgL = take((size_t)base.G * kl);
-    out.tgU = take((size_t)base.G * K);
+    // nrhs slabs each, at the strides apply_t uses
+    out.tauL = take((size_t)base.P * kl * nrhs);
+    out.tL = take((size_t)base.P * kl * nrhs);
+    out.tauU = take((size_t)base.P * K * nrhs);
+    out.tU = take((size_t)base.P * K * nrhs);
+    out.z = take((size_t)base.n16 * nrhs);
+    out.goutL = take((size_t)base.G * kl * nrhs);
+    out.goutU = take((size_t)base.G * K * nrhs);
+    out.tgL = take((size_t)base.G * kl * nrhs);
+    out.tgU = take((size_t)base.G * K * nrhs);
     out.counter = reinterpret_cast<unsigned*>(take((size_t)(base.G + 1) * (SPIKE_CTR_STRIDE / 4)));
     out.err = reinterpret_cast<int*>(take(4));
     if (base.bs > 0) {
-        out.pg = take((size_t)base.n16);
+        out.pg = take((size_t)base.n16 * nrhs);
         out.pz = take((size_t)base.nr);
     }
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned*>(out.err), 1, 0u);
@@ -978,8 +1101,12 @@ void spike_release(SpikeFactor& f) {
 // with its own barrier counter.
 static simm_status run_chain(const SpikeFactor& f, bool forward, int K, int64_t P, int64_t L, int64_t groups,
                              const cplx* Phi, const cplx* tau, cplx* tstate, cplx* gout, const cplx* init_src,
-                             int64_t init_row0, int64_t n, unsigned* counter, const int* active, hipStream_t st) {
+                             int64_t init_row0, int64_t n, unsigned* counter, const int* active, hipStream_t st,
+                             int nr = 1, int64_t ldt = 0, int64_t ldg = 0, int64_t ldi = 0) {
     SpikeChain c{};
+    c.ldt = ldt;
+    c.ldg = ldg;
+    c.ldi = ldi;
     c.n = n;
     c.K = K;
     c.P = P;
@@ -997,41 +1124,75 @@ static simm_status run_chain(const SpikeFactor& f, bool forward, int K, int64_t 
     // 16 threads per state row, 16 rows per workgroup: more, smaller workgroups make
     // the device-scope barrier of every step dearer than the rows they save
     const dim3 grid((unsigned)((K + 15) / 16), (unsigned)groups);
-    if (K <= 16 * 16) hipLaunchKernelGGL((k_spike_chain<16, 16>), grid, dim3(CH_THREADS), 0, st, c);
-    else if (K <= 32 * 16) hipLaunchKernelGGL((k_spike_chain<32, 16>), grid, dim3(CH_THREADS), 0, st, c);
-    else hipLaunchKernelGGL((k_spike_chain<64, 16>), grid, dim3(CH_THREADS), 0, st, c);
+    if (nr > 1 && K > 16 * 16) {
+        set_error("several right-hand sides need chain states of at most 256");
+        return SIMM_EINVAL;
+    }
+    if (nr == 4) {
+        hipLaunchKernelGGL((k_spike_chain<16, 16, 4>), grid, dim3(CH_THREADS), 0, st, c);
+    } else if (nr == 2) {
+        hipLaunchKernelGGL((k_spike_chain<16, 16, 2>), grid, dim3(CH_THREADS), 0, st, c);
+    } else {
+        if (K <= 16 * 16) hipLaunchKernelGGL((k_spike_chain<16, 16, 1>), grid, dim3(CH_THREADS), 0, st, c);
+        else if (K <= 32 * 16) hipLaunchKernelGGL((k_spike_chain<32, 16, 1>), grid, dim3(CH_THREADS), 0, st, c);
+        else hipLaunchKernelGGL((k_spike_chain<64, 16, 1>), grid, dim3(CH_THREADS), 0, st, c);
+    }
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;
 }
 
 // The chain over the chunks' boundary states of one sweep direction: one level, or
 // groups in parallel, the chain over the groups' start states and the fix-up.
+// nr right-hand sides: slabs of t and tau every P K, of gout and tg every G K, of the
+// initial states every ldi.
 static simm_status chain_states(const SpikeFactor& f, bool forward, int K, const cplx* Phi, const cplx* tau, cplx* t,
                                 const cplx* Pi, const cplx* PiFull, cplx* gout, cplx* tg, const cplx* init_src,
-                                int64_t init_row0, const int* active, hipStream_t st) {
+                                int64_t init_row0, const int* active, hipStream_t st, int nr = 1, int64_t ldi = 0) {
+    const int64_t ldt = f.P * K, ldg = f.G * K;
     // the counters are zero here: zeroed when the sweep data was made, and every chain
     // launch leaves its group's counters at zero when it ends
     SIMM_TRY(run_chain(f, forward, K, f.P, f.L, f.G, Phi, tau, t, gout, init_src, init_row0, f.n, f.counter, active,
-                       st));
+                       st, nr, ldt, ldg, ldi));
     if (f.G == 1) return SIMM_OK;
     // T_1 = gout_0; T_{g+1} = gout_g + PiFull_g T_g (g = 1 .. G-2), into tg[g-1]
     const int64_t KK = (int64_t)K * K;
     SIMM_TRY(run_chain(f, true, K, f.G - 1, f.G - 1, 1, PiFull + KK, gout + K, tg, nullptr, gout, 0, K,
-                       f.counter + f.G * SPIKE_CTR_STRIDE, active, st));
+                       f.counter + f.G * SPIKE_CTR_STRIDE, active, st, nr, ldg, 0, ldg));
     const dim3 grid((unsigned)((K + 15) / 16), (unsigned)f.P);
-    if (K <= 16 * 16) hipLaunchKernelGGL(k_spike_fix<16>, grid, dim3(256), 0, st, K, f.P, f.L, forward ? 1 : 0, Pi, tg, t,
-                                         active);
-    else if (K <= 32 * 16) hipLaunchKernelGGL(k_spike_fix<32>, grid, dim3(256), 0, st, K, f.P, f.L, forward ? 1 : 0, Pi,
-                                              tg, t, active);
-    else hipLaunchKernelGGL(k_spike_fix<64>, grid, dim3(256), 0, st, K, f.P, f.L, forward ? 1 : 0, Pi, tg, t, active);
+    const int fw = forward ? 1 : 0;
+    if (nr == 4) {   // K <= 256 (checked by run_chain)
+        hipLaunchKernelGGL((k_spike_fix<16, 4>), grid, dim3(256), 0, st, K, f.P, f.L, fw, Pi, tg, t, ldg, ldt, active);
+    } else if (nr == 2) {
+        hipLaunchKernelGGL((k_spike_fix<16, 2>), grid, dim3(256), 0, st, K, f.P, f.L, fw, Pi, tg, t, ldg, ldt, active);
+    } else {
+        if (K <= 16 * 16) hipLaunchKernelGGL((k_spike_fix<16, 1>), grid, dim3(256), 0, st, K, f.P, f.L, fw, Pi, tg, t, ldg,
+                                             ldt, active);
+        else if (K <= 32 * 16) hipLaunchKernelGGL((k_spike_fix<32, 1>), grid, dim3(256), 0, st, K, f.P, f.L, fw, Pi, tg, t,
+                                                  ldg, ldt, active);
+        else hipLaunchKernelGGL((k_spike_fix<64, 1>), grid, dim3(256), 0, st, K, f.P, f.L, fw, Pi, tg, t, ldg, ldt, active);
+    }
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;
 }
 
+template <typename GT, int NR>
+void launch_correct(const SpikeFactor& f, int K, const GT* Psi, const cplx* t, cplx* y, int64_t ldy, const int* active,
+                    hipStream_t st) {
+    const unsigned blocks = (unsigned)((f.n + 255) / 256);
+    hipLaunchKernelGGL((k_spike_correct<GT, NR>), dim3(blocks), dim3(256), sizeof(cplx) * 2 * K * NR, st, f.n, f.n16, K,
+                       f.s, Psi, t, y, f.P * (int64_t)K, ldy, active);
+}
+
+// nr columns u + r ldu -> y + r ldy (nr = 1: ldu, ldy unused); the scratch holds f.nrhs slabs.
 template <typename GT>
 static simm_status apply_t(const SpikeFactor& f, const GT* Gf, const GT* Hb, const GT* PsiL, const GT* PsiU,
-                           const cplx* u, cplx* y, const int* active, hipStream_t st) {
-    const unsigned blocks = (unsigned)((f.n + 255) / 256);
+                           const cplx* u, cplx* y, const int* active, hipStream_t st, int nr = 1, int64_t ldu = 0,
+                           int64_t ldy = 0) {
+    auto correct = [&](int K, const GT* Psi, const cplx* t, cplx* out, int64_t ld) {
+        if (nr == 4) launch_correct<GT, 4>(f, K, Psi, t, out, ld, active, st);
+        else if (nr == 2) launch_correct<GT, 2>(f, K, Psi, t, out, ld, active, st);
+        else launch_correct<GT, 1>(f, K, Psi, t, out, ld, active, st);
+    };
     // forward: z = L^{-1} P u
     cplx* z = f.z;
     SpikeFwdT<GT> a{};
@@ -1046,10 +1207,13 @@ static simm_status apply_t(const SpikeFactor& f, const GT* Gf, const GT* Hb, con
     a.y = z;
     a.tau = f.tauL;
     a.active = active;
-    SIMM_TRY(launch_fwd(a, f.P, 1, f.Wf, f.klx + 16, f.s, st));
-    SIMM_TRY(chain_states(f, true, f.klx, f.PhiL, f.tauL, f.tL, f.PiL, f.PiFullL, f.goutL, f.tgL, u, 0, active, st));
-    hipLaunchKernelGGL(k_spike_correct<GT>, dim3(blocks), dim3(256), sizeof(cplx) * 2 * f.klx, st, f.n, f.n16, f.klx,
-                       f.s, PsiL, (const cplx*)f.tL, z, active);
+    a.ldu = ldu;
+    a.ldy = f.n16;
+    a.ldt = f.P * (int64_t)f.klx;
+    SIMM_TRY(launch_fwd0(a, f.P, nr, f.Wf, f.klx + 16, f.s, st));
+    SIMM_TRY(chain_states(f, true, f.klx, f.PhiL, f.tauL, f.tL, f.PiL, f.PiFullL, f.goutL, f.tgL, u, 0, active, st, nr,
+                          ldu));
+    correct(f.klx, PsiL, f.tL, z, f.n16);
     // backward: y = U^{-1} z
     SpikeBwdT<GT> b{};
     b.n = f.n;
@@ -1062,11 +1226,13 @@ static simm_status apply_t(const SpikeFactor& f, const GT* Gf, const GT* Hb, con
     b.y = y;
     b.tau = f.tauU;
     b.active = active;
-    SIMM_TRY(launch_bwd(b, f.P, 1, f.Wb, f.K + 16, f.s, st));
+    b.ldu = f.n16;
+    b.ldy = ldy;
+    b.ldt = f.P * (int64_t)f.K;
+    SIMM_TRY(launch_bwd0(b, f.P, nr, f.Wb, f.K + 16, f.s, st));
     SIMM_TRY(chain_states(f, false, f.K, f.PhiU, f.tauU, f.tU, f.PiU, f.PiFullU, f.goutU, f.tgU, z, f.n16 - f.K, active,
-                          st));
-    hipLaunchKernelGGL(k_spike_correct<GT>, dim3(blocks), dim3(256), sizeof(cplx) * 2 * f.K, st, f.n, f.n16, f.K, f.s,
-                       PsiU, (const cplx*)f.tU, y, active);
+                          st, nr, f.n16));
+    correct(f.K, PsiU, f.tU, y, ldy);
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;
 }
@@ -1074,6 +1240,16 @@ static simm_status apply_t(const SpikeFactor& f, const GT* Gf, const GT* Hb, con
 simm_status spike_apply_diag(const SpikeFactor& f, const cplx* u, cplx* y, const int* active, hipStream_t st) {
     if (f.f32) return apply_t<cplxf>(f, f.Gf32, f.Hb32, f.PsiL32, f.PsiU32, u, y, active, st);
     return apply_t<cplx>(f, f.Gf, f.Hb, f.PsiL, f.PsiU, u, y, active, st);
+}
+
+simm_status spike_apply_diag_nr(const SpikeFactor& f, const cplx* u, int64_t ldu, cplx* y, int64_t ldy, int nr,
+                                hipStream_t st) {
+    if (!(nr == 1 || nr == 2 || nr == 4) || nr > f.nrhs || nr > spike_max_nrhs(f)) {
+        set_error("right-hand sides per application: 1, 2 or 4, within the scratch and the chunk kernels' LDS");
+        return SIMM_EINVAL;
+    }
+    if (f.f32) return apply_t<cplxf>(f, f.Gf32, f.Hb32, f.PsiL32, f.PsiU32, u, y, nullptr, st, nr, ldu, ldy);
+    return apply_t<cplx>(f, f.Gf, f.Hb, f.PsiL, f.PsiU, u, y, nullptr, st, nr, ldu, ldy);
 }
 
 simm_status spike_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int* active, hipStream_t st) {

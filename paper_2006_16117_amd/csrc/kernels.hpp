@@ -64,6 +64,9 @@ struct SpikeFwdT {
     GT* Psi;           // n16 x kl
     cplx* Phi;
     const int* active;
+    // mode 0 with several right-hand sides (the kernel's NR): column r of u, y and tau
+    // at u + r ldu, y + r ldy, tau + r ldt
+    int64_t ldu, ldy, ldt;
 };
 template <typename GT>
 struct SpikeBwdT {
@@ -79,6 +82,7 @@ struct SpikeBwdT {
     GT* Psi;           // n16 x K
     cplx* Phi;
     const int* active;
+    int64_t ldu, ldy, ldt;   // as in SpikeFwdT (ldu: of z)
 };
 using SpikeFwd = SpikeFwdT<cplx>;
 using SpikeBwd = SpikeBwdT<cplx>;
@@ -97,6 +101,9 @@ struct SpikeChain {
     unsigned* counter;    // one per group
     int* err;
     const int* active;
+    // several right-hand sides (the kernel's NR): state r of t and tau at + r ldt, of
+    // gout at + r ldg, of init_src at + r ldi
+    int64_t ldt, ldg, ldi;
 };
 struct SpikeFactor {
     int64_t n = 0, n16 = 0;
@@ -127,6 +134,9 @@ struct SpikeFactor {
     cplx *goutL = nullptr, *goutU = nullptr, *tgL = nullptr, *tgU = nullptr;
     unsigned* counter = nullptr;   // G + 1 counters
     int* err = nullptr;
+    // right-hand sides the per-application scratch above holds (z, tau*, t*, gout*, tg*
+    // in nrhs slabs each); applications with several at once: spike_apply_diag_nr
+    int nrhs = 1;
     // partitioned factorization (band_part.hip): A - sigma B = D + E with D block diagonal
     // (diagonal blocks of bs columns, the last one shorter) and E the couplings of
     // neighbouring blocks; the factor above is D's.  A solve is g = D^{-1} u, the reduced
@@ -147,6 +157,13 @@ simm_status spike_prepare(SpikeFactor& f, hipStream_t st);
 simm_status spike_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int* active, hipStream_t st);
 // an application with D's factor alone (the whole factor when not partitioned)
 simm_status spike_apply_diag(const SpikeFactor& f, const cplx* u, cplx* y, const int* active, hipStream_t st);
+// the same for nr right-hand sides at once (columns u + r ldu -> y + r ldy, r < nr), each
+// column computed exactly as spike_apply_diag computes it; nr <= f.nrhs and
+// nr <= spike_max_nrhs(f)
+simm_status spike_apply_diag_nr(const SpikeFactor& f, const cplx* u, int64_t ldu, cplx* y, int64_t ldy, int nr,
+                                hipStream_t st);
+// right-hand sides (1, 2 or 4) the chunk kernels of this factor take at once within the LDS
+int spike_max_nrhs(const SpikeFactor& f);
 
 // ---- partitioned factorization (band_part.hip) ----
 constexpr int64_t kPartMaxReduced = 2048;   // largest reduced order (its inverse is nr^2 entries)
@@ -163,7 +180,8 @@ simm_status part_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int* 
 void spike_release(SpikeFactor& f);
 // ordered = true: the scratch comes from the stream-ordered allocator on st and must be
 // freed with spike_release_ordered on st
-simm_status spike_clone_scratch(const SpikeFactor& base, SpikeFactor& out, hipStream_t st, bool ordered = false);
+simm_status spike_clone_scratch(const SpikeFactor& base, SpikeFactor& out, hipStream_t st, bool ordered = false,
+                                int nrhs = 1);
 void spike_release_ordered(SpikeFactor& f, hipStream_t st);
 int64_t spike_bytes_per_apply(const SpikeFactor& f);
 

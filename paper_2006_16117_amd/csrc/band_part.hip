@@ -292,6 +292,8 @@ constexpr int kSpikeStreams = 4;
 // turn, so that calls from several host threads (runs of a batch, factors built ahead)
 // mostly get streams of their own; each call orders its own work with events.
 constexpr int kPoolStreams = 16;
+}  // namespace
+
 simm_status spike_streams(hipStream_t* out) {
     static std::mutex mu;
     static std::map<int, std::array<hipStream_t, kPoolStreams>> pool;
@@ -309,6 +311,8 @@ simm_status spike_streams(hipStream_t* out) {
     for (int i = 0; i < kSpikeStreams; ++i) out[i] = it->second[first + i];
     return SIMM_OK;
 }
+
+namespace {
 
 simm_status spikes(const SpikeFactor& f, hipStream_t st) {
     const int kl = f.pkl, ku = f.pku, w = kl + ku;

@@ -1252,6 +1252,8 @@ simm_status associate(simm_pencil_s* p, const simm_params* prm, const cplx* f_de
     SIMM_TRY(schur_status.alloc(sizeof(int) * (ncell + 1), st));   // at most one shift per cell and the first
     SIMM_HIP_TRY(hipMemcpyAsync(cells_dev.p, cells_host.data(), sizeof(int64_t) * cells_host.size(),
                                 hipMemcpyHostToDevice, st));
+    // A stream of its own, made before the factors computed ahead make theirs (the HIP
+    // runtime gives a new stream the hardware queue that the fewest live streams use).
     struct SideStream {   // declared after the buffers its kernels use: joined before they are freed
         hipStream_t s = nullptr;
         hipEvent_t e = nullptr;
@@ -2930,6 +2932,15 @@ simm_status simm_pencil_create_banded(int64_t n, int32_t kl_a, int32_t ku_a, con
         SIMM_HIP_TRY(hipMemcpyAsync(p->B, b_band, sizeof(cplx) * nbb, kind, st));
     }
     SIMM_HIP_TRY(hipStreamSynchronize(st));
+    // A band that the shift factors partition uses the pooled spike streams: made now,
+    // before any stream of a run, they spread evenly over the hardware queues (the HIP
+    // runtime gives a new stream the queue that the fewest live streams use, so pooled
+    // streams made while a run's streams live would leave the queues unevenly used, and
+    // the worker streams made later would pile onto the least used one).
+    if (part_block_len(n, std::max(p->kla, p->klb), std::max(p->kua, p->kub)) > 0) {
+        hipStream_t pool[4] = {};
+        SIMM_TRY(spike_streams(pool));
+    }
     *out = p.release();
     return SIMM_OK;
 }

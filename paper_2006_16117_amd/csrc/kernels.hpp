@@ -177,6 +177,9 @@ size_t part_cpl_elems(int64_t n, int kl, int ku, int64_t bs);
 // spikes, the reduced system and its inverse of a prepared D factor (f.bs, f.cpl set)
 simm_status part_prepare(SpikeFactor& f, hipStream_t st);
 simm_status part_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int* active, hipStream_t st);
+// four streams of a per-device pool made on first use and kept for the process (each
+// call takes the next four in turn); callers order their work on them with events
+simm_status spike_streams(hipStream_t* out);
 void spike_release(SpikeFactor& f);
 // ordered = true: the scratch comes from the stream-ordered allocator on st and must be
 // freed with spike_release_ordered on st

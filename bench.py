@@ -30,8 +30,9 @@ sys.path.insert(0, ROOT)
 # is 4).  The driver computes one LU factor ahead per queue beyond the run's own (at
 # most 11), and streams beyond the queue count share queues and serialise.  Each
 # factor is a stream of short launches, and with more queues those launches slow the
-# run stream's own kernels more.  Means of 6 steps on the n = 40,000 workload: 7 ahead
-# with 8 queues 604 ms, 11 ahead with 12 queues 653 ms.  The other workloads keep 12:
+# run stream's own kernels more.  Means of 6 steps on the n = 40,000 workload: 6 ahead
+# with 8 queues 578-590 ms, 7 ahead 610 ms, 11 ahead with 12 queues 653 ms, 7 with 9
+# queues 679 ms, 8 with 10 queues 682 ms.  The other workloads keep 12:
 # their worker and spike streams share queues with 8 (adjoint gradient at n = 100,000:
 # 430 against 340 ms).
 def _workload_arg(argv):

@@ -322,7 +322,12 @@ simm_status spikes(const SpikeFactor& f, hipStream_t st) {
     // streams beyond the queues share one and their launches serialise
     int queues = 4;
     if (const char* e = getenv("GPU_MAX_HW_QUEUES")) queues = std::max(1, atoi(e));
-    const int ns = std::min({kSpikeStreams, w, std::max(2, queues)});
+    // at most as many streams as fit the device's budget of spinning chain workgroups,
+    // held (below, before the streams' release) until they are done
+    const int cw = spike_chain_weight(f);
+    const int ns = std::max(1, std::min({kSpikeStreams, w, std::max(2, queues), spike_chain_budget() / cw}));
+    ChainSlots slots;
+    SIMM_TRY(slots.acquire(ns * cw, st));
     hipStream_t ss[kSpikeStreams] = {};
     SIMM_TRY(spike_streams(ss));
     hipEvent_t ev[kSpikeStreams + 1] = {};

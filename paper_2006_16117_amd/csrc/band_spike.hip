@@ -29,6 +29,11 @@
 // register; per panel the rows meet once in LDS (one barrier), and the 16 values
 // every row needs are read by 16 lanes and broadcast with lane reads.  The matrix
 // is extended by identity to n16 = 16 ceil(n / 16) rows.
+#include <array>
+#include <condition_variable>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <type_traits>
 
 #include "common.hpp"
@@ -1095,6 +1100,66 @@ void spike_release(SpikeFactor& f) {
     (void)hipFree(f.part_mem);
     f.mem = nullptr;
     f.part_mem = nullptr;
+}
+
+// Chains of concurrent applications share the device.  A chain's workgroups spin at
+// device-scope barriers until all of a group's run, so chains on several streams whose
+// workgroups together exceed what the compute units hold could each wait for slots the
+// others' spinning workgroups keep (a bounded spin then reports the chain as timed
+// out).  Every phase that launches chains (a Krylov phase, the spike solves, a single
+// application) therefore holds, from before its first chain until its stream is done,
+// a share of a per-device budget of 256 compute units: a chain workgroup takes a
+// compute unit's registers for the 32- and 64-row forms (one wave per SIMD), half of
+// them for the 16-row form.  Only chains spin; every other kernel's workgroups leave.
+// A phase asking for more than the budget runs alone (a chain alone always progresses:
+// its groups are dispatched in order and wait only on themselves).
+namespace {
+constexpr int kChainBudget = 512;   // half compute units
+struct ChainBudget {
+    std::mutex mu;
+    std::condition_variable cv;
+    int avail = kChainBudget;
+};
+std::mutex g_budgets_mu;
+std::map<int, std::unique_ptr<ChainBudget>> g_budgets;
+ChainBudget* chain_budget(int dev) {
+    std::lock_guard<std::mutex> lk(g_budgets_mu);
+    auto& b = g_budgets[dev];
+    if (!b) b = std::make_unique<ChainBudget>();
+    return b.get();
+}
+}  // namespace
+
+int spike_chain_weight(const SpikeFactor& f) {
+    auto w = [&](int K) { return ((K + 15) / 16) * (int)std::max<int64_t>(1, f.G) * (K <= 16 * 16 ? 1 : 2); };
+    return std::max(1, std::min(kChainBudget, std::max(w(f.klx), w(f.K))));
+}
+
+int spike_chain_budget() { return kChainBudget; }
+
+simm_status ChainSlots::acquire(int weight, hipStream_t s) {
+    release();
+    weight = std::max(1, std::min(kChainBudget, weight));
+    SIMM_HIP_TRY(hipGetDevice(&dev));
+    ChainBudget* b = chain_budget(dev);
+    std::unique_lock<std::mutex> lk(b->mu);
+    b->cv.wait(lk, [&]() { return b->avail >= weight; });
+    b->avail -= weight;
+    w = weight;
+    st = s;
+    return SIMM_OK;
+}
+
+void ChainSlots::release() {
+    if (w <= 0) return;
+    (void)hipStreamSynchronize(st);   // the phase's chains are done
+    ChainBudget* b = chain_budget(dev);
+    {
+        std::lock_guard<std::mutex> lk(b->mu);
+        b->avail += w;
+    }
+    b->cv.notify_all();
+    w = 0;
 }
 
 // One chain launch: `groups` groups of L chunks (chain order) over P chunks, each group

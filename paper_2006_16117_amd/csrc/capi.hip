@@ -474,12 +474,32 @@ void release_stream_buffers(hipStream_t st) {
     }
 }
 
+// The current device's stream-ordered memory pool reuses a block freed on one stream
+// for another stream only once the free has run on the device (not on the strength of
+// event dependencies between the streams: those the runs make are for ordering work,
+// and the pool would otherwise hand a later allocation a block whose free is still
+// pending).  Set once per device.
+std::mutex g_pool_mu;
+std::set<int> g_pool_configured;
+void configure_pool() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (!g_pool_configured.insert(dev).second) return;
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) != hipSuccess || !pool) return;
+    int off = 0;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolReuseFollowEventDependencies, &off);
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolReuseAllowInternalDependencies, &off);
+}
+
 simm_status check_device() {
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || count == 0) {
         set_error("no HIP device");
         return SIMM_ENODEV;
     }
+    configure_pool();
     return SIMM_OK;
 }
 
@@ -788,6 +808,10 @@ simm_status krylov_shift(simm_shift_s* s, const cplx* f_dev, int m, hipStream_t 
         int init[4] = {INT_MAX, 1, m, 0};
         SIMM_HIP_TRY(hipMemcpyAsync(flags, init, sizeof(init), hipMemcpyHostToDevice, st));
     }
+    // the chains of this phase's applications hold their share of the device's budget
+    // until the phase is done on the device
+    ChainSlots slots;
+    SIMM_TRY(slots.acquire(spike_chain_weight(s->spike), st));
     // a3: b = (A - sigma B)^{-1} f, beta, v_1
     {
         KScope ks(clk, SIMM_K_BAND_SWEEP);
@@ -835,6 +859,7 @@ simm_status krylov_shift(simm_shift_s* s, const cplx* f_dev, int m, hipStream_t 
     std::vector<cplx> Hfull((size_t)(m + 1) * m);
     SIMM_HIP_TRY(hipMemcpyAsync(Hfull.data(), s->H, sizeof(cplx) * Hfull.size(), hipMemcpyDeviceToHost, st));
     SIMM_HIP_TRY(hipStreamSynchronize(st));
+    slots.release();
     if (spike_err != 0) {
         set_error("partitioned sweep: a chunk-chain barrier timed out");
         return SIMM_EHIP;
@@ -1150,15 +1175,15 @@ struct AheadBuild {
 
 // Number of shift factors the association may compute ahead: the requested
 // look-ahead (default: one per hardware queue the HIP runtime gives the process,
-// GPU_MAX_HW_QUEUES, 4 unless set, less the run's own, at most 11; more streams
-// than queues share a queue and run one after the other), cut so that the factors
-// take at most a quarter of the free device memory.
+// GPU_MAX_HW_QUEUES, 4 unless set, less the run stream's and the side stream's, at
+// most 11; more streams than queues share a queue and run one after the other), cut
+// so that the factors take at most a quarter of the free device memory.
 int lookahead_width(const simm_params* prm, const simm_pencil_s* p) {
     int w = prm->lookahead;
     if (w <= 0) {
         int queues = 4;
         if (const char* e = std::getenv("GPU_MAX_HW_QUEUES")) queues = std::max(1, std::atoi(e));
-        w = std::min(11, std::max(1, queues - 1));
+        w = std::min(11, std::max(1, queues - 2));
     }
     if (w <= 1) return 1;
     size_t free_b = 0, total_b = 0;
@@ -3139,6 +3164,8 @@ simm_status simm_shift_apply(simm_shift s, const double* x, double* y, int32_t m
         yd = yb.as<cplx>();
     }
     SIMM_TRY(prepare_input(n, xd, s->p->B, s->p->klb, s->p->kub, nullptr, nullptr, ub.as<cplx>(), nullptr, st));
+    ChainSlots slots;   // released (after a synchronize) when this returns
+    SIMM_TRY(slots.acquire(spike_chain_weight(s->spike), st));
     SIMM_TRY(apply_inverse(s, ub.as<const cplx>(), yd, nullptr, st));
     if (mem == SIMM_MEM_HOST) SIMM_HIP_TRY(hipMemcpyAsync(y, yd, sizeof(cplx) * n, hipMemcpyDeviceToHost, st));
     SIMM_HIP_TRY(hipStreamSynchronize(st));

@@ -164,6 +164,22 @@ simm_status spike_apply_diag_nr(const SpikeFactor& f, const cplx* u, int64_t ldu
                                 hipStream_t st);
 // right-hand sides (1, 2 or 4) the chunk kernels of this factor take at once within the LDS
 int spike_max_nrhs(const SpikeFactor& f);
+// Device-wide budget of the chains' spinning workgroups (band_spike.hip): a phase that
+// launches chains holds its weight from before its first launch until its stream is
+// done (release synchronizes the stream).  Weight of one stream's applications of f, in
+// half compute units, and the budget.
+int spike_chain_weight(const SpikeFactor& f);
+int spike_chain_budget();
+struct ChainSlots {
+    int dev = 0, w = 0;
+    hipStream_t st = nullptr;
+    ChainSlots() = default;
+    ChainSlots(const ChainSlots&) = delete;
+    ChainSlots& operator=(const ChainSlots&) = delete;
+    simm_status acquire(int weight, hipStream_t s);   // blocks the host until the weight is free
+    void release();
+    ~ChainSlots() { release(); }
+};
 
 // ---- partitioned factorization (band_part.hip) ----
 constexpr int64_t kPartMaxReduced = 2048;   // largest reduced order (its inverse is nr^2 entries)

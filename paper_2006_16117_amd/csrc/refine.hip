@@ -170,6 +170,8 @@ simm_status solve_backward_error(const SpikeFactor& f, const RefinePencil& pen, 
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, norms, 4);
     const int one = 1;
     SIMM_HIP_TRY(hipMemcpyAsync(gate, &one, sizeof(int), hipMemcpyHostToDevice, st));
+    ChainSlots slots;   // released (after a synchronize) when this returns
+    SIMM_TRY(slots.acquire(spike_chain_weight(f), st));
     SIMM_TRY(spike_apply(f, u, x, nullptr, st));
     hipLaunchKernelGGL(k_band_resid, dim3(blocks), dim3(256), 0, st, n, pen.A, pen.kla, pen.kua, pen.B, pen.klb,
                        pen.kub, pen.sigma, (const cplx*)u, (const cplx*)x, r, norms, (const int*)gate);

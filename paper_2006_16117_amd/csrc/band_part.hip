@@ -209,80 +209,127 @@ __global__ __launch_bounds__(256) void k_part_inverse(int64_t nr, int klr, int k
     for (int64_t i = threadIdx.x; i < nr; i += blockDim.x) Rinv[i * nr + c] = y[i];
 }
 
-// z = R^{-1} tips(g): one wavefront per reduced row (four rows a workgroup), each lane
-// summing its columns with four accumulators, then a fixed-order wave sum.
+// z_i = sum_c Rinv[i, c] g[tip(c)] for NR right-hand sides (g + r ldg -> z + r ldz): one
+// wavefront per reduced row, four accumulators per lane and column (a column's
+// operations are those of NR = 1).
+template <int NR>
 __global__ __launch_bounds__(256) void k_part_tips(int64_t nr, int kl, int ku, int64_t bs,
                                                    const cplx* __restrict__ Rinv, const cplx* __restrict__ g,
-                                                   cplx* __restrict__ z, const int* active) {
+                                                   int64_t ldg, cplx* __restrict__ z, int64_t ldz,
+                                                   const int* active) {
     if (active && *active == 0) return;
     const int lane = threadIdx.x & 63;
     const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= nr) return;
     const cplx* row = Rinv + i * nr;
-    cplx acc[4] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+    cplx acc[NR][4];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[r][u] = mk(0.0, 0.0);
     int64_t c = lane;
     for (; c + 3 * 64 < nr; c += 4 * 64) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc[u] = fma_c(acc[u], row[c + u * 64], g[tip_row(c + u * 64, kl, ku, bs)]);
-    }
-    for (int u = 0; c < nr; c += 64, ++u) acc[u] = fma_c(acc[u], row[c], g[tip_row(c, kl, ku, bs)]);
-    cplx t = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+        for (int u = 0; u < 4; ++u) {
+            const cplx rv = row[c + u * 64];
+            const int64_t tr = tip_row(c + u * 64, kl, ku, bs);
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        t.re += __shfl_xor(t.re, m, 64);
-        t.im += __shfl_xor(t.im, m, 64);
+            for (int r = 0; r < NR; ++r) acc[r][u] = fma_c(acc[r][u], rv, g[tr + r * ldg]);
+        }
     }
-    if (lane == 0) z[i] = t;
+    for (int u = 0; c < nr; c += 64, ++u) {
+        const cplx rv = row[c];
+        const int64_t tr = tip_row(c, kl, ku, bs);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[r][u] = fma_c(acc[r][u], rv, g[tr + r * ldg]);
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        cplx t = (acc[r][0] + acc[r][1]) + (acc[r][2] + acc[r][3]);
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+            t.re += __shfl_xor(t.re, m, 64);
+            t.im += __shfl_xor(t.im, m, 64);
+        }
+        if (lane == 0) z[i + r * ldz] = t;
+    }
 }
 
 // y_i = g_i - sum_k V[i,k] t_j[k] - sum_k W[i,k] b_{j-1}[k], j the block of row i: one
 // thread per row, the tips of the (at most two) blocks of the workgroup's rows staged in
-// LDS, four accumulators per row.
+// LDS, four accumulators per row; NR right-hand sides (z + r ldz, g + r ldg,
+// y + r ldy) share the loads of V and W.
+template <int NR>
 __global__ __launch_bounds__(256) void k_part_correct(int64_t n, int64_t n16, int kl, int ku, int64_t bs,
                                                       int64_t nbk, const cplx* __restrict__ V,
                                                       const cplx* __restrict__ W, const cplx* __restrict__ z,
-                                                      const cplx* __restrict__ g, cplx* __restrict__ y,
-                                                      const int* active) {
+                                                      int64_t ldz, const cplx* __restrict__ g, int64_t ldg,
+                                                      cplx* __restrict__ y, int64_t ldy, const int* active) {
     if (active && *active == 0) return;
     extern __shared__ double2 zsm[];
-    cplx* zs = reinterpret_cast<cplx*>(zsm);   // 2 x (ku + kl): t_j then b_{j-1}, for blocks jb, jb + 1
+    cplx* zs = reinterpret_cast<cplx*>(zsm);   // NR x 2 x (ku + kl): t_j then b_{j-1}, for blocks jb, jb + 1
     const int w = kl + ku;
     const int64_t r0 = (int64_t)blockIdx.x * 256;
     const int64_t jb = r0 / bs;
     for (int e = threadIdx.x; e < 2 * w; e += 256) {
         const int64_t j = jb + e / w;
         const int q = e % w;
-        cplx v = mk(0.0, 0.0);
-        if (q < ku) {
-            if (j <= nbk - 2) v = z[j * w + kl + q];
-        } else {
-            if (j >= 1 && j <= nbk - 1) v = z[(j - 1) * w + (q - ku)];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            cplx v = mk(0.0, 0.0);
+            if (q < ku) {
+                if (j <= nbk - 2) v = z[j * w + kl + q + r * ldz];
+            } else {
+                if (j >= 1 && j <= nbk - 1) v = z[(j - 1) * w + (q - ku) + r * ldz];
+            }
+            zs[r * 2 * w + e] = v;
         }
-        zs[e] = v;
     }
     __syncthreads();
     const int64_t i = r0 + threadIdx.x;
     if (i >= n) return;
     const int64_t j = i / bs;
-    const cplx* tz = zs + (j - jb) * w;         // t_j (ku values), then b_{j-1} (kl values)
-    cplx acc[4] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+    const int off = (int)(j - jb) * w;          // t_j (ku values), then b_{j-1} (kl values)
+    cplx acc[NR][4];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[r][u] = mk(0.0, 0.0);
     if (j <= nbk - 2) {
         int k = 0;
         for (; k + 3 < ku; k += 4) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acc[u] = fma_c(acc[u], V[i + (int64_t)(k + u) * n16], tz[k + u]);
+            for (int u = 0; u < 4; ++u) {
+                const cplx v = V[i + (int64_t)(k + u) * n16];
+#pragma unroll
+                for (int r = 0; r < NR; ++r) acc[r][u] = fma_c(acc[r][u], v, zs[r * 2 * w + off + k + u]);
+            }
         }
-        for (int u = 0; k < ku; ++k, ++u) acc[u] = fma_c(acc[u], V[i + (int64_t)k * n16], tz[k]);
+        for (int u = 0; k < ku; ++k, ++u) {
+            const cplx v = V[i + (int64_t)k * n16];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) acc[r][u] = fma_c(acc[r][u], v, zs[r * 2 * w + off + k]);
+        }
     }
     if (j >= 1) {
         int k = 0;
         for (; k + 3 < kl; k += 4) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acc[u] = fma_c(acc[u], W[i + (int64_t)(k + u) * n16], tz[ku + k + u]);
+            for (int u = 0; u < 4; ++u) {
+                const cplx v = W[i + (int64_t)(k + u) * n16];
+#pragma unroll
+                for (int r = 0; r < NR; ++r) acc[r][u] = fma_c(acc[r][u], v, zs[r * 2 * w + off + ku + k + u]);
+            }
         }
-        for (int u = 0; k < kl; ++k, ++u) acc[u] = fma_c(acc[u], W[i + (int64_t)k * n16], tz[ku + k]);
+        for (int u = 0; k < kl; ++k, ++u) {
+            const cplx v = W[i + (int64_t)k * n16];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) acc[r][u] = fma_c(acc[r][u], v, zs[r * 2 * w + off + ku + k]);
+        }
     }
-    y[i] = g[i] - ((acc[0] + acc[1]) + (acc[2] + acc[3]));
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+        y[i + r * ldy] = g[i + r * ldg] - ((acc[r][0] + acc[r][1]) + (acc[r][2] + acc[r][3]));
 }
 
 constexpr int kSpikeStreams = 4;
@@ -494,14 +541,32 @@ simm_status part_prepare(SpikeFactor& f, hipStream_t st) {
     return SIMM_OK;
 }
 
+namespace {
+template <int NR>
+void part_tail(const SpikeFactor& f, cplx* y, int64_t ldy, const int* active, hipStream_t st) {
+    hipLaunchKernelGGL((k_part_tips<NR>), dim3((unsigned)((f.nr + 3) / 4)), dim3(256), 0, st, f.nr, f.pkl, f.pku, f.bs,
+                       (const cplx*)f.Rinv, (const cplx*)f.pg, f.n16, f.pz, f.nr, active);
+    hipLaunchKernelGGL((k_part_correct<NR>), dim3((unsigned)((f.n + 255) / 256)), dim3(256),
+                       sizeof(cplx) * 2 * (size_t)(f.pkl + f.pku) * NR, st, f.n, f.n16, f.pkl, f.pku, f.bs, f.nbk,
+                       (const cplx*)f.Vs, (const cplx*)f.Ws, (const cplx*)f.pz, f.nr, (const cplx*)f.pg, f.n16, y, ldy,
+                       active);
+}
+}  // namespace
+
 simm_status part_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int* active, hipStream_t st) {
     SIMM_TRY(spike_apply_diag(f, u, f.pg, active, st));
-    hipLaunchKernelGGL(k_part_tips, dim3((unsigned)((f.nr + 3) / 4)), dim3(256), 0, st, f.nr, f.pkl, f.pku, f.bs,
-                       (const cplx*)f.Rinv, (const cplx*)f.pg, f.pz, active);
-    hipLaunchKernelGGL(k_part_correct, dim3((unsigned)((f.n + 255) / 256)), dim3(256),
-                       sizeof(cplx) * 2 * (size_t)(f.pkl + f.pku), st, f.n, f.n16, f.pkl,
-                       f.pku, f.bs, f.nbk, (const cplx*)f.Vs, (const cplx*)f.Ws, (const cplx*)f.pz,
-                       (const cplx*)f.pg, y, active);
+    part_tail<1>(f, y, f.n16, active, st);
+    SIMM_HIP_TRY(hipGetLastError());
+    return SIMM_OK;
+}
+
+simm_status part_apply_nr(const SpikeFactor& f, const cplx* u, int64_t ldu, cplx* y, int64_t ldy, int nr,
+                          hipStream_t st) {
+    // g = D^{-1} u for the nr columns (f.pg and f.pz hold f.nrhs columns each)
+    SIMM_TRY(spike_apply_diag_nr(f, u, ldu, f.pg, f.n16, nr, st));
+    if (nr == 4) part_tail<4>(f, y, ldy, nullptr, st);
+    else if (nr == 2) part_tail<2>(f, y, ldy, nullptr, st);
+    else part_tail<1>(f, y, ldy, nullptr, st);
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;
 }

@@ -205,11 +205,15 @@ __global__ __launch_bounds__(T) void k_chunk_fwd(SpikeFwdT<GT> a) {
     const int npan = len / 16;
     // LDS: window values by slot (2 x NR x RW, alternating per panel), the chunk's
     // outputs (NR x len), its input rows J0+kl .. J1+RW-1 (len + 16; NR columns of them
-    // in mode 0) and its pivots (len)
+    // in mode 0) and its pivots (len).  Several zero-state columns write their outputs
+    // over their inputs: the output of step i (entry 16 i + pos) replaces an input read
+    // at an earlier step (or before the first), across a barrier.
     const int NI = (a.mode == 0) ? NR : 1;
+    const bool inplace = NR > 1 && a.mode == 0;
     cplx* S = reinterpret_cast<cplx*>(sraw);
     cplx* outb = S + 2 * NR * RW;
-    cplx* inb = outb + NR * len;
+    cplx* inb = outb + (inplace ? 0 : NR * len);
+    auto outc = [&](int u) { return inplace ? inb + u * (len + 16) : outb + u * len; };
     int* pivb = reinterpret_cast<int*>(inb + NI * (len + 16));
     for (int q = tid; q < len; q += T) pivb[q] = a.ipiv[J0 + q] - (int)(J0 + (q & ~15));
     for (int q = tid; q < len + 16; q += T) {
@@ -274,7 +278,7 @@ __global__ __launch_bounds__(T) void k_chunk_fwd(SpikeFwdT<GT> a) {
             for (int q = 0; q < 16; ++q) acc = fma_c(acc, gc[q], rdl(tq, q));
             if (mine) {
                 if (pos < 16) {
-                    ldsw(outb + u * len + 16 * i + pos, acc);
+                    ldsw(outc(u) + 16 * i + pos, acc);
                     // row J0 + 16 i + RW + pos enters (zero in mode 1)
                     val[u] = inb[(a.mode == 0 ? u : 0) * (len + 16) + 16 * i + 16 + pos];
                 } else {
@@ -317,7 +321,7 @@ __global__ __launch_bounds__(T) void k_chunk_fwd(SpikeFwdT<GT> a) {
 #pragma unroll
         for (int u = 0; u < NR; ++u)
             for (int q = tid; q < len; q += T) {
-                const cplx v = ldsr(outb + u * len + q);
+                const cplx v = ldsr(outc(u) + q);
                 if (J0 + q < a.n) a.y[J0 + q + u * a.ldy] = v;
             }
     } else {
@@ -344,11 +348,15 @@ __global__ __launch_bounds__(T) void k_chunk_bwd(SpikeBwdT<GT> a) {
     const int len = (int)(J1 - J0);
     const int npan = len / 16;
     // LDS: window (2 x NR x RW), outputs (NR x len), input rows J0-K-16 .. J1-K-1 (len + 16;
-    // NR columns of them in mode 0)
+    // NR columns of them in mode 0).  Several zero-state columns write their outputs over
+    // their inputs: a step's output entry is the entry its thread reads the entering row
+    // from, read first.
     const int NI = (a.mode == 0) ? NR : 1;
+    const bool inplace = NR > 1 && a.mode == 0;
     cplx* S = reinterpret_cast<cplx*>(sraw);
     cplx* outb = S + 2 * NR * RW;
-    cplx* inb = outb + NR * len;
+    cplx* inb = outb + (inplace ? 0 : NR * len);
+    auto outc = [&](int u) { return inplace ? inb + u * (len + 16) : outb + u * len; };
     const int64_t in0 = J0 - K - 16;
     for (int q = tid; q < len + 16; q += T) {
         const int64_t row = in0 + q;
@@ -401,9 +409,10 @@ __global__ __launch_bounds__(T) void k_chunk_bwd(SpikeBwdT<GT> a) {
             for (int q = 0; q < 16; ++q) acc = fma_c(acc, hc[q], rdl(bq, q));
             if (mine) {
                 if (pos >= K) {
-                    ldsw(outb + u * len + (16 * p - J0) + pos - K, acc);
                     // row j0-16-K + (pos-K) enters (zero in mode 1)
-                    val[u] = inb[(a.mode == 0 ? u : 0) * (len + 16) + (16 * p - 16 - K + pos - K) - in0];
+                    const cplx enter = inb[(a.mode == 0 ? u : 0) * (len + 16) + (16 * p - 16 - K + pos - K) - in0];
+                    ldsw(outc(u) + (16 * p - J0) + pos - K, acc);
+                    val[u] = enter;
                 } else {
                     val[u] = acc;
                 }
@@ -444,7 +453,7 @@ __global__ __launch_bounds__(T) void k_chunk_bwd(SpikeBwdT<GT> a) {
 #pragma unroll
         for (int u = 0; u < NR; ++u)
             for (int q = tid; q < len; q += T) {
-                const cplx v = ldsr(outb + u * len + q);
+                const cplx v = ldsr(outc(u) + q);
                 if (J0 + q < a.n) a.y[J0 + q + u * a.ldy] = v;
             }
     } else {
@@ -803,7 +812,9 @@ simm_status launch_bwd(const Args& a, int64_t P, int nrhs, int W, int rows, int6
 // zero-state sweeps of nr columns: window (2 nr rows) + outputs (nr s) + inputs (nr (s + 16))
 // complex, and s pivots
 size_t window_lds0(int rows, int64_t s, int nr) {
-    return sizeof(cplx) * (2 * (size_t)nr * rows + (size_t)nr * s + (size_t)nr * (s + 16)) + sizeof(int) * (size_t)s;
+    // several columns: outputs over inputs
+    const size_t outs = nr > 1 ? 0 : (size_t)s;
+    return sizeof(cplx) * (2 * (size_t)nr * rows + outs + (size_t)nr * (s + 16)) + sizeof(int) * (size_t)s;
 }
 
 template <typename Args>
@@ -1082,7 +1093,7 @@ simm_status spike_clone_scratch(const SpikeFactor& base, SpikeFactor& out, hipSt
     out.err = reinterpret_cast<int*>(take(4));
     if (base.bs > 0) {
         out.pg = take((size_t)base.n16 * nrhs);
-        out.pz = take((size_t)base.nr);
+        out.pz = take((size_t)base.nr * nrhs);
     }
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned*>(out.err), 1, 0u);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, out.counter, (int)((base.G + 1) * SPIKE_CTR_STRIDE), 0u);
@@ -1315,6 +1326,12 @@ simm_status spike_apply_diag_nr(const SpikeFactor& f, const cplx* u, int64_t ldu
     }
     if (f.f32) return apply_t<cplxf>(f, f.Gf32, f.Hb32, f.PsiL32, f.PsiU32, u, y, nullptr, st, nr, ldu, ldy);
     return apply_t<cplx>(f, f.Gf, f.Hb, f.PsiL, f.PsiU, u, y, nullptr, st, nr, ldu, ldy);
+}
+
+simm_status spike_apply_nr(const SpikeFactor& f, const cplx* u, int64_t ldu, cplx* y, int64_t ldy, int nr,
+                           hipStream_t st) {
+    if (f.bs > 0) return part_apply_nr(f, u, ldu, y, ldy, nr, st);
+    return spike_apply_diag_nr(f, u, ldu, y, ldy, nr, st);
 }
 
 simm_status spike_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int* active, hipStream_t st) {

@@ -887,6 +887,112 @@ simm_status krylov_shift(simm_shift_s* s, const cplx* f_dev, int m, hipStream_t 
     return SIMM_OK;
 }
 
+// The Krylov phases (steps a3-a5) of nr <= 4 spaces of one factor in lockstep: every
+// application of M takes the nr current basis vectors in one pass over the factor
+// (spike_apply_nr, each column as alone); the Gram-Schmidt steps, H, beta and the
+// Schur forms stay per space, so each space gets exactly what krylov_shift gives it.
+// kvs[r] borrow the factor (sweep data ready, FP64), and kvs[0]->spike's scratch holds
+// nr columns; start vector r at F + r ldf.
+simm_status krylov_block(simm_shift_s* const* kvs, int nr, const cplx* F, int64_t ldf, int m, hipStream_t st) {
+    simm_shift_s* k0 = kvs[0];
+    const SpikeFactor& f = k0->spike;
+    if (nr < 1 || nr > 4 || nr > f.nrhs || nr > spike_max_nrhs(f) || k0->mixed) {
+        set_error("Krylov spaces in lockstep: 1 to 4 FP64 spaces within the factor's scratch");
+        return SIMM_EINVAL;
+    }
+    simm_pencil_s* p = k0->p;
+    const int64_t n = p->n, n16 = f.n16;
+    const int nblk = gs_row_blocks(n);
+    const int64_t rows = (n + nblk - 1) / nblk;
+    const int nblk_eff = (int)((n + rows - 1) / rows);
+    DevBuf work[4], uy;
+    ArnoldiWork aw[4];
+    int* flags[4] = {};
+    double* beta_d[4] = {};
+    const size_t bytes = sizeof(cplx) * ((size_t)nblk_eff * (m + 2) + 2 * (size_t)(m + 2)) + sizeof(double) * 4 +
+                         sizeof(int) * 8;
+    for (int r = 0; r < nr; ++r) {
+        simm_shift_s* s = kvs[r];
+        s->m = m;
+        SIMM_TRY(ensure_dev(&s->V, s->cap_V, (size_t)n * (m + 1)));
+        SIMM_TRY(ensure_dev(&s->H, s->cap_H, (size_t)(m + 1) * m));
+        SIMM_HIP_TRY(hipMemsetAsync(s->H, 0, sizeof(cplx) * (m + 1) * m, st));
+        SIMM_TRY(work[r].alloc(bytes + 8 * 256, st));
+        char* wp = work[r].as<char>();
+        auto take = [&](size_t b) {
+            char* q = wp;
+            wp += (b + 255) & ~(size_t)255;
+            return q;
+        };
+        aw[r].nblk = nblk_eff;
+        aw[r].partial = reinterpret_cast<cplx*>(take(sizeof(cplx) * (size_t)nblk_eff * (m + 2)));
+        aw[r].h1 = reinterpret_cast<cplx*>(take(sizeof(cplx) * (m + 2)));
+        aw[r].h2 = reinterpret_cast<cplx*>(take(sizeof(cplx) * (m + 2)));
+        aw[r].hnorm = reinterpret_cast<double*>(take(sizeof(double) * 4));
+        aw[r].u = nullptr;   // the block's own input buffer serves every space
+        flags[r] = reinterpret_cast<int*>(take(sizeof(int) * 8));   // [1] active, [2] m_eff, [3] schur status
+        beta_d[r] = aw[r].hnorm + 2;
+        int init[4] = {INT_MAX, 1, m, 0};
+        SIMM_HIP_TRY(hipMemcpyAsync(flags[r], init, sizeof(init), hipMemcpyHostToDevice, st));
+    }
+    SIMM_TRY(uy.alloc(sizeof(cplx) * (size_t)n16 * nr * 2, st));
+    cplx* U = uy.as<cplx>();
+    cplx* Y = U + n16 * nr;
+    ChainSlots slots;
+    SIMM_TRY(slots.acquire(spike_chain_weight(f), st));
+    // a3: b = (A - sigma B)^{-1} f, beta, v_1
+    SIMM_TRY(spike_apply_nr(f, F, ldf, Y, n16, nr, st));
+    for (int r = 0; r < nr; ++r) {
+        SIMM_HIP_TRY(hipMemcpyAsync(kvs[r]->V, Y + r * n16, sizeof(cplx) * n, hipMemcpyDeviceToDevice, st));
+        SIMM_TRY(vec_norm_scale(n, kvs[r]->V, kvs[r]->V, beta_d[r], aw[r], st));
+    }
+    // a4: Arnoldi steps (a space that broke down keeps receiving applications; its
+    // Gram-Schmidt steps are skipped and nothing reads those columns)
+    for (int j = 0; j < m; ++j) {
+        for (int r = 0; r < nr; ++r)
+            SIMM_TRY(prepare_input(n, kvs[r]->V + (int64_t)j * n, p->B, p->klb, p->kub, nullptr, nullptr, U + r * n16,
+                                   nullptr, st));
+        SIMM_TRY(spike_apply_nr(f, U, n16, Y, n16, nr, st));
+        for (int r = 0; r < nr; ++r) {
+            simm_shift_s* s = kvs[r];
+            SIMM_HIP_TRY(hipMemcpyAsync(s->V + (int64_t)(j + 1) * n, Y + r * n16, sizeof(cplx) * n,
+                                        hipMemcpyDeviceToDevice, st));
+            SIMM_TRY(arnoldi_step(n, s->V, n, j, s->H, m + 1, aw[r], flags[r] + 1, flags[r] + 2, st));
+        }
+    }
+    int spike_err = 0;
+    int fl[4][4];
+    double beta[4] = {};
+    std::vector<cplx> Hfull((size_t)nr * (m + 1) * m);
+    SIMM_HIP_TRY(hipMemcpyAsync(&spike_err, f.err, sizeof(int), hipMemcpyDeviceToHost, st));
+    for (int r = 0; r < nr; ++r) {
+        SIMM_HIP_TRY(hipMemcpyAsync(fl[r], flags[r], sizeof(fl[r]), hipMemcpyDeviceToHost, st));
+        SIMM_HIP_TRY(hipMemcpyAsync(&beta[r], beta_d[r], sizeof(double), hipMemcpyDeviceToHost, st));
+        SIMM_HIP_TRY(hipMemcpyAsync(Hfull.data() + (size_t)r * (m + 1) * m, kvs[r]->H, sizeof(cplx) * (m + 1) * m,
+                                    hipMemcpyDeviceToHost, st));
+    }
+    SIMM_HIP_TRY(hipStreamSynchronize(st));
+    slots.release();
+    if (spike_err != 0) {
+        set_error("partitioned sweep: a chunk-chain barrier timed out");
+        return SIMM_EHIP;
+    }
+    for (int r = 0; r < nr; ++r) {
+        simm_shift_s* s = kvs[r];
+        s->m_eff = fl[r][2];
+        s->beta = beta[r];
+        const int me = s->m_eff;
+        const cplx* Hr = Hfull.data() + (size_t)r * (m + 1) * m;
+        s->H_host.assign((size_t)(me + 1) * me, cplx{0, 0});
+        for (int j = 0; j < me; ++j)
+            for (int i = 0; i <= me; ++i) s->H_host[i + (size_t)j * (me + 1)] = Hr[i + (size_t)j * (m + 1)];
+        s->h_last = cabs(s->H_host[me + (size_t)(me - 1) * (me + 1)]);
+        // a5: Schur form of H_m
+        SIMM_TRY(schur_phase(s, m + 1, flags[r] + 3, st));
+    }
+    return SIMM_OK;
+}
+
 // Both phases of one shift (hot-path steps a1-a5).
 simm_status build_shift(simm_pencil_s* p, cplx sigma, const cplx* f_dev, int m, hipStream_t st,
                         std::unique_ptr<simm_shift_s>& out, int64_t* applies, KernelClock* clk = nullptr,
@@ -2683,7 +2789,7 @@ simm_status gradient(const std::vector<simm_shift_s*>& shifts, const std::vector
         hipStream_t st = nullptr;
         SpikeFactor sp;
         bool has_sp = false;
-        simm_shift_s kv;   // one adjoint space after another (its basis and Schur buffers kept)
+        simm_shift_s kv[4];   // the adjoint spaces of a block of squares (bases and Schur buffers kept)
         DevBuf xb, zb, z1b, yb, cwb, kb, pb, rhob;
         simm_status rc = SIMM_OK;
         std::string msg;
@@ -2716,7 +2822,7 @@ simm_status gradient(const std::vector<simm_shift_s*>& shifts, const std::vector
     for (int w = 0; w < W; ++w) {
         Worker& x = wk[(size_t)w];
         SIMM_HIP_TRY(hipStreamCreateWithFlags(&x.st, hipStreamNonBlocking));
-        SIMM_TRY(x.xb.alloc(sizeof(cplx) * (size_t)n, st));
+        SIMM_TRY(x.xb.alloc(sizeof(cplx) * (size_t)n * 4, st));   // x_R of up to four squares
         if (A1) SIMM_TRY(x.z1b.alloc(sizeof(cplx) * (size_t)n * 128, st));
         if (grad) SIMM_TRY(x.zb.alloc(sizeof(cplx) * (size_t)n * 128, st));
         SIMM_TRY(x.yb.alloc(sizeof(cplx) * (size_t)2 * nf * LDY, st));
@@ -2758,30 +2864,20 @@ simm_status gradient(const std::vector<simm_shift_s*>& shifts, const std::vector
             for (int k = 0; k < mf; ++k)
                 SIMM_TRY(prepare_input(n, fs->V + (int64_t)k * n, A1, kl1, ku1, nullptr, nullptr,
                                        wb.as<cplx>() + (int64_t)k * n, nullptr, st));
+        // squares in blocks of NB whose adjoint spaces advance in lockstep (one pass over
+        // the adjoint factor per step for all of them)
+        const int NB = af->mixed ? 1 : std::min(4, spike_max_nrhs(af->spike));
         for (auto& x : wk) {
             if (x.has_sp) spike_release(x.sp);
             x.has_sp = false;
-            SIMM_TRY(spike_clone_scratch(af->spike, x.sp, st));
+            SIMM_TRY(spike_clone_scratch(af->spike, x.sp, st, false, NB));
             x.has_sp = true;
         }
         SIMM_HIP_TRY(hipStreamSynchronize(st));
         const ShiftDev fd = shift_dev(fs);
-        // one square on worker x: x_R, the adjoint Krylov space, K_R, Z, Z1, row dots
-        auto square = [&](Worker& x, int w, int64_t r) -> simm_status {
-            SIMM_TRY(project(n, mf, fs->V, n, sums + (2 * r + 1) * mmax, mmax, 1, x.xb.as<cplx>(), nullptr, nullptr,
-                             0, SIMM_PROJ_FP64, x.st));
-            simm_shift_s& kv = x.kv;
-            kv.p = &adj;
-            kv.sigma = af->sigma;
-            kv.kl = af->kl;
-            kv.ku = af->ku;
-            kv.AB = af->AB;
-            kv.ipiv = af->ipiv;
-            kv.LP = af->LP;
-            kv.spike = x.sp;
-            kv.sweeps_ready = true;
-            kv.factor_borrowed = true;
-            SIMM_TRY(krylov_shift(&kv, x.xb.as<cplx>(), fs->m, x.st, nullptr));
+        // a block of squares on worker x: their x_R and adjoint Krylov spaces (in lockstep),
+        // then per square K_R, Z, Z1 and the row dots
+        auto square_rest = [&](Worker& x, int w, int64_t r, simm_shift_s& kv, const cplx* xr) -> simm_status {
             const int ma = kv.m_eff;
             if (ma > 128) {
                 set_error("Krylov dimension above 128");
@@ -2803,7 +2899,7 @@ simm_status gradient(const std::vector<simm_shift_s*>& shifts, const std::vector
                 SIMM_TRY(project(n, mf, wb.as<cplx>(), n, x.kb.as<cplx>(), mf, ma, x.z1b.as<cplx>(), nullptr,
                                  nullptr, 0, SIMM_PROJ_FP64, x.st));
             SIMM_TRY(grad_rowdot(n, ma, kv.V, n, grad ? x.zb.as<cplx>() : nullptr, A1 ? x.z1b.as<cplx>() : nullptr,
-                                 n, x.xb.as<cplx>(), grad ? gradsb.as<cplx>() + (int64_t)w * n : nullptr,
+                                 n, xr, grad ? gradsb.as<cplx>() + (int64_t)w * n : nullptr,
                                  x.pb.as<cplx>(), accb.as<double>() + 2 * w, x.st));
             std::vector<double> rho_adj((size_t)nf);
             SIMM_HIP_TRY(hipMemcpyAsync(rho_adj.data(), x.rhob.p, sizeof(double) * nf, hipMemcpyDeviceToHost, x.st));
@@ -2821,13 +2917,40 @@ simm_status gradient(const std::vector<simm_shift_s*>& shifts, const std::vector
             }
             return SIMM_OK;
         };
+        auto block = [&](Worker& x, int w, const int64_t* sq, int nb) -> simm_status {
+            simm_shift_s* kvp[4];
+            for (int b = 0; b < nb; ++b) {
+                SIMM_TRY(project(n, mf, fs->V, n, sums + (2 * sq[b] + 1) * mmax, mmax, 1, x.xb.as<cplx>() + b * n,
+                                 nullptr, nullptr, 0, SIMM_PROJ_FP64, x.st));
+                simm_shift_s& kv = x.kv[b];
+                kv.p = &adj;
+                kv.sigma = af->sigma;
+                kv.kl = af->kl;
+                kv.ku = af->ku;
+                kv.AB = af->AB;
+                kv.ipiv = af->ipiv;
+                kv.LP = af->LP;
+                kv.spike = x.sp;
+                kv.sweeps_ready = true;
+                kv.factor_borrowed = true;
+                kvp[b] = &kv;
+            }
+            if (nb == 1) SIMM_TRY(krylov_shift(kvp[0], x.xb.as<cplx>(), fs->m, x.st, nullptr));
+            else SIMM_TRY(krylov_block(kvp, nb, x.xb.as<cplx>(), n, fs->m, x.st));
+            for (int b = 0; b < nb; ++b) SIMM_TRY(square_rest(x, w, sq[b], x.kv[b], x.xb.as<cplx>() + b * n));
+            return SIMM_OK;
+        };
+        // blocks of NB consecutive squares, dealt to the workers in turn across shifts
+        const int64_t nblocks = ((int64_t)rs.size() + NB - 1) / NB;
         const int64_t first = next_worker;
         auto run_worker = [&](int w) {
             (void)hipSetDevice(dev);
             Worker& x = wk[(size_t)w];
-            for (size_t k = 0; k < rs.size(); ++k) {
-                if ((int)((first + (int64_t)k) % W) != w) continue;
-                const simm_status rc = square(x, w, rs[k]);
+            for (int64_t q = 0; q < nblocks; ++q) {
+                if ((int)((first + q) % W) != w) continue;
+                const int64_t k0 = q * NB;
+                const int nb = (int)std::min<int64_t>(NB, (int64_t)rs.size() - k0);
+                const simm_status rc = block(x, w, rs.data() + k0, nb);
                 if (rc != SIMM_OK) {
                     x.rc = rc;
                     x.msg = simm_last_error();
@@ -2839,7 +2962,7 @@ simm_status gradient(const std::vector<simm_shift_s*>& shifts, const std::vector
         for (int w = 1; w < W; ++w) pool.emplace_back(run_worker, w);
         run_worker(0);
         for (auto& t : pool) t.join();
-        next_worker = (first + (int64_t)rs.size()) % W;
+        next_worker = (first + nblocks) % W;
         for (auto& x : wk) {
             if (x.rc != SIMM_OK) {
                 for (auto& y : wk) (void)hipStreamSynchronize(y.st);   // before af and the buffers go

@@ -193,6 +193,12 @@ size_t part_cpl_elems(int64_t n, int kl, int ku, int64_t bs);
 // spikes, the reduced system and its inverse of a prepared D factor (f.bs, f.cpl set)
 simm_status part_prepare(SpikeFactor& f, hipStream_t st);
 simm_status part_apply(const SpikeFactor& f, const cplx* u, cplx* y, const int* active, hipStream_t st);
+simm_status part_apply_nr(const SpikeFactor& f, const cplx* u, int64_t ldu, cplx* y, int64_t ldy, int nr,
+                          hipStream_t st);
+// nr applications at once of the whole factor (partitioned or not): columns u + r ldu ->
+// y + r ldy, each as spike_apply computes it; needs nr <= f.nrhs, nr <= spike_max_nrhs(f)
+simm_status spike_apply_nr(const SpikeFactor& f, const cplx* u, int64_t ldu, cplx* y, int64_t ldy, int nr,
+                           hipStream_t st);
 // four streams of a per-device pool made on first use and kept for the process (each
 // call takes the next four in turn); callers order their work on them with events
 simm_status spike_streams(hipStream_t* out);

@@ -987,9 +987,30 @@ simm_status krylov_block(simm_shift_s* const* kvs, int nr, const cplx* F, int64_
         for (int j = 0; j < me; ++j)
             for (int i = 0; i <= me; ++i) s->H_host[i + (size_t)j * (me + 1)] = Hr[i + (size_t)j * (m + 1)];
         s->h_last = cabs(s->H_host[me + (size_t)(me - 1) * (me + 1)]);
-        // a5: Schur form of H_m
-        SIMM_TRY(schur_phase(s, m + 1, flags[r] + 3, st));
     }
+    // a5: the Schur forms of the nr matrices H_m side by side (each one wavefront), on st
+    // and on streams of their own made for them
+    struct Side {
+        hipStream_t s[4] = {};
+        hipEvent_t e = nullptr;
+        ~Side() {
+            for (auto& x : s)
+                if (x) {
+                    (void)hipStreamSynchronize(x);
+                    (void)hipStreamDestroy(x);
+                }
+            if (e) (void)hipEventDestroy(e);
+        }
+    } side;
+    SIMM_HIP_TRY(hipEventCreateWithFlags(&side.e, hipEventDisableTiming));
+    SIMM_HIP_TRY(hipEventRecord(side.e, st));
+    for (int r = 1; r < nr; ++r) {
+        SIMM_HIP_TRY(hipStreamCreateWithFlags(&side.s[r], hipStreamNonBlocking));
+        SIMM_HIP_TRY(hipStreamWaitEvent(side.s[r], side.e, 0));
+    }
+    auto sst = [&](int r) { return r == 0 ? st : side.s[r]; };
+    for (int r = 0; r < nr; ++r) SIMM_TRY(schur_launch(kvs[r], m + 1, flags[r] + 3, sst(r)));
+    for (int r = 0; r < nr; ++r) SIMM_TRY(schur_finish(kvs[r], flags[r] + 3, sst(r)));
     return SIMM_OK;
 }
 

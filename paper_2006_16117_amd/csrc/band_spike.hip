@@ -509,13 +509,17 @@ __global__ __launch_bounds__(CH_THREADS) void k_spike_chain(SpikeChain a) {
             if (g == 0 && r < K) a.t[chunk(q0) * K + r + u * a.ldt] = v;
         }
     }
-    cplx ph[MAXQ];
+    // Several right-hand sides with the longer states read their Phi row in halves of 16
+    // per step, not ahead (the whole row ahead beside the states' accumulators would spill
+    // registers); the accumulation order is the same.
+    constexpr bool SPLIT = NR > 1 && MAXQ > 16;
+    cplx ph[SPLIT ? 16 : MAXQ];
     auto load_phi = [&](int64_t c) {
         const cplx* prow = a.Phi + c * KK + (int64_t)ic * K;
 #pragma unroll
-        for (int q = 0; q < MAXQ; ++q) ph[q] = prow[min(part + CH_PARTS * q, K - 1)];
+        for (int q = 0; q < (SPLIT ? 16 : MAXQ); ++q) ph[q] = prow[min(part + CH_PARTS * q, K - 1)];
     };
-    if (nsteps > 0) load_phi(chunk(q0));
+    if (!SPLIT && nsteps > 0) load_phi(chunk(q0));
     __syncthreads();
     for (int64_t step = 0; step < nsteps; ++step) {
         const int64_t q = q0 + step;
@@ -527,12 +531,26 @@ __global__ __launch_bounds__(CH_THREADS) void k_spike_chain(SpikeChain a) {
         cplx acc[NR];
 #pragma unroll
         for (int u = 0; u < NR; ++u) acc[u] = mk(0.0, 0.0);
+        if constexpr (SPLIT) {
+            const cplx* prow = a.Phi + c * KK + (int64_t)ic * K;
 #pragma unroll
-        for (int qq = 0; qq < MAXQ; ++qq)
+            for (int h = 0; h < MAXQ / 16; ++h) {
 #pragma unroll
-            for (int u = 0; u < NR; ++u)
-                acc[u] = fma_c(acc[u], ph[qq], tcur[u][part + CH_PARTS * qq]);   // padded t is 0
-        if (step + 1 < nsteps) load_phi(chunk(q + 1));
+                for (int q = 0; q < 16; ++q) ph[q] = prow[min(part + CH_PARTS * (16 * h + q), K - 1)];
+#pragma unroll
+                for (int q = 0; q < 16; ++q)
+#pragma unroll
+                    for (int u = 0; u < NR; ++u)
+                        acc[u] = fma_c(acc[u], ph[q], tcur[u][part + CH_PARTS * (16 * h + q)]);   // padded t is 0
+            }
+        } else {
+#pragma unroll
+            for (int qq = 0; qq < MAXQ; ++qq)
+#pragma unroll
+                for (int u = 0; u < NR; ++u)
+                    acc[u] = fma_c(acc[u], ph[qq], tcur[u][part + CH_PARTS * qq]);   // padded t is 0
+            if (step + 1 < nsteps) load_phi(chunk(q + 1));
+        }
 #pragma unroll
         for (int u = 0; u < NR; ++u) {
 #pragma unroll
@@ -571,16 +589,30 @@ __global__ __launch_bounds__(CH_THREADS) void k_spike_chain(SpikeChain a) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             // all loads in flight at once (indices clamped into the state), then to LDS
             constexpr int NL = (CH_PARTS * MAXQ + 63) / 64;
-            cplx nxt[NR][NL];
+            if constexpr (NR == 1 || MAXQ <= 16) {
+                cplx nxt[NR][NL];
 #pragma unroll
-            for (int u = 0; u < NR; ++u)
+                for (int u = 0; u < NR; ++u)
 #pragma unroll
-                for (int v = 0; v < NL; ++v) nxt[u][v] = dst[min(tid + 64 * v, K - 1) + u * ldd];
+                    for (int v = 0; v < NL; ++v) nxt[u][v] = dst[min(tid + 64 * v, K - 1) + u * ldd];
 #pragma unroll
-            for (int u = 0; u < NR; ++u)
+                for (int u = 0; u < NR; ++u)
 #pragma unroll
-                for (int v = 0; v < NL; ++v)
-                    tcur[u][tid + 64 * v] = csel(tid + 64 * v < K, nxt[u][v], mk(0.0, 0.0));   // padding stays 0
+                    for (int v = 0; v < NL; ++v)
+                        tcur[u][tid + 64 * v] = csel(tid + 64 * v < K, nxt[u][v], mk(0.0, 0.0));   // padding stays 0
+            } else {
+                // the longer states of several right-hand sides one after another (all of
+                // them in flight at once would spill the registers that hold phi)
+#pragma unroll
+                for (int u = 0; u < NR; ++u) {
+                    cplx nxt[NL];
+#pragma unroll
+                    for (int v = 0; v < NL; ++v) nxt[v] = dst[min(tid + 64 * v, K - 1) + u * ldd];
+#pragma unroll
+                    for (int v = 0; v < NL; ++v) tcur[u][tid + 64 * v] = csel(tid + 64 * v < K, nxt[v], mk(0.0, 0.0));
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
         }
         __syncthreads();
     }
@@ -859,10 +891,11 @@ simm_status launch_bwd0(const Args& a, int64_t P, int nr, int W, int rows, int64
 }  // namespace
 
 int spike_max_nrhs(const SpikeFactor& f) {
-    // the 1024-thread chunk kernels take one, and so do chains of states longer than 256
-    // (their several-column forms would spill registers)
-    if (f.Wf > 512 || f.Wb > 512 || std::max(f.klx, f.K) > 16 * 16) return 1;
-    for (int nr = 4; nr > 1; nr /= 2)
+    // the 1024-thread chunk kernels take one, chains of states longer than 512 one, and of
+    // states longer than 256 two (more would spill registers)
+    if (f.Wf > 512 || f.Wb > 512 || std::max(f.klx, f.K) > 32 * 16) return 1;
+    const int cap = std::max(f.klx, f.K) > 16 * 16 ? 2 : 4;
+    for (int nr = cap; nr > 1; nr /= 2)
         if (window_lds0(f.klx + 16, f.s, nr) <= LDS_LIMIT && window_lds0(f.K + 16, f.s, nr) <= LDS_LIMIT) return nr;
     return 1;
 }
@@ -1200,14 +1233,15 @@ static simm_status run_chain(const SpikeFactor& f, bool forward, int K, int64_t 
     // 16 threads per state row, 16 rows per workgroup: more, smaller workgroups make
     // the device-scope barrier of every step dearer than the rows they save
     const dim3 grid((unsigned)((K + 15) / 16), (unsigned)groups);
-    if (nr > 1 && K > 16 * 16) {
-        set_error("several right-hand sides need chain states of at most 256");
+    if ((nr > 1 && K > 32 * 16) || (nr > 2 && K > 16 * 16)) {
+        set_error("several right-hand sides: four need chain states of at most 256, two of at most 512");
         return SIMM_EINVAL;
     }
     if (nr == 4) {
         hipLaunchKernelGGL((k_spike_chain<16, 16, 4>), grid, dim3(CH_THREADS), 0, st, c);
     } else if (nr == 2) {
-        hipLaunchKernelGGL((k_spike_chain<16, 16, 2>), grid, dim3(CH_THREADS), 0, st, c);
+        if (K <= 16 * 16) hipLaunchKernelGGL((k_spike_chain<16, 16, 2>), grid, dim3(CH_THREADS), 0, st, c);
+        else hipLaunchKernelGGL((k_spike_chain<32, 16, 2>), grid, dim3(CH_THREADS), 0, st, c);
     } else {
         if (K <= 16 * 16) hipLaunchKernelGGL((k_spike_chain<16, 16, 1>), grid, dim3(CH_THREADS), 0, st, c);
         else if (K <= 32 * 16) hipLaunchKernelGGL((k_spike_chain<32, 16, 1>), grid, dim3(CH_THREADS), 0, st, c);
@@ -1236,10 +1270,12 @@ static simm_status chain_states(const SpikeFactor& f, bool forward, int K, const
                        f.counter + f.G * SPIKE_CTR_STRIDE, active, st, nr, ldg, 0, ldg));
     const dim3 grid((unsigned)((K + 15) / 16), (unsigned)f.P);
     const int fw = forward ? 1 : 0;
-    if (nr == 4) {   // K <= 256 (checked by run_chain)
+    if (nr == 4) {   // K <= 256, and K <= 512 for two (checked by run_chain)
         hipLaunchKernelGGL((k_spike_fix<16, 4>), grid, dim3(256), 0, st, K, f.P, f.L, fw, Pi, tg, t, ldg, ldt, active);
     } else if (nr == 2) {
-        hipLaunchKernelGGL((k_spike_fix<16, 2>), grid, dim3(256), 0, st, K, f.P, f.L, fw, Pi, tg, t, ldg, ldt, active);
+        if (K <= 16 * 16) hipLaunchKernelGGL((k_spike_fix<16, 2>), grid, dim3(256), 0, st, K, f.P, f.L, fw, Pi, tg, t, ldg,
+                                             ldt, active);
+        else hipLaunchKernelGGL((k_spike_fix<32, 2>), grid, dim3(256), 0, st, K, f.P, f.L, fw, Pi, tg, t, ldg, ldt, active);
     } else {
         if (K <= 16 * 16) hipLaunchKernelGGL((k_spike_fix<16, 1>), grid, dim3(256), 0, st, K, f.P, f.L, fw, Pi, tg, t, ldg,
                                              ldt, active);

@@ -2625,15 +2625,24 @@ simm_status multiplicities(simm_result_s* R, const cplx* F, int k, double rel_to
         any_mixed = any_mixed || R->shifts[used[u]]->mixed;
     }
     SIMM_HIP_TRY(hipStreamSynchronize(st));
-    // The k Krylov spaces of a shift are independent: start vector i goes to worker i % W
-    // (a host thread with a stream of its own, the factor's per-application buffers and a
-    // shift object whose basis and Schur buffers it reuses), shifts in order, so column
-    // i of X receives its terms in the one-worker order.  Refined (mixed-precision)
-    // shifts share one refinement state per shift: one worker then.
-    const int W = any_mixed ? 1 : std::min(k, MULT_WORKERS);
+    // The k Krylov spaces of a shift are independent.  They go in blocks of NB consecutive
+    // start vectors whose spaces advance in lockstep (one multi-column application of M
+    // per step), block b to worker b % W (a host thread with a stream of its own, the
+    // factor's per-application buffers and shift objects whose basis and Schur buffers it
+    // reuses), shifts in order, so column i of X receives its terms in the one-worker
+    // order.  Refined (mixed-precision) shifts share one refinement state per shift: one
+    // worker and one space at a time then.
+    int NB = 1;
+    if (!any_mixed) {
+        NB = 4;
+        for (int u : used) NB = std::min(NB, spike_max_nrhs(R->shifts[u]->spike));
+        NB = std::max(1, std::min(NB, k));
+    }
+    const int nblocks = (k + NB - 1) / NB;
+    const int W = any_mixed ? 1 : std::min(nblocks, MULT_WORKERS);
     struct Worker {
         hipStream_t st = nullptr;
-        simm_shift_s kv;
+        simm_shift_s kv[4];
         DevBuf tb, yb, sb;
         simm_status rc = SIMM_OK;
         std::string msg;
@@ -2672,19 +2681,30 @@ simm_status multiplicities(simm_result_s* R, const cplx* F, int k, double rel_to
                 const int64_t* offd = q.ib.as<int64_t>();
                 const int64_t* idxd = offd + q.off.size();
                 SpikeFactor clone{};
-                const bool own = W > 1;
-                if (own) SIMM_TRY(spike_clone_scratch(base->spike, clone, x.st, true));
-                for (int i = w; i < k; i += W) {
-                    // Krylov space of f_i on the shift's factor
-                    x.kv.borrow_factor_of(base);
-                    if (own) x.kv.spike = clone;
-                    SIMM_TRY(krylov_shift(&x.kv, F + (int64_t)i * n, m, x.st, nullptr));
-                    EvalOut eo;
-                    SIMM_TRY(evaluate({&x.kv}, q.regs, prm, rule, x.st, eo, x.sb.as<cplx>(), m));
-                    SIMM_TRY(cluster_sums(x.sb.as<cplx>(), m, offd, idxd, ncl, x.kv.m_eff, x.yb.as<cplx>(), m, x.st));
-                    SIMM_TRY(project(n, x.kv.m_eff, x.kv.V, n, x.yb.as<cplx>(), m, ncl, x.tb.as<cplx>(), nullptr,
-                                     nullptr, 0, SIMM_PROJ_FP64, x.st));
-                    SIMM_TRY(accum_cols(n, ncl, x.tb.as<cplx>(), xb.as<cplx>() + (int64_t)i * n, (int64_t)k * n, x.st));
+                const bool own = W > 1 || NB > 1;
+                if (own) SIMM_TRY(spike_clone_scratch(base->spike, clone, x.st, true, NB));
+                for (int b = w; b < nblocks; b += W) {
+                    // Krylov spaces of f_i, i in block b, on the shift's factor
+                    const int i0 = b * NB, nb = std::min(NB, k - i0);
+                    simm_shift_s* kvp[4];
+                    for (int r = 0; r < nb; ++r) {
+                        x.kv[r].borrow_factor_of(base);
+                        if (own) x.kv[r].spike = clone;
+                        kvp[r] = &x.kv[r];
+                    }
+                    if (nb == 1) SIMM_TRY(krylov_shift(kvp[0], F + (int64_t)i0 * n, m, x.st, nullptr));
+                    else SIMM_TRY(krylov_block(kvp, nb, F + (int64_t)i0 * n, n, m, x.st));
+                    for (int r = 0; r < nb; ++r) {
+                        simm_shift_s& kv = x.kv[r];
+                        const int i = i0 + r;
+                        EvalOut eo;
+                        SIMM_TRY(evaluate({&kv}, q.regs, prm, rule, x.st, eo, x.sb.as<cplx>(), m));
+                        SIMM_TRY(cluster_sums(x.sb.as<cplx>(), m, offd, idxd, ncl, kv.m_eff, x.yb.as<cplx>(), m, x.st));
+                        SIMM_TRY(project(n, kv.m_eff, kv.V, n, x.yb.as<cplx>(), m, ncl, x.tb.as<cplx>(), nullptr,
+                                         nullptr, 0, SIMM_PROJ_FP64, x.st));
+                        SIMM_TRY(accum_cols(n, ncl, x.tb.as<cplx>(), xb.as<cplx>() + (int64_t)i * n, (int64_t)k * n,
+                                            x.st));
+                    }
                 }
                 if (own) {
                     int e = 0;

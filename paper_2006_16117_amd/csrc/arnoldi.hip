@@ -60,11 +60,9 @@ __device__ inline void chunk_dots(const cplx* __restrict__ V, int64_t ldv, int64
 
 // partial[blk * ldp + i] = sum over the block's rows of conj(V(r, i)) * w(r), i < ncol;
 // if with_norm, partial[blk * ldp + ncol] = sum |w(r)|^2 (real part).
-__global__ __launch_bounds__(GS_THREADS) void k_gs_dots(int64_t n, const cplx* __restrict__ V, int64_t ldv, int ncol,
-                                                        const cplx* __restrict__ w, int with_norm, cplx* partial,
-                                                        int ldp, const int* active) {
-    if (active != nullptr && *active == 0) return;
-    __shared__ cplx ws[1024];
+__device__ __forceinline__ void gs_dots_body(int64_t n, const cplx* __restrict__ V, int64_t ldv, int ncol,
+                                             const cplx* __restrict__ w, int with_norm, cplx* partial, int ldp,
+                                             cplx* ws) {
     const int64_t nblk = gridDim.x;
     const int64_t rows = (n + nblk - 1) / nblk;
     const int64_t r0 = blockIdx.x * rows;
@@ -84,12 +82,18 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_dots(int64_t n, const cplx* _
     }
 }
 
+__global__ __launch_bounds__(GS_THREADS) void k_gs_dots(int64_t n, const cplx* __restrict__ V, int64_t ldv, int ncol,
+                                                        const cplx* __restrict__ w, int with_norm, cplx* partial,
+                                                        int ldp, const int* active) {
+    if (active != nullptr && *active == 0) return;
+    __shared__ cplx ws[1024];
+    gs_dots_body(n, V, ldv, ncol, w, with_norm, partial, ldp, ws);
+}
+
 // out[i] = sum_blk partial[blk * ldp + i] for i < ntot: one block per column, a
 // fixed-shape tree over the (<= 256) row blocks, so the order never changes.
-__global__ __launch_bounds__(256) void k_gs_reduce(const cplx* partial, int nblk, int ldp, int ntot, cplx* out,
-                                                   const int* active) {
-    if (active != nullptr && *active == 0) return;
-    __shared__ cplx red[256];
+__device__ __forceinline__ void gs_reduce_body(const cplx* partial, int nblk, int ldp, int ntot, cplx* out,
+                                               cplx* red) {
     const int i = blockIdx.x;
     if (i >= ntot) return;
     cplx acc = mk(0.0, 0.0);
@@ -103,18 +107,21 @@ __global__ __launch_bounds__(256) void k_gs_reduce(const cplx* partial, int nblk
     if (threadIdx.x == 0) out[i] = red[0];
 }
 
+__global__ __launch_bounds__(256) void k_gs_reduce(const cplx* partial, int nblk, int ldp, int ntot, cplx* out,
+                                                   const int* active) {
+    if (active != nullptr && *active == 0) return;
+    __shared__ cplx red[256];
+    gs_reduce_body(partial, nblk, ldp, ntot, out, red);
+}
+
 // One Gram-Schmidt update fused with the partial sums of the next pass, over the same
 // row partition as k_gs_dots: w(r) -= sum_{i < ncol} V(r, i) h(i) for the block's rows
 // (one thread per row, columns in order), then, on the updated rows, the partial sums
 // of conj(V(r, i)) w(r) for i < ndots and, if with_norm, of |w(r)|^2 (as k_gs_dots).
 // Saves a launch and a pass over w per update.
-__global__ __launch_bounds__(GS_THREADS) void k_gs_update_dots(int64_t n, const cplx* __restrict__ V, int64_t ldv,
-                                                               int ncol, const cplx* __restrict__ h,
-                                                               cplx* __restrict__ w, int ndots, int with_norm,
-                                                               cplx* partial, int ldp, const int* active) {
-    if (active != nullptr && *active == 0) return;
-    __shared__ cplx ws[1024];
-    __shared__ cplx hs[GS_MAXCOL];
+__device__ __forceinline__ void gs_update_dots_body(int64_t n, const cplx* __restrict__ V, int64_t ldv, int ncol,
+                                                    const cplx* __restrict__ h, cplx* __restrict__ w, int ndots,
+                                                    int with_norm, cplx* partial, int ldp, cplx* ws, cplx* hs) {
     const int64_t nblk = gridDim.x;
     const int64_t rows = (n + nblk - 1) / nblk;
     const int64_t r0 = blockIdx.x * rows;
@@ -139,14 +146,22 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_update_dots(int64_t n, const 
     }
 }
 
+__global__ __launch_bounds__(GS_THREADS) void k_gs_update_dots(int64_t n, const cplx* __restrict__ V, int64_t ldv,
+                                                               int ncol, const cplx* __restrict__ h,
+                                                               cplx* __restrict__ w, int ndots, int with_norm,
+                                                               cplx* partial, int ldp, const int* active) {
+    if (active != nullptr && *active == 0) return;
+    __shared__ cplx ws[1024];
+    __shared__ cplx hs[GS_MAXCOL];
+    gs_update_dots_body(n, V, ldv, ncol, h, w, ndots, with_norm, partial, ldp, ws, hs);
+}
+
 // The reduction of ||w||^2 (as k_gs_reduce, one column) and the end of step j:
 // H(0..j, j) = h1 + h2, h_{j+1,j} = ||w||, breakdown test against ||M v_j|| (h1[j+1]
 // holds its square).
-__global__ __launch_bounds__(256) void k_gs_norm_finalize(const cplx* partial, int nblk, int j, const cplx* h1,
-                                                          const cplx* h2, cplx* hw, cplx* H, int ldh, double* hnorm,
-                                                          int* active, int* m_eff) {
-    if (*active == 0) return;
-    __shared__ cplx red[256];
+__device__ __forceinline__ void gs_norm_finalize_body(const cplx* partial, int nblk, int j, const cplx* h1,
+                                                      const cplx* h2, cplx* hw, cplx* H, int ldh, double* hnorm,
+                                                      int* active, int* m_eff, cplx* red) {
     cplx acc = mk(0.0, 0.0);
     for (int b = threadIdx.x; b < nblk; b += 256) acc = acc + partial[b];
     red[threadIdx.x] = acc;
@@ -170,6 +185,56 @@ __global__ __launch_bounds__(256) void k_gs_norm_finalize(const cplx* partial, i
             H[(j + 1) + (int64_t)j * ldh] = mk(wn, 0.0);
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_gs_norm_finalize(const cplx* partial, int nblk, int j, const cplx* h1,
+                                                          const cplx* h2, cplx* hw, cplx* H, int ldh, double* hnorm,
+                                                          int* active, int* m_eff) {
+    if (*active == 0) return;
+    __shared__ cplx red[256];
+    gs_norm_finalize_body(partial, nblk, j, h1, h2, hw, H, ldh, hnorm, active, m_eff, red);
+}
+
+// The same kernels for up to four independent Arnoldi processes at once (same n, j and
+// layout; space blockIdx.y), each space's arithmetic exactly that of the kernels above.
+__global__ __launch_bounds__(GS_THREADS) void k_gs_dots_b(int64_t n, GsBatch b, int64_t ldv, int ncol, int with_norm,
+                                                          int ldp) {
+    const int y = blockIdx.y;
+    if (*b.active[y] == 0) return;
+    __shared__ cplx ws[1024];
+    gs_dots_body(n, b.V[y], ldv, ncol, b.V[y] + (int64_t)ncol * ldv, with_norm, b.partial[y], ldp, ws);
+}
+__global__ __launch_bounds__(256) void k_gs_reduce_b(GsBatch b, int nblk, int ldp, int ntot, int which) {
+    const int y = blockIdx.y;
+    if (*b.active[y] == 0) return;
+    __shared__ cplx red[256];
+    gs_reduce_body(b.partial[y], nblk, ldp, ntot, which == 1 ? b.h1[y] : b.h2[y], red);
+}
+__global__ __launch_bounds__(GS_THREADS) void k_gs_update_dots_b(int64_t n, GsBatch b, int64_t ldv, int ncol, int which,
+                                                                 int ndots, int with_norm, int ldp) {
+    const int y = blockIdx.y;
+    if (*b.active[y] == 0) return;
+    __shared__ cplx ws[1024];
+    __shared__ cplx hs[GS_MAXCOL];
+    gs_update_dots_body(n, b.V[y], ldv, ncol, which == 1 ? b.h1[y] : b.h2[y], b.V[y] + (int64_t)ncol * ldv, ndots,
+                        with_norm, b.partial[y], ldp, ws, hs);
+}
+__global__ __launch_bounds__(256) void k_gs_norm_finalize_b(GsBatch b, int nblk, int j, int ldh) {
+    const int y = blockIdx.y;
+    if (*b.active[y] == 0) return;
+    __shared__ cplx red[256];
+    gs_norm_finalize_body(b.partial[y], nblk, j, b.h1[y], b.h2[y], b.h2[y] + (j + 2), b.H[y], ldh, b.hnorm[y],
+                          b.active[y], b.m_eff[y], red);
+}
+__global__ void k_scale_div_b(int64_t n, GsBatch b, int64_t ldv, int col) {
+    const int y = blockIdx.y;
+    if (*b.active[y] == 0) return;
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    cplx* v = b.V[y] + (int64_t)col * ldv;
+    const double s = *b.hnorm[y];
+    const cplx x = v[r];
+    v[r] = mk(x.re / s, x.im / s);
 }
 
 // v = w / s (in place) where s = *hnorm
@@ -224,6 +289,25 @@ simm_status arnoldi_step(int64_t n, cplx* V, int64_t ldv, int j, cplx* H, int ld
     hipLaunchKernelGGL(k_gs_norm_finalize, dim3(1), dim3(256), 0, st, (const cplx*)w.partial, w.nblk, j,
                        (const cplx*)w.h1, (const cplx*)w.h2, hw, H, ldh, w.hnorm, active, m_eff);
     hipLaunchKernelGGL(k_scale_div, dim3(blocks), dim3(256), 0, st, n, wv, (const double*)w.hnorm, (const int*)active);
+    SIMM_HIP_TRY(hipGetLastError());
+    return SIMM_OK;
+}
+
+// Gram-Schmidt part of step j for nr <= 4 spaces at once: w = V_r(:, j+1) holds M v_j of
+// space r; per space the operations of arnoldi_step.
+simm_status arnoldi_step_batch(int64_t n, const GsBatch& b, int nr, int64_t ldv, int j, int ldh, int nblk,
+                               hipStream_t st) {
+    const int ncol = j + 1;
+    const int ldp = ncol + 1;
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    const unsigned y = (unsigned)nr;
+    hipLaunchKernelGGL(k_gs_dots_b, dim3(nblk, y), dim3(GS_THREADS), 0, st, n, b, ldv, ncol, 1, ldp);
+    hipLaunchKernelGGL(k_gs_reduce_b, dim3(ncol + 1, y), dim3(256), 0, st, b, nblk, ldp, ncol + 1, 1);
+    hipLaunchKernelGGL(k_gs_update_dots_b, dim3(nblk, y), dim3(GS_THREADS), 0, st, n, b, ldv, ncol, 1, ncol, 0, ldp);
+    hipLaunchKernelGGL(k_gs_reduce_b, dim3(ncol, y), dim3(256), 0, st, b, nblk, ldp, ncol, 2);
+    hipLaunchKernelGGL(k_gs_update_dots_b, dim3(nblk, y), dim3(GS_THREADS), 0, st, n, b, ldv, ncol, 2, 0, 1, 1);
+    hipLaunchKernelGGL(k_gs_norm_finalize_b, dim3(1, y), dim3(256), 0, st, b, nblk, j, ldh);
+    hipLaunchKernelGGL(k_scale_div_b, dim3(blocks, y), dim3(256), 0, st, n, b, ldv, j + 1);
     SIMM_HIP_TRY(hipGetLastError());
     return SIMM_OK;
 }

@@ -938,6 +938,17 @@ simm_status krylov_block(simm_shift_s* const* kvs, int nr, const cplx* F, int64_
     SIMM_TRY(uy.alloc(sizeof(cplx) * (size_t)n16 * nr * 2, st));
     cplx* U = uy.as<cplx>();
     cplx* Y = U + n16 * nr;
+    GsBatch gb{};
+    for (int r = 0; r < nr; ++r) {
+        gb.V[r] = kvs[r]->V;
+        gb.H[r] = kvs[r]->H;
+        gb.partial[r] = aw[r].partial;
+        gb.h1[r] = aw[r].h1;
+        gb.h2[r] = aw[r].h2;
+        gb.hnorm[r] = aw[r].hnorm;
+        gb.active[r] = flags[r] + 1;
+        gb.m_eff[r] = flags[r] + 2;
+    }
     ChainSlots slots;
     SIMM_TRY(slots.acquire(spike_chain_weight(f), st));
     // a3: b = (A - sigma B)^{-1} f, beta, v_1
@@ -953,12 +964,11 @@ simm_status krylov_block(simm_shift_s* const* kvs, int nr, const cplx* F, int64_
             SIMM_TRY(prepare_input(n, kvs[r]->V + (int64_t)j * n, p->B, p->klb, p->kub, nullptr, nullptr, U + r * n16,
                                    nullptr, st));
         SIMM_TRY(spike_apply_nr(f, U, n16, Y, n16, nr, st));
-        for (int r = 0; r < nr; ++r) {
-            simm_shift_s* s = kvs[r];
-            SIMM_HIP_TRY(hipMemcpyAsync(s->V + (int64_t)(j + 1) * n, Y + r * n16, sizeof(cplx) * n,
+        for (int r = 0; r < nr; ++r)
+            SIMM_HIP_TRY(hipMemcpyAsync(kvs[r]->V + (int64_t)(j + 1) * n, Y + r * n16, sizeof(cplx) * n,
                                         hipMemcpyDeviceToDevice, st));
-            SIMM_TRY(arnoldi_step(n, s->V, n, j, s->H, m + 1, aw[r], flags[r] + 1, flags[r] + 2, st));
-        }
+        // the spaces' Gram-Schmidt steps in the same launches
+        SIMM_TRY(arnoldi_step_batch(n, gb, nr, n, j, m + 1, nblk_eff, st));
     }
     int spike_err = 0;
     int fl[4][4];

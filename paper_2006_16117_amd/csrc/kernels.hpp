@@ -250,6 +250,19 @@ struct ArnoldiWork {
 simm_status arnoldi_step(int64_t n, cplx* V, int64_t ldv, int j, cplx* H, int ldh, ArnoldiWork& w, int* active,
                          int* m_eff, hipStream_t st);
 simm_status vec_norm_scale(int64_t n, const cplx* b, cplx* v1, double* beta, ArnoldiWork& w, hipStream_t st);
+// per-space pointers of up to four Arnoldi processes advanced together
+struct GsBatch {
+    cplx* V[4];
+    cplx* H[4];
+    cplx* partial[4];
+    cplx* h1[4];
+    cplx* h2[4];
+    double* hnorm[4];
+    int* active[4];
+    int* m_eff[4];
+};
+simm_status arnoldi_step_batch(int64_t n, const GsBatch& b, int nr, int64_t ldv, int j, int ldh, int nblk,
+                               hipStream_t st);
 
 // ---- Schur form of H_m (schur.hip) ----
 struct SchurOut {

@@ -222,6 +222,14 @@ simm_status simm_shift_basis(simm_shift s, double* V, int32_t mem, void* hip_str
  * x and y in `mem` memory (distinct buffers). */
 simm_status simm_shift_apply(simm_shift s, const double* x, double* y, int32_t mem, void* hip_stream);
 
+/* Applies M to k vectors (Sec. 2, eq. (IMxb)): Y(:, r) = M X(:, r), r < k.  X and Y are
+ * n x k, column-major complex (leading dimension n), in `mem` memory, distinct buffers.
+ * Up to four columns share each pass over the factor; every column equals what
+ * simm_shift_apply gives for it.  Synchronous.  EINVAL: bad arguments, k < 0, the
+ * factor released; EHIP on a chain time-out. */
+simm_status simm_shift_apply_many(simm_shift s, const double* X, double* Y, int32_t k, int32_t mem,
+                                  void* hip_stream);
+
 void simm_shift_destroy(simm_shift s);
 
 /* Indicators of N squares (Sec. 2 eqs. (many), (error), (y); Sec. 3.1 eq.

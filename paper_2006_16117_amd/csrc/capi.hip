@@ -3346,6 +3346,76 @@ simm_status simm_shift_apply(simm_shift s, const double* x, double* y, int32_t m
     return SIMM_OK;
 }
 
+simm_status simm_shift_apply_many(simm_shift s, const double* X, double* Y, int32_t k, int32_t mem,
+                                  void* hip_stream) {
+    clear_error();
+    if (!s || !X || !Y || X == Y || k < 0) {
+        set_error("bad apply arguments");
+        return SIMM_EINVAL;
+    }
+    if (mem != SIMM_MEM_HOST && mem != SIMM_MEM_DEVICE) {
+        set_error("mem must be SIMM_MEM_HOST or SIMM_MEM_DEVICE");
+        return SIMM_EINVAL;
+    }
+    if (!s->has_factor()) {
+        set_error("the shift's factor was released (SIMM_FLAG_RELEASE_FACTORS)");
+        return SIMM_EINVAL;
+    }
+    if (k == 0) return SIMM_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    const int64_t n = s->p->n, n16 = s->spike.n16;
+    DevBuf xb, yb, ub;
+    const cplx* xd = nullptr;
+    SIMM_TRY(to_device_vec(X, mem, n * k, xb, &xd, st));
+    cplx* yd = reinterpret_cast<cplx*>(Y);
+    if (mem == SIMM_MEM_HOST) {
+        SIMM_TRY(yb.alloc(sizeof(cplx) * (size_t)n * k, st));
+        yd = yb.as<cplx>();
+    }
+    // up to four columns per pass over the factor (one at a time for a refined FP32 factor)
+    const int nb = s->mixed ? 1 : std::min(4, spike_max_nrhs(s->spike));
+    SpikeFactor clone{};
+    struct CloneRelease {
+        SpikeFactor* c;
+        hipStream_t st;
+        bool on = false;
+        ~CloneRelease() {
+            if (on) {
+                (void)hipStreamSynchronize(st);
+                spike_release_ordered(*c, st);
+            }
+        }
+    } clone_release{&clone, st};
+    if (nb > 1) {
+        SIMM_TRY(spike_clone_scratch(s->spike, clone, st, true, nb));
+        clone_release.on = true;
+    }
+    SIMM_TRY(ub.alloc(sizeof(cplx) * (size_t)n16 * nb, st));
+    cplx* U = ub.as<cplx>();
+    ChainSlots slots;   // released (after a synchronize) when this returns
+    SIMM_TRY(slots.acquire(spike_chain_weight(s->spike), st));
+    for (int c0 = 0; c0 < k;) {
+        int nr = std::min(nb, k - c0);
+        if (nr == 3) nr = 2;
+        for (int r = 0; r < nr; ++r)
+            SIMM_TRY(prepare_input(n, xd + (int64_t)(c0 + r) * n, s->p->B, s->p->klb, s->p->kub, nullptr, nullptr,
+                                   U + r * n16, nullptr, st));
+        if (nb == 1) SIMM_TRY(apply_inverse(s, U, yd + (int64_t)c0 * n, nullptr, st));
+        else SIMM_TRY(spike_apply_nr(clone, U, n16, yd + (int64_t)c0 * n, n, nr, st));
+        c0 += nr;
+    }
+    int err = 0;
+    SIMM_HIP_TRY(hipMemcpyAsync(&err, nb > 1 ? clone.err : s->spike.err, sizeof(int), hipMemcpyDeviceToHost, st));
+    if (mem == SIMM_MEM_HOST)
+        SIMM_HIP_TRY(hipMemcpyAsync(Y, yd, sizeof(cplx) * (size_t)n * k, hipMemcpyDeviceToHost, st));
+    SIMM_HIP_TRY(hipStreamSynchronize(st));
+    if (err) {
+        set_error("partitioned sweep: a chunk-chain barrier timed out");
+        return SIMM_EHIP;
+    }
+    return SIMM_OK;
+}
+
 void simm_shift_destroy(simm_shift s) {
     if (s && !s->borrowed) delete s;
 }

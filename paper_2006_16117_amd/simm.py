@@ -80,6 +80,7 @@ EXPORTS = {
     "simm_shift_info": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "simm_shift_basis": (C.c_int, [_vp, _vp, _i32, _vp]),
     "simm_shift_apply": (C.c_int, [_vp, _vp, _vp, _i32, _vp]),
+    "simm_shift_apply_many": (C.c_int, [_vp, _vp, _vp, _i32, _i32, _vp]),
     "simm_shift_destroy": (None, [_vp]),
     "simm_indicators": (C.c_int, [_vp, _i32, _vp, _i64, C.POINTER(simm_params), _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                   _i32, _i32, _vp]),
@@ -242,6 +243,15 @@ class Shift:
         py, _ = _ptr(y)
         _check(_lib.simm_shift_apply(self.handle, px, py, mem, _stream(stream)))
         return y
+
+    def apply_many(self, X, Y, stream=None):
+        """X, Y: n x k column-major complex (numpy arrays in Fortran order, or device
+        tensors whose storage is column-major)."""
+        px, mem = _ptr(X)
+        py, _ = _ptr(Y)
+        k = X.shape[1] if len(X.shape) > 1 else 1
+        _check(_lib.simm_shift_apply_many(self.handle, px, py, int(k), mem, _stream(stream)))
+        return Y
 
     def __del__(self):
         if getattr(self, "handle", None) and self._owner is None and _lib is not None:

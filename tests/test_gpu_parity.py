@@ -140,6 +140,49 @@ def test_partitioned_factor_matches_oracle(S, part_env, case):
     assert err <= 1e-12
 
 
+MANY_CASES = [
+    # name, n, kl, seed, b_kind, block length (0: the whole band), k columns, generator kwargs
+    ("whole-k8", 3000, 8, 120, "tridiag", 0, 5, {}),                 # four-column passes, then one
+    # strong pivoting: U's bandwidth above 256, so two columns, then one
+    ("whole-k140", 3000, 140, 121, "identity", 0, 3, dict(d_half=0.05, e_scale=1.0)),
+    ("part-k16", 5000, 16, 122, "tridiag", 512, 7, {}),              # partitioned: 4 + 2 + 1
+]
+
+
+@pytest.mark.parametrize("case", MANY_CASES, ids=[c[0] for c in MANY_CASES])
+def test_apply_many_equals_single_applications(S, part_env, case):
+    """simm_shift_apply_many (several columns per pass over the factor: the multi-column
+    chunk sweeps, chains, fix-ups and corrections, and for a partitioned factor the
+    multi-column tips product and correction) gives every column bit for bit what
+    simm_shift_apply gives it, and that agrees with the oracle's solve."""
+    name, n, kl, seed, b_kind, bs, k, kw = case
+    pen, f = random_band_pencil(n, kl, seed, b_kind=b_kind, b_offdiag=0.3, **kw)
+    part_env["SIMM_LU_PART"] = str(bs)
+    say("apply_many", name, f"n={n} kl=ku={kl} block={bs} k={k}")
+    P = S.Pencil.from_workload(pen)
+    sigma = 0.05 + 0.03j
+    sh = S.simm_shift_build(P, sigma, f, 4)
+    fi = sh.factor_info()
+    assert (fi["block_len"] > 0) == (bs > 0)
+    if bs == 0:
+        # U's bandwidth: ku plus the longest pivot jump (LAPACK's band LU, the same pivots)
+        _, ipiv, _, _ = O._band_factor(n, pen.kl_a, pen.ku_a, pen.a_band, pen.kl_b, pen.ku_b, pen.b_band, sigma)
+        K = pen.ku_a + int(np.max(ipiv - 1 - np.arange(n)))
+        say("  U bandwidth", K)
+        assert (K > 256) == (kl > 100)
+    rng = np.random.default_rng(seed)
+    X = np.asfortranarray(rng.standard_normal((n, k)) + 1j * rng.standard_normal((n, k)))
+    Y = np.zeros((n, k), np.complex128, order="F")
+    sh.apply_many(X, Y)
+    solver = O.ShiftedSolver(pen, sigma)
+    for r in range(k):
+        y = np.zeros(n, np.complex128)
+        sh.apply(np.ascontiguousarray(X[:, r]), y)
+        assert np.array_equal(Y[:, r], y), (r, float(np.max(np.abs(Y[:, r] - y))))
+        want = solver.apply_M(X[:, r])
+        assert np.linalg.norm(y - want) <= 1e-12 * np.linalg.norm(want)
+
+
 def test_partitioned_mixed_precision_refines(S, part_env):
     pen, f = random_band_pencil(5000, 16, 96, b_kind="tridiag", b_offdiag=0.3)
     sigma = -0.05 + 0.1j

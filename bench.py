@@ -405,7 +405,7 @@ def main():
     ap.add_argument("--mult-k", type=int, default=4, help="start vectors for the multiplicity step (0: skip)")
     ap.add_argument("--project-c", type=int, default=1600,
                     help="columns of the full-level projection measured after the steps (0: skip)")
-    ap.add_argument("--workers", type=int, default=6, help="runs in flight in the batched form")
+    ap.add_argument("--workers", type=int, default=16, help="runs in flight in the batched form (at most 16)")
     ap.add_argument("--lookahead", type=int, default=0,
                     help="LU factors computed ahead in the timed run (0: the library default)")
     ap.add_argument("--batch-lookahead", type=int, default=2,

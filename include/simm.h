@@ -344,7 +344,7 @@ simm_status simm_run(simm_pencil p, const simm_params* params, const double* f, 
 
 /* Batched form: simm_run on `count` independent pencils (sizes may differ), with the
  * same results as `count` separate runs.  Steps 1-3 (the shifts and the level-1 cells) of
- * up to `workers` pencils run in flight at once, each on a non-blocking stream of its own
+ * up to `workers` pencils (at most 16) run in flight at once, each on a non-blocking stream of its own
  * (a lookahead of 0 counts as 1 here, the runs in flight already sharing the queues).
  * Then the levels of all pencils are evaluated together (Sec. 3.3: all squares of a
  * level at once): per level one persistent indicator launch over the squares of every

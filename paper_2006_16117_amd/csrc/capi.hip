@@ -3755,6 +3755,9 @@ simm_status simm_run_batch(const simm_pencil* pencils, const simm_params* params
         }
     }
     if (count == 0) return SIMM_OK;
+    // at most 16 runs in flight: with 24 (and their factors ahead) the HIP runtime ran out
+    // of queue resources and aborted a queue (HSA_STATUS_ERROR_OUT_OF_RESOURCES)
+    workers = std::min(workers, 16);
     SIMM_TRY(check_device());
     int dev = 0;
     SIMM_HIP_TRY(hipGetDevice(&dev));

@@ -807,6 +807,35 @@ def test_multiplicities_match_oracle(S, planted_oracle_run, k):
         S.simm_multiplicities(res, F, rel_tol=0.0)
 
 
+def test_multiplicities_cfg1_match_eigenvalue_counts(S):
+    """Sec. 3.4 on the n = 40,000 run: with k start vectors the multiplicity of a cluster
+    is min(k, number of eigenvalues it holds).  The counts come from shift-invert ARPACK
+    on the host (tests/arpack_ref.py), independent of the oracle and of the HIP path;
+    the run's clusters are the oracle's stored ones, in the same order."""
+    from tests import arpack_ref
+    from workloads import load_config, start_vectors
+    name, k = "cfg1", 4
+    pen, f, params = make_workload(name)
+    with open(os.path.join(GOLDEN, f"{name}_oracle.json")) as fh:
+        gold = json.load(fh)
+    say("ARPACK eigenvalues of", name, "in R (host)")
+    eigs = arpack_ref.eigenvalues_in_region(pen, params["x0"], params["x1"], params["y0"], params["y1"])
+    w = (params["x1"] - params["x0"]) / params["n1"] / 2 ** (gold["K"] - 1)
+    members = [[tuple(mm) for mm in c["members"]] for c in gold["clusters"]]
+    counts, per_eig = arpack_ref.counts_per_cluster(eigs, members, params["x0"], params["y0"], w)
+    assert min(per_eig) == 1 and max(per_eig) == 1 and min(counts) >= 1
+    say("simm_run + simm_multiplicities", name, "k =", k, "clusters", len(members), "eigenvalues", len(eigs))
+    res = S.simm_run(S.Pencil.from_workload(pen), f, S.params_from_dict(params))
+    lam = np.array([complex(*c["lam"]) for c in gold["clusters"]])
+    assert len(res.lam) == len(lam) and np.all(np.abs(res.lam - lam) <= 1e-14 * np.abs(lam))
+    F = start_vectors(pen.n, k, load_config(name)["generator"]["seed"])
+    mult, sv = S.simm_multiplicities(res, F)
+    want = np.minimum(k, np.array(counts))
+    say("  multiplicities", np.bincount(mult).tolist(), "eigenvalue counts", np.bincount(want).tolist())
+    bad = np.nonzero(mult != want)[0]
+    assert len(bad) == 0, [(int(c), int(mult[c]), int(counts[c]), (sv[c] / sv[c][0]).tolist()) for c in bad]
+
+
 # ---------------------------------------------------------------------------
 # edge cases: empty inputs, empty levels, guards, the CSR entry point
 # ---------------------------------------------------------------------------

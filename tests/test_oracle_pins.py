@@ -390,3 +390,56 @@ def test_planted_margin_mistake_is_caught(name):
     mod = _mutant(**MARGIN_MUTANTS[name])
     with pytest.raises(AssertionError):
         P.check_p18_decision_margin(mod)
+
+
+# ---------------------------------------------------------------------------
+# P20: the stored n = 40,000 oracle run against ARPACK.  Dense QZ is out of reach at
+# this order; shift-invert ARPACK finds every eigenvalue of the pencil in R, and the
+# clusters of the last level (Sec. 3.3: squares that hold eigenvalues, merged) must hold
+# each of them, each cluster at least one.  This pins the expected values the GPU run
+# is compared with.
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def cfg1_arpack():
+    import json
+    import os
+
+    from tests import arpack_ref
+
+    pen, _, params = make_workload("cfg1")
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg1_oracle.json")) as fh:
+        gold = json.load(fh)
+    eigs = arpack_ref.eigenvalues_in_region(pen, params["x0"], params["x1"], params["y0"], params["y1"])
+    w = (params["x1"] - params["x0"]) / params["n1"] / 2 ** (gold["K"] - 1)
+    return params, gold, eigs, w
+
+
+def _check_p20(params, members, eigs, w):
+    from tests import arpack_ref
+
+    per_cluster, per_eig = arpack_ref.counts_per_cluster(eigs, members, params["x0"], params["y0"], w)
+    assert min(per_eig) >= 1, "an eigenvalue in R lies in no cluster"
+    assert min(per_cluster) >= 1, "a cluster holds no eigenvalue"
+    return per_cluster
+
+
+def test_p20_cfg1_clusters_against_arpack(cfg1_arpack):
+    params, gold, eigs, w = cfg1_arpack
+    members = [[tuple(mm) for mm in c["members"]] for c in gold["clusters"]]
+    assert not any(c["unresolved"] for c in gold["clusters"])
+    per_cluster = _check_p20(params, members, eigs, w)
+    # the eigenvalues are where the clusters are: about 100 of them (the region was chosen
+    # to hold that many), each in exactly one cluster
+    assert 80 <= len(eigs) <= 120 and sum(per_cluster) == len(eigs)
+
+
+def test_planted_cluster_mistake_is_caught(cfg1_arpack):
+    """A cluster moved by one square, or dropped, fails P20."""
+    params, gold, eigs, w = cfg1_arpack
+    members = [[tuple(mm) for mm in c["members"]] for c in gold["clusters"]]
+    moved = [list(m) for m in members]
+    moved[0] = [(ix + 1, iy) for ix, iy in moved[0]]
+    with pytest.raises(AssertionError):
+        _check_p20(params, moved, eigs, w)
+    with pytest.raises(AssertionError):
+        _check_p20(params, members[1:], eigs, w)

@@ -1364,3 +1364,14 @@ def test_run_mixed_cfg3_small_matches_oracle_and_fp64(S):
     assert np.array_equal(np.isfinite(r64.lam_ritz), np.isfinite(rmx.lam_ritz))
     assert err.size == 0 or err.max() <= 1e-8
     assert rmx.refine["max_eta"] <= 1e-12
+    # the error of every eigenvalue against an independent solver: shift-invert ARPACK on
+    # the host (tests/arpack_ref.py), every eigenvalue in R
+    from tests import arpack_ref
+    say("ARPACK eigenvalues of cfg3_small in R (host)")
+    eigs = arpack_ref.eigenvalues_in_region(pen, params["x0"], params["x1"], params["y0"], params["y1"],
+                                            nx=2, ny=2, k=30)
+    assert len(eigs) == int(ok.sum())
+    for tag, r in (("FP64", r64), ("mixed", rmx)):
+        e = np.array([np.min(np.abs(eigs - z)) / abs(z) for z in r.lam_ritz[ok]])
+        say(f"  {tag}: {len(e)} eigenvalues, rel. error vs ARPACK median {np.median(e):.1e}, max {e.max():.1e}")
+        assert e.max() <= 1e-8

@@ -393,25 +393,32 @@ def test_planted_margin_mistake_is_caught(name):
 
 
 # ---------------------------------------------------------------------------
-# P20: the stored n = 40,000 oracle run against ARPACK.  Dense QZ is out of reach at
-# this order; shift-invert ARPACK finds every eigenvalue of the pencil in R, and the
-# clusters of the last level (Sec. 3.3: squares that hold eigenvalues, merged) must hold
-# each of them, each cluster at least one.  This pins the expected values the GPU run
-# is compared with.
+# P20: stored oracle runs beyond dense QZ's reach (n = 40,000 and n = 20,000) against
+# ARPACK.  Shift-invert ARPACK finds every eigenvalue of the pencil in R; the clusters
+# of the last level (Sec. 3.3: squares that hold eigenvalues, merged) must hold each of
+# them, each cluster at least one, and a cluster's Ritz value (the eigenvalue of H_m
+# nearest it, mapped back through the Cayley transform) must match an eigenvalue.  This
+# pins the expected values the GPU runs are compared with.
 # ---------------------------------------------------------------------------
-@pytest.fixture(scope="module")
-def cfg1_arpack():
-    import json
-    import os
+ARPACK_CASES = {"cfg1": dict(nx=4, ny=2, k=40), "cfg3_small": dict(nx=2, ny=2, k=30)}
+_arpack_cache = {}
 
-    from tests import arpack_ref
 
-    pen, _, params = make_workload("cfg1")
-    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg1_oracle.json")) as fh:
-        gold = json.load(fh)
-    eigs = arpack_ref.eigenvalues_in_region(pen, params["x0"], params["x1"], params["y0"], params["y1"])
-    w = (params["x1"] - params["x0"]) / params["n1"] / 2 ** (gold["K"] - 1)
-    return params, gold, eigs, w
+def _arpack_case(name):
+    if name not in _arpack_cache:
+        import json
+        import os
+
+        from tests import arpack_ref
+
+        pen, _, params = make_workload(name)
+        with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"{name}_oracle.json")) as fh:
+            gold = json.load(fh)
+        eigs = arpack_ref.eigenvalues_in_region(pen, params["x0"], params["x1"], params["y0"], params["y1"],
+                                                **ARPACK_CASES[name])
+        w = (params["x1"] - params["x0"]) / params["n1"] / 2 ** (gold["K"] - 1)
+        _arpack_cache[name] = (params, gold, eigs, w)
+    return _arpack_cache[name]
 
 
 def _check_p20(params, members, eigs, w):
@@ -423,19 +430,24 @@ def _check_p20(params, members, eigs, w):
     return per_cluster
 
 
-def test_p20_cfg1_clusters_against_arpack(cfg1_arpack):
-    params, gold, eigs, w = cfg1_arpack
+@pytest.mark.parametrize("name", sorted(ARPACK_CASES))
+def test_p20_clusters_against_arpack(name):
+    params, gold, eigs, w = _arpack_case(name)
     members = [[tuple(mm) for mm in c["members"]] for c in gold["clusters"]]
     assert not any(c["unresolved"] for c in gold["clusters"])
     per_cluster = _check_p20(params, members, eigs, w)
-    # the eigenvalues are where the clusters are: about 100 of them (the region was chosen
-    # to hold that many), each in exactly one cluster
-    assert 80 <= len(eigs) <= 120 and sum(per_cluster) == len(eigs)
+    # each eigenvalue in exactly one cluster (the regions were chosen to hold about 100
+    # and about 25 eigenvalues)
+    assert len(eigs) >= 20 and sum(per_cluster) == len(eigs)
+    lr = [complex(*c["lam_ritz"]) for c in gold["clusters"] if c["lam_ritz"][0] is not None]
+    assert len(lr) == len(members)
+    err = max(float(np.min(np.abs(eigs - z))) / abs(z) for z in lr)
+    assert err <= 1e-10, err
 
 
-def test_planted_cluster_mistake_is_caught(cfg1_arpack):
+def test_planted_cluster_mistake_is_caught():
     """A cluster moved by one square, or dropped, fails P20."""
-    params, gold, eigs, w = cfg1_arpack
+    params, gold, eigs, w = _arpack_case("cfg1")
     members = [[tuple(mm) for mm in c["members"]] for c in gold["clusters"]]
     moved = [list(m) for m in members]
     moved[0] = [(ix + 1, iy) for ix, iy in moved[0]]

@@ -1342,6 +1342,36 @@ def test_run_mixed_cfg0_matches_oracle(S):
 
 
 @pytest.mark.skipif(not os.path.exists(os.path.join(GOLDEN, "cfg3_small_oracle.json")), reason="no stored run")
+def test_run_cfg3_eigenvalues_against_arpack_sample(S):
+    """The n = 250,000 mixed-precision workload at full size, sampled: the 40 eigenvalues
+    nearest R's centre from shift-invert ARPACK on the host (tests/arpack_ref.py).  Every
+    one of them that lies in R is the Ritz value of a cluster of the FP64 run and of the
+    mixed run within 1e-8 relative (the FP64 error of each eigenvalue), and both runs have
+    the same clusters."""
+    from tests import arpack_ref
+    pen, f, params = make_workload("cfg3")
+    P = S.Pencil.from_workload(pen)
+    say("run", "cfg3 FP64")
+    r64 = S.simm_run(P, f, S.params_from_dict(params))
+    say("run", "cfg3 mixed")
+    rmx = S.simm_run(P, f, S.params_from_dict(params, flags=S.SIMM_FLAG_PROJECT, precision=S.SIMM_PREC_MIXED))
+    assert np.array_equal(r64.lam, rmx.lam) and r64.n_unresolved == 0 and rmx.n_unresolved == 0
+    say("ARPACK: 40 eigenvalues nearest the centre of R (host)")
+    A, B = arpack_ref.pencil_csc(pen)
+    c = complex((params["x0"] + params["x1"]) / 2, (params["y0"] + params["y1"]) / 2)
+    lam, r = arpack_ref.nearest_eigenvalues(A, B, c, 40)
+    inR = (lam.real >= params["x0"]) & (lam.real <= params["x1"]) & (lam.imag >= params["y0"]) & \
+          (lam.imag <= params["y1"]) & (np.abs(lam - c) < 0.98 * r)
+    sample = lam[inR]
+    assert len(sample) >= 30
+    for tag, res in (("FP64", r64), ("mixed", rmx)):
+        z = res.lam_ritz[np.isfinite(res.lam_ritz)]
+        e = np.array([np.min(np.abs(z - v)) / abs(v) for v in sample])
+        say(f"  {tag}: {len(sample)} eigenvalues, rel. error of the nearest Ritz value median {np.median(e):.1e}, "
+            f"max {e.max():.1e}")
+        assert e.max() <= 1e-8
+
+
 def test_run_mixed_cfg3_small_matches_oracle_and_fp64(S):
     """The reduced mixed-precision workload (n = 20,000, half-bandwidth 64, m = 120, 32
     Gauss points per edge, 17 levels): FP64 and mixed runs both equal the oracle's squares,

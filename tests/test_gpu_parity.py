@@ -49,6 +49,7 @@ CASES = [
     # 256 up to 224, 512 up to 480
     ("band60-pivoting", 700, 60, 86, "tridiag", 20, 0.05 + 0.05j, dict(d_half=0.05, e_scale=1.0)),
     ("band224", 900, 224, 83, "tridiag", 20, 0.1 + 0.1j, {}),
+    ("band200-pivoting", 800, 200, 87, "tridiag", 20, 0.05 - 0.05j, dict(d_half=0.05, e_scale=1.0)),
     ("band240-pivoting", 1300, 240, 84, "identity", 20, -0.2 + 0.05j, dict(d_half=0.05, e_scale=1.0)),
     ("band480-pivoting", 1100, 480, 85, "identity", 16, 0.05 + 0.0j, dict(d_half=0.05, e_scale=1.0)),
 ]

@@ -73,7 +73,7 @@ enum {
     SIMM_PREC_MIXED = 1            /* band LU factored and stored in FP32; every solve with it is
                                       refined against the FP64 pencil until its normwise backward
                                       error ||u - (A - sigma B) x||_inf / (||A - sigma B||_inf
-                                      ||x||_inf + ||u||_inf) is at most 1e-12 (at most 8
+                                      ||x||_inf + ||u||_inf) is at most 1e-12 (at most 2
                                       corrections; SIMM_EREFINE otherwise).  Arnoldi, the Schur
                                       form, the shifted solves, sums and decisions stay FP64; a
                                       run projects in BF16 at levels 1-2 and FP32 after          */

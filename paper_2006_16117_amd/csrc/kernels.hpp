@@ -212,7 +212,10 @@ int64_t spike_bytes_per_apply(const SpikeFactor& f);
 
 // ---- mixed precision: FP64-residual refinement of FP32-factor solves (refine.hip) ----
 constexpr double kRefineTol = 1e-12;   // normwise backward error of every refined solve
-constexpr int kRefineMaxSteps = 8;     // corrections before the solve counts as failed
+// corrections before the solve counts as failed.  Every step's kernels are enqueued
+// (a device flag skips them once the solve has converged), so each allowed step costs
+// its launches on every solve: one correction is what the workloads need.
+constexpr int kRefineMaxSteps = 2;
 struct RefinePencil {                  // the FP64 shifted pencil the residuals are taken with
     const cplx* A;
     int kla, kua;

@@ -33,31 +33,44 @@ __device__ inline double wave_max64(double v) {
 
 // r = u - (A - sigma B) x, row by row, and the infinity norms of r, x and u
 // (norms[0..2], as the bit patterns of non-negative doubles).  Skipped when *gate == 0.
+// A wavefront takes 64 consecutive rows and walks the columns that meet them: at
+// column j its lanes read the entries (i, j) of their rows, which are consecutive in
+// band storage (one coalesced load; x_j is the same for every lane).  Each row still
+// accumulates its entries in ascending column order.
 __global__ __launch_bounds__(256) void k_band_resid(int64_t n, const cplx* __restrict__ A, int kla, int kua,
                                                     const cplx* __restrict__ B, int klb, int kub, cplx sigma,
                                                     const cplx* __restrict__ u, const cplx* __restrict__ x,
                                                     cplx* __restrict__ r, unsigned long long* norms, const int* gate) {
     if (*gate == 0) return;
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63);   // first row of this wavefront
+    const int64_t i = r0 + (threadIdx.x & 63);
     double nr = 0.0, nx = 0.0, nu = 0.0;
-    if (i < n) {
+    if (r0 < n) {
         const int lda = kla + kua + 1;
-        cplx acc = u[i];
-        const int dlo = (int)max((int64_t)-kla, -i), dhi = (int)min((int64_t)kua, n - 1 - i);
-        for (int d = dlo; d <= dhi; ++d) acc = fms(acc, A[(int64_t)(kua - d) + (i + d) * lda], x[i + d]);
-        if (B != nullptr) {
+        const bool row = i < n;
+        cplx acc = row ? u[i] : mk(0.0, 0.0);
+        const int64_t jlo = max((int64_t)0, r0 - kla), jhi = min(n - 1, r0 + 63 + kua);
+#pragma unroll 4
+        for (int64_t j = jlo; j <= jhi; ++j) {
+            const cplx xj = x[j];
+            const int64_t d = j - i;
+            if (row && d >= -kla && d <= kua) acc = fms(acc, A[(kua - d) + j * lda], xj);
+        }
+        if (row && B != nullptr) {
             const int ldb = klb + kub + 1;
             const int elo = (int)max((int64_t)-klb, -i), ehi = (int)min((int64_t)kub, n - 1 - i);
             cplx bx = mk(0.0, 0.0);
             for (int d = elo; d <= ehi; ++d) bx = fma_c(bx, B[(int64_t)(kub - d) + (i + d) * ldb], x[i + d]);
             acc = fma_c(acc, sigma, bx);
-        } else {
+        } else if (row) {
             acc = fma_c(acc, sigma, x[i]);
         }
-        r[i] = acc;
-        nr = cabs(acc);
-        nx = cabs(x[i]);
-        nu = cabs(u[i]);
+        if (row) {
+            r[i] = acc;
+            nr = cabs(acc);
+            nx = cabs(x[i]);
+            nu = cabs(u[i]);
+        }
     }
     nr = wave_max64(nr);
     nx = wave_max64(nx);
@@ -69,18 +82,23 @@ __global__ __launch_bounds__(256) void k_band_resid(int64_t n, const cplx* __res
     }
 }
 
-// ||A - sigma B||_inf into norms[0] (bit pattern)
+// ||A - sigma B||_inf into norms[0] (bit pattern).  Rows and columns are walked as in
+// k_band_resid (64 rows per wavefront, coalesced loads, each row in ascending column
+// order).
 __global__ __launch_bounds__(256) void k_band_rownorm(int64_t n, const cplx* __restrict__ A, int kla, int kua,
                                                       const cplx* __restrict__ B, int klb, int kub, cplx sigma,
                                                       unsigned long long* out) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63);   // first row of this wavefront
+    const int64_t i = r0 + (threadIdx.x & 63);
     double s = 0.0;
-    if (i < n) {
+    if (r0 < n) {
         const int lda = kla + kua + 1, ldb = klb + kub + 1;
         const int lo = -max(kla, B ? klb : 0), hi = max(kua, B ? kub : 0);
-        for (int d = lo; d <= hi; ++d) {
-            const int64_t j = i + d;
-            if (j < 0 || j >= n) continue;
+        const int64_t jlo = max((int64_t)0, r0 + lo), jhi = min(n - 1, r0 + 63 + hi);
+        for (int64_t j = jlo; j <= jhi; ++j) {
+            const int64_t dd = j - i;
+            if (i >= n || dd < lo || dd > hi) continue;
+            const int d = (int)dd;
             cplx c = (d >= -kla && d <= kua) ? A[(int64_t)(kua - d) + j * lda] : mk(0.0, 0.0);
             if (B != nullptr) {
                 if (d >= -klb && d <= kub) c = fms(c, sigma, B[(int64_t)(kub - d) + j * ldb]);

@@ -1121,6 +1121,37 @@ def test_gradient_matches_oracle_and_fd(S, case):
         assert abs(gd[i] - (fr + 1j * fi)) <= 1e-6 * scale
 
 
+GRAD_PART_CASES = [
+    # name, n, seed, level, squares near eigenvalues, m, block length of the forward factors
+    ("n300-level3-2blocks", 300, 11, 3, 2, 100, 256),
+    ("n600-level3-3blocks", 600, 17, 3, 3, 100, 256),
+]
+
+
+@pytest.mark.parametrize("case", GRAD_PART_CASES, ids=[c[0] for c in GRAD_PART_CASES])
+def test_gradient_partitioned_matches_oracle(S, part_env, case):
+    """Partitioned factors (two and three diagonal blocks) for the forward shifts and for
+    the conjugate-transposed pencil of the adjoint spaces: J, dJ/dp and dJ/dA_ii against
+    the oracle's dense adjoint gradient."""
+    name, n, seed, level, nsq, m, bs = case
+    part_env["SIMM_LU_PART"] = str(bs)
+    pen, f, a1, A1, regions, squares, sigmas, prm = _grad_problem(n, seed, level, nsq)
+    A, B = O.pencil_dense(pen)
+    J_o, dp_o, gd_o = O.projected_norms_gradient(A, A1, B, f, squares, prm["gauss_per_edge"])
+    say("gradient, partitioned factors", name, f"n={n} m={m} block={bs} squares={len(squares)}")
+    P = S.Pencil.from_workload(pen)
+    shifts = [S.simm_shift_build(P, s, f, m) for s in sigmas]
+    assert all(sh.factor_info()["block_len"] == bs for sh in shifts)
+    params = S.params_from_dict(prm, m=m)
+    J, dp, gd = S.simm_gradient(shifts, regions, params, a1, 1, 1)
+    scale = np.max(np.abs(gd_o))
+    err = np.max(np.abs(gd - gd_o)) / scale
+    say("  J", J, "oracle", J_o, "dJ/dp", dp, "oracle", dp_o, "grad_diag rel. error", err)
+    assert abs(J - J_o) <= 1e-8 * J_o
+    assert abs(dp - dp_o) <= 1e-6 * abs(dp_o)
+    assert err <= 1e-6
+
+
 def test_gradient_n100000_matches_banded_oracle(S):
     """The differentiation workload at full size (n = 100,000, half-bandwidth 32): the
     library's run fixes the same admissible squares as the oracle's run, and its Krylov

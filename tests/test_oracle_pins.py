@@ -469,7 +469,7 @@ def test_planted_cluster_mistake_is_caught():
 # that edge (||s_c|| = 14.2 against ||s_f|| = 0.67) puts the cell's indicator at
 # 0.047 < delta0 = 0.05.  In the pencil of order 36,870 an eigenvalue on the lower edge
 # of a level-1 cell takes that cell's six eigenvalues with it; in the pencil of order
-# 9,919 the two lost eigenvalues lie within 1e-3 of a square's edge.
+# 9,919 the two lost eigenvalues lie within 0.1% of a square's width from its edge.
 # ---------------------------------------------------------------------------
 BATCH_MISSED = {
     2426: [0.3098012635532085 + 0.14579820912179825j],

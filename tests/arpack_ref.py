@@ -39,7 +39,10 @@ def nearest_eigenvalues(A, B, s: complex, k: int):
     n = A.shape[0]
     lu = spla.splu((A - s * B).tocsc(), permc_spec="COLAMD")
     op = spla.LinearOperator((n, n), matvec=lambda v: lu.solve(B @ v), dtype=np.complex128)
-    theta = spla.eigs(op, k=k, which="LM", return_eigenvectors=False, tol=1e-12)
+    # a seeded start vector: the same iterations in every process and call order
+    rng = np.random.default_rng(12345)
+    v0 = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    theta = spla.eigs(op, k=k, which="LM", return_eigenvectors=False, tol=1e-12, v0=v0)
     lam = s + 1.0 / theta
     return lam, float(np.max(np.abs(lam - s)))
 

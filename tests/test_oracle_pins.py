@@ -507,3 +507,20 @@ def test_p21_batch_runs_against_arpack():
         assert len(missed) == len(want), (pen.n, missed)
         for m in want:
             assert min(abs(e - m) for e in missed) <= 2e-6, (pen.n, m, missed)
+
+
+def test_arpack_reference_against_dense_eigenvalues():
+    """The ARPACK region scan used by P20 and P21, against all eigenvalues of a small
+    pencil from the dense generalized eigensolver: the same set in the region."""
+    import scipy.linalg as sla
+
+    from tests import arpack_ref
+
+    pen, _ = random_band_pencil(600, 3, 91, b_kind="tridiag", b_offdiag=0.2)
+    A, B = arpack_ref.pencil_csc(pen)
+    ev = sla.eigvals(A.toarray(), B.toarray())
+    x0, x1, y0, y1 = -0.6, 0.6, -0.5, 0.7
+    want = np.sort_complex(ev[(ev.real >= x0) & (ev.real <= x1) & (ev.imag >= y0) & (ev.imag <= y1)])
+    got = np.sort_complex(arpack_ref.eigenvalues_in_region(pen, x0, x1, y0, y1, nx=2, ny=2, k=40))
+    assert len(want) >= 20 and len(got) == len(want)
+    assert np.max(np.abs(got - want)) <= 1e-10
